@@ -265,6 +265,48 @@ def test_cohesion_variant(orc):
 # Tangents of the SVD-based constitutive update vs central differences
 # --------------------------------------------------------------------------
 
+def _near_apex(d, pair_gap):
+    """F = Q diag(exp(eps)) Q^T on the cone just off its apex: a small negative
+    trace, a deviator of ~1e-4 (3D) or ~6e-7 (2D), two strains pair_gap apart."""
+    Q, _ = np.linalg.qr(RNG.standard_normal((d, d)))
+    if np.linalg.det(Q) < 0:
+        Q[:, 0] = -Q[:, 0]
+    if d == 3:
+        eps = np.array([-1e-5 + 1e-4, -1e-5 + 1e-4 + pair_gap, -1e-5 - 2e-4 - pair_gap])
+    else:
+        eps = np.array([-1e-7 + pair_gap / 2, -1e-7 - pair_gap / 2])
+    return Q @ np.diag(np.exp(eps)) @ Q.T
+
+
+@pytest.mark.parametrize("d,gap", [(3, 3e-7), (3, 3e-9), (2, 8e-7)])
+def test_constitutive_tangent_near_apex(orc, d, gap):
+    """Near-isotropic plastic states (projection onto the cone, Eq. DP) with two
+    close singular values: the SVD-frame derivative must use the divided
+    difference of the return map, not its pointwise derivative."""
+    E, nu, phi = 3.5e5, 0.3, 30.0
+    for trial in range(5):
+        F = _near_apex(d, gap)
+        dF = RNG.standard_normal((d, d))
+        cs, Fn, tau, dFn, dtau = orc.constitutive(F, E, nu, phi, dFt=dF)
+        assert cs == 3
+        h = 1e-7 if d == 3 else 2e-11
+
+        def ev(t):
+            c2, a, b, _, _ = orc.constitutive(F + t * dF, E, nu, phi)
+            assert c2 == 3
+            return a, b
+
+        Fp, Tp = ev(h)
+        Fm, Tm = ev(-h)
+        Fp2, Tp2 = ev(2 * h)
+        Fm2, Tm2 = ev(-2 * h)
+        fdF = (8 * (Fp - Fm) - (Fp2 - Fm2)) / (12 * h)
+        fdT = (8 * (Tp - Tm) - (Tp2 - Tm2)) / (12 * h)
+        rt = 1e-5 if d == 3 else 1e-4
+        np.testing.assert_allclose(dFn, fdF, rtol=rt, atol=rt * np.abs(fdF).max())
+        np.testing.assert_allclose(dtau, fdT, rtol=rt, atol=rt * np.abs(fdT).max())
+
+
 @pytest.mark.parametrize("d", [2, 3])
 @pytest.mark.parametrize("kind", ["generic", "identity", "repeated", "plastic"])
 def test_constitutive_tangent_vs_fd(orc, d, kind):
