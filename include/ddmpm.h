@@ -1,0 +1,211 @@
+/*
+ * ddmpm — differentiable MLS-MPM sand simulation on one MI355X (gfx950).
+ *
+ * C interface of libddmpm.so.  The library simulates granular material with
+ * the moving-least-squares material point method and returns exact reverse-mode
+ * gradients of a surface loss with respect to material and skill parameters,
+ * as set out in DDBot (arXiv 2510.17335):
+ *   - the problem: a state s, an action trajectory a(theta) from the digging
+ *     skill and deterministic dynamics s' = f(s, a) (Sec. III-A, "Problem
+ *     definition"), the objective J(theta) = r(o', g) and its gradient
+ *     dr/dtheta by the chain rule of Eq. grad-chain (Sec. III-E);
+ *   - the dynamics: the MLS-MPM sub-step of Algorithm 1 (Sec. III-A) with the
+ *     SVK-Hencky energy (Eqs. SVK, piola), Drucker-Prager plasticity (Eq. DP),
+ *     sigma = P' F'^T / det F' with det F' := 1, a kinematic shovel with
+ *     signed-distance contact and Coulomb friction, and container walls;
+ *   - the skill: four phases (Eqs. d1 .. delta_d4, Algorithm 2) with free
+ *     insert depth, rotate angle and push distance;
+ *   - the loss: the height-map distance of Eq. hm (squared) plus a scoop-mass
+ *     term.
+ *
+ * Conventions
+ *   Frame: y is up, the domain is [0,1]^dim, the grid has n_grid nodes per
+ *   axis (dx = 1/n_grid); the paper's (x, y, z) with z up maps to (x, z, y).
+ *   Memory: every device pointer is caller-owned.  ddm_create takes one
+ *   device workspace of the size ddm_workspace_query reports and never
+ *   allocates device memory; the context itself is a host object owned by
+ *   the library.  Host arrays passed in are copied before the call returns.
+ *   Streams: a context is bound to one HIP stream; all calls enqueue work on
+ *   it and return without waiting, except ddm_validate_config,
+ *   ddm_workspace_query, ddm_check, ddm_read_* and ddm_destroy.  A context is
+ *   not thread-safe.
+ *   Errors: every call returns a ddm_status; nothing throws across the
+ *   interface.  Errors found on the device (NaN, a particle whose stencil
+ *   leaves the grid, clamped singular values) are latched in a device word and
+ *   reported by ddm_check.
+ *   Precision: DDM_F32 or DDM_F64 for all particle and grid arithmetic; the
+ *   parameter-gradient accumulators are always FP64.
+ *   Particle state layout (ddm_get_state / ddm_set_state): structure of
+ *   arrays [2*dim + 2*dim*dim][padded_particles] in the context's precision,
+ *   rows x[dim], v[dim], C[dim*dim], F[dim*dim] (matrices row-major);
+ *   instance i owns columns [ddm_instance_offset(i), + n_particles), each
+ *   instance's range padded to a multiple of 256 columns.
+ */
+#ifndef DDMPM_H
+#define DDMPM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum ddm_status {
+  DDM_OK = 0,
+  DDM_EINVAL = 1,   /* bad configuration or parameter (message via ddm_last_error) */
+  DDM_ENOMEM = 2,   /* workspace too small */
+  DDM_EDEVICE = 3,  /* a HIP call failed */
+  DDM_ENAN = 4,     /* NaN or Inf in the state or a gradient (ddm_check) */
+  DDM_EDOMAIN = 5,  /* a particle's B-spline stencil left the grid (ddm_check) */
+  DDM_ESTATE = 6    /* call out of order, e.g. backward without a recorded rollout */
+} ddm_status;
+
+typedef enum ddm_precision { DDM_F32 = 0, DDM_F64 = 1 } ddm_precision;
+
+/* Problem description shared by all instances of a context. */
+typedef struct ddm_config {
+  int32_t dim;              /* 2 or 3 */
+  int32_t n_grid;           /* nodes per axis, power of two, 16..256 */
+  int32_t bound;            /* sticky wall layers on every face (nodes with index < bound
+                               or >= n_grid - bound get zero velocity) */
+  int32_t precision;        /* ddm_precision */
+  int32_t n_sub;            /* sub-steps per skill action (Sec. III-A, "Actions") */
+  int32_t shovel;           /* 1: kinematic shovel (3D only), 0: none */
+  int32_t hm_res;           /* height-map pixels per axis (40 in the paper) */
+  int32_t region_sign;      /* side of the blade holding the scoop region: +1 or -1 */
+  double gravity;           /* acceleration along y [m/s^2] */
+  double ppc;               /* particles per cell: particle volume V_p = dx^dim / ppc */
+  double shovel_half[3];    /* blade half extents along (width z, normal, pointing) [m] */
+  double contact_skin;      /* nodes closer than this to the blade are in contact [m] */
+  double shovel_mu;         /* Coulomb friction coefficient blade/material */
+  double v_lin;             /* skill linear speed v_l [m/s] */
+  double v_ang;             /* skill angular speed v_w [rad/s] */
+  double d_lift;            /* phase-4 lift distance d4 [m] */
+  double hm_origin[2];      /* (x, z) corner of the height-map window [m] */
+  double hm_size;           /* window edge [m] */
+  double hm_offset;         /* stencil offset r_p of the height map [m] */
+  double region_depth;      /* thickness of the scoop region in front of the blade [m] */
+  double m_target;          /* target scoop mass [kg] */
+  double m_ref;             /* mass normalisation [kg] */
+  double w_mass;            /* weight of the scoop-mass term */
+  double w_hm;              /* weight of the height-map term */
+  int32_t checkpoint_every; /* K: snapshot interval of ddm_rollout (>= 1) */
+  int32_t max_steps;        /* longest rollout the workspace is sized for */
+} ddm_config;
+
+/* One simulation instance: material, skill and time step. */
+typedef struct ddm_instance {
+  int64_t n_particles;      /* particles of this instance (> 0) */
+  double E;                 /* Young's modulus [Pa] (> 0) */
+  double nu;                /* Poisson's ratio, in (-1, 0.5) */
+  double phi_deg;           /* friction angle [deg], in (0, 90) */
+  double rho;               /* density [kg/m^3] (> 0) */
+  double cohesion;          /* [Pa] (>= 0); 0 is the paper's cohesionless sand */
+  double depth;             /* skill: insertion distance d2 [m] */
+  double angle_deg;         /* skill: rotation phi1 [deg] */
+  double push;              /* skill: push distance d3 [m] */
+  double dt;                /* sub-step [s] (> 0) */
+  double tip0[3];           /* initial blade tip [m] */
+} ddm_instance;
+
+/* Sizes reported by ddm_workspace_query. */
+typedef struct ddm_sizes {
+  size_t workspace_bytes;   /* device bytes ddm_create needs */
+  size_t state_bytes;       /* bytes of one instance-concatenated particle state */
+  int64_t padded_particles; /* particle slots after per-instance padding */
+} ddm_sizes;
+
+typedef struct ddm_ctx ddm_ctx;
+
+/* Device-side error report (ddm_check). */
+typedef struct ddm_device_error {
+  uint32_t flags;           /* bit 0: NaN/Inf, bit 1: stencil left the grid, bit 2: sigma clamped */
+  uint32_t first_instance;  /* instance of the first flagged particle */
+  uint64_t clamp_count;     /* singular values clamped to 1e-6 since the last reset */
+} ddm_device_error;
+
+/* Checks a configuration and instance list without touching a device.
+ * Returns DDM_EINVAL with a message in msg (if msg_len > 0) on: dim not 2/3,
+ * n_grid not a power of two in [16, 256], bound out of [0, n_grid/4], shovel
+ * with dim 2, E <= 0, nu outside (-1, 0.5), phi outside (0, 90) deg, rho <= 0,
+ * cohesion < 0, dt <= 0, n_particles <= 0, checkpoint_every < 1. */
+ddm_status ddm_validate_config(const ddm_config* cfg, int32_t n_inst, const ddm_instance* inst,
+                               char* msg, size_t msg_len);
+
+/* Device workspace needed for cfg and these instances (host only). */
+ddm_status ddm_workspace_query(const ddm_config* cfg, int32_t n_inst, const ddm_instance* inst,
+                               ddm_sizes* out);
+
+/* Creates a context on the current HIP device, bound to `stream` (a
+ * hipStream_t, or NULL for the default stream).  `workspace` is caller-owned
+ * device memory of at least workspace_bytes (256-byte aligned); the context
+ * uses it until ddm_destroy.  Builds the per-instance skill pose tables
+ * (Eqs. d1 .. delta_d4, Algorithm 2) on the host and uploads them. */
+ddm_status ddm_create(const ddm_config* cfg, int32_t n_inst, const ddm_instance* inst,
+                      void* workspace, size_t workspace_bytes, void* stream, ddm_ctx** out);
+
+/* Initial particle positions, device pointer to x0[n_total][dim] row-major in
+ * the context's precision, instances concatenated in order.  Sets v = 0,
+ * C = 0, F = I (the flattened bed at rest, Sec. III-A), resets the step
+ * counter, the recorded rollout and the device error word. */
+ddm_status ddm_init_state(ddm_ctx* ctx, const void* x0_dev);
+
+/* Advances every instance by n_steps sub-steps (Algorithm 1), no recording. */
+ddm_status ddm_step(ddm_ctx* ctx, int32_t n_steps);
+
+/* Runs n_steps sub-steps from the initial state and records a snapshot every
+ * checkpoint_every steps, so that ddm_backward can replay the rollout.
+ * n_steps <= max_steps. */
+ddm_status ddm_rollout(ddm_ctx* ctx, int32_t n_steps);
+
+/* Loss of every instance at the current state: height map of Eq. hm (40x40,
+ * five-point stencil, max height) against target_hm_dev
+ * ([n_inst][hm_res^(dim-1)] in double, device), plus the scoop-mass term.
+ * Writes loss_dev[n_inst] (double, device). */
+ddm_status ddm_loss(ddm_ctx* ctx, const double* target_hm_dev, double* loss_dev);
+
+/* Reverse pass of the last ddm_rollout + ddm_loss: with dloss_dev[n_inst]
+ * (double, device) the upstream gradient, writes grad_dev[n_inst][7] (double,
+ * device) = d(sum_i dloss_i * loss_i) / d(E, nu, phi_deg, rho, depth,
+ * angle_deg, push).  Recomputes each checkpoint segment forward, then runs the
+ * adjoint of every sub-step in reverse (Eq. po/pa).  DDM_ESTATE without a
+ * preceding ddm_rollout and ddm_loss. */
+ddm_status ddm_backward(ddm_ctx* ctx, const double* dloss_dev, double* grad_dev);
+
+/* Copies the current particle state (layout above) of all instances into /
+ * from caller device memory of state_bytes. */
+ddm_status ddm_get_state(ddm_ctx* ctx, void* state_dev);
+ddm_status ddm_set_state(ddm_ctx* ctx, const void* state_dev);
+
+/* Copies the grid of the last sub-step (per instance, n_grid^dim nodes,
+ * 8 values each: m, mv[3], v[3], 0) into caller device memory, in the
+ * context's precision.  For kernel-level tests. */
+ddm_status ddm_get_grid(ddm_ctx* ctx, void* grid_dev);
+
+/* Copies the height map of the last ddm_loss ([n_inst][hm_res^(dim-1)],
+ * double) into caller device memory. */
+ddm_status ddm_get_heightmap(ddm_ctx* ctx, double* hm_dev);
+
+/* Synchronises the stream and reads the device error word. */
+ddm_status ddm_check(ddm_ctx* ctx, ddm_device_error* out);
+
+/* Sub-steps taken since ddm_init_state. */
+int64_t ddm_steps_taken(const ddm_ctx* ctx);
+
+/* First state column of instance i (see the state layout), or -1. */
+int64_t ddm_instance_offset(const ddm_ctx* ctx, int32_t i);
+
+/* Releases the host context (the workspace stays the caller's). */
+void ddm_destroy(ddm_ctx* ctx);
+
+/* Static description of a status code, and the message of the last failing
+ * call on this thread. */
+const char* ddm_status_str(ddm_status s);
+const char* ddm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DDMPM_H */

@@ -1,0 +1,360 @@
+"""Python binding of libddmpm.so (differentiable MLS-MPM sand digging on MI355X).
+
+Argument marshalling only: every step of the simulation, the loss and the
+reverse pass runs in the library's HIP kernels.  PyTorch provides device
+memory (the workspace is one uint8 tensor) and the stream.  If the library is
+not built, importing works but creating a Simulator raises.
+
+The calls mirror include/ddmpm.h: validate_config, workspace_query, create,
+init_state, step, rollout, loss, backward, get_state / set_state, get_grid,
+get_heightmap, check.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libddmpm.so")
+
+DDM_OK, DDM_EINVAL, DDM_ENOMEM, DDM_EDEVICE, DDM_ENAN, DDM_EDOMAIN, DDM_ESTATE = range(7)
+DDM_F32, DDM_F64 = 0, 1
+PARAM_NAMES = ("E", "nu", "phi_deg", "rho", "depth", "angle_deg", "push")
+
+
+class DdmConfig(C.Structure):
+    _fields_ = [
+        ("dim", C.c_int32), ("n_grid", C.c_int32), ("bound", C.c_int32), ("precision", C.c_int32),
+        ("n_sub", C.c_int32), ("shovel", C.c_int32), ("hm_res", C.c_int32), ("region_sign", C.c_int32),
+        ("gravity", C.c_double), ("ppc", C.c_double), ("shovel_half", C.c_double * 3),
+        ("contact_skin", C.c_double), ("shovel_mu", C.c_double), ("v_lin", C.c_double),
+        ("v_ang", C.c_double), ("d_lift", C.c_double), ("hm_origin", C.c_double * 2), ("hm_size", C.c_double),
+        ("hm_offset", C.c_double), ("region_depth", C.c_double), ("m_target", C.c_double), ("m_ref", C.c_double),
+        ("w_mass", C.c_double), ("w_hm", C.c_double), ("checkpoint_every", C.c_int32), ("max_steps", C.c_int32),
+    ]
+
+
+class DdmInstance(C.Structure):
+    _fields_ = [
+        ("n_particles", C.c_int64), ("E", C.c_double), ("nu", C.c_double), ("phi_deg", C.c_double),
+        ("rho", C.c_double), ("cohesion", C.c_double), ("depth", C.c_double), ("angle_deg", C.c_double),
+        ("push", C.c_double), ("dt", C.c_double), ("tip0", C.c_double * 3),
+    ]
+
+
+class DdmSizes(C.Structure):
+    _fields_ = [("workspace_bytes", C.c_size_t), ("state_bytes", C.c_size_t), ("padded_particles", C.c_int64)]
+
+
+class DdmDeviceError(C.Structure):
+    _fields_ = [("flags", C.c_uint32), ("first_instance", C.c_uint32), ("clamp_count", C.c_uint64)]
+
+
+class DdmError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"ddmpm error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run __graft_entry__.build() (hipcc, gfx950) first")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+        cfgp, instp = C.POINTER(DdmConfig), C.POINTER(DdmInstance)
+        sig = {
+            "ddm_validate_config": (C.c_int, [cfgp, i32, instp, C.c_char_p, C.c_size_t]),
+            "ddm_workspace_query": (C.c_int, [cfgp, i32, instp, C.POINTER(DdmSizes)]),
+            "ddm_create": (C.c_int, [cfgp, i32, instp, vp, C.c_size_t, vp, C.POINTER(vp)]),
+            "ddm_init_state": (C.c_int, [vp, vp]),
+            "ddm_step": (C.c_int, [vp, i32]),
+            "ddm_rollout": (C.c_int, [vp, i32]),
+            "ddm_loss": (C.c_int, [vp, vp, vp]),
+            "ddm_backward": (C.c_int, [vp, vp, vp]),
+            "ddm_get_state": (C.c_int, [vp, vp]),
+            "ddm_set_state": (C.c_int, [vp, vp]),
+            "ddm_get_grid": (C.c_int, [vp, vp]),
+            "ddm_get_heightmap": (C.c_int, [vp, vp]),
+            "ddm_check": (C.c_int, [vp, C.POINTER(DdmDeviceError)]),
+            "ddm_steps_taken": (i64, [vp]),
+            "ddm_instance_offset": (i64, [vp, i32]),
+            "ddm_destroy": (None, [vp]),
+            "ddm_status_str": (C.c_char_p, [C.c_int]),
+            "ddm_last_error": (C.c_char_p, []),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != DDM_OK:
+        L = lib()
+        raise DdmError(rc, f"{L.ddm_status_str(rc).decode()}: {L.ddm_last_error().decode()}")
+
+
+# ---------------------------------------------------------------------------
+# Configuration helpers
+# ---------------------------------------------------------------------------
+
+def make_config(dim: int, n_grid: int, precision: str = "f32", *, bound: int = 3, n_sub: int = 10,
+                shovel: bool = False, gravity: float = -9.8, ppc: float = 8.0,
+                shovel_half=(0.05, 0.0025, 0.04), contact_skin: Optional[float] = None, shovel_mu: float = 0.5,
+                v_lin: float = 3.0, v_ang: float = 10 * math.pi, d_lift: float = 0.01, hm_res: int = 40,
+                hm_origin=(0.2, 0.2), hm_size: float = 0.6, hm_offset: Optional[float] = None,
+                region_depth: float = 0.03, m_target: float = 0.192, m_ref: float = 0.384, w_mass: float = 1.0,
+                w_hm: float = 1.0, region_sign: int = -1, checkpoint_every: int = 50,
+                max_steps: int = 1000) -> DdmConfig:
+    c = DdmConfig()
+    c.dim, c.n_grid, c.bound = dim, n_grid, bound
+    c.precision = DDM_F64 if precision == "f64" else DDM_F32
+    c.n_sub, c.shovel, c.hm_res, c.region_sign = n_sub, int(shovel), hm_res, region_sign
+    c.gravity, c.ppc = gravity, float(ppc)
+    for k in range(3):
+        c.shovel_half[k] = shovel_half[k]
+    c.contact_skin = 1.0 / n_grid if contact_skin is None else contact_skin
+    c.shovel_mu, c.v_lin, c.v_ang, c.d_lift = shovel_mu, v_lin, v_ang, d_lift
+    c.hm_origin[0], c.hm_origin[1] = hm_origin
+    c.hm_size = hm_size
+    c.hm_offset = (1.0 / n_grid) / round(ppc ** (1.0 / dim)) if hm_offset is None else hm_offset
+    c.region_depth, c.m_target, c.m_ref, c.w_mass, c.w_hm = region_depth, m_target, m_ref, w_mass, w_hm
+    c.checkpoint_every, c.max_steps = checkpoint_every, max_steps
+    return c
+
+
+def make_instance(n_particles: int, *, E=3.5e5, nu=0.3, phi_deg=30.0, rho=1600.0, cohesion=0.0, depth=0.05,
+                  angle_deg=30.0, push=0.15, dt=2e-4, tip0=(0.5, 0.34375, 0.5)) -> DdmInstance:
+    s = DdmInstance()
+    s.n_particles = int(n_particles)
+    s.E, s.nu, s.phi_deg, s.rho, s.cohesion = E, nu, phi_deg, rho, cohesion
+    s.depth, s.angle_deg, s.push, s.dt = depth, angle_deg, push, dt
+    t = list(tip0) + [0.0] * (3 - len(tip0))
+    for k in range(3):
+        s.tip0[k] = t[k]
+    return s
+
+
+def from_workload(w, max_steps: Optional[int] = None, checkpoint_every: Optional[int] = None,
+                  precision: Optional[str] = None):
+    """(config, instance) for an object with the attributes of a workload
+    description (dim, n_grid, dt, ppc, material, skill, ...)."""
+    cfg = make_config(
+        w.dim, w.n_grid, precision or w.precision, bound=w.bound, n_sub=w.n_sub, shovel=w.skill is not None,
+        gravity=w.gravity, ppc=w.ppc, shovel_half=w.shovel_half, contact_skin=w.skin, shovel_mu=w.mu_b,
+        v_lin=w.v_l, v_ang=w.v_w, d_lift=w.d_lift, hm_res=w.hm_res, hm_origin=w.hm_origin, hm_size=w.hm_size,
+        hm_offset=w.hm_offset, region_depth=w.region_depth, m_target=w.m_target, m_ref=w.m_ref, w_mass=w.w_mass,
+        w_hm=w.w_hm, region_sign=w.region_sign,
+        checkpoint_every=checkpoint_every or w.checkpoint_every or 50,
+        max_steps=max_steps or w.steps)
+    p = w.params7
+    inst = make_instance(w.n_particles, E=p[0], nu=p[1], phi_deg=p[2], rho=p[3], cohesion=w.material.cohesion,
+                         depth=p[4], angle_deg=p[5], push=p[6], dt=w.dt, tip0=w.tip0)
+    return cfg, inst
+
+
+def validate_config(cfg: DdmConfig, instances: Sequence[DdmInstance]) -> str:
+    """Empty string when valid, else the library's message (host only)."""
+    arr = (DdmInstance * len(instances))(*instances)
+    buf = C.create_string_buffer(512)
+    rc = lib().ddm_validate_config(C.byref(cfg), len(instances), arr, buf, 512)
+    return "" if rc == DDM_OK else buf.value.decode()
+
+
+def workspace_query(cfg: DdmConfig, instances: Sequence[DdmInstance]) -> DdmSizes:
+    arr = (DdmInstance * len(instances))(*instances)
+    out = DdmSizes()
+    _check(lib().ddm_workspace_query(C.byref(cfg), len(instances), arr, C.byref(out)))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Simulator
+# ---------------------------------------------------------------------------
+
+class Simulator:
+    """One library context: n instances sharing a configuration."""
+
+    def __init__(self, cfg: DdmConfig, instances: Sequence[DdmInstance], device="cuda", stream=None):
+        import torch
+        self.torch = torch
+        self.cfg = cfg
+        self.instances = list(instances)
+        self.n_inst = len(self.instances)
+        self.device = torch.device(device)
+        self.dtype = torch.float64 if cfg.precision == DDM_F64 else torch.float32
+        self.dim = cfg.dim
+        self.sizes = workspace_query(cfg, self.instances)
+        self.workspace = torch.empty(int(self.sizes.workspace_bytes), dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        arr = (DdmInstance * self.n_inst)(*self.instances)
+        ctx = C.c_void_p()
+        _check(lib().ddm_create(C.byref(cfg), self.n_inst, arr, C.c_void_p(self.workspace.data_ptr()),
+                                int(self.sizes.workspace_bytes), C.c_void_p(self.stream.cuda_stream), C.byref(ctx)))
+        self.ctx = ctx
+        self.offsets = [int(lib().ddm_instance_offset(ctx, i)) for i in range(self.n_inst)]
+        self.counts = [int(s.n_particles) for s in self.instances]
+        self.npix = cfg.hm_res ** (cfg.dim - 1)
+
+    def __del__(self):
+        ctx = getattr(self, "ctx", None)
+        if ctx and _lib is not None:
+            try:
+                self.stream.synchronize()
+                _lib.ddm_destroy(ctx)
+            except Exception:
+                pass
+            self.ctx = None
+
+    # -- state ---------------------------------------------------------------
+    @property
+    def state_rows(self) -> int:
+        d = self.dim
+        return 2 * d + 2 * d * d
+
+    def init_state(self, x0):
+        """x0: [sum N_i, dim] positions (numpy or torch), instances concatenated."""
+        t = self.torch
+        x0 = t.as_tensor(np.asarray(x0) if not isinstance(x0, t.Tensor) else x0)
+        self._x0 = x0.to(device=self.device, dtype=self.dtype).contiguous()
+        assert self._x0.shape == (sum(self.counts), self.dim)
+        _check(lib().ddm_init_state(self.ctx, C.c_void_p(self._x0.data_ptr())))
+
+    def step(self, n: int):
+        _check(lib().ddm_step(self.ctx, int(n)))
+
+    def rollout(self, n: int):
+        _check(lib().ddm_rollout(self.ctx, int(n)))
+
+    @property
+    def steps_taken(self) -> int:
+        return int(lib().ddm_steps_taken(self.ctx))
+
+    def get_state(self):
+        """Raw [rows, padded_particles] state tensor (a copy)."""
+        out = self.torch.empty((self.state_rows, int(self.sizes.padded_particles)), dtype=self.dtype,
+                               device=self.device)
+        _check(lib().ddm_get_state(self.ctx, C.c_void_p(out.data_ptr())))
+        return out
+
+    def set_state(self, state):
+        state = state.to(device=self.device, dtype=self.dtype).contiguous()
+        assert state.shape == (self.state_rows, int(self.sizes.padded_particles))
+        self._set_state_keep = state
+        _check(lib().ddm_set_state(self.ctx, C.c_void_p(state.data_ptr())))
+
+    def instance_state(self, state, i: int):
+        """(x, v, C, F) of instance i as [N, dim], [N, dim], [N, dim, dim], [N, dim, dim]."""
+        d, o, n = self.dim, self.offsets[i], self.counts[i]
+        s = state[:, o:o + n]
+        x = s[:d].T
+        v = s[d:2 * d].T
+        Cm = s[2 * d:2 * d + d * d].T.reshape(n, d, d)
+        F = s[2 * d + d * d:].T.reshape(n, d, d)
+        return x, v, Cm, F
+
+    def packed_state(self, i: int = 0) -> np.ndarray:
+        """Instance i as a float64 [N, 2d + 2d^2] array (x, v, C, F rows per particle)."""
+        st = self.get_state()
+        x, v, Cm, F = self.instance_state(st, i)
+        n = self.counts[i]
+        out = self.torch.cat([x, v, Cm.reshape(n, -1), F.reshape(n, -1)], dim=1)
+        return out.double().cpu().numpy()
+
+    def get_grid(self):
+        nodes = self.cfg.n_grid ** self.dim
+        out = self.torch.empty((self.n_inst, nodes, 8), dtype=self.dtype, device=self.device)
+        _check(lib().ddm_get_grid(self.ctx, C.c_void_p(out.data_ptr())))
+        return out
+
+    # -- loss and gradient ---------------------------------------------------
+    def loss(self, target):
+        """target: [n_inst, npix] float64 (numpy or torch). Returns loss [n_inst] (device, float64)."""
+        t = self.torch
+        tg = t.as_tensor(np.asarray(target) if not isinstance(target, t.Tensor) else target)
+        self._target = tg.to(device=self.device, dtype=t.float64).reshape(self.n_inst, self.npix).contiguous()
+        out = t.empty(self.n_inst, dtype=t.float64, device=self.device)
+        _check(lib().ddm_loss(self.ctx, C.c_void_p(self._target.data_ptr()), C.c_void_p(out.data_ptr())))
+        return out
+
+    def heightmap(self):
+        out = self.torch.empty((self.n_inst, self.npix), dtype=self.torch.float64, device=self.device)
+        _check(lib().ddm_get_heightmap(self.ctx, C.c_void_p(out.data_ptr())))
+        return out
+
+    def backward(self, dloss=None):
+        """Gradient [n_inst, 7] of sum(dloss * loss) w.r.t. PARAM_NAMES."""
+        t = self.torch
+        if dloss is None:
+            dloss = t.ones(self.n_inst, dtype=t.float64, device=self.device)
+        dl = t.as_tensor(dloss, dtype=t.float64).to(self.device).contiguous()
+        grad = t.empty((self.n_inst, 7), dtype=t.float64, device=self.device)
+        _check(lib().ddm_backward(self.ctx, C.c_void_p(dl.data_ptr()), C.c_void_p(grad.data_ptr())))
+        self._keep = dl
+        return grad
+
+    def check(self) -> DdmDeviceError:
+        e = DdmDeviceError()
+        _check(lib().ddm_check(self.ctx, C.byref(e)))
+        return e
+
+
+# ---------------------------------------------------------------------------
+# autograd
+# ---------------------------------------------------------------------------
+
+def _autograd_function():
+    import torch
+
+    class DigLoss(torch.autograd.Function):
+        """loss[n_inst] = rollout + loss of the digging simulation; gradients with
+        respect to params[n_inst, 7] = (E, nu, phi_deg, rho, depth, angle_deg,
+        push) come from the library's reverse pass (checkpointed recompute)."""
+
+        @staticmethod
+        def forward(ctx, params, x0, target, cfg, instances, steps):
+            p = params.detach().double().cpu().numpy()
+            insts = []
+            for i, base in enumerate(instances):
+                s = DdmInstance()
+                C.pointer(s)[0] = base
+                s.E, s.nu, s.phi_deg, s.rho, s.depth, s.angle_deg, s.push = (float(v) for v in p[i])
+                insts.append(s)
+            sim = Simulator(cfg, insts, device=x0.device if isinstance(x0, torch.Tensor) else "cuda")
+            sim.init_state(x0)
+            sim.rollout(steps)
+            loss = sim.loss(target)
+            ctx.sim = sim
+            ctx.param_device = params.device
+            ctx.param_dtype = params.dtype
+            return loss.to(params.device)
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            g = ctx.sim.backward(grad_out.detach().to(ctx.sim.device, torch.float64))
+            return g.to(ctx.param_device, ctx.param_dtype), None, None, None, None, None
+
+    return DigLoss
+
+
+_DIGLOSS = None
+
+
+def dig_loss(params, x0, target, cfg: DdmConfig, instances: Sequence[DdmInstance], steps: int):
+    """Differentiable loss per instance; see DigLoss."""
+    global _DIGLOSS
+    if _DIGLOSS is None:
+        _DIGLOSS = _autograd_function()
+    return _DIGLOSS.apply(params, x0, target, cfg, list(instances), int(steps))

@@ -1,0 +1,553 @@
+// Device math of the MLS-MPM sub-step for gfx950: small fixed-size matrix
+// helpers, the SVD of F, the Drucker-Prager return map with its adjoint, the
+// isotropic-function adjoint that carries gradients through the SVD, and the
+// shovel contact with its adjoint.  Everything lives in registers; T is float
+// or double, D is 2 or 3.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ddm {
+
+template <typename T> struct Lim;
+template <> struct Lim<float> {
+  static constexpr int sweeps = 6;
+  static __device__ __forceinline__ float tol() { return 1e-7f; }
+};
+template <> struct Lim<double> {
+  static constexpr int sweeps = 12;
+  static __device__ __forceinline__ double tol() { return 1e-16; }
+};
+
+template <typename T> __device__ __forceinline__ T dsqrt(T x) { return sqrt(x); }
+template <typename T> __device__ __forceinline__ T dabs(T x) { return x < T(0) ? -x : x; }
+
+// Sigma below this is clamped before the logarithm (ln S must exist).
+template <typename T> __device__ __forceinline__ T sigma_min() { return T(1e-6); }
+
+// ---------------------------------------------------------------------------
+// SVD  F = U diag(s) V^T  with U, V in SO(D).
+// Eigen-decomposition of the symmetric A = F^T F by cyclic Jacobi rotations
+// (stopped when the off-diagonal part is below tol relative to the diagonal),
+// eigenvalues sorted in decreasing order, then a Givens QR of B = F V gives U
+// and the singular values on the diagonal of R; the last one carries the sign
+// of det F.  Robust for rank-deficient F because U comes from the QR.
+// ---------------------------------------------------------------------------
+template <typename T, int D>
+__device__ __forceinline__ void svd(const T F[3][3], T U[3][3], T s[3], T V[3][3]) {
+  T a[3][3];
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      T acc = T(0);
+#pragma unroll
+      for (int k = 0; k < D; ++k) acc += F[k][i] * F[k][j];
+      a[i][j] = acc;
+    }
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) V[i][j] = T(i == j ? 1 : 0);
+
+  for (int sweep = 0; sweep < Lim<T>::sweeps; ++sweep) {
+    T off = T(0), dia = T(0);
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      dia += a[i][i] * a[i][i];
+#pragma unroll
+      for (int j = i + 1; j < D; ++j) off += a[i][j] * a[i][j];
+    }
+    if (!(off > Lim<T>::tol() * Lim<T>::tol() * dia)) break;
+#pragma unroll
+    for (int pq = 0; pq < (D == 3 ? 3 : 1); ++pq) {
+      const int p = pq == 2 ? 1 : 0;
+      const int q = pq == 0 ? 1 : 2;
+      const T apq = a[p][q];
+      if (apq == T(0)) continue;
+      const T theta = (a[q][q] - a[p][p]) / (T(2) * apq);
+      const T t = (theta >= T(0) ? T(1) : T(-1)) / (dabs(theta) + dsqrt(theta * theta + T(1)));
+      const T c = T(1) / dsqrt(t * t + T(1));
+      const T sn = t * c;
+      a[p][p] -= t * apq;
+      a[q][q] += t * apq;
+      a[p][q] = a[q][p] = T(0);
+      if (D == 3) {
+        const int r = 3 - p - q;
+        const T arp = a[r][p], arq = a[r][q];
+        a[r][p] = a[p][r] = c * arp - sn * arq;
+        a[r][q] = a[q][r] = sn * arp + c * arq;
+      }
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        const T vp = V[k][p], vq = V[k][q];
+        V[k][p] = c * vp - sn * vq;
+        V[k][q] = sn * vp + c * vq;
+      }
+    }
+  }
+  // Sort eigenvalues in decreasing order; each column swap is paired with a
+  // sign flip so that det V stays +1.
+  T ev[3] = {a[0][0], a[1][1], D == 3 ? a[2][2] : T(0)};
+  auto swap_cols = [&](int i, int j) {
+    const T t = ev[i]; ev[i] = ev[j]; ev[j] = t;
+#pragma unroll
+    for (int k = 0; k < D; ++k) { const T u = V[k][i]; V[k][i] = V[k][j]; V[k][j] = -u; }
+  };
+  if (ev[0] < ev[1]) swap_cols(0, 1);
+  if (D == 3) {
+    if (ev[0] < ev[2]) swap_cols(0, 2);
+    if (ev[1] < ev[2]) swap_cols(1, 2);
+  }
+  // B = F V, then Givens rotations zero its sub-diagonal: G B = R, U = G^T.
+  T B[3][3];
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      T acc = T(0);
+#pragma unroll
+      for (int k = 0; k < D; ++k) acc += F[i][k] * V[k][j];
+      B[i][j] = acc;
+    }
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) U[i][j] = T(i == j ? 1 : 0);
+  auto givens = [&](int i, int j, int col) {   // zero B[j][col] against B[i][col]
+    const T x = B[i][col], y = B[j][col];
+    const T r = dsqrt(x * x + y * y);
+    T c = T(1), sn = T(0);
+    if (r > T(0)) { c = x / r; sn = y / r; }
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      const T bi = B[i][k], bj = B[j][k];
+      B[i][k] = c * bi + sn * bj;
+      B[j][k] = -sn * bi + c * bj;
+      const T ui = U[k][i], uj = U[k][j];     // U = G1^T G2^T ... accumulates columns
+      U[k][i] = c * ui + sn * uj;
+      U[k][j] = -sn * ui + c * uj;
+    }
+  };
+  givens(0, 1, 0);
+  if (D == 3) {
+    givens(0, 2, 0);
+    givens(1, 2, 1);
+  }
+  s[0] = B[0][0];
+  s[1] = B[1][1];
+  s[2] = D == 3 ? B[2][2] : T(1);
+}
+
+// ---------------------------------------------------------------------------
+// Drucker-Prager return map on eps = ln s (Eq. DP), forward.
+// Cases: 1 tension (tr eps > 0, or beyond the shifted apex with cohesion):
+// eps' = apex; 2 inside the cone: eps' = eps; 3 projection onto the cone:
+// eps' = (tr/D) 1 - beta n, n = dev(eps)/|dev(eps)|,
+// beta = (alpha (D lam + 2 mu) tr - k_c) / (2 mu).
+// Outputs g = exp(eps') (plastic singular values) and the principal Kirchhoff
+// stresses h = 2 mu eps' + lam tr(eps').
+// ---------------------------------------------------------------------------
+template <typename T> struct DP {
+  T eps[3], ep[3], g[3], h[3];
+  T tr, nrm, beta, apex, stiff;
+  int cs;
+};
+
+template <typename T, int D>
+__device__ __forceinline__ void dp_forward(const T s[3], T mu, T lam, T alpha, T kc, DP<T>& o) {
+  o.tr = T(0);
+#pragma unroll
+  for (int i = 0; i < D; ++i) { o.eps[i] = log(s[i]); o.tr += o.eps[i]; }
+  T n2 = T(0), dev[3];
+#pragma unroll
+  for (int i = 0; i < D; ++i) { dev[i] = o.eps[i] - o.tr / T(D); n2 += dev[i] * dev[i]; }
+  o.nrm = n2 > T(0) ? dsqrt(n2) : T(0);
+  o.stiff = T(D) * lam + T(2) * mu;
+  o.beta = T(0);
+  o.apex = T(0);
+  const bool tension = (kc == T(0)) ? (o.tr > T(0)) : (alpha * o.stiff * o.tr > kc);
+  if (tension) {
+    o.cs = 1;
+    o.apex = kc / (T(D) * alpha * o.stiff);
+#pragma unroll
+    for (int i = 0; i < D; ++i) o.ep[i] = o.apex;
+  } else {
+    o.beta = (alpha * o.stiff * o.tr - kc) / (T(2) * mu);
+    const T dgam = o.nrm + o.beta;
+    if (!(dgam > T(0))) {
+      o.cs = 2;
+#pragma unroll
+      for (int i = 0; i < D; ++i) o.ep[i] = o.eps[i];
+    } else {
+      o.cs = 3;
+#pragma unroll
+      for (int i = 0; i < D; ++i) o.ep[i] = o.eps[i] - dgam * dev[i] / o.nrm;
+    }
+  }
+  T tre = T(0);
+#pragma unroll
+  for (int i = 0; i < D; ++i) tre += o.ep[i];
+#pragma unroll
+  for (int i = 0; i < D; ++i) { o.g[i] = exp(o.ep[i]); o.h[i] = T(2) * mu * o.ep[i] + lam * tre; }
+#pragma unroll
+  for (int i = D; i < 3; ++i) { o.g[i] = T(1); o.h[i] = T(0); o.eps[i] = o.ep[i] = T(0); }
+}
+
+// Adjoint of dp_forward: (gbar, hbar) -> sbar and material adjoints.
+template <typename T, int D>
+__device__ __forceinline__ void dp_backward(const DP<T>& o, const T s[3], T mu, T lam, T alpha, T kc,
+                                            const T gbar[3], const T hbar[3], T sbar[3], T& mub, T& lamb,
+                                            T& alb, T& kcb) {
+  T hsum = T(0), tre = T(0);
+#pragma unroll
+  for (int i = 0; i < D; ++i) { hsum += hbar[i]; tre += o.ep[i]; }
+  T epb[3];
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    epb[i] = gbar[i] * o.g[i] + T(2) * mu * hbar[i] + lam * hsum;
+    mub += T(2) * hbar[i] * o.ep[i];
+  }
+  lamb += hsum * tre;
+  T eb[3] = {T(0), T(0), T(0)};
+  if (o.cs == 2) {
+#pragma unroll
+    for (int i = 0; i < D; ++i) eb[i] = epb[i];
+  } else if (o.cs == 1) {
+    if (kc != T(0)) {
+      T ab = T(0);
+#pragma unroll
+      for (int i = 0; i < D; ++i) ab += epb[i];
+      // apex = kc / (D alpha stiff)
+      kcb += ab / (T(D) * alpha * o.stiff);
+      alb -= ab * o.apex / alpha;
+      const T sb = -ab * o.apex / o.stiff;
+      lamb += T(D) * sb;
+      mub += T(2) * sb;
+    }
+  } else {
+    // eps' = (tr/D) 1 - beta n
+    T nvec[3], trb = T(0), betab = T(0);
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      nvec[i] = (o.eps[i] - o.tr / T(D)) / o.nrm;
+      trb += epb[i] / T(D);
+      betab -= epb[i] * nvec[i];
+    }
+    T nb[3], nbn = T(0);
+#pragma unroll
+    for (int i = 0; i < D; ++i) { nb[i] = -o.beta * epb[i]; nbn += nb[i] * nvec[i]; }
+    // beta = (alpha stiff tr - kc) / (2 mu)
+    const T inv2mu = T(1) / (T(2) * mu);
+    trb += betab * alpha * o.stiff * inv2mu;
+    alb += betab * o.stiff * o.tr * inv2mu;
+    kcb -= betab * inv2mu;
+    const T sb = betab * alpha * o.tr * inv2mu;
+    mub += -betab * o.beta / mu + T(2) * sb;
+    lamb += T(D) * sb;
+    // n = dev / |dev|, dev = eps - tr/D
+    T devb[3], devbs = T(0);
+#pragma unroll
+    for (int i = 0; i < D; ++i) { devb[i] = (nb[i] - nbn * nvec[i]) / o.nrm; devbs += devb[i]; }
+#pragma unroll
+    for (int i = 0; i < D; ++i) eb[i] = devb[i] - devbs / T(D) + trb;
+  }
+#pragma unroll
+  for (int i = 0; i < D; ++i) sbar[i] = eb[i] / s[i];
+}
+
+// Divided differences of g and h across a pair of singular values, without
+// cancellation: eps'_i - eps'_j = k (eps_i - eps_j) with k = 1 (case 2),
+// 0 (case 1) or -beta/|dev| (case 3), and eps_i - eps_j = log1p((s_i-s_j)/s_j).
+template <typename T>
+__device__ __forceinline__ void divided(const DP<T>& o, T mu, T si, T sj, T gj, T& ddg, T& ddh, T& y) {
+  const T k = o.cs == 2 ? T(1) : (o.cs == 1 ? T(0) : -o.beta / o.nrm);
+  const T ds = si - sj;
+  const T de = log1p(ds / sj);
+  const T dl = ds != T(0) ? de / ds : T(1) / sj;       // (eps_i - eps_j) / (s_i - s_j)
+  y = k * de;                                            // eps'_i - eps'_j
+  const T em1 = y != T(0) ? expm1(y) / y : T(1);
+  ddg = gj * em1 * k * dl;
+  ddh = T(2) * mu * k * dl;
+}
+
+// ---------------------------------------------------------------------------
+// Constitutive update of one particle: F' = U diag(g) V^T, tau = U diag(h) U^T.
+// ---------------------------------------------------------------------------
+template <typename T, int D> struct Constit {
+  T U[3][3], V[3][3], s[3];
+  bool clamped[3];
+  int nclamp;
+  DP<T> dp;
+};
+
+template <typename T, int D>
+__device__ __forceinline__ void constit_forward(const T Ft[3][3], T mu, T lam, T alpha, T kc, Constit<T, D>& c) {
+  svd<T, D>(Ft, c.U, c.s, c.V);
+  c.nclamp = 0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    c.clamped[i] = false;
+    if (i < D && !(c.s[i] >= sigma_min<T>())) { c.s[i] = sigma_min<T>(); c.clamped[i] = true; ++c.nclamp; }
+  }
+  dp_forward<T, D>(c.s, mu, lam, alpha, kc, c.dp);
+}
+
+template <typename T, int D>
+__device__ __forceinline__ void constit_outputs(const Constit<T, D>& c, T Fn[3][3], T tau[3][3]) {
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      T a = T(0), b = T(0);
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        a += c.U[i][k] * c.dp.g[k] * c.V[j][k];
+        b += c.U[i][k] * c.dp.h[k] * c.U[j][k];
+      }
+      Fn[i][j] = a;
+      tau[i][j] = b;
+    }
+}
+
+// Adjoint of (F_tmp -> F', tau) for adjoints Fnb (of F') and taub (of tau).
+// In the SVD frame, with sym/skw the symmetric/skew parts of dF~ = U^T dF V,
+// dG~_ij = ddg sym + cg skw, dG~_ji = ddg sym - cg skw, dT~_ij = dT~_ji =
+// ddh sym + ch skw; the diagonal goes through s and the return map.
+template <typename T, int D>
+__device__ __forceinline__ void constit_backward(const Constit<T, D>& c, T mu, T lam, T alpha, T kc,
+                                                 const T Fnb[3][3], const T taub[3][3], T Ftb[3][3], T& mub,
+                                                 T& lamb, T& alb, T& kcb) {
+  T Gb[3][3], Tb[3][3];
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      T a = T(0), b = T(0);
+#pragma unroll
+      for (int p = 0; p < D; ++p)
+#pragma unroll
+        for (int q = 0; q < D; ++q) {
+          a += c.U[p][i] * Fnb[p][q] * c.V[q][j];
+          b += c.U[p][i] * taub[p][q] * c.U[q][j];
+        }
+      Gb[i][j] = a;
+      Tb[i][j] = b;
+    }
+  T gb[3], hb[3], sb[3];
+#pragma unroll
+  for (int i = 0; i < D; ++i) { gb[i] = Gb[i][i]; hb[i] = Tb[i][i]; }
+  dp_backward<T, D>(c.dp, c.s, mu, lam, alpha, kc, gb, hb, sb, mub, lamb, alb, kcb);
+  T Fb[3][3];
+#pragma unroll
+  for (int i = 0; i < D; ++i) Fb[i][i] = c.clamped[i] ? T(0) : sb[i];
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = i + 1; j < D; ++j) {
+      T ddg, ddh, y;
+      divided<T>(c.dp, mu, c.s[i], c.s[j], c.dp.g[j], ddg, ddh, y);
+      const T sum = c.s[i] + c.s[j];
+      const T cg = (c.dp.g[i] + c.dp.g[j]) / sum;
+      const T ch = -T(2) * mu * y / sum;
+      const T tsym = Tb[i][j] + Tb[j][i];
+      const T symb = ddg * (Gb[i][j] + Gb[j][i]) + ddh * tsym;
+      const T skwb = cg * (Gb[i][j] - Gb[j][i]) + ch * tsym;
+      Fb[i][j] = T(0.5) * (symb + skwb);
+      Fb[j][i] = T(0.5) * (symb - skwb);
+    }
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      T a = T(0);
+#pragma unroll
+      for (int p = 0; p < D; ++p)
+#pragma unroll
+        for (int q = 0; q < D; ++q) a += c.U[i][p] * Fb[p][q] * c.V[j][q];
+      Ftb[i][j] = a;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Shovel: oriented box about the tip.  Axes e_w = z, e_n = (cos psi, -sin psi, 0),
+// e_p = (-sin psi, -cos psi, 0) (pointing); centre = tip - half_p e_p.
+// ---------------------------------------------------------------------------
+template <typename T> struct Blade {
+  T tip[3], psi, vel[3], omega;   // pose and velocity of the sub-step
+  T sp, cp;                       // sin/cos psi
+};
+
+template <typename T> struct SDF {
+  T loc[3], q[3], o[3], od;  // local coordinates, q = |loc| - half, outside offsets
+  T n[3];                     // world normal
+  T phi;
+  int inside_axis;            // -1 when outside
+};
+
+template <typename T>
+__device__ __forceinline__ void blade_axes(const Blade<T>& b, T e[3][3]) {
+  e[0][0] = T(0); e[0][1] = T(0); e[0][2] = T(1);
+  e[1][0] = b.cp; e[1][1] = -b.sp; e[1][2] = T(0);
+  e[2][0] = -b.sp; e[2][1] = -b.cp; e[2][2] = T(0);
+}
+
+template <typename T>
+__device__ __forceinline__ void sdf_eval(const Blade<T>& b, const T half[3], const T x[3], SDF<T>& f) {
+  T e[3][3];
+  blade_axes(b, e);
+  T d[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) d[k] = x[k] - b.tip[k] + half[2] * e[2][k];
+  bool outside = false;
+  T o2 = T(0);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    f.loc[a] = d[0] * e[a][0] + d[1] * e[a][1] + d[2] * e[a][2];
+    f.q[a] = dabs(f.loc[a]) - half[a];
+    const T sg = f.loc[a] >= T(0) ? T(1) : T(-1);
+    f.o[a] = f.q[a] > T(0) ? sg * f.q[a] : T(0);
+    if (f.q[a] > T(0)) { outside = true; o2 += f.q[a] * f.q[a]; }
+  }
+  T nl[3];
+  if (outside) {
+    f.od = dsqrt(o2);
+    f.phi = f.od;
+    f.inside_axis = -1;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) nl[a] = f.o[a] / f.od;
+  } else {
+    int am = 0;
+    if (f.q[1] > f.q[am]) am = 1;
+    if (f.q[2] > f.q[am]) am = 2;
+    f.phi = f.q[am];
+    f.od = T(0);
+    f.inside_axis = am;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) nl[a] = T(0);
+    nl[am] = f.loc[am] >= T(0) ? T(1) : T(-1);
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) f.n[k] = nl[0] * e[0][k] + nl[1] * e[1][k] + nl[2] * e[2][k];
+}
+
+// Adjoint of the normal with respect to the blade pose (tip, psi).
+template <typename T>
+__device__ __forceinline__ void sdf_normal_backward(const Blade<T>& b, const T half[3], const T x[3],
+                                                    const SDF<T>& f, const T nb[3], T tipb[3], T& psib) {
+  T e[3][3];
+  blade_axes(b, e);
+  T eb[3][3] = {{T(0), T(0), T(0)}, {T(0), T(0), T(0)}, {T(0), T(0), T(0)}};
+  if (f.inside_axis >= 0) {
+    const int am = f.inside_axis;
+    const T sg = f.loc[am] >= T(0) ? T(1) : T(-1);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) eb[am][k] += sg * nb[k];
+  } else {
+    T nl[3], nlb[3], dotb = T(0);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      nl[a] = f.o[a] / f.od;
+      nlb[a] = nb[0] * e[a][0] + nb[1] * e[a][1] + nb[2] * e[a][2];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) eb[a][k] += nl[a] * nb[k];
+      dotb += nlb[a] * nl[a];
+    }
+    T d[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) d[k] = x[k] - b.tip[k] + half[2] * e[2][k];
+    T db[3] = {T(0), T(0), T(0)};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      if (!(f.q[a] > T(0))) continue;
+      const T locb = (nlb[a] - dotb * nl[a]) / f.od;     // d o_a / d loc_a = 1 when outside
+#pragma unroll
+      for (int k = 0; k < 3; ++k) { db[k] += locb * e[a][k]; eb[a][k] += locb * d[k]; }
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) { tipb[k] -= db[k]; eb[2][k] += half[2] * db[k]; }
+  }
+  // de_n/dpsi = e_p, de_p/dpsi = -e_n, e_w constant.
+  psib += eb[1][0] * e[2][0] + eb[1][1] * e[2][1] - eb[2][0] * e[1][0] - eb[2][1] * e[1][1];
+}
+
+// Coulomb contact (forward): returns the case (0 none/separating, 1 stick, 2 slip).
+template <typename T>
+__device__ __forceinline__ int coulomb_forward(const T vs[3], const T n[3], T mu_b, T v[3]) {
+  T vr[3], vn = T(0);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) { vr[k] = v[k] - vs[k]; vn += vr[k] * n[k]; }
+  if (vn >= T(0)) return 0;
+  T vt[3], t2 = T(0);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) { vt[k] = vr[k] - vn * n[k]; t2 += vt[k] * vt[k]; }
+  const T tn = dsqrt(t2);
+  if (tn <= -mu_b * vn) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) v[k] = vs[k];
+    return 1;
+  }
+  const T sc = T(1) + mu_b * vn / tn;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) v[k] = vs[k] + sc * vt[k];
+  return 2;
+}
+
+// Coulomb contact (adjoint): given the input velocity u and vb (adjoint of
+// the output), returns ub and the adjoints of vs and n.
+template <typename T>
+__device__ __forceinline__ void coulomb_backward(const T vs[3], const T n[3], T mu_b, const T u[3], const T vb[3],
+                                                 T ub[3], T vsb[3], T nb[3]) {
+  T vr[3], vn = T(0);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) { vr[k] = u[k] - vs[k]; vn += vr[k] * n[k]; nb[k] = T(0); }
+  if (vn >= T(0)) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) { ub[k] = vb[k]; vsb[k] = T(0); }
+    return;
+  }
+  T vt[3], t2 = T(0);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) { vt[k] = vr[k] - vn * n[k]; t2 += vt[k] * vt[k]; }
+  const T tn = dsqrt(t2);
+  if (tn <= -mu_b * vn) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) { ub[k] = T(0); vsb[k] = vb[k]; }
+    return;
+  }
+  const T sc = T(1) + mu_b * vn / tn;
+  T scb = T(0);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) scb += vb[k] * vt[k];
+  T vtb[3];
+  const T vnb0 = scb * mu_b / tn;
+  const T tnb = -scb * mu_b * vn / (tn * tn);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) vtb[k] = sc * vb[k] + tnb * vt[k] / tn;
+  // vt = vr - vn n
+  T vrb[3], vnb = vnb0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) { vrb[k] = vtb[k]; vnb -= vtb[k] * n[k]; nb[k] -= vn * vtb[k]; }
+  // vn = vr . n
+#pragma unroll
+  for (int k = 0; k < 3; ++k) { vrb[k] += vnb * n[k]; nb[k] += vnb * vr[k]; }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) { ub[k] = vrb[k]; vsb[k] = vb[k] - vrb[k]; }
+}
+
+// ---------------------------------------------------------------------------
+// Quadratic B-spline stencil along one axis: base = floor(x/dx - 1/2),
+// f = x/dx - base in [1/2, 3/2), weights and their derivatives in f.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void bspline(T f, T w[3], T dw[3]) {
+  const T a = T(1.5) - f, b = f - T(1), c = f - T(0.5);
+  w[0] = T(0.5) * a * a;
+  w[1] = T(0.75) - b * b;
+  w[2] = T(0.5) * c * c;
+  dw[0] = -a;
+  dw[1] = T(-2) * b;
+  dw[2] = c;
+}
+
+}  // namespace ddm

@@ -1,0 +1,997 @@
+// HIP kernels of the MLS-MPM sub-step (Algorithm 1 of the paper), the loss
+// (Eq. hm plus the scoop-mass term) and the adjoint of each sub-step
+// (Eq. po/pa), for gfx950 wave64.
+//
+// Layout: particle state in structure-of-arrays, component-major with stride
+// ntot: x[D], v[D], C[D*D], F[D*D] (row-major matrices).  Instances occupy
+// consecutive ranges padded to kBlock slots, so every 256-thread block belongs
+// to one instance (blk_inst).  Grid: per instance n^D nodes, x-major, each
+// node a 4-vector (mv0, mv1, mv2, m) before the grid update and (v0, v1, v2, m)
+// after it.
+#include <hip/hip_runtime.h>
+
+#include "ddm_device.hpp"
+#include "ddm_kernels.hpp"
+
+namespace ddm {
+
+template <typename T, int D> struct P {
+  T* s;
+  int64_t ntot;
+  __device__ __forceinline__ T& x(int a, int64_t p) const { return s[(int64_t)a * ntot + p]; }
+  __device__ __forceinline__ T& v(int a, int64_t p) const { return s[(int64_t)(D + a) * ntot + p]; }
+  __device__ __forceinline__ T& C(int a, int b, int64_t p) const { return s[(int64_t)(2 * D + a * D + b) * ntot + p]; }
+  __device__ __forceinline__ T& F(int a, int b, int64_t p) const {
+    return s[(int64_t)(2 * D + D * D + a * D + b) * ntot + p];
+  }
+};
+
+template <typename T, int D>
+__device__ __forceinline__ P<T, D> pv(const void* s, int64_t ntot) {
+  return P<T, D>{const_cast<T*>(static_cast<const T*>(s)), ntot};
+}
+
+__device__ __forceinline__ void flag_error(DevErr* e, unsigned int bit, int inst) {
+  const unsigned int old = atomicOr(&e->flags, bit);
+  if (old == 0) atomicExch(&e->first_inst, (unsigned int)inst);
+}
+
+// Stencil of one particle: base node, fractional offset, weights and their
+// derivatives per axis.  Returns false (and flags) when a node would fall
+// outside [0, n).
+template <typename T, int D> struct Stencil {
+  int base[3];
+  T w[3][3], dw[3][3], f[3];
+};
+
+template <typename T, int D>
+__device__ __forceinline__ bool make_stencil(const P<T, D>& st, int64_t p, const KCfg& c, Stencil<T, D>& S) {
+  const T inv_dx = T(c.inv_dx);
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    const T xs = st.x(a, p) * inv_dx;
+    const T bf = floor(xs - T(0.5));
+    if (!(bf >= T(0) && bf <= T(c.n - 3))) return false;
+    S.base[a] = (int)bf;
+    S.f[a] = xs - bf;
+    bspline(S.f[a], S.w[a], S.dw[a]);
+  }
+  return true;
+}
+
+template <int D>
+__device__ __forceinline__ int64_t node_of(const int base[3], int o0, int o1, int o2, int n) {
+  return D == 2 ? (int64_t)(base[0] + o0) * n + (base[1] + o1)
+                : ((int64_t)(base[0] + o0) * n + (base[1] + o1)) * n + (base[2] + o2);
+}
+
+template <typename T> __device__ __forceinline__ T ld(const void* p, int64_t i) { return static_cast<const T*>(p)[i]; }
+
+// Wave64 + block reduction of one double, added atomically to *dst by one lane.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <int N>
+__device__ __forceinline__ void block_accumulate(double (&v)[N], double* dst) {
+  __shared__ double red[kBlock / 64][N];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    const double s = wave_sum(v[k]);
+    if (lane == 0) red[wid][k] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < N) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) s += red[w][threadIdx.x];
+    if (s != 0.0) atomicAdd(&dst[threadIdx.x], s);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Utilities
+// ---------------------------------------------------------------------------
+// Fills with a 32-bit pattern (a kernel rather than a memset node, so that the
+// sequence stays correct when it is captured into a graph and replayed).
+__global__ void k_fill(uint32_t* p, int64_t words, uint32_t value) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < words; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = value;
+}
+
+static void launch_fill(void* p, int64_t words, uint32_t value, hipStream_t s) {
+  if (words <= 0) return;
+  int64_t blocks = (words + kBlock - 1) / kBlock;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_fill, dim3((unsigned)blocks), dim3(kBlock), 0, s, static_cast<uint32_t*>(p), words, value);
+}
+
+void launch_fill_zero(void* p, int64_t count, int elem_bytes, hipStream_t s) {
+  launch_fill(p, count * elem_bytes / 4, 0u, s);
+}
+
+template <typename T, int D>
+__global__ void k_init_state(KCfg c, Bufs b, const T* __restrict__ x0, void* state, uint32_t* pid) {
+  const int inst = b.blk_inst[blockIdx.x];
+  const InstDev& I = b.inst[inst];
+  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t local = p - I.off;
+  P<T, D> st = pv<T, D>(state, c.ntot);
+  // x0 is the instance-concatenated, unpadded [n_total][D] array.
+  int64_t src = 0;
+  for (int k = 0; k < inst; ++k) src += b.inst[k].n;
+  const bool live = local < I.n;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    st.x(a, p) = live ? x0[(src + local) * D + a] : T(0.5);
+    st.v(a, p) = T(0);
+#pragma unroll
+    for (int bb = 0; bb < D; ++bb) { st.C(a, bb, p) = T(0); st.F(a, bb, p) = T(a == bb ? 1 : 0); }
+  }
+  pid[p] = live ? (uint32_t)local : 0xFFFFFFFFu;
+}
+
+void launch_init_state(int prec, const KCfg& c, const Bufs& b, int nblk, const void* x0, void* state,
+                       uint32_t* pid, hipStream_t s) {
+  if (prec == 0) {
+    if (c.dim == 3) hipLaunchKernelGGL((k_init_state<float, 3>), dim3(nblk), dim3(kBlock), 0, s, c, b, (const float*)x0, state, pid);
+    else hipLaunchKernelGGL((k_init_state<float, 2>), dim3(nblk), dim3(kBlock), 0, s, c, b, (const float*)x0, state, pid);
+  } else {
+    if (c.dim == 3) hipLaunchKernelGGL((k_init_state<double, 3>), dim3(nblk), dim3(kBlock), 0, s, c, b, (const double*)x0, state, pid);
+    else hipLaunchKernelGGL((k_init_state<double, 2>), dim3(nblk), dim3(kBlock), 0, s, c, b, (const double*)x0, state, pid);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// P2G (Algorithm 1 lines 1-6): F_tmp = (I + dt C) F, SVD, return map, stress,
+// then the quadratic B-spline scatter of mass and MLS-MPM momentum
+// mv_i += w (m v + A (x_i - x_p)), A = -dt V_p (4/dx^2) tau + m C.
+// ---------------------------------------------------------------------------
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock) k_p2g(KCfg c, Bufs b, const void* st_in, void* st_out, T* __restrict__ grid) {
+  const int inst = b.blk_inst[blockIdx.x];
+  const InstDev& I = b.inst[inst];
+  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (p - I.off >= I.n) return;
+  const P<T, D> si = pv<T, D>(st_in, c.ntot), so = pv<T, D>(st_out, c.ntot);
+  const T dt = T(I.dt), mp = T(I.mp);
+  T Cm[3][3], Ft[3][3];
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int bb = 0; bb < D; ++bb) Cm[a][bb] = si.C(a, bb, p);
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int bb = 0; bb < D; ++bb) {
+      T acc = T(0);
+#pragma unroll
+      for (int k = 0; k < D; ++k) acc += (T(a == k ? 1 : 0) + dt * Cm[a][k]) * si.F(k, bb, p);
+      Ft[a][bb] = acc;
+    }
+  Constit<T, D> cs;
+  constit_forward<T, D>(Ft, T(I.mu), T(I.lam), T(I.alpha), T(I.kc), cs);
+  if (cs.nclamp) { flag_error(b.err, 4u, inst); atomicAdd(&b.err->clamps, (unsigned long long)cs.nclamp); }
+  T Fn[3][3], tau[3][3];
+  constit_outputs<T, D>(cs, Fn, tau);
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int bb = 0; bb < D; ++bb) so.F(a, bb, p) = Fn[a][bb];
+  const T k_str = -dt * T(I.Vp) * T(4.0 * c.inv_dx * c.inv_dx);
+  T A[3][3];
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int bb = 0; bb < D; ++bb) A[a][bb] = k_str * tau[a][bb] + mp * Cm[a][bb];
+  T vel[3];
+#pragma unroll
+  for (int a = 0; a < D; ++a) vel[a] = mp * si.v(a, p);
+  Stencil<T, D> S;
+  if (!make_stencil<T, D>(si, p, c, S)) { flag_error(b.err, 2u, inst); return; }
+  const T dx = T(c.dx);
+  T* g = grid + I.goff * kNodeVals;
+#pragma unroll
+  for (int o0 = 0; o0 < 3; ++o0)
+#pragma unroll
+    for (int o1 = 0; o1 < 3; ++o1)
+#pragma unroll
+      for (int o2 = 0; o2 < (D == 3 ? 3 : 1); ++o2) {
+        const int off[3] = {o0, o1, o2};
+        T w = T(1), r[3];
+#pragma unroll
+        for (int a = 0; a < D; ++a) { w *= S.w[a][off[a]]; r[a] = (T(off[a]) - S.f[a]) * dx; }
+        T* nd = g + node_of<D>(S.base, o0, o1, o2, c.n) * kNodeVals;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          T ar = vel[a];
+#pragma unroll
+          for (int bb = 0; bb < D; ++bb) ar += A[a][bb] * r[bb];
+          atomicAdd(nd + a, w * ar);
+        }
+        atomicAdd(nd + 3, w * mp);
+      }
+}
+
+void launch_p2g(int prec, const KCfg& c, const Bufs& b, int nblk, const void* st_in, void* st_out, void* grid,
+                hipStream_t s) {
+  if (prec == 0) {
+    if (c.dim == 3) hipLaunchKernelGGL((k_p2g<float, 3>), dim3(nblk), dim3(kBlock), 0, s, c, b, st_in, st_out, (float*)grid);
+    else hipLaunchKernelGGL((k_p2g<float, 2>), dim3(nblk), dim3(kBlock), 0, s, c, b, st_in, st_out, (float*)grid);
+  } else {
+    if (c.dim == 3) hipLaunchKernelGGL((k_p2g<double, 3>), dim3(nblk), dim3(kBlock), 0, s, c, b, st_in, st_out, (double*)grid);
+    else hipLaunchKernelGGL((k_p2g<double, 2>), dim3(nblk), dim3(kBlock), 0, s, c, b, st_in, st_out, (double*)grid);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Grid update (Algorithm 1 lines 7-9): v = mv/m + dt g, shovel contact at the
+// pose of this sub-step, then sticky walls.  Nodes without mass get v = 0.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ Blade<T> load_blade(const void* poses, int inst, int max_steps, int step) {
+  const T* q = static_cast<const T*>(poses) + ((int64_t)inst * max_steps + step) * 8;
+  Blade<T> bl;
+  bl.tip[0] = q[0]; bl.tip[1] = q[1]; bl.tip[2] = q[2]; bl.psi = q[3];
+  bl.vel[0] = q[4]; bl.vel[1] = q[5]; bl.vel[2] = q[6]; bl.omega = q[7];
+  bl.sp = sin(bl.psi);
+  bl.cp = cos(bl.psi);
+  return bl;
+}
+
+template <typename T>
+__device__ __forceinline__ void blade_velocity(const Blade<T>& bl, const T xi[3], T vs[3]) {
+  // v_lin + omega x (x - tip), omega = (0, 0, -psi_dot)
+  vs[0] = bl.vel[0] + bl.omega * (xi[1] - bl.tip[1]);
+  vs[1] = bl.vel[1] - bl.omega * (xi[0] - bl.tip[0]);
+  vs[2] = bl.vel[2];
+}
+
+template <int D>
+__device__ __forceinline__ void node_coords(int64_t node, int n, int idx[3]) {
+  if (D == 2) { idx[0] = (int)(node / n); idx[1] = (int)(node % n); idx[2] = 0; }
+  else { idx[0] = (int)(node / ((int64_t)n * n)); idx[1] = (int)((node / n) % n); idx[2] = (int)(node % n); }
+}
+
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock) k_grid_update(KCfg c, Bufs b, int step, const T* __restrict__ pre, T* __restrict__ post) {
+  const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (gid >= c.nodes * c.n_inst) return;
+  const int inst = (int)(gid / c.nodes);
+  const int64_t node = gid - (int64_t)inst * c.nodes;
+  const T m = pre[gid * kNodeVals + 3];
+  T v[3] = {T(0), T(0), T(0)};
+  if (m > T(0)) {
+    const T dt = T(b.inst[inst].dt);
+#pragma unroll
+    for (int a = 0; a < D; ++a) v[a] = pre[gid * kNodeVals + a] / m;
+    v[1] += dt * T(c.gravity);
+    int idx[3];
+    node_coords<D>(node, c.n, idx);
+    if (D == 3 && c.shovel) {
+      const Blade<T> bl = load_blade<T>(b.poses, inst, c.max_steps, step);
+      const T xi[3] = {T(idx[0]) * T(c.dx), T(idx[1]) * T(c.dx), T(idx[2]) * T(c.dx)};
+      const T half[3] = {T(c.half[0]), T(c.half[1]), T(c.half[2])};
+      SDF<T> f;
+      sdf_eval<T>(bl, half, xi, f);
+      if (f.phi < T(c.skin)) {
+        T vs[3];
+        blade_velocity<T>(bl, xi, vs);
+        coulomb_forward<T>(vs, f.n, T(c.mu_b), v);
+      }
+    }
+    bool wall = false;
+#pragma unroll
+    for (int a = 0; a < D; ++a) wall |= (idx[a] < c.bound) || (idx[a] >= c.n - c.bound);
+    if (wall) v[0] = v[1] = v[2] = T(0);
+  }
+  post[gid * kNodeVals + 0] = v[0];
+  post[gid * kNodeVals + 1] = v[1];
+  post[gid * kNodeVals + 2] = v[2];
+  post[gid * kNodeVals + 3] = m;
+}
+
+void launch_grid_update(int prec, const KCfg& c, const Bufs& b, int step, const void* pre, void* post, hipStream_t s) {
+  const int64_t total = c.nodes * c.n_inst;
+  const unsigned nb = (unsigned)((total + kBlock - 1) / kBlock);
+  if (prec == 0) {
+    if (c.dim == 3) hipLaunchKernelGGL((k_grid_update<float, 3>), dim3(nb), dim3(kBlock), 0, s, c, b, step, (const float*)pre, (float*)post);
+    else hipLaunchKernelGGL((k_grid_update<float, 2>), dim3(nb), dim3(kBlock), 0, s, c, b, step, (const float*)pre, (float*)post);
+  } else {
+    if (c.dim == 3) hipLaunchKernelGGL((k_grid_update<double, 3>), dim3(nb), dim3(kBlock), 0, s, c, b, step, (const double*)pre, (double*)post);
+    else hipLaunchKernelGGL((k_grid_update<double, 2>), dim3(nb), dim3(kBlock), 0, s, c, b, step, (const double*)pre, (double*)post);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// G2P (Algorithm 1 lines 10-13): v_p = sum w v_i, C_p = (4/dx^2) sum w v_i r^T,
+// x_p += dt v_p.
+// ---------------------------------------------------------------------------
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock) k_g2p(KCfg c, Bufs b, const void* st_in, void* st_out, const T* __restrict__ post) {
+  const int inst = b.blk_inst[blockIdx.x];
+  const InstDev& I = b.inst[inst];
+  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const P<T, D> si = pv<T, D>(st_in, c.ntot), so = pv<T, D>(st_out, c.ntot);
+  if (p - I.off >= I.n) {
+    // padding slots keep a harmless position so they never trip a check
+#pragma unroll
+    for (int a = 0; a < D; ++a) so.x(a, p) = T(0.5);
+    return;
+  }
+  Stencil<T, D> S;
+  if (!make_stencil<T, D>(si, p, c, S)) { flag_error(b.err, 2u, inst); return; }
+  const T dx = T(c.dx), Dk = T(4.0 * c.inv_dx * c.inv_dx);
+  const T* g = post + I.goff * kNodeVals;
+  T vn[3] = {T(0), T(0), T(0)}, Cn[3][3] = {{T(0), T(0), T(0)}, {T(0), T(0), T(0)}, {T(0), T(0), T(0)}};
+#pragma unroll
+  for (int o0 = 0; o0 < 3; ++o0)
+#pragma unroll
+    for (int o1 = 0; o1 < 3; ++o1)
+#pragma unroll
+      for (int o2 = 0; o2 < (D == 3 ? 3 : 1); ++o2) {
+        const int off[3] = {o0, o1, o2};
+        T w = T(1), r[3];
+#pragma unroll
+        for (int a = 0; a < D; ++a) { w *= S.w[a][off[a]]; r[a] = (T(off[a]) - S.f[a]) * dx; }
+        const T* nd = g + node_of<D>(S.base, o0, o1, o2, c.n) * kNodeVals;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          const T vi = nd[a];
+          vn[a] += w * vi;
+#pragma unroll
+          for (int bb = 0; bb < D; ++bb) Cn[a][bb] += (Dk * w) * vi * r[bb];
+        }
+      }
+  const T dt = T(b.inst[inst].dt);
+  T chk = T(0);
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    const T xn = si.x(a, p) + dt * vn[a];
+    so.x(a, p) = xn;
+    so.v(a, p) = vn[a];
+    chk += xn + vn[a];
+#pragma unroll
+    for (int bb = 0; bb < D; ++bb) so.C(a, bb, p) = Cn[a][bb];
+  }
+  if (!isfinite(chk)) flag_error(b.err, 1u, inst);
+}
+
+void launch_g2p(int prec, const KCfg& c, const Bufs& b, int nblk, const void* st_in, void* st_out,
+                const void* post, hipStream_t s) {
+  if (prec == 0) {
+    if (c.dim == 3) hipLaunchKernelGGL((k_g2p<float, 3>), dim3(nblk), dim3(kBlock), 0, s, c, b, st_in, st_out, (const float*)post);
+    else hipLaunchKernelGGL((k_g2p<float, 2>), dim3(nblk), dim3(kBlock), 0, s, c, b, st_in, st_out, (const float*)post);
+  } else {
+    if (c.dim == 3) hipLaunchKernelGGL((k_g2p<double, 3>), dim3(nblk), dim3(kBlock), 0, s, c, b, st_in, st_out, (const double*)post);
+    else hipLaunchKernelGGL((k_g2p<double, 2>), dim3(nblk), dim3(kBlock), 0, s, c, b, st_in, st_out, (const double*)post);
+  }
+}
+
+template <typename T>
+__global__ void k_grid_export(int64_t total, const T* pre, const T* post, T* out) {
+  const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (g >= total) return;
+  out[g * 8 + 0] = pre[g * 4 + 3];
+  for (int a = 0; a < 3; ++a) { out[g * 8 + 1 + a] = pre[g * 4 + a]; out[g * 8 + 4 + a] = post[g * 4 + a]; }
+  out[g * 8 + 7] = T(0);
+}
+
+void launch_grid_export(int prec, const KCfg& c, const void* pre, const void* post, void* out, hipStream_t s) {
+  const int64_t total = c.nodes * c.n_inst;
+  const unsigned nb = (unsigned)((total + kBlock - 1) / kBlock);
+  if (prec == 0) hipLaunchKernelGGL((k_grid_export<float>), dim3(nb), dim3(kBlock), 0, s, total, (const float*)pre, (const float*)post, (float*)out);
+  else hipLaunchKernelGGL((k_grid_export<double>), dim3(nb), dim3(kBlock), 0, s, total, (const double*)pre, (const double*)post, (double*)out);
+}
+
+// ---------------------------------------------------------------------------
+// Loss.  Height map (Eq. hm): every particle touches the pixel of its own
+// (x, z) and of the four points offset by +-r_p along x and z (2D: a profile
+// over x, three points); a pixel keeps the largest height, ties to the lowest
+// particle id.  Squared distance to the target, plus the scoop-mass term on a
+// P2G of particle masses at the final positions inside the scoop slab.
+// ---------------------------------------------------------------------------
+template <typename T> __device__ __forceinline__ unsigned long long obits(T y);
+template <> __device__ __forceinline__ unsigned long long obits<float>(float y) { return (unsigned long long)__float_as_uint(y); }
+template <> __device__ __forceinline__ unsigned long long obits<double>(double y) { return (unsigned long long)__double_as_longlong(y); }
+
+template <typename T, int D>
+__device__ __forceinline__ int hm_pixels(const KCfg& c, T x, T z, int pix[5]) {
+  const T pw = T(c.hm_pix), r = T(c.hm_off);
+  const T ox[5] = {T(0), r, -r, T(0), T(0)}, oz[5] = {T(0), T(0), T(0), r, -r};
+  const int npts = D == 3 ? 5 : 3;
+  int cnt = 0;
+  for (int k = 0; k < npts; ++k) {
+    const T px = x + ox[k];
+    const T fx = floor((px - T(c.hm_ox)) / pw);
+    int iz = 0;
+    if (D == 3) {
+      const T pz = z + oz[k];
+      const T fz = floor((pz - T(c.hm_oz)) / pw);
+      if (!(fz >= T(0) && fz < T(c.hm_res))) { pix[k] = -1; continue; }
+      iz = (int)fz;
+    }
+    if (!(fx >= T(0) && fx < T(c.hm_res))) { pix[k] = -1; continue; }
+    pix[k] = D == 3 ? (int)fx * c.hm_res + iz : (int)fx;
+    ++cnt;
+  }
+  for (int k = npts; k < 5; ++k) pix[k] = -1;
+  return cnt;
+}
+
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock) k_hm_max(KCfg c, Bufs b, const void* state, unsigned long long* hm) {
+  const int inst = b.blk_inst[blockIdx.x];
+  const InstDev& I = b.inst[inst];
+  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (p - I.off >= I.n) return;
+  const P<T, D> st = pv<T, D>(state, c.ntot);
+  const T y = st.x(1, p);
+  if (!(y > T(0))) return;
+  int pix[5];
+  hm_pixels<T, D>(c, st.x(0, p), D == 3 ? st.x(2, p) : T(0), pix);
+  const int npix = D == 3 ? c.hm_res * c.hm_res : c.hm_res;
+  const unsigned long long yb = obits<T>(y);
+  for (int k = 0; k < 5; ++k)
+    if (pix[k] >= 0) atomicMax(&hm[(int64_t)inst * npix + pix[k]], yb);
+}
+
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock) k_hm_owner(KCfg c, Bufs b, const void* state, const uint32_t* pid,
+                                                     const unsigned long long* hm, unsigned int* owner) {
+  const int inst = b.blk_inst[blockIdx.x];
+  const InstDev& I = b.inst[inst];
+  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (p - I.off >= I.n) return;
+  const P<T, D> st = pv<T, D>(state, c.ntot);
+  const T y = st.x(1, p);
+  if (!(y > T(0))) return;
+  int pix[5];
+  hm_pixels<T, D>(c, st.x(0, p), D == 3 ? st.x(2, p) : T(0), pix);
+  const int npix = D == 3 ? c.hm_res * c.hm_res : c.hm_res;
+  const unsigned long long yb = obits<T>(y);
+  for (int k = 0; k < 5; ++k)
+    if (pix[k] >= 0 && hm[(int64_t)inst * npix + pix[k]] == yb) atomicMin(&owner[(int64_t)inst * npix + pix[k]], pid[p]);
+}
+
+// Scoop region: nodes inside the slab in front of the final blade pose.
+template <typename T>
+__device__ __forceinline__ bool in_region(const KCfg& c, const Blade<T>& bl, const T xi[3]) {
+  T e[3][3];
+  blade_axes(bl, e);
+  T q[3];
+  const T hp = T(c.half[2]);
+  for (int a = 0; a < 3; ++a) {
+    q[a] = T(0);
+    for (int k = 0; k < 3; ++k) q[a] += (xi[k] - (bl.tip[k] - hp * e[2][k])) * e[a][k];
+  }
+  const T sn = T(c.region_sign) * q[1];
+  return dabs(q[0]) <= T(c.half[0]) && dabs(q[2]) <= hp && sn > T(c.half[1]) && sn <= T(c.half[1]) + T(c.region_depth);
+}
+
+template <typename T>
+__device__ __forceinline__ Blade<T> final_blade(const KCfg& c, const Bufs& b, int inst, int final_step) {
+  if (final_step >= 0) return load_blade<T>(b.poses, inst, c.max_steps, final_step);
+  Blade<T> bl;
+  for (int k = 0; k < 3; ++k) { bl.tip[k] = T(b.inst[inst].tip0[k]); bl.vel[k] = T(0); }
+  bl.psi = T(0); bl.omega = T(0); bl.sp = T(0); bl.cp = T(1);
+  return bl;
+}
+
+// Per particle: sum over stencil nodes inside the region of w (and grad w).
+template <typename T, int D>
+__device__ __forceinline__ T region_weights(const KCfg& c, const Blade<T>& bl, const Stencil<T, D>& S, T gw[3]) {
+  T acc = T(0);
+  gw[0] = gw[1] = gw[2] = T(0);
+  const T dx = T(c.dx), inv_dx = T(c.inv_dx);
+  for (int o0 = 0; o0 < 3; ++o0)
+    for (int o1 = 0; o1 < 3; ++o1)
+      for (int o2 = 0; o2 < 3; ++o2) {
+        const int off[3] = {o0, o1, o2};
+        const T xi[3] = {T(S.base[0] + o0) * dx, T(S.base[1] + o1) * dx, T(S.base[2] + o2) * dx};
+        if (!in_region<T>(c, bl, xi)) continue;
+        const T w0 = S.w[0][o0], w1 = S.w[1][o1], w2 = S.w[2][o2];
+        acc += w0 * w1 * w2;
+        gw[0] += S.dw[0][o0] * inv_dx * w1 * w2;
+        gw[1] += w0 * S.dw[1][o1] * inv_dx * w2;
+        gw[2] += w0 * w1 * S.dw[2][o2] * inv_dx;
+        (void)off;
+      }
+  return acc;
+}
+
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock) k_region_mass(KCfg c, Bufs b, const void* state, int final_step, double* region) {
+  const int inst = b.blk_inst[blockIdx.x];
+  const InstDev& I = b.inst[inst];
+  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  double v[1] = {0.0};
+  if (p - I.off < I.n) {
+    const P<T, D> st = pv<T, D>(state, c.ntot);
+    Stencil<T, D> S;
+    if (make_stencil<T, D>(st, p, c, S)) {
+      const Blade<T> bl = final_blade<T>(c, b, inst, final_step);
+      T gw[3];
+      v[0] = (double)(region_weights<T, D>(c, bl, S, gw) * T(I.mp));
+    }
+  }
+  block_accumulate<1>(v, region + inst);
+}
+
+template <typename T, int D>
+__global__ void k_loss_final(KCfg c, const unsigned long long* hm, const unsigned int* owner, LossBufs L) {
+  const int inst = blockIdx.x;
+  const int npix = D == 3 ? c.hm_res * c.hm_res : c.hm_res;
+  double acc = 0.0;
+  const double inv_dx = c.inv_dx;
+  for (int i = threadIdx.x; i < npix; i += blockDim.x) {
+    const int64_t k = (int64_t)inst * npix + i;
+    double h;
+    if (sizeof(T) == 4) h = (double)__uint_as_float((unsigned int)hm[k]);
+    else h = __longlong_as_double((long long)hm[k]);
+    L.hm_val[k] = h;
+    const double e = (h - L.target[k]) * inv_dx;
+    acc += e * e;
+    L.dldh[k] = owner[k] != 0xFFFFFFFFu ? 2.0 * c.w_hm / npix * (h - L.target[k]) * inv_dx * inv_dx : 0.0;
+  }
+  __shared__ double red[kBlock / 64];
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < (int)blockDim.x / 64; ++w) s += red[w];
+    double loss = c.w_hm / npix * s;
+    double dldm = 0.0;
+    if (D == 3 && c.shovel && c.w_mass != 0.0) {
+      const double e = (L.region[inst] - c.m_target) / c.m_ref;
+      loss += c.w_mass * e * e;
+      dldm = 2.0 * c.w_mass * e / c.m_ref;
+    }
+    L.loss[inst] = loss;
+    L.dldm[inst] = dldm;
+  }
+}
+
+void launch_loss(int prec, const KCfg& c, const Bufs& b, int nblk, const void* state, const uint32_t* pid,
+                 int final_step, const LossBufs& L, hipStream_t s) {
+  const int npix = c.dim == 3 ? c.hm_res * c.hm_res : c.hm_res;
+  launch_fill_zero(L.hm_bits, (int64_t)c.n_inst * npix, 8, s);
+  launch_fill(L.owner, (int64_t)c.n_inst * npix, 0xFFFFFFFFu, s);
+  launch_fill_zero(L.region, c.n_inst, 8, s);
+#define DDM_LOSS(T, DD)                                                                                      \
+  hipLaunchKernelGGL((k_hm_max<T, DD>), dim3(nblk), dim3(kBlock), 0, s, c, b, state, L.hm_bits);            \
+  hipLaunchKernelGGL((k_hm_owner<T, DD>), dim3(nblk), dim3(kBlock), 0, s, c, b, state, pid, L.hm_bits, L.owner); \
+  if (DD == 3 && c.shovel && c.w_mass != 0.0)                                                                \
+    hipLaunchKernelGGL((k_region_mass<T, 3>), dim3(nblk), dim3(kBlock), 0, s, c, b, state, final_step, L.region); \
+  hipLaunchKernelGGL((k_loss_final<T, DD>), dim3(c.n_inst), dim3(kBlock), 0, s, c, L.hm_bits, L.owner, L);
+  if (prec == 0) {
+    if (c.dim == 3) { DDM_LOSS(float, 3) } else { DDM_LOSS(float, 2) }
+  } else {
+    if (c.dim == 3) { DDM_LOSS(double, 3) } else { DDM_LOSS(double, 2) }
+  }
+#undef DDM_LOSS
+}
+
+// Seed of the reverse pass: adjoint of the final state from the loss.
+// Height: dL/dy_p sums dL/dH over the pixels p owns (each pixel once).
+// Scoop mass: dL/dx_p = dL/dM m_p sum_{i in R} grad w, dL/dm_p -> rho.
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock) k_loss_seed(KCfg c, Bufs b, const void* state, const uint32_t* pid,
+                                                      int final_step, LossBufs L, void* adj, double* pacc) {
+  const int inst = b.blk_inst[blockIdx.x];
+  const InstDev& I = b.inst[inst];
+  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const P<T, D> st = pv<T, D>(state, c.ntot), ad = pv<T, D>(adj, c.ntot);
+  double racc[1] = {0.0};
+  T xb[3] = {T(0), T(0), T(0)};
+  if (p - I.off < I.n) {
+    const T y = st.x(1, p);
+    if (y > T(0)) {
+      int pix[5];
+      hm_pixels<T, D>(c, st.x(0, p), D == 3 ? st.x(2, p) : T(0), pix);
+      const int npix = D == 3 ? c.hm_res * c.hm_res : c.hm_res;
+      double yb = 0.0;
+      for (int k = 0; k < 5; ++k) {
+        if (pix[k] < 0) continue;
+        bool dup = false;
+        for (int j = 0; j < k; ++j) dup |= pix[j] == pix[k];
+        const int64_t q = (int64_t)inst * npix + pix[k];
+        if (!dup && L.owner[q] == pid[p]) yb += L.dldh[q];
+      }
+      xb[1] = T(yb);
+    }
+    if (D == 3 && c.shovel && c.w_mass != 0.0) {
+      Stencil<T, D> S;
+      if (make_stencil<T, D>(st, p, c, S)) {
+        const Blade<T> bl = final_blade<T>(c, b, inst, final_step);
+        T gw[3];
+        const T wsum = region_weights<T, D>(c, bl, S, gw);
+        const T dm = T(L.dldm[inst]);
+        for (int a = 0; a < 3; ++a) xb[a] += dm * T(I.mp) * gw[a];
+        racc[0] = (double)dm * (double)wsum * I.Vp;
+      }
+    }
+  }
+  for (int a = 0; a < D; ++a) {
+    ad.x(a, p) = xb[a];
+    ad.v(a, p) = T(0);
+    for (int bb = 0; bb < D; ++bb) { ad.C(a, bb, p) = T(0); ad.F(a, bb, p) = T(0); }
+  }
+  block_accumulate<1>(racc, pacc + (int64_t)inst * 8 + 4);
+}
+
+void launch_loss_seed(int prec, const KCfg& c, const Bufs& b, int nblk, const void* state, const uint32_t* pid,
+                      int final_step, const LossBufs& L, void* adj, double* pacc, hipStream_t s) {
+  if (prec == 0) {
+    if (c.dim == 3) hipLaunchKernelGGL((k_loss_seed<float, 3>), dim3(nblk), dim3(kBlock), 0, s, c, b, state, pid, final_step, L, adj, pacc);
+    else hipLaunchKernelGGL((k_loss_seed<float, 2>), dim3(nblk), dim3(kBlock), 0, s, c, b, state, pid, final_step, L, adj, pacc);
+  } else {
+    if (c.dim == 3) hipLaunchKernelGGL((k_loss_seed<double, 3>), dim3(nblk), dim3(kBlock), 0, s, c, b, state, pid, final_step, L, adj, pacc);
+    else hipLaunchKernelGGL((k_loss_seed<double, 2>), dim3(nblk), dim3(kBlock), 0, s, c, b, state, pid, final_step, L, adj, pacc);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint of G2P + advection.  With vb = v'bar + dt x'bar:
+//   xbar = x'bar + sum_i [grad w (v_i . vb + (4/dx^2) v_i^T C'bar r) - (4/dx^2) w C'bar^T v_i]
+//   v_i bar += w (vb + (4/dx^2) C'bar r)            (scattered to the grid)
+// ---------------------------------------------------------------------------
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock) k_g2p_adj(KCfg c, Bufs b, const void* stv, const T* __restrict__ post,
+                                                    const void* adj_next, void* adj_cur, T* __restrict__ gvb) {
+  const int inst = b.blk_inst[blockIdx.x];
+  const InstDev& I = b.inst[inst];
+  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (p - I.off >= I.n) return;
+  const P<T, D> st = pv<T, D>(stv, c.ntot), an = pv<T, D>(adj_next, c.ntot), ac = pv<T, D>(adj_cur, c.ntot);
+  Stencil<T, D> S;
+  if (!make_stencil<T, D>(st, p, c, S)) return;
+  const T dt = T(I.dt), dx = T(c.dx), inv_dx = T(c.inv_dx), Dk = T(4.0 * c.inv_dx * c.inv_dx);
+  T xb[3], vb[3], Cb[3][3];
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    xb[a] = an.x(a, p);
+    vb[a] = an.v(a, p) + dt * xb[a];
+#pragma unroll
+    for (int bb = 0; bb < D; ++bb) Cb[a][bb] = an.C(a, bb, p);
+  }
+  const T* g = post + I.goff * kNodeVals;
+  T* gb = gvb + I.goff * kNodeVals;
+#pragma unroll
+  for (int o0 = 0; o0 < 3; ++o0)
+#pragma unroll
+    for (int o1 = 0; o1 < 3; ++o1)
+#pragma unroll
+      for (int o2 = 0; o2 < (D == 3 ? 3 : 1); ++o2) {
+        const int off[3] = {o0, o1, o2};
+        T w = T(1), r[3], gw[3];
+#pragma unroll
+        for (int a = 0; a < D; ++a) r[a] = (T(off[a]) - S.f[a]) * dx;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          T prod = S.dw[a][off[a]] * inv_dx;
+#pragma unroll
+          for (int bb = 0; bb < D; ++bb)
+            if (bb != a) prod *= S.w[bb][off[bb]];
+          gw[a] = prod;
+          w *= S.w[a][off[a]];
+        }
+        const int64_t nd = node_of<D>(S.base, o0, o1, o2, c.n) * kNodeVals;
+        T vi[3], Cr[3];
+#pragma unroll
+        for (int a = 0; a < D; ++a) vi[a] = g[nd + a];
+        T s = T(0);
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          Cr[a] = T(0);
+#pragma unroll
+          for (int bb = 0; bb < D; ++bb) Cr[a] += Cb[a][bb] * r[bb];
+          s += vi[a] * (vb[a] + Dk * Cr[a]);
+        }
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          T ctv = T(0);
+#pragma unroll
+          for (int bb = 0; bb < D; ++bb) ctv += Cb[bb][a] * vi[bb];
+          xb[a] += gw[a] * s - Dk * w * ctv;
+          atomicAdd(gb + nd + a, w * (vb[a] + Dk * Cr[a]));
+        }
+      }
+#pragma unroll
+  for (int a = 0; a < D; ++a) ac.x(a, p) = xb[a];
+}
+
+void launch_g2p_adj(int prec, const KCfg& c, const Bufs& b, int nblk, const void* st, const void* post,
+                    const void* adj_next, void* adj_cur, void* gvb, hipStream_t s) {
+  if (prec == 0) {
+    if (c.dim == 3) hipLaunchKernelGGL((k_g2p_adj<float, 3>), dim3(nblk), dim3(kBlock), 0, s, c, b, st, (const float*)post, adj_next, adj_cur, (float*)gvb);
+    else hipLaunchKernelGGL((k_g2p_adj<float, 2>), dim3(nblk), dim3(kBlock), 0, s, c, b, st, (const float*)post, adj_next, adj_cur, (float*)gvb);
+  } else {
+    if (c.dim == 3) hipLaunchKernelGGL((k_g2p_adj<double, 3>), dim3(nblk), dim3(kBlock), 0, s, c, b, st, (const double*)post, adj_next, adj_cur, (double*)gvb);
+    else hipLaunchKernelGGL((k_g2p_adj<double, 2>), dim3(nblk), dim3(kBlock), 0, s, c, b, st, (const double*)post, adj_next, adj_cur, (double*)gvb);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint of the grid update: walls cut the gradient, contact is replayed with
+// the same branch, u = mv/m + dt g gives mv bar = u bar / m and
+// m bar = -u bar . (mv/m) / m.  Pose adjoints (tip, psi, v_lin, omega) of the
+// sub-step are reduced over the contact nodes.
+// ---------------------------------------------------------------------------
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock) k_grid_adj(KCfg c, Bufs b, int step, const T* __restrict__ pre,
+                                                     const T* __restrict__ gvb, T* __restrict__ gb, double* pose_bar) {
+  const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t total = c.nodes * c.n_inst;
+  // the whole block belongs to one instance: nodes per instance is a multiple of kBlock
+  const int inst = (int)(((int64_t)blockIdx.x * kBlock) / c.nodes);
+  double pb[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  bool any = false;
+  if (gid < total) {
+    const int64_t node = gid - (int64_t)inst * c.nodes;
+    const T m = pre[gid * kNodeVals + 3];
+    T ub[3] = {T(0), T(0), T(0)};
+    T mb = T(0);
+    if (m > T(0)) {
+      int idx[3];
+      node_coords<D>(node, c.n, idx);
+      bool wall = false;
+#pragma unroll
+      for (int a = 0; a < D; ++a) wall |= (idx[a] < c.bound) || (idx[a] >= c.n - c.bound);
+      if (!wall) {
+        T vb[3] = {T(0), T(0), T(0)}, u[3] = {T(0), T(0), T(0)};
+        const T dt = T(b.inst[inst].dt);
+#pragma unroll
+        for (int a = 0; a < D; ++a) { vb[a] = gvb[gid * kNodeVals + a]; u[a] = pre[gid * kNodeVals + a] / m; }
+        u[1] += dt * T(c.gravity);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) ub[a] = vb[a];
+        if (D == 3 && c.shovel) {
+          const Blade<T> bl = load_blade<T>(b.poses, inst, c.max_steps, step);
+          const T xi[3] = {T(idx[0]) * T(c.dx), T(idx[1]) * T(c.dx), T(idx[2]) * T(c.dx)};
+          const T half[3] = {T(c.half[0]), T(c.half[1]), T(c.half[2])};
+          SDF<T> f;
+          sdf_eval<T>(bl, half, xi, f);
+          if (f.phi < T(c.skin)) {
+            T vs[3], vsb[3], nb[3];
+            blade_velocity<T>(bl, xi, vs);
+            coulomb_backward<T>(vs, f.n, T(c.mu_b), u, vb, ub, vsb, nb);
+            // v_s = v_lin + (psi_dot (y - tip_y), -psi_dot (x - tip_x), 0)
+            T tipb[3] = {T(0), T(0), T(0)}, psib = T(0);
+            const T omb = vsb[0] * (xi[1] - bl.tip[1]) - vsb[1] * (xi[0] - bl.tip[0]);
+            tipb[1] -= bl.omega * vsb[0];
+            tipb[0] += bl.omega * vsb[1];
+            sdf_normal_backward<T>(bl, half, xi, f, nb, tipb, psib);
+            pb[0] = tipb[0]; pb[1] = tipb[1]; pb[2] = tipb[2]; pb[3] = psib;
+            pb[4] = vsb[0]; pb[5] = vsb[1]; pb[6] = vsb[2]; pb[7] = omb;
+            any = true;
+          }
+        }
+        T dot = T(0);
+#pragma unroll
+        for (int a = 0; a < D; ++a) dot += ub[a] * pre[gid * kNodeVals + a];
+        mb = -dot / (m * m);
+#pragma unroll
+        for (int a = 0; a < D; ++a) ub[a] = ub[a] / m;
+      }
+    }
+    gb[gid * kNodeVals + 0] = ub[0];
+    gb[gid * kNodeVals + 1] = ub[1];
+    gb[gid * kNodeVals + 2] = ub[2];
+    gb[gid * kNodeVals + 3] = mb;
+  }
+  if (D == 3 && c.shovel && __syncthreads_or(any)) block_accumulate<8>(pb, pose_bar + ((int64_t)inst * c.max_steps + step) * 8);
+}
+
+void launch_grid_adj(int prec, const KCfg& c, const Bufs& b, int step, const void* pre, const void* gvb, void* gb,
+                     double* pose_bar, hipStream_t s) {
+  const int64_t total = c.nodes * c.n_inst;
+  const unsigned nb = (unsigned)((total + kBlock - 1) / kBlock);
+  if (prec == 0) {
+    if (c.dim == 3) hipLaunchKernelGGL((k_grid_adj<float, 3>), dim3(nb), dim3(kBlock), 0, s, c, b, step, (const float*)pre, (const float*)gvb, (float*)gb, pose_bar);
+    else hipLaunchKernelGGL((k_grid_adj<float, 2>), dim3(nb), dim3(kBlock), 0, s, c, b, step, (const float*)pre, (const float*)gvb, (float*)gb, pose_bar);
+  } else {
+    if (c.dim == 3) hipLaunchKernelGGL((k_grid_adj<double, 3>), dim3(nb), dim3(kBlock), 0, s, c, b, step, (const double*)pre, (const double*)gvb, (double*)gb, pose_bar);
+    else hipLaunchKernelGGL((k_grid_adj<double, 2>), dim3(nb), dim3(kBlock), 0, s, c, b, step, (const double*)pre, (const double*)gvb, (double*)gb, pose_bar);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint of P2G and of the constitutive update.  Gathers the grid adjoints
+// (m bar, mv bar) over the stencil, then goes back through A, the stress, the
+// return map and the SVD (isotropic-function adjoint) and F_tmp = (I + dt C) F.
+// Material adjoints (mu, lambda, alpha, k_c, rho) are block-reduced in double.
+// ---------------------------------------------------------------------------
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock) k_p2g_adj(KCfg c, Bufs b, const void* stv, const T* __restrict__ gbar,
+                                                    const void* adj_next, void* adj_cur, double* pacc) {
+  const int inst = b.blk_inst[blockIdx.x];
+  const InstDev& I = b.inst[inst];
+  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  double acc[5] = {0, 0, 0, 0, 0};
+  if (p - I.off < I.n) {
+    const P<T, D> st = pv<T, D>(stv, c.ntot), an = pv<T, D>(adj_next, c.ntot), ac = pv<T, D>(adj_cur, c.ntot);
+    Stencil<T, D> S;
+    if (make_stencil<T, D>(st, p, c, S)) {
+      const T dt = T(I.dt), mp = T(I.mp), dx = T(c.dx), inv_dx = T(c.inv_dx);
+      const T mu = T(I.mu), lam = T(I.lam), al = T(I.alpha), kc = T(I.kc);
+      T Cm[3][3], Fm[3][3], Ft[3][3], vel[3];
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        vel[a] = st.v(a, p);
+#pragma unroll
+        for (int bb = 0; bb < D; ++bb) { Cm[a][bb] = st.C(a, bb, p); Fm[a][bb] = st.F(a, bb, p); }
+      }
+#pragma unroll
+      for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int bb = 0; bb < D; ++bb) {
+          T s = T(0);
+#pragma unroll
+          for (int k = 0; k < D; ++k) s += (T(a == k ? 1 : 0) + dt * Cm[a][k]) * Fm[k][bb];
+          Ft[a][bb] = s;
+        }
+      Constit<T, D> cs;
+      constit_forward<T, D>(Ft, mu, lam, al, kc, cs);
+      T Fn[3][3], tau[3][3];
+      constit_outputs<T, D>(cs, Fn, tau);
+      const T k_str = -dt * T(I.Vp) * T(4.0 * c.inv_dx * c.inv_dx);
+      T A[3][3];
+#pragma unroll
+      for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int bb = 0; bb < D; ++bb) A[a][bb] = k_str * tau[a][bb] + mp * Cm[a][bb];
+      // gather
+      T mpb = T(0), vb[3] = {T(0), T(0), T(0)}, Ab[3][3] = {{T(0), T(0), T(0)}, {T(0), T(0), T(0)}, {T(0), T(0), T(0)}};
+      T xb[3];
+#pragma unroll
+      for (int a = 0; a < D; ++a) xb[a] = ac.x(a, p);     // G2P part, written by k_g2p_adj
+      const T* g = gbar + I.goff * kNodeVals;
+#pragma unroll
+      for (int o0 = 0; o0 < 3; ++o0)
+#pragma unroll
+        for (int o1 = 0; o1 < 3; ++o1)
+#pragma unroll
+          for (int o2 = 0; o2 < (D == 3 ? 3 : 1); ++o2) {
+            const int off[3] = {o0, o1, o2};
+            T w = T(1), r[3], gw[3];
+#pragma unroll
+            for (int a = 0; a < D; ++a) r[a] = (T(off[a]) - S.f[a]) * dx;
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+              T prod = S.dw[a][off[a]] * inv_dx;
+#pragma unroll
+              for (int bb = 0; bb < D; ++bb)
+                if (bb != a) prod *= S.w[bb][off[bb]];
+              gw[a] = prod;
+              w *= S.w[a][off[a]];
+            }
+            const int64_t nd = node_of<D>(S.base, o0, o1, o2, c.n) * kNodeVals;
+            T mvb[3];
+#pragma unroll
+            for (int a = 0; a < D; ++a) mvb[a] = g[nd + a];
+            const T mb = g[nd + 3];
+            // value scattered to this node: m_p w and w (m_p v + A r)
+            T sc = mp * mb;
+            T vm = T(0);
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+              T ar = mp * vel[a];
+#pragma unroll
+              for (int bb = 0; bb < D; ++bb) ar += A[a][bb] * r[bb];
+              sc += mvb[a] * ar;
+              vm += vel[a] * mvb[a];
+            }
+            mpb += w * (mb + vm);
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+              vb[a] += w * mp * mvb[a];
+              T atm = T(0);
+#pragma unroll
+              for (int bb = 0; bb < D; ++bb) { Ab[a][bb] += w * mvb[a] * r[bb]; atm += A[bb][a] * mvb[bb]; }
+              xb[a] += gw[a] * sc - w * atm;
+            }
+          }
+      // A = k_str tau + m_p C
+      T taub[3][3], Cb[3][3];
+#pragma unroll
+      for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int bb = 0; bb < D; ++bb) {
+          taub[a][bb] = k_str * Ab[a][bb];
+          Cb[a][bb] = mp * Ab[a][bb];
+          mpb += Ab[a][bb] * Cm[a][bb];
+        }
+      T Fnb[3][3];
+#pragma unroll
+      for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int bb = 0; bb < D; ++bb) Fnb[a][bb] = an.F(a, bb, p);
+      T Ftb[3][3], mub = T(0), lamb = T(0), alb = T(0), kcb = T(0);
+      constit_backward<T, D>(cs, mu, lam, al, kc, Fnb, taub, Ftb, mub, lamb, alb, kcb);
+      // F_tmp = (I + dt C) F
+#pragma unroll
+      for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int bb = 0; bb < D; ++bb) {
+          T fb = T(0), cb = T(0);
+#pragma unroll
+          for (int k = 0; k < D; ++k) {
+            fb += (T(k == a ? 1 : 0) + dt * Cm[k][a]) * Ftb[k][bb];
+            cb += Ftb[a][k] * Fm[bb][k];
+          }
+          ac.F(a, bb, p) = fb;
+          ac.C(a, bb, p) = Cb[a][bb] + dt * cb;
+        }
+#pragma unroll
+      for (int a = 0; a < D; ++a) { ac.x(a, p) = xb[a]; ac.v(a, p) = vb[a]; }
+      acc[0] = (double)mub;
+      acc[1] = (double)lamb;
+      acc[2] = (double)alb;
+      acc[3] = (double)kcb;
+      acc[4] = (double)mpb * I.Vp;
+    }
+  }
+  block_accumulate<5>(acc, pacc + (int64_t)inst * 8);
+}
+
+void launch_p2g_adj(int prec, const KCfg& c, const Bufs& b, int nblk, const void* st, const void* gb,
+                    const void* adj_next, void* adj_cur, double* pacc, hipStream_t s) {
+  if (prec == 0) {
+    if (c.dim == 3) hipLaunchKernelGGL((k_p2g_adj<float, 3>), dim3(nblk), dim3(kBlock), 0, s, c, b, st, (const float*)gb, adj_next, adj_cur, pacc);
+    else hipLaunchKernelGGL((k_p2g_adj<float, 2>), dim3(nblk), dim3(kBlock), 0, s, c, b, st, (const float*)gb, adj_next, adj_cur, pacc);
+  } else {
+    if (c.dim == 3) hipLaunchKernelGGL((k_p2g_adj<double, 3>), dim3(nblk), dim3(kBlock), 0, s, c, b, st, (const double*)gb, adj_next, adj_cur, pacc);
+    else hipLaunchKernelGGL((k_p2g_adj<double, 2>), dim3(nblk), dim3(kBlock), 0, s, c, b, st, (const double*)gb, adj_next, adj_cur, pacc);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Final gradient per instance: chain (mu, lambda, alpha, k_c, rho) adjoints to
+// (E, nu, phi_deg, rho) and the per-sub-step pose adjoints through the pose
+// Jacobian d pose / d (depth, angle_deg, push); scale by dloss.
+// ---------------------------------------------------------------------------
+__global__ void k_grad_final(KCfg c, const InstDev* inst, const double* pacc, const double* pose_bar,
+                             const double* pose_jac, int n_steps, const double* dloss, double* grad) {
+  const int i = blockIdx.x;
+  double s[3] = {0.0, 0.0, 0.0};
+  for (int st = threadIdx.x; st < n_steps; st += blockDim.x) {
+    const double* pb = pose_bar + ((int64_t)i * c.max_steps + st) * 8;
+    const double* J = pose_jac + ((int64_t)i * c.max_steps + st) * 24;
+    for (int k = 0; k < 8; ++k)
+      for (int j = 0; j < 3; ++j) s[j] += pb[k] * J[k * 3 + j];
+  }
+  __shared__ double red[kBlock / 64][3];
+  for (int j = 0; j < 3; ++j) {
+    const double v = wave_sum(s[j]);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][j] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const InstDev& I = inst[i];
+    const double* a = pacc + (int64_t)i * 8;
+    const double sc = dloss[i];
+    double sk[3] = {0.0, 0.0, 0.0};
+    for (int w = 0; w < (int)blockDim.x / 64; ++w)
+      for (int j = 0; j < 3; ++j) sk[j] += red[w][j];
+    grad[i * 7 + 0] = sc * (a[0] * I.dmu_dE + a[1] * I.dlam_dE);
+    grad[i * 7 + 1] = sc * (a[0] * I.dmu_dnu + a[1] * I.dlam_dnu);
+    grad[i * 7 + 2] = sc * (a[2] * I.dal_dphi + a[3] * I.dkc_dphi);
+    grad[i * 7 + 3] = sc * a[4];
+    grad[i * 7 + 4] = sc * sk[0];
+    grad[i * 7 + 5] = sc * sk[1];
+    grad[i * 7 + 6] = sc * sk[2];
+  }
+}
+
+void launch_grad_final(const KCfg& c, const InstDev* inst, const double* pacc, const double* pose_bar,
+                       const double* pose_jac, int n_steps, const double* dloss, double* grad, hipStream_t s) {
+  hipLaunchKernelGGL(k_grad_final, dim3(c.n_inst), dim3(kBlock), 0, s, c, inst, pacc, pose_bar, pose_jac, n_steps,
+                     dloss, grad);
+}
+
+}  // namespace ddm

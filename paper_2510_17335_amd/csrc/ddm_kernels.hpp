@@ -1,0 +1,87 @@
+// Kernel launch interface shared by the runtime (ddm_runtime.hip) and the
+// kernels (ddm_kernels.hip).  Internal to libddmpm.so.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ddm {
+
+constexpr int kBlock = 256;          // particle kernels: threads per block, and the
+                                     // padding unit of every instance's particle range
+constexpr int kNodeVals = 4;         // node record: mv[0..2] (or v), m
+
+// Per-instance constants on the device (double; kernels cast to their type).
+struct InstDev {
+  double mu, lam, alpha, kc;         // Lame constants, alpha_f, cohesion shift k_c
+  double mp, Vp, dt;                 // particle mass and volume, sub-step
+  double dmu_dE, dmu_dnu, dlam_dE, dlam_dnu, dal_dphi, dkc_dphi;   // chain to (E, nu, phi_deg)
+  int64_t off, n;                    // first padded particle slot and particle count
+  int64_t goff;                      // first grid node of the instance
+  double tip0[3];
+};
+
+// Device error word.
+struct DevErr {
+  unsigned int flags;                // 1: NaN/Inf, 2: stencil left the grid, 4: sigma clamped
+  unsigned int first_inst;
+  unsigned long long clamps;
+};
+
+// Configuration passed by value to every kernel.
+struct KCfg {
+  int dim, n, bound, shovel, hm_res, region_sign, n_inst, max_steps;
+  int64_t nodes;                     // nodes per instance
+  int64_t ntot;                      // padded particle slots (SoA stride)
+  double dx, inv_dx, gravity, skin, mu_b, half[3];
+  double hm_ox, hm_oz, hm_pix, hm_off, region_depth;
+  double w_hm, w_mass, m_target, m_ref;
+};
+
+// Pointers of one launch.
+struct Bufs {
+  const InstDev* inst;
+  const int* blk_inst;               // instance of every particle block
+  const void* poses;                 // [n_inst][max_steps][8] (tip xyz, psi, vel xyz, omega)
+  DevErr* err;
+};
+
+// Forward sub-step pieces.  state_* are SoA particle states (stride ntot).
+void launch_fill_zero(void* p, int64_t count, int elem_bytes, hipStream_t s);
+void launch_init_state(int prec, const KCfg& c, const Bufs& b, int nblk, const void* x0, void* state,
+                       uint32_t* pid, hipStream_t s);
+void launch_p2g(int prec, const KCfg& c, const Bufs& b, int nblk, const void* st_in, void* st_out, void* grid,
+                hipStream_t s);
+void launch_grid_update(int prec, const KCfg& c, const Bufs& b, int step, const void* grid_pre, void* grid_post,
+                        hipStream_t s);
+void launch_g2p(int prec, const KCfg& c, const Bufs& b, int nblk, const void* st_in, void* st_out,
+                const void* grid_post, hipStream_t s);
+void launch_grid_export(int prec, const KCfg& c, const void* grid_pre, const void* grid_post, void* out,
+                        hipStream_t s);
+
+// Loss (height map + scoop mass) and its seed adjoint.
+struct LossBufs {
+  unsigned long long* hm_bits;       // [n_inst][npix] max height as ordered bits
+  unsigned int* owner;               // [n_inst][npix] lowest particle id at the max
+  const double* target;              // [n_inst][npix]
+  double* hm_val;                    // [n_inst][npix]
+  double* dldh;                      // [n_inst][npix]
+  double* region;                    // [n_inst] scoop mass
+  double* dldm;                      // [n_inst]
+  double* loss;                      // [n_inst]
+};
+void launch_loss(int prec, const KCfg& c, const Bufs& b, int nblk, const void* state, const uint32_t* pid,
+                 int final_step, const LossBufs& L, hipStream_t s);
+void launch_loss_seed(int prec, const KCfg& c, const Bufs& b, int nblk, const void* state, const uint32_t* pid,
+                      int final_step, const LossBufs& L, void* adj, double* pacc, hipStream_t s);
+
+// Adjoint sub-step pieces (reverse order: g2p_adj, grid_adj, p2g_adj).
+void launch_g2p_adj(int prec, const KCfg& c, const Bufs& b, int nblk, const void* st, const void* grid_post,
+                    const void* adj_next, void* adj_cur, void* gvb, hipStream_t s);
+void launch_grid_adj(int prec, const KCfg& c, const Bufs& b, int step, const void* grid_pre, const void* gvb,
+                     void* gb, double* pose_bar, hipStream_t s);
+void launch_p2g_adj(int prec, const KCfg& c, const Bufs& b, int nblk, const void* st, const void* gb,
+                    const void* adj_next, void* adj_cur, double* pacc, hipStream_t s);
+void launch_grad_final(const KCfg& c, const InstDev* inst, const double* pacc, const double* pose_bar,
+                       const double* pose_jac, int n_steps, const double* dloss, double* grad, hipStream_t s);
+
+}  // namespace ddm

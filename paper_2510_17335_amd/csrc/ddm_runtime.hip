@@ -1,0 +1,610 @@
+// Host runtime of libddmpm.so: validation, workspace layout, the digging
+// skill's pose tables, the rollout with checkpoints and the reverse pass, and
+// the C interface declared in include/ddmpm.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/ddmpm.h"
+#include "ddm_kernels.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+ddm_status fail(ddm_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+ddm_status hip_check(hipError_t e, const char* what) {
+  if (e == hipSuccess) return DDM_OK;
+  return fail(DDM_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define DDM_HIP(call)                                   \
+  do {                                                  \
+    ddm_status _s = hip_check((call), #call);           \
+    if (_s != DDM_OK) return _s;                        \
+  } while (0)
+
+constexpr double kPi = 3.14159265358979323846;
+
+bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
+
+int64_t pad_up(int64_t n, int64_t m) { return (n + m - 1) / m * m; }
+
+// Device workspace carved into 256-byte aligned pieces.
+struct Layout {
+  size_t inst = 0, blk_inst = 0, poses = 0, pose_jac = 0, err = 0, pid = 0;
+  size_t cur = 0, grid_pre = 0, grid_post = 0;
+  size_t ckpt = 0, seg_state = 0, seg_grid = 0;
+  size_t adj0 = 0, adj1 = 0, gvb = 0, gb = 0, pacc = 0, pose_bar = 0;
+  size_t hm_bits = 0, owner = 0, target = 0, hm_val = 0, dldh = 0, region = 0, dldm = 0, loss = 0;
+  size_t total = 0;
+  size_t state_bytes = 0, grid_bytes = 0;
+  int64_t ntot = 0, nblk = 0;
+  int n_ckpt = 0, K = 1;
+};
+
+struct Carver {
+  size_t off = 0;
+  size_t take(size_t bytes) {
+    off = (off + 255) / 256 * 256;
+    const size_t o = off;
+    off += bytes;
+    return o;
+  }
+};
+
+Layout make_layout(const ddm_config& c, int n_inst, const ddm_instance* in) {
+  Layout L;
+  const int D = c.dim;
+  const int b = c.precision == DDM_F64 ? 8 : 4;
+  int64_t ntot = 0;
+  for (int i = 0; i < n_inst; ++i) ntot += pad_up(in[i].n_particles, ddm::kBlock);
+  L.ntot = ntot;
+  L.nblk = ntot / ddm::kBlock;
+  int64_t nodes = 1;
+  for (int a = 0; a < D; ++a) nodes *= c.n_grid;
+  const int S = 2 * D + 2 * D * D;
+  L.state_bytes = (size_t)S * ntot * b;
+  L.grid_bytes = (size_t)n_inst * nodes * ddm::kNodeVals * b;
+  L.K = std::max(1, (int)c.checkpoint_every);
+  L.n_ckpt = (c.max_steps + L.K - 1) / L.K + 1;
+  const int npix = D == 3 ? c.hm_res * c.hm_res : c.hm_res;
+  Carver cv;
+  L.inst = cv.take(sizeof(ddm::InstDev) * n_inst);
+  L.blk_inst = cv.take(sizeof(int) * L.nblk);
+  L.poses = cv.take((size_t)n_inst * c.max_steps * 8 * b);
+  L.pose_jac = cv.take((size_t)n_inst * c.max_steps * 24 * sizeof(double));
+  L.err = cv.take(sizeof(ddm::DevErr));
+  L.pid = cv.take(sizeof(uint32_t) * ntot);
+  L.cur = cv.take(L.state_bytes);
+  L.grid_pre = cv.take(L.grid_bytes);
+  L.grid_post = cv.take(L.grid_bytes);
+  L.ckpt = cv.take(L.state_bytes * L.n_ckpt);
+  L.seg_state = cv.take(L.state_bytes * (L.K + 1));
+  L.seg_grid = cv.take(L.grid_bytes * 2 * L.K);
+  L.adj0 = cv.take(L.state_bytes);
+  L.adj1 = cv.take(L.state_bytes);
+  L.gvb = cv.take(L.grid_bytes);
+  L.gb = cv.take(L.grid_bytes);
+  L.pacc = cv.take(sizeof(double) * 8 * n_inst);
+  L.pose_bar = cv.take(sizeof(double) * 8 * (size_t)n_inst * c.max_steps);
+  L.hm_bits = cv.take(sizeof(unsigned long long) * (size_t)n_inst * npix);
+  L.owner = cv.take(sizeof(unsigned int) * (size_t)n_inst * npix);
+  L.target = cv.take(sizeof(double) * (size_t)n_inst * npix);
+  L.hm_val = cv.take(sizeof(double) * (size_t)n_inst * npix);
+  L.dldh = cv.take(sizeof(double) * (size_t)n_inst * npix);
+  L.region = cv.take(sizeof(double) * n_inst);
+  L.dldm = cv.take(sizeof(double) * n_inst);
+  L.loss = cv.take(sizeof(double) * n_inst);
+  L.total = cv.take(0);
+  return L;
+}
+
+// ---------------------------------------------------------------------------
+// Digging skill (Sec. III-B): phase lengths T_i = round(T^float_i) (half away
+// from zero, no derivative), per-action displacements of the four phases with
+// d1 = 0 and push angle phi3 = pi fixed, and the per-sub-step blade pose: the
+// action is spread evenly over the n_sub sub-steps and applied before the grid
+// collision (Algorithm 1 line 7).  Build frame: paper (x, y, z) -> (x, z, y),
+// rotation about the paper's x axis -> psi.  Jacobian columns: d/d(depth,
+// angle_deg, push).
+// ---------------------------------------------------------------------------
+struct Action { double d[6]; double J[6][3]; };   // paper frame [dx, dy, dz, drx, dry, drz]
+
+std::vector<Action> skill_actions(const ddm_config& c, const ddm_instance& in) {
+  const double dta = c.n_sub * in.dt;
+  const double rad = kPi / 180.0;
+  const double phi1 = in.angle_deg * rad, d2 = in.depth, d3 = in.push, d4 = c.d_lift;
+  const double phi3 = kPi;                           // push angle parameter 0 -> (0 + 3) pi / 3
+  const double Tf_phi1 = std::fabs(phi1 / (c.v_ang * dta));
+  const long T1 = std::lround(Tf_phi1);              // d1 = 0, so the rotation sets the length
+  const long T2 = std::lround(d2 / (c.v_lin * dta));
+  const long T3 = std::lround(std::fabs(d3 / (c.v_lin * dta)));
+  const long T4 = std::lround(std::max(Tf_phi1, d4 / (c.v_lin * dta)));
+  const double phi2 = phi1 + kPi / 2.0;
+  std::vector<Action> out;
+  auto blank = [] { Action a; std::memset(&a, 0, sizeof(a)); return a; };
+  for (long t = 0; t < T1; ++t) {
+    Action a = blank();
+    a.d[3] = phi1 / T1;
+    a.J[3][1] = rad / T1;
+    out.push_back(a);
+  }
+  for (long t = 0; t < T2; ++t) {
+    Action a = blank();
+    a.d[0] = d2 * std::cos(phi2) / T2;
+    a.d[2] = -(d2 * std::sin(phi2)) / T2;
+    a.J[0][0] = std::cos(phi2) / T2;
+    a.J[0][1] = -d2 * std::sin(phi2) * rad / T2;
+    a.J[2][0] = -std::sin(phi2) / T2;
+    a.J[2][1] = -d2 * std::cos(phi2) * rad / T2;
+    out.push_back(a);
+  }
+  for (long t = 0; t < T3; ++t) {
+    Action a = blank();
+    a.d[0] = d3 * std::cos(phi3) / T3;
+    a.d[2] = d3 * std::sin(phi3) / T3;
+    a.J[0][2] = std::cos(phi3) / T3;
+    a.J[2][2] = std::sin(phi3) / T3;
+    out.push_back(a);
+  }
+  for (long t = 0; t < T4; ++t) {
+    Action a = blank();
+    a.d[3] = -phi1 / T4;
+    a.d[2] = d4 / T4;
+    a.J[3][1] = -rad / T4;
+    out.push_back(a);
+  }
+  return out;
+}
+
+// Pose rows (tip xyz, psi, vel xyz, omega) and their Jacobians for steps 0..max_steps-1.
+void pose_table(const ddm_config& c, const ddm_instance& in, std::vector<double>& pose, std::vector<double>& jac) {
+  const std::vector<Action> acts = skill_actions(c, in);
+  pose.assign((size_t)c.max_steps * 8, 0.0);
+  jac.assign((size_t)c.max_steps * 24, 0.0);
+  double tip[3] = {in.tip0[0], in.tip0[1], in.tip0[2]}, psi = 0.0;
+  double Jtip[3][3] = {{0}}, Jpsi[3] = {0, 0, 0};
+  const double inv_n = 1.0 / c.n_sub;
+  for (int n = 0; n < c.max_steps; ++n) {
+    const size_t t = (size_t)(n / c.n_sub);
+    double* row = &pose[(size_t)n * 8];
+    double* J = &jac[(size_t)n * 24];
+    double vel[3] = {0, 0, 0}, om = 0.0, Jvel[3][3] = {{0}}, Jom[3] = {0, 0, 0};
+    if (t < acts.size()) {
+      const Action& a = acts[t];
+      const int map[3] = {0, 2, 1};                // build axis k takes paper entry map[k]
+      for (int k = 0; k < 3; ++k) {
+        const double dk = a.d[map[k]] * inv_n;
+        tip[k] += dk;
+        vel[k] = dk / in.dt;
+        for (int j = 0; j < 3; ++j) {
+          Jtip[k][j] += a.J[map[k]][j] * inv_n;
+          Jvel[k][j] = a.J[map[k]][j] * inv_n / in.dt;
+        }
+      }
+      const double dpsi = a.d[3] * inv_n;
+      psi += dpsi;
+      om = dpsi / in.dt;
+      for (int j = 0; j < 3; ++j) { Jpsi[j] += a.J[3][j] * inv_n; Jom[j] = a.J[3][j] * inv_n / in.dt; }
+    }
+    for (int k = 0; k < 3; ++k) { row[k] = tip[k]; row[4 + k] = vel[k]; }
+    row[3] = psi;
+    row[7] = om;
+    for (int j = 0; j < 3; ++j) {
+      for (int k = 0; k < 3; ++k) { J[k * 3 + j] = Jtip[k][j]; J[(4 + k) * 3 + j] = Jvel[k][j]; }
+      J[3 * 3 + j] = Jpsi[j];
+      J[7 * 3 + j] = Jom[j];
+    }
+  }
+}
+
+}  // namespace
+
+struct ddm_ctx {
+  ddm_config cfg;
+  int n_inst = 0;
+  std::vector<ddm_instance> inst;
+  Layout L;
+  char* ws = nullptr;
+  hipStream_t stream = nullptr;
+  ddm::KCfg kc;
+  int prec = 0;
+  int64_t steps = 0;             // sub-steps since ddm_init_state
+  bool initialised = false;
+  bool recorded = false;         // a rollout is recorded
+  int64_t rec_k0 = 0, rec_n = 0;
+  bool loss_ready = false;
+
+  template <typename T = char> T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
+  ddm::Bufs bufs() const {
+    ddm::Bufs b;
+    b.inst = at<const ddm::InstDev>(L.inst);
+    b.blk_inst = at<const int>(L.blk_inst);
+    b.poses = at<const void>(L.poses);
+    b.err = at<ddm::DevErr>(L.err);
+    return b;
+  }
+  ddm::LossBufs lossbufs() const {
+    ddm::LossBufs l;
+    l.hm_bits = at<unsigned long long>(L.hm_bits);
+    l.owner = at<unsigned int>(L.owner);
+    l.target = at<const double>(L.target);
+    l.hm_val = at<double>(L.hm_val);
+    l.dldh = at<double>(L.dldh);
+    l.region = at<double>(L.region);
+    l.dldm = at<double>(L.dldm);
+    l.loss = at<double>(L.loss);
+    return l;
+  }
+};
+
+namespace {
+
+ddm_status validate(const ddm_config* c, int32_t n_inst, const ddm_instance* in) {
+  if (!c) return fail(DDM_EINVAL, "config is NULL");
+  if (c->dim != 2 && c->dim != 3) return fail(DDM_EINVAL, "dim must be 2 or 3");
+  if (!is_pow2(c->n_grid) || c->n_grid < 16 || c->n_grid > 256)
+    return fail(DDM_EINVAL, "n_grid must be a power of two in [16, 256]");
+  if (c->bound < 0 || c->bound > c->n_grid / 4) return fail(DDM_EINVAL, "bound out of [0, n_grid/4]");
+  if (c->precision != DDM_F32 && c->precision != DDM_F64) return fail(DDM_EINVAL, "precision must be DDM_F32 or DDM_F64");
+  if (c->shovel && c->dim != 3) return fail(DDM_EINVAL, "the shovel needs dim 3");
+  if (c->n_sub < 1) return fail(DDM_EINVAL, "n_sub must be >= 1");
+  if (!(c->ppc > 0)) return fail(DDM_EINVAL, "ppc must be > 0");
+  if (c->hm_res < 1 || c->hm_res > 4096) return fail(DDM_EINVAL, "hm_res out of [1, 4096]");
+  if (!(c->hm_size > 0)) return fail(DDM_EINVAL, "hm_size must be > 0");
+  if (c->checkpoint_every < 1) return fail(DDM_EINVAL, "checkpoint_every must be >= 1");
+  if (c->max_steps < 1) return fail(DDM_EINVAL, "max_steps must be >= 1");
+  if (c->shovel && !(c->v_lin > 0 && c->v_ang > 0 && c->d_lift > 0 && c->contact_skin >= 0 && c->shovel_mu >= 0))
+    return fail(DDM_EINVAL, "shovel speeds, lift, skin and friction must be positive");
+  if (n_inst < 1 || !in) return fail(DDM_EINVAL, "need at least one instance");
+  int64_t nodes = 1;
+  for (int a = 0; a < c->dim; ++a) nodes *= c->n_grid;
+  if ((double)nodes * n_inst * ddm::kNodeVals > 9.0e18) return fail(DDM_EINVAL, "grid too large");
+  int64_t ntot = 0;
+  for (int i = 0; i < n_inst; ++i) {
+    const ddm_instance& s = in[i];
+    char buf[160];
+    auto bad = [&](const char* what) {
+      std::snprintf(buf, sizeof(buf), "instance %d: %s", i, what);
+      return fail(DDM_EINVAL, buf);
+    };
+    if (s.n_particles <= 0) return bad("n_particles must be > 0");
+    if (s.n_particles > 0x7FFFFFFF) return bad("n_particles too large");
+    if (!(s.E > 0)) return bad("E must be > 0");
+    if (!(s.nu > -1.0 && s.nu < 0.5)) return bad("nu must be in (-1, 0.5)");
+    if (!(s.phi_deg > 0 && s.phi_deg < 90)) return bad("phi_deg must be in (0, 90)");
+    if (!(s.rho > 0)) return bad("rho must be > 0");
+    if (!(s.cohesion >= 0)) return bad("cohesion must be >= 0");
+    if (!(s.dt > 0)) return bad("dt must be > 0");
+    if (c->shovel && !(s.depth >= 0 && s.push >= 0)) return bad("skill depth and push must be >= 0");
+    ntot += pad_up(s.n_particles, ddm::kBlock);
+  }
+  if (ntot > ((int64_t)1 << 31)) return fail(DDM_EINVAL, "too many particles in total");
+  return DDM_OK;
+}
+
+template <typename T>
+void to_prec(const std::vector<double>& src, std::vector<char>& out) {
+  out.resize(src.size() * sizeof(T));
+  T* d = reinterpret_cast<T*>(out.data());
+  for (size_t i = 0; i < src.size(); ++i) d[i] = (T)src[i];
+}
+
+ddm_status launch_status() { return hip_check(hipGetLastError(), "kernel launch"); }
+
+// One forward sub-step from st_in to st_out (may alias); grids given.
+ddm_status forward_step(ddm_ctx* x, int64_t step, const void* st_in, void* st_out, void* gpre, void* gpost) {
+  const ddm::Bufs b = x->bufs();
+  const int esz = x->prec ? 8 : 4;
+  ddm::launch_fill_zero(gpre, (int64_t)x->L.grid_bytes / esz, esz, x->stream);
+  ddm::launch_p2g(x->prec, x->kc, b, (int)x->L.nblk, st_in, st_out, gpre, x->stream);
+  ddm::launch_grid_update(x->prec, x->kc, b, (int)step, gpre, gpost, x->stream);
+  ddm::launch_g2p(x->prec, x->kc, b, (int)x->L.nblk, st_in, st_out, gpost, x->stream);
+  return launch_status();
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ddm_status_str(ddm_status s) {
+  switch (s) {
+    case DDM_OK: return "ok";
+    case DDM_EINVAL: return "invalid argument";
+    case DDM_ENOMEM: return "workspace too small";
+    case DDM_EDEVICE: return "device error";
+    case DDM_ENAN: return "NaN or Inf in the state";
+    case DDM_EDOMAIN: return "particle stencil left the grid";
+    case DDM_ESTATE: return "call out of order";
+  }
+  return "unknown status";
+}
+
+const char* ddm_last_error(void) { return g_last_error.c_str(); }
+
+ddm_status ddm_validate_config(const ddm_config* cfg, int32_t n_inst, const ddm_instance* inst, char* msg,
+                               size_t msg_len) {
+  const ddm_status s = validate(cfg, n_inst, inst);
+  if (msg && msg_len) {
+    const std::string& m = s == DDM_OK ? std::string() : g_last_error;
+    std::snprintf(msg, msg_len, "%s", m.c_str());
+  }
+  return s;
+}
+
+ddm_status ddm_workspace_query(const ddm_config* cfg, int32_t n_inst, const ddm_instance* inst, ddm_sizes* out) {
+  const ddm_status s = validate(cfg, n_inst, inst);
+  if (s != DDM_OK) return s;
+  if (!out) return fail(DDM_EINVAL, "out is NULL");
+  const Layout L = make_layout(*cfg, n_inst, inst);
+  out->workspace_bytes = L.total;
+  out->state_bytes = L.state_bytes;
+  out->padded_particles = L.ntot;
+  return DDM_OK;
+}
+
+ddm_status ddm_create(const ddm_config* cfg, int32_t n_inst, const ddm_instance* inst, void* workspace,
+                      size_t workspace_bytes, void* stream, ddm_ctx** out) {
+  if (!out) return fail(DDM_EINVAL, "out is NULL");
+  *out = nullptr;
+  ddm_status s = validate(cfg, n_inst, inst);
+  if (s != DDM_OK) return s;
+  const Layout L = make_layout(*cfg, n_inst, inst);
+  if (!workspace) return fail(DDM_EINVAL, "workspace is NULL");
+  if ((reinterpret_cast<uintptr_t>(workspace) & 255u) != 0) return fail(DDM_EINVAL, "workspace must be 256-byte aligned");
+  if (workspace_bytes < L.total)
+    return fail(DDM_ENOMEM, "workspace too small: need " + std::to_string(L.total) + " bytes, got " +
+                                std::to_string(workspace_bytes));
+  ddm_ctx* x = new ddm_ctx();
+  x->cfg = *cfg;
+  x->n_inst = n_inst;
+  x->inst.assign(inst, inst + n_inst);
+  x->L = L;
+  x->ws = static_cast<char*>(workspace);
+  x->stream = static_cast<hipStream_t>(stream);
+  x->prec = cfg->precision == DDM_F64 ? 1 : 0;
+  ddm::KCfg& k = x->kc;
+  k.dim = cfg->dim; k.n = cfg->n_grid; k.bound = cfg->bound; k.shovel = cfg->shovel;
+  k.hm_res = cfg->hm_res; k.region_sign = cfg->region_sign >= 0 ? 1 : -1; k.n_inst = n_inst;
+  k.max_steps = cfg->max_steps;
+  k.nodes = 1;
+  for (int a = 0; a < cfg->dim; ++a) k.nodes *= cfg->n_grid;
+  k.ntot = L.ntot;
+  k.dx = 1.0 / cfg->n_grid; k.inv_dx = (double)cfg->n_grid; k.gravity = cfg->gravity;
+  k.skin = cfg->contact_skin; k.mu_b = cfg->shovel_mu;
+  for (int a = 0; a < 3; ++a) k.half[a] = cfg->shovel_half[a];
+  k.hm_ox = cfg->hm_origin[0]; k.hm_oz = cfg->hm_origin[1]; k.hm_pix = cfg->hm_size / cfg->hm_res;
+  k.hm_off = cfg->hm_offset; k.region_depth = cfg->region_depth;
+  k.w_hm = cfg->w_hm; k.w_mass = cfg->w_mass; k.m_target = cfg->m_target; k.m_ref = cfg->m_ref;
+
+  // Per-instance constants: Lame constants from (E, nu), alpha_f and the
+  // cohesion shift from the friction angle, particle mass and volume, and
+  // their derivatives for the final chain rule.
+  std::vector<ddm::InstDev> dev(n_inst);
+  std::vector<int> blk((size_t)L.nblk);
+  int64_t off = 0;
+  const double dxd = std::pow(1.0 / cfg->n_grid, cfg->dim);
+  for (int i = 0; i < n_inst; ++i) {
+    const ddm_instance& s = inst[i];
+    ddm::InstDev& d = dev[i];
+    const double E = s.E, nu = s.nu, ph = s.phi_deg * kPi / 180.0, sp = std::sin(ph), cp = std::cos(ph);
+    d.mu = E / (2.0 * (1.0 + nu));
+    d.lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+    const double r23 = std::sqrt(2.0 / 3.0);
+    d.alpha = r23 * 2.0 * sp / (3.0 - sp);
+    d.kc = r23 * 6.0 * s.cohesion * cp / (3.0 - sp);
+    d.Vp = dxd / cfg->ppc;
+    d.mp = s.rho * d.Vp;
+    d.dt = s.dt;
+    d.dmu_dE = 1.0 / (2.0 * (1.0 + nu));
+    d.dmu_dnu = -E / (2.0 * (1.0 + nu) * (1.0 + nu));
+    const double den = (1.0 + nu) * (1.0 - 2.0 * nu);
+    d.dlam_dE = nu / den;
+    d.dlam_dnu = E * (1.0 + 2.0 * nu * nu) / (den * den);
+    const double rad = kPi / 180.0;
+    d.dal_dphi = r23 * 6.0 * cp / ((3.0 - sp) * (3.0 - sp)) * rad;
+    d.dkc_dphi = r23 * 6.0 * s.cohesion * (1.0 - 3.0 * sp) / ((3.0 - sp) * (3.0 - sp)) * rad;
+    d.off = off;
+    d.n = s.n_particles;
+    d.goff = (int64_t)i * k.nodes;
+    for (int a = 0; a < 3; ++a) d.tip0[a] = s.tip0[a];
+    const int64_t np = pad_up(s.n_particles, ddm::kBlock);
+    for (int64_t bI = off / ddm::kBlock; bI < (off + np) / ddm::kBlock; ++bI) blk[(size_t)bI] = i;
+    off += np;
+  }
+  std::vector<double> poses((size_t)n_inst * cfg->max_steps * 8, 0.0), jac((size_t)n_inst * cfg->max_steps * 24, 0.0);
+  if (cfg->shovel) {
+    for (int i = 0; i < n_inst; ++i) {
+      std::vector<double> p, j;
+      pose_table(*cfg, inst[i], p, j);
+      std::copy(p.begin(), p.end(), poses.begin() + (size_t)i * cfg->max_steps * 8);
+      std::copy(j.begin(), j.end(), jac.begin() + (size_t)i * cfg->max_steps * 24);
+    }
+  }
+  std::vector<char> poses_t;
+  if (x->prec) to_prec<double>(poses, poses_t); else to_prec<float>(poses, poses_t);
+  // Host staging arrays are copied synchronously so the caller's memory is free on return.
+  s = hip_check(hipMemcpy(x->at(L.inst), dev.data(), sizeof(ddm::InstDev) * n_inst, hipMemcpyHostToDevice), "upload instances");
+  if (s == DDM_OK) s = hip_check(hipMemcpy(x->at(L.blk_inst), blk.data(), sizeof(int) * blk.size(), hipMemcpyHostToDevice), "upload block map");
+  if (s == DDM_OK) s = hip_check(hipMemcpy(x->at(L.poses), poses_t.data(), poses_t.size(), hipMemcpyHostToDevice), "upload poses");
+  if (s == DDM_OK) s = hip_check(hipMemcpy(x->at(L.pose_jac), jac.data(), jac.size() * sizeof(double), hipMemcpyHostToDevice), "upload pose Jacobian");
+  if (s == DDM_OK) s = hip_check(hipMemset(x->at(L.err), 0, sizeof(ddm::DevErr)), "clear error word");
+  if (s != DDM_OK) { delete x; return s; }
+  *out = x;
+  return DDM_OK;
+}
+
+ddm_status ddm_init_state(ddm_ctx* x, const void* x0_dev) {
+  if (!x || !x0_dev) return fail(DDM_EINVAL, "NULL argument");
+  ddm::launch_init_state(x->prec, x->kc, x->bufs(), (int)x->L.nblk, x0_dev, x->at(x->L.cur), x->at<uint32_t>(x->L.pid),
+                         x->stream);
+  DDM_HIP(hipMemsetAsync(x->at(x->L.err), 0, sizeof(ddm::DevErr), x->stream));
+  x->steps = 0;
+  x->initialised = true;
+  x->recorded = false;
+  x->loss_ready = false;
+  return launch_status();
+}
+
+ddm_status ddm_step(ddm_ctx* x, int32_t n_steps) {
+  if (!x) return fail(DDM_EINVAL, "NULL context");
+  if (!x->initialised) return fail(DDM_ESTATE, "ddm_init_state first");
+  if (n_steps < 0) return fail(DDM_EINVAL, "n_steps < 0");
+  if (x->cfg.shovel && x->steps + n_steps > x->cfg.max_steps)
+    return fail(DDM_EINVAL, "steps beyond max_steps (the pose table length)");
+  for (int i = 0; i < n_steps; ++i) {
+    const ddm_status s = forward_step(x, x->steps, x->at(x->L.cur), x->at(x->L.cur), x->at(x->L.grid_pre), x->at(x->L.grid_post));
+    if (s != DDM_OK) return s;
+    ++x->steps;
+  }
+  x->recorded = false;
+  x->loss_ready = false;
+  return DDM_OK;
+}
+
+ddm_status ddm_rollout(ddm_ctx* x, int32_t n_steps) {
+  if (!x) return fail(DDM_EINVAL, "NULL context");
+  if (!x->initialised) return fail(DDM_ESTATE, "ddm_init_state first");
+  if (n_steps < 1) return fail(DDM_EINVAL, "n_steps must be >= 1");
+  if (x->steps + n_steps > x->cfg.max_steps) return fail(DDM_EINVAL, "rollout longer than max_steps");
+  const int K = x->L.K;
+  const int64_t k0 = x->steps;
+  for (int i = 0; i < n_steps; ++i) {
+    if (i % K == 0)
+      DDM_HIP(hipMemcpyAsync(x->at(x->L.ckpt + (size_t)(i / K) * x->L.state_bytes), x->at(x->L.cur), x->L.state_bytes,
+                             hipMemcpyDeviceToDevice, x->stream));
+    const ddm_status s = forward_step(x, k0 + i, x->at(x->L.cur), x->at(x->L.cur), x->at(x->L.grid_pre), x->at(x->L.grid_post));
+    if (s != DDM_OK) return s;
+    ++x->steps;
+  }
+  x->recorded = true;
+  x->rec_k0 = k0;
+  x->rec_n = n_steps;
+  x->loss_ready = false;
+  return DDM_OK;
+}
+
+ddm_status ddm_loss(ddm_ctx* x, const double* target_hm_dev, double* loss_dev) {
+  if (!x || !target_hm_dev || !loss_dev) return fail(DDM_EINVAL, "NULL argument");
+  if (!x->initialised) return fail(DDM_ESTATE, "ddm_init_state first");
+  const int npix = x->cfg.dim == 3 ? x->cfg.hm_res * x->cfg.hm_res : x->cfg.hm_res;
+  DDM_HIP(hipMemcpyAsync(x->at(x->L.target), target_hm_dev, sizeof(double) * (size_t)x->n_inst * npix,
+                         hipMemcpyDeviceToDevice, x->stream));
+  ddm::launch_loss(x->prec, x->kc, x->bufs(), (int)x->L.nblk, x->at(x->L.cur), x->at<uint32_t>(x->L.pid),
+                   (int)x->steps - 1, x->lossbufs(), x->stream);
+  DDM_HIP(hipMemcpyAsync(loss_dev, x->at(x->L.loss), sizeof(double) * x->n_inst, hipMemcpyDeviceToDevice, x->stream));
+  x->loss_ready = x->recorded && x->steps == x->rec_k0 + x->rec_n;
+  return launch_status();
+}
+
+ddm_status ddm_backward(ddm_ctx* x, const double* dloss_dev, double* grad_dev) {
+  if (!x || !dloss_dev || !grad_dev) return fail(DDM_EINVAL, "NULL argument");
+  if (!x->recorded || !x->loss_ready) return fail(DDM_ESTATE, "ddm_backward needs ddm_rollout then ddm_loss");
+  const Layout& L = x->L;
+  const ddm::Bufs b = x->bufs();
+  const int esz = x->prec ? 8 : 4;
+  hipStream_t st = x->stream;
+  ddm::launch_fill_zero(x->at(L.pacc), (int64_t)8 * x->n_inst, 8, st);
+  ddm::launch_fill_zero(x->at(L.pose_bar), (int64_t)8 * x->n_inst * x->cfg.max_steps, 8, st);
+  void* adj[2] = {x->at(L.adj0), x->at(L.adj1)};
+  int cur = 0;
+  ddm::launch_loss_seed(x->prec, x->kc, b, (int)L.nblk, x->at(L.cur), x->at<uint32_t>(L.pid), (int)x->steps - 1,
+                        x->lossbufs(), adj[cur], x->at<double>(L.pacc), st);
+  const int K = L.K;
+  const int64_t n = x->rec_n, k0 = x->rec_k0;
+  const int nseg = (int)((n + K - 1) / K);
+  auto slot = [&](int j) { return x->at(L.seg_state + (size_t)j * L.state_bytes); };
+  auto gpre = [&](int j) { return x->at(L.seg_grid + (size_t)(2 * j) * L.grid_bytes); };
+  auto gpost = [&](int j) { return x->at(L.seg_grid + (size_t)(2 * j + 1) * L.grid_bytes); };
+  for (int seg = nseg - 1; seg >= 0; --seg) {
+    const int64_t s0 = (int64_t)seg * K;
+    const int len = (int)std::min<int64_t>(K, n - s0);
+    DDM_HIP(hipMemcpyAsync(slot(0), x->at(L.ckpt + (size_t)seg * L.state_bytes), L.state_bytes, hipMemcpyDeviceToDevice, st));
+    for (int j = 0; j < len; ++j) {
+      const ddm_status s = forward_step(x, k0 + s0 + j, slot(j), slot(j + 1), gpre(j), gpost(j));
+      if (s != DDM_OK) return s;
+    }
+    for (int j = len - 1; j >= 0; --j) {
+      ddm::launch_fill_zero(x->at(L.gvb), (int64_t)L.grid_bytes / esz, esz, st);
+      ddm::launch_g2p_adj(x->prec, x->kc, b, (int)L.nblk, slot(j), gpost(j), adj[cur], adj[1 - cur], x->at(L.gvb), st);
+      ddm::launch_grid_adj(x->prec, x->kc, b, (int)(k0 + s0 + j), gpre(j), x->at(L.gvb), x->at(L.gb),
+                           x->at<double>(L.pose_bar), st);
+      ddm::launch_p2g_adj(x->prec, x->kc, b, (int)L.nblk, slot(j), x->at(L.gb), adj[cur], adj[1 - cur],
+                          x->at<double>(L.pacc), st);
+      cur = 1 - cur;
+    }
+    const ddm_status s = launch_status();
+    if (s != DDM_OK) return s;
+  }
+  ddm::launch_grad_final(x->kc, x->at<const ddm::InstDev>(L.inst), x->at<const double>(L.pacc),
+                         x->at<const double>(L.pose_bar), x->at<const double>(L.pose_jac), (int)(k0 + n), dloss_dev,
+                         grad_dev, st);
+  return launch_status();
+}
+
+ddm_status ddm_get_state(ddm_ctx* x, void* state_dev) {
+  if (!x || !state_dev) return fail(DDM_EINVAL, "NULL argument");
+  DDM_HIP(hipMemcpyAsync(state_dev, x->at(x->L.cur), x->L.state_bytes, hipMemcpyDeviceToDevice, x->stream));
+  return DDM_OK;
+}
+
+ddm_status ddm_set_state(ddm_ctx* x, const void* state_dev) {
+  if (!x || !state_dev) return fail(DDM_EINVAL, "NULL argument");
+  if (!x->initialised) return fail(DDM_ESTATE, "ddm_init_state first");
+  DDM_HIP(hipMemcpyAsync(x->at(x->L.cur), state_dev, x->L.state_bytes, hipMemcpyDeviceToDevice, x->stream));
+  x->recorded = false;
+  x->loss_ready = false;
+  return DDM_OK;
+}
+
+ddm_status ddm_get_grid(ddm_ctx* x, void* grid_dev) {
+  if (!x || !grid_dev) return fail(DDM_EINVAL, "NULL argument");
+  ddm::launch_grid_export(x->prec, x->kc, x->at(x->L.grid_pre), x->at(x->L.grid_post), grid_dev, x->stream);
+  return launch_status();
+}
+
+ddm_status ddm_get_heightmap(ddm_ctx* x, double* hm_dev) {
+  if (!x || !hm_dev) return fail(DDM_EINVAL, "NULL argument");
+  const int npix = x->cfg.dim == 3 ? x->cfg.hm_res * x->cfg.hm_res : x->cfg.hm_res;
+  DDM_HIP(hipMemcpyAsync(hm_dev, x->at(x->L.hm_val), sizeof(double) * (size_t)x->n_inst * npix, hipMemcpyDeviceToDevice,
+                         x->stream));
+  return DDM_OK;
+}
+
+ddm_status ddm_check(ddm_ctx* x, ddm_device_error* out) {
+  if (!x) return fail(DDM_EINVAL, "NULL context");
+  DDM_HIP(hipStreamSynchronize(x->stream));
+  ddm::DevErr e;
+  DDM_HIP(hipMemcpy(&e, x->at(x->L.err), sizeof(e), hipMemcpyDeviceToHost));
+  if (out) {
+    out->flags = e.flags;
+    out->first_instance = e.first_inst;
+    out->clamp_count = e.clamps;
+  }
+  if (e.flags & 1u) return fail(DDM_ENAN, "NaN or Inf in instance " + std::to_string(e.first_inst));
+  if (e.flags & 2u) return fail(DDM_EDOMAIN, "a particle stencil left the grid in instance " + std::to_string(e.first_inst));
+  return DDM_OK;
+}
+
+int64_t ddm_steps_taken(const ddm_ctx* x) { return x ? x->steps : -1; }
+
+int64_t ddm_instance_offset(const ddm_ctx* x, int32_t i) {
+  if (!x || i < 0 || i >= x->n_inst) return -1;
+  int64_t off = 0;
+  for (int k = 0; k < i; ++k) off += pad_up(x->inst[k].n_particles, ddm::kBlock);
+  return off;
+}
+
+void ddm_destroy(ddm_ctx* x) { delete x; }
+
+}  // extern "C"

@@ -1,0 +1,132 @@
+"""The C-ABI boundary on the host: the library loads, exports every declared
+entry point, validates configurations and sizes its workspace.  No GPU."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+import paper_2510_17335_amd as ddm
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", fn)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names |= set(re.findall(r"\b(ddm_[a-z_]+)\s*\(", text))
+    return names
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(ddm.LIB_PATH):
+        from paper_2510_17335_amd import build
+        build.build()
+    return ddm.lib()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = _declared_symbols()
+    assert len(names) >= 18
+    for n in sorted(names):
+        assert hasattr(lib, n), n
+
+
+def test_status_strings(lib):
+    for code in range(7):
+        assert lib.ddm_status_str(code)
+
+
+def _good():
+    w = W.dig_3d()
+    cfg, inst = ddm.from_workload(w)
+    return cfg, inst
+
+
+def test_validate_accepts_workloads(lib):
+    for w in (W.column_2d(), W.dig_3d(), W.dig_3d_backward(), W.dig_3d_large(), W.tiny(2), W.tiny(3, shovel=True)):
+        cfg, inst = ddm.from_workload(w)
+        assert ddm.validate_config(cfg, [inst]) == ""
+
+
+@pytest.mark.parametrize("field,value,needle", [
+    ("nu", 0.5, "nu"), ("nu", -1.0, "nu"), ("E", 0.0, "E"), ("E", -1.0, "E"), ("phi_deg", 0.0, "phi"),
+    ("phi_deg", 90.0, "phi"), ("rho", 0.0, "rho"), ("dt", 0.0, "dt"), ("n_particles", 0, "n_particles"),
+    ("cohesion", -1.0, "cohesion"), ("depth", -0.01, "depth"),
+])
+def test_validate_rejects_bad_instance(lib, field, value, needle):
+    cfg, inst = _good()
+    setattr(inst, field, value)
+    msg = ddm.validate_config(cfg, [inst])
+    assert needle in msg
+
+
+@pytest.mark.parametrize("field,value,needle", [
+    ("dim", 4, "dim"), ("n_grid", 48, "n_grid"), ("n_grid", 8, "n_grid"), ("n_grid", 512, "n_grid"),
+    ("bound", 40, "bound"), ("precision", 7, "precision"), ("checkpoint_every", 0, "checkpoint"),
+    ("max_steps", 0, "max_steps"), ("n_sub", 0, "n_sub"),
+])
+def test_validate_rejects_bad_config(lib, field, value, needle):
+    cfg, inst = _good()
+    setattr(cfg, field, value)
+    assert needle in ddm.validate_config(cfg, [inst])
+
+
+def test_shovel_needs_3d(lib):
+    cfg, inst = ddm.from_workload(W.column_2d())
+    cfg.shovel = 1
+    assert "shovel" in ddm.validate_config(cfg, [inst])
+
+
+def test_workspace_sizes(lib):
+    cfg, inst = _good()
+    s1 = ddm.workspace_query(cfg, [inst])
+    assert s1.padded_particles == 219488 + (-219488) % 256
+    assert s1.state_bytes == 24 * 4 * s1.padded_particles
+    # checkpoints + segment: more memory for longer rollouts and larger K
+    cfg.max_steps = 2000
+    s2 = ddm.workspace_query(cfg, [inst])
+    assert s2.workspace_bytes > s1.workspace_bytes
+    cfg.precision = ddm.DDM_F64
+    s3 = ddm.workspace_query(cfg, [inst])
+    assert s3.state_bytes == 2 * s2.state_bytes
+    # batched: padded ranges per instance
+    i2 = ddm.make_instance(1000)
+    s4 = ddm.workspace_query(cfg, [inst, i2])
+    assert s4.padded_particles == s3.padded_particles + 1024
+
+
+def test_workspace_query_rejects_bad(lib):
+    cfg, inst = _good()
+    inst.nu = 0.7
+    with pytest.raises(ddm.DdmError) as e:
+        ddm.workspace_query(cfg, [inst])
+    assert e.value.code == ddm.DDM_EINVAL
+
+
+def test_create_rejects_small_or_null_workspace(lib):
+    cfg, inst = _good()
+    arr = (ddm.DdmInstance * 1)(inst)
+    ctx = C.c_void_p()
+    rc = lib.ddm_create(C.byref(cfg), 1, arr, None, 0, None, C.byref(ctx))
+    assert rc == ddm.DDM_EINVAL and not ctx.value
+    # a fake, aligned, too-small "workspace" is rejected before any device access
+    rc = lib.ddm_create(C.byref(cfg), 1, arr, C.c_void_p(256), 1024, None, C.byref(ctx))
+    assert rc == ddm.DDM_ENOMEM and not ctx.value
+    assert b"need" in lib.ddm_last_error()
+    rc = lib.ddm_create(C.byref(cfg), 1, arr, C.c_void_p(257), 1 << 40, None, C.byref(ctx))
+    assert rc == ddm.DDM_EINVAL
+
+
+def test_null_context_calls_fail_cleanly(lib):
+    assert lib.ddm_step(None, 1) == ddm.DDM_EINVAL
+    assert lib.ddm_rollout(None, 1) == ddm.DDM_EINVAL
+    assert lib.ddm_backward(None, None, None) == ddm.DDM_EINVAL
+    assert lib.ddm_steps_taken(None) == -1
+    assert lib.ddm_instance_offset(None, 0) == -1
+    lib.ddm_destroy(None)
