@@ -36,10 +36,14 @@
  *   Precision: DDM_F32 or DDM_F64 for all particle and grid arithmetic; the
  *   parameter-gradient accumulators are always FP64.
  *   Particle state layout (ddm_get_state / ddm_set_state): structure of
- *   arrays [2*dim + 2*dim*dim][padded_particles] in the context's precision,
- *   rows x[dim], v[dim], C[dim*dim], F[dim*dim] (matrices row-major);
- *   instance i owns columns [ddm_instance_offset(i), + n_particles), each
- *   instance's range padded to a multiple of 256 columns.
+ *   arrays [2*dim + 2*dim*dim][padded_particles] of 4-byte (DDM_F32) or
+ *   8-byte (DDM_F64) elements, rows x[dim], v[dim], C[dim*dim],
+ *   G[dim*dim] = F - I (the deformation gradient minus the identity, so that
+ *   small strains keep their precision; matrices row-major).  In DDM_F32
+ *   contexts the x rows are unsigned 32-bit fixed point, x = value * 2^-32;
+ *   in DDM_F64 they are doubles.  Instance i owns columns
+ *   [ddm_instance_offset(i), + n_particles), each instance's range padded to
+ *   a multiple of 256 columns.
  */
 #ifndef DDMPM_H
 #define DDMPM_H

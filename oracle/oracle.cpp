@@ -324,13 +324,12 @@ static void constitutive(int d, const double Ft[3][3], double mu, double lam, do
 //                  dG~_ji = sym (g_i-g_j)/(s_i-s_j) - skw (g_i+g_j)/(s_i+s_j),
 //                  dT~_ij = dT~_ji = sym (h_i-h_j)/(s_i-s_j) + skw (h_j-h_i)/(s_i+s_j)
 //                  (sigma's frame is U on both sides).
-// Where |s_i - s_j| is below 1e-8 max(s), the divided difference is replaced by
-// the value of dg_i/ds_i - dg_i/ds_j at the pair's midpoint (s_i = s_j =
-// (s_i + s_j)/2), from a Dual<3> evaluation in s.  For a symmetric g,
-// (g_i - g_j)/(s_i - s_j) is the mean of dg_i/ds_i - dg_i/ds_j along the
-// segment from s to s with s_i and s_j swapped, so the midpoint value is
-// second-order accurate; the derivative at s itself is not, when g varies on
-// a scale as small as |s_i - s_j| (near-isotropic states on the cone).
+// Where |s_i - s_j| is below 1e-8 max(s), the divided difference is computed as
+// the mean of dg_i/ds_i - dg_i/ds_j along the segment from s to s with s_i and
+// s_j swapped (for a symmetric g this mean equals (g_i - g_j)/(s_i - s_j)),
+// by two-point Gauss-Legendre quadrature of Dual<3> derivatives in s.  The
+// derivative at s itself is not accurate when g varies on a scale as small
+// as |s_i - s_j| (near-isotropic states on the cone).
 // This follows from F = U S V^T and never differentiates the SVD iteration.
 // ---------------------------------------------------------------------------
 template <int K>
@@ -362,16 +361,22 @@ static void constitutive(int d, const Dual<K> Ft[3][3], const Dual<K>& mu, const
     for (int k = 0; k < K; ++k) s[i].d[k] = cl[i] ? 0.0 : Fk[k][i][i];
   Dual<K> g[3], h[3];
   return_map(d, s, mu, lam, alpha, kc, g, h, dp_case);
-  // Limit of the divided differences of pair (i, j) at its midpoint.
+  // Divided differences of pair (i, j) by quadrature along the swap segment.
   auto pair_limit = [&](int i, int j, double* ddg, double* ddh) {
-    Dual<3> s3[3], g3[3], h3[3];
-    double sm[3] = {sc[0], sc[1], sc[2]};
-    sm[i] = sm[j] = 0.5 * (sc[i] + sc[j]);
-    for (int q = 0; q < 3; ++q) s3[q] = (q < d && !cl[q]) ? Dual<3>::var(sm[q], q) : Dual<3>(sm[q]);
-    int c3;
-    return_map(d, s3, Dual<3>(mu.v), Dual<3>(lam.v), Dual<3>(alpha.v), Dual<3>(kc.v), g3, h3, &c3);
-    *ddg = g3[i].d[i] - g3[i].d[j];
-    *ddh = h3[i].d[i] - h3[i].d[j];
+    *ddg = 0.0;
+    *ddh = 0.0;
+    const double tq[2] = {0.5 - 0.5 / std::sqrt(3.0), 0.5 + 0.5 / std::sqrt(3.0)};
+    for (int k = 0; k < 2; ++k) {
+      Dual<3> s3[3], g3[3], h3[3];
+      double sm[3] = {sc[0], sc[1], sc[2]};
+      sm[i] = sc[j] + tq[k] * (sc[i] - sc[j]);
+      sm[j] = sc[i] + tq[k] * (sc[j] - sc[i]);
+      for (int q = 0; q < 3; ++q) s3[q] = (q < d && !cl[q]) ? Dual<3>::var(sm[q], q) : Dual<3>(sm[q]);
+      int c3;
+      return_map(d, s3, Dual<3>(mu.v), Dual<3>(lam.v), Dual<3>(alpha.v), Dual<3>(kc.v), g3, h3, &c3);
+      *ddg += 0.5 * (g3[i].d[i] - g3[i].d[j]);
+      *ddh += 0.5 * (h3[i].d[i] - h3[i].d[j]);
+    }
   };
   const double smax = std::max(sc[0], std::max(sc[1], d == 3 ? sc[2] : 0.0));
   for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) { Fn[i][j] = Dual<K>(0.0); tau[i][j] = Dual<K>(0.0); }

@@ -256,22 +256,29 @@ class Simulator:
         _check(lib().ddm_set_state(self.ctx, C.c_void_p(state.data_ptr())))
 
     def instance_state(self, state, i: int):
-        """(x, v, C, F) of instance i as [N, dim], [N, dim], [N, dim, dim], [N, dim, dim]."""
+        """(x, v, C, F) of instance i as float64 [N, dim], [N, dim], [N, dim, dim],
+        [N, dim, dim], decoded from a raw state: in FP32 the position rows hold
+        32-bit fixed point (x = value * 2^-32), and the last rows hold F - I."""
+        t = self.torch
         d, o, n = self.dim, self.offsets[i], self.counts[i]
         s = state[:, o:o + n]
-        x = s[:d].T
-        v = s[d:2 * d].T
-        Cm = s[2 * d:2 * d + d * d].T.reshape(n, d, d)
-        F = s[2 * d + d * d:].T.reshape(n, d, d)
+        if self.dtype == t.float32:
+            xi = s[:d].contiguous().view(t.int32).to(t.int64) & 0xFFFFFFFF
+            x = (xi.double() * 2.0 ** -32).T
+        else:
+            x = s[:d].double().T
+        v = s[d:2 * d].double().T
+        Cm = s[2 * d:2 * d + d * d].double().T.reshape(n, d, d)
+        F = s[2 * d + d * d:].double().T.reshape(n, d, d) + t.eye(d, dtype=t.float64, device=s.device)
         return x, v, Cm, F
 
     def packed_state(self, i: int = 0) -> np.ndarray:
-        """Instance i as a float64 [N, 2d + 2d^2] array (x, v, C, F rows per particle)."""
+        """Instance i as a float64 [N, 2d + 2d^2] array (x, v, C, F per particle)."""
         st = self.get_state()
         x, v, Cm, F = self.instance_state(st, i)
         n = self.counts[i]
         out = self.torch.cat([x, v, Cm.reshape(n, -1), F.reshape(n, -1)], dim=1)
-        return out.double().cpu().numpy()
+        return out.cpu().numpy()
 
     def get_grid(self):
         nodes = self.cfg.n_grid ** self.dim

@@ -26,30 +26,17 @@ template <typename T> __device__ __forceinline__ T dabs(T x) { return x < T(0) ?
 template <typename T> __device__ __forceinline__ T sigma_min() { return T(1e-6); }
 
 // ---------------------------------------------------------------------------
-// SVD  F = U diag(s) V^T  with U, V in SO(D).
-// Eigen-decomposition of the symmetric A = F^T F by cyclic Jacobi rotations
+// Eigen-decomposition of a small symmetric matrix by cyclic Jacobi rotations
 // (stopped when the off-diagonal part is below tol relative to the diagonal),
-// eigenvalues sorted in decreasing order, then a Givens QR of B = F V gives U
-// and the singular values on the diagonal of R; the last one carries the sign
-// of det F.  Robust for rank-deficient F because U comes from the QR.
+// eigenvalues left on the diagonal of a and sorted in decreasing order, each
+// column swap of V paired with a sign flip so that det V stays +1.
 // ---------------------------------------------------------------------------
 template <typename T, int D>
-__device__ __forceinline__ void svd(const T F[3][3], T U[3][3], T s[3], T V[3][3]) {
-  T a[3][3];
-#pragma unroll
-  for (int i = 0; i < D; ++i)
-#pragma unroll
-    for (int j = 0; j < D; ++j) {
-      T acc = T(0);
-#pragma unroll
-      for (int k = 0; k < D; ++k) acc += F[k][i] * F[k][j];
-      a[i][j] = acc;
-    }
+__device__ __forceinline__ void jacobi_sym(T a[3][3], T V[3][3], T ev[3]) {
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j) V[i][j] = T(i == j ? 1 : 0);
-
   for (int sweep = 0; sweep < Lim<T>::sweeps; ++sweep) {
     T off = T(0), dia = T(0);
 #pragma unroll
@@ -86,9 +73,9 @@ __device__ __forceinline__ void svd(const T F[3][3], T U[3][3], T s[3], T V[3][3
       }
     }
   }
-  // Sort eigenvalues in decreasing order; each column swap is paired with a
-  // sign flip so that det V stays +1.
-  T ev[3] = {a[0][0], a[1][1], D == 3 ? a[2][2] : T(0)};
+  ev[0] = a[0][0];
+  ev[1] = a[1][1];
+  ev[2] = D == 3 ? a[2][2] : T(0);
   auto swap_cols = [&](int i, int j) {
     const T t = ev[i]; ev[i] = ev[j]; ev[j] = t;
 #pragma unroll
@@ -99,44 +86,6 @@ __device__ __forceinline__ void svd(const T F[3][3], T U[3][3], T s[3], T V[3][3
     if (ev[0] < ev[2]) swap_cols(0, 2);
     if (ev[1] < ev[2]) swap_cols(1, 2);
   }
-  // B = F V, then Givens rotations zero its sub-diagonal: G B = R, U = G^T.
-  T B[3][3];
-#pragma unroll
-  for (int i = 0; i < D; ++i)
-#pragma unroll
-    for (int j = 0; j < D; ++j) {
-      T acc = T(0);
-#pragma unroll
-      for (int k = 0; k < D; ++k) acc += F[i][k] * V[k][j];
-      B[i][j] = acc;
-    }
-#pragma unroll
-  for (int i = 0; i < 3; ++i)
-#pragma unroll
-    for (int j = 0; j < 3; ++j) U[i][j] = T(i == j ? 1 : 0);
-  auto givens = [&](int i, int j, int col) {   // zero B[j][col] against B[i][col]
-    const T x = B[i][col], y = B[j][col];
-    const T r = dsqrt(x * x + y * y);
-    T c = T(1), sn = T(0);
-    if (r > T(0)) { c = x / r; sn = y / r; }
-#pragma unroll
-    for (int k = 0; k < D; ++k) {
-      const T bi = B[i][k], bj = B[j][k];
-      B[i][k] = c * bi + sn * bj;
-      B[j][k] = -sn * bi + c * bj;
-      const T ui = U[k][i], uj = U[k][j];     // U = G1^T G2^T ... accumulates columns
-      U[k][i] = c * ui + sn * uj;
-      U[k][j] = -sn * ui + c * uj;
-    }
-  };
-  givens(0, 1, 0);
-  if (D == 3) {
-    givens(0, 2, 0);
-    givens(1, 2, 1);
-  }
-  s[0] = B[0][0];
-  s[1] = B[1][1];
-  s[2] = D == 3 ? B[2][2] : T(1);
 }
 
 // ---------------------------------------------------------------------------
@@ -155,10 +104,10 @@ template <typename T> struct DP {
 };
 
 template <typename T, int D>
-__device__ __forceinline__ void dp_forward(const T s[3], T mu, T lam, T alpha, T kc, DP<T>& o) {
+__device__ __forceinline__ void dp_forward(const T eps[3], T mu, T lam, T alpha, T kc, DP<T>& o) {
   o.tr = T(0);
 #pragma unroll
-  for (int i = 0; i < D; ++i) { o.eps[i] = log(s[i]); o.tr += o.eps[i]; }
+  for (int i = 0; i < D; ++i) { o.eps[i] = eps[i]; o.tr += o.eps[i]; }
   T n2 = T(0), dev[3];
 #pragma unroll
   for (int i = 0; i < D; ++i) { dev[i] = o.eps[i] - o.tr / T(D); n2 += dev[i] * dev[i]; }
@@ -258,11 +207,11 @@ __device__ __forceinline__ void dp_backward(const DP<T>& o, const T s[3], T mu, 
 
 // Divided differences of g and h across a pair of singular values, without
 // cancellation: eps'_i - eps'_j = k (eps_i - eps_j) with k = 1 (case 2),
-// 0 (case 1) or -beta/|dev| (case 3), and eps_i - eps_j = log1p((s_i-s_j)/s_j).
+// 0 (case 1) or -beta/|dev| (case 3), and eps_i - eps_j = log1p((s_i-s_j)/s_j);
+// ds = s_i - s_j is passed in, computed from s - 1 without cancellation.
 template <typename T>
-__device__ __forceinline__ void divided(const DP<T>& o, T mu, T si, T sj, T gj, T& ddg, T& ddh, T& y) {
+__device__ __forceinline__ void divided(const DP<T>& o, T mu, T ds, T sj, T gj, T& ddg, T& ddh, T& y) {
   const T k = o.cs == 2 ? T(1) : (o.cs == 1 ? T(0) : -o.beta / o.nrm);
-  const T ds = si - sj;
   const T de = log1p(ds / sj);
   const T dl = ds != T(0) ? de / ds : T(1) / sj;       // (eps_i - eps_j) / (s_i - s_j)
   y = k * de;                                            // eps'_i - eps'_j
@@ -272,29 +221,98 @@ __device__ __forceinline__ void divided(const DP<T>& o, T mu, T si, T sj, T gj, 
 }
 
 // ---------------------------------------------------------------------------
-// Constitutive update of one particle: F' = U diag(g) V^T, tau = U diag(h) U^T.
+// Constitutive update of one particle, on the displacement gradient G = F - I
+// (kept instead of F so that small strains keep their relative precision).
+// F = U diag(s) V^T = R S (polar): V and s^2 - 1 from the eigen-decomposition
+// of F^T F - I = G + G^T + G^T G, eps = ln s = log1p(s^2 - 1)/2,
+// R - I = (G - (S - I)) S^-1, U = R V.  Outputs, without cancellation:
+//   G' = F' - I = (S' - I) + (R - I) + (R - I)(S' - I), S' - I = V diag(expm1(eps')) V^T
+//   tau = U diag(h) U^T.
 // ---------------------------------------------------------------------------
 template <typename T, int D> struct Constit {
-  T U[3][3], V[3][3], s[3];
+  T U[3][3], V[3][3], s[3], sm1[3], eps[3], RmI[3][3];
   bool clamped[3];
   int nclamp;
   DP<T> dp;
 };
 
 template <typename T, int D>
-__device__ __forceinline__ void constit_forward(const T Ft[3][3], T mu, T lam, T alpha, T kc, Constit<T, D>& c) {
-  svd<T, D>(Ft, c.U, c.s, c.V);
-  c.nclamp = 0;
+__device__ __forceinline__ void constit_forward(const T G[3][3], T mu, T lam, T alpha, T kc, Constit<T, D>& c) {
+  T a[3][3];
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      T acc = G[i][j] + G[j][i];
+#pragma unroll
+      for (int k = 0; k < D; ++k) acc += G[k][i] * G[k][j];
+      a[i][j] = acc;
+    }
+  T ev[3];
+  jacobi_sym<T, D>(a, c.V, ev);
+  // det F <= 0 (an inverted particle) has no logarithmic strain: flagged as a clamp.
+  T detF;
+  if (D == 2) {
+    detF = (T(1) + G[0][0]) * (T(1) + G[1][1]) - G[0][1] * G[1][0];
+  } else {
+    const T f00 = T(1) + G[0][0], f11 = T(1) + G[1][1], f22 = T(1) + G[2][2];
+    detF = f00 * (f11 * f22 - G[1][2] * G[2][1]) - G[0][1] * (G[1][0] * f22 - G[1][2] * G[2][0]) +
+           G[0][2] * (G[1][0] * G[2][1] - f11 * G[2][0]);
+  }
+  c.nclamp = detF > T(0) ? 0 : 1;
+  const T smin = sigma_min<T>();
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     c.clamped[i] = false;
-    if (i < D && !(c.s[i] >= sigma_min<T>())) { c.s[i] = sigma_min<T>(); c.clamped[i] = true; ++c.nclamp; }
+    if (i >= D) { c.s[i] = T(1); c.sm1[i] = T(0); c.eps[i] = T(0); continue; }
+    const T l = ev[i];                       // s^2 - 1
+    if (!(T(1) + l > smin * smin)) {
+      c.s[i] = smin; c.sm1[i] = smin - T(1); c.eps[i] = log(smin);
+      c.clamped[i] = true; ++c.nclamp;
+    } else {
+      c.s[i] = dsqrt(T(1) + l);
+      c.sm1[i] = l / (T(1) + c.s[i]);
+      c.eps[i] = T(0.5) * log1p(l);
+    }
   }
-  dp_forward<T, D>(c.s, mu, lam, alpha, kc, c.dp);
+  // R - I = (G - (S - I)) S^-1
+  T GmS[3][3], Sinv[3][3];
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      T smi = T(0), si = T(0);
+#pragma unroll
+      for (int k = 0; k < D; ++k) { smi += c.V[i][k] * c.sm1[k] * c.V[j][k]; si += c.V[i][k] * c.V[j][k] / c.s[k]; }
+      GmS[i][j] = G[i][j] - smi;
+      Sinv[i][j] = si;
+    }
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      T acc = T(0);
+#pragma unroll
+      for (int k = 0; k < D; ++k) acc += GmS[i][k] * Sinv[k][j];
+      c.RmI[i][j] = acc;
+    }
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      T acc = c.V[i][j];
+#pragma unroll
+      for (int k = 0; k < D; ++k) acc += c.RmI[i][k] * c.V[k][j];
+      c.U[i][j] = acc;
+    }
+  dp_forward<T, D>(c.eps, mu, lam, alpha, kc, c.dp);
 }
 
 template <typename T, int D>
-__device__ __forceinline__ void constit_outputs(const Constit<T, D>& c, T Fn[3][3], T tau[3][3]) {
+__device__ __forceinline__ void constit_outputs(const Constit<T, D>& c, T Gn[3][3], T tau[3][3]) {
+  T em[3], SpmI[3][3];
+#pragma unroll
+  for (int k = 0; k < D; ++k) em[k] = expm1(c.dp.ep[k]);
 #pragma unroll
   for (int i = 0; i < D; ++i)
 #pragma unroll
@@ -302,15 +320,25 @@ __device__ __forceinline__ void constit_outputs(const Constit<T, D>& c, T Fn[3][
       T a = T(0), b = T(0);
 #pragma unroll
       for (int k = 0; k < D; ++k) {
-        a += c.U[i][k] * c.dp.g[k] * c.V[j][k];
+        a += c.V[i][k] * em[k] * c.V[j][k];
         b += c.U[i][k] * c.dp.h[k] * c.U[j][k];
       }
-      Fn[i][j] = a;
+      SpmI[i][j] = a;
       tau[i][j] = b;
+    }
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      T acc = SpmI[i][j] + c.RmI[i][j];
+#pragma unroll
+      for (int k = 0; k < D; ++k) acc += c.RmI[i][k] * SpmI[k][j];
+      Gn[i][j] = acc;
     }
 }
 
-// Adjoint of (F_tmp -> F', tau) for adjoints Fnb (of F') and taub (of tau).
+// Adjoint of (F_tmp -> F', tau) for adjoints Fnb (of F', equally of G') and
+// taub (of tau); the result is the adjoint of F_tmp (equally of G_tmp).
 // In the SVD frame, with sym/skw the symmetric/skew parts of dF~ = U^T dF V,
 // dG~_ij = ddg sym + cg skw, dG~_ji = ddg sym - cg skw, dT~_ij = dT~_ji =
 // ddh sym + ch skw; the diagonal goes through s and the return map.
@@ -346,7 +374,7 @@ __device__ __forceinline__ void constit_backward(const Constit<T, D>& c, T mu, T
 #pragma unroll
     for (int j = i + 1; j < D; ++j) {
       T ddg, ddh, y;
-      divided<T>(c.dp, mu, c.s[i], c.s[j], c.dp.g[j], ddg, ddh, y);
+      divided<T>(c.dp, mu, c.sm1[i] - c.sm1[j], c.s[j], c.dp.g[j], ddg, ddh, y);
       const T sum = c.s[i] + c.s[j];
       const T cg = (c.dp.g[i] + c.dp.g[j]) / sum;
       const T ch = -T(2) * mu * y / sum;

@@ -3,7 +3,9 @@
 // (Eq. po/pa), for gfx950 wave64.
 //
 // Layout: particle state in structure-of-arrays, component-major with stride
-// ntot: x[D], v[D], C[D*D], F[D*D] (row-major matrices).  Instances occupy
+// ntot: x[D], v[D], C[D*D], G[D*D] with G = F - I (row-major matrices).  In
+// FP32 the positions are unsigned 32-bit fixed point (x = value * 2^-32), in
+// FP64 doubles.  Instances occupy
 // consecutive ranges padded to kBlock slots, so every 256-thread block belongs
 // to one instance (blk_inst).  Grid: per instance n^D nodes, x-major, each
 // node a 4-vector (mv0, mv1, mv2, m) before the grid update and (v0, v1, v2, m)
@@ -15,13 +17,71 @@
 
 namespace ddm {
 
+// Position storage: 32-bit fixed point in FP32 (resolution 2^-32 of the unit
+// domain, 60x finer than float near x = 0.5, and cell indices come out of
+// integer arithmetic), plain double in FP64.
+template <typename T> struct Pos;
+template <> struct Pos<float> {
+  using X = uint32_t;
+  static __device__ __forceinline__ bool cell(X xr, const KCfg& c, int& base, float& f) {
+    const uint64_t q = (uint64_t)xr << c.nlog2;          // x n in units of 2^-32
+    if (q < 0x80000000ull) return false;
+    const uint64_t s = q - 0x80000000ull;                // x n - 1/2
+    const uint64_t b = s >> 32;
+    if (b > (uint64_t)(c.n - 3)) return false;
+    base = (int)b;
+    f = 0.5f + (float)(uint32_t)(s & 0xFFFFFFFFull) * 2.3283064365386963e-10f;
+    return true;
+  }
+  static __device__ __forceinline__ double real(X xr) { return (double)xr * 2.3283064365386963e-10; }
+  static __device__ __forceinline__ X advance(X xr, float d, bool& ok) {
+    const float q = rintf(d * 4294967296.0f);
+    ok = fabsf(q) < 1073741824.0f;
+    return ok ? xr + (uint32_t)(int32_t)q : xr;
+  }
+  static __device__ __forceinline__ X from_real(double x) {
+    const double q = rint(x * 4294967296.0);
+    return q <= 0.0 ? 0u : (q >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)q);
+  }
+  static __device__ __forceinline__ unsigned long long key(X xr) { return (unsigned long long)xr; }
+  static __device__ __forceinline__ double unkey(unsigned long long k) { return (double)k * 2.3283064365386963e-10; }
+};
+template <> struct Pos<double> {
+  using X = double;
+  static __device__ __forceinline__ bool cell(X xr, const KCfg& c, int& base, double& f) {
+    const double xs = xr * c.inv_dx;
+    const double bf = floor(xs - 0.5);
+    if (!(bf >= 0.0 && bf <= (double)(c.n - 3))) return false;
+    base = (int)bf;
+    f = xs - bf;
+    return true;
+  }
+  static __device__ __forceinline__ double real(X xr) { return xr; }
+  static __device__ __forceinline__ X advance(X xr, double d, bool& ok) { ok = true; return xr + d; }
+  static __device__ __forceinline__ X from_real(double x) { return x; }
+  static __device__ __forceinline__ unsigned long long key(X xr) { return (unsigned long long)__double_as_longlong(xr); }
+  static __device__ __forceinline__ double unkey(unsigned long long k) { return __longlong_as_double((long long)k); }
+};
+
 template <typename T, int D> struct P {
+  T* s;
+  int64_t ntot;
+  using X = typename Pos<T>::X;
+  __device__ __forceinline__ X& xr(int a, int64_t p) const { return reinterpret_cast<X*>(s)[(int64_t)a * ntot + p]; }
+  __device__ __forceinline__ T& v(int a, int64_t p) const { return s[(int64_t)(D + a) * ntot + p]; }
+  __device__ __forceinline__ T& C(int a, int b, int64_t p) const { return s[(int64_t)(2 * D + a * D + b) * ntot + p]; }
+  __device__ __forceinline__ T& G(int a, int b, int64_t p) const {
+    return s[(int64_t)(2 * D + D * D + a * D + b) * ntot + p];
+  }
+};
+// Adjoint states hold plain T in every row.
+template <typename T, int D> struct A {
   T* s;
   int64_t ntot;
   __device__ __forceinline__ T& x(int a, int64_t p) const { return s[(int64_t)a * ntot + p]; }
   __device__ __forceinline__ T& v(int a, int64_t p) const { return s[(int64_t)(D + a) * ntot + p]; }
   __device__ __forceinline__ T& C(int a, int b, int64_t p) const { return s[(int64_t)(2 * D + a * D + b) * ntot + p]; }
-  __device__ __forceinline__ T& F(int a, int b, int64_t p) const {
+  __device__ __forceinline__ T& G(int a, int b, int64_t p) const {
     return s[(int64_t)(2 * D + D * D + a * D + b) * ntot + p];
   }
 };
@@ -29,6 +89,10 @@ template <typename T, int D> struct P {
 template <typename T, int D>
 __device__ __forceinline__ P<T, D> pv(const void* s, int64_t ntot) {
   return P<T, D>{const_cast<T*>(static_cast<const T*>(s)), ntot};
+}
+template <typename T, int D>
+__device__ __forceinline__ A<T, D> av(const void* s, int64_t ntot) {
+  return A<T, D>{const_cast<T*>(static_cast<const T*>(s)), ntot};
 }
 
 __device__ __forceinline__ void flag_error(DevErr* e, unsigned int bit, int inst) {
@@ -46,14 +110,9 @@ template <typename T, int D> struct Stencil {
 
 template <typename T, int D>
 __device__ __forceinline__ bool make_stencil(const P<T, D>& st, int64_t p, const KCfg& c, Stencil<T, D>& S) {
-  const T inv_dx = T(c.inv_dx);
 #pragma unroll
   for (int a = 0; a < D; ++a) {
-    const T xs = st.x(a, p) * inv_dx;
-    const T bf = floor(xs - T(0.5));
-    if (!(bf >= T(0) && bf <= T(c.n - 3))) return false;
-    S.base[a] = (int)bf;
-    S.f[a] = xs - bf;
+    if (!Pos<T>::cell(st.xr(a, p), c, S.base[a], S.f[a])) return false;
     bspline(S.f[a], S.w[a], S.dw[a]);
   }
   return true;
@@ -126,10 +185,10 @@ __global__ void k_init_state(KCfg c, Bufs b, const T* __restrict__ x0, void* sta
   const bool live = local < I.n;
 #pragma unroll
   for (int a = 0; a < D; ++a) {
-    st.x(a, p) = live ? x0[(src + local) * D + a] : T(0.5);
+    st.xr(a, p) = Pos<T>::from_real(live ? (double)x0[(src + local) * D + a] : 0.5);
     st.v(a, p) = T(0);
 #pragma unroll
-    for (int bb = 0; bb < D; ++bb) { st.C(a, bb, p) = T(0); st.F(a, bb, p) = T(a == bb ? 1 : 0); }
+    for (int bb = 0; bb < D; ++bb) { st.C(a, bb, p) = T(0); st.G(a, bb, p) = T(0); }
   }
   pid[p] = live ? (uint32_t)local : 0xFFFFFFFFu;
 }
@@ -146,7 +205,8 @@ void launch_init_state(int prec, const KCfg& c, const Bufs& b, int nblk, const v
 }
 
 // ---------------------------------------------------------------------------
-// P2G (Algorithm 1 lines 1-6): F_tmp = (I + dt C) F, SVD, return map, stress,
+// P2G (Algorithm 1 lines 1-6): F_tmp = (I + dt C) F, i.e. G_tmp = G + dt C (I + G),
+// SVD, return map, stress,
 // then the quadratic B-spline scatter of mass and MLS-MPM momentum
 // mv_i += w (m v + A (x_i - x_p)), A = -dt V_p (4/dx^2) tau + m C.
 // ---------------------------------------------------------------------------
@@ -158,19 +218,19 @@ __global__ void __launch_bounds__(kBlock) k_p2g(KCfg c, Bufs b, const void* st_i
   if (p - I.off >= I.n) return;
   const P<T, D> si = pv<T, D>(st_in, c.ntot), so = pv<T, D>(st_out, c.ntot);
   const T dt = T(I.dt), mp = T(I.mp);
-  T Cm[3][3], Ft[3][3];
+  T Cm[3][3], Gm[3][3], Ft[3][3];
 #pragma unroll
   for (int a = 0; a < D; ++a)
 #pragma unroll
-    for (int bb = 0; bb < D; ++bb) Cm[a][bb] = si.C(a, bb, p);
+    for (int bb = 0; bb < D; ++bb) { Cm[a][bb] = si.C(a, bb, p); Gm[a][bb] = si.G(a, bb, p); }
 #pragma unroll
   for (int a = 0; a < D; ++a)
 #pragma unroll
     for (int bb = 0; bb < D; ++bb) {
-      T acc = T(0);
+      T acc = Cm[a][bb];
 #pragma unroll
-      for (int k = 0; k < D; ++k) acc += (T(a == k ? 1 : 0) + dt * Cm[a][k]) * si.F(k, bb, p);
-      Ft[a][bb] = acc;
+      for (int k = 0; k < D; ++k) acc += Cm[a][k] * Gm[k][bb];
+      Ft[a][bb] = Gm[a][bb] + dt * acc;
     }
   Constit<T, D> cs;
   constit_forward<T, D>(Ft, T(I.mu), T(I.lam), T(I.alpha), T(I.kc), cs);
@@ -180,7 +240,7 @@ __global__ void __launch_bounds__(kBlock) k_p2g(KCfg c, Bufs b, const void* st_i
 #pragma unroll
   for (int a = 0; a < D; ++a)
 #pragma unroll
-    for (int bb = 0; bb < D; ++bb) so.F(a, bb, p) = Fn[a][bb];
+    for (int bb = 0; bb < D; ++bb) so.G(a, bb, p) = Fn[a][bb];
   const T k_str = -dt * T(I.Vp) * T(4.0 * c.inv_dx * c.inv_dx);
   T A[3][3];
 #pragma unroll
@@ -319,7 +379,7 @@ __global__ void __launch_bounds__(kBlock) k_g2p(KCfg c, Bufs b, const void* st_i
   if (p - I.off >= I.n) {
     // padding slots keep a harmless position so they never trip a check
 #pragma unroll
-    for (int a = 0; a < D; ++a) so.x(a, p) = T(0.5);
+    for (int a = 0; a < D; ++a) so.xr(a, p) = Pos<T>::from_real(0.5);
     return;
   }
   Stencil<T, D> S;
@@ -348,16 +408,18 @@ __global__ void __launch_bounds__(kBlock) k_g2p(KCfg c, Bufs b, const void* st_i
       }
   const T dt = T(b.inst[inst].dt);
   T chk = T(0);
+  bool ok = true;
 #pragma unroll
   for (int a = 0; a < D; ++a) {
-    const T xn = si.x(a, p) + dt * vn[a];
-    so.x(a, p) = xn;
+    bool oka;
+    so.xr(a, p) = Pos<T>::advance(si.xr(a, p), dt * vn[a], oka);
+    ok &= oka;
     so.v(a, p) = vn[a];
-    chk += xn + vn[a];
+    chk += vn[a];
 #pragma unroll
-    for (int bb = 0; bb < D; ++bb) so.C(a, bb, p) = Cn[a][bb];
+    for (int bb = 0; bb < D; ++bb) { so.C(a, bb, p) = Cn[a][bb]; chk += Cn[a][bb]; }
   }
-  if (!isfinite(chk)) flag_error(b.err, 1u, inst);
+  if (!isfinite(chk) || !ok) flag_error(b.err, 1u, inst);
 }
 
 void launch_g2p(int prec, const KCfg& c, const Bufs& b, int nblk, const void* st_in, void* st_out,
@@ -394,27 +456,24 @@ void launch_grid_export(int prec, const KCfg& c, const void* pre, const void* po
 // particle id.  Squared distance to the target, plus the scoop-mass term on a
 // P2G of particle masses at the final positions inside the scoop slab.
 // ---------------------------------------------------------------------------
-template <typename T> __device__ __forceinline__ unsigned long long obits(T y);
-template <> __device__ __forceinline__ unsigned long long obits<float>(float y) { return (unsigned long long)__float_as_uint(y); }
-template <> __device__ __forceinline__ unsigned long long obits<double>(double y) { return (unsigned long long)__double_as_longlong(y); }
-
-template <typename T, int D>
-__device__ __forceinline__ int hm_pixels(const KCfg& c, T x, T z, int pix[5]) {
-  const T pw = T(c.hm_pix), r = T(c.hm_off);
-  const T ox[5] = {T(0), r, -r, T(0), T(0)}, oz[5] = {T(0), T(0), T(0), r, -r};
+// Pixel arithmetic in double on the exact stored position.
+template <int D>
+__device__ __forceinline__ int hm_pixels(const KCfg& c, double x, double z, int pix[5]) {
+  const double pw = c.hm_pix, r = c.hm_off;
+  const double ox[5] = {0.0, r, -r, 0.0, 0.0}, oz[5] = {0.0, 0.0, 0.0, r, -r};
   const int npts = D == 3 ? 5 : 3;
   int cnt = 0;
   for (int k = 0; k < npts; ++k) {
-    const T px = x + ox[k];
-    const T fx = floor((px - T(c.hm_ox)) / pw);
+    const double px = x + ox[k];
+    const double fx = floor((px - c.hm_ox) / pw);
     int iz = 0;
     if (D == 3) {
-      const T pz = z + oz[k];
-      const T fz = floor((pz - T(c.hm_oz)) / pw);
-      if (!(fz >= T(0) && fz < T(c.hm_res))) { pix[k] = -1; continue; }
+      const double pz = z + oz[k];
+      const double fz = floor((pz - c.hm_oz) / pw);
+      if (!(fz >= 0.0 && fz < (double)c.hm_res)) { pix[k] = -1; continue; }
       iz = (int)fz;
     }
-    if (!(fx >= T(0) && fx < T(c.hm_res))) { pix[k] = -1; continue; }
+    if (!(fx >= 0.0 && fx < (double)c.hm_res)) { pix[k] = -1; continue; }
     pix[k] = D == 3 ? (int)fx * c.hm_res + iz : (int)fx;
     ++cnt;
   }
@@ -429,12 +488,12 @@ __global__ void __launch_bounds__(kBlock) k_hm_max(KCfg c, Bufs b, const void* s
   const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (p - I.off >= I.n) return;
   const P<T, D> st = pv<T, D>(state, c.ntot);
-  const T y = st.x(1, p);
-  if (!(y > T(0))) return;
+  const double y = Pos<T>::real(st.xr(1, p));
+  if (!(y > 0.0)) return;
   int pix[5];
-  hm_pixels<T, D>(c, st.x(0, p), D == 3 ? st.x(2, p) : T(0), pix);
+  hm_pixels<D>(c, Pos<T>::real(st.xr(0, p)), D == 3 ? Pos<T>::real(st.xr(2, p)) : 0.0, pix);
   const int npix = D == 3 ? c.hm_res * c.hm_res : c.hm_res;
-  const unsigned long long yb = obits<T>(y);
+  const unsigned long long yb = Pos<T>::key(st.xr(1, p));
   for (int k = 0; k < 5; ++k)
     if (pix[k] >= 0) atomicMax(&hm[(int64_t)inst * npix + pix[k]], yb);
 }
@@ -447,12 +506,12 @@ __global__ void __launch_bounds__(kBlock) k_hm_owner(KCfg c, Bufs b, const void*
   const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (p - I.off >= I.n) return;
   const P<T, D> st = pv<T, D>(state, c.ntot);
-  const T y = st.x(1, p);
-  if (!(y > T(0))) return;
+  const double y = Pos<T>::real(st.xr(1, p));
+  if (!(y > 0.0)) return;
   int pix[5];
-  hm_pixels<T, D>(c, st.x(0, p), D == 3 ? st.x(2, p) : T(0), pix);
+  hm_pixels<D>(c, Pos<T>::real(st.xr(0, p)), D == 3 ? Pos<T>::real(st.xr(2, p)) : 0.0, pix);
   const int npix = D == 3 ? c.hm_res * c.hm_res : c.hm_res;
-  const unsigned long long yb = obits<T>(y);
+  const unsigned long long yb = Pos<T>::key(st.xr(1, p));
   for (int k = 0; k < 5; ++k)
     if (pix[k] >= 0 && hm[(int64_t)inst * npix + pix[k]] == yb) atomicMin(&owner[(int64_t)inst * npix + pix[k]], pid[p]);
 }
@@ -529,9 +588,7 @@ __global__ void k_loss_final(KCfg c, const unsigned long long* hm, const unsigne
   const double inv_dx = c.inv_dx;
   for (int i = threadIdx.x; i < npix; i += blockDim.x) {
     const int64_t k = (int64_t)inst * npix + i;
-    double h;
-    if (sizeof(T) == 4) h = (double)__uint_as_float((unsigned int)hm[k]);
-    else h = __longlong_as_double((long long)hm[k]);
+    const double h = Pos<T>::unkey(hm[k]);
     L.hm_val[k] = h;
     const double e = (h - L.target[k]) * inv_dx;
     acc += e * e;
@@ -585,14 +642,15 @@ __global__ void __launch_bounds__(kBlock) k_loss_seed(KCfg c, Bufs b, const void
   const int inst = b.blk_inst[blockIdx.x];
   const InstDev& I = b.inst[inst];
   const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const P<T, D> st = pv<T, D>(state, c.ntot), ad = pv<T, D>(adj, c.ntot);
+  const P<T, D> st = pv<T, D>(state, c.ntot);
+  const A<T, D> ad = av<T, D>(adj, c.ntot);
   double racc[1] = {0.0};
   T xb[3] = {T(0), T(0), T(0)};
   if (p - I.off < I.n) {
-    const T y = st.x(1, p);
-    if (y > T(0)) {
+    const double y = Pos<T>::real(st.xr(1, p));
+    if (y > 0.0) {
       int pix[5];
-      hm_pixels<T, D>(c, st.x(0, p), D == 3 ? st.x(2, p) : T(0), pix);
+      hm_pixels<D>(c, Pos<T>::real(st.xr(0, p)), D == 3 ? Pos<T>::real(st.xr(2, p)) : 0.0, pix);
       const int npix = D == 3 ? c.hm_res * c.hm_res : c.hm_res;
       double yb = 0.0;
       for (int k = 0; k < 5; ++k) {
@@ -619,7 +677,7 @@ __global__ void __launch_bounds__(kBlock) k_loss_seed(KCfg c, Bufs b, const void
   for (int a = 0; a < D; ++a) {
     ad.x(a, p) = xb[a];
     ad.v(a, p) = T(0);
-    for (int bb = 0; bb < D; ++bb) { ad.C(a, bb, p) = T(0); ad.F(a, bb, p) = T(0); }
+    for (int bb = 0; bb < D; ++bb) { ad.C(a, bb, p) = T(0); ad.G(a, bb, p) = T(0); }
   }
   block_accumulate<1>(racc, pacc + (int64_t)inst * 8 + 4);
 }
@@ -647,7 +705,8 @@ __global__ void __launch_bounds__(kBlock) k_g2p_adj(KCfg c, Bufs b, const void* 
   const InstDev& I = b.inst[inst];
   const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (p - I.off >= I.n) return;
-  const P<T, D> st = pv<T, D>(stv, c.ntot), an = pv<T, D>(adj_next, c.ntot), ac = pv<T, D>(adj_cur, c.ntot);
+  const P<T, D> st = pv<T, D>(stv, c.ntot);
+  const A<T, D> an = av<T, D>(adj_next, c.ntot), ac = av<T, D>(adj_cur, c.ntot);
   Stencil<T, D> S;
   if (!make_stencil<T, D>(st, p, c, S)) return;
   const T dt = T(I.dt), dx = T(c.dx), inv_dx = T(c.inv_dx), Dk = T(4.0 * c.inv_dx * c.inv_dx);
@@ -814,26 +873,27 @@ __global__ void __launch_bounds__(kBlock) k_p2g_adj(KCfg c, Bufs b, const void* 
   const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   double acc[5] = {0, 0, 0, 0, 0};
   if (p - I.off < I.n) {
-    const P<T, D> st = pv<T, D>(stv, c.ntot), an = pv<T, D>(adj_next, c.ntot), ac = pv<T, D>(adj_cur, c.ntot);
+    const P<T, D> st = pv<T, D>(stv, c.ntot);
+    const A<T, D> an = av<T, D>(adj_next, c.ntot), ac = av<T, D>(adj_cur, c.ntot);
     Stencil<T, D> S;
     if (make_stencil<T, D>(st, p, c, S)) {
       const T dt = T(I.dt), mp = T(I.mp), dx = T(c.dx), inv_dx = T(c.inv_dx);
       const T mu = T(I.mu), lam = T(I.lam), al = T(I.alpha), kc = T(I.kc);
-      T Cm[3][3], Fm[3][3], Ft[3][3], vel[3];
+      T Cm[3][3], Gm[3][3], Ft[3][3], vel[3];
 #pragma unroll
       for (int a = 0; a < D; ++a) {
         vel[a] = st.v(a, p);
 #pragma unroll
-        for (int bb = 0; bb < D; ++bb) { Cm[a][bb] = st.C(a, bb, p); Fm[a][bb] = st.F(a, bb, p); }
+        for (int bb = 0; bb < D; ++bb) { Cm[a][bb] = st.C(a, bb, p); Gm[a][bb] = st.G(a, bb, p); }
       }
 #pragma unroll
       for (int a = 0; a < D; ++a)
 #pragma unroll
         for (int bb = 0; bb < D; ++bb) {
-          T s = T(0);
+          T s = Cm[a][bb];
 #pragma unroll
-          for (int k = 0; k < D; ++k) s += (T(a == k ? 1 : 0) + dt * Cm[a][k]) * Fm[k][bb];
-          Ft[a][bb] = s;
+          for (int k = 0; k < D; ++k) s += Cm[a][k] * Gm[k][bb];
+          Ft[a][bb] = Gm[a][bb] + dt * s;
         }
       Constit<T, D> cs;
       constit_forward<T, D>(Ft, mu, lam, al, kc, cs);
@@ -910,21 +970,21 @@ __global__ void __launch_bounds__(kBlock) k_p2g_adj(KCfg c, Bufs b, const void* 
 #pragma unroll
       for (int a = 0; a < D; ++a)
 #pragma unroll
-        for (int bb = 0; bb < D; ++bb) Fnb[a][bb] = an.F(a, bb, p);
+        for (int bb = 0; bb < D; ++bb) Fnb[a][bb] = an.G(a, bb, p);
       T Ftb[3][3], mub = T(0), lamb = T(0), alb = T(0), kcb = T(0);
       constit_backward<T, D>(cs, mu, lam, al, kc, Fnb, taub, Ftb, mub, lamb, alb, kcb);
-      // F_tmp = (I + dt C) F
+      // F_tmp = (I + dt C) F with F = I + G
 #pragma unroll
       for (int a = 0; a < D; ++a)
 #pragma unroll
         for (int bb = 0; bb < D; ++bb) {
-          T fb = T(0), cb = T(0);
+          T fb = Ftb[a][bb], cb = Ftb[a][bb];
 #pragma unroll
           for (int k = 0; k < D; ++k) {
-            fb += (T(k == a ? 1 : 0) + dt * Cm[k][a]) * Ftb[k][bb];
-            cb += Ftb[a][k] * Fm[bb][k];
+            fb += dt * Cm[k][a] * Ftb[k][bb];
+            cb += Ftb[a][k] * Gm[bb][k];
           }
-          ac.F(a, bb, p) = fb;
+          ac.G(a, bb, p) = fb;
           ac.C(a, bb, p) = Cb[a][bb] + dt * cb;
         }
 #pragma unroll

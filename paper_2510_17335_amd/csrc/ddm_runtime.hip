@@ -375,6 +375,8 @@ ddm_status ddm_create(const ddm_config* cfg, int32_t n_inst, const ddm_instance*
   x->prec = cfg->precision == DDM_F64 ? 1 : 0;
   ddm::KCfg& k = x->kc;
   k.dim = cfg->dim; k.n = cfg->n_grid; k.bound = cfg->bound; k.shovel = cfg->shovel;
+  k.nlog2 = 0;
+  while ((1 << k.nlog2) < cfg->n_grid) ++k.nlog2;
   k.hm_res = cfg->hm_res; k.region_sign = cfg->region_sign >= 0 ? 1 : -1; k.n_inst = n_inst;
   k.max_steps = cfg->max_steps;
   k.nodes = 1;
