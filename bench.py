@@ -1,0 +1,225 @@
+"""Benchmark: differentiable MLS-MPM sand digging, forward + backward, on one GPU.
+
+One step = one full pass of the hot path over the batch: init state, a
+500-sub-step recorded rollout (P2G with the SVD / Drucker-Prager update, grid
+update with shovel contact, G2P, periodic binning, checkpoints), the loss,
+and the reverse pass (segment recompute + adjoint of every sub-step).
+
+Workload (default): batched system identification, 64 instances on 64^3
+grids with particle counts uniform in [20k, 200k] (seeded), log-uniform E in
+[1e4, 1e6] Pa, nu in [0.2, 0.4], friction angle in [20, 45] deg, 500 sub-steps
+fwd+bwd, FP32, checkpoints every 50 sub-steps, binning every 8.
+
+Prints one JSON line (rank 0).  `value` is the batched fwd+bwd particle-steps/s;
+the plain per-instance loop on the same GPU and the FP32-vs-FP64 gradient
+gate are reported beside it.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import workloads as W  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "particle-steps/s fwd+bwd, batched vs plain, at grad rel-err <=1e-3 vs FP64"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="sysid64", choices=["sysid64", "dig3d_bwd"])
+    ap.add_argument("--sub-steps", type=int, default=None, help="override rollout length (testing only)")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-gate", action="store_true")
+    ap.add_argument("--sort-every", type=int, default=8)
+    return ap.parse_args()
+
+
+def build_batch(args):
+    if args.workload == "sysid64":
+        ws = W.sysid_batch(64, steps=500)
+        name = "sysid64: 64 instances, 64^3, N_i~U[20k,200k], 500 sub-steps fwd+bwd, K=50, FP32"
+    else:
+        ws = [W.dig_3d_backward()]
+        name = "dig3d_bwd: 64^3, 219488 particles, 1000 sub-steps fwd+bwd, K=50, FP32"
+    if args.sub_steps:
+        for w in ws:
+            w.steps = args.sub_steps
+    return ws, name
+
+
+class Pass:
+    """One context over a list of instances and the inputs of a full pass."""
+
+    def __init__(self, ddm, ws, sort_every, precision=None):
+        self.ws = ws
+        self.steps = ws[0].steps
+        K = ws[0].checkpoint_every or 50
+        cfgs = [ddm.from_workload(w, max_steps=self.steps, checkpoint_every=K, precision=precision,
+                                  sort_every=sort_every) for w in ws]
+        self.sim = ddm.Simulator(cfgs[0][0], [c[1] for c in cfgs])
+        self.x0 = np.concatenate([W.bed_positions(w) for w in ws])
+        self.tg = np.stack([W.target_heightmap(w) for w in ws])
+        self.sim.init_state(self.x0)           # uploads x0 once
+        self.x0_dev = self.sim._x0
+        self.tg_dev = None
+
+    def run(self):
+        sim = self.sim
+        sim.init_state(self.x0_dev)
+        sim.rollout(self.steps)
+        loss = sim.loss(self.tg if self.tg_dev is None else self.tg_dev)
+        self.tg_dev = sim._target
+        return loss, sim.backward()
+
+    @property
+    def particle_steps(self):
+        return sum(w.n_particles for w in self.ws) * self.steps
+
+
+def algorithmic_bytes_p2g(ws, b=4, d=3):
+    """P2G moves per particle the state it reads (x, v, C, G: (2d + 2d^2) b) and
+    the G' it writes (d^2 b); per occupied grid node the (d + 1) b it adds.
+    Occupied nodes ~ particles / ppc (the bed's cells) plus the halo."""
+    n = sum(w.n_particles for w in ws)
+    per_particle = (2 * d + 2 * d * d) * b + d * d * b
+    nodes = sum(w.n_particles / w.ppc * 1.3 for w in ws)
+    return n * per_particle + nodes * (d + 1) * b
+
+
+def cpu_baseline(ws):
+    """The FP64 oracle (single thread) with 7 forward-mode tangents on the
+    smallest instance of the batch, 20 sub-steps: fwd+bwd-equivalent rate."""
+    import oracle
+    oracle.build(force=False)
+    w = min(ws, key=lambda q: q.n_particles)
+    steps = 20
+    s0 = oracle.initial_state(W.bed_positions(w))
+    t0 = time.perf_counter()
+    oracle.rollout(oracle.config(w), w.params7, s0, steps, target=W.target_heightmap(w), grad=True)
+    dt = time.perf_counter() - t0
+    return {"value": w.n_particles * steps / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"smallest instance ({w.n_particles} particles), {steps} sub-steps, FP64 with 7 "
+                      f"forward-mode tangents, {dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2510_17335_amd as ddm
+    assert torch.cuda.is_available(), "needs a GPU"
+    dev = torch.device("cuda:0")
+    ws, wname = build_batch(args)
+    print(f"# workload {wname}: {len(ws)} instances, {sum(w.n_particles for w in ws)} particles", flush=True)
+
+    bp = Pass(ddm, ws, args.sort_every)
+    for i in range(args.warmup):
+        bp.run()
+        torch.cuda.synchronize()
+        print(f"# warmup {i + 1}/{args.warmup} done", flush=True)
+    bp.sim.check()
+    bp.sim.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        loss, grad = bp.run()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    timing = bp.sim.read_timing()
+    bp.sim.set_timing(False)
+    err = bp.sim.check()
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = bp.particle_steps * args.steps / elapsed
+    print(f"# batched: {ms_per_step:.1f} ms/step, {value:.3e} particle-steps/s, device flags {err.flags}",
+          flush=True)
+    grads32 = grad.cpu().numpy()
+
+    # dominant kernel and its roofline (bytes moved per launch / measured launch time)
+    dom = max(timing, key=lambda k: timing[k][0])
+    p2g_ms, p2g_n = timing["p2g"]
+    per_launch_bytes = algorithmic_bytes_p2g(ws)
+    achieved = per_launch_bytes / (p2g_ms / p2g_n * 1e-3) / 1e9 if p2g_n else None
+    breakdown = {k: {"ms": round(v[0], 3), "launches": v[1]} for k, v in timing.items() if v[1]}
+
+    plain_value = None
+    if not args.no_plain:
+        del bp
+        torch.cuda.empty_cache()
+        t_plain = 0.0
+        for w in ws:
+            pp = Pass(ddm, [w], args.sort_every)
+            pp.run()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            pp.run()
+            torch.cuda.synchronize()
+            t_plain += time.perf_counter() - t1
+            del pp
+        plain_value = sum(w.n_particles for w in ws) * ws[0].steps / t_plain
+        print(f"# plain loop: {t_plain * 1e3:.1f} ms/pass, {plain_value:.3e} particle-steps/s", flush=True)
+        torch.cuda.empty_cache()
+
+    gate = None
+    if not args.no_gate:
+        # FP32 (batched) gradients of the two smallest instances against the FP64 path
+        idx = sorted(range(len(ws)), key=lambda i: ws[i].n_particles)[:2]
+        rels = []
+        for i in idx:
+            p64 = Pass(ddm, [ws[i]], args.sort_every, precision="f64")
+            _, g64 = p64.run()
+            g64 = g64[0].cpu().numpy()
+            scale = np.abs(g64).max()
+            rel = np.abs(grads32[i] - g64) / np.maximum(np.abs(g64), 1e-6 * scale)
+            rels.append(float(rel[np.abs(g64) > 1e-6 * scale].max()))
+            del p64
+        gate = {"instances": idx, "max_rel_err": max(rels), "pass": max(rels) <= 1e-3}
+        print(f"# gradient gate (FP32 vs FP64): {gate}", flush=True)
+
+    cpu = None if args.no_cpu else cpu_baseline(ws)
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded beds and targets, no dataset)",
+        "config": {"workload": wname, "instances": len(ws), "particles": sum(w.n_particles for w in ws),
+                   "sub_steps": ws[0].steps, "checkpoint_every": ws[0].checkpoint_every,
+                   "sort_every": args.sort_every},
+        "plain_value": plain_value,
+        "batched_over_plain": (value / plain_value) if plain_value else None,
+        "grad_gate": gate,
+        "kernel_ms": breakdown,
+        "roofline": {"bound": "hbm", "kernel": "p2g", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
+                     "dominant_group": dom},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -96,6 +96,10 @@ typedef struct ddm_config {
   double w_hm;              /* weight of the height-map term */
   int32_t checkpoint_every; /* K: snapshot interval of ddm_rollout (>= 1) */
   int32_t max_steps;        /* longest rollout the workspace is sized for */
+  int32_t sort_every;       /* R: particles are re-binned (sorted by cell) every R sub-steps, and
+                               always after ddm_init_state / ddm_set_state and at every
+                               checkpoint of a recorded rollout; 0 = only then */
+  int32_t pad0;
 } ddm_config;
 
 /* One simulation instance: material, skill and time step. */
@@ -178,9 +182,20 @@ ddm_status ddm_loss(ddm_ctx* ctx, const double* target_hm_dev, double* loss_dev)
 ddm_status ddm_backward(ddm_ctx* ctx, const double* dloss_dev, double* grad_dev);
 
 /* Copies the current particle state (layout above) of all instances into /
- * from caller device memory of state_bytes. */
+ * from caller device memory of state_bytes.  Particles are exported in their
+ * initial order (binning reorders them internally); ddm_set_state takes that
+ * order and restarts the binning. */
 ddm_status ddm_get_state(ddm_ctx* ctx, void* state_dev);
 ddm_status ddm_set_state(ddm_ctx* ctx, const void* state_dev);
+
+/* Binning of the current state without reordering it: keys_dev[padded]
+ * receives each slot's cell key inst * (n^dim + 1) + tile * 4^dim +
+ * cell-in-tile (4^dim-cell tiles, lexicographic with the last axis fastest,
+ * base cell floor(x n - 1/2) per axis; padding slots inst * (n^dim + 1) +
+ * n^dim) and perm_dev[padded] the stable sort of the slots by key (uint32,
+ * device).  Slots follow the state's internal order, which is the initial
+ * order right after ddm_init_state. */
+ddm_status ddm_bin_keys(ddm_ctx* ctx, uint32_t* keys_dev, uint32_t* perm_dev);
 
 /* Copies the grid of the last sub-step (per instance, n_grid^dim nodes,
  * 8 values each: m, mv[3], v[3], 0) into caller device memory, in the
@@ -190,6 +205,15 @@ ddm_status ddm_get_grid(ddm_ctx* ctx, void* grid_dev);
 /* Copies the height map of the last ddm_loss ([n_inst][hm_res^(dim-1)],
  * double) into caller device memory. */
 ddm_status ddm_get_heightmap(ddm_ctx* ctx, double* hm_dev);
+
+/* Kernel timing for measurement: when enabled, every launch group of the
+ * sub-step is bracketed by HIP events on the context's stream.  Groups:
+ * 0 P2G, 1 grid update, 2 G2P, 3 binning (keys, sort, gather, tile list),
+ * 4 G2P adjoint, 5 grid adjoint, 6 P2G adjoint, 7 grid clears, 8 loss.
+ * ddm_read_timing synchronises and returns the summed milliseconds and the
+ * number of launches of a group since timing was enabled. */
+ddm_status ddm_set_timing(ddm_ctx* ctx, int32_t enable);
+ddm_status ddm_read_timing(ddm_ctx* ctx, int32_t group, double* total_ms, int64_t* launches);
 
 /* Synchronises the stream and reads the device error word. */
 ddm_status ddm_check(ddm_ctx* ctx, ddm_device_error* out);

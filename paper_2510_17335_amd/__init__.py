@@ -35,6 +35,7 @@ class DdmConfig(C.Structure):
         ("v_ang", C.c_double), ("d_lift", C.c_double), ("hm_origin", C.c_double * 2), ("hm_size", C.c_double),
         ("hm_offset", C.c_double), ("region_depth", C.c_double), ("m_target", C.c_double), ("m_ref", C.c_double),
         ("w_mass", C.c_double), ("w_hm", C.c_double), ("checkpoint_every", C.c_int32), ("max_steps", C.c_int32),
+        ("sort_every", C.c_int32), ("pad0", C.c_int32),
     ]
 
 
@@ -84,10 +85,13 @@ def lib():
             "ddm_get_state": (C.c_int, [vp, vp]),
             "ddm_set_state": (C.c_int, [vp, vp]),
             "ddm_get_grid": (C.c_int, [vp, vp]),
+            "ddm_bin_keys": (C.c_int, [vp, vp, vp]),
             "ddm_get_heightmap": (C.c_int, [vp, vp]),
             "ddm_check": (C.c_int, [vp, C.POINTER(DdmDeviceError)]),
             "ddm_steps_taken": (i64, [vp]),
             "ddm_instance_offset": (i64, [vp, i32]),
+            "ddm_set_timing": (C.c_int, [vp, i32]),
+            "ddm_read_timing": (C.c_int, [vp, i32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
             "ddm_destroy": (None, [vp]),
             "ddm_status_str": (C.c_char_p, [C.c_int]),
             "ddm_last_error": (C.c_char_p, []),
@@ -117,7 +121,7 @@ def make_config(dim: int, n_grid: int, precision: str = "f32", *, bound: int = 3
                 hm_origin=(0.2, 0.2), hm_size: float = 0.6, hm_offset: Optional[float] = None,
                 region_depth: float = 0.03, m_target: float = 0.192, m_ref: float = 0.384, w_mass: float = 1.0,
                 w_hm: float = 1.0, region_sign: int = -1, checkpoint_every: int = 50,
-                max_steps: int = 1000) -> DdmConfig:
+                max_steps: int = 1000, sort_every: int = 8) -> DdmConfig:
     c = DdmConfig()
     c.dim, c.n_grid, c.bound = dim, n_grid, bound
     c.precision = DDM_F64 if precision == "f64" else DDM_F32
@@ -131,7 +135,7 @@ def make_config(dim: int, n_grid: int, precision: str = "f32", *, bound: int = 3
     c.hm_size = hm_size
     c.hm_offset = (1.0 / n_grid) / round(ppc ** (1.0 / dim)) if hm_offset is None else hm_offset
     c.region_depth, c.m_target, c.m_ref, c.w_mass, c.w_hm = region_depth, m_target, m_ref, w_mass, w_hm
-    c.checkpoint_every, c.max_steps = checkpoint_every, max_steps
+    c.checkpoint_every, c.max_steps, c.sort_every = checkpoint_every, max_steps, sort_every
     return c
 
 
@@ -148,7 +152,7 @@ def make_instance(n_particles: int, *, E=3.5e5, nu=0.3, phi_deg=30.0, rho=1600.0
 
 
 def from_workload(w, max_steps: Optional[int] = None, checkpoint_every: Optional[int] = None,
-                  precision: Optional[str] = None):
+                  precision: Optional[str] = None, sort_every: int = 8):
     """(config, instance) for an object with the attributes of a workload
     description (dim, n_grid, dt, ppc, material, skill, ...)."""
     cfg = make_config(
@@ -158,7 +162,7 @@ def from_workload(w, max_steps: Optional[int] = None, checkpoint_every: Optional
         hm_offset=w.hm_offset, region_depth=w.region_depth, m_target=w.m_target, m_ref=w.m_ref, w_mass=w.w_mass,
         w_hm=w.w_hm, region_sign=w.region_sign,
         checkpoint_every=checkpoint_every or w.checkpoint_every or 50,
-        max_steps=max_steps or w.steps)
+        max_steps=max_steps or w.steps, sort_every=sort_every)
     p = w.params7
     inst = make_instance(w.n_particles, E=p[0], nu=p[1], phi_deg=p[2], rho=p[3], cohesion=w.material.cohesion,
                          depth=p[4], angle_deg=p[5], push=p[6], dt=w.dt, tip0=w.tip0)
@@ -280,6 +284,15 @@ class Simulator:
         out = self.torch.cat([x, v, Cm.reshape(n, -1), F.reshape(n, -1)], dim=1)
         return out.cpu().numpy()
 
+    def bin_keys(self):
+        """(keys, perm) of the current state's slots, uint32 numpy arrays."""
+        t = self.torch
+        n = int(self.sizes.padded_particles)
+        keys = t.empty(n, dtype=t.int32, device=self.device)
+        perm = t.empty(n, dtype=t.int32, device=self.device)
+        _check(lib().ddm_bin_keys(self.ctx, C.c_void_p(keys.data_ptr()), C.c_void_p(perm.data_ptr())))
+        return keys.cpu().numpy().view(np.uint32), perm.cpu().numpy().view(np.uint32)
+
     def get_grid(self):
         nodes = self.cfg.n_grid ** self.dim
         out = self.torch.empty((self.n_inst, nodes, 8), dtype=self.dtype, device=self.device)
@@ -311,6 +324,20 @@ class Simulator:
         _check(lib().ddm_backward(self.ctx, C.c_void_p(dl.data_ptr()), C.c_void_p(grad.data_ptr())))
         self._keep = dl
         return grad
+
+    TIMING_GROUPS = ("p2g", "grid_update", "g2p", "binning", "g2p_adj", "grid_adj", "p2g_adj", "clear", "loss")
+
+    def set_timing(self, enable: bool):
+        _check(lib().ddm_set_timing(self.ctx, int(bool(enable))))
+
+    def read_timing(self) -> dict:
+        """{group: (total_ms, launches)} since timing was enabled."""
+        out = {}
+        for g, name in enumerate(self.TIMING_GROUPS):
+            ms, n = C.c_double(), C.c_int64()
+            _check(lib().ddm_read_timing(self.ctx, g, C.byref(ms), C.byref(n)))
+            out[name] = (ms.value, n.value)
+        return out
 
     def check(self) -> DdmDeviceError:
         e = DdmDeviceError()

@@ -346,22 +346,31 @@ template <typename T, int D>
 __device__ __forceinline__ void constit_backward(const Constit<T, D>& c, T mu, T lam, T alpha, T kc,
                                                  const T Fnb[3][3], const T taub[3][3], T Ftb[3][3], T& mub,
                                                  T& lamb, T& alb, T& kcb) {
+  // Gb = U^T Fnb V and Tb = U^T taub U as two-step products.
   T Gb[3][3], Tb[3][3];
+  {
+    T UtF[3][3], UtT[3][3];
 #pragma unroll
-  for (int i = 0; i < D; ++i)
+    for (int i = 0; i < D; ++i)
 #pragma unroll
-    for (int j = 0; j < D; ++j) {
-      T a = T(0), b = T(0);
+      for (int q = 0; q < D; ++q) {
+        T a = T(0), b = T(0);
 #pragma unroll
-      for (int p = 0; p < D; ++p)
+        for (int p = 0; p < D; ++p) { a += c.U[p][i] * Fnb[p][q]; b += c.U[p][i] * taub[p][q]; }
+        UtF[i][q] = a;
+        UtT[i][q] = b;
+      }
 #pragma unroll
-        for (int q = 0; q < D; ++q) {
-          a += c.U[p][i] * Fnb[p][q] * c.V[q][j];
-          b += c.U[p][i] * taub[p][q] * c.U[q][j];
-        }
-      Gb[i][j] = a;
-      Tb[i][j] = b;
-    }
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        T a = T(0), b = T(0);
+#pragma unroll
+        for (int q = 0; q < D; ++q) { a += UtF[i][q] * c.V[q][j]; b += UtT[i][q] * c.U[q][j]; }
+        Gb[i][j] = a;
+        Tb[i][j] = b;
+      }
+  }
   T gb[3], hb[3], sb[3];
 #pragma unroll
   for (int i = 0; i < D; ++i) { gb[i] = Gb[i][i]; hb[i] = Tb[i][i]; }
@@ -384,15 +393,24 @@ __device__ __forceinline__ void constit_backward(const Constit<T, D>& c, T mu, T
       Fb[i][j] = T(0.5) * (symb + skwb);
       Fb[j][i] = T(0.5) * (symb - skwb);
     }
+  // Ftb = U Fb V^T
+  T UF[3][3];
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+      T a = T(0);
+#pragma unroll
+      for (int p = 0; p < D; ++p) a += c.U[i][p] * Fb[p][q];
+      UF[i][q] = a;
+    }
 #pragma unroll
   for (int i = 0; i < D; ++i)
 #pragma unroll
     for (int j = 0; j < D; ++j) {
       T a = T(0);
 #pragma unroll
-      for (int p = 0; p < D; ++p)
-#pragma unroll
-        for (int q = 0; q < D; ++q) a += c.U[i][p] * Fb[p][q] * c.V[j][q];
+      for (int q = 0; q < D; ++q) a += UF[i][q] * c.V[j][q];
       Ftb[i][j] = a;
     }
 }

@@ -75,7 +75,7 @@ template <typename T, int D> struct P {
   }
 };
 // Adjoint states hold plain T in every row.
-template <typename T, int D> struct A {
+template <typename T, int D> struct Adj {
   T* s;
   int64_t ntot;
   __device__ __forceinline__ T& x(int a, int64_t p) const { return s[(int64_t)a * ntot + p]; }
@@ -91,8 +91,8 @@ __device__ __forceinline__ P<T, D> pv(const void* s, int64_t ntot) {
   return P<T, D>{const_cast<T*>(static_cast<const T*>(s)), ntot};
 }
 template <typename T, int D>
-__device__ __forceinline__ A<T, D> av(const void* s, int64_t ntot) {
-  return A<T, D>{const_cast<T*>(static_cast<const T*>(s)), ntot};
+__device__ __forceinline__ Adj<T, D> av(const void* s, int64_t ntot) {
+  return Adj<T, D>{const_cast<T*>(static_cast<const T*>(s)), ntot};
 }
 
 __device__ __forceinline__ void flag_error(DevErr* e, unsigned int bit, int inst) {
@@ -210,13 +210,30 @@ void launch_init_state(int prec, const KCfg& c, const Bufs& b, int nblk, const v
 // then the quadratic B-spline scatter of mass and MLS-MPM momentum
 // mv_i += w (m v + A (x_i - x_p)), A = -dt V_p (4/dx^2) tau + m C.
 // ---------------------------------------------------------------------------
+// Tile geometry: global tile id -> instance and the window origin (tile
+// corner minus one cell, so particles that drifted by up to one cell since
+// the last binning still fall inside the kWin^D node window).
+template <int D>
+__device__ __forceinline__ void tile_origin(const KCfg& c, uint32_t gt, int& inst, int org[3]) {
+  const int nt = c.n / kTile;
+  const uint32_t per = D == 3 ? (uint32_t)(nt * nt * nt) : (uint32_t)(nt * nt);
+  inst = (int)(gt / per);
+  uint32_t t = gt - (uint32_t)inst * per;
+  org[2] = 0;
+  for (int a = D - 1; a >= 0; --a) { org[a] = (int)(t % nt) * kTile - 1; t /= nt; }
+}
+
+template <int D> struct Win {
+  static constexpr int nodes = D == 3 ? kWin * kWin * kWin : kWin * kWin;
+  static __device__ __forceinline__ int idx(int i, int j, int k) { return D == 3 ? (i * kWin + j) * kWin + k : i * kWin + j; }
+};
+
+// Per-particle constitutive update and P2G contributions; emit(node offsets,
+// weight, values) receives the D+1 scattered values of each stencil node.
 template <typename T, int D>
-__global__ void __launch_bounds__(kBlock) k_p2g(KCfg c, Bufs b, const void* st_in, void* st_out, T* __restrict__ grid) {
-  const int inst = b.blk_inst[blockIdx.x];
-  const InstDev& I = b.inst[inst];
-  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (p - I.off >= I.n) return;
-  const P<T, D> si = pv<T, D>(st_in, c.ntot), so = pv<T, D>(st_out, c.ntot);
+__device__ __forceinline__ bool p2g_particle(const KCfg& c, const Bufs& b, const InstDev& I, int inst,
+                                             const P<T, D>& si, const P<T, D>& so, int64_t p, Stencil<T, D>& S,
+                                             T (&A)[3][3], T (&vel)[3]) {
   const T dt = T(I.dt), mp = T(I.mp);
   T Cm[3][3], Gm[3][3], Ft[3][3];
 #pragma unroll
@@ -242,48 +259,97 @@ __global__ void __launch_bounds__(kBlock) k_p2g(KCfg c, Bufs b, const void* st_i
 #pragma unroll
     for (int bb = 0; bb < D; ++bb) so.G(a, bb, p) = Fn[a][bb];
   const T k_str = -dt * T(I.Vp) * T(4.0 * c.inv_dx * c.inv_dx);
-  T A[3][3];
 #pragma unroll
   for (int a = 0; a < D; ++a)
 #pragma unroll
     for (int bb = 0; bb < D; ++bb) A[a][bb] = k_str * tau[a][bb] + mp * Cm[a][bb];
-  T vel[3];
 #pragma unroll
   for (int a = 0; a < D; ++a) vel[a] = mp * si.v(a, p);
-  Stencil<T, D> S;
-  if (!make_stencil<T, D>(si, p, c, S)) { flag_error(b.err, 2u, inst); return; }
-  const T dx = T(c.dx);
-  T* g = grid + I.goff * kNodeVals;
-#pragma unroll
-  for (int o0 = 0; o0 < 3; ++o0)
-#pragma unroll
-    for (int o1 = 0; o1 < 3; ++o1)
-#pragma unroll
-      for (int o2 = 0; o2 < (D == 3 ? 3 : 1); ++o2) {
-        const int off[3] = {o0, o1, o2};
-        T w = T(1), r[3];
-#pragma unroll
-        for (int a = 0; a < D; ++a) { w *= S.w[a][off[a]]; r[a] = (T(off[a]) - S.f[a]) * dx; }
-        T* nd = g + node_of<D>(S.base, o0, o1, o2, c.n) * kNodeVals;
-#pragma unroll
-        for (int a = 0; a < D; ++a) {
-          T ar = vel[a];
-#pragma unroll
-          for (int bb = 0; bb < D; ++bb) ar += A[a][bb] * r[bb];
-          atomicAdd(nd + a, w * ar);
-        }
-        atomicAdd(nd + 3, w * mp);
-      }
+  if (!make_stencil<T, D>(si, p, c, S)) { flag_error(b.err, 2u, inst); return false; }
+  return true;
 }
 
-void launch_p2g(int prec, const KCfg& c, const Bufs& b, int nblk, const void* st_in, void* st_out, void* grid,
-                hipStream_t s) {
+// P2G over occupied tiles: one workgroup per tile (grid-stride over the tile
+// list), contributions accumulated with LDS atomics in a kWin^D window and
+// flushed to the grid once per tile; particles outside the window (drifted
+// more than one cell since binning) add to the grid directly.
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock) k_p2g(KCfg c, Bufs b, TileList tl, const void* st_in, void* st_out,
+                                                T* __restrict__ grid) {
+  __shared__ T win[Win<D>::nodes * kNodeVals];
+  const uint32_t ntiles = *tl.count;
+  const P<T, D> si = pv<T, D>(st_in, c.ntot), so = pv<T, D>(st_out, c.ntot);
+  const T dx = T(c.dx);
+  for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const TileRec tr = tl.list[t];
+    int inst, org[3];
+    tile_origin<D>(c, tr.tile, inst, org);
+    const InstDev& I = b.inst[inst];
+    T* g = grid + I.goff * kNodeVals;
+    for (int i = threadIdx.x; i < Win<D>::nodes * kNodeVals; i += kBlock) win[i] = T(0);
+    __syncthreads();
+    for (uint32_t p0 = tr.start; p0 < tr.end; p0 += kBlock) {
+      const int64_t p = (int64_t)p0 + threadIdx.x;
+      if (p >= tr.end) continue;
+      Stencil<T, D> S;
+      T A[3][3], vel[3];
+      if (!p2g_particle<T, D>(c, b, I, inst, si, so, p, S, A, vel)) continue;
+      const T mp = T(I.mp);
+      int loc[3] = {0, 0, 0};
+      bool inwin = true;
+#pragma unroll
+      for (int a = 0; a < D; ++a) { loc[a] = S.base[a] - org[a]; inwin &= loc[a] >= 0 && loc[a] <= kWin - 3; }
+#pragma unroll
+      for (int o0 = 0; o0 < 3; ++o0)
+#pragma unroll
+        for (int o1 = 0; o1 < 3; ++o1)
+#pragma unroll
+          for (int o2 = 0; o2 < (D == 3 ? 3 : 1); ++o2) {
+            const int off[3] = {o0, o1, o2};
+            T w = T(1), r[3];
+#pragma unroll
+            for (int a = 0; a < D; ++a) { w *= S.w[a][off[a]]; r[a] = (T(off[a]) - S.f[a]) * dx; }
+            T val[4];
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+              T ar = vel[a];
+#pragma unroll
+              for (int bb = 0; bb < D; ++bb) ar += A[a][bb] * r[bb];
+              val[a] = w * ar;
+            }
+            val[3] = w * mp;
+            T* dst = inwin ? win + Win<D>::idx(loc[0] + o0, loc[1] + o1, loc[2] + o2) * kNodeVals
+                           : g + node_of<D>(S.base, o0, o1, o2, c.n) * kNodeVals;
+#pragma unroll
+            for (int a = 0; a < D; ++a) atomicAdd(dst + a, val[a]);
+            atomicAdd(dst + 3, val[3]);
+          }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < Win<D>::nodes; i += kBlock) {
+      const T m = win[i * kNodeVals + 3];
+      if (m == T(0)) continue;
+      int l[3];
+      if (D == 3) { l[0] = i / (kWin * kWin); l[1] = (i / kWin) % kWin; l[2] = i % kWin; }
+      else { l[0] = i / kWin; l[1] = i % kWin; l[2] = 0; }
+      const int gb[3] = {org[0] + l[0], org[1] + l[1], D == 3 ? org[2] + l[2] : 0};
+      T* dst = g + node_of<D>(gb, 0, 0, 0, c.n) * kNodeVals;
+#pragma unroll
+      for (int a = 0; a < D; ++a) atomicAdd(dst + a, win[i * kNodeVals + a]);
+      atomicAdd(dst + 3, m);
+    }
+    __syncthreads();
+  }
+}
+
+void launch_p2g(int prec, const KCfg& c, const Bufs& b, const TileList& tl, int nwg, const void* st_in, void* st_out,
+                void* grid, hipStream_t s) {
   if (prec == 0) {
-    if (c.dim == 3) hipLaunchKernelGGL((k_p2g<float, 3>), dim3(nblk), dim3(kBlock), 0, s, c, b, st_in, st_out, (float*)grid);
-    else hipLaunchKernelGGL((k_p2g<float, 2>), dim3(nblk), dim3(kBlock), 0, s, c, b, st_in, st_out, (float*)grid);
+    if (c.dim == 3) hipLaunchKernelGGL((k_p2g<float, 3>), dim3(nwg), dim3(kBlock), 0, s, c, b, tl, st_in, st_out, (float*)grid);
+    else hipLaunchKernelGGL((k_p2g<float, 2>), dim3(nwg), dim3(kBlock), 0, s, c, b, tl, st_in, st_out, (float*)grid);
   } else {
-    if (c.dim == 3) hipLaunchKernelGGL((k_p2g<double, 3>), dim3(nblk), dim3(kBlock), 0, s, c, b, st_in, st_out, (double*)grid);
-    else hipLaunchKernelGGL((k_p2g<double, 2>), dim3(nblk), dim3(kBlock), 0, s, c, b, st_in, st_out, (double*)grid);
+    if (c.dim == 3) hipLaunchKernelGGL((k_p2g<double, 3>), dim3(nwg), dim3(kBlock), 0, s, c, b, tl, st_in, st_out, (double*)grid);
+    else hipLaunchKernelGGL((k_p2g<double, 2>), dim3(nwg), dim3(kBlock), 0, s, c, b, tl, st_in, st_out, (double*)grid);
   }
 }
 
@@ -431,6 +497,40 @@ void launch_g2p(int prec, const KCfg& c, const Bufs& b, int nblk, const void* st
     if (c.dim == 3) hipLaunchKernelGGL((k_g2p<double, 3>), dim3(nblk), dim3(kBlock), 0, s, c, b, st_in, st_out, (const double*)post);
     else hipLaunchKernelGGL((k_g2p<double, 2>), dim3(nblk), dim3(kBlock), 0, s, c, b, st_in, st_out, (const double*)post);
   }
+}
+
+// State export in the initial particle order: column off_i + pid of the
+// output takes the slot holding particle pid of instance i; padding columns
+// are zero.
+__global__ void k_export_state(KCfg c, Bufs b, int rows, int elem_bytes, const void* in, void* out, const uint32_t* pid) {
+  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const InstDev& I = b.inst[b.blk_inst[blockIdx.x]];
+  const bool live = p - I.off < I.n;
+  const int64_t dst = live ? I.off + pid[p] : p;
+  for (int r = 0; r < rows; ++r) {
+    if (elem_bytes == 4) {
+      const uint32_t v = live ? static_cast<const uint32_t*>(in)[(int64_t)r * c.ntot + p] : 0u;
+      static_cast<uint32_t*>(out)[(int64_t)r * c.ntot + dst] = v;
+    } else {
+      const uint64_t v = live ? static_cast<const uint64_t*>(in)[(int64_t)r * c.ntot + p] : 0ull;
+      static_cast<uint64_t*>(out)[(int64_t)r * c.ntot + dst] = v;
+    }
+  }
+}
+
+void launch_export_state(const KCfg& c, const Bufs& b, int nblk, int rows, int elem_bytes, const void* in, void* out,
+                         const uint32_t* pid, hipStream_t s) {
+  hipLaunchKernelGGL(k_export_state, dim3(nblk), dim3(kBlock), 0, s, c, b, rows, elem_bytes, in, out, pid);
+}
+
+__global__ void k_reset_pid(Bufs b, uint32_t* pid) {
+  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const InstDev& I = b.inst[b.blk_inst[blockIdx.x]];
+  pid[p] = p - I.off < I.n ? (uint32_t)(p - I.off) : 0xFFFFFFFFu;
+}
+
+void launch_reset_pid(const Bufs& b, int nblk, uint32_t* pid, hipStream_t s) {
+  hipLaunchKernelGGL(k_reset_pid, dim3(nblk), dim3(kBlock), 0, s, b, pid);
 }
 
 template <typename T>
@@ -643,7 +743,7 @@ __global__ void __launch_bounds__(kBlock) k_loss_seed(KCfg c, Bufs b, const void
   const InstDev& I = b.inst[inst];
   const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const P<T, D> st = pv<T, D>(state, c.ntot);
-  const A<T, D> ad = av<T, D>(adj, c.ntot);
+  const Adj<T, D> ad = av<T, D>(adj, c.ntot);
   double racc[1] = {0.0};
   T xb[3] = {T(0), T(0), T(0)};
   if (p - I.off < I.n) {
@@ -699,79 +799,111 @@ void launch_loss_seed(int prec, const KCfg& c, const Bufs& b, int nblk, const vo
 //   v_i bar += w (vb + (4/dx^2) C'bar r)            (scattered to the grid)
 // ---------------------------------------------------------------------------
 template <typename T, int D>
-__global__ void __launch_bounds__(kBlock) k_g2p_adj(KCfg c, Bufs b, const void* stv, const T* __restrict__ post,
-                                                    const void* adj_next, void* adj_cur, T* __restrict__ gvb) {
-  const int inst = b.blk_inst[blockIdx.x];
-  const InstDev& I = b.inst[inst];
-  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (p - I.off >= I.n) return;
+__global__ void __launch_bounds__(kBlock) k_g2p_adj(KCfg c, Bufs b, TileList tl, const void* stv,
+                                                    const T* __restrict__ post, const void* adj_next, void* adj_cur,
+                                                    T* __restrict__ gvb) {
+  __shared__ T win[Win<D>::nodes * 4];
+  const uint32_t ntiles = *tl.count;
   const P<T, D> st = pv<T, D>(stv, c.ntot);
-  const A<T, D> an = av<T, D>(adj_next, c.ntot), ac = av<T, D>(adj_cur, c.ntot);
-  Stencil<T, D> S;
-  if (!make_stencil<T, D>(st, p, c, S)) return;
-  const T dt = T(I.dt), dx = T(c.dx), inv_dx = T(c.inv_dx), Dk = T(4.0 * c.inv_dx * c.inv_dx);
-  T xb[3], vb[3], Cb[3][3];
+  const Adj<T, D> an = av<T, D>(adj_next, c.ntot), ac = av<T, D>(adj_cur, c.ntot);
+  const T dx = T(c.dx), inv_dx = T(c.inv_dx), Dk = T(4.0 * c.inv_dx * c.inv_dx);
+  for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const TileRec tr = tl.list[t];
+    int inst, org[3];
+    tile_origin<D>(c, tr.tile, inst, org);
+    const InstDev& I = b.inst[inst];
+    const T dt = T(I.dt);
+    const T* g = post + I.goff * kNodeVals;
+    T* gbv = gvb + I.goff * kNodeVals;
+    for (int i = threadIdx.x; i < Win<D>::nodes * 4; i += kBlock) win[i] = T(0);
+    __syncthreads();
+    for (uint32_t p0 = tr.start; p0 < tr.end; p0 += kBlock) {
+      const int64_t p = (int64_t)p0 + threadIdx.x;
+      if (p >= tr.end) continue;
+      Stencil<T, D> S;
+      if (!make_stencil<T, D>(st, p, c, S)) continue;
+      T xb[3], vb[3], Cb[3][3];
 #pragma unroll
-  for (int a = 0; a < D; ++a) {
-    xb[a] = an.x(a, p);
-    vb[a] = an.v(a, p) + dt * xb[a];
+      for (int a = 0; a < D; ++a) {
+        xb[a] = an.x(a, p);
+        vb[a] = an.v(a, p) + dt * xb[a];
 #pragma unroll
-    for (int bb = 0; bb < D; ++bb) Cb[a][bb] = an.C(a, bb, p);
-  }
-  const T* g = post + I.goff * kNodeVals;
-  T* gb = gvb + I.goff * kNodeVals;
-#pragma unroll
-  for (int o0 = 0; o0 < 3; ++o0)
-#pragma unroll
-    for (int o1 = 0; o1 < 3; ++o1)
-#pragma unroll
-      for (int o2 = 0; o2 < (D == 3 ? 3 : 1); ++o2) {
-        const int off[3] = {o0, o1, o2};
-        T w = T(1), r[3], gw[3];
-#pragma unroll
-        for (int a = 0; a < D; ++a) r[a] = (T(off[a]) - S.f[a]) * dx;
-#pragma unroll
-        for (int a = 0; a < D; ++a) {
-          T prod = S.dw[a][off[a]] * inv_dx;
-#pragma unroll
-          for (int bb = 0; bb < D; ++bb)
-            if (bb != a) prod *= S.w[bb][off[bb]];
-          gw[a] = prod;
-          w *= S.w[a][off[a]];
-        }
-        const int64_t nd = node_of<D>(S.base, o0, o1, o2, c.n) * kNodeVals;
-        T vi[3], Cr[3];
-#pragma unroll
-        for (int a = 0; a < D; ++a) vi[a] = g[nd + a];
-        T s = T(0);
-#pragma unroll
-        for (int a = 0; a < D; ++a) {
-          Cr[a] = T(0);
-#pragma unroll
-          for (int bb = 0; bb < D; ++bb) Cr[a] += Cb[a][bb] * r[bb];
-          s += vi[a] * (vb[a] + Dk * Cr[a]);
-        }
-#pragma unroll
-        for (int a = 0; a < D; ++a) {
-          T ctv = T(0);
-#pragma unroll
-          for (int bb = 0; bb < D; ++bb) ctv += Cb[bb][a] * vi[bb];
-          xb[a] += gw[a] * s - Dk * w * ctv;
-          atomicAdd(gb + nd + a, w * (vb[a] + Dk * Cr[a]));
-        }
+        for (int bb = 0; bb < D; ++bb) Cb[a][bb] = an.C(a, bb, p);
       }
+      int loc[3] = {0, 0, 0};
+      bool inwin = true;
 #pragma unroll
-  for (int a = 0; a < D; ++a) ac.x(a, p) = xb[a];
+      for (int a = 0; a < D; ++a) { loc[a] = S.base[a] - org[a]; inwin &= loc[a] >= 0 && loc[a] <= kWin - 3; }
+#pragma unroll
+      for (int o0 = 0; o0 < 3; ++o0)
+#pragma unroll
+        for (int o1 = 0; o1 < 3; ++o1)
+#pragma unroll
+          for (int o2 = 0; o2 < (D == 3 ? 3 : 1); ++o2) {
+            const int off[3] = {o0, o1, o2};
+            T w = T(1), r[3], gw[3];
+#pragma unroll
+            for (int a = 0; a < D; ++a) r[a] = (T(off[a]) - S.f[a]) * dx;
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+              T prod = S.dw[a][off[a]] * inv_dx;
+#pragma unroll
+              for (int bb = 0; bb < D; ++bb)
+                if (bb != a) prod *= S.w[bb][off[bb]];
+              gw[a] = prod;
+              w *= S.w[a][off[a]];
+            }
+            const int64_t nd = node_of<D>(S.base, o0, o1, o2, c.n) * kNodeVals;
+            T vi[3], Cr[3];
+#pragma unroll
+            for (int a = 0; a < D; ++a) vi[a] = g[nd + a];
+            T sdot = T(0);
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+              Cr[a] = T(0);
+#pragma unroll
+              for (int bb = 0; bb < D; ++bb) Cr[a] += Cb[a][bb] * r[bb];
+              sdot += vi[a] * (vb[a] + Dk * Cr[a]);
+            }
+            T* dst = inwin ? win + Win<D>::idx(loc[0] + o0, loc[1] + o1, loc[2] + o2) * 4 : gbv + nd;
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+              T ctv = T(0);
+#pragma unroll
+              for (int bb = 0; bb < D; ++bb) ctv += Cb[bb][a] * vi[bb];
+              xb[a] += gw[a] * sdot - Dk * w * ctv;
+              atomicAdd(dst + a, w * (vb[a] + Dk * Cr[a]));
+            }
+          }
+#pragma unroll
+      for (int a = 0; a < D; ++a) ac.x(a, p) = xb[a];
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < Win<D>::nodes; i += kBlock) {
+      int l[3];
+      if (D == 3) { l[0] = i / (kWin * kWin); l[1] = (i / kWin) % kWin; l[2] = i % kWin; }
+      else { l[0] = i / kWin; l[1] = i % kWin; l[2] = 0; }
+      bool any = false;
+#pragma unroll
+      for (int a = 0; a < D; ++a) any |= win[i * 4 + a] != T(0);
+      if (!any) continue;
+      const int gbase[3] = {org[0] + l[0], org[1] + l[1], D == 3 ? org[2] + l[2] : 0};
+      T* dst = gbv + node_of<D>(gbase, 0, 0, 0, c.n) * kNodeVals;
+#pragma unroll
+      for (int a = 0; a < D; ++a) atomicAdd(dst + a, win[i * 4 + a]);
+    }
+    __syncthreads();
+  }
 }
 
-void launch_g2p_adj(int prec, const KCfg& c, const Bufs& b, int nblk, const void* st, const void* post,
-                    const void* adj_next, void* adj_cur, void* gvb, hipStream_t s) {
+void launch_g2p_adj(int prec, const KCfg& c, const Bufs& b, const TileList& tl, int nwg, const void* st,
+                    const void* post, const void* adj_next, void* adj_cur, void* gvb, hipStream_t s) {
   if (prec == 0) {
-    if (c.dim == 3) hipLaunchKernelGGL((k_g2p_adj<float, 3>), dim3(nblk), dim3(kBlock), 0, s, c, b, st, (const float*)post, adj_next, adj_cur, (float*)gvb);
-    else hipLaunchKernelGGL((k_g2p_adj<float, 2>), dim3(nblk), dim3(kBlock), 0, s, c, b, st, (const float*)post, adj_next, adj_cur, (float*)gvb);
+    if (c.dim == 3) hipLaunchKernelGGL((k_g2p_adj<float, 3>), dim3(nwg), dim3(kBlock), 0, s, c, b, tl, st, (const float*)post, adj_next, adj_cur, (float*)gvb);
+    else hipLaunchKernelGGL((k_g2p_adj<float, 2>), dim3(nwg), dim3(kBlock), 0, s, c, b, tl, st, (const float*)post, adj_next, adj_cur, (float*)gvb);
   } else {
-    if (c.dim == 3) hipLaunchKernelGGL((k_g2p_adj<double, 3>), dim3(nblk), dim3(kBlock), 0, s, c, b, st, (const double*)post, adj_next, adj_cur, (double*)gvb);
-    else hipLaunchKernelGGL((k_g2p_adj<double, 2>), dim3(nblk), dim3(kBlock), 0, s, c, b, st, (const double*)post, adj_next, adj_cur, (double*)gvb);
+    if (c.dim == 3) hipLaunchKernelGGL((k_g2p_adj<double, 3>), dim3(nwg), dim3(kBlock), 0, s, c, b, tl, st, (const double*)post, adj_next, adj_cur, (double*)gvb);
+    else hipLaunchKernelGGL((k_g2p_adj<double, 2>), dim3(nwg), dim3(kBlock), 0, s, c, b, tl, st, (const double*)post, adj_next, adj_cur, (double*)gvb);
   }
 }
 
@@ -860,52 +992,63 @@ void launch_grid_adj(int prec, const KCfg& c, const Bufs& b, int step, const voi
 }
 
 // ---------------------------------------------------------------------------
-// Adjoint of P2G and of the constitutive update.  Gathers the grid adjoints
-// (m bar, mv bar) over the stencil, then goes back through A, the stress, the
-// return map and the SVD (isotropic-function adjoint) and F_tmp = (I + dt C) F.
-// Material adjoints (mu, lambda, alpha, k_c, rho) are block-reduced in double.
+// Adjoint of P2G and of the constitutive update, in two kernels so that the
+// 27-node gather and the SVD-frame adjoint do not hold registers at the same
+// time.
+//  k_p2g_adj_gather: recomputes the stress and A = k tau + m_p C, gathers the
+//    grid adjoints (m bar, mv bar) over the stencil and writes x bar (adding
+//    to the G2P part already there), v bar, and A bar into the C bar rows;
+//    the density adjoint V_p (m_p bar + A bar : C) is block-reduced.
+//  k_p2g_adj_constit: tau bar = k A bar, back through the return map and the
+//    SVD (isotropic-function adjoint) and F_tmp = (I + dt C)(I + G); writes
+//    G bar and C bar = m_p A bar + dt F_tmp bar (I + G)^T; material adjoints
+//    (mu, lambda, alpha, k_c) are block-reduced in double.
 // ---------------------------------------------------------------------------
 template <typename T, int D>
-__global__ void __launch_bounds__(kBlock) k_p2g_adj(KCfg c, Bufs b, const void* stv, const T* __restrict__ gbar,
-                                                    const void* adj_next, void* adj_cur, double* pacc) {
+__device__ __forceinline__ void ftmp_of(const P<T, D>& st, int64_t p, T dt, T Cm[3][3], T Gm[3][3], T Ft[3][3]) {
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int bb = 0; bb < D; ++bb) { Cm[a][bb] = st.C(a, bb, p); Gm[a][bb] = st.G(a, bb, p); }
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int bb = 0; bb < D; ++bb) {
+      T s = Cm[a][bb];
+#pragma unroll
+      for (int k = 0; k < D; ++k) s += Cm[a][k] * Gm[k][bb];
+      Ft[a][bb] = Gm[a][bb] + dt * s;
+    }
+}
+
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock) k_p2g_adj_gather(KCfg c, Bufs b, const void* stv, const T* __restrict__ gbar,
+                                                           void* adj_cur, double* pacc) {
   const int inst = b.blk_inst[blockIdx.x];
   const InstDev& I = b.inst[inst];
   const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  double acc[5] = {0, 0, 0, 0, 0};
+  double acc[1] = {0.0};
   if (p - I.off < I.n) {
     const P<T, D> st = pv<T, D>(stv, c.ntot);
-    const A<T, D> an = av<T, D>(adj_next, c.ntot), ac = av<T, D>(adj_cur, c.ntot);
+    const Adj<T, D> ac = av<T, D>(adj_cur, c.ntot);
     Stencil<T, D> S;
     if (make_stencil<T, D>(st, p, c, S)) {
       const T dt = T(I.dt), mp = T(I.mp), dx = T(c.dx), inv_dx = T(c.inv_dx);
-      const T mu = T(I.mu), lam = T(I.lam), al = T(I.alpha), kc = T(I.kc);
-      T Cm[3][3], Gm[3][3], Ft[3][3], vel[3];
+      T Cm[3][3], Gm[3][3], Ft[3][3], vel[3], A[3][3];
+      ftmp_of<T, D>(st, p, dt, Cm, Gm, Ft);
+      {
+        Constit<T, D> cs;
+        constit_forward<T, D>(Ft, T(I.mu), T(I.lam), T(I.alpha), T(I.kc), cs);
+        T Fn[3][3], tau[3][3];
+        constit_outputs<T, D>(cs, Fn, tau);
+        const T k_str = -dt * T(I.Vp) * T(4.0 * c.inv_dx * c.inv_dx);
 #pragma unroll
-      for (int a = 0; a < D; ++a) {
-        vel[a] = st.v(a, p);
+        for (int a = 0; a < D; ++a)
 #pragma unroll
-        for (int bb = 0; bb < D; ++bb) { Cm[a][bb] = st.C(a, bb, p); Gm[a][bb] = st.G(a, bb, p); }
+          for (int bb = 0; bb < D; ++bb) A[a][bb] = k_str * tau[a][bb] + mp * Cm[a][bb];
       }
 #pragma unroll
-      for (int a = 0; a < D; ++a)
-#pragma unroll
-        for (int bb = 0; bb < D; ++bb) {
-          T s = Cm[a][bb];
-#pragma unroll
-          for (int k = 0; k < D; ++k) s += Cm[a][k] * Gm[k][bb];
-          Ft[a][bb] = Gm[a][bb] + dt * s;
-        }
-      Constit<T, D> cs;
-      constit_forward<T, D>(Ft, mu, lam, al, kc, cs);
-      T Fn[3][3], tau[3][3];
-      constit_outputs<T, D>(cs, Fn, tau);
-      const T k_str = -dt * T(I.Vp) * T(4.0 * c.inv_dx * c.inv_dx);
-      T A[3][3];
-#pragma unroll
-      for (int a = 0; a < D; ++a)
-#pragma unroll
-        for (int bb = 0; bb < D; ++bb) A[a][bb] = k_str * tau[a][bb] + mp * Cm[a][bb];
-      // gather
+      for (int a = 0; a < D; ++a) vel[a] = st.v(a, p);
       T mpb = T(0), vb[3] = {T(0), T(0), T(0)}, Ab[3][3] = {{T(0), T(0), T(0)}, {T(0), T(0), T(0)}, {T(0), T(0), T(0)}};
       T xb[3];
 #pragma unroll
@@ -956,58 +1099,79 @@ __global__ void __launch_bounds__(kBlock) k_p2g_adj(KCfg c, Bufs b, const void* 
               xb[a] += gw[a] * sc - w * atm;
             }
           }
-      // A = k_str tau + m_p C
-      T taub[3][3], Cb[3][3];
 #pragma unroll
-      for (int a = 0; a < D; ++a)
+      for (int a = 0; a < D; ++a) {
+        ac.x(a, p) = xb[a];
+        ac.v(a, p) = vb[a];
 #pragma unroll
-        for (int bb = 0; bb < D; ++bb) {
-          taub[a][bb] = k_str * Ab[a][bb];
-          Cb[a][bb] = mp * Ab[a][bb];
-          mpb += Ab[a][bb] * Cm[a][bb];
-        }
-      T Fnb[3][3];
-#pragma unroll
-      for (int a = 0; a < D; ++a)
-#pragma unroll
-        for (int bb = 0; bb < D; ++bb) Fnb[a][bb] = an.G(a, bb, p);
-      T Ftb[3][3], mub = T(0), lamb = T(0), alb = T(0), kcb = T(0);
-      constit_backward<T, D>(cs, mu, lam, al, kc, Fnb, taub, Ftb, mub, lamb, alb, kcb);
-      // F_tmp = (I + dt C) F with F = I + G
-#pragma unroll
-      for (int a = 0; a < D; ++a)
-#pragma unroll
-        for (int bb = 0; bb < D; ++bb) {
-          T fb = Ftb[a][bb], cb = Ftb[a][bb];
-#pragma unroll
-          for (int k = 0; k < D; ++k) {
-            fb += dt * Cm[k][a] * Ftb[k][bb];
-            cb += Ftb[a][k] * Gm[bb][k];
-          }
-          ac.G(a, bb, p) = fb;
-          ac.C(a, bb, p) = Cb[a][bb] + dt * cb;
-        }
-#pragma unroll
-      for (int a = 0; a < D; ++a) { ac.x(a, p) = xb[a]; ac.v(a, p) = vb[a]; }
-      acc[0] = (double)mub;
-      acc[1] = (double)lamb;
-      acc[2] = (double)alb;
-      acc[3] = (double)kcb;
-      acc[4] = (double)mpb * I.Vp;
+        for (int bb = 0; bb < D; ++bb) { ac.C(a, bb, p) = Ab[a][bb]; mpb += Ab[a][bb] * Cm[a][bb]; }
+      }
+      acc[0] = (double)mpb * I.Vp;
     }
   }
-  block_accumulate<5>(acc, pacc + (int64_t)inst * 8);
+  block_accumulate<1>(acc, pacc + (int64_t)inst * 8 + 4);
+}
+
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock) k_p2g_adj_constit(KCfg c, Bufs b, const void* stv, const void* adj_next,
+                                                            void* adj_cur, double* pacc) {
+  const int inst = b.blk_inst[blockIdx.x];
+  const InstDev& I = b.inst[inst];
+  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  double acc[4] = {0, 0, 0, 0};
+  if (p - I.off < I.n) {
+    const P<T, D> st = pv<T, D>(stv, c.ntot);
+    const Adj<T, D> an = av<T, D>(adj_next, c.ntot), ac = av<T, D>(adj_cur, c.ntot);
+    const T dt = T(I.dt), mp = T(I.mp);
+    const T mu = T(I.mu), lam = T(I.lam), al = T(I.alpha), kc = T(I.kc);
+    const T k_str = -dt * T(I.Vp) * T(4.0 * c.inv_dx * c.inv_dx);
+    T Cm[3][3], Gm[3][3], Ft[3][3], Ab[3][3], taub[3][3], Fnb[3][3];
+    ftmp_of<T, D>(st, p, dt, Cm, Gm, Ft);
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+      for (int bb = 0; bb < D; ++bb) {
+        Ab[a][bb] = ac.C(a, bb, p);
+        taub[a][bb] = k_str * Ab[a][bb];
+        Fnb[a][bb] = an.G(a, bb, p);
+      }
+    Constit<T, D> cs;
+    constit_forward<T, D>(Ft, mu, lam, al, kc, cs);
+    T Ftb[3][3], mub = T(0), lamb = T(0), alb = T(0), kcb = T(0);
+    constit_backward<T, D>(cs, mu, lam, al, kc, Fnb, taub, Ftb, mub, lamb, alb, kcb);
+    // F_tmp = (I + dt C) F with F = I + G
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+      for (int bb = 0; bb < D; ++bb) {
+        T fb = Ftb[a][bb], cb = Ftb[a][bb];
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+          fb += dt * Cm[k][a] * Ftb[k][bb];
+          cb += Ftb[a][k] * Gm[bb][k];
+        }
+        ac.G(a, bb, p) = fb;
+        ac.C(a, bb, p) = mp * Ab[a][bb] + dt * cb;
+      }
+    acc[0] = (double)mub;
+    acc[1] = (double)lamb;
+    acc[2] = (double)alb;
+    acc[3] = (double)kcb;
+  }
+  block_accumulate<4>(acc, pacc + (int64_t)inst * 8);
 }
 
 void launch_p2g_adj(int prec, const KCfg& c, const Bufs& b, int nblk, const void* st, const void* gb,
                     const void* adj_next, void* adj_cur, double* pacc, hipStream_t s) {
+#define DDM_P2GADJ(T, DD)                                                                                          \
+  hipLaunchKernelGGL((k_p2g_adj_gather<T, DD>), dim3(nblk), dim3(kBlock), 0, s, c, b, st, (const T*)gb, adj_cur, pacc); \
+  hipLaunchKernelGGL((k_p2g_adj_constit<T, DD>), dim3(nblk), dim3(kBlock), 0, s, c, b, st, adj_next, adj_cur, pacc);
   if (prec == 0) {
-    if (c.dim == 3) hipLaunchKernelGGL((k_p2g_adj<float, 3>), dim3(nblk), dim3(kBlock), 0, s, c, b, st, (const float*)gb, adj_next, adj_cur, pacc);
-    else hipLaunchKernelGGL((k_p2g_adj<float, 2>), dim3(nblk), dim3(kBlock), 0, s, c, b, st, (const float*)gb, adj_next, adj_cur, pacc);
+    if (c.dim == 3) { DDM_P2GADJ(float, 3) } else { DDM_P2GADJ(float, 2) }
   } else {
-    if (c.dim == 3) hipLaunchKernelGGL((k_p2g_adj<double, 3>), dim3(nblk), dim3(kBlock), 0, s, c, b, st, (const double*)gb, adj_next, adj_cur, pacc);
-    else hipLaunchKernelGGL((k_p2g_adj<double, 2>), dim3(nblk), dim3(kBlock), 0, s, c, b, st, (const double*)gb, adj_next, adj_cur, pacc);
+    if (c.dim == 3) { DDM_P2GADJ(double, 3) } else { DDM_P2GADJ(double, 2) }
   }
+#undef DDM_P2GADJ
 }
 
 // ---------------------------------------------------------------------------

@@ -9,6 +9,12 @@ namespace ddm {
 constexpr int kBlock = 256;          // particle kernels: threads per block, and the
                                      // padding unit of every instance's particle range
 constexpr int kNodeVals = 4;         // node record: mv[0..2] (or v), m
+constexpr int kTile = 4;             // binning tile edge in cells
+constexpr int kWin = kTile + 4;      // LDS window edge in nodes: tile + stencil + 1-cell drift each side
+
+// An occupied tile: slots [start, end) of the sorted state, global tile id.
+struct TileRec { uint32_t start, end, tile; };
+struct TileList { const TileRec* list; const uint32_t* count; };
 
 // Per-instance constants on the device (double; kernels cast to their type).
 struct InstDev {
@@ -49,12 +55,15 @@ struct Bufs {
 void launch_fill_zero(void* p, int64_t count, int elem_bytes, hipStream_t s);
 void launch_init_state(int prec, const KCfg& c, const Bufs& b, int nblk, const void* x0, void* state,
                        uint32_t* pid, hipStream_t s);
-void launch_p2g(int prec, const KCfg& c, const Bufs& b, int nblk, const void* st_in, void* st_out, void* grid,
-                hipStream_t s);
+void launch_p2g(int prec, const KCfg& c, const Bufs& b, const TileList& tl, int nwg, const void* st_in, void* st_out,
+                void* grid, hipStream_t s);
 void launch_grid_update(int prec, const KCfg& c, const Bufs& b, int step, const void* grid_pre, void* grid_post,
                         hipStream_t s);
 void launch_g2p(int prec, const KCfg& c, const Bufs& b, int nblk, const void* st_in, void* st_out,
                 const void* grid_post, hipStream_t s);
+void launch_export_state(const KCfg& c, const Bufs& b, int nblk, int rows, int elem_bytes, const void* in, void* out,
+                         const uint32_t* pid, hipStream_t s);
+void launch_reset_pid(const Bufs& b, int nblk, uint32_t* pid, hipStream_t s);
 void launch_grid_export(int prec, const KCfg& c, const void* grid_pre, const void* grid_post, void* out,
                         hipStream_t s);
 
@@ -75,13 +84,28 @@ void launch_loss_seed(int prec, const KCfg& c, const Bufs& b, int nblk, const vo
                       int final_step, const LossBufs& L, void* adj, double* pacc, hipStream_t s);
 
 // Adjoint sub-step pieces (reverse order: g2p_adj, grid_adj, p2g_adj).
-void launch_g2p_adj(int prec, const KCfg& c, const Bufs& b, int nblk, const void* st, const void* grid_post,
-                    const void* adj_next, void* adj_cur, void* gvb, hipStream_t s);
+void launch_g2p_adj(int prec, const KCfg& c, const Bufs& b, const TileList& tl, int nwg, const void* st,
+                    const void* grid_post, const void* adj_next, void* adj_cur, void* gvb, hipStream_t s);
 void launch_grid_adj(int prec, const KCfg& c, const Bufs& b, int step, const void* grid_pre, const void* gvb,
                      void* gb, double* pose_bar, hipStream_t s);
 void launch_p2g_adj(int prec, const KCfg& c, const Bufs& b, int nblk, const void* st, const void* gb,
                     const void* adj_next, void* adj_cur, double* pacc, hipStream_t s);
 void launch_grad_final(const KCfg& c, const InstDev* inst, const double* pacc, const double* pose_bar,
                        const double* pose_jac, int n_steps, const double* dloss, double* grad, hipStream_t s);
+
+// Binning (ddm_sort.hip).
+void launch_keys(int prec, const KCfg& c, const Bufs& b, int nblk, const void* state, uint32_t* keys, uint32_t* vals,
+                 hipStream_t s);
+int sort_passes(uint32_t max_key);
+int64_t sort_hist_words(int64_t n);
+int64_t sort_sum_words(int64_t n);
+int radix_sort(uint32_t* keys[2], uint32_t* vals[2], int64_t n, uint32_t max_key, uint32_t* hist, uint32_t* sums,
+                hipStream_t s);
+void launch_gather(int elem_bytes, const void* in, void* out, const uint32_t* perm, int rows, int64_t ntot,
+                   const uint32_t* pid_in, uint32_t* pid_out, hipStream_t s);
+void launch_unpermute(int elem_bytes, const void* in, void* out, const uint32_t* perm, int rows, int64_t ntot,
+                      hipStream_t s);
+void launch_tile_list(const KCfg& c, const uint32_t* sorted_keys, uint32_t* tstart, uint32_t* tend, TileRec* list,
+                      uint32_t* count, hipStream_t s);
 
 }  // namespace ddm

@@ -41,15 +41,17 @@ int64_t pad_up(int64_t n, int64_t m) { return (n + m - 1) / m * m; }
 
 // Device workspace carved into 256-byte aligned pieces.
 struct Layout {
-  size_t inst = 0, blk_inst = 0, poses = 0, pose_jac = 0, err = 0, pid = 0;
-  size_t cur = 0, grid_pre = 0, grid_post = 0;
-  size_t ckpt = 0, seg_state = 0, seg_grid = 0;
+  size_t inst = 0, blk_inst = 0, poses = 0, pose_jac = 0, err = 0, pid = 0, pid_tmp = 0;
+  size_t cur = 0, grid_pre = 0, grid_post = 0, scratch = 0;
+  size_t ckpt = 0, seg_state = 0, seg_grid = 0, seg_perm = 0, seg_tiles = 0, seg_tcount = 0;
   size_t adj0 = 0, adj1 = 0, gvb = 0, gb = 0, pacc = 0, pose_bar = 0;
   size_t hm_bits = 0, owner = 0, target = 0, hm_val = 0, dldh = 0, region = 0, dldm = 0, loss = 0;
+  size_t keys0 = 0, keys1 = 0, vals0 = 0, vals1 = 0, hist = 0, sums = 0, tstart = 0, tend = 0, tiles = 0, tcount = 0;
   size_t total = 0;
   size_t state_bytes = 0, grid_bytes = 0;
-  int64_t ntot = 0, nblk = 0;
-  int n_ckpt = 0, K = 1;
+  int64_t ntot = 0, nblk = 0, total_tiles = 0, max_chunks = 0;
+  int n_ckpt = 0, K = 1, rows = 0, esz = 4, nwg = 1;
+  uint32_t max_key = 0;
 };
 
 struct Carver {
@@ -73,7 +75,17 @@ Layout make_layout(const ddm_config& c, int n_inst, const ddm_instance* in) {
   int64_t nodes = 1;
   for (int a = 0; a < D; ++a) nodes *= c.n_grid;
   const int S = 2 * D + 2 * D * D;
+  L.rows = S;
+  L.esz = b;
   L.state_bytes = (size_t)S * ntot * b;
+  const int64_t tiles_per_inst = nodes / (D == 3 ? ddm::kTile * ddm::kTile * ddm::kTile : ddm::kTile * ddm::kTile);
+  L.total_tiles = tiles_per_inst * n_inst;
+  L.max_key = (uint32_t)((uint64_t)n_inst * (uint64_t)(nodes + 1) - 1);
+  // Chunk records: occupied tiles split into chunks of at most kBlock
+  // particles (at most one partial chunk per tile).  Workgroups of the tile
+  // kernels: about one per expected chunk, grid-stride beyond that.
+  L.max_chunks = L.total_tiles + L.nblk;
+  L.nwg = (int)std::max<int64_t>(1, std::min<int64_t>(L.max_chunks, L.nblk + L.nblk / 2 + 256));
   L.grid_bytes = (size_t)n_inst * nodes * ddm::kNodeVals * b;
   L.K = std::max(1, (int)c.checkpoint_every);
   L.n_ckpt = (c.max_steps + L.K - 1) / L.K + 1;
@@ -85,12 +97,17 @@ Layout make_layout(const ddm_config& c, int n_inst, const ddm_instance* in) {
   L.pose_jac = cv.take((size_t)n_inst * c.max_steps * 24 * sizeof(double));
   L.err = cv.take(sizeof(ddm::DevErr));
   L.pid = cv.take(sizeof(uint32_t) * ntot);
+  L.pid_tmp = cv.take(sizeof(uint32_t) * ntot);
   L.cur = cv.take(L.state_bytes);
+  L.scratch = cv.take(L.state_bytes);
   L.grid_pre = cv.take(L.grid_bytes);
   L.grid_post = cv.take(L.grid_bytes);
   L.ckpt = cv.take(L.state_bytes * L.n_ckpt);
   L.seg_state = cv.take(L.state_bytes * (L.K + 1));
   L.seg_grid = cv.take(L.grid_bytes * 2 * L.K);
+  L.seg_perm = cv.take(sizeof(uint32_t) * ntot * L.K);
+  L.seg_tiles = cv.take(sizeof(ddm::TileRec) * L.max_chunks * L.K);
+  L.seg_tcount = cv.take(sizeof(uint32_t) * L.K);
   L.adj0 = cv.take(L.state_bytes);
   L.adj1 = cv.take(L.state_bytes);
   L.gvb = cv.take(L.grid_bytes);
@@ -105,6 +122,16 @@ Layout make_layout(const ddm_config& c, int n_inst, const ddm_instance* in) {
   L.region = cv.take(sizeof(double) * n_inst);
   L.dldm = cv.take(sizeof(double) * n_inst);
   L.loss = cv.take(sizeof(double) * n_inst);
+  L.keys0 = cv.take(sizeof(uint32_t) * ntot);
+  L.keys1 = cv.take(sizeof(uint32_t) * ntot);
+  L.vals0 = cv.take(sizeof(uint32_t) * ntot);
+  L.vals1 = cv.take(sizeof(uint32_t) * ntot);
+  L.hist = cv.take(sizeof(uint32_t) * ddm::sort_hist_words(ntot));
+  L.sums = cv.take(sizeof(uint32_t) * ddm::sort_sum_words(ddm::sort_hist_words(ntot)));
+  L.tstart = cv.take(sizeof(uint32_t) * L.total_tiles);
+  L.tend = cv.take(sizeof(uint32_t) * L.total_tiles);
+  L.tiles = cv.take(sizeof(ddm::TileRec) * L.max_chunks);
+  L.tcount = cv.take(sizeof(uint32_t));
   L.total = cv.take(0);
   return L;
 }
@@ -224,8 +251,22 @@ struct ddm_ctx {
   bool recorded = false;         // a rollout is recorded
   int64_t rec_k0 = 0, rec_n = 0;
   bool loss_ready = false;
+  bool need_sort = true;          // re-bin before the next sub-step
+  std::vector<char> rec_sorted;   // per recorded step: binned at its start
+  // kernel timing
+  bool timing = false;
+  struct Ev { int group; hipEvent_t a, b; };
+  std::vector<Ev> events;
+  std::vector<hipEvent_t> pool;
+  double t_ms[9] = {0};
+  int64_t t_n[9] = {0};
 
   template <typename T = char> T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
+  ddm::TileList tiles() const { return ddm::TileList{at<const ddm::TileRec>(L.tiles), at<const uint32_t>(L.tcount)}; }
+  ddm::TileList seg_tiles(int j) const {
+    return ddm::TileList{at<const ddm::TileRec>(L.seg_tiles + sizeof(ddm::TileRec) * L.max_chunks * j),
+                         at<const uint32_t>(L.seg_tcount + sizeof(uint32_t) * j)};
+  }
   ddm::Bufs bufs() const {
     ddm::Bufs b;
     b.inst = at<const ddm::InstDev>(L.inst);
@@ -264,6 +305,7 @@ ddm_status validate(const ddm_config* c, int32_t n_inst, const ddm_instance* in)
   if (!(c->hm_size > 0)) return fail(DDM_EINVAL, "hm_size must be > 0");
   if (c->checkpoint_every < 1) return fail(DDM_EINVAL, "checkpoint_every must be >= 1");
   if (c->max_steps < 1) return fail(DDM_EINVAL, "max_steps must be >= 1");
+  if (c->sort_every < 0) return fail(DDM_EINVAL, "sort_every must be >= 0");
   if (c->shovel && !(c->v_lin > 0 && c->v_ang > 0 && c->d_lift > 0 && c->contact_skin >= 0 && c->shovel_mu >= 0))
     return fail(DDM_EINVAL, "shovel speeds, lift, skin and friction must be positive");
   if (n_inst < 1 || !in) return fail(DDM_EINVAL, "need at least one instance");
@@ -302,15 +344,82 @@ void to_prec(const std::vector<double>& src, std::vector<char>& out) {
 
 ddm_status launch_status() { return hip_check(hipGetLastError(), "kernel launch"); }
 
-// One forward sub-step from st_in to st_out (may alias); grids given.
-ddm_status forward_step(ddm_ctx* x, int64_t step, const void* st_in, void* st_out, void* gpre, void* gpost) {
+hipEvent_t take_event(ddm_ctx* x) {
+  if (!x->pool.empty()) { hipEvent_t e = x->pool.back(); x->pool.pop_back(); return e; }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Brackets a launch group with events when timing is on.
+struct Timed {
+  ddm_ctx* x;
+  int group;
+  hipEvent_t a = nullptr;
+  Timed(ddm_ctx* x_, int g) : x(x_), group(g) {
+    if (x->timing && (a = take_event(x))) (void)hipEventRecord(a, x->stream);
+  }
+  ~Timed() {
+    if (!a) return;
+    hipEvent_t b = take_event(x);
+    if (!b) return;
+    (void)hipEventRecord(b, x->stream);
+    x->events.push_back(ddm_ctx::Ev{group, a, b});
+  }
+};
+
+void resolve_events(ddm_ctx* x) {
+  for (const auto& e : x->events) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, e.a, e.b) == hipSuccess) { x->t_ms[e.group] += ms; x->t_n[e.group] += 1; }
+    x->pool.push_back(e.a);
+    x->pool.push_back(e.b);
+  }
+  x->events.clear();
+}
+
+// Bins the particles of `state` in place: exact cell keys, stable radix sort
+// by (instance, tile, cell), gather of the state rows (and ids) into sorted
+// order, and the occupied-tile list.  When perm_out / tiles_out are given the
+// permutation and the tile list are also stored there (for the reverse pass).
+ddm_status bin_state(ddm_ctx* x, void* state, uint32_t* pid, uint32_t* perm_out, ddm::TileRec* tiles_out,
+                     uint32_t* tcount_out) {
+  Timed tm(x, 3);
+  const Layout& L = x->L;
+  hipStream_t st = x->stream;
+  uint32_t* keys[2] = {x->at<uint32_t>(L.keys0), x->at<uint32_t>(L.keys1)};
+  uint32_t* vals[2] = {x->at<uint32_t>(L.vals0), x->at<uint32_t>(L.vals1)};
+  ddm::launch_keys(x->prec, x->kc, x->bufs(), (int)L.nblk, state, keys[0], vals[0], st);
+  const int r = ddm::radix_sort(keys, vals, L.ntot, L.max_key, x->at<uint32_t>(L.hist), x->at<uint32_t>(L.sums), st);
+  ddm::launch_gather(L.esz, state, x->at(L.scratch), vals[r], L.rows, L.ntot, pid, pid ? x->at<uint32_t>(L.pid_tmp) : nullptr, st);
+  DDM_HIP(hipMemcpyAsync(state, x->at(L.scratch), L.state_bytes, hipMemcpyDeviceToDevice, st));
+  if (pid) DDM_HIP(hipMemcpyAsync(pid, x->at(L.pid_tmp), sizeof(uint32_t) * L.ntot, hipMemcpyDeviceToDevice, st));
+  ddm::launch_tile_list(x->kc, keys[r], x->at<uint32_t>(L.tstart), x->at<uint32_t>(L.tend), x->at<ddm::TileRec>(L.tiles),
+                        x->at<uint32_t>(L.tcount), st);
+  if (perm_out) DDM_HIP(hipMemcpyAsync(perm_out, vals[r], sizeof(uint32_t) * L.ntot, hipMemcpyDeviceToDevice, st));
+  if (tiles_out) {
+    DDM_HIP(hipMemcpyAsync(tiles_out, x->at(L.tiles), sizeof(ddm::TileRec) * L.max_chunks, hipMemcpyDeviceToDevice, st));
+    DDM_HIP(hipMemcpyAsync(tcount_out, x->at(L.tcount), sizeof(uint32_t), hipMemcpyDeviceToDevice, st));
+  }
+  return launch_status();
+}
+
+// One forward sub-step from st_in to st_out (may alias) with the given tile
+// list; grids given.
+ddm_status forward_step(ddm_ctx* x, int64_t step, const ddm::TileList& tl, const void* st_in, void* st_out,
+                        void* gpre, void* gpost) {
   const ddm::Bufs b = x->bufs();
   const int esz = x->prec ? 8 : 4;
-  ddm::launch_fill_zero(gpre, (int64_t)x->L.grid_bytes / esz, esz, x->stream);
-  ddm::launch_p2g(x->prec, x->kc, b, (int)x->L.nblk, st_in, st_out, gpre, x->stream);
-  ddm::launch_grid_update(x->prec, x->kc, b, (int)step, gpre, gpost, x->stream);
-  ddm::launch_g2p(x->prec, x->kc, b, (int)x->L.nblk, st_in, st_out, gpost, x->stream);
+  { Timed t(x, 7); ddm::launch_fill_zero(gpre, (int64_t)x->L.grid_bytes / esz, esz, x->stream); }
+  { Timed t(x, 0); ddm::launch_p2g(x->prec, x->kc, b, tl, x->L.nwg, st_in, st_out, gpre, x->stream); }
+  { Timed t(x, 1); ddm::launch_grid_update(x->prec, x->kc, b, (int)step, gpre, gpost, x->stream); }
+  { Timed t(x, 2); ddm::launch_g2p(x->prec, x->kc, b, (int)x->L.nblk, st_in, st_out, gpost, x->stream); }
   return launch_status();
+}
+
+bool sort_due(const ddm_ctx* x, int64_t step) {
+  const int R = x->cfg.sort_every;
+  return x->need_sort || (R > 0 && step % R == 0);
 }
 
 }  // namespace
@@ -455,6 +564,7 @@ ddm_status ddm_init_state(ddm_ctx* x, const void* x0_dev) {
   x->initialised = true;
   x->recorded = false;
   x->loss_ready = false;
+  x->need_sort = true;
   return launch_status();
 }
 
@@ -465,7 +575,13 @@ ddm_status ddm_step(ddm_ctx* x, int32_t n_steps) {
   if (x->cfg.shovel && x->steps + n_steps > x->cfg.max_steps)
     return fail(DDM_EINVAL, "steps beyond max_steps (the pose table length)");
   for (int i = 0; i < n_steps; ++i) {
-    const ddm_status s = forward_step(x, x->steps, x->at(x->L.cur), x->at(x->L.cur), x->at(x->L.grid_pre), x->at(x->L.grid_post));
+    if (sort_due(x, x->steps)) {
+      const ddm_status s = bin_state(x, x->at(x->L.cur), x->at<uint32_t>(x->L.pid), nullptr, nullptr, nullptr);
+      if (s != DDM_OK) return s;
+      x->need_sort = false;
+    }
+    const ddm_status s = forward_step(x, x->steps, x->tiles(), x->at(x->L.cur), x->at(x->L.cur), x->at(x->L.grid_pre),
+                                      x->at(x->L.grid_post));
     if (s != DDM_OK) return s;
     ++x->steps;
   }
@@ -481,11 +597,23 @@ ddm_status ddm_rollout(ddm_ctx* x, int32_t n_steps) {
   if (x->steps + n_steps > x->cfg.max_steps) return fail(DDM_EINVAL, "rollout longer than max_steps");
   const int K = x->L.K;
   const int64_t k0 = x->steps;
+  x->rec_sorted.assign((size_t)n_steps, 0);
   for (int i = 0; i < n_steps; ++i) {
-    if (i % K == 0)
+    // Checkpoints hold the state before the binning of their step; every
+    // checkpointed step re-bins, so a replayed segment needs nothing older.
+    if (i % K == 0) {
       DDM_HIP(hipMemcpyAsync(x->at(x->L.ckpt + (size_t)(i / K) * x->L.state_bytes), x->at(x->L.cur), x->L.state_bytes,
                              hipMemcpyDeviceToDevice, x->stream));
-    const ddm_status s = forward_step(x, k0 + i, x->at(x->L.cur), x->at(x->L.cur), x->at(x->L.grid_pre), x->at(x->L.grid_post));
+      x->need_sort = true;
+    }
+    if (sort_due(x, k0 + i)) {
+      const ddm_status s = bin_state(x, x->at(x->L.cur), x->at<uint32_t>(x->L.pid), nullptr, nullptr, nullptr);
+      if (s != DDM_OK) return s;
+      x->need_sort = false;
+      x->rec_sorted[(size_t)i] = 1;
+    }
+    const ddm_status s = forward_step(x, k0 + i, x->tiles(), x->at(x->L.cur), x->at(x->L.cur), x->at(x->L.grid_pre),
+                                      x->at(x->L.grid_post));
     if (s != DDM_OK) return s;
     ++x->steps;
   }
@@ -502,8 +630,11 @@ ddm_status ddm_loss(ddm_ctx* x, const double* target_hm_dev, double* loss_dev) {
   const int npix = x->cfg.dim == 3 ? x->cfg.hm_res * x->cfg.hm_res : x->cfg.hm_res;
   DDM_HIP(hipMemcpyAsync(x->at(x->L.target), target_hm_dev, sizeof(double) * (size_t)x->n_inst * npix,
                          hipMemcpyDeviceToDevice, x->stream));
-  ddm::launch_loss(x->prec, x->kc, x->bufs(), (int)x->L.nblk, x->at(x->L.cur), x->at<uint32_t>(x->L.pid),
-                   (int)x->steps - 1, x->lossbufs(), x->stream);
+  {
+    Timed t(x, 8);
+    ddm::launch_loss(x->prec, x->kc, x->bufs(), (int)x->L.nblk, x->at(x->L.cur), x->at<uint32_t>(x->L.pid),
+                     (int)x->steps - 1, x->lossbufs(), x->stream);
+  }
   DDM_HIP(hipMemcpyAsync(loss_dev, x->at(x->L.loss), sizeof(double) * x->n_inst, hipMemcpyDeviceToDevice, x->stream));
   x->loss_ready = x->recorded && x->steps == x->rec_k0 + x->rec_n;
   return launch_status();
@@ -528,22 +659,41 @@ ddm_status ddm_backward(ddm_ctx* x, const double* dloss_dev, double* grad_dev) {
   auto slot = [&](int j) { return x->at(L.seg_state + (size_t)j * L.state_bytes); };
   auto gpre = [&](int j) { return x->at(L.seg_grid + (size_t)(2 * j) * L.grid_bytes); };
   auto gpost = [&](int j) { return x->at(L.seg_grid + (size_t)(2 * j + 1) * L.grid_bytes); };
+  auto perm = [&](int j) { return x->at<uint32_t>(L.seg_perm + sizeof(uint32_t) * (size_t)L.ntot * j); };
   for (int seg = nseg - 1; seg >= 0; --seg) {
     const int64_t s0 = (int64_t)seg * K;
     const int len = (int)std::min<int64_t>(K, n - s0);
     DDM_HIP(hipMemcpyAsync(slot(0), x->at(L.ckpt + (size_t)seg * L.state_bytes), L.state_bytes, hipMemcpyDeviceToDevice, st));
+    // Replay the segment: same binning steps as the recorded forward pass.
+    std::vector<int> tl_of(len, 0);
+    int last = 0;
     for (int j = 0; j < len; ++j) {
-      const ddm_status s = forward_step(x, k0 + s0 + j, slot(j), slot(j + 1), gpre(j), gpost(j));
+      if (x->rec_sorted[(size_t)(s0 + j)]) {
+        const ddm_status s = bin_state(x, slot(j), nullptr, perm(j),
+                                       x->at<ddm::TileRec>(L.seg_tiles + sizeof(ddm::TileRec) * L.max_chunks * j),
+                                       x->at<uint32_t>(L.seg_tcount + sizeof(uint32_t) * j));
+        if (s != DDM_OK) return s;
+        last = j;
+      }
+      tl_of[j] = last;
+      const ddm_status s = forward_step(x, k0 + s0 + j, x->seg_tiles(last), slot(j), slot(j + 1), gpre(j), gpost(j));
       if (s != DDM_OK) return s;
     }
     for (int j = len - 1; j >= 0; --j) {
-      ddm::launch_fill_zero(x->at(L.gvb), (int64_t)L.grid_bytes / esz, esz, st);
-      ddm::launch_g2p_adj(x->prec, x->kc, b, (int)L.nblk, slot(j), gpost(j), adj[cur], adj[1 - cur], x->at(L.gvb), st);
-      ddm::launch_grid_adj(x->prec, x->kc, b, (int)(k0 + s0 + j), gpre(j), x->at(L.gvb), x->at(L.gb),
-                           x->at<double>(L.pose_bar), st);
-      ddm::launch_p2g_adj(x->prec, x->kc, b, (int)L.nblk, slot(j), x->at(L.gb), adj[cur], adj[1 - cur],
-                          x->at<double>(L.pacc), st);
-      cur = 1 - cur;
+      const ddm::TileList tl = x->seg_tiles(tl_of[j]);
+      { Timed t(x, 7); ddm::launch_fill_zero(x->at(L.gvb), (int64_t)L.grid_bytes / esz, esz, st); }
+      { Timed t(x, 4); ddm::launch_g2p_adj(x->prec, x->kc, b, tl, L.nwg, slot(j), gpost(j), adj[cur], adj[1 - cur], x->at(L.gvb), st); }
+      { Timed t(x, 5); ddm::launch_grid_adj(x->prec, x->kc, b, (int)(k0 + s0 + j), gpre(j), x->at(L.gvb), x->at(L.gb),
+                                            x->at<double>(L.pose_bar), st); }
+      { Timed t(x, 6); ddm::launch_p2g_adj(x->prec, x->kc, b, (int)L.nblk, slot(j), x->at(L.gb), adj[cur], adj[1 - cur],
+                                           x->at<double>(L.pacc), st); }
+      if (x->rec_sorted[(size_t)(s0 + j)]) {
+        // the adjoint of a permutation is its inverse
+        Timed t(x, 3);
+        ddm::launch_unpermute(esz, adj[1 - cur], adj[cur], perm(j), L.rows, L.ntot, st);
+      } else {
+        cur = 1 - cur;
+      }
     }
     const ddm_status s = launch_status();
     if (s != DDM_OK) return s;
@@ -556,17 +706,33 @@ ddm_status ddm_backward(ddm_ctx* x, const double* dloss_dev, double* grad_dev) {
 
 ddm_status ddm_get_state(ddm_ctx* x, void* state_dev) {
   if (!x || !state_dev) return fail(DDM_EINVAL, "NULL argument");
-  DDM_HIP(hipMemcpyAsync(state_dev, x->at(x->L.cur), x->L.state_bytes, hipMemcpyDeviceToDevice, x->stream));
-  return DDM_OK;
+  ddm::launch_export_state(x->kc, x->bufs(), (int)x->L.nblk, x->L.rows, x->L.esz, x->at(x->L.cur), state_dev,
+                           x->at<uint32_t>(x->L.pid), x->stream);
+  return launch_status();
 }
 
 ddm_status ddm_set_state(ddm_ctx* x, const void* state_dev) {
   if (!x || !state_dev) return fail(DDM_EINVAL, "NULL argument");
   if (!x->initialised) return fail(DDM_ESTATE, "ddm_init_state first");
   DDM_HIP(hipMemcpyAsync(x->at(x->L.cur), state_dev, x->L.state_bytes, hipMemcpyDeviceToDevice, x->stream));
+  ddm::launch_reset_pid(x->bufs(), (int)x->L.nblk, x->at<uint32_t>(x->L.pid), x->stream);
   x->recorded = false;
   x->loss_ready = false;
-  return DDM_OK;
+  x->need_sort = true;
+  return launch_status();
+}
+
+ddm_status ddm_bin_keys(ddm_ctx* x, uint32_t* keys_dev, uint32_t* perm_dev) {
+  if (!x || !keys_dev || !perm_dev) return fail(DDM_EINVAL, "NULL argument");
+  if (!x->initialised) return fail(DDM_ESTATE, "ddm_init_state first");
+  const Layout& L = x->L;
+  uint32_t* keys[2] = {x->at<uint32_t>(L.keys0), x->at<uint32_t>(L.keys1)};
+  uint32_t* vals[2] = {x->at<uint32_t>(L.vals0), x->at<uint32_t>(L.vals1)};
+  ddm::launch_keys(x->prec, x->kc, x->bufs(), (int)L.nblk, x->at(L.cur), keys[0], vals[0], x->stream);
+  DDM_HIP(hipMemcpyAsync(keys_dev, keys[0], sizeof(uint32_t) * L.ntot, hipMemcpyDeviceToDevice, x->stream));
+  const int r = ddm::radix_sort(keys, vals, L.ntot, L.max_key, x->at<uint32_t>(L.hist), x->at<uint32_t>(L.sums), x->stream);
+  DDM_HIP(hipMemcpyAsync(perm_dev, vals[r], sizeof(uint32_t) * L.ntot, hipMemcpyDeviceToDevice, x->stream));
+  return launch_status();
 }
 
 ddm_status ddm_get_grid(ddm_ctx* x, void* grid_dev) {
@@ -607,6 +773,31 @@ int64_t ddm_instance_offset(const ddm_ctx* x, int32_t i) {
   return off;
 }
 
-void ddm_destroy(ddm_ctx* x) { delete x; }
+ddm_status ddm_set_timing(ddm_ctx* x, int32_t enable) {
+  if (!x) return fail(DDM_EINVAL, "NULL context");
+  DDM_HIP(hipStreamSynchronize(x->stream));
+  resolve_events(x);
+  for (int g = 0; g < 9; ++g) { x->t_ms[g] = 0.0; x->t_n[g] = 0; }
+  x->timing = enable != 0;
+  return DDM_OK;
+}
+
+ddm_status ddm_read_timing(ddm_ctx* x, int32_t group, double* total_ms, int64_t* launches) {
+  if (!x || group < 0 || group >= 9) return fail(DDM_EINVAL, "bad context or group");
+  DDM_HIP(hipStreamSynchronize(x->stream));
+  resolve_events(x);
+  if (total_ms) *total_ms = x->t_ms[group];
+  if (launches) *launches = x->t_n[group];
+  return DDM_OK;
+}
+
+void ddm_destroy(ddm_ctx* x) {
+  if (!x) return;
+  if (hipStreamSynchronize(x->stream) == hipSuccess) {
+    for (const auto& e : x->events) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
+    for (hipEvent_t e : x->pool) (void)hipEventDestroy(e);
+  }
+  delete x;
+}
 
 }  // extern "C"

@@ -181,6 +181,61 @@ def test_batched_equals_plain_f64(ddm):
         np.testing.assert_allclose(gb[i], p["grad"], rtol=1e-8, atol=1e-12 * np.abs(p["grad"]).max())
 
 
+@pytest.mark.parametrize("dim,ninst", [(3, 1), (3, 3), (2, 2)])
+def test_binning_keys_and_permutation_bit_exact(ddm, orc, dim, ninst):
+    """Cell keys and the stable sort permutation equal the oracle's, bit for bit,
+    on identical positions (several instances, ragged counts)."""
+    ws = []
+    for i in range(ninst):
+        w = W.dig_3d(ppc=1) if dim == 3 else W.column_2d()
+        w.seed = 40 + i
+        if i:
+            w.bed_hi = tuple(h - i for h in w.bed_hi)
+        ws.append(w)
+    cfgs = [ddm.from_workload(w, max_steps=4) for w in ws]
+    sim = ddm.Simulator(cfgs[0][0], [c[1] for c in cfgs])
+    xs = [W.bed_positions(w) for w in ws]
+    _log(f"case binning dim{dim} inst{ninst} N={[len(x) for x in xs]}")
+    sim.init_state(np.concatenate(xs))
+    keys, perm = sim.bin_keys()
+    n_grid = ws[0].n_grid
+    cells = n_grid ** dim
+    inst = np.concatenate([np.full(len(x), i, np.int32) for i, x in enumerate(xs)])
+    okeys, operm = orc.bin_keys(np.concatenate(xs), n_grid, 4, inst)
+    # GPU keys of live slots, in particle order
+    live = np.concatenate([np.arange(o, o + n) for o, n in zip(sim.offsets, sim.counts)])
+    gk = keys[live].astype(np.int64) - inst.astype(np.int64) * (cells + 1)
+    ok = okeys.astype(np.int64) - inst.astype(np.int64) * cells
+    assert np.array_equal(gk, ok)
+    # permutation restricted to live slots, mapped to particle indices
+    slot_to_pid = np.full(len(keys), -1, np.int64)
+    slot_to_pid[live] = np.arange(len(live))
+    gp = slot_to_pid[perm.astype(np.int64)]
+    gp = gp[gp >= 0]
+    assert np.array_equal(gp, operm.astype(np.int64))
+
+
+@pytest.mark.parametrize("sort_every", [0, 1, 3])
+def test_sort_interval_does_not_change_results(ddm, orc, sort_every):
+    """Forward state and reverse-pass gradient are the same for any binning
+    interval (the reverse pass carries adjoints back through each sort)."""
+    w = W.tiny(3, shovel=True, steps=40)
+    tgt = W.target_heightmap(w)
+    _log(f"case sort_every={sort_every}")
+    cfg, inst = ddm.from_workload(w, max_steps=40, checkpoint_every=16, sort_every=sort_every)
+    sim = ddm.Simulator(cfg, [inst])
+    sim.init_state(W.bed_positions(w))
+    sim.rollout(40)
+    loss = float(sim.loss(tgt[None])[0])
+    grad = sim.backward()[0].cpu().numpy()
+    r = run_oracle(orc, w, 40, target=tgt, grad=True)
+    e = field_errors(sim.packed_state(0), r["state"], 3)
+    assert max(e.values()) < 1e-9, e
+    assert abs(loss - r["loss"]) <= 1e-10 * abs(r["loss"])
+    rel = np.abs(grad - r["grad"]) / np.maximum(np.abs(r["grad"]), 1e-9 * np.abs(r["grad"]).max())
+    assert np.all(rel < 1e-6), rel
+
+
 def test_domain_error_is_reported(ddm):
     w = W.tiny(3)
     x0 = W.bed_positions(w)
