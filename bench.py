@@ -37,7 +37,7 @@ METRIC = "particle-steps/s fwd+bwd, batched vs plain, at grad rel-err <=1e-3 vs 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="sysid64", choices=["sysid64", "dig3d_bwd"])
     ap.add_argument("--sub-steps", type=int, default=None, help="override rollout length (testing only)")
@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-gate", action="store_true")
     ap.add_argument("--sort-every", type=int, default=8)
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also run a plain 1 GiB device copy (calibrates the HBM byte counters)")
     return ap.parse_args()
 
 
@@ -100,6 +102,47 @@ def algorithmic_bytes_p2g(ws, b=4, d=3):
     return n * per_particle + nodes * (d + 1) * b
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "p2g_sysid64_traffic.txt")
+KERNEL_SRC = os.path.join(ROOT, "paper_2510_17335_amd", "csrc", "ddm_kernels.hip")
+
+
+def measured_traffic():
+    """HBM bytes per P2G launch from the committed counter summary (FETCH_SIZE and
+    WRITE_SIZE per dispatch, each scaled by what the same counter reads for a
+    plain copy of known size).  None when the summary is absent or the kernel
+    source has changed since the counters were taken."""
+    import hashlib
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    rec = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            rec[k.strip()] = v.strip()
+    try:
+        sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+        if rec.get("kernel_source_sha256") != sha:
+            return None
+        copy_bytes = float(rec["copy_bytes"])
+        f_fac = copy_bytes / (float(rec["copy_fetch_kib"]) * 1024)
+        w_fac = copy_bytes / (float(rec["copy_write_kib"]) * 1024)
+        return (float(rec["p2g_fetch_kib"]) * f_fac + float(rec["p2g_write_kib"]) * w_fac) * 1024
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_calibration(torch):
+    """A plain device copy of 1 GiB (read 1 GiB, write 1 GiB), three times."""
+    n = 1 << 28
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+    print(f"# copy calibration: 3 x {4 * n} bytes read + written (elementwise neg)", flush=True)
+    del src, dst
+
+
 def cpu_baseline(ws):
     """The FP64 oracle (single thread) with 7 forward-mode tangents on the
     smallest instance of the batch, 20 sub-steps: fwd+bwd-equivalent rate."""
@@ -126,6 +169,8 @@ def main():
     import paper_2510_17335_amd as ddm
     assert torch.cuda.is_available(), "needs a GPU"
     dev = torch.device("cuda:0")
+    if args.copy_calib:
+        copy_calibration(torch)
     ws, wname = build_batch(args)
     print(f"# workload {wname}: {len(ws)} instances, {sum(w.n_particles for w in ws)} particles", flush=True)
 
@@ -214,7 +259,8 @@ def main():
         "grad_gate": gate,
         "kernel_ms": breakdown,
         "roofline": {"bound": "hbm", "kernel": "p2g", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
+                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": measured_traffic(),
+                     "algorithmic_bytes": per_launch_bytes,
                      "dominant_group": dom},
         "cpu_baseline": cpu,
     }
