@@ -126,6 +126,18 @@ __device__ __forceinline__ int64_t node_of(const int base[3], int o0, int o1, in
 
 template <typename T> __device__ __forceinline__ T ld(const void* p, int64_t i) { return static_cast<const T*>(p)[i]; }
 
+// One grid node record (4 values) in one vector load: 16 B for float, two
+// 16 B loads for double (node records are 4-element aligned).
+template <typename T> struct Node4 { T v[4]; };
+__device__ __forceinline__ Node4<float> ld_node(const float* p) {
+  const float4 q = *reinterpret_cast<const float4*>(p);
+  return Node4<float>{{q.x, q.y, q.z, q.w}};
+}
+__device__ __forceinline__ Node4<double> ld_node(const double* p) {
+  const double2 a = reinterpret_cast<const double2*>(p)[0], b = reinterpret_cast<const double2*>(p)[1];
+  return Node4<double>{{a.x, a.y, b.x, b.y}};
+}
+
 // Wave64 + block reduction of one double, added atomically to *dst by one lane.
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -239,13 +251,13 @@ template <int D> struct Win {
   }
 };
 
-// Slot handled by thread t in a chunk of cnt sorted particles: for full
-// chunks the lanes of a wave are spread over cells (stride 8 in the cell
-// order, about one particle per cell) so that LDS atomics of one instruction
-// rarely share an address.
-__device__ __forceinline__ int chunk_slot(int t, int cnt) {
-  return cnt == kBlock ? ((t & 31) << 3) + (t >> 5) : t;
-}
+// Particle slots of a chunk of cnt sorted particles, one wave-iteration at a
+// time: wave w of the workgroup takes iterations q = w, w + 4, ... < nq, and
+// lane l of iteration q takes slot l * nq + q.  (l, q) -> slot is a bijection
+// onto [0, 64 nq) >= [0, cnt), and the 64 lanes of one iteration sit about
+// cnt / 64 slots apart in the cell order, i.e. about one particle per cell,
+// so LDS atomics of one instruction rarely share an address.
+__device__ __forceinline__ int chunk_iters(int cnt) { return (kBlock / 64) * ((cnt + kBlock - 1) / kBlock); }
 
 // Per-particle constitutive update and P2G contributions; emit(node offsets,
 // weight, values) receives the D+1 scattered values of each stencil node.
@@ -288,9 +300,10 @@ __device__ __forceinline__ bool p2g_particle(const KCfg& c, const Bufs& b, const
   return true;
 }
 
-// P2G over occupied tiles: one workgroup per tile (grid-stride over the tile
-// list), contributions accumulated with LDS atomics in a kWin^D window and
-// flushed to the grid once per tile; particles outside the window (drifted
+// P2G over occupied tiles: one workgroup per chunk of up to kChunk particles
+// of a tile (grid-stride over the tile list),
+// contributions accumulated with LDS atomics in a kWin^D window and flushed to
+// the grid once per chunk; particles outside the window (drifted
 // more than one cell since binning) add to the grid directly.
 template <typename T, int D>
 __global__ void __launch_bounds__(kBlock) k_p2g(KCfg c, Bufs b, TileList tl, const void* st_in, void* st_out,
@@ -308,13 +321,14 @@ __global__ void __launch_bounds__(kBlock) k_p2g(KCfg c, Bufs b, TileList tl, con
     T* g = grid + I.goff * kNodeVals;
     for (int i = threadIdx.x; i < WS * kNodeVals; i += kBlock) win[i] = 0.0;
     __syncthreads();
-    {
-      const int cnt = (int)(tr.end - tr.start);
-      if (threadIdx.x >= cnt) goto flush;
-      const int64_t p = (int64_t)tr.start + chunk_slot(threadIdx.x, cnt);
+    const int cnt = (int)(tr.end - tr.start), nq = chunk_iters(cnt);
+    for (int q = threadIdx.x >> 6; q < nq; q += kBlock / 64) {
+      const int slot = (threadIdx.x & 63) * nq + q;
+      if (slot >= cnt) continue;
+      const int64_t p = (int64_t)tr.start + slot;
       Stencil<T, D> S;
       T A[3][3], vel[3];
-      if (!p2g_particle<T, D>(c, b, I, inst, si, so, p, S, A, vel)) goto flush;
+      if (!p2g_particle<T, D>(c, b, I, inst, si, so, p, S, A, vel)) continue;
       const T mp = T(I.mp);
       int loc[3] = {0, 0, 0};
       bool inwin = true;
@@ -352,7 +366,6 @@ __global__ void __launch_bounds__(kBlock) k_p2g(KCfg c, Bufs b, TileList tl, con
             }
           }
     }
-  flush:
     __syncthreads();
     for (int i = threadIdx.x; i < Win<D>::nodes; i += kBlock) {
       int l[3];
@@ -491,10 +504,10 @@ __global__ void __launch_bounds__(kBlock) k_g2p(KCfg c, Bufs b, const void* st_i
         T w = T(1), r[3];
 #pragma unroll
         for (int a = 0; a < D; ++a) { w *= S.w[a][off[a]]; r[a] = (T(off[a]) - S.f[a]) * dx; }
-        const T* nd = g + node_of<D>(S.base, o0, o1, o2, c.n) * kNodeVals;
+        const Node4<T> nd = ld_node(g + node_of<D>(S.base, o0, o1, o2, c.n) * kNodeVals);
 #pragma unroll
         for (int a = 0; a < D; ++a) {
-          const T vi = nd[a];
+          const T vi = nd.v[a];
           vn[a] += w * vi;
 #pragma unroll
           for (int bb = 0; bb < D; ++bb) Cn[a][bb] += (Dk * w) * vi * r[bb];
@@ -846,12 +859,13 @@ __global__ void __launch_bounds__(kBlock) k_g2p_adj(KCfg c, Bufs b, TileList tl,
     T* gbv = gvb + I.goff * kNodeVals;
     for (int i = threadIdx.x; i < WS * D; i += kBlock) win[i] = 0.0;
     __syncthreads();
-    {
-      const int cnt = (int)(tr.end - tr.start);
-      if (threadIdx.x >= cnt) goto flush;
-      const int64_t p = (int64_t)tr.start + chunk_slot(threadIdx.x, cnt);
+    const int cnt = (int)(tr.end - tr.start), nq = chunk_iters(cnt);
+    for (int q = threadIdx.x >> 6; q < nq; q += kBlock / 64) {
+      const int slot = (threadIdx.x & 63) * nq + q;
+      if (slot >= cnt) continue;
+      const int64_t p = (int64_t)tr.start + slot;
       Stencil<T, D> S;
-      if (!make_stencil<T, D>(st, p, c, S)) goto flush;
+      if (!make_stencil<T, D>(st, p, c, S)) continue;
       T xb[3], vb[3], Cb[3][3];
 #pragma unroll
       for (int a = 0; a < D; ++a) {
@@ -864,9 +878,11 @@ __global__ void __launch_bounds__(kBlock) k_g2p_adj(KCfg c, Bufs b, TileList tl,
       bool inwin = true;
 #pragma unroll
       for (int a = 0; a < D; ++a) { loc[a] = S.base[a] - org[a]; inwin &= loc[a] >= 0 && loc[a] <= kWin - 3; }
-#pragma unroll
+      // Offsets 0 and 1 stay loops: unrolling all 27 nodes hoists their loads
+      // and leaves one wave per SIMD (256 VGPRs); this way 112.
+#pragma unroll 1
       for (int o0 = 0; o0 < 3; ++o0)
-#pragma unroll
+#pragma unroll 1
         for (int o1 = 0; o1 < 3; ++o1)
 #pragma unroll
           for (int o2 = 0; o2 < (D == 3 ? 3 : 1); ++o2) {
@@ -884,9 +900,10 @@ __global__ void __launch_bounds__(kBlock) k_g2p_adj(KCfg c, Bufs b, TileList tl,
               w *= S.w[a][off[a]];
             }
             const int64_t nd = node_of<D>(S.base, o0, o1, o2, c.n) * kNodeVals;
+            const Node4<T> gv = ld_node(g + nd);
             T vi[3], Cr[3];
 #pragma unroll
-            for (int a = 0; a < D; ++a) vi[a] = g[nd + a];
+            for (int a = 0; a < D; ++a) vi[a] = gv.v[a];
             T sdot = T(0);
 #pragma unroll
             for (int a = 0; a < D; ++a) {
@@ -910,7 +927,6 @@ __global__ void __launch_bounds__(kBlock) k_g2p_adj(KCfg c, Bufs b, TileList tl,
 #pragma unroll
       for (int a = 0; a < D; ++a) ac.x(a, p) = xb[a];
     }
-  flush:
     __syncthreads();
     for (int i = threadIdx.x; i < Win<D>::nodes; i += kBlock) {
       int l[3];
@@ -1107,10 +1123,11 @@ __global__ void __launch_bounds__(kBlock) k_p2g_adj_gather(KCfg c, Bufs b, const
               w *= S.w[a][off[a]];
             }
             const int64_t nd = node_of<D>(S.base, o0, o1, o2, c.n) * kNodeVals;
+            const Node4<T> gn = ld_node(g + nd);
             T mvb[3];
 #pragma unroll
-            for (int a = 0; a < D; ++a) mvb[a] = g[nd + a];
-            const T mb = g[nd + 3];
+            for (int a = 0; a < D; ++a) mvb[a] = gn.v[a];
+            const T mb = gn.v[3];
             // value scattered to this node: m_p w and w (m_p v + A r)
             T sc = mp * mb;
             T vm = T(0);

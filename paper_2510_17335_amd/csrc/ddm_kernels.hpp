@@ -11,6 +11,12 @@ constexpr int kBlock = 256;          // particle kernels: threads per block, and
 constexpr int kNodeVals = 4;         // node record: mv[0..2] (or v), m
 constexpr int kTile = 4;             // binning tile edge in cells
 constexpr int kWin = kTile + 4;      // LDS window edge in nodes: tile + stencil + 1-cell drift each side
+#ifndef DDM_CHUNK
+#define DDM_CHUNK 1024
+#endif
+constexpr int kChunk = DDM_CHUNK;    // particles per tile-list record (a multiple of kBlock); larger
+                                     // tiles are split, so one workgroup's window flush covers
+                                     // up to kChunk particles
 
 // An occupied tile: slots [start, end) of the sorted state, global tile id.
 struct TileRec { uint32_t start, end, tile; };

@@ -298,8 +298,8 @@ __global__ void k_tile_bounds(KCfg c, const uint32_t* keys, int tshift, uint32_t
   if (tn != t) tend[t] = (uint32_t)(j + 1);
 }
 
-// One record per chunk of at most kBlock particles of an occupied tile, so
-// that a workgroup handles one chunk and large tiles spread over several.
+// One record per chunk of at most kChunk particles of an occupied tile, so
+// that a workgroup handles one chunk and very full tiles spread over several.
 __global__ void k_tile_list(int64_t total_tiles, const uint32_t* tstart, const uint32_t* tend, TileRec* list,
                             uint32_t* count) {
   const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -307,11 +307,11 @@ __global__ void k_tile_list(int64_t total_tiles, const uint32_t* tstart, const u
   const uint32_t e = tend[t];
   if (e == 0u) return;
   const uint32_t s = tstart[t];
-  const uint32_t nch = (e - s + kBlock - 1) / kBlock;
+  const uint32_t nch = (e - s + kChunk - 1) / kChunk;
   const uint32_t idx = atomicAdd(count, nch);
   for (uint32_t k = 0; k < nch; ++k) {
-    const uint32_t a = s + k * kBlock;
-    list[idx + k] = TileRec{a, min(e, a + (uint32_t)kBlock), (uint32_t)t};
+    const uint32_t a = s + k * kChunk;
+    list[idx + k] = TileRec{a, min(e, a + (uint32_t)kChunk), (uint32_t)t};
   }
 }
 
