@@ -22,6 +22,15 @@ template <> struct Lim<double> {
 template <typename T> __device__ __forceinline__ T dsqrt(T x) { return sqrt(x); }
 template <typename T> __device__ __forceinline__ T dabs(T x) { return x < T(0) ? -x : x; }
 
+// Reciprocal and reciprocal square root: the hardware approximations
+// (v_rcp_f32, v_rsq_f32, about 1 ulp) in float, exact division in double.
+template <typename T> __device__ __forceinline__ T frcp(T x);
+template <> __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+template <> __device__ __forceinline__ double frcp(double x) { return 1.0 / x; }
+template <typename T> __device__ __forceinline__ T frsq(T x);
+template <> __device__ __forceinline__ float frsq(float x) { return __builtin_amdgcn_rsqf(x); }
+template <> __device__ __forceinline__ double frsq(double x) { return 1.0 / sqrt(x); }
+
 // Sigma below this is clamped before the logarithm (ln S must exist).
 template <typename T> __device__ __forceinline__ T sigma_min() { return T(1e-6); }
 
@@ -52,9 +61,9 @@ __device__ __forceinline__ void jacobi_sym(T a[3][3], T V[3][3], T ev[3]) {
       const int q = pq == 0 ? 1 : 2;
       const T apq = a[p][q];
       if (apq == T(0)) continue;
-      const T theta = (a[q][q] - a[p][p]) / (T(2) * apq);
-      const T t = (theta >= T(0) ? T(1) : T(-1)) / (dabs(theta) + dsqrt(theta * theta + T(1)));
-      const T c = T(1) / dsqrt(t * t + T(1));
+      const T theta = (a[q][q] - a[p][p]) * frcp(T(2) * apq);
+      const T t = (theta >= T(0) ? T(1) : T(-1)) * frcp(dabs(theta) + dsqrt(theta * theta + T(1)));
+      const T c = frsq(t * t + T(1));
       const T sn = t * c;
       a[p][p] -= t * apq;
       a[q][q] += t * apq;
@@ -109,8 +118,9 @@ __device__ __forceinline__ void dp_forward(const T eps[3], T mu, T lam, T alpha,
 #pragma unroll
   for (int i = 0; i < D; ++i) { o.eps[i] = eps[i]; o.tr += o.eps[i]; }
   T n2 = T(0), dev[3];
+  const T mean = o.tr * T(1.0 / D);
 #pragma unroll
-  for (int i = 0; i < D; ++i) { dev[i] = o.eps[i] - o.tr / T(D); n2 += dev[i] * dev[i]; }
+  for (int i = 0; i < D; ++i) { dev[i] = o.eps[i] - mean; n2 += dev[i] * dev[i]; }
   o.nrm = n2 > T(0) ? dsqrt(n2) : T(0);
   o.stiff = T(D) * lam + T(2) * mu;
   o.beta = T(0);
@@ -118,11 +128,11 @@ __device__ __forceinline__ void dp_forward(const T eps[3], T mu, T lam, T alpha,
   const bool tension = (kc == T(0)) ? (o.tr > T(0)) : (alpha * o.stiff * o.tr > kc);
   if (tension) {
     o.cs = 1;
-    o.apex = kc / (T(D) * alpha * o.stiff);
+    o.apex = kc * frcp(T(D) * alpha * o.stiff);
 #pragma unroll
     for (int i = 0; i < D; ++i) o.ep[i] = o.apex;
   } else {
-    o.beta = (alpha * o.stiff * o.tr - kc) / (T(2) * mu);
+    o.beta = (alpha * o.stiff * o.tr - kc) * frcp(T(2) * mu);
     const T dgam = o.nrm + o.beta;
     if (!(dgam > T(0))) {
       o.cs = 2;
@@ -130,8 +140,9 @@ __device__ __forceinline__ void dp_forward(const T eps[3], T mu, T lam, T alpha,
       for (int i = 0; i < D; ++i) o.ep[i] = o.eps[i];
     } else {
       o.cs = 3;
+      const T f = dgam * frcp(o.nrm);
 #pragma unroll
-      for (int i = 0; i < D; ++i) o.ep[i] = o.eps[i] - dgam * dev[i] / o.nrm;
+      for (int i = 0; i < D; ++i) o.ep[i] = o.eps[i] - f * dev[i];
     }
   }
   T tre = T(0);
@@ -168,41 +179,42 @@ __device__ __forceinline__ void dp_backward(const DP<T>& o, const T s[3], T mu, 
 #pragma unroll
       for (int i = 0; i < D; ++i) ab += epb[i];
       // apex = kc / (D alpha stiff)
-      kcb += ab / (T(D) * alpha * o.stiff);
-      alb -= ab * o.apex / alpha;
-      const T sb = -ab * o.apex / o.stiff;
+      kcb += ab * frcp(T(D) * alpha * o.stiff);
+      alb -= ab * o.apex * frcp(alpha);
+      const T sb = -ab * o.apex * frcp(o.stiff);
       lamb += T(D) * sb;
       mub += T(2) * sb;
     }
   } else {
     // eps' = (tr/D) 1 - beta n
     T nvec[3], trb = T(0), betab = T(0);
+    const T inrm = frcp(o.nrm), mean = o.tr * T(1.0 / D);
 #pragma unroll
     for (int i = 0; i < D; ++i) {
-      nvec[i] = (o.eps[i] - o.tr / T(D)) / o.nrm;
-      trb += epb[i] / T(D);
+      nvec[i] = (o.eps[i] - mean) * inrm;
+      trb += epb[i] * T(1.0 / D);
       betab -= epb[i] * nvec[i];
     }
     T nb[3], nbn = T(0);
 #pragma unroll
     for (int i = 0; i < D; ++i) { nb[i] = -o.beta * epb[i]; nbn += nb[i] * nvec[i]; }
     // beta = (alpha stiff tr - kc) / (2 mu)
-    const T inv2mu = T(1) / (T(2) * mu);
+    const T inv2mu = frcp(T(2) * mu);
     trb += betab * alpha * o.stiff * inv2mu;
     alb += betab * o.stiff * o.tr * inv2mu;
     kcb -= betab * inv2mu;
     const T sb = betab * alpha * o.tr * inv2mu;
-    mub += -betab * o.beta / mu + T(2) * sb;
+    mub += T(2) * (sb - betab * o.beta * inv2mu);
     lamb += T(D) * sb;
     // n = dev / |dev|, dev = eps - tr/D
     T devb[3], devbs = T(0);
 #pragma unroll
-    for (int i = 0; i < D; ++i) { devb[i] = (nb[i] - nbn * nvec[i]) / o.nrm; devbs += devb[i]; }
+    for (int i = 0; i < D; ++i) { devb[i] = (nb[i] - nbn * nvec[i]) * inrm; devbs += devb[i]; }
 #pragma unroll
-    for (int i = 0; i < D; ++i) eb[i] = devb[i] - devbs / T(D) + trb;
+    for (int i = 0; i < D; ++i) eb[i] = devb[i] - devbs * T(1.0 / D) + trb;
   }
 #pragma unroll
-  for (int i = 0; i < D; ++i) sbar[i] = eb[i] / s[i];
+  for (int i = 0; i < D; ++i) sbar[i] = eb[i] * frcp(s[i]);
 }
 
 // Divided differences of g and h across a pair of singular values, without
@@ -211,11 +223,12 @@ __device__ __forceinline__ void dp_backward(const DP<T>& o, const T s[3], T mu, 
 // ds = s_i - s_j is passed in, computed from s - 1 without cancellation.
 template <typename T>
 __device__ __forceinline__ void divided(const DP<T>& o, T mu, T ds, T sj, T gj, T& ddg, T& ddh, T& y) {
-  const T k = o.cs == 2 ? T(1) : (o.cs == 1 ? T(0) : -o.beta / o.nrm);
-  const T de = log1p(ds / sj);
-  const T dl = ds != T(0) ? de / ds : T(1) / sj;       // (eps_i - eps_j) / (s_i - s_j)
+  const T k = o.cs == 2 ? T(1) : (o.cs == 1 ? T(0) : -o.beta * frcp(o.nrm));
+  const T isj = frcp(sj);
+  const T de = log1p(ds * isj);
+  const T dl = ds != T(0) ? de * frcp(ds) : isj;        // (eps_i - eps_j) / (s_i - s_j)
   y = k * de;                                            // eps'_i - eps'_j
-  const T em1 = y != T(0) ? expm1(y) / y : T(1);
+  const T em1 = y != T(0) ? expm1(y) * frcp(y) : T(1);
   ddg = gj * em1 * k * dl;
   ddh = T(2) * mu * k * dl;
 }
@@ -271,19 +284,21 @@ __device__ __forceinline__ void constit_forward(const T G[3][3], T mu, T lam, T 
       c.clamped[i] = true; ++c.nclamp;
     } else {
       c.s[i] = dsqrt(T(1) + l);
-      c.sm1[i] = l / (T(1) + c.s[i]);
+      c.sm1[i] = l * frcp(T(1) + c.s[i]);
       c.eps[i] = T(0.5) * log1p(l);
     }
   }
   // R - I = (G - (S - I)) S^-1
-  T GmS[3][3], Sinv[3][3];
+  T GmS[3][3], Sinv[3][3], is[3];
+#pragma unroll
+  for (int k = 0; k < D; ++k) is[k] = frcp(c.s[k]);
 #pragma unroll
   for (int i = 0; i < D; ++i)
 #pragma unroll
     for (int j = 0; j < D; ++j) {
       T smi = T(0), si = T(0);
 #pragma unroll
-      for (int k = 0; k < D; ++k) { smi += c.V[i][k] * c.sm1[k] * c.V[j][k]; si += c.V[i][k] * c.V[j][k] / c.s[k]; }
+      for (int k = 0; k < D; ++k) { smi += c.V[i][k] * c.sm1[k] * c.V[j][k]; si += c.V[i][k] * c.V[j][k] * is[k]; }
       GmS[i][j] = G[i][j] - smi;
       Sinv[i][j] = si;
     }
@@ -313,18 +328,19 @@ __device__ __forceinline__ void constit_outputs(const Constit<T, D>& c, T Gn[3][
   T em[3], SpmI[3][3];
 #pragma unroll
   for (int k = 0; k < D; ++k) em[k] = expm1(c.dp.ep[k]);
+  // both are symmetric: the upper triangle is computed and mirrored
 #pragma unroll
   for (int i = 0; i < D; ++i)
 #pragma unroll
-    for (int j = 0; j < D; ++j) {
+    for (int j = i; j < D; ++j) {
       T a = T(0), b = T(0);
 #pragma unroll
       for (int k = 0; k < D; ++k) {
         a += c.V[i][k] * em[k] * c.V[j][k];
         b += c.U[i][k] * c.dp.h[k] * c.U[j][k];
       }
-      SpmI[i][j] = a;
-      tau[i][j] = b;
+      SpmI[i][j] = SpmI[j][i] = a;
+      tau[i][j] = tau[j][i] = b;
     }
 #pragma unroll
   for (int i = 0; i < D; ++i)
@@ -384,9 +400,9 @@ __device__ __forceinline__ void constit_backward(const Constit<T, D>& c, T mu, T
     for (int j = i + 1; j < D; ++j) {
       T ddg, ddh, y;
       divided<T>(c.dp, mu, c.sm1[i] - c.sm1[j], c.s[j], c.dp.g[j], ddg, ddh, y);
-      const T sum = c.s[i] + c.s[j];
-      const T cg = (c.dp.g[i] + c.dp.g[j]) / sum;
-      const T ch = -T(2) * mu * y / sum;
+      const T isum = frcp(c.s[i] + c.s[j]);
+      const T cg = (c.dp.g[i] + c.dp.g[j]) * isum;
+      const T ch = -T(2) * mu * y * isum;
       const T tsym = Tb[i][j] + Tb[j][i];
       const T symb = ddg * (Gb[i][j] + Gb[j][i]) + ddh * tsym;
       const T skwb = cg * (Gb[i][j] - Gb[j][i]) + ch * tsym;

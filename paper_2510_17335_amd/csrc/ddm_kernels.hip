@@ -126,6 +126,12 @@ __device__ __forceinline__ int64_t node_of(const int base[3], int o0, int o1, in
 
 template <typename T> __device__ __forceinline__ T ld(const void* p, int64_t i) { return static_cast<const T*>(p)[i]; }
 
+// Row of entry (a, b) of a symmetric D x D matrix stored as its upper triangle.
+template <int D> __device__ __forceinline__ int sym_row(int a, int b) {
+  const int i = a < b ? a : b, j = a < b ? b : a;
+  return D == 3 ? (i == 0 ? j : (i == 1 ? 2 + j : 5)) : i + j;
+}
+
 // One grid node record (4 values) in one vector load: 16 B for float, two
 // 16 B loads for double (node records are 4-element aligned).
 template <typename T> struct Node4 { T v[4]; };
@@ -264,7 +270,7 @@ __device__ __forceinline__ int chunk_iters(int cnt) { return (kBlock / 64) * ((c
 template <typename T, int D>
 __device__ __forceinline__ bool p2g_particle(const KCfg& c, const Bufs& b, const InstDev& I, int inst,
                                              const P<T, D>& si, const P<T, D>& so, int64_t p, Stencil<T, D>& S,
-                                             T (&A)[3][3], T (&vel)[3]) {
+                                             T (&A)[3][3], T (&vel)[3], T* tau_out) {
   const T dt = T(I.dt), mp = T(I.mp);
   T Cm[3][3], Gm[3][3], Ft[3][3];
 #pragma unroll
@@ -289,6 +295,12 @@ __device__ __forceinline__ bool p2g_particle(const KCfg& c, const Bufs& b, const
   for (int a = 0; a < D; ++a)
 #pragma unroll
     for (int bb = 0; bb < D; ++bb) so.G(a, bb, p) = Fn[a][bb];
+  if (tau_out) {
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+      for (int bb = a; bb < D; ++bb) tau_out[(int64_t)sym_row<D>(a, bb) * c.ntot + p] = tau[a][bb];
+  }
   const T k_str = -dt * T(I.Vp) * T(4.0 * c.inv_dx * c.inv_dx);
 #pragma unroll
   for (int a = 0; a < D; ++a)
@@ -307,7 +319,7 @@ __device__ __forceinline__ bool p2g_particle(const KCfg& c, const Bufs& b, const
 // more than one cell since binning) add to the grid directly.
 template <typename T, int D>
 __global__ void __launch_bounds__(kBlock) k_p2g(KCfg c, Bufs b, TileList tl, const void* st_in, void* st_out,
-                                                T* __restrict__ grid) {
+                                                T* __restrict__ grid, T* __restrict__ tau_out) {
   __shared__ double win[Win<D>::stride * kNodeVals];
   const uint32_t ntiles = *tl.count;
   const P<T, D> si = pv<T, D>(st_in, c.ntot), so = pv<T, D>(st_out, c.ntot);
@@ -328,7 +340,7 @@ __global__ void __launch_bounds__(kBlock) k_p2g(KCfg c, Bufs b, TileList tl, con
       const int64_t p = (int64_t)tr.start + slot;
       Stencil<T, D> S;
       T A[3][3], vel[3];
-      if (!p2g_particle<T, D>(c, b, I, inst, si, so, p, S, A, vel)) continue;
+      if (!p2g_particle<T, D>(c, b, I, inst, si, so, p, S, A, vel, tau_out)) continue;
       const T mp = T(I.mp);
       int loc[3] = {0, 0, 0};
       bool inwin = true;
@@ -384,13 +396,13 @@ __global__ void __launch_bounds__(kBlock) k_p2g(KCfg c, Bufs b, TileList tl, con
 }
 
 void launch_p2g(int prec, const KCfg& c, const Bufs& b, const TileList& tl, int nwg, const void* st_in, void* st_out,
-                void* grid, hipStream_t s) {
+                void* grid, void* tau_out, hipStream_t s) {
   if (prec == 0) {
-    if (c.dim == 3) hipLaunchKernelGGL((k_p2g<float, 3>), dim3(nwg), dim3(kBlock), 0, s, c, b, tl, st_in, st_out, (float*)grid);
-    else hipLaunchKernelGGL((k_p2g<float, 2>), dim3(nwg), dim3(kBlock), 0, s, c, b, tl, st_in, st_out, (float*)grid);
+    if (c.dim == 3) hipLaunchKernelGGL((k_p2g<float, 3>), dim3(nwg), dim3(kBlock), 0, s, c, b, tl, st_in, st_out, (float*)grid, (float*)tau_out);
+    else hipLaunchKernelGGL((k_p2g<float, 2>), dim3(nwg), dim3(kBlock), 0, s, c, b, tl, st_in, st_out, (float*)grid, (float*)tau_out);
   } else {
-    if (c.dim == 3) hipLaunchKernelGGL((k_p2g<double, 3>), dim3(nwg), dim3(kBlock), 0, s, c, b, tl, st_in, st_out, (double*)grid);
-    else hipLaunchKernelGGL((k_p2g<double, 2>), dim3(nwg), dim3(kBlock), 0, s, c, b, tl, st_in, st_out, (double*)grid);
+    if (c.dim == 3) hipLaunchKernelGGL((k_p2g<double, 3>), dim3(nwg), dim3(kBlock), 0, s, c, b, tl, st_in, st_out, (double*)grid, (double*)tau_out);
+    else hipLaunchKernelGGL((k_p2g<double, 2>), dim3(nwg), dim3(kBlock), 0, s, c, b, tl, st_in, st_out, (double*)grid, (double*)tau_out);
   }
 }
 
@@ -1044,7 +1056,7 @@ void launch_grid_adj(int prec, const KCfg& c, const Bufs& b, int step, const voi
 // Adjoint of P2G and of the constitutive update, in two kernels so that the
 // 27-node gather and the SVD-frame adjoint do not hold registers at the same
 // time.
-//  k_p2g_adj_gather: recomputes the stress and A = k tau + m_p C, gathers the
+//  k_p2g_adj_gather: rebuilds A = k tau + m_p C from the stored stress, gathers the
 //    grid adjoints (m bar, mv bar) over the stencil and writes x bar (adding
 //    to the G2P part already there), v bar, and A bar into the C bar rows;
 //    the density adjoint V_p (m_p bar + A bar : C) is block-reduced.
@@ -1071,8 +1083,8 @@ __device__ __forceinline__ void ftmp_of(const P<T, D>& st, int64_t p, T dt, T Cm
 }
 
 template <typename T, int D>
-__global__ void __launch_bounds__(kBlock) k_p2g_adj_gather(KCfg c, Bufs b, const void* stv, const T* __restrict__ gbar,
-                                                           void* adj_cur, double* pacc) {
+__global__ void __launch_bounds__(kBlock) k_p2g_adj_gather(KCfg c, Bufs b, const void* stv, const T* __restrict__ tau,
+                                                           const T* __restrict__ gbar, void* adj_cur, double* pacc) {
   const int inst = b.blk_inst[blockIdx.x];
   const InstDev& I = b.inst[inst];
   const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -1083,19 +1095,16 @@ __global__ void __launch_bounds__(kBlock) k_p2g_adj_gather(KCfg c, Bufs b, const
     Stencil<T, D> S;
     if (make_stencil<T, D>(st, p, c, S)) {
       const T dt = T(I.dt), mp = T(I.mp), dx = T(c.dx), inv_dx = T(c.inv_dx);
-      T Cm[3][3], Gm[3][3], Ft[3][3], vel[3], A[3][3];
-      ftmp_of<T, D>(st, p, dt, Cm, Gm, Ft);
-      {
-        Constit<T, D> cs;
-        constit_forward<T, D>(Ft, T(I.mu), T(I.lam), T(I.alpha), T(I.kc), cs);
-        T Fn[3][3], tau[3][3];
-        constit_outputs<T, D>(cs, Fn, tau);
-        const T k_str = -dt * T(I.Vp) * T(4.0 * c.inv_dx * c.inv_dx);
+      // A = k tau + m_p C with the stress the recomputed forward step stored
+      T Cm[3][3], vel[3], A[3][3];
+      const T k_str = -dt * T(I.Vp) * T(4.0 * c.inv_dx * c.inv_dx);
 #pragma unroll
-        for (int a = 0; a < D; ++a)
+      for (int a = 0; a < D; ++a)
 #pragma unroll
-          for (int bb = 0; bb < D; ++bb) A[a][bb] = k_str * tau[a][bb] + mp * Cm[a][bb];
-      }
+        for (int bb = 0; bb < D; ++bb) {
+          Cm[a][bb] = st.C(a, bb, p);
+          A[a][bb] = k_str * tau[(int64_t)sym_row<D>(a, bb) * c.ntot + p] + mp * Cm[a][bb];
+        }
 #pragma unroll
       for (int a = 0; a < D; ++a) vel[a] = st.v(a, p);
       T mpb = T(0), vb[3] = {T(0), T(0), T(0)}, Ab[3][3] = {{T(0), T(0), T(0)}, {T(0), T(0), T(0)}, {T(0), T(0), T(0)}};
@@ -1211,10 +1220,11 @@ __global__ void __launch_bounds__(kBlock) k_p2g_adj_constit(KCfg c, Bufs b, cons
   block_accumulate<4>(acc, pacc + (int64_t)inst * 8);
 }
 
-void launch_p2g_adj(int prec, const KCfg& c, const Bufs& b, int nblk, const void* st, const void* gb,
+void launch_p2g_adj(int prec, const KCfg& c, const Bufs& b, int nblk, const void* st, const void* tau, const void* gb,
                     const void* adj_next, void* adj_cur, double* pacc, hipStream_t s) {
 #define DDM_P2GADJ(T, DD)                                                                                          \
-  hipLaunchKernelGGL((k_p2g_adj_gather<T, DD>), dim3(nblk), dim3(kBlock), 0, s, c, b, st, (const T*)gb, adj_cur, pacc); \
+  hipLaunchKernelGGL((k_p2g_adj_gather<T, DD>), dim3(nblk), dim3(kBlock), 0, s, c, b, st, (const T*)tau, (const T*)gb, \
+                     adj_cur, pacc);                                                                                \
   hipLaunchKernelGGL((k_p2g_adj_constit<T, DD>), dim3(nblk), dim3(kBlock), 0, s, c, b, st, adj_next, adj_cur, pacc);
   if (prec == 0) {
     if (c.dim == 3) { DDM_P2GADJ(float, 3) } else { DDM_P2GADJ(float, 2) }

@@ -61,8 +61,10 @@ struct Bufs {
 void launch_fill_zero(void* p, int64_t count, int elem_bytes, hipStream_t s);
 void launch_init_state(int prec, const KCfg& c, const Bufs& b, int nblk, const void* x0, void* state,
                        uint32_t* pid, hipStream_t s);
+// tau_out (may be NULL): the Kirchhoff stress of every particle, symmetric
+// rows (00, 01, 02, 11, 12, 22; 2D: 00, 01, 11) of stride ntot, for the reverse pass.
 void launch_p2g(int prec, const KCfg& c, const Bufs& b, const TileList& tl, int nwg, const void* st_in, void* st_out,
-                void* grid, hipStream_t s);
+                void* grid, void* tau_out, hipStream_t s);
 void launch_grid_update(int prec, const KCfg& c, const Bufs& b, int step, const void* grid_pre, void* grid_post,
                         hipStream_t s);
 void launch_g2p(int prec, const KCfg& c, const Bufs& b, int nblk, const void* st_in, void* st_out,
@@ -94,7 +96,7 @@ void launch_g2p_adj(int prec, const KCfg& c, const Bufs& b, const TileList& tl, 
                     const void* grid_post, const void* adj_next, void* adj_cur, void* gvb, hipStream_t s);
 void launch_grid_adj(int prec, const KCfg& c, const Bufs& b, int step, const void* grid_pre, const void* gvb,
                      void* gb, double* pose_bar, hipStream_t s);
-void launch_p2g_adj(int prec, const KCfg& c, const Bufs& b, int nblk, const void* st, const void* gb,
+void launch_p2g_adj(int prec, const KCfg& c, const Bufs& b, int nblk, const void* st, const void* tau, const void* gb,
                     const void* adj_next, void* adj_cur, double* pacc, hipStream_t s);
 void launch_grad_final(const KCfg& c, const InstDev* inst, const double* pacc, const double* pose_bar,
                        const double* pose_jac, int n_steps, const double* dloss, double* grad, hipStream_t s);

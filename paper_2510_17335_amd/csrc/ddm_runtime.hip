@@ -43,7 +43,8 @@ int64_t pad_up(int64_t n, int64_t m) { return (n + m - 1) / m * m; }
 struct Layout {
   size_t inst = 0, blk_inst = 0, poses = 0, pose_jac = 0, err = 0, pid = 0, pid_tmp = 0;
   size_t cur = 0, grid_pre = 0, grid_post = 0, scratch = 0;
-  size_t ckpt = 0, seg_state = 0, seg_grid = 0, seg_perm = 0, seg_tiles = 0, seg_tcount = 0;
+  size_t ckpt = 0, seg_state = 0, seg_grid = 0, seg_tau = 0, seg_perm = 0, seg_tiles = 0, seg_tcount = 0;
+  size_t tau_bytes = 0;
   size_t adj0 = 0, adj1 = 0, gvb = 0, gb = 0, pacc = 0, pose_bar = 0;
   size_t hm_bits = 0, owner = 0, target = 0, hm_val = 0, dldh = 0, region = 0, dldm = 0, loss = 0;
   size_t keys0 = 0, keys1 = 0, vals0 = 0, vals1 = 0, hist = 0, sums = 0, tstart = 0, tend = 0, tiles = 0, tcount = 0;
@@ -105,6 +106,8 @@ Layout make_layout(const ddm_config& c, int n_inst, const ddm_instance* in) {
   L.ckpt = cv.take(L.state_bytes * L.n_ckpt);
   L.seg_state = cv.take(L.state_bytes * (L.K + 1));
   L.seg_grid = cv.take(L.grid_bytes * 2 * L.K);
+  L.tau_bytes = (size_t)(D * (D + 1) / 2) * ntot * b;
+  L.seg_tau = cv.take(L.tau_bytes * L.K);
   L.seg_perm = cv.take(sizeof(uint32_t) * ntot * L.K);
   L.seg_tiles = cv.take(sizeof(ddm::TileRec) * L.max_chunks * L.K);
   L.seg_tcount = cv.take(sizeof(uint32_t) * L.K);
@@ -407,11 +410,11 @@ ddm_status bin_state(ddm_ctx* x, void* state, uint32_t* pid, uint32_t* perm_out,
 // One forward sub-step from st_in to st_out (may alias) with the given tile
 // list; grids given.
 ddm_status forward_step(ddm_ctx* x, int64_t step, const ddm::TileList& tl, const void* st_in, void* st_out,
-                        void* gpre, void* gpost) {
+                        void* gpre, void* gpost, void* tau_out = nullptr) {
   const ddm::Bufs b = x->bufs();
   const int esz = x->prec ? 8 : 4;
   { Timed t(x, 7); ddm::launch_fill_zero(gpre, (int64_t)x->L.grid_bytes / esz, esz, x->stream); }
-  { Timed t(x, 0); ddm::launch_p2g(x->prec, x->kc, b, tl, x->L.nwg, st_in, st_out, gpre, x->stream); }
+  { Timed t(x, 0); ddm::launch_p2g(x->prec, x->kc, b, tl, x->L.nwg, st_in, st_out, gpre, tau_out, x->stream); }
   { Timed t(x, 1); ddm::launch_grid_update(x->prec, x->kc, b, (int)step, gpre, gpost, x->stream); }
   { Timed t(x, 2); ddm::launch_g2p(x->prec, x->kc, b, (int)x->L.nblk, st_in, st_out, gpost, x->stream); }
   return launch_status();
@@ -660,6 +663,7 @@ ddm_status ddm_backward(ddm_ctx* x, const double* dloss_dev, double* grad_dev) {
   auto gpre = [&](int j) { return x->at(L.seg_grid + (size_t)(2 * j) * L.grid_bytes); };
   auto gpost = [&](int j) { return x->at(L.seg_grid + (size_t)(2 * j + 1) * L.grid_bytes); };
   auto perm = [&](int j) { return x->at<uint32_t>(L.seg_perm + sizeof(uint32_t) * (size_t)L.ntot * j); };
+  auto tau = [&](int j) { return x->at(L.seg_tau + L.tau_bytes * (size_t)j); };
   for (int seg = nseg - 1; seg >= 0; --seg) {
     const int64_t s0 = (int64_t)seg * K;
     const int len = (int)std::min<int64_t>(K, n - s0);
@@ -676,7 +680,7 @@ ddm_status ddm_backward(ddm_ctx* x, const double* dloss_dev, double* grad_dev) {
         last = j;
       }
       tl_of[j] = last;
-      const ddm_status s = forward_step(x, k0 + s0 + j, x->seg_tiles(last), slot(j), slot(j + 1), gpre(j), gpost(j));
+      const ddm_status s = forward_step(x, k0 + s0 + j, x->seg_tiles(last), slot(j), slot(j + 1), gpre(j), gpost(j), tau(j));
       if (s != DDM_OK) return s;
     }
     for (int j = len - 1; j >= 0; --j) {
@@ -685,7 +689,7 @@ ddm_status ddm_backward(ddm_ctx* x, const double* dloss_dev, double* grad_dev) {
       { Timed t(x, 4); ddm::launch_g2p_adj(x->prec, x->kc, b, tl, L.nwg, slot(j), gpost(j), adj[cur], adj[1 - cur], x->at(L.gvb), st); }
       { Timed t(x, 5); ddm::launch_grid_adj(x->prec, x->kc, b, (int)(k0 + s0 + j), gpre(j), x->at(L.gvb), x->at(L.gb),
                                             x->at<double>(L.pose_bar), st); }
-      { Timed t(x, 6); ddm::launch_p2g_adj(x->prec, x->kc, b, (int)L.nblk, slot(j), x->at(L.gb), adj[cur], adj[1 - cur],
+      { Timed t(x, 6); ddm::launch_p2g_adj(x->prec, x->kc, b, (int)L.nblk, slot(j), tau(j), x->at(L.gb), adj[cur], adj[1 - cur],
                                            x->at<double>(L.pacc), st); }
       if (x->rec_sorted[(size_t)(s0 + j)]) {
         // the adjoint of a permutation is its inverse
