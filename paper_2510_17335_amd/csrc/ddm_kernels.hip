@@ -258,8 +258,8 @@ template <int D> struct Win {
 };
 
 // Particle slots of a chunk of cnt sorted particles, one wave-iteration at a
-// time: wave w of the workgroup takes iterations q = w, w + 4, ... < nq, and
-// lane l of iteration q takes slot l * nq + q.  (l, q) -> slot is a bijection
+// time: wave w of the workgroup takes iterations it = w, w + 4, ... < nq, and
+// lane l of iteration it takes slot l * nq + it.  (l, it) -> slot is a bijection
 // onto [0, 64 nq) >= [0, cnt), and the 64 lanes of one iteration sit about
 // cnt / 64 slots apart in the cell order, i.e. about one particle per cell,
 // so LDS atomics of one instruction rarely share an address.
@@ -312,6 +312,35 @@ __device__ __forceinline__ bool p2g_particle(const KCfg& c, const Bufs& b, const
   return true;
 }
 
+// Quadratic B-spline scatter of one particle: node o = (o0, o1, o2) receives
+// w_o (q + B o) (D values) and w_o m, w_o the product of the per-axis weights
+// wt[axis][o_axis]; q + B o is advanced incrementally along the last axis.
+template <typename T, int D, typename Emit>
+__device__ __forceinline__ void scatter_stencil(const T (&wt)[3][3], const T (&q)[3], const T (&B)[3][3], T m,
+                                                Emit&& emit) {
+#pragma unroll
+  for (int o0 = 0; o0 < 3; ++o0)
+#pragma unroll
+    for (int o1 = 0; o1 < 3; ++o1) {
+      const T wxy = wt[0][o0] * wt[1][o1];
+      T t[3] = {T(0), T(0), T(0)};
+#pragma unroll
+      for (int a = 0; a < D; ++a) t[a] = q[a] + T(o0) * B[a][0] + T(o1) * B[a][1];
+#pragma unroll
+      for (int o2 = 0; o2 < (D == 3 ? 3 : 1); ++o2) {
+        const T w = D == 3 ? wxy * wt[2][o2] : wxy;
+        T v[4] = {T(0), T(0), T(0), w * m};
+#pragma unroll
+        for (int a = 0; a < D; ++a) v[a] = w * t[a];
+        emit(o0, o1, o2, v);
+        if (D == 3) {
+#pragma unroll
+          for (int a = 0; a < D; ++a) t[a] += B[a][2];
+        }
+      }
+    }
+}
+
 // P2G over occupied tiles: one workgroup per chunk of up to kChunk particles
 // of a tile (grid-stride over the tile list),
 // contributions accumulated with LDS atomics in a kWin^D window and flushed to
@@ -323,7 +352,6 @@ __global__ void __launch_bounds__(kBlock) k_p2g(KCfg c, Bufs b, TileList tl, con
   __shared__ double win[Win<D>::stride * kNodeVals];
   const uint32_t ntiles = *tl.count;
   const P<T, D> si = pv<T, D>(st_in, c.ntot), so = pv<T, D>(st_out, c.ntot);
-  const T dx = T(c.dx);
   constexpr int WS = Win<D>::stride;
   for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const TileRec tr = tl.list[t];
@@ -334,49 +362,45 @@ __global__ void __launch_bounds__(kBlock) k_p2g(KCfg c, Bufs b, TileList tl, con
     for (int i = threadIdx.x; i < WS * kNodeVals; i += kBlock) win[i] = 0.0;
     __syncthreads();
     const int cnt = (int)(tr.end - tr.start), nq = chunk_iters(cnt);
-    for (int q = threadIdx.x >> 6; q < nq; q += kBlock / 64) {
-      const int slot = (threadIdx.x & 63) * nq + q;
+    for (int it = threadIdx.x >> 6; it < nq; it += kBlock / 64) {
+      const int slot = (threadIdx.x & 63) * nq + it;
       if (slot >= cnt) continue;
       const int64_t p = (int64_t)tr.start + slot;
       Stencil<T, D> S;
       T A[3][3], vel[3];
       if (!p2g_particle<T, D>(c, b, I, inst, si, so, p, S, A, vel, tau_out)) continue;
-      const T mp = T(I.mp);
+      // node o receives w_o (q + B o) and w_o m_p with q = m_p v - A f dx and
+      // B = A dx (the MLS-MPM momentum m_p v + A (x_i - x_p), x_i - x_p = (o - f) dx)
+      T q[3] = {T(0), T(0), T(0)}, B[3][3];
+      const T tdx = T(c.dx);
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        T af = T(0);
+#pragma unroll
+        for (int bb = 0; bb < D; ++bb) { B[a][bb] = A[a][bb] * tdx; af += B[a][bb] * S.f[bb]; }
+        q[a] = vel[a] - af;
+      }
+      const T mpt = T(I.mp);
       int loc[3] = {0, 0, 0};
       bool inwin = true;
 #pragma unroll
       for (int a = 0; a < D; ++a) { loc[a] = S.base[a] - org[a]; inwin &= loc[a] >= 0 && loc[a] <= kWin - 3; }
+      if (inwin) {
+        double* w0 = win + Win<D>::idx(loc[0], loc[1], loc[2]);
+        scatter_stencil<T, D>(S.w, q, B, mpt, [&](int o0, int o1, int o2, const T (&v)[4]) {
+          const int off = Win<D>::idx(o0, o1, o2);
 #pragma unroll
-      for (int o0 = 0; o0 < 3; ++o0)
+          for (int a = 0; a < D; ++a) atomicAdd(w0 + a * WS + off, (double)v[a]);
+          atomicAdd(w0 + 3 * WS + off, (double)v[3]);
+        });
+      } else {
+        scatter_stencil<T, D>(S.w, q, B, mpt, [&](int o0, int o1, int o2, const T (&v)[4]) {
+          T* dst = g + node_of<D>(S.base, o0, o1, o2, c.n) * kNodeVals;
 #pragma unroll
-        for (int o1 = 0; o1 < 3; ++o1)
-#pragma unroll
-          for (int o2 = 0; o2 < (D == 3 ? 3 : 1); ++o2) {
-            const int off[3] = {o0, o1, o2};
-            T w = T(1), r[3];
-#pragma unroll
-            for (int a = 0; a < D; ++a) { w *= S.w[a][off[a]]; r[a] = (T(off[a]) - S.f[a]) * dx; }
-            T val[4];
-#pragma unroll
-            for (int a = 0; a < D; ++a) {
-              T ar = vel[a];
-#pragma unroll
-              for (int bb = 0; bb < D; ++bb) ar += A[a][bb] * r[bb];
-              val[a] = w * ar;
-            }
-            val[3] = w * mp;
-            if (inwin) {
-              const int wi = Win<D>::idx(loc[0] + o0, loc[1] + o1, loc[2] + o2);
-#pragma unroll
-              for (int a = 0; a < D; ++a) atomicAdd(win + a * WS + wi, (double)val[a]);
-              atomicAdd(win + 3 * WS + wi, (double)val[3]);
-            } else {
-              T* dst = g + node_of<D>(S.base, o0, o1, o2, c.n) * kNodeVals;
-#pragma unroll
-              for (int a = 0; a < D; ++a) atomicAdd(dst + a, val[a]);
-              atomicAdd(dst + 3, val[3]);
-            }
-          }
+          for (int a = 0; a < D; ++a) atomicAdd(dst + a, v[a]);
+          atomicAdd(dst + 3, v[3]);
+        });
+      }
     }
     __syncthreads();
     for (int i = threadIdx.x; i < Win<D>::nodes; i += kBlock) {
@@ -872,8 +896,8 @@ __global__ void __launch_bounds__(kBlock) k_g2p_adj(KCfg c, Bufs b, TileList tl,
     for (int i = threadIdx.x; i < WS * D; i += kBlock) win[i] = 0.0;
     __syncthreads();
     const int cnt = (int)(tr.end - tr.start), nq = chunk_iters(cnt);
-    for (int q = threadIdx.x >> 6; q < nq; q += kBlock / 64) {
-      const int slot = (threadIdx.x & 63) * nq + q;
+    for (int it = threadIdx.x >> 6; it < nq; it += kBlock / 64) {
+      const int slot = (threadIdx.x & 63) * nq + it;
       if (slot >= cnt) continue;
       const int64_t p = (int64_t)tr.start + slot;
       Stencil<T, D> S;
@@ -890,52 +914,77 @@ __global__ void __launch_bounds__(kBlock) k_g2p_adj(KCfg c, Bufs b, TileList tl,
       bool inwin = true;
 #pragma unroll
       for (int a = 0; a < D; ++a) { loc[a] = S.base[a] - org[a]; inwin &= loc[a] >= 0 && loc[a] <= kWin - 3; }
-      // Offsets 0 and 1 stay loops: unrolling all 27 nodes hoists their loads
-      // and leaves one wave per SIMD (256 VGPRs); this way 112.
+      // With t_o = vb + Dk C'bar r_o = q + B o (q = vb - B f, B = Dk dx C'bar):
+      //   node o receives w_o t_o;
+      //   xbar += sum_o grad w_o (v_o . t_o) - Dk C'bar^T sum_o w_o v_o,
+      // the first sum factored by axis (weights are products of per-axis terms).
+      T q[3] = {T(0), T(0), T(0)}, B[3][3], dwi[3][3];
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        T bf = T(0);
+#pragma unroll
+        for (int bb = 0; bb < D; ++bb) { B[a][bb] = Dk * dx * Cb[a][bb]; bf += B[a][bb] * S.f[bb]; }
+        q[a] = vb[a] - bf;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) dwi[a][k] = S.dw[a][k] * inv_dx;
+      }
+      T xg[3] = {T(0), T(0), T(0)}, vw[3] = {T(0), T(0), T(0)};
+      auto body = [&](auto&& emit) {
+        // Offsets 0 and 1 stay loops: unrolling all 27 nodes hoists their
+        // loads and costs occupancy.
 #pragma unroll 1
-      for (int o0 = 0; o0 < 3; ++o0)
+        for (int o0 = 0; o0 < 3; ++o0)
 #pragma unroll 1
-        for (int o1 = 0; o1 < 3; ++o1)
+          for (int o1 = 0; o1 < 3; ++o1) {
+            const T wxy = S.w[0][o0] * S.w[1][o1];
+            const T a0 = dwi[0][o0] * S.w[1][o1], a1 = S.w[0][o0] * dwi[1][o1];
+            T t[3] = {T(0), T(0), T(0)}, u[3] = {T(0), T(0), T(0)}, sw = T(0), sd = T(0);
 #pragma unroll
-          for (int o2 = 0; o2 < (D == 3 ? 3 : 1); ++o2) {
-            const int off[3] = {o0, o1, o2};
-            T w = T(1), r[3], gw[3];
+            for (int a = 0; a < D; ++a) t[a] = q[a] + T(o0) * B[a][0] + T(o1) * B[a][1];
 #pragma unroll
-            for (int a = 0; a < D; ++a) r[a] = (T(off[a]) - S.f[a]) * dx;
+            for (int o2 = 0; o2 < (D == 3 ? 3 : 1); ++o2) {
+              const T w2 = D == 3 ? S.w[2][o2] : T(1);
+              const T w = wxy * w2;
+              const int64_t nd = node_of<D>(S.base, o0, o1, o2, c.n) * kNodeVals;
+              const Node4<T> gv = ld_node(g + nd);
+              T sdot = T(0);
 #pragma unroll
-            for (int a = 0; a < D; ++a) {
-              T prod = S.dw[a][off[a]] * inv_dx;
+              for (int a = 0; a < D; ++a) { sdot += gv.v[a] * t[a]; u[a] += w2 * gv.v[a]; }
+              sw += w2 * sdot;
+              if (D == 3) sd += dwi[2][o2] * sdot;
+              emit(o0, o1, o2, nd, w, t);
+              if (D == 3) {
 #pragma unroll
-              for (int bb = 0; bb < D; ++bb)
-                if (bb != a) prod *= S.w[bb][off[bb]];
-              gw[a] = prod;
-              w *= S.w[a][off[a]];
+                for (int a = 0; a < D; ++a) t[a] += B[a][2];
+              }
             }
-            const int64_t nd = node_of<D>(S.base, o0, o1, o2, c.n) * kNodeVals;
-            const Node4<T> gv = ld_node(g + nd);
-            T vi[3], Cr[3];
+            xg[0] += a0 * sw;
+            xg[1] += a1 * sw;
+            if (D == 3) xg[2] += wxy * sd;
 #pragma unroll
-            for (int a = 0; a < D; ++a) vi[a] = gv.v[a];
-            T sdot = T(0);
-#pragma unroll
-            for (int a = 0; a < D; ++a) {
-              Cr[a] = T(0);
-#pragma unroll
-              for (int bb = 0; bb < D; ++bb) Cr[a] += Cb[a][bb] * r[bb];
-              sdot += vi[a] * (vb[a] + Dk * Cr[a]);
-            }
-            const int wi = Win<D>::idx(loc[0] + o0, loc[1] + o1, loc[2] + o2);
-#pragma unroll
-            for (int a = 0; a < D; ++a) {
-              T ctv = T(0);
-#pragma unroll
-              for (int bb = 0; bb < D; ++bb) ctv += Cb[bb][a] * vi[bb];
-              xb[a] += gw[a] * sdot - Dk * w * ctv;
-              const T add = w * (vb[a] + Dk * Cr[a]);
-              if (inwin) atomicAdd(win + a * WS + wi, (double)add);
-              else atomicAdd(gbv + nd + a, add);
-            }
+            for (int a = 0; a < D; ++a) vw[a] += wxy * u[a];
           }
+      };
+      if (inwin) {
+        double* w0 = win + Win<D>::idx(loc[0], loc[1], loc[2]);
+        body([&](int o0, int o1, int o2, int64_t, T w, const T (&t)[3]) {
+          const int off = Win<D>::idx(o0, o1, o2);
+#pragma unroll
+          for (int a = 0; a < D; ++a) atomicAdd(w0 + a * WS + off, (double)(w * t[a]));
+        });
+      } else {
+        body([&](int, int, int, int64_t nd, T w, const T (&t)[3]) {
+#pragma unroll
+          for (int a = 0; a < D; ++a) atomicAdd(gbv + nd + a, w * t[a]);
+        });
+      }
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        T ctv = T(0);
+#pragma unroll
+        for (int bb = 0; bb < D; ++bb) ctv += Cb[bb][a] * vw[bb];
+        xb[a] += xg[a] - Dk * ctv;
+      }
 #pragma unroll
       for (int a = 0; a < D; ++a) ac.x(a, p) = xb[a];
     }
