@@ -258,3 +258,96 @@ def test_backward_needs_rollout_and_loss(ddm):
     with pytest.raises(ddm.DdmError) as e:
         sim.backward()
     assert e.value.code == ddm.DDM_ESTATE
+
+
+def test_cohesion_forward_and_gradient_f64(ddm, orc):
+    """Cohesive variant of the return map (shifted cone apex k_c): tiny 3D dig with
+    c = 500 Pa, forward state and the 7 gradients against the oracle."""
+    w = W.tiny(3, shovel=True, steps=60)
+    w.material = W.Material(cohesion=500.0)
+    tgt = W.target_heightmap(w)
+    _log("case cohesion tiny3d f64")
+    g = run_gpu(ddm, w, 60, record=True, target=tgt, K=16)
+    r = run_oracle(orc, w, 60, target=tgt, grad=True)
+    e = field_errors(g["state"], r["state"], 3)
+    _log("cohesion errors", e, "\ngpu grad", g["grad"], "\noracle grad", r["grad"])
+    for k, v in e.items():
+        assert v < 1e-9, (k, v)
+    assert abs(g["loss"] - r["loss"]) <= 1e-10 * abs(r["loss"])
+    rel = np.abs(g["grad"] - r["grad"]) / np.maximum(np.abs(r["grad"]), 1e-9 * np.abs(r["grad"]).max())
+    assert np.all(rel < 1e-6), rel
+
+
+def _sampled_instances(ws, n_random=2, seed=9):
+    """Smallest, largest and n_random seeded other instances of a batch."""
+    ns = [w.n_particles for w in ws]
+    picks = [int(np.argmin(ns)), int(np.argmax(ns))]
+    rest = [i for i in range(len(ws)) if i not in picks]
+    rng = np.random.default_rng(seed)
+    picks += [int(i) for i in rng.choice(rest, n_random, replace=False)]
+    return picks
+
+
+@pytest.mark.timeout(600)
+def test_batch_sysid64_sampled_vs_oracle(ddm, orc):
+    """The benchmark batch at full size and in its launch configuration (64
+    instances, 7.6 M particles, FP32, binning every 8, K = 50): states of four
+    sampled instances after 40 sub-steps (<= 1e-4) and the gradients of the two
+    smallest (<= 1e-3) against the FP64 oracle run on each instance alone."""
+    steps = 40
+    ws = W.sysid_batch(64, steps=steps)
+    cfgs = [ddm.from_workload(w, max_steps=steps, checkpoint_every=50, sort_every=8) for w in ws]
+    sim = ddm.Simulator(cfgs[0][0], [c[1] for c in cfgs])
+    sim.init_state(np.concatenate([W.bed_positions(w) for w in ws]))
+    _log(f"case sysid64 batch {sum(w.n_particles for w in ws)} particles, {steps} sub-steps")
+    sim.rollout(steps)
+    tg = np.stack([W.target_heightmap(w) for w in ws])
+    loss = sim.loss(tg).cpu().numpy()
+    grad = sim.backward().cpu().numpy()
+    sim.check()
+    st = sim.get_state()
+    picks = _sampled_instances(ws)
+    for i in picks:
+        w = ws[i]
+        got = np.concatenate([t.reshape(t.shape[0], -1).cpu().numpy() for t in sim.instance_state(st, i)], 1)
+        r = run_oracle(orc, w, steps)
+        e = field_errors(got, r["state"], 3)
+        _log(f"instance {i} N={w.n_particles} errors", e)
+        for k, v in e.items():
+            assert v < 1e-4, (i, k, v)
+    smallest = sorted(range(len(ws)), key=lambda i: ws[i].n_particles)[:2]
+    for i in smallest:
+        r = run_oracle(orc, ws[i], steps, target=tg[i], grad=True)
+        rel = np.abs(grad[i] - r["grad"]) / np.maximum(np.abs(r["grad"]), 1e-6 * np.abs(r["grad"]).max())
+        _log(f"instance {i} loss {loss[i]} vs {r['loss']}, grad rel err {rel.max():.2e}")
+        assert abs(loss[i] - r["loss"]) <= 1e-4 * abs(r["loss"])
+        assert np.all(rel < 1e-3), rel
+
+
+@pytest.mark.timeout(400)
+def test_large_cohesive_bed_vs_oracle(ddm, orc):
+    """128^3 grid, 1 802 416 particles of cohesive soil, FP32, 5 sub-steps: the
+    full state against the FP64 oracle (<= 1e-4)."""
+    w = W.dig_3d_large()
+    _log("case dig3d_large 5 sub-steps")
+    g = run_gpu(ddm, w, 5)
+    r = run_oracle(orc, w, 5)
+    e = field_errors(g["state"], r["state"], 3)
+    _log("dig3d_large errors", e)
+    assert g["err"].flags & 3 == 0
+    for k, v in e.items():
+        assert v < 1e-4, (k, v)
+
+
+def test_largest_grid_f64(ddm, orc):
+    """The largest grid the library accepts (256^3) with a small bed near the
+    far corner, FP64, 6 sub-steps against the oracle."""
+    w = W.tiny(3, n_grid=256, ppc=1, steps=6)
+    w.bed_lo, w.bed_hi = (240, 3, 240), (250, 9, 251)
+    _log("case 256^3 grid")
+    g = run_gpu(ddm, w, 6)
+    r = run_oracle(orc, w, 6)
+    e = field_errors(g["state"], r["state"], 3)
+    _log("256^3 errors", e)
+    for k, v in e.items():
+        assert v < 1e-9, (k, v)
