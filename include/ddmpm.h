@@ -199,7 +199,10 @@ ddm_status ddm_bin_keys(ddm_ctx* ctx, uint32_t* keys_dev, uint32_t* perm_dev);
 
 /* Copies the grid of the last sub-step (per instance, n_grid^dim nodes,
  * 8 values each: m, mv[3], v[3], 0) into caller device memory, in the
- * context's precision.  For kernel-level tests. */
+ * context's precision; nodes that cannot hold mass are zero.  For
+ * kernel-level tests.  DDM_ESTATE when no forward sub-step ran since
+ * ddm_init_state, ddm_set_state or ddm_backward (the reverse pass reuses the
+ * grid buffers). */
 ddm_status ddm_get_grid(ddm_ctx* ctx, void* grid_dev);
 
 /* Copies the height map of the last ddm_loss ([n_inst][hm_res^(dim-1)],

@@ -179,7 +179,7 @@ __global__ void k_fill(uint32_t* p, int64_t words, uint32_t value) {
     p[i] = value;
 }
 
-static void launch_fill(void* p, int64_t words, uint32_t value, hipStream_t s) {
+void launch_fill_u32(void* p, int64_t words, uint32_t value, hipStream_t s) {
   if (words <= 0) return;
   int64_t blocks = (words + kBlock - 1) / kBlock;
   if (blocks > 65536) blocks = 65536;
@@ -187,7 +187,7 @@ static void launch_fill(void* p, int64_t words, uint32_t value, hipStream_t s) {
 }
 
 void launch_fill_zero(void* p, int64_t count, int elem_bytes, hipStream_t s) {
-  launch_fill(p, count * elem_bytes / 4, 0u, s);
+  launch_fill_u32(p, count * elem_bytes / 4, 0u, s);
 }
 
 template <typename T, int D>
@@ -312,6 +312,131 @@ __device__ __forceinline__ bool p2g_particle(const KCfg& c, const Bufs& b, const
   return true;
 }
 
+// ---------------------------------------------------------------------------
+// Run-based window scatter of one round of up to kBlock sorted particles.
+// Phase 1 (the caller): thread t handles slot t of the round and leaves in
+// LDS the particle's q (D values), B (D x D) and fractional position f, and
+// wbase[t] = the window index of its stencil base (-1: nothing to scatter).
+// Phase 2 (here): consecutive slots with the same base form a run (sorted
+// particles of one cell); work items are (run, stencil row), a row being the
+// 3 nodes along the last axis; each item sums its run's contributions in
+// registers and adds them to the double LDS window once.  An LDS float atomic
+// is slow on gfx950 (about 195 cycles per wave instruction, double about 10)
+// and every atomic instruction costs the same whether 1 or 64 lanes are
+// active, so the gain comes from issuing about 1/ppc as many atomics.
+// ---------------------------------------------------------------------------
+template <typename T> struct RunLDS {
+  T rec[4][kBlock][4];            // group g of slot t: (q0 q1 q2 -), (B_a0 B_a1 B_a2 f_a) for a = g - 1
+  int wbase[kBlock];
+  int wcount[kBlock / 64];
+  unsigned short start[kBlock + 1];
+  int nruns;
+};
+
+template <typename T> __device__ __forceinline__ void st4(T* p, T a, T b, T c, T d) { p[0] = a; p[1] = b; p[2] = c; p[3] = d; }
+template <> __device__ __forceinline__ void st4<float>(float* p, float a, float b, float c, float d) {
+  *reinterpret_cast<float4*>(p) = make_float4(a, b, c, d);
+}
+template <typename T> __device__ __forceinline__ void ld4(const T* p, T (&o)[4]) { o[0] = p[0]; o[1] = p[1]; o[2] = p[2]; o[3] = p[3]; }
+template <> __device__ __forceinline__ void ld4<float>(const float* p, float (&o)[4]) {
+  const float4 v = *reinterpret_cast<const float4*>(p);
+  o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+}
+
+// Phase-1 record of slot t.
+template <typename T, int D>
+__device__ __forceinline__ void put_record(RunLDS<T>& L, int t, const T (&q)[3], const T (&B)[3][3], const T (&f)[3]) {
+  st4<T>(L.rec[0][t], q[0], q[1], D == 3 ? q[2] : T(0), T(0));
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (a < D) st4<T>(L.rec[1 + a][t], B[a][0], B[a][1], D == 3 ? B[a][2] : T(0), f[a]);
+    else st4<T>(L.rec[1 + a][t], T(0), T(0), T(0), T(0));
+  }
+}
+
+// Phase 2 for a round of rc slots whose records and wbase are in L (the
+// caller synchronised after writing them).  NV = D + 1 scatters momentum and
+// mass (mass per particle m); NV = D scatters a D-vector.  Ends synchronised.
+template <typename T, int D, int NV>
+__device__ void run_scatter_round(RunLDS<T>& L, int rc, double* win, T m) {
+  constexpr int WS = Win<D>::stride;
+  constexpr int ROWS = D == 3 ? 9 : 3;
+  const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+  const bool flag = t < rc && L.wbase[t] >= 0 && (t == 0 || L.wbase[t] != L.wbase[t - 1]);
+  const unsigned long long bal = __ballot(flag);
+  if (lane == 0) L.wcount[wid] = __popcll(bal);
+  __syncthreads();
+  int off = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < kBlock / 64; ++w) { off += w < wid ? L.wcount[w] : 0; tot += L.wcount[w]; }
+  if (flag) L.start[off + __popcll(bal & ((1ull << lane) - 1ull))] = (unsigned short)t;
+  if (t == 0) L.start[tot] = (unsigned short)rc;
+  __syncthreads();
+  for (int it = t; it < tot * ROWS; it += kBlock) {
+    const int r = it / ROWS, row = it - r * ROWS;
+    const int o0 = D == 3 ? row / 3 : row, o1 = D == 3 ? row % 3 : 0;
+    const int s0 = L.start[r], s1 = L.start[r + 1];
+    const int base = L.wbase[s0];
+    T acc[3][4] = {{T(0), T(0), T(0), T(0)}, {T(0), T(0), T(0), T(0)}, {T(0), T(0), T(0), T(0)}};
+    for (int sl = s0; sl < s1; ++sl) {
+      if (L.wbase[sl] != base) continue;            // a particle without a window record
+      T q[4], b0[4], b1[4], b2[4];
+      ld4<T>(L.rec[0][sl], q);
+      ld4<T>(L.rec[1][sl], b0);
+      ld4<T>(L.rec[2][sl], b1);
+      if (D == 3) ld4<T>(L.rec[3][sl], b2);
+      // B column c of row a is b_a[c]; f_a is b_a[3]
+      T wr[3], dw[3], wa[3], wi[3];
+      bspline<T>(b0[3], wa, dw);
+      T wrow = wa[o0];
+      if (D == 3) { bspline<T>(b1[3], wr, dw); wrow *= wr[o1]; bspline<T>(b2[3], wi, dw); }
+      else bspline<T>(b1[3], wi, dw);
+      // t = q + B (o0, o1, 0) (3D) or q + B (o0, 0) (2D); then + B e_last per node
+      T tv[3], bl[3];
+      const T bcol0[3] = {b0[0], b1[0], D == 3 ? b2[0] : T(0)};
+      const T bcol1[3] = {b0[1], b1[1], D == 3 ? b2[1] : T(0)};
+      const T bcol2[3] = {b0[2], b1[2], D == 3 ? b2[2] : T(0)};
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        tv[a] = q[a] + T(o0) * bcol0[a] + (D == 3 ? T(o1) * bcol1[a] : T(0));
+        bl[a] = D == 3 ? bcol2[a] : bcol1[a];
+      }
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const T w = wrow * wi[k];
+#pragma unroll
+        for (int a = 0; a < D; ++a) { acc[k][a] += w * tv[a]; tv[a] += bl[a]; }
+        if (NV == D + 1) acc[k][3] += w;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const int wi = base + (D == 3 ? Win<D>::idx(o0, o1, k) : Win<D>::idx(o0, k, 0));
+#pragma unroll
+      for (int a = 0; a < D; ++a) atomicAdd(win + a * WS + wi, (double)acc[k][a]);
+      if (NV == D + 1) atomicAdd(win + 3 * WS + wi, (double)(acc[k][3] * m));
+    }
+  }
+  __syncthreads();
+}
+
+// Adds the node blocks of a particle's stencil (nodes base .. base + 2 per
+// axis) to the active set, each block once.
+template <int D>
+__device__ void mark_stencil_blocks(const KCfg& c, int inst, const int base[3], const ActiveSet& act) {
+  const int nt = c.n / kTile;
+  const uint32_t per = D == 3 ? (uint32_t)(nt * nt * nt) : (uint32_t)(nt * nt);
+  int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+  for (int a = 0; a < D; ++a) { lo[a] = base[a] / kTile; hi[a] = (base[a] + 2) / kTile; }
+  for (int b0 = lo[0]; b0 <= hi[0]; ++b0)
+    for (int b1 = lo[1]; b1 <= hi[1]; ++b1)
+      for (int b2 = lo[2]; b2 <= hi[2]; ++b2) {
+        const uint32_t gb = (uint32_t)inst * per +
+                            (D == 3 ? (uint32_t)((b0 * nt + b1) * nt + b2) : (uint32_t)(b0 * nt + b1));
+        if (atomicOr(&act.mask[gb], 1u) == 0u) act.list[atomicAdd(act.count, 1u)] = gb;
+      }
+}
+
 // Quadratic B-spline scatter of one particle: node o = (o0, o1, o2) receives
 // w_o (q + B o) (D values) and w_o m, w_o the product of the per-axis weights
 // wt[axis][o_axis]; q + B o is advanced incrementally along the last axis.
@@ -341,93 +466,96 @@ __device__ __forceinline__ void scatter_stencil(const T (&wt)[3][3], const T (&q
     }
 }
 
-// P2G over occupied tiles: one workgroup per chunk of up to kChunk particles
-// of a tile (grid-stride over the tile list),
-// contributions accumulated with LDS atomics in a kWin^D window and flushed to
-// the grid once per chunk; particles outside the window (drifted
-// more than one cell since binning) add to the grid directly.
+// P2G over occupied tiles: one workgroup per tile (grid-stride over the tile
+// list), contributions accumulated with LDS atomics in a kWin^D window that is
+// then stored whole to the tile's staging record (no global atomics); the
+// grid update sums the windows covering each node.  Particles outside the
+// window (drifted more than one cell since binning) add to the outlier grid
+// with global atomics and put their node blocks in the active set.
 template <typename T, int D>
 __global__ void __launch_bounds__(kBlock) k_p2g(KCfg c, Bufs b, TileList tl, const void* st_in, void* st_out,
-                                                T* __restrict__ grid, T* __restrict__ tau_out) {
+                                                T* __restrict__ stg, T* __restrict__ gout, ActiveSet act,
+                                                T* __restrict__ tau_out) {
   __shared__ double win[Win<D>::stride * kNodeVals];
+  __shared__ RunLDS<T> rl;
   const uint32_t ntiles = *tl.count;
   const P<T, D> si = pv<T, D>(st_in, c.ntot), so = pv<T, D>(st_out, c.ntot);
-  constexpr int WS = Win<D>::stride;
   for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const TileRec tr = tl.list[t];
     int inst, org[3];
     tile_origin<D>(c, tr.tile, inst, org);
     const InstDev& I = b.inst[inst];
-    T* g = grid + I.goff * kNodeVals;
-    for (int i = threadIdx.x; i < WS * kNodeVals; i += kBlock) win[i] = 0.0;
-    __syncthreads();
-    const int cnt = (int)(tr.end - tr.start), nq = chunk_iters(cnt);
-    for (int it = threadIdx.x >> 6; it < nq; it += kBlock / 64) {
-      const int slot = (threadIdx.x & 63) * nq + it;
-      if (slot >= cnt) continue;
-      const int64_t p = (int64_t)tr.start + slot;
-      Stencil<T, D> S;
-      T A[3][3], vel[3];
-      if (!p2g_particle<T, D>(c, b, I, inst, si, so, p, S, A, vel, tau_out)) continue;
-      // node o receives w_o (q + B o) and w_o m_p with q = m_p v - A f dx and
-      // B = A dx (the MLS-MPM momentum m_p v + A (x_i - x_p), x_i - x_p = (o - f) dx)
-      T q[3] = {T(0), T(0), T(0)}, B[3][3];
-      const T tdx = T(c.dx);
+    T* g = gout + I.goff * kNodeVals;
+    const T mpt = T(I.mp);
+    for (int i = threadIdx.x; i < Win<D>::stride * kNodeVals; i += kBlock) win[i] = 0.0;
+    const int cnt = (int)(tr.end - tr.start);
+    for (int r0 = 0; r0 < cnt; r0 += kBlock) {
+      const int rc = min(kBlock, cnt - r0);
+      int wb = -1;
+      if (threadIdx.x < rc) {
+        const int64_t p = (int64_t)tr.start + r0 + threadIdx.x;
+        Stencil<T, D> S;
+        T A[3][3], vel[3];
+        if (p2g_particle<T, D>(c, b, I, inst, si, so, p, S, A, vel, tau_out)) {
+          // node o receives w_o (q + B o) and w_o m_p with q = m_p v - A f dx and
+          // B = A dx (the MLS-MPM momentum m_p v + A (x_i - x_p), x_i - x_p = (o - f) dx)
+          T q[3] = {T(0), T(0), T(0)}, B[3][3] = {{T(0), T(0), T(0)}, {T(0), T(0), T(0)}, {T(0), T(0), T(0)}};
+          const T tdx = T(c.dx);
 #pragma unroll
-      for (int a = 0; a < D; ++a) {
-        T af = T(0);
+          for (int a = 0; a < D; ++a) {
+            T af = T(0);
 #pragma unroll
-        for (int bb = 0; bb < D; ++bb) { B[a][bb] = A[a][bb] * tdx; af += B[a][bb] * S.f[bb]; }
-        q[a] = vel[a] - af;
+            for (int bb = 0; bb < D; ++bb) { B[a][bb] = A[a][bb] * tdx; af += B[a][bb] * S.f[bb]; }
+            q[a] = vel[a] - af;
+          }
+          int loc[3] = {0, 0, 0};
+          bool inwin = true;
+#pragma unroll
+          for (int a = 0; a < D; ++a) { loc[a] = S.base[a] - org[a]; inwin &= loc[a] >= 0 && loc[a] <= kWin - 3; }
+          if (inwin) {
+            wb = Win<D>::idx(loc[0], loc[1], loc[2]);
+            T f[3] = {S.f[0], S.f[1], D == 3 ? S.f[2] : T(0)};
+            put_record<T, D>(rl, threadIdx.x, q, B, f);
+          } else {
+            mark_stencil_blocks<D>(c, inst, S.base, act);
+            scatter_stencil<T, D>(S.w, q, B, mpt, [&](int o0, int o1, int o2, const T (&v)[4]) {
+              T* dst = g + node_of<D>(S.base, o0, o1, o2, c.n) * kNodeVals;
+#pragma unroll
+              for (int a = 0; a < D; ++a) atomicAdd(dst + a, v[a]);
+              atomicAdd(dst + 3, v[3]);
+            });
+          }
+        }
       }
-      const T mpt = T(I.mp);
-      int loc[3] = {0, 0, 0};
-      bool inwin = true;
-#pragma unroll
-      for (int a = 0; a < D; ++a) { loc[a] = S.base[a] - org[a]; inwin &= loc[a] >= 0 && loc[a] <= kWin - 3; }
-      if (inwin) {
-        double* w0 = win + Win<D>::idx(loc[0], loc[1], loc[2]);
-        scatter_stencil<T, D>(S.w, q, B, mpt, [&](int o0, int o1, int o2, const T (&v)[4]) {
-          const int off = Win<D>::idx(o0, o1, o2);
-#pragma unroll
-          for (int a = 0; a < D; ++a) atomicAdd(w0 + a * WS + off, (double)v[a]);
-          atomicAdd(w0 + 3 * WS + off, (double)v[3]);
-        });
-      } else {
-        scatter_stencil<T, D>(S.w, q, B, mpt, [&](int o0, int o1, int o2, const T (&v)[4]) {
-          T* dst = g + node_of<D>(S.base, o0, o1, o2, c.n) * kNodeVals;
-#pragma unroll
-          for (int a = 0; a < D; ++a) atomicAdd(dst + a, v[a]);
-          atomicAdd(dst + 3, v[3]);
-        });
-      }
+      rl.wbase[threadIdx.x] = wb;
+      __syncthreads();
+      run_scatter_round<T, D, D + 1>(rl, rc, win, mpt);
     }
     __syncthreads();
+    // the whole window, zeros included, to the tile's staging record
+    T* rec = stg + (int64_t)t * (kNodeVals * Win<D>::nodes);
     for (int i = threadIdx.x; i < Win<D>::nodes; i += kBlock) {
       int l[3];
       Win<D>::coords(i, l);
       const int wi = Win<D>::idx(l[0], l[1], l[2]);
-      const double m = win[3 * WS + wi];
-      if (m == 0.0) continue;
-      const int gb[3] = {org[0] + l[0], org[1] + l[1], D == 3 ? org[2] + l[2] : 0};
-      T* dst = g + node_of<D>(gb, 0, 0, 0, c.n) * kNodeVals;
 #pragma unroll
-      for (int a = 0; a < D; ++a) atomicAdd(dst + a, (T)win[a * WS + wi]);
-      atomicAdd(dst + 3, (T)m);
+      for (int a = 0; a < kNodeVals; ++a) rec[a * Win<D>::nodes + i] = (T)win[a * Win<D>::stride + wi];
     }
     __syncthreads();
   }
 }
 
 void launch_p2g(int prec, const KCfg& c, const Bufs& b, const TileList& tl, int nwg, const void* st_in, void* st_out,
-                void* grid, void* tau_out, hipStream_t s) {
+                const Staging& stg, void* gout, const ActiveSet& act, void* tau_out, hipStream_t s) {
+#define DDM_P2G(T, DD)                                                                                             \
+  hipLaunchKernelGGL((k_p2g<T, DD>), dim3(nwg), dim3(kBlock), 0, s, c, b, tl, st_in, st_out, (T*)stg.win, (T*)gout, \
+                     act, (T*)tau_out)
   if (prec == 0) {
-    if (c.dim == 3) hipLaunchKernelGGL((k_p2g<float, 3>), dim3(nwg), dim3(kBlock), 0, s, c, b, tl, st_in, st_out, (float*)grid, (float*)tau_out);
-    else hipLaunchKernelGGL((k_p2g<float, 2>), dim3(nwg), dim3(kBlock), 0, s, c, b, tl, st_in, st_out, (float*)grid, (float*)tau_out);
+    if (c.dim == 3) DDM_P2G(float, 3); else DDM_P2G(float, 2);
   } else {
-    if (c.dim == 3) hipLaunchKernelGGL((k_p2g<double, 3>), dim3(nwg), dim3(kBlock), 0, s, c, b, tl, st_in, st_out, (double*)grid, (double*)tau_out);
-    else hipLaunchKernelGGL((k_p2g<double, 2>), dim3(nwg), dim3(kBlock), 0, s, c, b, tl, st_in, st_out, (double*)grid, (double*)tau_out);
+    if (c.dim == 3) DDM_P2G(double, 3); else DDM_P2G(double, 2);
   }
+#undef DDM_P2G
 }
 
 // ---------------------------------------------------------------------------
@@ -459,54 +587,135 @@ __device__ __forceinline__ void node_coords(int64_t node, int n, int idx[3]) {
   else { idx[0] = (int)(node / ((int64_t)n * n)); idx[1] = (int)((node / n) % n); idx[2] = (int)(node % n); }
 }
 
-template <typename T, int D>
-__global__ void __launch_bounds__(kBlock) k_grid_update(KCfg c, Bufs b, int step, const T* __restrict__ pre, T* __restrict__ post) {
-  const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (gid >= c.nodes * c.n_inst) return;
-  const int inst = (int)(gid / c.nodes);
-  const int64_t node = gid - (int64_t)inst * c.nodes;
-  const T m = pre[gid * kNodeVals + 3];
-  T v[3] = {T(0), T(0), T(0)};
-  if (m > T(0)) {
-    const T dt = T(b.inst[inst].dt);
-#pragma unroll
-    for (int a = 0; a < D; ++a) v[a] = pre[gid * kNodeVals + a] / m;
-    v[1] += dt * T(c.gravity);
-    int idx[3];
-    node_coords<D>(node, c.n, idx);
-    if (D == 3 && c.shovel) {
-      const Blade<T> bl = load_blade<T>(b.poses, inst, c.max_steps, step);
-      const T xi[3] = {T(idx[0]) * T(c.dx), T(idx[1]) * T(c.dx), T(idx[2]) * T(c.dx)};
-      const T half[3] = {T(c.half[0]), T(c.half[1]), T(c.half[2])};
-      SDF<T> f;
-      sdf_eval<T>(bl, half, xi, f);
-      if (f.phi < T(c.skin)) {
-        T vs[3];
-        blade_velocity<T>(bl, xi, vs);
-        coulomb_forward<T>(vs, f.n, T(c.mu_b), v);
-      }
-    }
-    bool wall = false;
-#pragma unroll
-    for (int a = 0; a < D; ++a) wall |= (idx[a] < c.bound) || (idx[a] >= c.n - c.bound);
-    if (wall) v[0] = v[1] = v[2] = T(0);
-  }
-  post[gid * kNodeVals + 0] = v[0];
-  post[gid * kNodeVals + 1] = v[1];
-  post[gid * kNodeVals + 2] = v[2];
-  post[gid * kNodeVals + 3] = m;
+// Node of an active-set item: item i is node i % 4^D of listed block i / 4^D.
+template <int D>
+__device__ __forceinline__ void active_node(const KCfg& c, uint32_t gb, int k, int& inst, int idx[3], int64_t& node) {
+  const int nt = c.n / kTile;
+  const uint32_t per = D == 3 ? (uint32_t)(nt * nt * nt) : (uint32_t)(nt * nt);
+  inst = (int)(gb / per);
+  uint32_t t = gb - (uint32_t)inst * per;
+  int bc[3] = {0, 0, 0};
+  for (int a = D - 1; a >= 0; --a) { bc[a] = (int)(t % (uint32_t)nt); t /= (uint32_t)nt; }
+  if (D == 3) { idx[0] = bc[0] * kTile + (k >> 4); idx[1] = bc[1] * kTile + ((k >> 2) & 3); idx[2] = bc[2] * kTile + (k & 3); }
+  else { idx[0] = bc[0] * kTile + (k >> 2); idx[1] = bc[1] * kTile + (k & 3); idx[2] = 0; }
+  node = D == 3 ? ((int64_t)idx[0] * c.n + idx[1]) * c.n + idx[2] : (int64_t)idx[0] * c.n + idx[1];
 }
 
-void launch_grid_update(int prec, const KCfg& c, const Bufs& b, int step, const void* pre, void* post, hipStream_t s) {
-  const int64_t total = c.nodes * c.n_inst;
-  const unsigned nb = (unsigned)((total + kBlock - 1) / kBlock);
-  if (prec == 0) {
-    if (c.dim == 3) hipLaunchKernelGGL((k_grid_update<float, 3>), dim3(nb), dim3(kBlock), 0, s, c, b, step, (const float*)pre, (float*)post);
-    else hipLaunchKernelGGL((k_grid_update<float, 2>), dim3(nb), dim3(kBlock), 0, s, c, b, step, (const float*)pre, (float*)post);
-  } else {
-    if (c.dim == 3) hipLaunchKernelGGL((k_grid_update<double, 3>), dim3(nb), dim3(kBlock), 0, s, c, b, step, (const double*)pre, (double*)post);
-    else hipLaunchKernelGGL((k_grid_update<double, 2>), dim3(nb), dim3(kBlock), 0, s, c, b, step, (const double*)pre, (double*)post);
+// Sum of the staged windows covering a node: per axis the tiles (x + 1) / 4 - 1
+// and (x + 1) / 4, whose windows start at 4t - 1.
+template <typename T, int D>
+__device__ __forceinline__ void gather_windows(const KCfg& c, int inst, const int idx[3], const T* __restrict__ stg,
+                                               const uint32_t* __restrict__ tslot, T acc[4]) {
+  const int nt = c.n / kTile;
+  const uint32_t per = D == 3 ? (uint32_t)(nt * nt * nt) : (uint32_t)(nt * nt);
+  int tt[3][2], ll[3][2];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const int t1 = a < D ? (idx[a] + 1) >> 2 : 0;
+    tt[a][0] = t1 - 1; tt[a][1] = t1;
+    ll[a][0] = a < D ? idx[a] - kTile * (t1 - 1) + 1 : 0;
+    ll[a][1] = a < D ? idx[a] - kTile * t1 + 1 : 0;
   }
+#pragma unroll
+  for (int j0 = 0; j0 < 2; ++j0)
+#pragma unroll
+    for (int j1 = 0; j1 < 2; ++j1)
+#pragma unroll
+      for (int j2 = 0; j2 < (D == 3 ? 2 : 1); ++j2) {
+        const int q0 = tt[0][j0], q1 = tt[1][j1], q2 = D == 3 ? tt[2][j2] : 0;
+        if (q0 < 0 || q0 >= nt || q1 < 0 || q1 >= nt || (D == 3 && (q2 < 0 || q2 >= nt))) continue;
+        const uint32_t gt = (uint32_t)inst * per + (D == 3 ? (uint32_t)((q0 * nt + q1) * nt + q2) : (uint32_t)(q0 * nt + q1));
+        const uint32_t r = tslot[gt];
+        if (r == kNoSlot) continue;
+        const int wn = D == 3 ? (ll[0][j0] * kWin + ll[1][j1]) * kWin + ll[2][j2] : ll[0][j0] * kWin + ll[1][j1];
+        const T* rec = stg + (int64_t)r * (kNodeVals * Win<D>::nodes) + wn;
+#pragma unroll
+        for (int a = 0; a < kNodeVals; ++a) acc[a] += rec[a * Win<D>::nodes];
+      }
+}
+
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock) k_grid_update(KCfg c, Bufs b, int step, const T* __restrict__ stg,
+                                                        const uint32_t* __restrict__ tslot, T* __restrict__ gout,
+                                                        ActiveSet act, T* __restrict__ pre, T* __restrict__ post,
+                                                        uint32_t* __restrict__ list_out, uint32_t* __restrict__ count_out) {
+  constexpr int NPB = D == 3 ? kTile * kTile * kTile : kTile * kTile;
+  const uint32_t nact = *act.count;
+  if (count_out && blockIdx.x == 0 && threadIdx.x == 0) *count_out = nact;
+  const int64_t items = (int64_t)nact * NPB;
+  for (int64_t it = (int64_t)blockIdx.x * kBlock + threadIdx.x; it < items; it += (int64_t)gridDim.x * kBlock) {
+    const uint32_t gb = act.list[it / NPB];
+    const int k = (int)(it % NPB);
+    if (list_out && k == 0) list_out[it / NPB] = gb;
+    int inst, idx[3];
+    int64_t node;
+    active_node<D>(c, gb, k, inst, idx, node);
+    const int64_t gid = b.inst[inst].goff + node;
+    T acc[4] = {T(0), T(0), T(0), T(0)};
+    gather_windows<T, D>(c, inst, idx, stg, tslot, acc);
+    {
+      // particles that left their windows: read and clear
+      T* go = gout + gid * kNodeVals;
+      const Node4<T> o = ld_node(go);
+      if (o.v[3] != T(0) || o.v[0] != T(0) || o.v[1] != T(0) || o.v[2] != T(0)) {
+#pragma unroll
+        for (int a = 0; a < kNodeVals; ++a) { acc[a] += o.v[a]; go[a] = T(0); }
+      }
+    }
+    const T m = acc[3];
+    T v[3] = {T(0), T(0), T(0)};
+    if (m > T(0)) {
+      const T dt = T(b.inst[inst].dt);
+#pragma unroll
+      for (int a = 0; a < D; ++a) v[a] = acc[a] / m;
+      v[1] += dt * T(c.gravity);
+      if (D == 3 && c.shovel) {
+        const Blade<T> bl = load_blade<T>(b.poses, inst, c.max_steps, step);
+        const T xi[3] = {T(idx[0]) * T(c.dx), T(idx[1]) * T(c.dx), T(idx[2]) * T(c.dx)};
+        const T half[3] = {T(c.half[0]), T(c.half[1]), T(c.half[2])};
+        SDF<T> f;
+        sdf_eval<T>(bl, half, xi, f);
+        if (f.phi < T(c.skin)) {
+          T vs[3];
+          blade_velocity<T>(bl, xi, vs);
+          coulomb_forward<T>(vs, f.n, T(c.mu_b), v);
+        }
+      }
+      bool wall = false;
+#pragma unroll
+      for (int a = 0; a < D; ++a) wall |= (idx[a] < c.bound) || (idx[a] >= c.n - c.bound);
+      if (wall) v[0] = v[1] = v[2] = T(0);
+    }
+#pragma unroll
+    for (int a = 0; a < kNodeVals; ++a) pre[gid * kNodeVals + a] = acc[a];
+    post[gid * kNodeVals + 0] = v[0];
+    post[gid * kNodeVals + 1] = v[1];
+    post[gid * kNodeVals + 2] = v[2];
+    post[gid * kNodeVals + 3] = m;
+  }
+}
+
+static unsigned active_grid(const KCfg& c) {
+  const int tshift = c.dim == 3 ? 6 : 4;
+  const int64_t total_tiles = (c.nodes >> tshift) * c.n_inst;
+  const int64_t items = total_tiles << tshift;
+  const int64_t nb = (items + kBlock - 1) / kBlock;
+  return (unsigned)(nb < 4096 ? nb : 4096);
+}
+
+void launch_grid_update(int prec, const KCfg& c, const Bufs& b, int step, const Staging& stg, void* gout,
+                        const ActiveSet& act, void* pre, void* post, uint32_t* list_out, uint32_t* count_out,
+                        hipStream_t s) {
+  const unsigned nb = active_grid(c);
+#define DDM_GU(T, DD)                                                                                              \
+  hipLaunchKernelGGL((k_grid_update<T, DD>), dim3(nb), dim3(kBlock), 0, s, c, b, step, (const T*)stg.win, stg.tslot, \
+                     (T*)gout, act, (T*)pre, (T*)post, list_out, count_out)
+  if (prec == 0) {
+    if (c.dim == 3) DDM_GU(float, 3); else DDM_GU(float, 2);
+  } else {
+    if (c.dim == 3) DDM_GU(double, 3); else DDM_GU(double, 2);
+  }
+#undef DDM_GU
 }
 
 // ---------------------------------------------------------------------------
@@ -610,20 +819,39 @@ void launch_reset_pid(const Bufs& b, int nblk, uint32_t* pid, hipStream_t s) {
   hipLaunchKernelGGL(k_reset_pid, dim3(nblk), dim3(kBlock), 0, s, b, pid);
 }
 
-template <typename T>
-__global__ void k_grid_export(int64_t total, const T* pre, const T* post, T* out) {
+// Dense export; nodes outside the active blocks of the last sub-step hold no
+// mass and are exported as zeros.
+template <typename T, int D>
+__global__ void k_grid_export(KCfg c, const T* pre, const T* post, const uint32_t* mask, T* out) {
   const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (g >= total) return;
-  out[g * 8 + 0] = pre[g * 4 + 3];
-  for (int a = 0; a < 3; ++a) { out[g * 8 + 1 + a] = pre[g * 4 + a]; out[g * 8 + 4 + a] = post[g * 4 + a]; }
+  if (g >= c.nodes * c.n_inst) return;
+  const int inst = (int)(g / c.nodes);
+  int idx[3];
+  node_coords<D>(g - (int64_t)inst * c.nodes, c.n, idx);
+  const int nt = c.n / kTile;
+  const int64_t lb = D == 3 ? ((int64_t)(idx[0] / kTile) * nt + idx[1] / kTile) * nt + idx[2] / kTile
+                            : (int64_t)(idx[0] / kTile) * nt + idx[1] / kTile;
+  const bool act = mask[(c.nodes >> (D == 3 ? 6 : 4)) * inst + lb] != 0u;
+  out[g * 8 + 0] = act ? pre[g * 4 + 3] : T(0);
+  for (int a = 0; a < 3; ++a) {
+    out[g * 8 + 1 + a] = act ? pre[g * 4 + a] : T(0);
+    out[g * 8 + 4 + a] = act ? post[g * 4 + a] : T(0);
+  }
   out[g * 8 + 7] = T(0);
 }
 
-void launch_grid_export(int prec, const KCfg& c, const void* pre, const void* post, void* out, hipStream_t s) {
+void launch_grid_export(int prec, const KCfg& c, const void* pre, const void* post, const uint32_t* mask, void* out,
+                        hipStream_t s) {
   const int64_t total = c.nodes * c.n_inst;
   const unsigned nb = (unsigned)((total + kBlock - 1) / kBlock);
-  if (prec == 0) hipLaunchKernelGGL((k_grid_export<float>), dim3(nb), dim3(kBlock), 0, s, total, (const float*)pre, (const float*)post, (float*)out);
-  else hipLaunchKernelGGL((k_grid_export<double>), dim3(nb), dim3(kBlock), 0, s, total, (const double*)pre, (const double*)post, (double*)out);
+#define DDM_GX(T, DD) \
+  hipLaunchKernelGGL((k_grid_export<T, DD>), dim3(nb), dim3(kBlock), 0, s, c, (const T*)pre, (const T*)post, mask, (T*)out)
+  if (prec == 0) {
+    if (c.dim == 3) DDM_GX(float, 3); else DDM_GX(float, 2);
+  } else {
+    if (c.dim == 3) DDM_GX(double, 3); else DDM_GX(double, 2);
+  }
+#undef DDM_GX
 }
 
 // ---------------------------------------------------------------------------
@@ -794,7 +1022,7 @@ void launch_loss(int prec, const KCfg& c, const Bufs& b, int nblk, const void* s
                  int final_step, const LossBufs& L, hipStream_t s) {
   const int npix = c.dim == 3 ? c.hm_res * c.hm_res : c.hm_res;
   launch_fill_zero(L.hm_bits, (int64_t)c.n_inst * npix, 8, s);
-  launch_fill(L.owner, (int64_t)c.n_inst * npix, 0xFFFFFFFFu, s);
+  launch_fill_u32(L.owner, (int64_t)c.n_inst * npix, 0xFFFFFFFFu, s);
   launch_fill_zero(L.region, c.n_inst, 8, s);
 #define DDM_LOSS(T, DD)                                                                                      \
   hipLaunchKernelGGL((k_hm_max<T, DD>), dim3(nblk), dim3(kBlock), 0, s, c, b, state, L.hm_bits);            \
@@ -1024,30 +1252,43 @@ void launch_g2p_adj(int prec, const KCfg& c, const Bufs& b, const TileList& tl, 
 // sub-step are reduced over the contact nodes.
 // ---------------------------------------------------------------------------
 template <typename T, int D>
-__global__ void __launch_bounds__(kBlock) k_grid_adj(KCfg c, Bufs b, int step, const T* __restrict__ pre,
-                                                     const T* __restrict__ gvb, T* __restrict__ gb, double* pose_bar) {
-  const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const int64_t total = c.nodes * c.n_inst;
-  // the whole block belongs to one instance: nodes per instance is a multiple of kBlock
-  const int inst = (int)(((int64_t)blockIdx.x * kBlock) / c.nodes);
-  double pb[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  bool any = false;
-  if (gid < total) {
-    const int64_t node = gid - (int64_t)inst * c.nodes;
-    const T m = pre[gid * kNodeVals + 3];
+__global__ void __launch_bounds__(kBlock) k_grid_adj(KCfg c, Bufs b, int step, const uint32_t* __restrict__ list,
+                                                     const uint32_t* __restrict__ count, const T* __restrict__ pre,
+                                                     T* __restrict__ gvb, T* __restrict__ gb, double* pose_bar) {
+  constexpr int NPB = D == 3 ? kTile * kTile * kTile : kTile * kTile;
+  const int64_t items = (int64_t)(*count) * NPB;
+  // 3D: the 64 lanes of a wave take the 64 nodes of one block, hence one instance
+  for (int64_t it = (int64_t)blockIdx.x * kBlock + threadIdx.x; it < items; it += (int64_t)gridDim.x * kBlock) {
+    int inst, idx[3];
+    int64_t node;
+    active_node<D>(c, list[it / NPB], (int)(it % NPB), inst, idx, node);
+    const int64_t gid = b.inst[inst].goff + node;
+    double pb[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    bool any = false;
+    const Node4<T> pr = ld_node(pre + gid * kNodeVals);
+    T vb[3] = {T(0), T(0), T(0)};
+    {
+      T* gv = gvb + gid * kNodeVals;
+      const Node4<T> o = ld_node(gv);
+#pragma unroll
+      for (int a = 0; a < D; ++a) vb[a] = o.v[a];
+      if (o.v[0] != T(0) || o.v[1] != T(0) || o.v[2] != T(0)) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) gv[a] = T(0);
+      }
+    }
+    const T m = pr.v[3];
     T ub[3] = {T(0), T(0), T(0)};
     T mb = T(0);
     if (m > T(0)) {
-      int idx[3];
-      node_coords<D>(node, c.n, idx);
       bool wall = false;
 #pragma unroll
       for (int a = 0; a < D; ++a) wall |= (idx[a] < c.bound) || (idx[a] >= c.n - c.bound);
       if (!wall) {
-        T vb[3] = {T(0), T(0), T(0)}, u[3] = {T(0), T(0), T(0)};
+        T u[3] = {T(0), T(0), T(0)};
         const T dt = T(b.inst[inst].dt);
 #pragma unroll
-        for (int a = 0; a < D; ++a) { vb[a] = gvb[gid * kNodeVals + a]; u[a] = pre[gid * kNodeVals + a] / m; }
+        for (int a = 0; a < D; ++a) u[a] = pr.v[a] / m;
         u[1] += dt * T(c.gravity);
 #pragma unroll
         for (int a = 0; a < 3; ++a) ub[a] = vb[a];
@@ -1074,7 +1315,7 @@ __global__ void __launch_bounds__(kBlock) k_grid_adj(KCfg c, Bufs b, int step, c
         }
         T dot = T(0);
 #pragma unroll
-        for (int a = 0; a < D; ++a) dot += ub[a] * pre[gid * kNodeVals + a];
+        for (int a = 0; a < D; ++a) dot += ub[a] * pr.v[a];
         mb = -dot / (m * m);
 #pragma unroll
         for (int a = 0; a < D; ++a) ub[a] = ub[a] / m;
@@ -1084,21 +1325,29 @@ __global__ void __launch_bounds__(kBlock) k_grid_adj(KCfg c, Bufs b, int step, c
     gb[gid * kNodeVals + 1] = ub[1];
     gb[gid * kNodeVals + 2] = ub[2];
     gb[gid * kNodeVals + 3] = mb;
+    if (D == 3 && c.shovel && __any(any)) {
+      double* dst = pose_bar + ((int64_t)inst * c.max_steps + step) * 8;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const double sum = wave_sum(pb[k]);
+        if ((threadIdx.x & 63) == 0 && sum != 0.0) atomicAdd(dst + k, sum);
+      }
+    }
   }
-  if (D == 3 && c.shovel && __syncthreads_or(any)) block_accumulate<8>(pb, pose_bar + ((int64_t)inst * c.max_steps + step) * 8);
 }
 
-void launch_grid_adj(int prec, const KCfg& c, const Bufs& b, int step, const void* pre, const void* gvb, void* gb,
-                     double* pose_bar, hipStream_t s) {
-  const int64_t total = c.nodes * c.n_inst;
-  const unsigned nb = (unsigned)((total + kBlock - 1) / kBlock);
+void launch_grid_adj(int prec, const KCfg& c, const Bufs& b, int step, const uint32_t* list, const uint32_t* count,
+                     const void* pre, void* gvb, void* gb, double* pose_bar, hipStream_t s) {
+  const unsigned nb = active_grid(c);
+#define DDM_GA(T, DD)                                                                                             \
+  hipLaunchKernelGGL((k_grid_adj<T, DD>), dim3(nb), dim3(kBlock), 0, s, c, b, step, list, count, (const T*)pre,  \
+                     (T*)gvb, (T*)gb, pose_bar)
   if (prec == 0) {
-    if (c.dim == 3) hipLaunchKernelGGL((k_grid_adj<float, 3>), dim3(nb), dim3(kBlock), 0, s, c, b, step, (const float*)pre, (const float*)gvb, (float*)gb, pose_bar);
-    else hipLaunchKernelGGL((k_grid_adj<float, 2>), dim3(nb), dim3(kBlock), 0, s, c, b, step, (const float*)pre, (const float*)gvb, (float*)gb, pose_bar);
+    if (c.dim == 3) DDM_GA(float, 3); else DDM_GA(float, 2);
   } else {
-    if (c.dim == 3) hipLaunchKernelGGL((k_grid_adj<double, 3>), dim3(nb), dim3(kBlock), 0, s, c, b, step, (const double*)pre, (const double*)gvb, (double*)gb, pose_bar);
-    else hipLaunchKernelGGL((k_grid_adj<double, 2>), dim3(nb), dim3(kBlock), 0, s, c, b, step, (const double*)pre, (const double*)gvb, (double*)gb, pose_bar);
+    if (c.dim == 3) DDM_GA(double, 3); else DDM_GA(double, 2);
   }
+#undef DDM_GA
 }
 
 // ---------------------------------------------------------------------------

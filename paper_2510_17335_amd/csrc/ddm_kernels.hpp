@@ -11,16 +11,23 @@ constexpr int kBlock = 256;          // particle kernels: threads per block, and
 constexpr int kNodeVals = 4;         // node record: mv[0..2] (or v), m
 constexpr int kTile = 4;             // binning tile edge in cells
 constexpr int kWin = kTile + 4;      // LDS window edge in nodes: tile + stencil + 1-cell drift each side
-#ifndef DDM_CHUNK
-#define DDM_CHUNK 1024
-#endif
-constexpr int kChunk = DDM_CHUNK;    // particles per tile-list record (a multiple of kBlock); larger
-                                     // tiles are split, so one workgroup's window flush covers
-                                     // up to kChunk particles
 
 // An occupied tile: slots [start, end) of the sorted state, global tile id.
+// Tiles and grid node blocks share one index space: tile t holds the cells
+// [4t, 4t + 4) per axis and node block t the nodes [4t, 4t + 4).
 struct TileRec { uint32_t start, end, tile; };
 struct TileList { const TileRec* list; const uint32_t* count; };
+
+// Window of a tile in the staging buffer: record r holds kNodeVals planes of
+// kWin^D nodes (node (l0, l1[, l2]) of the window at ((l0 kWin + l1) kWin + l2)),
+// covering grid nodes [4t - 1, 4t + 7) per axis.  tslot[t] is the record of
+// tile t, or kNoSlot.
+constexpr uint32_t kNoSlot = 0xFFFFFFFFu;
+struct Staging { void* win; const uint32_t* tslot; };
+
+// Active node blocks of a sub-step: every block that can hold mass.  mask[t]
+// is nonzero for listed blocks; list[0 .. *count) holds each such block once.
+struct ActiveSet { uint32_t* mask; uint32_t* list; uint32_t* count; };
 
 // Per-instance constants on the device (double; kernels cast to their type).
 struct InstDev {
@@ -59,21 +66,32 @@ struct Bufs {
 
 // Forward sub-step pieces.  state_* are SoA particle states (stride ntot).
 void launch_fill_zero(void* p, int64_t count, int elem_bytes, hipStream_t s);
+void launch_fill_u32(void* p, int64_t words, uint32_t value, hipStream_t s);
 void launch_init_state(int prec, const KCfg& c, const Bufs& b, int nblk, const void* x0, void* state,
                        uint32_t* pid, hipStream_t s);
+// P2G writes every occupied tile's window to the staging buffer; particles
+// that left their window add to the dense outlier grid gout (kept zero
+// otherwise) and add their node blocks to the active set.
 // tau_out (may be NULL): the Kirchhoff stress of every particle, symmetric
 // rows (00, 01, 02, 11, 12, 22; 2D: 00, 01, 11) of stride ntot, for the reverse pass.
 void launch_p2g(int prec, const KCfg& c, const Bufs& b, const TileList& tl, int nwg, const void* st_in, void* st_out,
-                void* grid, void* tau_out, hipStream_t s);
-void launch_grid_update(int prec, const KCfg& c, const Bufs& b, int step, const void* grid_pre, void* grid_post,
-                        hipStream_t s);
+                const Staging& stg, void* gout, const ActiveSet& act, void* tau_out, hipStream_t s);
+// Grid update over the active blocks: sums the staged windows and the outlier
+// grid (zeroing what it read) into grid_pre (m, mv), writes grid_post (v, m).
+// list_out / count_out (may be NULL) receive a copy of the active list.
+void launch_grid_update(int prec, const KCfg& c, const Bufs& b, int step, const Staging& stg, void* gout,
+                        const ActiveSet& act, void* grid_pre, void* grid_post, uint32_t* list_out,
+                        uint32_t* count_out, hipStream_t s);
+// Active set of a fresh binning: the blocks of the occupied tiles and of their
+// neighbours (a tile's window reaches one block beyond it on each side).
+void launch_active_set(const KCfg& c, const TileList& tl, const ActiveSet& act, hipStream_t s);
 void launch_g2p(int prec, const KCfg& c, const Bufs& b, int nblk, const void* st_in, void* st_out,
                 const void* grid_post, hipStream_t s);
 void launch_export_state(const KCfg& c, const Bufs& b, int nblk, int rows, int elem_bytes, const void* in, void* out,
                          const uint32_t* pid, hipStream_t s);
 void launch_reset_pid(const Bufs& b, int nblk, uint32_t* pid, hipStream_t s);
-void launch_grid_export(int prec, const KCfg& c, const void* grid_pre, const void* grid_post, void* out,
-                        hipStream_t s);
+void launch_grid_export(int prec, const KCfg& c, const void* grid_pre, const void* grid_post, const uint32_t* mask,
+                        void* out, hipStream_t s);
 
 // Loss (height map + scoop mass) and its seed adjoint.
 struct LossBufs {
@@ -94,8 +112,9 @@ void launch_loss_seed(int prec, const KCfg& c, const Bufs& b, int nblk, const vo
 // Adjoint sub-step pieces (reverse order: g2p_adj, grid_adj, p2g_adj).
 void launch_g2p_adj(int prec, const KCfg& c, const Bufs& b, const TileList& tl, int nwg, const void* st,
                     const void* grid_post, const void* adj_next, void* adj_cur, void* gvb, hipStream_t s);
-void launch_grid_adj(int prec, const KCfg& c, const Bufs& b, int step, const void* grid_pre, const void* gvb,
-                     void* gb, double* pose_bar, hipStream_t s);
+// Over the active blocks (list, count) of the sub-step; zeroes gvb where it read it.
+void launch_grid_adj(int prec, const KCfg& c, const Bufs& b, int step, const uint32_t* list, const uint32_t* count,
+                     const void* grid_pre, void* gvb, void* gb, double* pose_bar, hipStream_t s);
 void launch_p2g_adj(int prec, const KCfg& c, const Bufs& b, int nblk, const void* st, const void* tau, const void* gb,
                     const void* adj_next, void* adj_cur, double* pacc, hipStream_t s);
 void launch_grad_final(const KCfg& c, const InstDev* inst, const double* pacc, const double* pose_bar,
@@ -113,7 +132,8 @@ void launch_gather(int elem_bytes, const void* in, void* out, const uint32_t* pe
                    const uint32_t* pid_in, uint32_t* pid_out, hipStream_t s);
 void launch_unpermute(int elem_bytes, const void* in, void* out, const uint32_t* perm, int rows, int64_t ntot,
                       hipStream_t s);
+// One record per occupied tile, and tslot (record of each tile, or kNoSlot).
 void launch_tile_list(const KCfg& c, const uint32_t* sorted_keys, uint32_t* tstart, uint32_t* tend, TileRec* list,
-                      uint32_t* count, hipStream_t s);
+                      uint32_t* count, uint32_t* tslot, hipStream_t s);
 
 }  // namespace ddm

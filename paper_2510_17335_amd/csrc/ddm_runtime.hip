@@ -48,9 +48,11 @@ struct Layout {
   size_t adj0 = 0, adj1 = 0, gvb = 0, gb = 0, pacc = 0, pose_bar = 0;
   size_t hm_bits = 0, owner = 0, target = 0, hm_val = 0, dldh = 0, region = 0, dldm = 0, loss = 0;
   size_t keys0 = 0, keys1 = 0, vals0 = 0, vals1 = 0, hist = 0, sums = 0, tstart = 0, tend = 0, tiles = 0, tcount = 0;
+  size_t tslot = 0, staging = 0, gout = 0, amask = 0, alist = 0, acount = 0, seg_alist = 0, seg_acount = 0;
   size_t total = 0;
   size_t state_bytes = 0, grid_bytes = 0;
   int64_t ntot = 0, nblk = 0, total_tiles = 0, max_chunks = 0;
+  size_t win_bytes = 0;               // one staged window
   int n_ckpt = 0, K = 1, rows = 0, esz = 4, nwg = 1;
   uint32_t max_key = 0;
 };
@@ -82,11 +84,11 @@ Layout make_layout(const ddm_config& c, int n_inst, const ddm_instance* in) {
   const int64_t tiles_per_inst = nodes / (D == 3 ? ddm::kTile * ddm::kTile * ddm::kTile : ddm::kTile * ddm::kTile);
   L.total_tiles = tiles_per_inst * n_inst;
   L.max_key = (uint32_t)((uint64_t)n_inst * (uint64_t)(nodes + 1) - 1);
-  // Chunk records: occupied tiles split into chunks of at most kBlock
-  // particles (at most one partial chunk per tile).  Workgroups of the tile
-  // kernels: about one per expected chunk, grid-stride beyond that.
-  L.max_chunks = L.total_tiles + L.nblk;
-  L.nwg = (int)std::max<int64_t>(1, std::min<int64_t>(L.max_chunks, L.nblk + L.nblk / 2 + 256));
+  // One record per occupied tile.  Workgroups of the tile kernels: about one
+  // per expected occupied tile, grid-stride beyond that.
+  L.max_chunks = L.total_tiles;
+  L.nwg = (int)std::max<int64_t>(1, std::min<int64_t>(L.total_tiles, L.nblk + 1024));
+  L.win_bytes = (size_t)ddm::kNodeVals * (D == 3 ? ddm::kWin * ddm::kWin * ddm::kWin : ddm::kWin * ddm::kWin) * b;
   L.grid_bytes = (size_t)n_inst * nodes * ddm::kNodeVals * b;
   L.K = std::max(1, (int)c.checkpoint_every);
   L.n_ckpt = (c.max_steps + L.K - 1) / L.K + 1;
@@ -135,6 +137,14 @@ Layout make_layout(const ddm_config& c, int n_inst, const ddm_instance* in) {
   L.tend = cv.take(sizeof(uint32_t) * L.total_tiles);
   L.tiles = cv.take(sizeof(ddm::TileRec) * L.max_chunks);
   L.tcount = cv.take(sizeof(uint32_t));
+  L.tslot = cv.take(sizeof(uint32_t) * L.total_tiles);
+  L.staging = cv.take(L.win_bytes * L.total_tiles);
+  L.gout = cv.take(L.grid_bytes);
+  L.amask = cv.take(sizeof(uint32_t) * L.total_tiles);
+  L.alist = cv.take(sizeof(uint32_t) * L.total_tiles);
+  L.acount = cv.take(sizeof(uint32_t));
+  L.seg_alist = cv.take(sizeof(uint32_t) * L.total_tiles * L.K);
+  L.seg_acount = cv.take(sizeof(uint32_t) * L.K);
   L.total = cv.take(0);
   return L;
 }
@@ -255,6 +265,7 @@ struct ddm_ctx {
   int64_t rec_k0 = 0, rec_n = 0;
   bool loss_ready = false;
   bool need_sort = true;          // re-bin before the next sub-step
+  bool grid_valid = false;        // grid_pre/grid_post and the active set are those of the last sub-step
   std::vector<char> rec_sorted;   // per recorded step: binned at its start
   // kernel timing
   bool timing = false;
@@ -270,6 +281,12 @@ struct ddm_ctx {
     return ddm::TileList{at<const ddm::TileRec>(L.seg_tiles + sizeof(ddm::TileRec) * L.max_chunks * j),
                          at<const uint32_t>(L.seg_tcount + sizeof(uint32_t) * j)};
   }
+  ddm::Staging staging() const { return ddm::Staging{at<void>(L.staging), at<const uint32_t>(L.tslot)}; }
+  ddm::ActiveSet active() const {
+    return ddm::ActiveSet{at<uint32_t>(L.amask), at<uint32_t>(L.alist), at<uint32_t>(L.acount)};
+  }
+  uint32_t* seg_alist(int j) const { return at<uint32_t>(L.seg_alist + sizeof(uint32_t) * L.total_tiles * j); }
+  uint32_t* seg_acount(int j) const { return at<uint32_t>(L.seg_acount + sizeof(uint32_t) * j); }
   ddm::Bufs bufs() const {
     ddm::Bufs b;
     b.inst = at<const ddm::InstDev>(L.inst);
@@ -383,7 +400,8 @@ void resolve_events(ddm_ctx* x) {
 
 // Bins the particles of `state` in place: exact cell keys, stable radix sort
 // by (instance, tile, cell), gather of the state rows (and ids) into sorted
-// order, and the occupied-tile list.  When perm_out / tiles_out are given the
+// order, the occupied-tile list with each tile's staging record, and the
+// active node blocks.  When perm_out / tiles_out are given the
 // permutation and the tile list are also stored there (for the reverse pass).
 ddm_status bin_state(ddm_ctx* x, void* state, uint32_t* pid, uint32_t* perm_out, ddm::TileRec* tiles_out,
                      uint32_t* tcount_out) {
@@ -398,7 +416,8 @@ ddm_status bin_state(ddm_ctx* x, void* state, uint32_t* pid, uint32_t* perm_out,
   DDM_HIP(hipMemcpyAsync(state, x->at(L.scratch), L.state_bytes, hipMemcpyDeviceToDevice, st));
   if (pid) DDM_HIP(hipMemcpyAsync(pid, x->at(L.pid_tmp), sizeof(uint32_t) * L.ntot, hipMemcpyDeviceToDevice, st));
   ddm::launch_tile_list(x->kc, keys[r], x->at<uint32_t>(L.tstart), x->at<uint32_t>(L.tend), x->at<ddm::TileRec>(L.tiles),
-                        x->at<uint32_t>(L.tcount), st);
+                        x->at<uint32_t>(L.tcount), x->at<uint32_t>(L.tslot), st);
+  ddm::launch_active_set(x->kc, x->tiles(), x->active(), st);
   if (perm_out) DDM_HIP(hipMemcpyAsync(perm_out, vals[r], sizeof(uint32_t) * L.ntot, hipMemcpyDeviceToDevice, st));
   if (tiles_out) {
     DDM_HIP(hipMemcpyAsync(tiles_out, x->at(L.tiles), sizeof(ddm::TileRec) * L.max_chunks, hipMemcpyDeviceToDevice, st));
@@ -408,14 +427,18 @@ ddm_status bin_state(ddm_ctx* x, void* state, uint32_t* pid, uint32_t* perm_out,
 }
 
 // One forward sub-step from st_in to st_out (may alias) with the given tile
-// list; grids given.
+// list; grids given.  The reverse pass also keeps the stress (tau_out) and the
+// active blocks of the sub-step (list_out, count_out).
 ddm_status forward_step(ddm_ctx* x, int64_t step, const ddm::TileList& tl, const void* st_in, void* st_out,
-                        void* gpre, void* gpost, void* tau_out = nullptr) {
+                        void* gpre, void* gpost, void* tau_out = nullptr, uint32_t* list_out = nullptr,
+                        uint32_t* count_out = nullptr) {
   const ddm::Bufs b = x->bufs();
-  const int esz = x->prec ? 8 : 4;
-  { Timed t(x, 7); ddm::launch_fill_zero(gpre, (int64_t)x->L.grid_bytes / esz, esz, x->stream); }
-  { Timed t(x, 0); ddm::launch_p2g(x->prec, x->kc, b, tl, x->L.nwg, st_in, st_out, gpre, tau_out, x->stream); }
-  { Timed t(x, 1); ddm::launch_grid_update(x->prec, x->kc, b, (int)step, gpre, gpost, x->stream); }
+  const ddm::Staging stg = x->staging();
+  const ddm::ActiveSet act = x->active();
+  void* gout = x->at(x->L.gout);
+  { Timed t(x, 0); ddm::launch_p2g(x->prec, x->kc, b, tl, x->L.nwg, st_in, st_out, stg, gout, act, tau_out, x->stream); }
+  { Timed t(x, 1); ddm::launch_grid_update(x->prec, x->kc, b, (int)step, stg, gout, act, gpre, gpost, list_out,
+                                           count_out, x->stream); }
   { Timed t(x, 2); ddm::launch_g2p(x->prec, x->kc, b, (int)x->L.nblk, st_in, st_out, gpost, x->stream); }
   return launch_status();
 }
@@ -562,7 +585,10 @@ ddm_status ddm_init_state(ddm_ctx* x, const void* x0_dev) {
   if (!x || !x0_dev) return fail(DDM_EINVAL, "NULL argument");
   ddm::launch_init_state(x->prec, x->kc, x->bufs(), (int)x->L.nblk, x0_dev, x->at(x->L.cur), x->at<uint32_t>(x->L.pid),
                          x->stream);
-  DDM_HIP(hipMemsetAsync(x->at(x->L.err), 0, sizeof(ddm::DevErr), x->stream));
+  // fill kernels rather than memset nodes, so that the call can be captured in a graph
+  ddm::launch_fill_zero(x->at(x->L.err), sizeof(ddm::DevErr) / 4, 4, x->stream);
+  ddm::launch_fill_zero(x->at(x->L.gout), (int64_t)(x->L.grid_bytes / 4), 4, x->stream);
+  x->grid_valid = false;
   x->steps = 0;
   x->initialised = true;
   x->recorded = false;
@@ -587,6 +613,7 @@ ddm_status ddm_step(ddm_ctx* x, int32_t n_steps) {
                                       x->at(x->L.grid_post));
     if (s != DDM_OK) return s;
     ++x->steps;
+    x->grid_valid = true;
   }
   x->recorded = false;
   x->loss_ready = false;
@@ -619,6 +646,7 @@ ddm_status ddm_rollout(ddm_ctx* x, int32_t n_steps) {
                                       x->at(x->L.grid_post));
     if (s != DDM_OK) return s;
     ++x->steps;
+    x->grid_valid = true;
   }
   x->recorded = true;
   x->rec_k0 = k0;
@@ -652,6 +680,8 @@ ddm_status ddm_backward(ddm_ctx* x, const double* dloss_dev, double* grad_dev) {
   hipStream_t st = x->stream;
   ddm::launch_fill_zero(x->at(L.pacc), (int64_t)8 * x->n_inst, 8, st);
   ddm::launch_fill_zero(x->at(L.pose_bar), (int64_t)8 * x->n_inst * x->cfg.max_steps, 8, st);
+  // the v-bar grid starts at zero; each grid adjoint step clears what it read
+  { Timed t(x, 7); ddm::launch_fill_zero(x->at(L.gvb), (int64_t)L.grid_bytes / esz, esz, st); }
   void* adj[2] = {x->at(L.adj0), x->at(L.adj1)};
   int cur = 0;
   ddm::launch_loss_seed(x->prec, x->kc, b, (int)L.nblk, x->at(L.cur), x->at<uint32_t>(L.pid), (int)x->steps - 1,
@@ -680,15 +710,15 @@ ddm_status ddm_backward(ddm_ctx* x, const double* dloss_dev, double* grad_dev) {
         last = j;
       }
       tl_of[j] = last;
-      const ddm_status s = forward_step(x, k0 + s0 + j, x->seg_tiles(last), slot(j), slot(j + 1), gpre(j), gpost(j), tau(j));
+      const ddm_status s = forward_step(x, k0 + s0 + j, x->seg_tiles(last), slot(j), slot(j + 1), gpre(j), gpost(j), tau(j),
+                                          x->seg_alist(j), x->seg_acount(j));
       if (s != DDM_OK) return s;
     }
     for (int j = len - 1; j >= 0; --j) {
       const ddm::TileList tl = x->seg_tiles(tl_of[j]);
-      { Timed t(x, 7); ddm::launch_fill_zero(x->at(L.gvb), (int64_t)L.grid_bytes / esz, esz, st); }
       { Timed t(x, 4); ddm::launch_g2p_adj(x->prec, x->kc, b, tl, L.nwg, slot(j), gpost(j), adj[cur], adj[1 - cur], x->at(L.gvb), st); }
-      { Timed t(x, 5); ddm::launch_grid_adj(x->prec, x->kc, b, (int)(k0 + s0 + j), gpre(j), x->at(L.gvb), x->at(L.gb),
-                                            x->at<double>(L.pose_bar), st); }
+      { Timed t(x, 5); ddm::launch_grid_adj(x->prec, x->kc, b, (int)(k0 + s0 + j), x->seg_alist(j), x->seg_acount(j),
+                                            gpre(j), x->at(L.gvb), x->at(L.gb), x->at<double>(L.pose_bar), st); }
       { Timed t(x, 6); ddm::launch_p2g_adj(x->prec, x->kc, b, (int)L.nblk, slot(j), tau(j), x->at(L.gb), adj[cur], adj[1 - cur],
                                            x->at<double>(L.pacc), st); }
       if (x->rec_sorted[(size_t)(s0 + j)]) {
@@ -705,6 +735,10 @@ ddm_status ddm_backward(ddm_ctx* x, const double* dloss_dev, double* grad_dev) {
   ddm::launch_grad_final(x->kc, x->at<const ddm::InstDev>(L.inst), x->at<const double>(L.pacc),
                          x->at<const double>(L.pose_bar), x->at<const double>(L.pose_jac), (int)(k0 + n), dloss_dev,
                          grad_dev, st);
+  // the replay re-binned segment states: the current state is binned afresh
+  // before its next sub-step, and the last forward grid is gone
+  x->need_sort = true;
+  x->grid_valid = false;
   return launch_status();
 }
 
@@ -720,6 +754,8 @@ ddm_status ddm_set_state(ddm_ctx* x, const void* state_dev) {
   if (!x->initialised) return fail(DDM_ESTATE, "ddm_init_state first");
   DDM_HIP(hipMemcpyAsync(x->at(x->L.cur), state_dev, x->L.state_bytes, hipMemcpyDeviceToDevice, x->stream));
   ddm::launch_reset_pid(x->bufs(), (int)x->L.nblk, x->at<uint32_t>(x->L.pid), x->stream);
+  ddm::launch_fill_zero(x->at(x->L.gout), (int64_t)(x->L.grid_bytes / 4), 4, x->stream);
+  x->grid_valid = false;
   x->recorded = false;
   x->loss_ready = false;
   x->need_sort = true;
@@ -741,7 +777,9 @@ ddm_status ddm_bin_keys(ddm_ctx* x, uint32_t* keys_dev, uint32_t* perm_dev) {
 
 ddm_status ddm_get_grid(ddm_ctx* x, void* grid_dev) {
   if (!x || !grid_dev) return fail(DDM_EINVAL, "NULL argument");
-  ddm::launch_grid_export(x->prec, x->kc, x->at(x->L.grid_pre), x->at(x->L.grid_post), grid_dev, x->stream);
+  if (!x->grid_valid) return fail(DDM_ESTATE, "ddm_get_grid needs a forward sub-step since the last ddm_backward");
+  ddm::launch_grid_export(x->prec, x->kc, x->at(x->L.grid_pre), x->at(x->L.grid_post), x->at<const uint32_t>(x->L.amask),
+                          grid_dev, x->stream);
   return launch_status();
 }
 

@@ -298,33 +298,70 @@ __global__ void k_tile_bounds(KCfg c, const uint32_t* keys, int tshift, uint32_t
   if (tn != t) tend[t] = (uint32_t)(j + 1);
 }
 
-// One record per chunk of at most kChunk particles of an occupied tile, so
-// that a workgroup handles one chunk and very full tiles spread over several.
+// One record per occupied tile (a workgroup takes a whole tile, however many
+// particles it holds), and the record of each tile in tslot.
 __global__ void k_tile_list(int64_t total_tiles, const uint32_t* tstart, const uint32_t* tend, TileRec* list,
-                            uint32_t* count) {
+                            uint32_t* count, uint32_t* tslot) {
   const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (t >= total_tiles) return;
   const uint32_t e = tend[t];
   if (e == 0u) return;
-  const uint32_t s = tstart[t];
-  const uint32_t nch = (e - s + kChunk - 1) / kChunk;
-  const uint32_t idx = atomicAdd(count, nch);
-  for (uint32_t k = 0; k < nch; ++k) {
-    const uint32_t a = s + k * kChunk;
-    list[idx + k] = TileRec{a, min(e, a + (uint32_t)kChunk), (uint32_t)t};
-  }
+  const uint32_t idx = atomicAdd(count, 1u);
+  list[idx] = TileRec{tstart[t], e, (uint32_t)t};
+  tslot[t] = idx;
 }
 
 void launch_tile_list(const KCfg& c, const uint32_t* sorted_keys, uint32_t* tstart, uint32_t* tend, TileRec* list,
-                      uint32_t* count, hipStream_t s) {
+                      uint32_t* count, uint32_t* tslot, hipStream_t s) {
   const int tshift = c.dim == 3 ? 6 : 4;   // log2(kTile^D)
   const int64_t total_tiles = (c.nodes >> tshift) * c.n_inst;
   launch_fill_zero(tend, total_tiles, 4, s);
   launch_fill_zero(count, 1, 4, s);
+  launch_fill_u32(tslot, total_tiles, kNoSlot, s);
   hipLaunchKernelGGL(k_tile_bounds, dim3((unsigned)((c.ntot + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, c,
                      sorted_keys, tshift, tstart, tend);
   hipLaunchKernelGGL(k_tile_list, dim3((unsigned)((total_tiles + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
-                     total_tiles, tstart, tend, list, count);
+                     total_tiles, tstart, tend, list, count, tslot);
+}
+
+// Active set after a binning: mark the 3^D blocks around every occupied tile,
+// then list the marked blocks.
+__global__ void k_mark_active(KCfg c, TileList tl, int64_t max_records, uint32_t* mask) {
+  const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (r >= max_records || r >= (int64_t)*tl.count) return;
+  const int D = c.dim, nt = c.n / kTile;
+  const uint32_t per = D == 3 ? (uint32_t)(nt * nt * nt) : (uint32_t)(nt * nt);
+  const uint32_t gt = tl.list[r].tile;
+  const uint32_t inst = gt / per;
+  uint32_t t = gt - inst * per;
+  int tc[3] = {0, 0, 0};
+  for (int a = D - 1; a >= 0; --a) { tc[a] = (int)(t % (uint32_t)nt); t /= (uint32_t)nt; }
+  for (int d0 = -1; d0 <= 1; ++d0)
+    for (int d1 = -1; d1 <= 1; ++d1)
+      for (int d2 = (D == 3 ? -1 : 0); d2 <= (D == 3 ? 1 : 0); ++d2) {
+        const int q[3] = {tc[0] + d0, tc[1] + d1, tc[2] + d2};
+        bool ok = true;
+        for (int a = 0; a < D; ++a) ok &= q[a] >= 0 && q[a] < nt;
+        if (!ok) continue;
+        const uint32_t lb = D == 3 ? (uint32_t)((q[0] * nt + q[1]) * nt + q[2]) : (uint32_t)(q[0] * nt + q[1]);
+        mask[inst * per + lb] = 1u;
+      }
+}
+
+__global__ void k_list_active(int64_t total_tiles, const uint32_t* mask, uint32_t* list, uint32_t* count) {
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (t >= total_tiles || mask[t] == 0u) return;
+  list[atomicAdd(count, 1u)] = (uint32_t)t;
+}
+
+void launch_active_set(const KCfg& c, const TileList& tl, const ActiveSet& act, hipStream_t s) {
+  const int tshift = c.dim == 3 ? 6 : 4;
+  const int64_t total_tiles = (c.nodes >> tshift) * c.n_inst;
+  const unsigned nb = (unsigned)((total_tiles + kBlock - 1) / kBlock);
+  launch_fill_zero(act.mask, total_tiles, 4, s);
+  launch_fill_zero(act.count, 1, 4, s);
+  hipLaunchKernelGGL(k_mark_active, dim3(nb), dim3(kBlock), 0, s, c, tl, total_tiles, act.mask);
+  hipLaunchKernelGGL(k_list_active, dim3(nb), dim3(kBlock), 0, s, total_tiles, act.mask, act.list, act.count);
 }
 
 }  // namespace ddm

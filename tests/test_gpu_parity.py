@@ -351,3 +351,43 @@ def test_largest_grid_f64(ddm, orc):
     _log("256^3 errors", e)
     for k, v in e.items():
         assert v < 1e-9, (k, v)
+
+
+def test_drift_beyond_windows_f64(ddm, orc):
+    """Particles that drift more than a cell away from the tile they were binned
+    in (binning only at the start) leave their LDS windows and take the outlier
+    path (global atomics, active blocks added on the fly): forward state and
+    gradients still equal the oracle's."""
+    import torch
+    w = W.tiny(3, steps=60)
+    w.dt = 1e-3
+    w.target_seed = 11
+    vel = np.array([0.3, 2.5, -0.3])
+    steps = 60
+    cfg, inst = ddm.from_workload(w, max_steps=steps, checkpoint_every=steps, sort_every=0)
+    sim = ddm.Simulator(cfg, [inst])
+    x0 = W.bed_positions(w)
+    sim.init_state(x0)
+    st = sim.get_state()
+    o, n = sim.offsets[0], sim.counts[0]
+    for a in range(3):
+        st[3 + a, o:o + n] = float(vel[a])
+    sim.set_state(st)
+    _log("case drift beyond windows")
+    sim.rollout(steps)
+    tgt = W.target_heightmap(w)
+    loss = float(sim.loss(tgt[None])[0])
+    grad = sim.backward()[0].cpu().numpy()
+    got = sim.packed_state(0)
+    s0 = orc.initial_state(x0)
+    s0[:, 3:6] = vel
+    r = orc.rollout(orc.config(w), w.params7, s0, steps, target=tgt, grad=True)
+    # the bed moved by more than one cell (dx = 1/16) along y
+    assert got[:, 1].mean() - x0[:, 1].mean() > 1.5 / 16
+    e = field_errors(got, r["state"], 3)
+    _log("drift errors", e, "\ngpu grad", grad, "\noracle grad", r["grad"])
+    for k, v in e.items():
+        assert v < 1e-9, (k, v)
+    assert abs(loss - r["loss"]) <= 1e-10 * abs(r["loss"])
+    rel = np.abs(grad - r["grad"]) / np.maximum(np.abs(r["grad"]), 1e-9 * np.abs(r["grad"]).max())
+    assert np.all(rel < 1e-6), rel
