@@ -257,14 +257,6 @@ template <int D> struct Win {
   }
 };
 
-// Particle slots of a chunk of cnt sorted particles, one wave-iteration at a
-// time: wave w of the workgroup takes iterations it = w, w + 4, ... < nq, and
-// lane l of iteration it takes slot l * nq + it.  (l, it) -> slot is a bijection
-// onto [0, 64 nq) >= [0, cnt), and the 64 lanes of one iteration sit about
-// cnt / 64 slots apart in the cell order, i.e. about one particle per cell,
-// so LDS atomics of one instruction rarely share an address.
-__device__ __forceinline__ int chunk_iters(int cnt) { return (kBlock / 64) * ((cnt + kBlock - 1) / kBlock); }
-
 // Per-particle constitutive update and P2G contributions; emit(node offsets,
 // weight, values) receives the D+1 scattered values of each stencil node.
 template <typename T, int D>
@@ -1108,6 +1100,7 @@ __global__ void __launch_bounds__(kBlock) k_g2p_adj(KCfg c, Bufs b, TileList tl,
                                                     const T* __restrict__ post, const void* adj_next, void* adj_cur,
                                                     T* __restrict__ gvb) {
   __shared__ double win[Win<D>::stride * D];
+  __shared__ RunLDS<T> rl;
   const uint32_t ntiles = *tl.count;
   const P<T, D> st = pv<T, D>(stv, c.ntot);
   const Adj<T, D> an = av<T, D>(adj_next, c.ntot), ac = av<T, D>(adj_cur, c.ntot);
@@ -1122,14 +1115,15 @@ __global__ void __launch_bounds__(kBlock) k_g2p_adj(KCfg c, Bufs b, TileList tl,
     const T* g = post + I.goff * kNodeVals;
     T* gbv = gvb + I.goff * kNodeVals;
     for (int i = threadIdx.x; i < WS * D; i += kBlock) win[i] = 0.0;
-    __syncthreads();
-    const int cnt = (int)(tr.end - tr.start), nq = chunk_iters(cnt);
-    for (int it = threadIdx.x >> 6; it < nq; it += kBlock / 64) {
-      const int slot = (threadIdx.x & 63) * nq + it;
-      if (slot >= cnt) continue;
-      const int64_t p = (int64_t)tr.start + slot;
+    const int cnt = (int)(tr.end - tr.start);
+    for (int r0 = 0; r0 < cnt; r0 += kBlock) {
+    const int rc = min(kBlock, cnt - r0);
+    int wb = -1;
+    do {
+      if (threadIdx.x >= rc) break;
+      const int64_t p = (int64_t)tr.start + r0 + threadIdx.x;
       Stencil<T, D> S;
-      if (!make_stencil<T, D>(st, p, c, S)) continue;
+      if (!make_stencil<T, D>(st, p, c, S)) break;
       T xb[3], vb[3], Cb[3][3];
 #pragma unroll
       for (int a = 0; a < D; ++a) {
@@ -1194,12 +1188,11 @@ __global__ void __launch_bounds__(kBlock) k_g2p_adj(KCfg c, Bufs b, TileList tl,
           }
       };
       if (inwin) {
-        double* w0 = win + Win<D>::idx(loc[0], loc[1], loc[2]);
-        body([&](int o0, int o1, int o2, int64_t, T w, const T (&t)[3]) {
-          const int off = Win<D>::idx(o0, o1, o2);
-#pragma unroll
-          for (int a = 0; a < D; ++a) atomicAdd(w0 + a * WS + off, (double)(w * t[a]));
-        });
+        // the scatter of w_o t_o happens in the run phase
+        body([&](int, int, int, int64_t, T, const T (&)[3]) {});
+        wb = Win<D>::idx(loc[0], loc[1], loc[2]);
+        T f[3] = {S.f[0], S.f[1], D == 3 ? S.f[2] : T(0)};
+        put_record<T, D>(rl, threadIdx.x, q, B, f);
       } else {
         body([&](int, int, int, int64_t nd, T w, const T (&t)[3]) {
 #pragma unroll
@@ -1215,6 +1208,10 @@ __global__ void __launch_bounds__(kBlock) k_g2p_adj(KCfg c, Bufs b, TileList tl,
       }
 #pragma unroll
       for (int a = 0; a < D; ++a) ac.x(a, p) = xb[a];
+    } while (false);
+    rl.wbase[threadIdx.x] = wb;
+    __syncthreads();
+    run_scatter_round<T, D, D>(rl, rc, win, T(0));
     }
     __syncthreads();
     for (int i = threadIdx.x; i < Win<D>::nodes; i += kBlock) {
