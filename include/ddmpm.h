@@ -181,6 +181,31 @@ ddm_status ddm_loss(ddm_ctx* ctx, const double* target_hm_dev, double* loss_dev)
  * preceding ddm_rollout and ddm_loss. */
 ddm_status ddm_backward(ddm_ctx* ctx, const double* dloss_dev, double* grad_dev);
 
+/* One full pass of a gradient-based optimiser or line search (Sec. III-D,
+ * system identification in Sec. IV-B): ddm_init_state(x0_dev),
+ * ddm_rollout(n_steps), ddm_loss(target_hm_dev, loss_dev) and
+ * ddm_backward(dloss_dev, grad_dev) in one call, with the arguments and
+ * outputs of those calls.  use_graph != 0: the pass is captured into a HIP
+ * graph on the first call and later calls with the same pointers and n_steps
+ * replay it (one launch for the whole pass); other arguments capture afresh.
+ * The graph holds only kernels and device-to-device copies.  Timing events are
+ * not recorded inside a captured pass.  Errors: those of the four calls;
+ * DDM_EINVAL for NULL pointers or n_steps outside [1, max_steps]. */
+ddm_status ddm_pass(ddm_ctx* ctx, const void* x0_dev, int32_t n_steps, const double* target_hm_dev,
+                    const double* dloss_dev, double* loss_dev, double* grad_dev, int32_t use_graph);
+
+/* Chooses the binning interval R (ddm_config.sort_every) for this context by
+ * timing the same forward sub-steps from the current state for R in
+ * {2, 4, 8, 16, 32}, after a warm-up round.  The state is restored, and a
+ * recorded rollout, its loss and its checkpoints stay valid.  With cache_path
+ * != NULL, a line "ddmpm dim=.. n_grid=.. prec=.. n_inst=.. particles=..
+ * ppc=.. sort_every=R" for this problem is looked up first (no probe when
+ * found) and appended after a probe.  The chosen R is written to
+ * *sort_every_out (may be NULL).  Synchronises the stream.  DDM_ESTATE
+ * before ddm_init_state.  The results do not depend on R beyond the order of
+ * floating-point atomic sums. */
+ddm_status ddm_autotune(ddm_ctx* ctx, const char* cache_path, int32_t* sort_every_out);
+
 /* Copies the current particle state (layout above) of all instances into /
  * from caller device memory of state_bytes.  Particles are exported in their
  * initial order (binning reorders them internally); ddm_set_state takes that

@@ -82,6 +82,8 @@ def lib():
             "ddm_rollout": (C.c_int, [vp, i32]),
             "ddm_loss": (C.c_int, [vp, vp, vp]),
             "ddm_backward": (C.c_int, [vp, vp, vp]),
+            "ddm_pass": (C.c_int, [vp, vp, i32, vp, vp, vp, vp, i32]),
+            "ddm_autotune": (C.c_int, [vp, C.c_char_p, C.POINTER(i32)]),
             "ddm_get_state": (C.c_int, [vp, vp]),
             "ddm_set_state": (C.c_int, [vp, vp]),
             "ddm_get_grid": (C.c_int, [vp, vp]),
@@ -212,6 +214,19 @@ class Simulator:
         self.counts = [int(s.n_particles) for s in self.instances]
         self.npix = cfg.hm_res ** (cfg.dim - 1)
 
+    # Stream order between torch's current stream (where tensors given to and
+    # returned by these methods are produced and consumed) and the context's
+    # stream, when they differ.
+    def _inputs_ready(self):
+        cur = self.torch.cuda.current_stream(self.device)
+        if cur != self.stream:
+            self.stream.wait_stream(cur)
+
+    def _outputs_ready(self):
+        cur = self.torch.cuda.current_stream(self.device)
+        if cur != self.stream:
+            cur.wait_stream(self.stream)
+
     def __del__(self):
         ctx = getattr(self, "ctx", None)
         if ctx and _lib is not None:
@@ -234,6 +249,7 @@ class Simulator:
         x0 = t.as_tensor(np.asarray(x0) if not isinstance(x0, t.Tensor) else x0)
         self._x0 = x0.to(device=self.device, dtype=self.dtype).contiguous()
         assert self._x0.shape == (sum(self.counts), self.dim)
+        self._inputs_ready()
         _check(lib().ddm_init_state(self.ctx, C.c_void_p(self._x0.data_ptr())))
 
     def step(self, n: int):
@@ -250,13 +266,16 @@ class Simulator:
         """Raw [rows, padded_particles] state tensor (a copy)."""
         out = self.torch.empty((self.state_rows, int(self.sizes.padded_particles)), dtype=self.dtype,
                                device=self.device)
+        self._inputs_ready()
         _check(lib().ddm_get_state(self.ctx, C.c_void_p(out.data_ptr())))
+        self._outputs_ready()
         return out
 
     def set_state(self, state):
         state = state.to(device=self.device, dtype=self.dtype).contiguous()
         assert state.shape == (self.state_rows, int(self.sizes.padded_particles))
         self._set_state_keep = state
+        self._inputs_ready()
         _check(lib().ddm_set_state(self.ctx, C.c_void_p(state.data_ptr())))
 
     def instance_state(self, state, i: int):
@@ -290,13 +309,17 @@ class Simulator:
         n = int(self.sizes.padded_particles)
         keys = t.empty(n, dtype=t.int32, device=self.device)
         perm = t.empty(n, dtype=t.int32, device=self.device)
+        self._inputs_ready()
         _check(lib().ddm_bin_keys(self.ctx, C.c_void_p(keys.data_ptr()), C.c_void_p(perm.data_ptr())))
+        self._outputs_ready()
         return keys.cpu().numpy().view(np.uint32), perm.cpu().numpy().view(np.uint32)
 
     def get_grid(self):
         nodes = self.cfg.n_grid ** self.dim
         out = self.torch.empty((self.n_inst, nodes, 8), dtype=self.dtype, device=self.device)
+        self._inputs_ready()
         _check(lib().ddm_get_grid(self.ctx, C.c_void_p(out.data_ptr())))
+        self._outputs_ready()
         return out
 
     # -- loss and gradient ---------------------------------------------------
@@ -306,12 +329,16 @@ class Simulator:
         tg = t.as_tensor(np.asarray(target) if not isinstance(target, t.Tensor) else target)
         self._target = tg.to(device=self.device, dtype=t.float64).reshape(self.n_inst, self.npix).contiguous()
         out = t.empty(self.n_inst, dtype=t.float64, device=self.device)
+        self._inputs_ready()
         _check(lib().ddm_loss(self.ctx, C.c_void_p(self._target.data_ptr()), C.c_void_p(out.data_ptr())))
+        self._outputs_ready()
         return out
 
     def heightmap(self):
         out = self.torch.empty((self.n_inst, self.npix), dtype=self.torch.float64, device=self.device)
+        self._inputs_ready()
         _check(lib().ddm_get_heightmap(self.ctx, C.c_void_p(out.data_ptr())))
+        self._outputs_ready()
         return out
 
     def backward(self, dloss=None):
@@ -321,9 +348,50 @@ class Simulator:
             dloss = t.ones(self.n_inst, dtype=t.float64, device=self.device)
         dl = t.as_tensor(dloss, dtype=t.float64).to(self.device).contiguous()
         grad = t.empty((self.n_inst, 7), dtype=t.float64, device=self.device)
+        self._inputs_ready()
         _check(lib().ddm_backward(self.ctx, C.c_void_p(dl.data_ptr()), C.c_void_p(grad.data_ptr())))
         self._keep = dl
+        self._outputs_ready()
         return grad
+
+    def full_pass(self, x0, n: int, target, dloss=None, graph: bool = False):
+        """init_state(x0) + rollout(n) + loss(target) + backward(dloss) as one
+        library call (ddm_pass).  graph=True captures the pass into a HIP graph
+        on the first call and replays it on later calls; the inputs are copied
+        into buffers this Simulator keeps, so the graph sees fixed pointers.
+        Needs a Simulator created on a non-default stream for graph=True.
+        Returns (loss [n_inst], grad [n_inst, 7]), device tensors that the next
+        pass overwrites."""
+        t = self.torch
+        if not hasattr(self, "_pass_bufs"):
+            self._pass_bufs = {
+                "x0": t.empty((sum(self.counts), self.dim), dtype=self.dtype, device=self.device),
+                "tg": t.empty((self.n_inst, self.npix), dtype=t.float64, device=self.device),
+                "dl": t.empty(self.n_inst, dtype=t.float64, device=self.device),
+                "loss": t.empty(self.n_inst, dtype=t.float64, device=self.device),
+                "grad": t.empty((self.n_inst, 7), dtype=t.float64, device=self.device),
+            }
+        B = self._pass_bufs
+        self._inputs_ready()
+        with t.cuda.stream(self.stream):
+            B["x0"].copy_(t.as_tensor(np.asarray(x0) if not isinstance(x0, t.Tensor) else x0).reshape(B["x0"].shape))
+            B["tg"].copy_(t.as_tensor(np.asarray(target) if not isinstance(target, t.Tensor) else target)
+                          .reshape(B["tg"].shape))
+            if dloss is None:
+                B["dl"].fill_(1.0)
+            else:
+                B["dl"].copy_(t.as_tensor(dloss, dtype=t.float64))
+        ptr = {k: C.c_void_p(v.data_ptr()) for k, v in B.items()}
+        _check(lib().ddm_pass(self.ctx, ptr["x0"], int(n), ptr["tg"], ptr["dl"], ptr["loss"], ptr["grad"],
+                              int(bool(graph))))
+        self._outputs_ready()
+        return B["loss"], B["grad"]
+
+    def autotune(self, cache_path: Optional[str] = None) -> int:
+        """Chooses and sets the binning interval (ddm_autotune); returns it."""
+        r = C.c_int32()
+        _check(lib().ddm_autotune(self.ctx, cache_path.encode() if cache_path else None, C.byref(r)))
+        return int(r.value)
 
     TIMING_GROUPS = ("p2g", "grid_update", "g2p", "binning", "g2p_adj", "grid_adj", "p2g_adj", "clear", "loss")
 

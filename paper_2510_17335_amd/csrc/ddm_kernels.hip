@@ -143,6 +143,13 @@ __device__ __forceinline__ Node4<double> ld_node(const double* p) {
   const double2 a = reinterpret_cast<const double2*>(p)[0], b = reinterpret_cast<const double2*>(p)[1];
   return Node4<double>{{a.x, a.y, b.x, b.y}};
 }
+__device__ __forceinline__ void st_node(float* p, float a, float b, float c, float d) {
+  *reinterpret_cast<float4*>(p) = make_float4(a, b, c, d);
+}
+__device__ __forceinline__ void st_node(double* p, double a, double b, double c, double d) {
+  reinterpret_cast<double2*>(p)[0] = make_double2(a, b);
+  reinterpret_cast<double2*>(p)[1] = make_double2(c, d);
+}
 
 // Wave64 + block reduction of one double, added atomically to *dst by one lane.
 __device__ __forceinline__ double wave_sum(double v) {
@@ -530,8 +537,8 @@ __global__ void __launch_bounds__(kBlock) k_p2g(KCfg c, Bufs b, TileList tl, con
       int l[3];
       Win<D>::coords(i, l);
       const int wi = Win<D>::idx(l[0], l[1], l[2]);
-#pragma unroll
-      for (int a = 0; a < kNodeVals; ++a) rec[a * Win<D>::nodes + i] = (T)win[a * Win<D>::stride + wi];
+      st_node(rec + (int64_t)i * kNodeVals, (T)win[wi], (T)win[Win<D>::stride + wi], (T)win[2 * Win<D>::stride + wi],
+              (T)win[3 * Win<D>::stride + wi]);
     }
     __syncthreads();
   }
@@ -620,9 +627,9 @@ __device__ __forceinline__ void gather_windows(const KCfg& c, int inst, const in
         const uint32_t r = tslot[gt];
         if (r == kNoSlot) continue;
         const int wn = D == 3 ? (ll[0][j0] * kWin + ll[1][j1]) * kWin + ll[2][j2] : ll[0][j0] * kWin + ll[1][j1];
-        const T* rec = stg + (int64_t)r * (kNodeVals * Win<D>::nodes) + wn;
+        const Node4<T> v = ld_node(stg + ((int64_t)r * Win<D>::nodes + wn) * kNodeVals);
 #pragma unroll
-        for (int a = 0; a < kNodeVals; ++a) acc[a] += rec[a * Win<D>::nodes];
+        for (int a = 0; a < kNodeVals; ++a) acc[a] += v.v[a];
       }
 }
 

@@ -18,8 +18,8 @@ constexpr int kWin = kTile + 4;      // LDS window edge in nodes: tile + stencil
 struct TileRec { uint32_t start, end, tile; };
 struct TileList { const TileRec* list; const uint32_t* count; };
 
-// Window of a tile in the staging buffer: record r holds kNodeVals planes of
-// kWin^D nodes (node (l0, l1[, l2]) of the window at ((l0 kWin + l1) kWin + l2)),
+// Window of a tile in the staging buffer: record r holds kWin^D nodes of
+// kNodeVals values (node (l0, l1[, l2]) of the window at ((l0 kWin + l1) kWin + l2)),
 // covering grid nodes [4t - 1, 4t + 7) per axis.  tslot[t] is the record of
 // tile t, or kNoSlot.
 constexpr uint32_t kNoSlot = 0xFFFFFFFFu;

@@ -7,6 +7,8 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <fstream>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -266,6 +268,13 @@ struct ddm_ctx {
   bool loss_ready = false;
   bool need_sort = true;          // re-bin before the next sub-step
   bool grid_valid = false;        // grid_pre/grid_post and the active set are those of the last sub-step
+  // captured full pass (ddm_pass with use_graph): the graph and the arguments it was captured with
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  const void* g_x0 = nullptr;
+  const double *g_target = nullptr, *g_dloss = nullptr;
+  double *g_loss = nullptr, *g_grad = nullptr;
+  int32_t g_steps = 0;
   std::vector<char> rec_sorted;   // per recorded step: binned at its start
   // kernel timing
   bool timing = false;
@@ -742,6 +751,146 @@ ddm_status ddm_backward(ddm_ctx* x, const double* dloss_dev, double* grad_dev) {
   return launch_status();
 }
 
+namespace {
+
+// The four calls of one optimiser pass, in order.
+ddm_status run_pass(ddm_ctx* x, const void* x0, int32_t n_steps, const double* target, const double* dloss,
+                    double* loss, double* grad) {
+  ddm_status s = ddm_init_state(x, x0);
+  if (s == DDM_OK) s = ddm_rollout(x, n_steps);
+  if (s == DDM_OK) s = ddm_loss(x, target, loss);
+  if (s == DDM_OK) s = ddm_backward(x, dloss, grad);
+  return s;
+}
+
+void drop_graph(ddm_ctx* x) {
+  if (x->gexec) (void)hipGraphExecDestroy(x->gexec);
+  if (x->graph) (void)hipGraphDestroy(x->graph);
+  x->gexec = nullptr;
+  x->graph = nullptr;
+}
+
+}  // namespace
+
+ddm_status ddm_pass(ddm_ctx* x, const void* x0_dev, int32_t n_steps, const double* target_hm_dev,
+                    const double* dloss_dev, double* loss_dev, double* grad_dev, int32_t use_graph) {
+  if (!x || !x0_dev || !target_hm_dev || !dloss_dev || !loss_dev || !grad_dev) return fail(DDM_EINVAL, "NULL argument");
+  if (n_steps < 1 || n_steps > x->cfg.max_steps) return fail(DDM_EINVAL, "n_steps outside [1, max_steps]");
+  if (!use_graph) return run_pass(x, x0_dev, n_steps, target_hm_dev, dloss_dev, loss_dev, grad_dev);
+  const bool same = x->gexec && x->g_x0 == x0_dev && x->g_steps == n_steps && x->g_target == target_hm_dev &&
+                    x->g_dloss == dloss_dev && x->g_loss == loss_dev && x->g_grad == grad_dev;
+  if (!same) {
+    drop_graph(x);
+    // Capture: the sequence of kernels and copies is fixed by (n_steps, config),
+    // and nothing in it waits for the host.  Timing events stay out of the graph.
+    const bool timing = x->timing;
+    x->timing = false;
+    DDM_HIP(hipStreamBeginCapture(x->stream, hipStreamCaptureModeThreadLocal));
+    const ddm_status s = run_pass(x, x0_dev, n_steps, target_hm_dev, dloss_dev, loss_dev, grad_dev);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(x->stream, &g);
+    x->timing = timing;
+    if (s != DDM_OK) { if (g) (void)hipGraphDestroy(g); return s; }
+    DDM_HIP(e);
+    x->graph = g;
+    const hipError_t ei = hipGraphInstantiate(&x->gexec, g, nullptr, nullptr, 0);
+    if (ei != hipSuccess) { drop_graph(x); return hip_check(ei, "instantiate the pass graph"); }
+    x->g_x0 = x0_dev; x->g_steps = n_steps; x->g_target = target_hm_dev; x->g_dloss = dloss_dev;
+    x->g_loss = loss_dev; x->g_grad = grad_dev;
+  }
+  DDM_HIP(hipGraphLaunch(x->gexec, x->stream));
+  // host-side state after a pass (the capture set it the same way)
+  x->steps = n_steps;
+  x->initialised = true;
+  x->recorded = true;
+  x->rec_k0 = 0;
+  x->rec_n = n_steps;
+  x->loss_ready = true;
+  x->need_sort = true;
+  x->grid_valid = false;
+  return DDM_OK;
+}
+
+ddm_status ddm_autotune(ddm_ctx* x, const char* cache_path, int32_t* sort_every_out) {
+  if (!x) return fail(DDM_EINVAL, "NULL context");
+  if (!x->initialised) return fail(DDM_ESTATE, "ddm_init_state first (the probe runs on the current state)");
+  const Layout& L = x->L;
+  int64_t n_part = 0;
+  for (const auto& in : x->inst) n_part += in.n_particles;
+  std::ostringstream key;
+  key << "ddmpm dim=" << x->cfg.dim << " n_grid=" << x->cfg.n_grid << " prec=" << x->prec << " n_inst=" << x->n_inst
+      << " particles=" << n_part << " ppc=" << x->cfg.ppc;
+  int best = -1;
+  if (cache_path) {
+    std::ifstream f(cache_path);
+    std::string line;
+    while (std::getline(f, line)) {
+      const size_t k = line.rfind(" sort_every=");
+      if (k != std::string::npos && line.compare(0, k, key.str()) == 0) best = std::atoi(line.c_str() + k + 12);
+    }
+  }
+  if (best <= 0) {
+    // Probe: the same forward sub-steps from the current state for every
+    // candidate interval, the state restored before each.  The snapshot lives in
+    // reverse-pass buffers (segment state 0, segment permutations), which hold
+    // nothing between calls.
+    const int P = std::min<int>(32, x->cfg.max_steps);
+    const int cand[] = {2, 4, 8, 16, 32};
+    void* snap = x->at(L.seg_state);
+    void* pid_snap = x->at(L.seg_perm);
+    DDM_HIP(hipMemcpyAsync(snap, x->at(L.cur), L.state_bytes, hipMemcpyDeviceToDevice, x->stream));
+    DDM_HIP(hipMemcpyAsync(pid_snap, x->at(L.pid), sizeof(uint32_t) * L.ntot, hipMemcpyDeviceToDevice, x->stream));
+    const int saved_R = x->cfg.sort_every;
+    const bool saved_timing = x->timing;
+    x->timing = false;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    DDM_HIP(hipEventCreate(&e0));
+    DDM_HIP(hipEventCreate(&e1));
+    float best_ms = 0.f;
+    ddm_status st = DDM_OK;
+    for (int rep = 0; rep < 2 && st == DDM_OK; ++rep) {          // the first round warms up
+      for (int R : cand) {
+        DDM_HIP(hipMemcpyAsync(x->at(L.cur), snap, L.state_bytes, hipMemcpyDeviceToDevice, x->stream));
+        DDM_HIP(hipMemcpyAsync(x->at(L.pid), pid_snap, sizeof(uint32_t) * L.ntot, hipMemcpyDeviceToDevice, x->stream));
+        x->cfg.sort_every = R;
+        x->need_sort = true;
+        DDM_HIP(hipEventRecord(e0, x->stream));
+        for (int i = 0; i < P && st == DDM_OK; ++i) {
+          // pose rows 0 .. P-1: the cost of a sub-step does not depend on the pose
+          if (sort_due(x, i)) {
+            st = bin_state(x, x->at(L.cur), x->at<uint32_t>(L.pid), nullptr, nullptr, nullptr);
+            x->need_sort = false;
+          }
+          if (st == DDM_OK)
+            st = forward_step(x, i, x->tiles(), x->at(L.cur), x->at(L.cur), x->at(L.grid_pre), x->at(L.grid_post));
+        }
+        DDM_HIP(hipEventRecord(e1, x->stream));
+        DDM_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        DDM_HIP(hipEventElapsedTime(&ms, e0, e1));
+        if (rep == 1 && (best < 0 || ms < best_ms)) { best = R; best_ms = ms; }
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    DDM_HIP(hipMemcpyAsync(x->at(L.cur), snap, L.state_bytes, hipMemcpyDeviceToDevice, x->stream));
+    DDM_HIP(hipMemcpyAsync(x->at(L.pid), pid_snap, sizeof(uint32_t) * L.ntot, hipMemcpyDeviceToDevice, x->stream));
+    DDM_HIP(hipStreamSynchronize(x->stream));
+    x->timing = saved_timing;
+    x->cfg.sort_every = saved_R;
+    if (st != DDM_OK) return st;
+    if (cache_path) {
+      std::ofstream f(cache_path, std::ios::app);
+      if (f) f << key.str() << " sort_every=" << best << "\n";
+    }
+  }
+  x->cfg.sort_every = best;
+  x->need_sort = true;            // the probe left the binning of another state
+  x->grid_valid = false;
+  if (sort_every_out) *sort_every_out = best;
+  return DDM_OK;
+}
+
 ddm_status ddm_get_state(ddm_ctx* x, void* state_dev) {
   if (!x || !state_dev) return fail(DDM_EINVAL, "NULL argument");
   ddm::launch_export_state(x->kc, x->bufs(), (int)x->L.nblk, x->L.rows, x->L.esz, x->at(x->L.cur), state_dev,
@@ -836,6 +985,7 @@ ddm_status ddm_read_timing(ddm_ctx* x, int32_t group, double* total_ms, int64_t*
 void ddm_destroy(ddm_ctx* x) {
   if (!x) return;
   if (hipStreamSynchronize(x->stream) == hipSuccess) {
+    drop_graph(x);
     for (const auto& e : x->events) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
     for (hipEvent_t e : x->pool) (void)hipEventDestroy(e);
   }

@@ -391,3 +391,70 @@ def test_drift_beyond_windows_f64(ddm, orc):
     assert abs(loss - r["loss"]) <= 1e-10 * abs(r["loss"])
     rel = np.abs(grad - r["grad"]) / np.maximum(np.abs(r["grad"]), 1e-9 * np.abs(r["grad"]).max())
     assert np.all(rel < 1e-6), rel
+
+
+def test_pass_graph_replays_match_eager(ddm):
+    """A captured full pass (init, recorded rollout, loss, backward) replayed
+    several times, with eager work and synchronisations in between and new
+    input values in between, gives what the eager calls give each time."""
+    import torch
+    w = W.tiny(3, shovel=True, steps=40)
+    tgt = W.target_heightmap(w)
+    x0 = W.bed_positions(w)
+    cfg, inst = ddm.from_workload(w, max_steps=40, checkpoint_every=16)
+
+    def eager(xa, tg):
+        sim = ddm.Simulator(cfg, [inst])
+        sim.init_state(xa)
+        sim.rollout(40)
+        loss = sim.loss(tg[None]).cpu().numpy()
+        grad = sim.backward().cpu().numpy()
+        return loss, grad, sim.packed_state(0)
+
+    _log("case graph replay")
+    ref = eager(x0, tgt)
+    x1 = x0 + 0.25 / w.n_grid * np.sin(np.arange(x0.size)).reshape(x0.shape)
+    tgt1 = tgt + 0.01
+    ref1 = eager(x1, tgt1)
+    sg = ddm.Simulator(cfg, [inst], stream=torch.cuda.Stream())
+    for rep, (xa, tg, r) in enumerate([(x0, tgt, ref), (x0, tgt, ref), (x1, tgt1, ref1), (x0, tgt, ref)]):
+        loss, grad = sg.full_pass(xa, 40, tg[None], graph=True)
+        sg.stream.synchronize()
+        loss, grad = loss.cpu().numpy(), grad.cpu().numpy()
+        st = sg.packed_state(0)
+        _log(f"replay {rep}: loss {loss[0]} vs {r[0][0]}")
+        np.testing.assert_allclose(loss, r[0], rtol=1e-12)
+        np.testing.assert_allclose(grad, r[1], rtol=1e-9, atol=1e-12 * np.abs(r[1]).max())
+        np.testing.assert_allclose(st, r[2], rtol=1e-11, atol=1e-13)
+        # eager work of the program between replays
+        other = ddm.Simulator(cfg, [inst])
+        other.init_state(x1)
+        other.step(5)
+        torch.cuda.synchronize()
+
+
+def test_autotune_restores_state_and_caches(ddm, orc, tmp_path):
+    """ddm_autotune picks a binning interval, leaves the state as it was, writes
+    and reuses its cache line, and the tuned context still matches the oracle."""
+    w = W.tiny(3, shovel=True, steps=30)
+    cfg, inst = ddm.from_workload(w, max_steps=30, checkpoint_every=16)
+    sim = ddm.Simulator(cfg, [inst])
+    sim.init_state(W.bed_positions(w))
+    sim.step(3)
+    before = sim.get_state().cpu().numpy()
+    cache = str(tmp_path / "tune.txt")
+    _log("case autotune")
+    r = sim.autotune(cache)
+    assert r in (2, 4, 8, 16, 32)
+    after = sim.get_state().cpu().numpy()
+    assert np.array_equal(before, after)
+    assert sim.steps_taken == 3
+    lines = open(cache).read().splitlines()
+    assert len(lines) == 1 and lines[0].endswith(f"sort_every={r}")
+    assert sim.autotune(cache) == r and len(open(cache).read().splitlines()) == 1
+    sim.step(27)
+    ref = run_oracle(orc, w, 30)
+    e = field_errors(sim.packed_state(0), ref["state"], 3)
+    _log("autotune R", r, "errors", e)
+    for k, v in e.items():
+        assert v < 1e-9, (k, v)
