@@ -8,11 +8,14 @@ and the reverse pass (segment recompute + adjoint of every sub-step).
 Workload (default): batched system identification, 64 instances on 64^3
 grids with particle counts uniform in [20k, 200k] (seeded), log-uniform E in
 [1e4, 1e6] Pa, nu in [0.2, 0.4], friction angle in [20, 45] deg, 500 sub-steps
-fwd+bwd, FP32, checkpoints every 50 sub-steps, binning every 8.
+fwd+bwd, FP32, checkpoints every 50 sub-steps, binning interval autotuned.
+Other workloads: the 64^3 dig with 1000 sub-steps fwd+bwd (dig3d_bwd) and the
+128^3 cohesive bed with 2000 sub-steps fwd+bwd and its peak memory (dig3d_large).
 
-Prints one JSON line (rank 0).  `value` is the batched fwd+bwd particle-steps/s;
-the plain per-instance loop on the same GPU and the FP32-vs-FP64 gradient
-gate are reported beside it.
+Prints one JSON line (rank 0).  `value` is the batched fwd+bwd particle-steps/s
+(eager launches, every kernel bracketed by HIP events); the same pass replayed
+from a captured HIP graph, the plain per-instance loop on the same GPU and the
+FP32-vs-FP64 gradient gate are reported beside it.
 """
 from __future__ import annotations
 
@@ -39,12 +42,14 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="sysid64", choices=["sysid64", "dig3d_bwd"])
+    ap.add_argument("--workload", default="sysid64", choices=["sysid64", "dig3d_bwd", "dig3d_large"])
     ap.add_argument("--sub-steps", type=int, default=None, help="override rollout length (testing only)")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-gate", action="store_true")
-    ap.add_argument("--sort-every", type=int, default=8)
+    ap.add_argument("--sort-every", type=int, default=0,
+                    help="binning interval; 0 = autotune the batched context (the plain loop uses 8)")
+    ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB device copy (calibrates the HBM byte counters)")
     return ap.parse_args()
@@ -54,9 +59,12 @@ def build_batch(args):
     if args.workload == "sysid64":
         ws = W.sysid_batch(64, steps=500)
         name = "sysid64: 64 instances, 64^3, N_i~U[20k,200k], 500 sub-steps fwd+bwd, K=50, FP32"
-    else:
+    elif args.workload == "dig3d_bwd":
         ws = [W.dig_3d_backward()]
         name = "dig3d_bwd: 64^3, 219488 particles, 1000 sub-steps fwd+bwd, K=50, FP32"
+    else:
+        ws = [W.dig_3d_large()]
+        name = "dig3d_large: 128^3 cohesive bed, 1802416 particles, 2000 sub-steps fwd+bwd, K=100, FP32"
     if args.sub_steps:
         for w in ws:
             w.steps = args.sub_steps
@@ -64,28 +72,21 @@ def build_batch(args):
 
 
 class Pass:
-    """One context over a list of instances and the inputs of a full pass."""
+    """One context over a list of instances and the inputs of a full pass
+    (init, recorded rollout, loss, backward: one ddm_pass call)."""
 
-    def __init__(self, ddm, ws, sort_every, precision=None):
+    def __init__(self, ddm, ws, sort_every, precision=None, stream=None):
         self.ws = ws
         self.steps = ws[0].steps
         K = ws[0].checkpoint_every or 50
         cfgs = [ddm.from_workload(w, max_steps=self.steps, checkpoint_every=K, precision=precision,
                                   sort_every=sort_every) for w in ws]
-        self.sim = ddm.Simulator(cfgs[0][0], [c[1] for c in cfgs])
+        self.sim = ddm.Simulator(cfgs[0][0], [c[1] for c in cfgs], stream=stream)
         self.x0 = np.concatenate([W.bed_positions(w) for w in ws])
         self.tg = np.stack([W.target_heightmap(w) for w in ws])
-        self.sim.init_state(self.x0)           # uploads x0 once
-        self.x0_dev = self.sim._x0
-        self.tg_dev = None
 
-    def run(self):
-        sim = self.sim
-        sim.init_state(self.x0_dev)
-        sim.rollout(self.steps)
-        loss = sim.loss(self.tg if self.tg_dev is None else self.tg_dev)
-        self.tg_dev = sim._target
-        return loss, sim.backward()
+    def run(self, graph=False):
+        return self.sim.full_pass(self.x0, self.steps, self.tg, graph=graph)
 
     @property
     def particle_steps(self):
@@ -145,11 +146,12 @@ def copy_calibration(torch):
 
 def cpu_baseline(ws):
     """The FP64 oracle (single thread) with 7 forward-mode tangents on the
-    smallest instance of the batch, 20 sub-steps: fwd+bwd-equivalent rate."""
+    smallest instance of the batch, for about 15 s of work: the fwd+bwd-equivalent
+    rate."""
     import oracle
     oracle.build(force=False)
     w = min(ws, key=lambda q: q.n_particles)
-    steps = 20
+    steps = int(min(60, max(1, round(1.3e6 / w.n_particles))))
     s0 = oracle.initial_state(W.bed_positions(w))
     t0 = time.perf_counter()
     oracle.rollout(oracle.config(w), w.params7, s0, steps, target=W.target_heightmap(w), grad=True)
@@ -174,12 +176,20 @@ def main():
     ws, wname = build_batch(args)
     print(f"# workload {wname}: {len(ws)} instances, {sum(w.n_particles for w in ws)} particles", flush=True)
 
-    bp = Pass(ddm, ws, args.sort_every)
+    # batched: one context on its own stream, binning interval autotuned on the
+    # initial state (unless --sort-every is given)
+    bp = Pass(ddm, ws, args.sort_every or 8, stream=torch.cuda.Stream())
+    tuned = None
+    if not args.sort_every:
+        bp.sim.init_state(bp.x0)
+        tuned = bp.sim.autotune()
+        print(f"# autotuned binning interval: every {tuned} sub-steps", flush=True)
     for i in range(args.warmup):
         bp.run()
         torch.cuda.synchronize()
         print(f"# warmup {i + 1}/{args.warmup} done", flush=True)
     bp.sim.check()
+    torch.cuda.reset_peak_memory_stats()
     bp.sim.set_timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -187,6 +197,7 @@ def main():
         loss, grad = bp.run()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    peak_gb = torch.cuda.max_memory_allocated() / 1e9
     timing = bp.sim.read_timing()
     bp.sim.set_timing(False)
     err = bp.sim.check()
@@ -195,6 +206,19 @@ def main():
     print(f"# batched: {ms_per_step:.1f} ms/step, {value:.3e} particle-steps/s, device flags {err.flags}",
           flush=True)
     grads32 = grad.cpu().numpy()
+
+    # the same pass captured once into a HIP graph and replayed (not the timed
+    # region above: per-kernel events cannot sit inside a graph)
+    graph_value = None
+    if not args.no_graph:
+        bp.run(graph=True)
+        torch.cuda.synchronize()
+        tg0 = time.perf_counter()
+        for i in range(args.steps):
+            bp.run(graph=True)
+        torch.cuda.synchronize()
+        graph_value = bp.particle_steps * args.steps / (time.perf_counter() - tg0)
+        print(f"# graph replay: {graph_value:.3e} particle-steps/s", flush=True)
 
     # dominant kernel and its roofline (bytes moved per launch / measured launch time)
     dom = max(timing, key=lambda k: timing[k][0])
@@ -209,7 +233,7 @@ def main():
         torch.cuda.empty_cache()
         t_plain = 0.0
         for w in ws:
-            pp = Pass(ddm, [w], args.sort_every)
+            pp = Pass(ddm, [w], 8)
             pp.run()
             torch.cuda.synchronize()
             t1 = time.perf_counter()
@@ -227,7 +251,7 @@ def main():
         idx = sorted(range(len(ws)), key=lambda i: ws[i].n_particles)[:2]
         rels = []
         for i in idx:
-            p64 = Pass(ddm, [ws[i]], args.sort_every, precision="f64")
+            p64 = Pass(ddm, [ws[i]], 8, precision="f64")
             _, g64 = p64.run()
             g64 = g64[0].cpu().numpy()
             scale = np.abs(g64).max()
@@ -253,7 +277,9 @@ def main():
         "data": "synthetic (seeded beds and targets, no dataset)",
         "config": {"workload": wname, "instances": len(ws), "particles": sum(w.n_particles for w in ws),
                    "sub_steps": ws[0].steps, "checkpoint_every": ws[0].checkpoint_every,
-                   "sort_every": args.sort_every},
+                   "sort_every": tuned or args.sort_every, "sort_every_autotuned": tuned is not None,
+                   "peak_mem_gb": round(peak_gb, 2)},
+        "graph_value": graph_value,
         "plain_value": plain_value,
         "batched_over_plain": (value / plain_value) if plain_value else None,
         "grad_gate": gate,
