@@ -324,7 +324,7 @@ __device__ __forceinline__ bool p2g_particle(const KCfg& c, const Bufs& b, const
 // and every atomic instruction costs the same whether 1 or 64 lanes are
 // active, so the gain comes from issuing about 1/ppc as many atomics.
 // ---------------------------------------------------------------------------
-template <typename T> struct RunLDS {
+template <typename T> struct alignas(16) RunLDS {
   T rec[4][kBlock][4];            // group g of slot t: (q0 q1 q2 -), (B_a0 B_a1 B_a2 f_a) for a = g - 1
   int wbase[kBlock];
   int wcount[kBlock / 64];
@@ -1108,6 +1108,7 @@ __global__ void __launch_bounds__(kBlock) k_g2p_adj(KCfg c, Bufs b, TileList tl,
                                                     T* __restrict__ gvb) {
   __shared__ double win[Win<D>::stride * D];
   __shared__ RunLDS<T> rl;
+  __shared__ alignas(16) T gwin[Win<D>::nodes][kNodeVals];     // grid velocities of the tile's window
   const uint32_t ntiles = *tl.count;
   const P<T, D> st = pv<T, D>(stv, c.ntot);
   const Adj<T, D> an = av<T, D>(adj_next, c.ntot), ac = av<T, D>(adj_cur, c.ntot);
@@ -1122,6 +1123,19 @@ __global__ void __launch_bounds__(kBlock) k_g2p_adj(KCfg c, Bufs b, TileList tl,
     const T* g = post + I.goff * kNodeVals;
     T* gbv = gvb + I.goff * kNodeVals;
     for (int i = threadIdx.x; i < WS * D; i += kBlock) win[i] = 0.0;
+    // stage the window's grid velocities (nodes outside the grid are never read)
+    for (int i = threadIdx.x; i < Win<D>::nodes; i += kBlock) {
+      int l[3];
+      Win<D>::coords(i, l);
+      const int gi[3] = {org[0] + l[0], org[1] + l[1], D == 3 ? org[2] + l[2] : 0};
+      bool ok = true;
+#pragma unroll
+      for (int a = 0; a < D; ++a) ok &= gi[a] >= 0 && gi[a] < c.n;
+      Node4<T> v = {{T(0), T(0), T(0), T(0)}};
+      if (ok) v = ld_node(g + node_of<D>(gi, 0, 0, 0, c.n) * kNodeVals);
+      st_node(gwin[i], v.v[0], v.v[1], v.v[2], v.v[3]);
+    }
+    __syncthreads();
     const int cnt = (int)(tr.end - tr.start);
     for (int r0 = 0; r0 < cnt; r0 += kBlock) {
     const int rc = min(kBlock, cnt - r0);
@@ -1158,7 +1172,7 @@ __global__ void __launch_bounds__(kBlock) k_g2p_adj(KCfg c, Bufs b, TileList tl,
         for (int k = 0; k < 3; ++k) dwi[a][k] = S.dw[a][k] * inv_dx;
       }
       T xg[3] = {T(0), T(0), T(0)}, vw[3] = {T(0), T(0), T(0)};
-      auto body = [&](auto&& emit) {
+      auto body = [&](auto&& emit, auto&& load) {
         // Offsets 0 and 1 stay loops: unrolling all 27 nodes hoists their
         // loads and costs occupancy.
 #pragma unroll 1
@@ -1175,7 +1189,7 @@ __global__ void __launch_bounds__(kBlock) k_g2p_adj(KCfg c, Bufs b, TileList tl,
               const T w2 = D == 3 ? S.w[2][o2] : T(1);
               const T w = wxy * w2;
               const int64_t nd = node_of<D>(S.base, o0, o1, o2, c.n) * kNodeVals;
-              const Node4<T> gv = ld_node(g + nd);
+              const Node4<T> gv = load(o0, o1, o2, nd);
               T sdot = T(0);
 #pragma unroll
               for (int a = 0; a < D; ++a) { sdot += gv.v[a] * t[a]; u[a] += w2 * gv.v[a]; }
@@ -1196,15 +1210,20 @@ __global__ void __launch_bounds__(kBlock) k_g2p_adj(KCfg c, Bufs b, TileList tl,
       };
       if (inwin) {
         // the scatter of w_o t_o happens in the run phase
-        body([&](int, int, int, int64_t, T, const T (&)[3]) {});
+        const int wn0 = D == 3 ? (loc[0] * kWin + loc[1]) * kWin + loc[2] : loc[0] * kWin + loc[1];
+        body([&](int, int, int, int64_t, T, const T (&)[3]) {},
+             [&](int o0, int o1, int o2, int64_t) {
+               return ld_node(gwin[wn0 + (D == 3 ? (o0 * kWin + o1) * kWin + o2 : o0 * kWin + o1)]);
+             });
         wb = Win<D>::idx(loc[0], loc[1], loc[2]);
         T f[3] = {S.f[0], S.f[1], D == 3 ? S.f[2] : T(0)};
         put_record<T, D>(rl, threadIdx.x, q, B, f);
       } else {
         body([&](int, int, int, int64_t nd, T w, const T (&t)[3]) {
 #pragma unroll
-          for (int a = 0; a < D; ++a) atomicAdd(gbv + nd + a, w * t[a]);
-        });
+               for (int a = 0; a < D; ++a) atomicAdd(gbv + nd + a, w * t[a]);
+             },
+             [&](int, int, int, int64_t nd) { return ld_node(g + nd); });
       }
 #pragma unroll
       for (int a = 0; a < D; ++a) {
