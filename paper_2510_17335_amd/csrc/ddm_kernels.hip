@@ -563,12 +563,12 @@ void launch_p2g(int prec, const KCfg& c, const Bufs& b, const TileList& tl, int 
 // ---------------------------------------------------------------------------
 template <typename T>
 __device__ __forceinline__ Blade<T> load_blade(const void* poses, int inst, int max_steps, int step) {
-  const T* q = static_cast<const T*>(poses) + ((int64_t)inst * max_steps + step) * 8;
+  const T* q = static_cast<const T*>(poses) + ((int64_t)inst * max_steps + step) * kPoseVals;
   Blade<T> bl;
   bl.tip[0] = q[0]; bl.tip[1] = q[1]; bl.tip[2] = q[2]; bl.psi = q[3];
   bl.vel[0] = q[4]; bl.vel[1] = q[5]; bl.vel[2] = q[6]; bl.omega = q[7];
-  bl.sp = sin(bl.psi);
-  bl.cp = cos(bl.psi);
+  bl.sp = q[8];           // sin and cos of the angle, evaluated once per sub-step on the host
+  bl.cp = q[9];
   return bl;
 }
 
@@ -589,15 +589,18 @@ __device__ __forceinline__ void node_coords(int64_t node, int n, int idx[3]) {
 // Node of an active-set item: item i is node i % 4^D of listed block i / 4^D.
 template <int D>
 __device__ __forceinline__ void active_node(const KCfg& c, uint32_t gb, int k, int& inst, int idx[3], int64_t& node) {
-  const int nt = c.n / kTile;
-  const uint32_t per = D == 3 ? (uint32_t)(nt * nt * nt) : (uint32_t)(nt * nt);
-  inst = (int)(gb / per);
-  uint32_t t = gb - (uint32_t)inst * per;
+  // grids are powers of two: blocks per axis 2^tb, blocks per instance 2^(D tb)
+  const int tb = c.nlog2 - 2, pb = D * tb;
+  const uint32_t mb = (1u << tb) - 1u;
+  inst = (int)(gb >> pb);
+  const uint32_t t = gb & ((1u << pb) - 1u);
   int bc[3] = {0, 0, 0};
-  for (int a = D - 1; a >= 0; --a) { bc[a] = (int)(t % (uint32_t)nt); t /= (uint32_t)nt; }
+  if (D == 3) { bc[0] = (int)(t >> (2 * tb)); bc[1] = (int)((t >> tb) & mb); bc[2] = (int)(t & mb); }
+  else { bc[0] = (int)(t >> tb); bc[1] = (int)(t & mb); }
   if (D == 3) { idx[0] = bc[0] * kTile + (k >> 4); idx[1] = bc[1] * kTile + ((k >> 2) & 3); idx[2] = bc[2] * kTile + (k & 3); }
   else { idx[0] = bc[0] * kTile + (k >> 2); idx[1] = bc[1] * kTile + (k & 3); idx[2] = 0; }
-  node = D == 3 ? ((int64_t)idx[0] * c.n + idx[1]) * c.n + idx[2] : (int64_t)idx[0] * c.n + idx[1];
+  node = D == 3 ? ((int64_t)idx[0] << (2 * c.nlog2)) + ((int64_t)idx[1] << c.nlog2) + idx[2]
+                : ((int64_t)idx[0] << c.nlog2) + idx[1];
 }
 
 // Sum of the staged windows covering a node: per axis the tiles (x + 1) / 4 - 1

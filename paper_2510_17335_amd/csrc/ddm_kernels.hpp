@@ -9,6 +9,7 @@ namespace ddm {
 constexpr int kBlock = 256;          // particle kernels: threads per block, and the
                                      // padding unit of every instance's particle range
 constexpr int kNodeVals = 4;         // node record: mv[0..2] (or v), m
+constexpr int kPoseVals = 10;        // device pose row of a sub-step
 constexpr int kTile = 4;             // binning tile edge in cells
 constexpr int kWin = kTile + 4;      // LDS window edge in nodes: tile + stencil + 1-cell drift each side
 
@@ -60,7 +61,7 @@ struct KCfg {
 struct Bufs {
   const InstDev* inst;
   const int* blk_inst;               // instance of every particle block
-  const void* poses;                 // [n_inst][max_steps][8] (tip xyz, psi, vel xyz, omega)
+  const void* poses;                 // [n_inst][max_steps][kPoseVals]: tip xyz, psi, vel xyz, omega, sin psi, cos psi
   DevErr* err;
 };
 

@@ -98,7 +98,7 @@ Layout make_layout(const ddm_config& c, int n_inst, const ddm_instance* in) {
   Carver cv;
   L.inst = cv.take(sizeof(ddm::InstDev) * n_inst);
   L.blk_inst = cv.take(sizeof(int) * L.nblk);
-  L.poses = cv.take((size_t)n_inst * c.max_steps * 8 * b);
+  L.poses = cv.take((size_t)n_inst * c.max_steps * ddm::kPoseVals * b);
   L.pose_jac = cv.take((size_t)n_inst * c.max_steps * 24 * sizeof(double));
   L.err = cv.take(sizeof(ddm::DevErr));
   L.pid = cv.take(sizeof(uint32_t) * ntot);
@@ -268,6 +268,9 @@ struct ddm_ctx {
   bool loss_ready = false;
   bool need_sort = true;          // re-bin before the next sub-step
   bool grid_valid = false;        // grid_pre/grid_post and the active set are those of the last sub-step
+  // the current particle state and its ids live in one of two buffers each;
+  // a binning gathers into the other one and the two swap roles
+  size_t cur_off = 0, spare_off = 0, pid_off = 0, pid_spare_off = 0;
   // captured full pass (ddm_pass with use_graph): the graph and the arguments it was captured with
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
@@ -275,6 +278,7 @@ struct ddm_ctx {
   const double *g_target = nullptr, *g_dloss = nullptr;
   double *g_loss = nullptr, *g_grad = nullptr;
   int32_t g_steps = 0;
+  size_t g_cur_off = 0, g_spare_off = 0, g_pid_off = 0, g_pid_spare_off = 0;   // buffer roles at the end of the captured pass
   std::vector<char> rec_sorted;   // per recorded step: binned at its start
   // kernel timing
   bool timing = false;
@@ -285,6 +289,8 @@ struct ddm_ctx {
   int64_t t_n[9] = {0};
 
   template <typename T = char> T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
+  void* cur() const { return at(cur_off); }
+  uint32_t* pid() const { return at<uint32_t>(pid_off); }
   ddm::TileList tiles() const { return ddm::TileList{at<const ddm::TileRec>(L.tiles), at<const uint32_t>(L.tcount)}; }
   ddm::TileList seg_tiles(int j) const {
     return ddm::TileList{at<const ddm::TileRec>(L.seg_tiles + sizeof(ddm::TileRec) * L.max_chunks * j),
@@ -407,23 +413,21 @@ void resolve_events(ddm_ctx* x) {
   x->events.clear();
 }
 
-// Bins the particles of `state` in place: exact cell keys, stable radix sort
-// by (instance, tile, cell), gather of the state rows (and ids) into sorted
-// order, the occupied-tile list with each tile's staging record, and the
-// active node blocks.  When perm_out / tiles_out are given the
+// Bins the particles of state `src` into `dst` (another buffer): exact cell
+// keys, stable radix sort by (instance, tile, cell), gather of the state rows
+// (and ids, when given) into sorted order, the occupied-tile list with each
+// tile's staging record, and the active node blocks.  When perm_out / tiles_out are given the
 // permutation and the tile list are also stored there (for the reverse pass).
-ddm_status bin_state(ddm_ctx* x, void* state, uint32_t* pid, uint32_t* perm_out, ddm::TileRec* tiles_out,
-                     uint32_t* tcount_out) {
+ddm_status bin_state(ddm_ctx* x, const void* src, void* dst, const uint32_t* pid_src, uint32_t* pid_dst,
+                     uint32_t* perm_out, ddm::TileRec* tiles_out, uint32_t* tcount_out) {
   Timed tm(x, 3);
   const Layout& L = x->L;
   hipStream_t st = x->stream;
   uint32_t* keys[2] = {x->at<uint32_t>(L.keys0), x->at<uint32_t>(L.keys1)};
   uint32_t* vals[2] = {x->at<uint32_t>(L.vals0), x->at<uint32_t>(L.vals1)};
-  ddm::launch_keys(x->prec, x->kc, x->bufs(), (int)L.nblk, state, keys[0], vals[0], st);
+  ddm::launch_keys(x->prec, x->kc, x->bufs(), (int)L.nblk, src, keys[0], vals[0], st);
   const int r = ddm::radix_sort(keys, vals, L.ntot, L.max_key, x->at<uint32_t>(L.hist), x->at<uint32_t>(L.sums), st);
-  ddm::launch_gather(L.esz, state, x->at(L.scratch), vals[r], L.rows, L.ntot, pid, pid ? x->at<uint32_t>(L.pid_tmp) : nullptr, st);
-  DDM_HIP(hipMemcpyAsync(state, x->at(L.scratch), L.state_bytes, hipMemcpyDeviceToDevice, st));
-  if (pid) DDM_HIP(hipMemcpyAsync(pid, x->at(L.pid_tmp), sizeof(uint32_t) * L.ntot, hipMemcpyDeviceToDevice, st));
+  ddm::launch_gather(L.esz, src, dst, vals[r], L.rows, L.ntot, pid_src, pid_dst, st);
   ddm::launch_tile_list(x->kc, keys[r], x->at<uint32_t>(L.tstart), x->at<uint32_t>(L.tend), x->at<ddm::TileRec>(L.tiles),
                         x->at<uint32_t>(L.tcount), x->at<uint32_t>(L.tslot), st);
   ddm::launch_active_set(x->kc, x->tiles(), x->active(), st);
@@ -433,6 +437,15 @@ ddm_status bin_state(ddm_ctx* x, void* state, uint32_t* pid, uint32_t* perm_out,
     DDM_HIP(hipMemcpyAsync(tcount_out, x->at(L.tcount), sizeof(uint32_t), hipMemcpyDeviceToDevice, st));
   }
   return launch_status();
+}
+
+// Bins the current state into the spare buffers and swaps the roles.
+ddm_status bin_current(ddm_ctx* x) {
+  const ddm_status s = bin_state(x, x->cur(), x->at(x->spare_off), x->pid(), x->at<uint32_t>(x->pid_spare_off), nullptr,
+                                 nullptr, nullptr);
+  std::swap(x->cur_off, x->spare_off);
+  std::swap(x->pid_off, x->pid_spare_off);
+  return s;
 }
 
 // One forward sub-step from st_in to st_out (may alias) with the given tile
@@ -514,6 +527,10 @@ ddm_status ddm_create(const ddm_config* cfg, int32_t n_inst, const ddm_instance*
   x->n_inst = n_inst;
   x->inst.assign(inst, inst + n_inst);
   x->L = L;
+  x->cur_off = L.cur;
+  x->spare_off = L.scratch;
+  x->pid_off = L.pid;
+  x->pid_spare_off = L.pid_tmp;
   x->ws = static_cast<char*>(workspace);
   x->stream = static_cast<hipStream_t>(stream);
   x->prec = cfg->precision == DDM_F64 ? 1 : 0;
@@ -577,8 +594,15 @@ ddm_status ddm_create(const ddm_config* cfg, int32_t n_inst, const ddm_instance*
       std::copy(j.begin(), j.end(), jac.begin() + (size_t)i * cfg->max_steps * 24);
     }
   }
+  // device rows: the 8 pose values and sin / cos of the blade angle
+  std::vector<double> prow((size_t)n_inst * cfg->max_steps * ddm::kPoseVals, 0.0);
+  for (size_t r = 0; r < (size_t)n_inst * cfg->max_steps; ++r) {
+    std::copy(poses.begin() + r * 8, poses.begin() + r * 8 + 8, prow.begin() + r * ddm::kPoseVals);
+    prow[r * ddm::kPoseVals + 8] = std::sin(poses[r * 8 + 3]);
+    prow[r * ddm::kPoseVals + 9] = std::cos(poses[r * 8 + 3]);
+  }
   std::vector<char> poses_t;
-  if (x->prec) to_prec<double>(poses, poses_t); else to_prec<float>(poses, poses_t);
+  if (x->prec) to_prec<double>(prow, poses_t); else to_prec<float>(prow, poses_t);
   // Host staging arrays are copied synchronously so the caller's memory is free on return.
   s = hip_check(hipMemcpy(x->at(L.inst), dev.data(), sizeof(ddm::InstDev) * n_inst, hipMemcpyHostToDevice), "upload instances");
   if (s == DDM_OK) s = hip_check(hipMemcpy(x->at(L.blk_inst), blk.data(), sizeof(int) * blk.size(), hipMemcpyHostToDevice), "upload block map");
@@ -592,7 +616,7 @@ ddm_status ddm_create(const ddm_config* cfg, int32_t n_inst, const ddm_instance*
 
 ddm_status ddm_init_state(ddm_ctx* x, const void* x0_dev) {
   if (!x || !x0_dev) return fail(DDM_EINVAL, "NULL argument");
-  ddm::launch_init_state(x->prec, x->kc, x->bufs(), (int)x->L.nblk, x0_dev, x->at(x->L.cur), x->at<uint32_t>(x->L.pid),
+  ddm::launch_init_state(x->prec, x->kc, x->bufs(), (int)x->L.nblk, x0_dev, x->cur(), x->pid(),
                          x->stream);
   // fill kernels rather than memset nodes, so that the call can be captured in a graph
   ddm::launch_fill_zero(x->at(x->L.err), sizeof(ddm::DevErr) / 4, 4, x->stream);
@@ -614,11 +638,11 @@ ddm_status ddm_step(ddm_ctx* x, int32_t n_steps) {
     return fail(DDM_EINVAL, "steps beyond max_steps (the pose table length)");
   for (int i = 0; i < n_steps; ++i) {
     if (sort_due(x, x->steps)) {
-      const ddm_status s = bin_state(x, x->at(x->L.cur), x->at<uint32_t>(x->L.pid), nullptr, nullptr, nullptr);
+      const ddm_status s = bin_current(x);
       if (s != DDM_OK) return s;
       x->need_sort = false;
     }
-    const ddm_status s = forward_step(x, x->steps, x->tiles(), x->at(x->L.cur), x->at(x->L.cur), x->at(x->L.grid_pre),
+    const ddm_status s = forward_step(x, x->steps, x->tiles(), x->cur(), x->cur(), x->at(x->L.grid_pre),
                                       x->at(x->L.grid_post));
     if (s != DDM_OK) return s;
     ++x->steps;
@@ -641,17 +665,17 @@ ddm_status ddm_rollout(ddm_ctx* x, int32_t n_steps) {
     // Checkpoints hold the state before the binning of their step; every
     // checkpointed step re-bins, so a replayed segment needs nothing older.
     if (i % K == 0) {
-      DDM_HIP(hipMemcpyAsync(x->at(x->L.ckpt + (size_t)(i / K) * x->L.state_bytes), x->at(x->L.cur), x->L.state_bytes,
+      DDM_HIP(hipMemcpyAsync(x->at(x->L.ckpt + (size_t)(i / K) * x->L.state_bytes), x->cur(), x->L.state_bytes,
                              hipMemcpyDeviceToDevice, x->stream));
       x->need_sort = true;
     }
     if (sort_due(x, k0 + i)) {
-      const ddm_status s = bin_state(x, x->at(x->L.cur), x->at<uint32_t>(x->L.pid), nullptr, nullptr, nullptr);
+      const ddm_status s = bin_current(x);
       if (s != DDM_OK) return s;
       x->need_sort = false;
       x->rec_sorted[(size_t)i] = 1;
     }
-    const ddm_status s = forward_step(x, k0 + i, x->tiles(), x->at(x->L.cur), x->at(x->L.cur), x->at(x->L.grid_pre),
+    const ddm_status s = forward_step(x, k0 + i, x->tiles(), x->cur(), x->cur(), x->at(x->L.grid_pre),
                                       x->at(x->L.grid_post));
     if (s != DDM_OK) return s;
     ++x->steps;
@@ -672,7 +696,7 @@ ddm_status ddm_loss(ddm_ctx* x, const double* target_hm_dev, double* loss_dev) {
                          hipMemcpyDeviceToDevice, x->stream));
   {
     Timed t(x, 8);
-    ddm::launch_loss(x->prec, x->kc, x->bufs(), (int)x->L.nblk, x->at(x->L.cur), x->at<uint32_t>(x->L.pid),
+    ddm::launch_loss(x->prec, x->kc, x->bufs(), (int)x->L.nblk, x->cur(), x->pid(),
                      (int)x->steps - 1, x->lossbufs(), x->stream);
   }
   DDM_HIP(hipMemcpyAsync(loss_dev, x->at(x->L.loss), sizeof(double) * x->n_inst, hipMemcpyDeviceToDevice, x->stream));
@@ -693,7 +717,7 @@ ddm_status ddm_backward(ddm_ctx* x, const double* dloss_dev, double* grad_dev) {
   { Timed t(x, 7); ddm::launch_fill_zero(x->at(L.gvb), (int64_t)L.grid_bytes / esz, esz, st); }
   void* adj[2] = {x->at(L.adj0), x->at(L.adj1)};
   int cur = 0;
-  ddm::launch_loss_seed(x->prec, x->kc, b, (int)L.nblk, x->at(L.cur), x->at<uint32_t>(L.pid), (int)x->steps - 1,
+  ddm::launch_loss_seed(x->prec, x->kc, b, (int)L.nblk, x->cur(), x->pid(), (int)x->steps - 1,
                         x->lossbufs(), adj[cur], x->at<double>(L.pacc), st);
   const int K = L.K;
   const int64_t n = x->rec_n, k0 = x->rec_k0;
@@ -706,21 +730,27 @@ ddm_status ddm_backward(ddm_ctx* x, const double* dloss_dev, double* grad_dev) {
   for (int seg = nseg - 1; seg >= 0; --seg) {
     const int64_t s0 = (int64_t)seg * K;
     const int len = (int)std::min<int64_t>(K, n - s0);
-    DDM_HIP(hipMemcpyAsync(slot(0), x->at(L.ckpt + (size_t)seg * L.state_bytes), L.state_bytes, hipMemcpyDeviceToDevice, st));
-    // Replay the segment: same binning steps as the recorded forward pass.
+    // Replay the segment: same binning steps as the recorded forward pass.  A
+    // binning gathers into its slot from the checkpoint (the first step of a
+    // segment always re-bins) or from the spare buffer the previous step wrote.
+    const void* ck = x->at(L.ckpt + (size_t)seg * L.state_bytes);
+    void* spare = x->at(x->spare_off);
     std::vector<int> tl_of(len, 0);
     int last = 0;
     for (int j = 0; j < len; ++j) {
       if (x->rec_sorted[(size_t)(s0 + j)]) {
-        const ddm_status s = bin_state(x, slot(j), nullptr, perm(j),
+        const ddm_status s = bin_state(x, j == 0 ? ck : spare, slot(j), nullptr, nullptr, perm(j),
                                        x->at<ddm::TileRec>(L.seg_tiles + sizeof(ddm::TileRec) * L.max_chunks * j),
                                        x->at<uint32_t>(L.seg_tcount + sizeof(uint32_t) * j));
         if (s != DDM_OK) return s;
         last = j;
+      } else if (j == 0) {
+        DDM_HIP(hipMemcpyAsync(slot(0), ck, L.state_bytes, hipMemcpyDeviceToDevice, st));
       }
       tl_of[j] = last;
-      const ddm_status s = forward_step(x, k0 + s0 + j, x->seg_tiles(last), slot(j), slot(j + 1), gpre(j), gpost(j), tau(j),
-                                          x->seg_alist(j), x->seg_acount(j));
+      const bool next_bins = j + 1 < len && x->rec_sorted[(size_t)(s0 + j + 1)];
+      const ddm_status s = forward_step(x, k0 + s0 + j, x->seg_tiles(last), slot(j), next_bins ? spare : slot(j + 1),
+                                          gpre(j), gpost(j), tau(j), x->seg_alist(j), x->seg_acount(j));
       if (s != DDM_OK) return s;
     }
     for (int j = len - 1; j >= 0; --j) {
@@ -797,9 +827,14 @@ ddm_status ddm_pass(ddm_ctx* x, const void* x0_dev, int32_t n_steps, const doubl
     if (ei != hipSuccess) { drop_graph(x); return hip_check(ei, "instantiate the pass graph"); }
     x->g_x0 = x0_dev; x->g_steps = n_steps; x->g_target = target_hm_dev; x->g_dloss = dloss_dev;
     x->g_loss = loss_dev; x->g_grad = grad_dev;
+    x->g_cur_off = x->cur_off; x->g_spare_off = x->spare_off;
+    x->g_pid_off = x->pid_off; x->g_pid_spare_off = x->pid_spare_off;
   }
   DDM_HIP(hipGraphLaunch(x->gexec, x->stream));
-  // host-side state after a pass (the capture set it the same way)
+  // host-side state after a pass (the capture set it the same way); the graph
+  // ends with the state in the buffers that were current when it was captured
+  x->cur_off = x->g_cur_off; x->spare_off = x->g_spare_off;
+  x->pid_off = x->g_pid_off; x->pid_spare_off = x->g_pid_spare_off;
   x->steps = n_steps;
   x->initialised = true;
   x->recorded = true;
@@ -838,8 +873,8 @@ ddm_status ddm_autotune(ddm_ctx* x, const char* cache_path, int32_t* sort_every_
     const int cand[] = {2, 4, 8, 16, 32};
     void* snap = x->at(L.seg_state);
     void* pid_snap = x->at(L.seg_perm);
-    DDM_HIP(hipMemcpyAsync(snap, x->at(L.cur), L.state_bytes, hipMemcpyDeviceToDevice, x->stream));
-    DDM_HIP(hipMemcpyAsync(pid_snap, x->at(L.pid), sizeof(uint32_t) * L.ntot, hipMemcpyDeviceToDevice, x->stream));
+    DDM_HIP(hipMemcpyAsync(snap, x->cur(), L.state_bytes, hipMemcpyDeviceToDevice, x->stream));
+    DDM_HIP(hipMemcpyAsync(pid_snap, x->pid(), sizeof(uint32_t) * L.ntot, hipMemcpyDeviceToDevice, x->stream));
     const int saved_R = x->cfg.sort_every;
     const bool saved_timing = x->timing;
     x->timing = false;
@@ -850,19 +885,19 @@ ddm_status ddm_autotune(ddm_ctx* x, const char* cache_path, int32_t* sort_every_
     ddm_status st = DDM_OK;
     for (int rep = 0; rep < 2 && st == DDM_OK; ++rep) {          // the first round warms up
       for (int R : cand) {
-        DDM_HIP(hipMemcpyAsync(x->at(L.cur), snap, L.state_bytes, hipMemcpyDeviceToDevice, x->stream));
-        DDM_HIP(hipMemcpyAsync(x->at(L.pid), pid_snap, sizeof(uint32_t) * L.ntot, hipMemcpyDeviceToDevice, x->stream));
+        DDM_HIP(hipMemcpyAsync(x->cur(), snap, L.state_bytes, hipMemcpyDeviceToDevice, x->stream));
+        DDM_HIP(hipMemcpyAsync(x->pid(), pid_snap, sizeof(uint32_t) * L.ntot, hipMemcpyDeviceToDevice, x->stream));
         x->cfg.sort_every = R;
         x->need_sort = true;
         DDM_HIP(hipEventRecord(e0, x->stream));
         for (int i = 0; i < P && st == DDM_OK; ++i) {
           // pose rows 0 .. P-1: the cost of a sub-step does not depend on the pose
           if (sort_due(x, i)) {
-            st = bin_state(x, x->at(L.cur), x->at<uint32_t>(L.pid), nullptr, nullptr, nullptr);
+            st = bin_current(x);
             x->need_sort = false;
           }
           if (st == DDM_OK)
-            st = forward_step(x, i, x->tiles(), x->at(L.cur), x->at(L.cur), x->at(L.grid_pre), x->at(L.grid_post));
+            st = forward_step(x, i, x->tiles(), x->cur(), x->cur(), x->at(L.grid_pre), x->at(L.grid_post));
         }
         DDM_HIP(hipEventRecord(e1, x->stream));
         DDM_HIP(hipEventSynchronize(e1));
@@ -873,8 +908,8 @@ ddm_status ddm_autotune(ddm_ctx* x, const char* cache_path, int32_t* sort_every_
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    DDM_HIP(hipMemcpyAsync(x->at(L.cur), snap, L.state_bytes, hipMemcpyDeviceToDevice, x->stream));
-    DDM_HIP(hipMemcpyAsync(x->at(L.pid), pid_snap, sizeof(uint32_t) * L.ntot, hipMemcpyDeviceToDevice, x->stream));
+    DDM_HIP(hipMemcpyAsync(x->cur(), snap, L.state_bytes, hipMemcpyDeviceToDevice, x->stream));
+    DDM_HIP(hipMemcpyAsync(x->pid(), pid_snap, sizeof(uint32_t) * L.ntot, hipMemcpyDeviceToDevice, x->stream));
     DDM_HIP(hipStreamSynchronize(x->stream));
     x->timing = saved_timing;
     x->cfg.sort_every = saved_R;
@@ -893,16 +928,16 @@ ddm_status ddm_autotune(ddm_ctx* x, const char* cache_path, int32_t* sort_every_
 
 ddm_status ddm_get_state(ddm_ctx* x, void* state_dev) {
   if (!x || !state_dev) return fail(DDM_EINVAL, "NULL argument");
-  ddm::launch_export_state(x->kc, x->bufs(), (int)x->L.nblk, x->L.rows, x->L.esz, x->at(x->L.cur), state_dev,
-                           x->at<uint32_t>(x->L.pid), x->stream);
+  ddm::launch_export_state(x->kc, x->bufs(), (int)x->L.nblk, x->L.rows, x->L.esz, x->cur(), state_dev,
+                           x->pid(), x->stream);
   return launch_status();
 }
 
 ddm_status ddm_set_state(ddm_ctx* x, const void* state_dev) {
   if (!x || !state_dev) return fail(DDM_EINVAL, "NULL argument");
   if (!x->initialised) return fail(DDM_ESTATE, "ddm_init_state first");
-  DDM_HIP(hipMemcpyAsync(x->at(x->L.cur), state_dev, x->L.state_bytes, hipMemcpyDeviceToDevice, x->stream));
-  ddm::launch_reset_pid(x->bufs(), (int)x->L.nblk, x->at<uint32_t>(x->L.pid), x->stream);
+  DDM_HIP(hipMemcpyAsync(x->cur(), state_dev, x->L.state_bytes, hipMemcpyDeviceToDevice, x->stream));
+  ddm::launch_reset_pid(x->bufs(), (int)x->L.nblk, x->pid(), x->stream);
   ddm::launch_fill_zero(x->at(x->L.gout), (int64_t)(x->L.grid_bytes / 4), 4, x->stream);
   x->grid_valid = false;
   x->recorded = false;
@@ -917,7 +952,7 @@ ddm_status ddm_bin_keys(ddm_ctx* x, uint32_t* keys_dev, uint32_t* perm_dev) {
   const Layout& L = x->L;
   uint32_t* keys[2] = {x->at<uint32_t>(L.keys0), x->at<uint32_t>(L.keys1)};
   uint32_t* vals[2] = {x->at<uint32_t>(L.vals0), x->at<uint32_t>(L.vals1)};
-  ddm::launch_keys(x->prec, x->kc, x->bufs(), (int)L.nblk, x->at(L.cur), keys[0], vals[0], x->stream);
+  ddm::launch_keys(x->prec, x->kc, x->bufs(), (int)L.nblk, x->cur(), keys[0], vals[0], x->stream);
   DDM_HIP(hipMemcpyAsync(keys_dev, keys[0], sizeof(uint32_t) * L.ntot, hipMemcpyDeviceToDevice, x->stream));
   const int r = ddm::radix_sort(keys, vals, L.ntot, L.max_key, x->at<uint32_t>(L.hist), x->at<uint32_t>(L.sums), x->stream);
   DDM_HIP(hipMemcpyAsync(perm_dev, vals[r], sizeof(uint32_t) * L.ntot, hipMemcpyDeviceToDevice, x->stream));
