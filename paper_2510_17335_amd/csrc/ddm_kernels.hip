@@ -1431,57 +1431,88 @@ __global__ void __launch_bounds__(kBlock) k_p2g_adj_gather(KCfg c, Bufs b, const
         }
 #pragma unroll
       for (int a = 0; a < D; ++a) vel[a] = st.v(a, p);
-      T mpb = T(0), vb[3] = {T(0), T(0), T(0)}, Ab[3][3] = {{T(0), T(0), T(0)}, {T(0), T(0), T(0)}, {T(0), T(0), T(0)}};
+      // Node o (weight w_o, offset r_o = (o - f) dx) received m_p w_o and
+      // w_o t_o, t_o = m_p v + A r_o.  With g_m, g_v its mass and momentum
+      // adjoints and G = sum w_o g_v:
+      //   mass adjoint   sum w_o (g_m + v . g_v) = sum w_o g_m + v . G
+      //   v bar          m_p G
+      //   A bar          sum w_o g_v r_o^T
+      //   x bar         += sum grad w_o (m_p g_m + g_v . t_o) - A^T G
+      // The sums run along the last axis first and are factored by axis.
       T xb[3];
 #pragma unroll
       for (int a = 0; a < D; ++a) xb[a] = ac.x(a, p);     // G2P part, written by k_g2p_adj
       const T* g = gbar + I.goff * kNodeVals;
+      T rr[3][3], dwi[3][3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          rr[a][k] = a < D ? (T(k) - S.f[a]) * dx : T(0);
+          dwi[a][k] = a < D ? S.dw[a][k] * inv_dx : T(0);
+        }
+      T mvv[3] = {T(0), T(0), T(0)}, Bl[3] = {T(0), T(0), T(0)};
+#pragma unroll
+      for (int a = 0; a < D; ++a) { mvv[a] = mp * vel[a]; Bl[a] = A[a][D - 1] * dx; }
+      T G[3] = {T(0), T(0), T(0)}, Gm = T(0), xg[3] = {T(0), T(0), T(0)};
+      T Ab[3][3] = {{T(0), T(0), T(0)}, {T(0), T(0), T(0)}, {T(0), T(0), T(0)}};
 #pragma unroll
       for (int o0 = 0; o0 < 3; ++o0)
 #pragma unroll
-        for (int o1 = 0; o1 < 3; ++o1)
+        for (int o1 = 0; o1 < (D == 3 ? 3 : 1); ++o1) {
+          // 3D: row (o0, o1) along axis 2; 2D: row o0 along axis 1
+          const T wa = S.w[0][o0], wb = D == 3 ? S.w[1][o1] : T(1);
+          const T wxy = wa * wb;
+          const T a0 = dwi[0][o0] * wb, a1 = D == 3 ? wa * dwi[1][o1] : T(0);
+          T t[3] = {T(0), T(0), T(0)};
 #pragma unroll
-          for (int o2 = 0; o2 < (D == 3 ? 3 : 1); ++o2) {
-            const int off[3] = {o0, o1, o2};
-            T w = T(1), r[3], gw[3];
+          for (int a = 0; a < D; ++a)
+            t[a] = mvv[a] + A[a][0] * rr[0][o0] + (D == 3 ? A[a][1] * rr[1][o1] : T(0)) + A[a][D - 1] * rr[D - 1][0];
+          T u[3] = {T(0), T(0), T(0)}, ul[3] = {T(0), T(0), T(0)}, um = T(0), sw = T(0), sd = T(0);
 #pragma unroll
-            for (int a = 0; a < D; ++a) r[a] = (T(off[a]) - S.f[a]) * dx;
-#pragma unroll
-            for (int a = 0; a < D; ++a) {
-              T prod = S.dw[a][off[a]] * inv_dx;
-#pragma unroll
-              for (int bb = 0; bb < D; ++bb)
-                if (bb != a) prod *= S.w[bb][off[bb]];
-              gw[a] = prod;
-              w *= S.w[a][off[a]];
-            }
-            const int64_t nd = node_of<D>(S.base, o0, o1, o2, c.n) * kNodeVals;
+          for (int ol = 0; ol < 3; ++ol) {
+            const T wl = S.w[D - 1][ol];
+            const int64_t nd = (D == 3 ? node_of<D>(S.base, o0, o1, ol, c.n) : node_of<D>(S.base, o0, ol, 0, c.n)) * kNodeVals;
             const Node4<T> gn = ld_node(g + nd);
-            T mvb[3];
+            T sc = mp * gn.v[3];
 #pragma unroll
-            for (int a = 0; a < D; ++a) mvb[a] = gn.v[a];
-            const T mb = gn.v[3];
-            // value scattered to this node: m_p w and w (m_p v + A r)
-            T sc = mp * mb;
-            T vm = T(0);
+            for (int a = 0; a < D; ++a) sc += gn.v[a] * t[a];
+            sw += wl * sc;
+            sd += dwi[D - 1][ol] * sc;
+            um += wl * gn.v[3];
+            const T wr = wl * rr[D - 1][ol];
 #pragma unroll
-            for (int a = 0; a < D; ++a) {
-              T ar = mp * vel[a];
-#pragma unroll
-              for (int bb = 0; bb < D; ++bb) ar += A[a][bb] * r[bb];
-              sc += mvb[a] * ar;
-              vm += vel[a] * mvb[a];
-            }
-            mpb += w * (mb + vm);
-#pragma unroll
-            for (int a = 0; a < D; ++a) {
-              vb[a] += w * mp * mvb[a];
-              T atm = T(0);
-#pragma unroll
-              for (int bb = 0; bb < D; ++bb) { Ab[a][bb] += w * mvb[a] * r[bb]; atm += A[bb][a] * mvb[bb]; }
-              xb[a] += gw[a] * sc - w * atm;
-            }
+            for (int a = 0; a < D; ++a) { u[a] += wl * gn.v[a]; ul[a] += wr * gn.v[a]; t[a] += Bl[a]; }
           }
+          Gm += wxy * um;
+          if (D == 3) {
+            xg[0] += a0 * sw;
+            xg[1] += a1 * sw;
+            xg[2] += wxy * sd;
+          } else {
+            xg[0] += a0 * sw;
+            xg[1] += wa * sd;
+          }
+          const T r0 = wxy * rr[0][o0], r1 = D == 3 ? wxy * rr[1][o1] : T(0);
+#pragma unroll
+          for (int a = 0; a < D; ++a) {
+            G[a] += wxy * u[a];
+            Ab[a][0] += r0 * u[a];
+            if (D == 3) Ab[a][1] += r1 * u[a];
+            Ab[a][D - 1] += wxy * ul[a];
+          }
+        }
+      T vb[3] = {T(0), T(0), T(0)};
+      T mpb = Gm;
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        mpb += vel[a] * G[a];
+        vb[a] = mp * G[a];
+        T atg = T(0);
+#pragma unroll
+        for (int bb = 0; bb < D; ++bb) atg += A[bb][a] * G[bb];
+        xb[a] += xg[a] - atg;
+      }
 #pragma unroll
       for (int a = 0; a < D; ++a) {
         ac.x(a, p) = xb[a];
