@@ -740,26 +740,36 @@ __global__ void __launch_bounds__(kBlock) k_g2p(KCfg c, Bufs b, const void* st_i
   if (!make_stencil<T, D>(si, p, c, S)) { flag_error(b.err, 2u, inst); return; }
   const T dx = T(c.dx), Dk = T(4.0 * c.inv_dx * c.inv_dx);
   const T* g = post + I.goff * kNodeVals;
+  // v_p = sum w_o v_o, C_p = (4/dx^2) sum w_o v_o r_o^T with r_o = (o - f) dx:
+  // sums along the last axis first, then per row
   T vn[3] = {T(0), T(0), T(0)}, Cn[3][3] = {{T(0), T(0), T(0)}, {T(0), T(0), T(0)}, {T(0), T(0), T(0)}};
+  T rr[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) rr[a][k] = a < D ? (T(k) - S.f[a]) * dx : T(0);
 #pragma unroll
   for (int o0 = 0; o0 < 3; ++o0)
 #pragma unroll
-    for (int o1 = 0; o1 < 3; ++o1)
+    for (int o1 = 0; o1 < (D == 3 ? 3 : 1); ++o1) {
+      const T wxy = S.w[0][o0] * (D == 3 ? S.w[1][o1] : T(1));
+      T u[3] = {T(0), T(0), T(0)}, ul[3] = {T(0), T(0), T(0)};
 #pragma unroll
-      for (int o2 = 0; o2 < (D == 3 ? 3 : 1); ++o2) {
-        const int off[3] = {o0, o1, o2};
-        T w = T(1), r[3];
+      for (int ol = 0; ol < 3; ++ol) {
+        const T wl = S.w[D - 1][ol], wr = wl * rr[D - 1][ol];
+        const Node4<T> nd = ld_node(g + (D == 3 ? node_of<D>(S.base, o0, o1, ol, c.n) : node_of<D>(S.base, o0, ol, 0, c.n)) * kNodeVals);
 #pragma unroll
-        for (int a = 0; a < D; ++a) { w *= S.w[a][off[a]]; r[a] = (T(off[a]) - S.f[a]) * dx; }
-        const Node4<T> nd = ld_node(g + node_of<D>(S.base, o0, o1, o2, c.n) * kNodeVals);
-#pragma unroll
-        for (int a = 0; a < D; ++a) {
-          const T vi = nd.v[a];
-          vn[a] += w * vi;
-#pragma unroll
-          for (int bb = 0; bb < D; ++bb) Cn[a][bb] += (Dk * w) * vi * r[bb];
-        }
+        for (int a = 0; a < D; ++a) { u[a] += wl * nd.v[a]; ul[a] += wr * nd.v[a]; }
       }
+      const T r0 = Dk * wxy * rr[0][o0], r1 = D == 3 ? Dk * wxy * rr[1][o1] : T(0), wl2 = Dk * wxy;
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        vn[a] += wxy * u[a];
+        Cn[a][0] += r0 * u[a];
+        if (D == 3) Cn[a][1] += r1 * u[a];
+        Cn[a][D - 1] += wl2 * ul[a];
+      }
+    }
   const T dt = T(b.inst[inst].dt);
   T chk = T(0);
   bool ok = true;
