@@ -325,7 +325,10 @@ __device__ __forceinline__ bool p2g_particle(const KCfg& c, const Bufs& b, const
 // active, so the gain comes from issuing about 1/ppc as many atomics.
 // ---------------------------------------------------------------------------
 template <typename T> struct alignas(16) RunLDS {
-  T rec[4][kBlock][4];            // group g of slot t: (q0 q1 q2 -), (B_a0 B_a1 B_a2 f_a) for a = g - 1
+  // group g of slot t (w_a^k: weight of offset k on axis a; w_a^1 = 1 - w_a^0 - w_a^2):
+  //   0: q0 q1 q2 w_0^0   1: B00 B01 B02 w_0^2   2: B10 B11 B12 w_1^0
+  //   3: B20 B21 B22 w_1^2   4: w_2^0 w_2^2 - -
+  T rec[5][kBlock][4];
   int wbase[kBlock];
   int wcount[kBlock / 64];
   unsigned short start[kBlock + 1];
@@ -342,24 +345,31 @@ template <> __device__ __forceinline__ void ld4<float>(const float* p, float (&o
   o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
 }
 
-// Phase-1 record of slot t.
+// Phase-1 record of slot t: q, B and the stencil weights w[axis][offset].
 template <typename T, int D>
-__device__ __forceinline__ void put_record(RunLDS<T>& L, int t, const T (&q)[3], const T (&B)[3][3], const T (&f)[3]) {
-  st4<T>(L.rec[0][t], q[0], q[1], D == 3 ? q[2] : T(0), T(0));
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    if (a < D) st4<T>(L.rec[1 + a][t], B[a][0], B[a][1], D == 3 ? B[a][2] : T(0), f[a]);
-    else st4<T>(L.rec[1 + a][t], T(0), T(0), T(0), T(0));
+__device__ __forceinline__ void put_record(RunLDS<T>& L, int t, const T (&q)[3], const T (&B)[3][3], const T (&w)[3][3]) {
+  st4<T>(L.rec[0][t], q[0], q[1], D == 3 ? q[2] : T(0), w[0][0]);
+  st4<T>(L.rec[1][t], B[0][0], B[0][1], D == 3 ? B[0][2] : T(0), w[0][2]);
+  st4<T>(L.rec[2][t], B[1][0], B[1][1], D == 3 ? B[1][2] : T(0), w[1][0]);
+  if (D == 3) {
+    st4<T>(L.rec[3][t], B[2][0], B[2][1], B[2][2], w[1][2]);
+    st4<T>(L.rec[4][t], w[2][0], w[2][2], T(0), T(0));
+  } else {
+    st4<T>(L.rec[3][t], T(0), T(0), T(0), w[1][2]);
   }
 }
 
 // Phase 2 for a round of rc slots whose records and wbase are in L (the
 // caller synchronised after writing them).  NV = D + 1 scatters momentum and
-// mass (mass per particle m); NV = D scatters a D-vector.  Ends synchronised.
-template <typename T, int D, int NV>
+// mass (mass per particle m); NV = D scatters a D-vector.  Work items cover
+// NN = 3 or 9 nodes of a run's stencil: NN = 9 takes a plane (fixed offset o0
+// in 3D, the whole stencil in 2D), NN = 3 a row along the last axis (fewer
+// registers, more items).  Ends synchronised.
+template <typename T, int D, int NV, int NN>
 __device__ void run_scatter_round(RunLDS<T>& L, int rc, double* win, T m) {
   constexpr int WS = Win<D>::stride;
-  constexpr int ROWS = D == 3 ? 9 : 3;
+  constexpr int NJ = NN / 3;                                  // rows per item
+  constexpr int ITEMS = (D == 3 ? 9 : 3) / NJ;                // items per run
   const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
   const bool flag = t < rc && L.wbase[t] >= 0 && (t == 0 || L.wbase[t] != L.wbase[t - 1]);
   const unsigned long long bal = __ballot(flag);
@@ -371,50 +381,74 @@ __device__ void run_scatter_round(RunLDS<T>& L, int rc, double* win, T m) {
   if (flag) L.start[off + __popcll(bal & ((1ull << lane) - 1ull))] = (unsigned short)t;
   if (t == 0) L.start[tot] = (unsigned short)rc;
   __syncthreads();
-  for (int it = t; it < tot * ROWS; it += kBlock) {
-    const int r = it / ROWS, row = it - r * ROWS;
-    const int o0 = D == 3 ? row / 3 : row, o1 = D == 3 ? row % 3 : 0;
+  for (int it = t; it < tot * ITEMS; it += kBlock) {
+    const int r = it / ITEMS, sub = it - r * ITEMS;
+    // the item's first row: 3D (o0, j0), 2D j0; rows j0 .. j0 + NJ - 1 along the middle axis
+    const int o0 = D == 3 ? (NJ == 3 ? sub : sub / 3) : 0;
+    const int j0 = NJ == 3 ? 0 : (D == 3 ? sub % 3 : sub);
     const int s0 = L.start[r], s1 = L.start[r + 1];
     const int base = L.wbase[s0];
-    T acc[3][4] = {{T(0), T(0), T(0), T(0)}, {T(0), T(0), T(0), T(0)}, {T(0), T(0), T(0), T(0)}};
+    // acc[row j][node k][value]: 3D node (o0, j0 + j, k), 2D node (j0 + j, k)
+    T acc[NJ][3][4];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j)
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int a = 0; a < 4; ++a) acc[j][k][a] = T(0);
     for (int sl = s0; sl < s1; ++sl) {
       if (L.wbase[sl] != base) continue;            // a particle without a window record
-      T q[4], b0[4], b1[4], b2[4];
-      ld4<T>(L.rec[0][sl], q);
-      ld4<T>(L.rec[1][sl], b0);
-      ld4<T>(L.rec[2][sl], b1);
-      if (D == 3) ld4<T>(L.rec[3][sl], b2);
-      // B column c of row a is b_a[c]; f_a is b_a[3]
-      T wr[3], dw[3], wa[3], wi[3];
-      bspline<T>(b0[3], wa, dw);
-      T wrow = wa[o0];
-      if (D == 3) { bspline<T>(b1[3], wr, dw); wrow *= wr[o1]; bspline<T>(b2[3], wi, dw); }
-      else bspline<T>(b1[3], wi, dw);
-      // t = q + B (o0, o1, 0) (3D) or q + B (o0, 0) (2D); then + B e_last per node
-      T tv[3], bl[3];
-      const T bcol0[3] = {b0[0], b1[0], D == 3 ? b2[0] : T(0)};
-      const T bcol1[3] = {b0[1], b1[1], D == 3 ? b2[1] : T(0)};
-      const T bcol2[3] = {b0[2], b1[2], D == 3 ? b2[2] : T(0)};
+      T g0[4], g1[4], g2[4], g3[4], g4[4] = {T(0), T(0), T(0), T(0)};
+      ld4<T>(L.rec[0][sl], g0);
+      ld4<T>(L.rec[1][sl], g1);
+      ld4<T>(L.rec[2][sl], g2);
+      ld4<T>(L.rec[3][sl], g3);
+      if (D == 3) ld4<T>(L.rec[4][sl], g4);
+      // per-axis weights
+      const T wa[3] = {g0[3], T(1) - g0[3] - g1[3], g1[3]};
+      const T wb[3] = {g2[3], T(1) - g2[3] - g3[3], g3[3]};
+      const T wc[3] = {g4[0], T(1) - g4[0] - g4[1], g4[1]};
+      // B columns (B row a is group a + 1)
+      const T bc0[3] = {g1[0], g2[0], D == 3 ? g3[0] : T(0)};
+      const T bc1[3] = {g1[1], g2[1], D == 3 ? g3[1] : T(0)};
+      const T bc2[3] = {g1[2], g2[2], D == 3 ? g3[2] : T(0)};
+      // 3D: inner axes 1 (j) and 2 (k) at fixed o0; 2D: axes 0 (j) and 1 (k)
+      const T wo = D == 3 ? (o0 == 0 ? wa[0] : (o0 == 1 ? wa[1] : wa[2])) : T(1);
+      const T(&wj)[3] = D == 3 ? wb : wa;
+      const T(&wk)[3] = D == 3 ? wc : wb;
+      const T(&bj)[3] = D == 3 ? bc1 : bc0;
+      const T(&bk)[3] = D == 3 ? bc2 : bc1;
+      T tj[3];
 #pragma unroll
-      for (int a = 0; a < D; ++a) {
-        tv[a] = q[a] + T(o0) * bcol0[a] + (D == 3 ? T(o1) * bcol1[a] : T(0));
-        bl[a] = D == 3 ? bcol2[a] : bcol1[a];
+      for (int a = 0; a < D; ++a) tj[a] = g0[a] + (D == 3 ? T(o0) * bc0[a] : T(0)) + (NJ == 3 ? T(0) : T(j0) * bj[a]);
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        const int jj = NJ == 3 ? j : j0;
+        const T w1 = wo * (jj == 0 ? wj[0] : (jj == 1 ? wj[1] : wj[2]));
+        T tk[3];
+#pragma unroll
+        for (int a = 0; a < D; ++a) tk[a] = tj[a];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          const T w = w1 * wk[k];
+#pragma unroll
+          for (int a = 0; a < D; ++a) { acc[j][k][a] += w * tk[a]; tk[a] += bk[a]; }
+          if (NV == D + 1) acc[j][k][3] += w;
+        }
+#pragma unroll
+        for (int a = 0; a < D; ++a) tj[a] += bj[a];
       }
+    }
+#pragma unroll
+    for (int j = 0; j < NJ; ++j)
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
-        const T w = wrow * wi[k];
+        const int jj = NJ == 3 ? j : j0;
+        const int wi = base + (D == 3 ? Win<D>::idx(o0, jj, k) : Win<D>::idx(jj, k, 0));
 #pragma unroll
-        for (int a = 0; a < D; ++a) { acc[k][a] += w * tv[a]; tv[a] += bl[a]; }
-        if (NV == D + 1) acc[k][3] += w;
+        for (int a = 0; a < D; ++a) atomicAdd(win + a * WS + wi, (double)acc[j][k][a]);
+        if (NV == D + 1) atomicAdd(win + 3 * WS + wi, (double)(acc[j][k][3] * m));
       }
-    }
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const int wi = base + (D == 3 ? Win<D>::idx(o0, o1, k) : Win<D>::idx(o0, k, 0));
-#pragma unroll
-      for (int a = 0; a < D; ++a) atomicAdd(win + a * WS + wi, (double)acc[k][a]);
-      if (NV == D + 1) atomicAdd(win + 3 * WS + wi, (double)(acc[k][3] * m));
-    }
   }
   __syncthreads();
 }
@@ -513,8 +547,7 @@ __global__ void __launch_bounds__(kBlock) k_p2g(KCfg c, Bufs b, TileList tl, con
           for (int a = 0; a < D; ++a) { loc[a] = S.base[a] - org[a]; inwin &= loc[a] >= 0 && loc[a] <= kWin - 3; }
           if (inwin) {
             wb = Win<D>::idx(loc[0], loc[1], loc[2]);
-            T f[3] = {S.f[0], S.f[1], D == 3 ? S.f[2] : T(0)};
-            put_record<T, D>(rl, threadIdx.x, q, B, f);
+            put_record<T, D>(rl, threadIdx.x, q, B, S.w);
           } else {
             mark_stencil_blocks<D>(c, inst, S.base, act);
             scatter_stencil<T, D>(S.w, q, B, mpt, [&](int o0, int o1, int o2, const T (&v)[4]) {
@@ -528,7 +561,7 @@ __global__ void __launch_bounds__(kBlock) k_p2g(KCfg c, Bufs b, TileList tl, con
       }
       rl.wbase[threadIdx.x] = wb;
       __syncthreads();
-      run_scatter_round<T, D, D + 1>(rl, rc, win, mpt);
+      run_scatter_round<T, D, D + 1, 3>(rl, rc, win, mpt);
     }
     __syncthreads();
     // the whole window, zeros included, to the tile's staging record
@@ -1229,8 +1262,7 @@ __global__ void __launch_bounds__(kBlock) k_g2p_adj(KCfg c, Bufs b, TileList tl,
                return ld_node(gwin[wn0 + (D == 3 ? (o0 * kWin + o1) * kWin + o2 : o0 * kWin + o1)]);
              });
         wb = Win<D>::idx(loc[0], loc[1], loc[2]);
-        T f[3] = {S.f[0], S.f[1], D == 3 ? S.f[2] : T(0)};
-        put_record<T, D>(rl, threadIdx.x, q, B, f);
+        put_record<T, D>(rl, threadIdx.x, q, B, S.w);
       } else {
         body([&](int, int, int, int64_t nd, T w, const T (&t)[3]) {
 #pragma unroll
@@ -1250,7 +1282,7 @@ __global__ void __launch_bounds__(kBlock) k_g2p_adj(KCfg c, Bufs b, TileList tl,
     } while (false);
     rl.wbase[threadIdx.x] = wb;
     __syncthreads();
-    run_scatter_round<T, D, D>(rl, rc, win, T(0));
+    run_scatter_round<T, D, D, 9>(rl, rc, win, T(0));
     }
     __syncthreads();
     for (int i = threadIdx.x; i < Win<D>::nodes; i += kBlock) {
