@@ -1381,12 +1381,15 @@ __global__ void __launch_bounds__(kBlock) k_grid_adj(KCfg c, Bufs b, int step, c
             any = true;
           }
         }
+        // m bar = -(u bar . mv) / m^2, formed as -(u bar . (mv / m)) / m: for a node
+        // that holds only a sliver of B-spline weight, m^2 underflows in FP32
+        const T im = T(1) / m;
         T dot = T(0);
 #pragma unroll
-        for (int a = 0; a < D; ++a) dot += ub[a] * pr.v[a];
-        mb = -dot / (m * m);
+        for (int a = 0; a < D; ++a) dot += ub[a] * (pr.v[a] * im);
+        mb = -dot * im;
 #pragma unroll
-        for (int a = 0; a < D; ++a) ub[a] = ub[a] / m;
+        for (int a = 0; a < D; ++a) ub[a] = ub[a] * im;
       }
     }
     gb[gid * kNodeVals + 0] = ub[0];
