@@ -42,7 +42,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="sysid64", choices=["sysid64", "dig3d_bwd", "dig3d_large"])
+    ap.add_argument("--workload", default="sysid64", choices=["sysid64", "dig3d_bwd", "dig3d_large", "optim"])
     ap.add_argument("--sub-steps", type=int, default=None, help="override rollout length (testing only)")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
@@ -161,6 +161,32 @@ def cpu_baseline(ws):
                       f"forward-mode tangents, {dt:.1f} s"}
 
 
+def optimiser_bench(args, torch, ddm):
+    """Skill optimisation on the 64^3 dig (500 sub-steps, FP32): RMSprop with
+    the 5-candidate line search, every iteration one fwd+bwd pass and one
+    batched forward of the 5 candidates.  Reports iterations per second."""
+    from paper_2510_17335_amd import optim as O
+    w = W.dig_3d(steps=args.sub_steps or 500)
+    x0, tg = W.bed_positions(w), W.target_heightmap(w)
+    ev = O.GpuEvaluator(ddm, w, x0, tg, w.steps, checkpoint_every=50)
+    spec = O.OptimSpec(free=["depth", "angle_deg", "push"], step=O.skill_steps())
+    O.optimise(w.params7, spec, ev.grad, ev.losses, max(1, args.warmup))      # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = O.optimise(w.params7, spec, ev.grad, ev.losses, args.steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    n = sum(w.n_particles for _ in range(1)) * w.steps
+    out = {"metric": "optimiser iterations/s (skill optimisation, 1 fwd+bwd pass + 5 batched candidate forwards)",
+           "value": args.steps / el, "unit": "iterations/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": 1e3 * el / args.steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic (seeded bed and target, no dataset)",
+           "config": {"workload": f"optim: dig3d 64^3, {w.n_particles} particles, {w.steps} sub-steps, free depth/angle/push",
+                      "particle_steps_per_iteration": n * 6},
+           "losses": [h["loss"] for h in st.history], "chosen_alpha": [O.LINE_SEARCH[h["chosen"]] for h in st.history]}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -169,6 +195,9 @@ def main():
         sys.exit(2)
     import torch
     import paper_2510_17335_amd as ddm
+    if args.workload == "optim":
+        optimiser_bench(args, torch, ddm)
+        return
     assert torch.cuda.is_available(), "needs a GPU"
     dev = torch.device("cuda:0")
     if args.copy_calib:

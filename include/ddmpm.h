@@ -153,6 +153,17 @@ ddm_status ddm_workspace_query(const ddm_config* cfg, int32_t n_inst, const ddm_
 ddm_status ddm_create(const ddm_config* cfg, int32_t n_inst, const ddm_instance* inst,
                       void* workspace, size_t workspace_bytes, void* stream, ddm_ctx** out);
 
+/* Replaces the per-instance parameters (material, skill, dt, tip0) of a
+ * context for the next pass, for optimiser loops and parameter sweeps that
+ * reuse one workspace (Sec. III-D: the parameters change every iteration, the
+ * problem does not).  n_inst and every n_particles must equal those given to
+ * ddm_create.  Recomputes and uploads the instance constants and the pose
+ * tables with synchronous copies, after waiting for the context's stream.
+ * A recorded rollout and its loss are dropped; a graph captured by ddm_pass
+ * stays valid and uses the new values.  Errors: DDM_EINVAL as
+ * ddm_validate_config, or for a changed count. */
+ddm_status ddm_set_instances(ddm_ctx* ctx, int32_t n_inst, const ddm_instance* inst);
+
 /* Initial particle positions, device pointer to x0[n_total][dim] row-major in
  * the context's precision, instances concatenated in order.  Sets v = 0,
  * C = 0, F = I (the flattened bed at rest, Sec. III-A), resets the step

@@ -78,6 +78,7 @@ def lib():
             "ddm_workspace_query": (C.c_int, [cfgp, i32, instp, C.POINTER(DdmSizes)]),
             "ddm_create": (C.c_int, [cfgp, i32, instp, vp, C.c_size_t, vp, C.POINTER(vp)]),
             "ddm_init_state": (C.c_int, [vp, vp]),
+            "ddm_set_instances": (C.c_int, [vp, i32, instp]),
             "ddm_step": (C.c_int, [vp, i32]),
             "ddm_rollout": (C.c_int, [vp, i32]),
             "ddm_loss": (C.c_int, [vp, vp, vp]),
@@ -236,6 +237,14 @@ class Simulator:
             except Exception:
                 pass
             self.ctx = None
+
+    def set_instances(self, instances: Sequence[DdmInstance]):
+        """New per-instance parameters (same count and particle counts), e.g.
+        the candidates of an optimiser step (ddm_set_instances)."""
+        instances = list(instances)
+        arr = (DdmInstance * len(instances))(*instances)
+        _check(lib().ddm_set_instances(self.ctx, len(instances), arr))
+        self.instances = instances
 
     # -- state ---------------------------------------------------------------
     @property

@@ -470,6 +470,74 @@ bool sort_due(const ddm_ctx* x, int64_t step) {
   return x->need_sort || (R > 0 && step % R == 0);
 }
 
+// Per-instance constants (Lame constants from (E, nu), alpha_f and the
+// cohesion shift from the friction angle, particle mass and volume, and their
+// derivatives for the final chain rule), the block-to-instance map, and the
+// pose table with its Jacobian; uploaded with synchronous copies.
+ddm_status upload_instances(ddm_ctx* x, const ddm_instance* inst) {
+  const ddm_config* cfg = &x->cfg;
+  const Layout& L = x->L;
+  const int n_inst = x->n_inst;
+  const ddm::KCfg& k = x->kc;
+  ddm_status s = DDM_OK;
+  std::vector<ddm::InstDev> dev(n_inst);
+  std::vector<int> blk((size_t)L.nblk);
+  int64_t off = 0;
+  const double dxd = std::pow(1.0 / cfg->n_grid, cfg->dim);
+  for (int i = 0; i < n_inst; ++i) {
+    const ddm_instance& s = inst[i];
+    ddm::InstDev& d = dev[i];
+    const double E = s.E, nu = s.nu, ph = s.phi_deg * kPi / 180.0, sp = std::sin(ph), cp = std::cos(ph);
+    d.mu = E / (2.0 * (1.0 + nu));
+    d.lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+    const double r23 = std::sqrt(2.0 / 3.0);
+    d.alpha = r23 * 2.0 * sp / (3.0 - sp);
+    d.kc = r23 * 6.0 * s.cohesion * cp / (3.0 - sp);
+    d.Vp = dxd / cfg->ppc;
+    d.mp = s.rho * d.Vp;
+    d.dt = s.dt;
+    d.dmu_dE = 1.0 / (2.0 * (1.0 + nu));
+    d.dmu_dnu = -E / (2.0 * (1.0 + nu) * (1.0 + nu));
+    const double den = (1.0 + nu) * (1.0 - 2.0 * nu);
+    d.dlam_dE = nu / den;
+    d.dlam_dnu = E * (1.0 + 2.0 * nu * nu) / (den * den);
+    const double rad = kPi / 180.0;
+    d.dal_dphi = r23 * 6.0 * cp / ((3.0 - sp) * (3.0 - sp)) * rad;
+    d.dkc_dphi = r23 * 6.0 * s.cohesion * (1.0 - 3.0 * sp) / ((3.0 - sp) * (3.0 - sp)) * rad;
+    d.off = off;
+    d.n = s.n_particles;
+    d.goff = (int64_t)i * k.nodes;
+    for (int a = 0; a < 3; ++a) d.tip0[a] = s.tip0[a];
+    const int64_t np = pad_up(s.n_particles, ddm::kBlock);
+    for (int64_t bI = off / ddm::kBlock; bI < (off + np) / ddm::kBlock; ++bI) blk[(size_t)bI] = i;
+    off += np;
+  }
+  std::vector<double> poses((size_t)n_inst * cfg->max_steps * 8, 0.0), jac((size_t)n_inst * cfg->max_steps * 24, 0.0);
+  if (cfg->shovel) {
+    for (int i = 0; i < n_inst; ++i) {
+      std::vector<double> p, j;
+      pose_table(*cfg, inst[i], p, j);
+      std::copy(p.begin(), p.end(), poses.begin() + (size_t)i * cfg->max_steps * 8);
+      std::copy(j.begin(), j.end(), jac.begin() + (size_t)i * cfg->max_steps * 24);
+    }
+  }
+  // device rows: the 8 pose values and sin / cos of the blade angle
+  std::vector<double> prow((size_t)n_inst * cfg->max_steps * ddm::kPoseVals, 0.0);
+  for (size_t r = 0; r < (size_t)n_inst * cfg->max_steps; ++r) {
+    std::copy(poses.begin() + r * 8, poses.begin() + r * 8 + 8, prow.begin() + r * ddm::kPoseVals);
+    prow[r * ddm::kPoseVals + 8] = std::sin(poses[r * 8 + 3]);
+    prow[r * ddm::kPoseVals + 9] = std::cos(poses[r * 8 + 3]);
+  }
+  std::vector<char> poses_t;
+  if (x->prec) to_prec<double>(prow, poses_t); else to_prec<float>(prow, poses_t);
+  // Host staging arrays are copied synchronously so the caller's memory is free on return.
+  s = hip_check(hipMemcpy(x->at(L.inst), dev.data(), sizeof(ddm::InstDev) * n_inst, hipMemcpyHostToDevice), "upload instances");
+  if (s == DDM_OK) s = hip_check(hipMemcpy(x->at(L.blk_inst), blk.data(), sizeof(int) * blk.size(), hipMemcpyHostToDevice), "upload block map");
+  if (s == DDM_OK) s = hip_check(hipMemcpy(x->at(L.poses), poses_t.data(), poses_t.size(), hipMemcpyHostToDevice), "upload poses");
+  if (s == DDM_OK) s = hip_check(hipMemcpy(x->at(L.pose_jac), jac.data(), jac.size() * sizeof(double), hipMemcpyHostToDevice), "upload pose Jacobian");
+  return s;
+}
+
 }  // namespace
 
 extern "C" {
@@ -550,67 +618,28 @@ ddm_status ddm_create(const ddm_config* cfg, int32_t n_inst, const ddm_instance*
   k.hm_off = cfg->hm_offset; k.region_depth = cfg->region_depth;
   k.w_hm = cfg->w_hm; k.w_mass = cfg->w_mass; k.m_target = cfg->m_target; k.m_ref = cfg->m_ref;
 
-  // Per-instance constants: Lame constants from (E, nu), alpha_f and the
-  // cohesion shift from the friction angle, particle mass and volume, and
-  // their derivatives for the final chain rule.
-  std::vector<ddm::InstDev> dev(n_inst);
-  std::vector<int> blk((size_t)L.nblk);
-  int64_t off = 0;
-  const double dxd = std::pow(1.0 / cfg->n_grid, cfg->dim);
-  for (int i = 0; i < n_inst; ++i) {
-    const ddm_instance& s = inst[i];
-    ddm::InstDev& d = dev[i];
-    const double E = s.E, nu = s.nu, ph = s.phi_deg * kPi / 180.0, sp = std::sin(ph), cp = std::cos(ph);
-    d.mu = E / (2.0 * (1.0 + nu));
-    d.lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
-    const double r23 = std::sqrt(2.0 / 3.0);
-    d.alpha = r23 * 2.0 * sp / (3.0 - sp);
-    d.kc = r23 * 6.0 * s.cohesion * cp / (3.0 - sp);
-    d.Vp = dxd / cfg->ppc;
-    d.mp = s.rho * d.Vp;
-    d.dt = s.dt;
-    d.dmu_dE = 1.0 / (2.0 * (1.0 + nu));
-    d.dmu_dnu = -E / (2.0 * (1.0 + nu) * (1.0 + nu));
-    const double den = (1.0 + nu) * (1.0 - 2.0 * nu);
-    d.dlam_dE = nu / den;
-    d.dlam_dnu = E * (1.0 + 2.0 * nu * nu) / (den * den);
-    const double rad = kPi / 180.0;
-    d.dal_dphi = r23 * 6.0 * cp / ((3.0 - sp) * (3.0 - sp)) * rad;
-    d.dkc_dphi = r23 * 6.0 * s.cohesion * (1.0 - 3.0 * sp) / ((3.0 - sp) * (3.0 - sp)) * rad;
-    d.off = off;
-    d.n = s.n_particles;
-    d.goff = (int64_t)i * k.nodes;
-    for (int a = 0; a < 3; ++a) d.tip0[a] = s.tip0[a];
-    const int64_t np = pad_up(s.n_particles, ddm::kBlock);
-    for (int64_t bI = off / ddm::kBlock; bI < (off + np) / ddm::kBlock; ++bI) blk[(size_t)bI] = i;
-    off += np;
-  }
-  std::vector<double> poses((size_t)n_inst * cfg->max_steps * 8, 0.0), jac((size_t)n_inst * cfg->max_steps * 24, 0.0);
-  if (cfg->shovel) {
-    for (int i = 0; i < n_inst; ++i) {
-      std::vector<double> p, j;
-      pose_table(*cfg, inst[i], p, j);
-      std::copy(p.begin(), p.end(), poses.begin() + (size_t)i * cfg->max_steps * 8);
-      std::copy(j.begin(), j.end(), jac.begin() + (size_t)i * cfg->max_steps * 24);
-    }
-  }
-  // device rows: the 8 pose values and sin / cos of the blade angle
-  std::vector<double> prow((size_t)n_inst * cfg->max_steps * ddm::kPoseVals, 0.0);
-  for (size_t r = 0; r < (size_t)n_inst * cfg->max_steps; ++r) {
-    std::copy(poses.begin() + r * 8, poses.begin() + r * 8 + 8, prow.begin() + r * ddm::kPoseVals);
-    prow[r * ddm::kPoseVals + 8] = std::sin(poses[r * 8 + 3]);
-    prow[r * ddm::kPoseVals + 9] = std::cos(poses[r * 8 + 3]);
-  }
-  std::vector<char> poses_t;
-  if (x->prec) to_prec<double>(prow, poses_t); else to_prec<float>(prow, poses_t);
-  // Host staging arrays are copied synchronously so the caller's memory is free on return.
-  s = hip_check(hipMemcpy(x->at(L.inst), dev.data(), sizeof(ddm::InstDev) * n_inst, hipMemcpyHostToDevice), "upload instances");
-  if (s == DDM_OK) s = hip_check(hipMemcpy(x->at(L.blk_inst), blk.data(), sizeof(int) * blk.size(), hipMemcpyHostToDevice), "upload block map");
-  if (s == DDM_OK) s = hip_check(hipMemcpy(x->at(L.poses), poses_t.data(), poses_t.size(), hipMemcpyHostToDevice), "upload poses");
-  if (s == DDM_OK) s = hip_check(hipMemcpy(x->at(L.pose_jac), jac.data(), jac.size() * sizeof(double), hipMemcpyHostToDevice), "upload pose Jacobian");
+  s = upload_instances(x, inst);
   if (s == DDM_OK) s = hip_check(hipMemset(x->at(L.err), 0, sizeof(ddm::DevErr)), "clear error word");
   if (s != DDM_OK) { delete x; return s; }
   *out = x;
+  return DDM_OK;
+}
+
+ddm_status ddm_set_instances(ddm_ctx* x, int32_t n_inst, const ddm_instance* inst) {
+  if (!x || !inst) return fail(DDM_EINVAL, "NULL argument");
+  if (n_inst != x->n_inst) return fail(DDM_EINVAL, "the instance count is fixed at ddm_create");
+  for (int i = 0; i < n_inst; ++i)
+    if (inst[i].n_particles != x->inst[(size_t)i].n_particles)
+      return fail(DDM_EINVAL, "instance " + std::to_string(i) + ": the particle count is fixed at ddm_create");
+  const ddm_status v = validate(&x->cfg, n_inst, inst);
+  if (v != DDM_OK) return v;
+  // kernels in flight may still read the old constants
+  DDM_HIP(hipStreamSynchronize(x->stream));
+  x->inst.assign(inst, inst + n_inst);
+  const ddm_status s = upload_instances(x, inst);
+  if (s != DDM_OK) return s;
+  x->recorded = false;
+  x->loss_ready = false;
   return DDM_OK;
 }
 
