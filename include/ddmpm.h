@@ -245,10 +245,46 @@ ddm_status ddm_get_grid(ddm_ctx* ctx, void* grid_dev);
  * double) into caller device memory. */
 ddm_status ddm_get_heightmap(ddm_ctx* ctx, double* hm_dev);
 
+/* Gradient treatments inside the reverse pass (Sec. III-E) and the record of
+ * how the adjoints grow backwards in time (Appendix D).
+ *   The adjoint of each key variable of a sub-step is treated as one vector
+ *   per instance.  Variables: 0 particle positions, 1 particle velocities,
+ *   2 particle deformation gradients (the adjoint state of the start of the
+ *   sub-step, after its reverse sub-step), 3 grid velocities after the grid
+ *   update (once G2P's adjoint is complete), 4 grid momenta and 5 grid masses
+ *   as P2G wrote them (once the grid update's adjoint is complete).  Each is
+ *   treated where it is complete, before the rest of the reverse pass reads it.
+ *   Modes: DDM_TREAT_NONE; DDM_TREAT_CLIP, every element into [-clip, clip];
+ *   DDM_TREAT_SCALE, divide the vector by 10^d + delta, d = round(log10(max
+ *   |element|)) - oom (halves rounded away from zero), when d > 0;
+ *   DDM_TREAT_NORM, divide it by (2-norm + delta).  The paper's values: clip
+ *   1e4, oom 4, delta 1e-6.  Treated gradients are not derivatives of the loss.
+ *   Record: with stats_dev != NULL (double, device, caller-owned,
+ *   [stats_steps][n_inst][6 variables][6], valid until the setting is
+ *   replaced), every ddm_backward first zeroes the buffer and then writes, for
+ *   each sub-step k < stats_steps of the recorded rollout, the max, min and
+ *   2-norm of each vector before the treatment and after it (the values before
+ *   it again for DDM_TREAT_NONE).  A vector's max shows a NaN in it.
+ *   The setting holds for later ddm_backward and ddm_pass calls; setting it
+ *   drops a captured ddm_pass graph.
+ *   Errors: DDM_EINVAL for a NULL context, an unknown mode, clip <= 0 with
+ *   DDM_TREAT_CLIP, a non-finite oom, delta < 0 or non-finite, stats_steps < 0,
+ *   or stats_dev and stats_steps > 0 not given together. */
+typedef enum ddm_grad_treatment {
+  DDM_TREAT_NONE = 0,
+  DDM_TREAT_CLIP = 1,
+  DDM_TREAT_SCALE = 2,
+  DDM_TREAT_NORM = 3
+} ddm_grad_treatment;
+
+ddm_status ddm_set_grad_treatment(ddm_ctx* ctx, int32_t mode, double clip, double oom, double delta,
+                                  double* stats_dev, int32_t stats_steps);
+
 /* Kernel timing for measurement: when enabled, every launch group of the
  * sub-step is bracketed by HIP events on the context's stream.  Groups:
  * 0 P2G, 1 grid update, 2 G2P, 3 binning (keys, sort, gather, tile list),
- * 4 G2P adjoint, 5 grid adjoint, 6 P2G adjoint, 7 grid clears, 8 loss.
+ * 4 G2P adjoint, 5 grid adjoint, 6 P2G adjoint, 7 grid clears, 8 loss,
+ * 9 gradient treatments and their statistics.
  * ddm_read_timing synchronises and returns the summed milliseconds and the
  * number of launches of a group since timing was enabled. */
 ddm_status ddm_set_timing(ddm_ctx* ctx, int32_t enable);

@@ -55,6 +55,12 @@ class DdmDeviceError(C.Structure):
     _fields_ = [("flags", C.c_uint32), ("first_instance", C.c_uint32), ("clamp_count", C.c_uint64)]
 
 
+# Gradient treatments of the reverse pass and the adjoint vectors they act on
+# (ddm_set_grad_treatment).
+TREATMENTS = ("none", "clip", "scale", "norm")
+TREAT_VARS = ("x", "v", "F", "grid_v_post", "grid_mv", "grid_m")
+
+
 class DdmError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"ddmpm error {code}: {msg}")
@@ -93,6 +99,7 @@ def lib():
             "ddm_check": (C.c_int, [vp, C.POINTER(DdmDeviceError)]),
             "ddm_steps_taken": (i64, [vp]),
             "ddm_instance_offset": (i64, [vp, i32]),
+            "ddm_set_grad_treatment": (C.c_int, [vp, i32, C.c_double, C.c_double, C.c_double, vp, i32]),
             "ddm_set_timing": (C.c_int, [vp, i32]),
             "ddm_read_timing": (C.c_int, [vp, i32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
             "ddm_destroy": (None, [vp]),
@@ -402,7 +409,32 @@ class Simulator:
         _check(lib().ddm_autotune(self.ctx, cache_path.encode() if cache_path else None, C.byref(r)))
         return int(r.value)
 
-    TIMING_GROUPS = ("p2g", "grid_update", "g2p", "binning", "g2p_adj", "grid_adj", "p2g_adj", "clear", "loss")
+    TIMING_GROUPS = ("p2g", "grid_update", "g2p", "binning", "g2p_adj", "grid_adj", "p2g_adj", "clear", "loss",
+                     "treat")
+
+    # -- gradient treatments (Sec. III-E) --------------------------------------
+    def set_grad_treatment(self, mode: str = "none", clip: float = 1e4, oom: float = 4.0, delta: float = 1e-6,
+                           record_steps: int = 0):
+        """Treatment of the adjoint vectors inside every later backward pass
+        (ddm_set_grad_treatment): mode in TREATMENTS; record_steps > 0 keeps
+        the max / min / 2-norm of each vector before and after its treatment
+        for sub-steps 0 .. record_steps-1, read back with grad_stats()."""
+        t = self.torch
+        code = TREATMENTS.index(mode)
+        self._stats = (t.zeros((record_steps, self.n_inst, len(TREAT_VARS), 6), dtype=t.float64, device=self.device)
+                       if record_steps > 0 else None)
+        ptr = C.c_void_p(self._stats.data_ptr()) if self._stats is not None else None
+        self._inputs_ready()
+        _check(lib().ddm_set_grad_treatment(self.ctx, code, float(clip), float(oom), float(delta), ptr,
+                                            int(record_steps)))
+
+    def grad_stats(self) -> np.ndarray:
+        """[record_steps, n_inst, 6 variables (TREAT_VARS), 6] of the last
+        backward pass: max, min, 2-norm before the treatment, then after it."""
+        if getattr(self, "_stats", None) is None:
+            raise RuntimeError("no statistics recorded: set_grad_treatment(record_steps=...) first")
+        self._outputs_ready()
+        return self._stats.cpu().numpy()
 
     def set_timing(self, enable: bool):
         _check(lib().ddm_set_timing(self.ctx, int(bool(enable))))

@@ -619,23 +619,6 @@ __device__ __forceinline__ void node_coords(int64_t node, int n, int idx[3]) {
   else { idx[0] = (int)(node / ((int64_t)n * n)); idx[1] = (int)((node / n) % n); idx[2] = (int)(node % n); }
 }
 
-// Node of an active-set item: item i is node i % 4^D of listed block i / 4^D.
-template <int D>
-__device__ __forceinline__ void active_node(const KCfg& c, uint32_t gb, int k, int& inst, int idx[3], int64_t& node) {
-  // grids are powers of two: blocks per axis 2^tb, blocks per instance 2^(D tb)
-  const int tb = c.nlog2 - 2, pb = D * tb;
-  const uint32_t mb = (1u << tb) - 1u;
-  inst = (int)(gb >> pb);
-  const uint32_t t = gb & ((1u << pb) - 1u);
-  int bc[3] = {0, 0, 0};
-  if (D == 3) { bc[0] = (int)(t >> (2 * tb)); bc[1] = (int)((t >> tb) & mb); bc[2] = (int)(t & mb); }
-  else { bc[0] = (int)(t >> tb); bc[1] = (int)(t & mb); }
-  if (D == 3) { idx[0] = bc[0] * kTile + (k >> 4); idx[1] = bc[1] * kTile + ((k >> 2) & 3); idx[2] = bc[2] * kTile + (k & 3); }
-  else { idx[0] = bc[0] * kTile + (k >> 2); idx[1] = bc[1] * kTile + (k & 3); idx[2] = 0; }
-  node = D == 3 ? ((int64_t)idx[0] << (2 * c.nlog2)) + ((int64_t)idx[1] << c.nlog2) + idx[2]
-                : ((int64_t)idx[0] << c.nlog2) + idx[1];
-}
-
 // Sum of the staged windows covering a node: per axis the tiles (x + 1) / 4 - 1
 // and (x + 1) / 4, whose windows start at 4t - 1.
 template <typename T, int D>

@@ -57,6 +57,23 @@ struct KCfg {
   double w_hm, w_mass, m_target, m_ref;
 };
 
+// Node of an active-set item: item i is node i % 4^D of listed block i / 4^D.
+template <int D>
+__device__ __forceinline__ void active_node(const KCfg& c, uint32_t gb, int k, int& inst, int idx[3], int64_t& node) {
+  // grids are powers of two: blocks per axis 2^tb, blocks per instance 2^(D tb)
+  const int tb = c.nlog2 - 2, pb = D * tb;
+  const uint32_t mb = (1u << tb) - 1u;
+  inst = (int)(gb >> pb);
+  const uint32_t t = gb & ((1u << pb) - 1u);
+  int bc[3] = {0, 0, 0};
+  if (D == 3) { bc[0] = (int)(t >> (2 * tb)); bc[1] = (int)((t >> tb) & mb); bc[2] = (int)(t & mb); }
+  else { bc[0] = (int)(t >> tb); bc[1] = (int)(t & mb); }
+  if (D == 3) { idx[0] = bc[0] * kTile + (k >> 4); idx[1] = bc[1] * kTile + ((k >> 2) & 3); idx[2] = bc[2] * kTile + (k & 3); }
+  else { idx[0] = bc[0] * kTile + (k >> 2); idx[1] = bc[1] * kTile + (k & 3); idx[2] = 0; }
+  node = D == 3 ? ((int64_t)idx[0] << (2 * c.nlog2)) + ((int64_t)idx[1] << c.nlog2) + idx[2]
+                : ((int64_t)idx[0] << c.nlog2) + idx[1];
+}
+
 // Pointers of one launch.
 struct Bufs {
   const InstDev* inst;
@@ -136,5 +153,28 @@ void launch_unpermute(int elem_bytes, const void* in, void* out, const uint32_t*
 // One record per occupied tile, and tslot (record of each tile, or kNoSlot).
 void launch_tile_list(const KCfg& c, const uint32_t* sorted_keys, uint32_t* tstart, uint32_t* tend, TileRec* list,
                       uint32_t* count, uint32_t* tslot, hipStream_t s);
+
+// Gradient treatments of the reverse pass (ddm_treat.hip).  Variables (one
+// vector per instance each): 0 particle x, 1 particle v, 2 particle F, 3 grid
+// velocity after the grid update, 4 grid momentum, 5 grid mass.  acc holds
+// treat_acc_words(n_inst) 64-bit words, [n_inst][variable][phase][3], zeroed
+// before each reduction; phase 0 is reduced before a treatment, phase 1 after it.
+constexpr int kTreatVars = 6;
+constexpr int kTreatNone = 0, kTreatClip = 1, kTreatScale = 2, kTreatNorm = 3;
+struct Treat { int mode; double clip, oom, delta; };
+size_t treat_acc_words(int n_inst);
+void launch_treat_stats_particles(int prec, const KCfg& c, const Bufs& b, int nblk, const void* adj,
+                                  unsigned long long* acc, int phase, hipStream_t s);
+void launch_treat_apply_particles(int prec, const KCfg& c, const Bufs& b, int nblk, void* adj, const Treat& t,
+                                  const unsigned long long* acc, hipStream_t s);
+// Grid vectors of the nodes of the listed active blocks: values 0 .. dim-1
+// of a node form variable var, value 3 variable var + 1 when with_mass.
+void launch_treat_stats_grid(int prec, const KCfg& c, const Bufs& b, const uint32_t* list, const uint32_t* count,
+                             const void* g, int var, bool with_mass, unsigned long long* acc, int phase, hipStream_t s);
+void launch_treat_apply_grid(int prec, const KCfg& c, const Bufs& b, const uint32_t* list, const uint32_t* count,
+                             void* g, int var, bool with_mass, const Treat& t, const unsigned long long* acc,
+                             hipStream_t s);
+// out[n_inst][kTreatVars][6]: max, min, 2-norm before the treatment and after it.
+void launch_treat_record(int n_inst, const unsigned long long* acc, bool post, double* out, hipStream_t s);
 
 }  // namespace ddm

@@ -51,6 +51,7 @@ struct Layout {
   size_t hm_bits = 0, owner = 0, target = 0, hm_val = 0, dldh = 0, region = 0, dldm = 0, loss = 0;
   size_t keys0 = 0, keys1 = 0, vals0 = 0, vals1 = 0, hist = 0, sums = 0, tstart = 0, tend = 0, tiles = 0, tcount = 0;
   size_t tslot = 0, staging = 0, gout = 0, amask = 0, alist = 0, acount = 0, seg_alist = 0, seg_acount = 0;
+  size_t treat_acc = 0;
   size_t total = 0;
   size_t state_bytes = 0, grid_bytes = 0;
   int64_t ntot = 0, nblk = 0, total_tiles = 0, max_chunks = 0;
@@ -120,6 +121,7 @@ Layout make_layout(const ddm_config& c, int n_inst, const ddm_instance* in) {
   L.gvb = cv.take(L.grid_bytes);
   L.gb = cv.take(L.grid_bytes);
   L.pacc = cv.take(sizeof(double) * 8 * n_inst);
+  L.treat_acc = cv.take(sizeof(unsigned long long) * ddm::treat_acc_words(n_inst));
   L.pose_bar = cv.take(sizeof(double) * 8 * (size_t)n_inst * c.max_steps);
   L.hm_bits = cv.take(sizeof(unsigned long long) * (size_t)n_inst * npix);
   L.owner = cv.take(sizeof(unsigned int) * (size_t)n_inst * npix);
@@ -252,6 +254,9 @@ void pose_table(const ddm_config& c, const ddm_instance& in, std::vector<double>
 
 }  // namespace
 
+// Launch groups timed by ddm_set_timing.
+constexpr int kTimingGroups = 10;
+
 struct ddm_ctx {
   ddm_config cfg;
   int n_inst = 0;
@@ -285,8 +290,12 @@ struct ddm_ctx {
   struct Ev { int group; hipEvent_t a, b; };
   std::vector<Ev> events;
   std::vector<hipEvent_t> pool;
-  double t_ms[9] = {0};
-  int64_t t_n[9] = {0};
+  double t_ms[kTimingGroups] = {0};
+  int64_t t_n[kTimingGroups] = {0};
+  // gradient treatments of the reverse pass and the caller's statistics buffer
+  ddm::Treat treat{ddm::kTreatNone, 1e4, 4.0, 1e-6};
+  double* stats_dev = nullptr;
+  int32_t stats_steps = 0;
 
   template <typename T = char> T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
   void* cur() const { return at(cur_off); }
@@ -733,6 +742,40 @@ ddm_status ddm_loss(ddm_ctx* x, const double* target_hm_dev, double* loss_dev) {
   return launch_status();
 }
 
+namespace {
+
+// Gradient treatment of one group of adjoint vectors (Sec. III-E): the
+// particle state (grid == false) or the nodes of the listed active blocks of
+// one grid buffer.  Statistics before the treatment when it or the record
+// needs them, the treatment, statistics after it for the record.
+struct TreatTarget {
+  bool grid;
+  void* g;                        // adjoint state or grid buffer
+  const uint32_t* list = nullptr;
+  const uint32_t* count = nullptr;
+  int var = 0;                    // first grid variable
+  bool with_mass = false;
+};
+
+void treat_vectors(ddm_ctx* x, bool record, const TreatTarget& t) {
+  unsigned long long* acc = x->at<unsigned long long>(x->L.treat_acc);
+  const ddm::Bufs b = x->bufs();
+  const int nblk = (int)x->L.nblk;
+  auto stats = [&](int ph) {
+    if (t.grid) ddm::launch_treat_stats_grid(x->prec, x->kc, b, t.list, t.count, t.g, t.var, t.with_mass, acc, ph, x->stream);
+    else ddm::launch_treat_stats_particles(x->prec, x->kc, b, nblk, t.g, acc, ph, x->stream);
+  };
+  const int m = x->treat.mode;
+  if (m == ddm::kTreatScale || m == ddm::kTreatNorm || record) stats(0);
+  if (m != ddm::kTreatNone) {
+    if (t.grid) ddm::launch_treat_apply_grid(x->prec, x->kc, b, t.list, t.count, t.g, t.var, t.with_mass, x->treat, acc, x->stream);
+    else ddm::launch_treat_apply_particles(x->prec, x->kc, b, nblk, t.g, x->treat, acc, x->stream);
+  }
+  if (record && m != ddm::kTreatNone) stats(1);
+}
+
+}  // namespace
+
 ddm_status ddm_backward(ddm_ctx* x, const double* dloss_dev, double* grad_dev) {
   if (!x || !dloss_dev || !grad_dev) return fail(DDM_EINVAL, "NULL argument");
   if (!x->recorded || !x->loss_ready) return fail(DDM_ESTATE, "ddm_backward needs ddm_rollout then ddm_loss");
@@ -744,6 +787,9 @@ ddm_status ddm_backward(ddm_ctx* x, const double* dloss_dev, double* grad_dev) {
   ddm::launch_fill_zero(x->at(L.pose_bar), (int64_t)8 * x->n_inst * x->cfg.max_steps, 8, st);
   // the v-bar grid starts at zero; each grid adjoint step clears what it read
   { Timed t(x, 7); ddm::launch_fill_zero(x->at(L.gvb), (int64_t)L.grid_bytes / esz, esz, st); }
+  const int64_t stat_vals = (int64_t)x->n_inst * ddm::kTreatVars * 6;
+  if (x->stats_dev) ddm::launch_fill_zero(x->stats_dev, stat_vals * x->stats_steps, 8, st);
+  unsigned long long* acc = x->at<unsigned long long>(L.treat_acc);
   void* adj[2] = {x->at(L.adj0), x->at(L.adj1)};
   int cur = 0;
   ddm::launch_loss_seed(x->prec, x->kc, b, (int)L.nblk, x->cur(), x->pid(), (int)x->steps - 1,
@@ -784,11 +830,29 @@ ddm_status ddm_backward(ddm_ctx* x, const double* dloss_dev, double* grad_dev) {
     }
     for (int j = len - 1; j >= 0; --j) {
       const ddm::TileList tl = x->seg_tiles(tl_of[j]);
+      const int64_t k = k0 + s0 + j;
+      const bool rec = x->stats_dev && k < x->stats_steps;
+      const bool treat = rec || x->treat.mode != ddm::kTreatNone;
+      const bool reduce = rec || x->treat.mode == ddm::kTreatScale || x->treat.mode == ddm::kTreatNorm;
+      if (reduce) { Timed t(x, 9); ddm::launch_fill_zero(acc, (int64_t)ddm::treat_acc_words(x->n_inst), 8, st); }
       { Timed t(x, 4); ddm::launch_g2p_adj(x->prec, x->kc, b, tl, L.nwg, slot(j), gpost(j), adj[cur], adj[1 - cur], x->at(L.gvb), st); }
-      { Timed t(x, 5); ddm::launch_grid_adj(x->prec, x->kc, b, (int)(k0 + s0 + j), x->seg_alist(j), x->seg_acount(j),
+      if (treat) {
+        Timed t(x, 9);
+        treat_vectors(x, rec, TreatTarget{true, x->at(L.gvb), x->seg_alist(j), x->seg_acount(j), 3, false});
+      }
+      { Timed t(x, 5); ddm::launch_grid_adj(x->prec, x->kc, b, (int)k, x->seg_alist(j), x->seg_acount(j),
                                             gpre(j), x->at(L.gvb), x->at(L.gb), x->at<double>(L.pose_bar), st); }
+      if (treat) {
+        Timed t(x, 9);
+        treat_vectors(x, rec, TreatTarget{true, x->at(L.gb), x->seg_alist(j), x->seg_acount(j), 4, true});
+      }
       { Timed t(x, 6); ddm::launch_p2g_adj(x->prec, x->kc, b, (int)L.nblk, slot(j), tau(j), x->at(L.gb), adj[cur], adj[1 - cur],
                                            x->at<double>(L.pacc), st); }
+      if (treat) {
+        Timed t(x, 9);
+        treat_vectors(x, rec, TreatTarget{false, adj[1 - cur]});
+        if (rec) ddm::launch_treat_record(x->n_inst, acc, x->treat.mode != ddm::kTreatNone, x->stats_dev + stat_vals * k, st);
+      }
       if (x->rec_sorted[(size_t)(s0 + j)]) {
         // the adjoint of a permutation is its inverse
         Timed t(x, 3);
@@ -830,6 +894,24 @@ void drop_graph(ddm_ctx* x) {
 }
 
 }  // namespace
+
+ddm_status ddm_set_grad_treatment(ddm_ctx* x, int32_t mode, double clip, double oom, double delta, double* stats_dev,
+                                  int32_t stats_steps) {
+  if (!x) return fail(DDM_EINVAL, "NULL context");
+  if (mode < DDM_TREAT_NONE || mode > DDM_TREAT_NORM) return fail(DDM_EINVAL, "mode must be one of DDM_TREAT_*");
+  if (mode == DDM_TREAT_CLIP && !(clip > 0)) return fail(DDM_EINVAL, "clip must be > 0");
+  if (!std::isfinite(oom)) return fail(DDM_EINVAL, "oom must be finite");
+  if (!(delta >= 0) || !std::isfinite(delta)) return fail(DDM_EINVAL, "delta must be finite and >= 0");
+  if (stats_steps < 0 || (stats_steps > 0) != (stats_dev != nullptr))
+    return fail(DDM_EINVAL, "stats_dev and stats_steps > 0 go together");
+  static_assert(DDM_TREAT_CLIP == ddm::kTreatClip && DDM_TREAT_SCALE == ddm::kTreatScale &&
+                    DDM_TREAT_NORM == ddm::kTreatNorm, "treatment codes");
+  x->treat = ddm::Treat{mode, clip, oom, delta};
+  x->stats_dev = stats_dev;
+  x->stats_steps = stats_steps;
+  drop_graph(x);   // a captured pass holds the old setting
+  return DDM_OK;
+}
 
 ddm_status ddm_pass(ddm_ctx* x, const void* x0_dev, int32_t n_steps, const double* target_hm_dev,
                     const double* dloss_dev, double* loss_dev, double* grad_dev, int32_t use_graph) {
@@ -1032,13 +1114,13 @@ ddm_status ddm_set_timing(ddm_ctx* x, int32_t enable) {
   if (!x) return fail(DDM_EINVAL, "NULL context");
   DDM_HIP(hipStreamSynchronize(x->stream));
   resolve_events(x);
-  for (int g = 0; g < 9; ++g) { x->t_ms[g] = 0.0; x->t_n[g] = 0; }
+  for (int g = 0; g < kTimingGroups; ++g) { x->t_ms[g] = 0.0; x->t_n[g] = 0; }
   x->timing = enable != 0;
   return DDM_OK;
 }
 
 ddm_status ddm_read_timing(ddm_ctx* x, int32_t group, double* total_ms, int64_t* launches) {
-  if (!x || group < 0 || group >= 9) return fail(DDM_EINVAL, "bad context or group");
+  if (!x || group < 0 || group >= kTimingGroups) return fail(DDM_EINVAL, "bad context or group");
   DDM_HIP(hipStreamSynchronize(x->stream));
   resolve_events(x);
   if (total_ms) *total_ms = x->t_ms[group];
