@@ -50,6 +50,9 @@ def parse():
     ap.add_argument("--sort-every", type=int, default=0,
                     help="binning interval; 0 = autotune the batched context (the plain loop uses 8)")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--treat", default="none", choices=["none", "clip", "scale", "norm", "record"],
+                    help="gradient treatment inside the reverse pass (Sec. III-E) at the paper's thresholds; "
+                         "'record' keeps the per-sub-step adjoint statistics without treating")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB device copy (calibrates the HBM byte counters)")
     return ap.parse_args()
@@ -161,6 +164,15 @@ def cpu_baseline(ws):
                       f"forward-mode tangents, {dt:.1f} s"}
 
 
+def treatment_kwargs(args, steps):
+    """Simulator.set_grad_treatment arguments for --treat (None for none)."""
+    if args.treat == "none":
+        return None
+    if args.treat == "record":
+        return {"mode": "none", "record_steps": steps}
+    return {"mode": args.treat}
+
+
 def optimiser_bench(args, torch, ddm):
     """Skill optimisation on the 64^3 dig (500 sub-steps, FP32): RMSprop with
     the 5-candidate line search, every iteration one fwd+bwd pass and one
@@ -168,7 +180,7 @@ def optimiser_bench(args, torch, ddm):
     from paper_2510_17335_amd import optim as O
     w = W.dig_3d(steps=args.sub_steps or 500)
     x0, tg = W.bed_positions(w), W.target_heightmap(w)
-    ev = O.GpuEvaluator(ddm, w, x0, tg, w.steps, checkpoint_every=50)
+    ev = O.GpuEvaluator(ddm, w, x0, tg, w.steps, checkpoint_every=50, treatment=treatment_kwargs(args, w.steps))
     spec = O.OptimSpec(free=["depth", "angle_deg", "push"], step=O.skill_steps())
     O.optimise(w.params7, spec, ev.grad, ev.losses, max(1, args.warmup))      # warm-up
     torch.cuda.synchronize()
@@ -182,6 +194,7 @@ def optimiser_bench(args, torch, ddm):
            "ms_per_step": 1e3 * el / args.steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "f32", "data": "synthetic (seeded bed and target, no dataset)",
            "config": {"workload": f"optim: dig3d 64^3, {w.n_particles} particles, {w.steps} sub-steps, free depth/angle/push",
+                      "grad_treatment": args.treat,
                       "particle_steps_per_iteration": n * 6},
            "losses": [h["loss"] for h in st.history], "chosen_alpha": [O.LINE_SEARCH[h["chosen"]] for h in st.history]}
     print(json.dumps(out), flush=True)
@@ -208,6 +221,9 @@ def main():
     # batched: one context on its own stream, binning interval autotuned on the
     # initial state (unless --sort-every is given)
     bp = Pass(ddm, ws, args.sort_every or 8, stream=torch.cuda.Stream())
+    treat = treatment_kwargs(args, ws[0].steps)
+    if treat:
+        bp.sim.set_grad_treatment(**treat)
     tuned = None
     if not args.sort_every:
         bp.sim.init_state(bp.x0)
@@ -307,6 +323,7 @@ def main():
         "config": {"workload": wname, "instances": len(ws), "particles": sum(w.n_particles for w in ws),
                    "sub_steps": ws[0].steps, "checkpoint_every": ws[0].checkpoint_every,
                    "sort_every": tuned or args.sort_every, "sort_every_autotuned": tuned is not None,
+                   "grad_treatment": args.treat,
                    "peak_mem_gb": round(peak_gb, 2)},
         "graph_value": graph_value,
         "plain_value": plain_value,

@@ -436,6 +436,19 @@ class Simulator:
         self._outputs_ready()
         return self._stats.cpu().numpy()
 
+    def grad_growth(self, segment: Optional[int] = None) -> np.ndarray:
+        """Growth of the adjoints backwards in time, per segment of `segment`
+        sub-steps (the checkpoint interval by default): [n_segments, n_inst,
+        6 variables, 2] = the largest magnitude and the largest 2-norm of each
+        variable's adjoint over the segment's sub-steps, before treatment."""
+        S = self.grad_stats()
+        seg = int(segment or self.cfg.checkpoint_every)
+        amax = np.maximum(np.abs(S[..., 0]), np.abs(S[..., 1]))
+        out = []
+        for k in range(0, S.shape[0], seg):
+            out.append(np.stack([amax[k:k + seg].max(axis=0), S[k:k + seg, ..., 2].max(axis=0)], axis=-1))
+        return np.stack(out)
+
     def set_timing(self, enable: bool):
         _check(lib().ddm_set_timing(self.ctx, int(bool(enable))))
 

@@ -163,17 +163,13 @@ constexpr int kTreatVars = 6;
 constexpr int kTreatNone = 0, kTreatClip = 1, kTreatScale = 2, kTreatNorm = 3;
 struct Treat { int mode; double clip, oom, delta; };
 size_t treat_acc_words(int n_inst);
-void launch_treat_stats_particles(int prec, const KCfg& c, const Bufs& b, int nblk, const void* adj,
-                                  unsigned long long* acc, int phase, hipStream_t s);
-void launch_treat_apply_particles(int prec, const KCfg& c, const Bufs& b, int nblk, void* adj, const Treat& t,
-                                  const unsigned long long* acc, hipStream_t s);
-// Grid vectors of the nodes of the listed active blocks: values 0 .. dim-1
-// of a node form variable var, value 3 variable var + 1 when with_mass.
-void launch_treat_stats_grid(int prec, const KCfg& c, const Bufs& b, const uint32_t* list, const uint32_t* count,
-                             const void* g, int var, bool with_mass, unsigned long long* acc, int phase, hipStream_t s);
-void launch_treat_apply_grid(int prec, const KCfg& c, const Bufs& b, const uint32_t* list, const uint32_t* count,
-                             void* g, int var, bool with_mass, const Treat& t, const unsigned long long* acc,
-                             hipStream_t s);
+// The treatment of the particle adjoints (x, v, F) and of one grid buffer
+// (variable var, and var + 1 for value 3 of a node when with_mass), with the
+// statistics before and after it into acc when record is set.
+void launch_treat_particles(int prec, const KCfg& c, const Bufs& b, int nblk, void* adj, const Treat& t, bool record,
+                            unsigned long long* acc, hipStream_t s);
+void launch_treat_grid(int prec, const KCfg& c, const Bufs& b, const uint32_t* list, const uint32_t* count, void* g,
+                       int var, bool with_mass, const Treat& t, bool record, unsigned long long* acc, hipStream_t s);
 // out[n_inst][kTreatVars][6]: max, min, 2-norm before the treatment and after it.
 void launch_treat_record(int n_inst, const unsigned long long* acc, bool post, double* out, hipStream_t s);
 

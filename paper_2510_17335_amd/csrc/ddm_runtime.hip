@@ -746,8 +746,7 @@ namespace {
 
 // Gradient treatment of one group of adjoint vectors (Sec. III-E): the
 // particle state (grid == false) or the nodes of the listed active blocks of
-// one grid buffer.  Statistics before the treatment when it or the record
-// needs them, the treatment, statistics after it for the record.
+// one grid buffer.
 struct TreatTarget {
   bool grid;
   void* g;                        // adjoint state or grid buffer
@@ -760,18 +759,10 @@ struct TreatTarget {
 void treat_vectors(ddm_ctx* x, bool record, const TreatTarget& t) {
   unsigned long long* acc = x->at<unsigned long long>(x->L.treat_acc);
   const ddm::Bufs b = x->bufs();
-  const int nblk = (int)x->L.nblk;
-  auto stats = [&](int ph) {
-    if (t.grid) ddm::launch_treat_stats_grid(x->prec, x->kc, b, t.list, t.count, t.g, t.var, t.with_mass, acc, ph, x->stream);
-    else ddm::launch_treat_stats_particles(x->prec, x->kc, b, nblk, t.g, acc, ph, x->stream);
-  };
-  const int m = x->treat.mode;
-  if (m == ddm::kTreatScale || m == ddm::kTreatNorm || record) stats(0);
-  if (m != ddm::kTreatNone) {
-    if (t.grid) ddm::launch_treat_apply_grid(x->prec, x->kc, b, t.list, t.count, t.g, t.var, t.with_mass, x->treat, acc, x->stream);
-    else ddm::launch_treat_apply_particles(x->prec, x->kc, b, nblk, t.g, x->treat, acc, x->stream);
-  }
-  if (record && m != ddm::kTreatNone) stats(1);
+  if (t.grid)
+    ddm::launch_treat_grid(x->prec, x->kc, b, t.list, t.count, t.g, t.var, t.with_mass, x->treat, record, acc, x->stream);
+  else
+    ddm::launch_treat_particles(x->prec, x->kc, b, (int)x->L.nblk, t.g, x->treat, record, acc, x->stream);
 }
 
 }  // namespace

@@ -5,7 +5,10 @@ simulator (Sec. III-D, III-E, III-F; experiment design in Sec. IV-B).
   parameter units (Table I for E, nu, rho, phi_f; the skill step of 0.03 on the
   normalised skill parameters of Eqs. d1-d3, converted to physical units by
   `skill_steps`).
-- An element-wise clip of the parameter gradients at 1e4 (Sec. III-E).
+- The gradient treatments of Sec. III-E inside the reverse pass (clipping of
+  the particle and grid adjoints at 1e4 is the paper's best setting), passed
+  to `GpuEvaluator` as `treatment`; and, on top, an element-wise clip of the
+  parameter gradients at `OptimSpec.clip` (1e4 by default, inf disables it).
 - A line search before each update (Sec. III-F): the update is scaled by
   alpha in {0.1, 0.5, 1.0, 1.5, 2.0}; the five candidates are run as five
   instances of one batched forward launch and the one with the lowest loss is
@@ -132,13 +135,18 @@ class GpuEvaluator:
     initial positions x0 and a target height map."""
 
     def __init__(self, ddm, w, x0: np.ndarray, target: np.ndarray, steps: int, batch: int = len(LINE_SEARCH),
-                 checkpoint_every: int = 50, precision: Optional[str] = None, sort_every: int = 8):
+                 checkpoint_every: int = 50, precision: Optional[str] = None, sort_every: int = 8,
+                 treatment: Optional[dict] = None):
+        """treatment: keyword arguments of Simulator.set_grad_treatment for
+        the gradient passes, e.g. {"mode": "clip", "clip": 1e4}."""
         self.ddm = ddm
         self.steps = steps
         cfg, inst = ddm.from_workload(w, max_steps=steps, checkpoint_every=checkpoint_every, precision=precision,
                                       sort_every=sort_every)
         self.base = inst
         self.grad_sim = ddm.Simulator(cfg, [inst])
+        if treatment:
+            self.grad_sim.set_grad_treatment(**treatment)
         self.batch = batch
         self.batch_sim = ddm.Simulator(cfg, [inst] * batch)
         self.x0 = np.asarray(x0)

@@ -115,6 +115,14 @@ def test_record_keeps_gradient_and_is_consistent(ddm, precision):
     if precision == "f32":
         _same_record(sim.grad_stats(), S, precision, "second record")
     _log("norms of x-bar at steps 0, mid, last:", S[0, 0, 0, 2], S[STEPS // 2, 0, 0, 2], S[-1, 0, 0, 2])
+    # growth per checkpoint segment: maxima over the segment's sub-steps
+    G = sim.grad_growth()
+    S = sim.grad_stats()
+    assert G.shape == ((STEPS + 15) // 16, 1, 6, 2)
+    amax = np.maximum(np.abs(S[..., 0]), np.abs(S[..., 1]))
+    for q in range(G.shape[0]):
+        assert np.array_equal(G[q, ..., 0], amax[16 * q:16 * (q + 1)].max(axis=0))
+        assert np.array_equal(G[q, ..., 1], S[16 * q:16 * (q + 1), ..., 2].max(axis=0))
 
 
 def test_idle_thresholds_keep_gradient(ddm):
@@ -214,3 +222,24 @@ def test_graph_pass_with_treatment(ddm):
         _log(f"replay {rep}: {g[0]}")
         _same(g, ge, "f32", f"gradient of replay {rep}")
         _same_record(sim.grad_stats(), Se, "f32", f"record of replay {rep}")
+
+
+def test_optimiser_evaluator_applies_treatment(ddm):
+    """GpuEvaluator(treatment=...) computes its gradients with the treatment."""
+    from paper_2510_17335_amd import optim as O
+    _log("case evaluator with clip f32")
+    w = W.dig_3d(steps=STEPS)
+    x0, tg = W.bed_positions(w), W.target_heightmap(w)
+    plain = O.GpuEvaluator(ddm, w, x0, tg, STEPS, batch=2, checkpoint_every=16, precision="f32")
+    _, g0 = plain.grad(w.params7)
+    _, sim, xs, tgs = _sim(ddm, "f32")
+    sim.set_grad_treatment("none", record_steps=STEPS)
+    _grad(sim, xs, tgs)
+    c, _ = _acting_thresholds(sim.grad_stats())
+    sim.set_grad_treatment("clip", clip=c)
+    gs = _grad(sim, xs, tgs)[0]
+    ev = O.GpuEvaluator(ddm, w, x0, tg, STEPS, batch=2, checkpoint_every=16, precision="f32",
+                        treatment={"mode": "clip", "clip": c})
+    _, g1 = ev.grad(w.params7)
+    _same(g1, gs, "f32", "evaluator with clip")
+    assert not np.allclose(g1, g0, rtol=1e-3)
