@@ -157,7 +157,7 @@ def cpu_baseline(ws):
     steps = int(min(60, max(1, round(1.3e6 / w.n_particles))))
     s0 = oracle.initial_state(W.bed_positions(w))
     t0 = time.perf_counter()
-    oracle.rollout(oracle.config(w), w.params7, s0, steps, target=W.target_heightmap(w), grad=True)
+    oracle.rollout(oracle.config(w), w.params, s0, steps, target=W.target_heightmap(w), grad=True)
     dt = time.perf_counter() - t0
     return {"value": w.n_particles * steps / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
             "sample": f"smallest instance ({w.n_particles} particles), {steps} sub-steps, FP64 with 7 "
@@ -182,10 +182,10 @@ def optimiser_bench(args, torch, ddm):
     x0, tg = W.bed_positions(w), W.target_heightmap(w)
     ev = O.GpuEvaluator(ddm, w, x0, tg, w.steps, checkpoint_every=50, treatment=treatment_kwargs(args, w.steps))
     spec = O.OptimSpec(free=["depth", "angle_deg", "push"], step=O.skill_steps())
-    O.optimise(w.params7, spec, ev.grad, ev.losses, max(1, args.warmup))      # warm-up
+    O.optimise(w.params, spec, ev.grad, ev.losses, max(1, args.warmup))      # warm-up
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    st = O.optimise(w.params7, spec, ev.grad, ev.losses, args.steps)
+    st = O.optimise(w.params, spec, ev.grad, ev.losses, args.steps)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     n = sum(w.n_particles for _ in range(1)) * w.steps

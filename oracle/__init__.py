@@ -15,6 +15,10 @@ from typing import Optional
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
+
+# Differentiable inputs, in the order of rollout's params and gradient:
+# E, nu, phi_deg, rho, depth, angle_deg, push, displace, push_angle_deg.
+N_PARAMS = 9
 LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _SRC = [os.path.join(_HERE, "oracle.cpp"), os.path.join(_HERE, "dual.hpp")]
 
@@ -35,7 +39,7 @@ def build(force: bool = True) -> str:
 class OrcConfig(C.Structure):
     _fields_ = [
         ("dim", C.c_int32), ("n_grid", C.c_int32), ("bound", C.c_int32), ("n_sub", C.c_int32),
-        ("shovel", C.c_int32), ("hm_res", C.c_int32), ("region_sign", C.c_int32), ("pad0", C.c_int32),
+        ("shovel", C.c_int32), ("hm_res", C.c_int32), ("region_sign", C.c_int32), ("skill_unrounded", C.c_int32),
         ("dt", C.c_double), ("gravity", C.c_double), ("ppc", C.c_double),
         ("half_w", C.c_double), ("half_n", C.c_double), ("half_p", C.c_double),
         ("skin", C.c_double), ("mu_b", C.c_double),
@@ -45,6 +49,7 @@ class OrcConfig(C.Structure):
         ("region_depth", C.c_double), ("m_target", C.c_double), ("m_ref", C.c_double),
         ("w_mass", C.c_double), ("w_hm", C.c_double),
         ("cohesion", C.c_double),
+        ("particle_contact", C.c_int32), ("pad1", C.c_int32),
     ]
 
 
@@ -62,11 +67,10 @@ def lib():
         L.orc_rollout.argtypes = [C.POINTER(OrcConfig), dp, C.c_int, dp, C.c_int, C.c_int, dp, dp, dp, dp, dp,
                                   C.POINTER(C.c_int64), dp]
         L.orc_skill_actions.restype = C.c_int
-        L.orc_skill_actions.argtypes = [dp, C.c_double, C.c_double, C.c_double, C.c_double, C.c_int,
+        L.orc_skill_actions.argtypes = [dp, C.c_double, C.c_double, C.c_double, C.c_double, C.c_int, C.c_int,
                                         C.POINTER(C.c_int), dp, dp]
         L.orc_pose_table.restype = C.c_int
-        L.orc_pose_table.argtypes = [C.POINTER(OrcConfig), C.c_double, C.c_double, C.c_double, C.c_double,
-                                     C.c_int, dp, dp]
+        L.orc_pose_table.argtypes = [C.POINTER(OrcConfig), dp, C.c_double, C.c_int, dp, dp]
         L.orc_svd.argtypes = [C.c_int, dp, dp, dp, dp]
         L.orc_material.argtypes = [C.c_double] * 4 + [dp]
         L.orc_material.restype = None
@@ -113,6 +117,8 @@ def config(w, shovel: Optional[bool] = None, **over) -> OrcConfig:
     c.region_depth, c.m_target, c.m_ref = w.region_depth, w.m_target, w.m_ref
     c.w_mass, c.w_hm = w.w_mass, w.w_hm
     c.cohesion = w.material.cohesion
+    c.skill_unrounded = int(w.skill_unrounded)
+    c.particle_contact = int(w.particle_contact)
     for k, v in over.items():
         setattr(c, k, v)
     return c
@@ -155,7 +161,7 @@ def rollout(cfg: OrcConfig, params: np.ndarray, state: np.ndarray, n_steps: int,
     n = state.shape[0]
     out = np.zeros_like(state)
     loss = np.zeros(1)
-    g = np.zeros(7) if grad else None
+    g = np.zeros(N_PARAMS) if grad else None
     npix = cfg.hm_res ** (cfg.dim - 1)
     hm = np.zeros(npix) if target is not None else None
     tgt = np.ascontiguousarray(target, dtype=np.float64).reshape(-1) if target is not None else None
@@ -177,22 +183,25 @@ def rollout(cfg: OrcConfig, params: np.ndarray, state: np.ndarray, n_steps: int,
     return res
 
 
-def skill_actions(theta, v_l=3.0, v_w=10.0 * np.pi, dta=2e-3, d4=0.01, max_T=10000):
+def skill_actions(theta, v_l=3.0, v_w=10.0 * np.pi, dta=2e-3, d4=0.01, max_T=10000, unrounded=False):
     L = lib()
     th = np.ascontiguousarray(theta, dtype=np.float64)
     T = (C.c_int * 4)()
     acts = np.zeros((max_T, 6))
     jac = np.zeros((max_T, 6, 5))
-    n = L.orc_skill_actions(_p(th), v_l, v_w, dta, d4, max_T, T, _p(acts), _p(jac))
+    n = L.orc_skill_actions(_p(th), v_l, v_w, dta, d4, int(bool(unrounded)), max_T, T, _p(acts), _p(jac))
     if n < 0:
         raise OracleError("too many actions")
     return list(T), acts[:n].copy(), jac[:n].copy()
 
 
-def pose_table(cfg: OrcConfig, depth: float, angle_deg: float, push: float, dt: float, n_steps: int):
+def pose_table(cfg: OrcConfig, skill5, dt: float, n_steps: int):
+    """Pose rows and their Jacobian [n_steps, 8, 5] with respect to the
+    physical skill parameters (depth, angle_deg, push, displace, push_angle_deg)."""
+    sk = np.ascontiguousarray(skill5, dtype=np.float64)
     out = np.zeros((n_steps, 8))
-    jac = np.zeros((n_steps, 8, 3))
-    lib().orc_pose_table(C.byref(cfg), depth, angle_deg, push, dt, n_steps, _p(out), _p(jac))
+    jac = np.zeros((n_steps, 8, 5))
+    lib().orc_pose_table(C.byref(cfg), _p(sk), dt, n_steps, _p(out), _p(jac))
     return out, jac
 
 

@@ -12,11 +12,15 @@
 //      alpha_f from the friction angle;
 //    * the stress passed to P2G is sigma = P' F'^T / det F' with det F' := 1
 //      imposed, as the text after Eq. DP states;
-//    * the digging skill: Eqs. d1 .. delta_d4 and Algorithm 2 (Sec. III-B);
+//    * the digging skill: Eqs. d1 .. delta_d4 and Algorithm 2 (Sec. III-B),
+//      optionally with the unrounded T_1^float, T_4^float in the per-action
+//      displacements of phases 1 and 4 (the ablation variant of Sec. III-B);
+//    * the particle-level collision of Algorithm 1 line 12 (optional);
 //    * the height-map observation and loss (Eq. hm, Sec. III-A "Goal").
-//  Gradients are exact forward-mode tangents (Dual<7>) of all of the above with
+//  Gradients are exact forward-mode tangents (Dual<9>) of all of the above with
 //  respect to (E, nu, phi_f[deg], rho, insert depth, rotate angle[deg], push
-//  distance); the rounded phase lengths T_i carry no tangent (Sec. III-B).
+//  distance, displacement d1, push angle phi3[deg]); the rounded phase lengths
+//  T_i carry no tangent (Sec. III-B).
 //
 //  Nothing in the product may include, link or call this file.  It shares no
 //  source with the GPU path.  Readings of points the paper leaves open (grid,
@@ -48,7 +52,7 @@ extern "C" {
 // Field order must match oracle/__init__.py.
 typedef struct orc_config {
   int32_t dim, n_grid, bound, n_sub;
-  int32_t shovel, hm_res, region_sign, pad0;
+  int32_t shovel, hm_res, region_sign, skill_unrounded;
   double dt, gravity, ppc;
   double half_w, half_n, half_p;   // shovel half extents along (width, normal, pointing)
   double skin, mu_b;               // contact skin and Coulomb coefficient
@@ -57,6 +61,7 @@ typedef struct orc_config {
   double hm_origin[2], hm_size, hm_offset;
   double region_depth, m_target, m_ref, w_mass, w_hm;
   double cohesion;
+  int32_t particle_contact, pad1;  // Algorithm 1 line 12 on (1) or off (0)
 } orc_config;
 }
 
@@ -77,19 +82,27 @@ template <class S> static void set_identity(S A[3][3]) {
 // Actions are 6-vectors [dx, dy, dz, drx, dry, drz] in the paper's z-up frame.
 // Phase bounds are cumulative (the actions of phase i follow those of phase
 // i-1), round() is half away from zero, and the T_i carry no derivative.
+// unrounded: the per-action displacements of phases 1 and 4 divide by the
+// real-valued T_1^float and T_4^float (a tangent flows through them), while
+// the number of actions stays T_1, T_4 (Sec. III-B, the alternative mapping;
+// max() takes its first argument on ties, as the case split of Appendix A).
 // ---------------------------------------------------------------------------
 static int round_half_away(double x) { return (int)std::llround(x); }
 
+template <class S> static S max_first(const S& a, const S& b) { return val(a) >= val(b) ? a : b; }
+
 template <class S>
-static void skill_actions(const S th[5], double v_l, double v_w, double dta, double d4,
+static void skill_actions(const S th[5], double v_l, double v_w, double dta, double d4, bool unrounded,
                           int T[4], std::vector<std::array<S, 6>>* acts) {
   const S d1 = th[0] * 0.12;                          // Eq. d1
   const S phi1 = th[1] * (kPi / 3.0);
-  const double Tf_d1 = std::fabs(val(d1) / (v_l * dta));   // Eq. Tf1
-  const double Tf_phi1 = std::fabs(val(phi1) / (v_w * dta));
-  T[0] = round_half_away(std::max(Tf_d1, Tf_phi1));   // Eq. Ti1
-  const S dx1 = T[0] > 0 ? d1 / double(T[0]) : S(0.0);  // Eq. delta_d1
-  const S drx1 = T[0] > 0 ? phi1 / double(T[0]) : S(0.0);
+  const S Tf_d1 = fabs(d1) / (v_l * dta);             // Eq. Tf1
+  const S Tf_phi1 = fabs(phi1) / (v_w * dta);
+  const S Tf1 = max_first(Tf_d1, Tf_phi1);
+  T[0] = round_half_away(val(Tf1));                   // Eq. Ti1
+  const S div1 = unrounded ? Tf1 : S(double(T[0]));
+  const S dx1 = T[0] > 0 ? d1 / div1 : S(0.0);        // Eq. delta_d1
+  const S drx1 = T[0] > 0 ? phi1 / div1 : S(0.0);
 
   const S d2 = (th[2] + 1.0) * 0.03;                  // Eq. d2
   const S phi2 = phi1 + kPi / 2.0;
@@ -103,10 +116,12 @@ static void skill_actions(const S th[5], double v_l, double v_w, double dta, dou
   const S dx3 = T[2] > 0 ? d3 * cos(phi3) / double(T[2]) : S(0.0);    // Eq. delta_d3
   const S dz3 = T[2] > 0 ? d3 * sin(phi3) / double(T[2]) : S(0.0);
 
-  const double Tf_d4 = d4 / (v_l * dta);              // Eq. Tf4
-  T[3] = round_half_away(std::max(Tf_phi1, Tf_d4));   // Eq. Ti4
-  const S drx4 = T[3] > 0 ? -phi1 / double(T[3]) : S(0.0);             // Eq. delta_d4
-  const S dz4 = T[3] > 0 ? S(d4 / double(T[3])) : S(0.0);
+  const S Tf_d4 = S(d4 / (v_l * dta));                // Eq. Tf4
+  const S Tf4 = max_first(Tf_phi1, Tf_d4);
+  T[3] = round_half_away(val(Tf4));                   // Eq. Ti4
+  const S div4 = unrounded ? Tf4 : S(double(T[3]));
+  const S drx4 = T[3] > 0 ? -phi1 / div4 : S(0.0);    // Eq. delta_d4
+  const S dz4 = T[3] > 0 ? d4 / div4 : S(0.0);
 
   acts->clear();
   const int total = T[0] + T[1] + T[2] + T[3];
@@ -121,15 +136,16 @@ static void skill_actions(const S th[5], double v_l, double v_w, double dta, dou
   }
 }
 
-// Physical skill parameters (insert depth [m], rotate angle [deg], push [m])
-// to the paper's normalised theta, with displace = 0 and push_angle = 0 fixed.
+// Physical skill parameters (insert depth d2 [m], rotate angle phi1 [deg],
+// push distance d3 [m], displacement d1 [m], push angle phi3 [deg]) to the
+// paper's normalised theta, inverting Eqs. d1, d2 and d3.
 template <class S>
-static void theta_from_physical(const S& depth, const S& angle_deg, const S& push, S th[5]) {
-  th[0] = S(0.0);
-  th[1] = angle_deg * (kPi / 180.0) / (kPi / 3.0);
-  th[2] = depth / 0.03 - 1.0;
-  th[3] = (push - 0.04) / 0.1 - 1.0;
-  th[4] = S(0.0);
+static void theta_from_physical(const S sk[5], S th[5]) {
+  th[0] = sk[3] / 0.12;
+  th[1] = sk[1] * (kPi / 180.0) / (kPi / 3.0);
+  th[2] = sk[0] / 0.03 - 1.0;
+  th[3] = (sk[2] - 0.04) / 0.1 - 1.0;
+  th[4] = sk[4] * (kPi / 180.0) / (kPi / 3.0) - 3.0;
 }
 
 // Agent pose per sub-step (Sec. III-A "Actions"; Algorithm 1 line 7).  Build
@@ -140,13 +156,12 @@ static void theta_from_physical(const S& depth, const S& angle_deg, const S& pus
 template <class S> struct Pose { S tip[3]; S psi; S vel[3]; S omega; };
 
 template <class S>
-static void pose_table(const orc_config& c, const S& depth, const S& angle_deg, const S& push,
-                       double dt, int n_steps, std::vector<Pose<S>>* out) {
+static void pose_table(const orc_config& c, const S sk[5], double dt, int n_steps, std::vector<Pose<S>>* out) {
   S th[5];
-  theta_from_physical(depth, angle_deg, push, th);
+  theta_from_physical(sk, th);
   int T[4];
   std::vector<std::array<S, 6>> acts;
-  skill_actions(th, c.v_l, c.v_w, c.n_sub * dt, c.d_lift, T, &acts);
+  skill_actions(th, c.v_l, c.v_w, c.n_sub * dt, c.d_lift, c.skill_unrounded != 0, T, &acts);
   Pose<S> cur;
   for (int k = 0; k < 3; ++k) cur.tip[k] = S(c.tip0[k]);
   cur.psi = S(0.0);
@@ -633,8 +648,35 @@ struct Sim {
     }
   }
 
-  // Lines 10-13: G2P (APIC velocity and affine matrix), advection.
-  bool g2p() {
+  // Line 12: the collision of line 9 applied to a particle's velocity at its
+  // position x_p (before advection): the shovel's Coulomb contact when x_p is
+  // within the contact skin, then the sticky container (zero velocity) when
+  // x_p lies in the wall layers (closer than bound cells to a face).
+  void particle_collision(int p, int step, S vn[3]) {
+    if (c.shovel && d == 3) {
+      const Frame<S> fr = shovel_frame(c, poses[step].tip, poses[step].psi);
+      S xp[3] = {x[p * 3 + 0], x[p * 3 + 1], x[p * 3 + 2]}, nr[3];
+      const S phi = box_sdf(c, fr, xp, nr);
+      if (val(phi) < c.skin) {
+        const Pose<S>& P = poses[step];
+        S vs[3];
+        vs[0] = P.vel[0] + P.omega * (xp[1] - P.tip[1]);
+        vs[1] = P.vel[1] - P.omega * (xp[0] - P.tip[0]);
+        vs[2] = P.vel[2];
+        coulomb(vs, nr, c.mu_b, vn);
+      }
+    }
+    bool wall = false;
+    for (int a = 0; a < d; ++a) {
+      const double xa = val(x[p * 3 + a]);
+      if (xa < c.bound * dx || xa >= (n - c.bound) * dx) wall = true;
+    }
+    if (wall) for (int a = 0; a < 3; ++a) vn[a] = S(0.0);
+  }
+
+  // Lines 10-13: G2P (APIC velocity and affine matrix), particle collision
+  // (when enabled), advection.
+  bool g2p(int step) {
     const double Dinv = 4.0 * inv_dx * inv_dx;
     for (int p = 0; p < N; ++p) {
       int base[3] = {0, 0, 0};
@@ -655,6 +697,7 @@ struct Sim {
           for (int b = 0; b < d; ++b) Cn[a][b] += (Dinv * wt) * gv[gi * 3 + a] * r[b];
         }
       }
+      if (c.particle_contact) particle_collision(p, step, vn);
       for (int a = 0; a < d; ++a) {
         v[p * 3 + a] = vn[a];
         x[p * 3 + a] += dt * vn[a];
@@ -667,7 +710,7 @@ struct Sim {
   bool substep(int step) {
     if (!p2g()) return false;
     grid_update(step);
-    return g2p();
+    return g2p(step);
   }
 
   // ------------------------------------------------------------------------
@@ -742,7 +785,7 @@ struct Sim {
 
 template <class S> static S param(const double* p, int k, bool dual);
 template <> double param<double>(const double* p, int k, bool) { return p[k]; }
-template <> Dual<7> param<Dual<7>>(const double* p, int k, bool) { return Dual<7>::var(p[k], k); }
+template <> Dual<9> param<Dual<9>>(const double* p, int k, bool) { return Dual<9>::var(p[k], k); }
 
 static int validate(const orc_config* c, const double* p) {
   if (c->dim != 2 && c->dim != 3) return ORC_EINVAL;
@@ -752,7 +795,7 @@ static int validate(const orc_config* c, const double* p) {
 }
 
 // Runs sub-steps [step0, step0 + n_steps) from a packed state and writes back
-// the final state; optional loss and 7 gradients.
+// the final state; optional loss and 9 gradients (the parameter order of p).
 template <class S>
 static int rollout(const orc_config* c, const double* p, int N, const double* state_in, int step0,
                    int n_steps, double* state_out, const double* target, double* loss_out,
@@ -761,9 +804,11 @@ static int rollout(const orc_config* c, const double* p, int N, const double* st
   Sim<S> sim(*c, N);
   sim.set_material(param<S>(p, 0, dual), param<S>(p, 1, dual), param<S>(p, 2, dual), param<S>(p, 3, dual));
   const int total = step0 + n_steps;
-  if (c->shovel && c->dim == 3)
-    pose_table(*c, param<S>(p, 4, dual), param<S>(p, 5, dual), param<S>(p, 6, dual), c->dt,
-               std::max(total, 1), &sim.poses);
+  if (c->shovel && c->dim == 3) {
+    const S sk[5] = {param<S>(p, 4, dual), param<S>(p, 5, dual), param<S>(p, 6, dual), param<S>(p, 7, dual),
+                     param<S>(p, 8, dual)};
+    pose_table(*c, sk, c->dt, std::max(total, 1), &sim.poses);
+  }
   const int d = c->dim, sd = 2 * d + 2 * d * d;
   for (int q = 0; q < N; ++q) {
     const double* s = state_in + (size_t)q * sd;
@@ -785,7 +830,7 @@ static int rollout(const orc_config* c, const double* p, int N, const double* st
       sim.grid_update(st);
       for (int gi = 0; gi < sim.nodes; ++gi)
         for (int a = 0; a < 3; ++a) grid_out[gi * 7 + 4 + a] = val(sim.gv[gi * 3 + a]);
-      if (!sim.g2p()) { rc = ORC_EDOMAIN; break; }
+      if (!sim.g2p(st)) { rc = ORC_EDOMAIN; break; }
     } else if (!sim.substep(st)) { rc = ORC_EDOMAIN; break; }
   }
   if (stats) for (int k = 0; k < 8; ++k) stats[k] = sim.stats[k];
@@ -804,7 +849,7 @@ static int rollout(const orc_config* c, const double* p, int N, const double* st
     const S L = sim.loss(target, total - 1, &H);
     if (loss_out) *loss_out = val(L);
     if (hm_out) for (size_t i = 0; i < H.size(); ++i) hm_out[i] = val(H[i]);
-    if (grad_out) for (int k = 0; k < 7; ++k) grad_out[k] = gradient_of(L, k);
+    if (grad_out) for (int k = 0; k < 9; ++k) grad_out[k] = gradient_of(L, k);
   }
   return ORC_OK;
 }
@@ -822,18 +867,18 @@ int orc_rollout(const orc_config* c, const double* p, int N, const double* state
                 double* state_out, const double* target, double* loss_out, double* grad_out,
                 double* hm_out, int64_t* stats, double* grid_out) {
   if (validate(c, p) != ORC_OK || N < 0 || n_steps < 0 || step0 < 0) return ORC_EINVAL;
-  if (grad_out) return rollout<Dual<7>>(c, p, N, state_in, step0, n_steps, state_out, target, loss_out, grad_out, hm_out, stats, grid_out);
+  if (grad_out) return rollout<Dual<9>>(c, p, N, state_in, step0, n_steps, state_out, target, loss_out, grad_out, hm_out, stats, grid_out);
   return rollout<double>(c, p, N, state_in, step0, n_steps, state_out, target, loss_out, nullptr, hm_out, stats, grid_out);
 }
 
 // Skill actions for the paper's theta; jac (optional) = d action / d theta,
 // [T][6][5].  Returns the number of actions, or -1 if more than max_T.
-int orc_skill_actions(const double* theta, double v_l, double v_w, double dta, double d4, int max_T,
-                      int* T_out, double* actions, double* jac) {
+int orc_skill_actions(const double* theta, double v_l, double v_w, double dta, double d4, int unrounded,
+                      int max_T, int* T_out, double* actions, double* jac) {
   Dual<5> th[5];
   for (int k = 0; k < 5; ++k) th[k] = Dual<5>::var(theta[k], k);
   std::vector<std::array<Dual<5>, 6>> acts;
-  skill_actions(th, v_l, v_w, dta, d4, T_out, &acts);
+  skill_actions(th, v_l, v_w, dta, d4, unrounded != 0, T_out, &acts);
   if ((int)acts.size() > max_T) return -1;
   for (size_t t = 0; t < acts.size(); ++t)
     for (int i = 0; i < 6; ++i) {
@@ -843,17 +888,19 @@ int orc_skill_actions(const double* theta, double v_l, double v_w, double dta, d
   return (int)acts.size();
 }
 
-// Pose table [n_steps][8] = (tip xyz, psi, vel xyz, omega); jac [n_steps][8][3]
-// with respect to (depth, angle_deg, push).
-int orc_pose_table(const orc_config* c, double depth, double angle_deg, double push, double dt, int n_steps,
-                   double* out, double* jac) {
-  std::vector<Pose<Dual<3>>> P;
-  pose_table(*c, Dual<3>::var(depth, 0), Dual<3>::var(angle_deg, 1), Dual<3>::var(push, 2), dt, n_steps, &P);
+// Pose table [n_steps][8] = (tip xyz, psi, vel xyz, omega); jac [n_steps][8][5]
+// with respect to the physical skill parameters sk = (depth, angle_deg, push,
+// displace, push_angle_deg).
+int orc_pose_table(const orc_config* c, const double* sk, double dt, int n_steps, double* out, double* jac) {
+  std::vector<Pose<Dual<5>>> P;
+  Dual<5> skd[5];
+  for (int k = 0; k < 5; ++k) skd[k] = Dual<5>::var(sk[k], k);
+  pose_table(*c, skd, dt, n_steps, &P);
   for (int n = 0; n < n_steps; ++n) {
-    const Dual<3> e[8] = {P[n].tip[0], P[n].tip[1], P[n].tip[2], P[n].psi, P[n].vel[0], P[n].vel[1], P[n].vel[2], P[n].omega};
+    const Dual<5> e[8] = {P[n].tip[0], P[n].tip[1], P[n].tip[2], P[n].psi, P[n].vel[0], P[n].vel[1], P[n].vel[2], P[n].omega};
     for (int i = 0; i < 8; ++i) {
       out[n * 8 + i] = e[i].v;
-      if (jac) for (int k = 0; k < 3; ++k) jac[(n * 8 + i) * 3 + k] = e[i].d[k];
+      if (jac) for (int k = 0; k < 5; ++k) jac[(n * 8 + i) * 5 + k] = e[i].d[k];
     }
   }
   return ORC_OK;

@@ -173,7 +173,7 @@ def from_workload(w, max_steps: Optional[int] = None, checkpoint_every: Optional
         w_hm=w.w_hm, region_sign=w.region_sign,
         checkpoint_every=checkpoint_every or w.checkpoint_every or 50,
         max_steps=max_steps or w.steps, sort_every=sort_every)
-    p = w.params7
+    p = w.params
     inst = make_instance(w.n_particles, E=p[0], nu=p[1], phi_deg=p[2], rho=p[3], cohesion=w.material.cohesion,
                          depth=p[4], angle_deg=p[5], push=p[6], dt=w.dt, tip0=w.tip0)
     return cfg, inst

@@ -32,7 +32,7 @@ def test_optimiser_matches_an_oracle_driven_reference(ddm, orc):
     steps = 60
     free = ["E", "phi_deg", "depth", "angle_deg"]
     step = {"E": 2e4, "phi_deg": 2.0, **O.skill_steps()}
-    theta0 = w.params7.copy()
+    theta0 = w.params.copy()
     ev = O.GpuEvaluator(ddm, w, x0, tg, steps, checkpoint_every=16, precision="f64")
     spec = O.OptimSpec(free=free, step=step, lo={"E": 1e4}, hi={"phi_deg": 60.0})
     st = O.optimise(theta0, spec, ev.grad, ev.losses, 2)
@@ -77,7 +77,7 @@ def test_batched_candidates_equal_single_runs(ddm):
     rng = np.random.default_rng(3)
     thetas = []
     for k in range(7):                      # two launches, the second padded
-        th = w.params7.copy()
+        th = w.params.copy()
         th[0] *= 10 ** rng.uniform(-0.5, 0.5)
         th[2] += rng.uniform(-8, 8)
         th[4] *= rng.uniform(0.6, 1.4)

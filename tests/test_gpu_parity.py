@@ -60,7 +60,7 @@ def run_gpu(ddm, w, steps, *, record=False, target=None, K=None, precision=None)
 
 
 def run_oracle(orc, w, steps, target=None, grad=False):
-    return orc.rollout(orc.config(w), w.params7, orc.initial_state(W.bed_positions(w)), steps, target=target,
+    return orc.rollout(orc.config(w), w.params, orc.initial_state(W.bed_positions(w)), steps, target=target,
                        grad=grad)
 
 
@@ -97,7 +97,7 @@ def test_single_step_grid_f64(ddm, orc):
     # shovel engaged: start the comparison at sub-step 0 (rotation about the tip in the bed)
     g = run_gpu(ddm, w, 5)
     grid = g["sim"].get_grid()[0].cpu().numpy()
-    r = orc.rollout(orc.config(w), w.params7, orc.initial_state(W.bed_positions(w)), 5, want_grid=True)
+    r = orc.rollout(orc.config(w), w.params, orc.initial_state(W.bed_positions(w)), 5, want_grid=True)
     ref = r["grid"]
     np.testing.assert_allclose(grid[:, 0], ref[:, 0], rtol=1e-12, atol=1e-15)
     np.testing.assert_allclose(grid[:, 1:4], ref[:, 1:4], rtol=1e-10, atol=1e-12 * np.abs(ref[:, 1:4]).max())
@@ -381,7 +381,7 @@ def test_drift_beyond_windows_f64(ddm, orc):
     got = sim.packed_state(0)
     s0 = orc.initial_state(x0)
     s0[:, 3:6] = vel
-    r = orc.rollout(orc.config(w), w.params7, s0, steps, target=tgt, grad=True)
+    r = orc.rollout(orc.config(w), w.params, s0, steps, target=tgt, grad=True)
     # the bed moved by more than one cell (dx = 1/16) along y
     assert got[:, 1].mean() - x0[:, 1].mean() > 1.5 / 16
     e = field_errors(got, r["state"], 3)

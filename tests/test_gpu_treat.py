@@ -185,7 +185,7 @@ def test_batched_instances_are_treated_alone(ddm):
     summation order of the reductions."""
     _log("case treat norm batched vs alone f32")
     w = W.dig_3d(steps=STEPS)
-    th = [w.params7.copy(), w.params7.copy()]
+    th = [w.params.copy(), w.params.copy()]
     th[1][0] *= 1.7
     th[1][5] += 6.0
     _, bsim, x0b, tgb = _sim(ddm, "f32", th)
@@ -231,7 +231,7 @@ def test_optimiser_evaluator_applies_treatment(ddm):
     w = W.dig_3d(steps=STEPS)
     x0, tg = W.bed_positions(w), W.target_heightmap(w)
     plain = O.GpuEvaluator(ddm, w, x0, tg, STEPS, batch=2, checkpoint_every=16, precision="f32")
-    _, g0 = plain.grad(w.params7)
+    _, g0 = plain.grad(w.params)
     _, sim, xs, tgs = _sim(ddm, "f32")
     sim.set_grad_treatment("none", record_steps=STEPS)
     _grad(sim, xs, tgs)
@@ -240,6 +240,6 @@ def test_optimiser_evaluator_applies_treatment(ddm):
     gs = _grad(sim, xs, tgs)[0]
     ev = O.GpuEvaluator(ddm, w, x0, tg, STEPS, batch=2, checkpoint_every=16, precision="f32",
                         treatment={"mode": "clip", "clip": c})
-    _, g1 = ev.grad(w.params7)
+    _, g1 = ev.grad(w.params)
     _same(g1, gs, "f32", "evaluator with clip")
     assert not np.allclose(g1, g0, rtol=1e-3)

@@ -80,7 +80,7 @@ def test_skill_phase_lengths_by_hand(orc):
 def test_pose_table_follows_actions(orc):
     w = W.dig_3d()
     cfg = orc.config(w)
-    P, J = orc.pose_table(cfg, 0.05, 30.0, 0.15, w.dt, 500)
+    P, J = orc.pose_table(cfg, [0.05, 30.0, 0.15, 0.0, 180.0], w.dt, 500)
     T, acts, _ = orc.skill_actions([0.0, 0.5, 2.0 / 3.0, 0.1, 0.0], dta=10 * w.dt)
     # After all 49 actions the tip moved by the summed displacement
     # (paper x, y, z -> build x, z, y) and psi returned to 0.
@@ -95,6 +95,125 @@ def test_pose_table_follows_actions(orc):
     np.testing.assert_allclose(d_ins, 0.05 * np.array([-math.sin(math.pi / 6), -math.cos(math.pi / 6), 0]), atol=1e-14)
     # velocity * dt equals the per-sub-step displacement
     np.testing.assert_allclose(P[1:490, :3] - P[:489, :3], P[1:490, 4:7] * w.dt, atol=1e-15)
+
+
+def _phase_sums(jac, T):
+    """Sums of d a / d theta over each phase's actions and all entries: [4, 5]."""
+    b = np.cumsum([0] + list(T))
+    return np.stack([jac[b[i]:b[i + 1]].sum(axis=(0, 1)) for i in range(4)])
+
+
+def _fd_phase_sums(orc, theta, T, k, unrounded, h=1e-6, **kw):
+    tp, tm = list(theta), list(theta)
+    tp[k] += h
+    tm[k] -= h
+    Tp, ap, _ = orc.skill_actions(tp, unrounded=unrounded, **kw)
+    Tm, am, _ = orc.skill_actions(tm, unrounded=unrounded, **kw)
+    assert Tp == T and Tm == T
+    b = np.cumsum([0] + list(T))
+    return np.array([(ap[b[i]:b[i + 1]].sum() - am[b[i]:b[i + 1]].sum()) / (2 * h) for i in range(4)])
+
+
+# Unrounded variant (Sec. III-B): phases 1 and 4 divide by T^float.  The
+# paper's closed forms (Eqs. da-dtheta1-unrounded, da-dtheta2-unrounded and
+# the two phase terms after it), with Delta t the action interval:
+def _paper_unrounded(th, T, v_l, v_w, dta, d4):
+    td, tr = th[0], th[1]
+    Tf_d1, Tf_phi1 = abs(0.12 * td) / (v_l * dta), abs(tr * math.pi / 3) / (v_w * dta)
+    Tf_lift = d4 / (v_l * dta)
+    out = {}
+    # d a[0:T1] / d theta_displace
+    if Tf_d1 >= Tf_phi1 > 0 and td > 0:
+        out["p1_displace"] = T[0] * (-math.pi * tr * v_l * dta / (0.36 * td ** 2))
+    elif Tf_d1 >= Tf_phi1 > 0 and td < 0:
+        out["p1_displace"] = T[0] * (2 * v_l * dta / td + math.pi * tr * v_l * dta / (0.36 * td ** 2))
+    elif 0 < Tf_d1 < Tf_phi1:
+        out["p1_displace"] = T[0] * 0.12 * v_w * dta / (abs(tr) * math.pi / 3)
+    # d a[0:T1] / d theta_rotate
+    if Tf_phi1 > Tf_d1 > 0 and tr > 0:
+        out["p1_rotate"] = T[0] * (-0.36 * td * v_w * dta / (tr ** 2 * math.pi))
+    elif Tf_phi1 > Tf_d1 > 0 and tr < 0:
+        out["p1_rotate"] = T[0] * (2 * v_w * dta / tr + 0.36 * td * v_w * dta / (tr ** 2 * math.pi))
+    elif 0 < Tf_phi1 <= Tf_d1:
+        out["p1_rotate"] = T[0] * (math.pi / 3) * v_l * dta / (abs(td) * 0.12)
+    # d a[T1+T2+T3:] / d theta_rotate
+    if Tf_phi1 >= Tf_lift > 0 and tr > 0:
+        out["p4_rotate"] = T[3] * (-3 * d4 * v_w * dta / (tr ** 2 * math.pi))
+    elif Tf_phi1 >= Tf_lift > 0 and tr < 0:
+        out["p4_rotate"] = T[3] * (-2 * v_w * dta / tr + 3 * d4 * v_w * dta / (tr ** 2 * math.pi))
+    elif 0 < Tf_phi1 < Tf_lift:
+        out["p4_rotate"] = T[3] * (-math.pi * v_l * dta / (3 * d4))
+    # d a[T1:T1+T2] / d theta_rotate (T2 stays rounded)
+    phi1 = tr * math.pi / 3
+    out["p2_rotate"] = -(th[2] + 1) * 0.03 * math.pi / 3 * (math.sin(phi1 + math.pi / 2) + math.cos(phi1 + math.pi / 2))
+    return out
+
+
+@pytest.mark.parametrize("theta", [
+    [0.6, 0.2, 0.3, -0.2, 0.1],      # phase 1 set by the displacement, theta > 0
+    [0.1, 0.7, 0.8, 0.4, -0.3],      # phase 1 set by the rotation, theta > 0; phase 4 by the rotation
+    [0.5, 0.05, 0.1, 0.0, 0.2],      # phase 4 set by the lift
+    [-0.6, 0.2, 0.3, -0.2, 0.1],     # negative displacement
+    [0.1, -0.7, 0.8, 0.4, -0.3],     # negative rotation
+])
+def test_unrounded_skill_jacobian(orc, theta):
+    """Phase sums of the unrounded Jacobian against the paper's closed forms
+    where theta_displace and theta_rotate are positive, and against central
+    differences of the actions in every case.  For a negative theta the
+    paper's expressions carry an extra 2 v dt / theta term; the derivative of
+    the constant per-action step (-v dt) it would come from is zero, so the
+    oracle follows the central differences there."""
+    v_l, v_w, dta, d4 = 3.0, 10.0 * math.pi, 2e-3, 0.01
+    T, acts, jac = orc.skill_actions(theta, v_l=v_l, v_w=v_w, dta=dta, d4=d4, unrounded=True)
+    S = _phase_sums(jac, T)
+    paper = _paper_unrounded(theta, T, v_l, v_w, dta, d4)
+    got = {"p1_displace": S[0, 0], "p1_rotate": S[0, 1], "p4_rotate": S[3, 1], "p2_rotate": S[1, 1]}
+    fd0 = _fd_phase_sums(orc, theta, T, 0, True)
+    fd1 = _fd_phase_sums(orc, theta, T, 1, True)
+    fds = {"p1_displace": fd0[0], "p1_rotate": fd1[0], "p4_rotate": fd1[3], "p2_rotate": fd1[1]}
+    for key, g in got.items():
+        assert abs(g - fds[key]) <= 1e-6 * max(1.0, abs(g)), (key, g, fds[key])
+        neg = (key == "p1_displace" and theta[0] < 0) or (key in ("p1_rotate", "p4_rotate") and theta[1] < 0)
+        if neg and key in paper:
+            th = theta[0] if key == "p1_displace" else theta[1]
+            v = v_l if key == "p1_displace" else v_w
+            extra = 2 * v * dta / th * (T[0] if key != "p4_rotate" else -T[3])
+            assert abs((paper[key] - extra) - g) <= 1e-9 * max(1.0, abs(g)), (key, paper[key], g, extra)
+        elif key in paper:
+            assert abs(paper[key] - g) <= 1e-9 * max(1.0, abs(g)), (key, paper[key], g)
+    # phases 2 and 3 are those of the rounded mapping
+    Tr, ar, jr = orc.skill_actions(theta, v_l=v_l, v_w=v_w, dta=dta, d4=d4)
+    assert Tr == T
+    b = np.cumsum([0] + list(T))
+    np.testing.assert_array_equal(acts[b[1]:b[3]], ar[b[1]:b[3]])
+    np.testing.assert_array_equal(jac[b[1]:b[3]], jr[b[1]:b[3]])
+
+
+def test_unrounded_equals_rounded_at_integer_lengths(orc):
+    """With T^float an integer the two mappings coincide: d1 / (v_l dta) = 4
+    exactly for d1 = 0.024 m at v_l dta = 0.006 m; the rotation is shorter."""
+    th = [0.2, 0.05, 0.3, 0.1, 0.0]
+    T, a, _ = orc.skill_actions(th, unrounded=False)
+    Tu, au, _ = orc.skill_actions(th, unrounded=True)
+    assert T == Tu and T[0] == 4
+    np.testing.assert_allclose(au[:4], a[:4], rtol=1e-15)
+
+
+def test_pose_jacobian_of_new_skill_parameters(orc):
+    """Columns of the pose Jacobian for the displacement and the push angle
+    against central differences of the pose table."""
+    w = W.dig_3d()
+    cfg = orc.config(w)
+    sk = np.array([0.05, 30.0, 0.15, 0.02, 170.0])
+    P, J = orc.pose_table(cfg, sk, w.dt, 500)
+    for k, h in ((3, 1e-6), (4, 1e-4)):
+        sp, sm = sk.copy(), sk.copy()
+        sp[k] += h
+        sm[k] -= h
+        Pp, _ = orc.pose_table(cfg, sp, w.dt, 500)
+        Pm, _ = orc.pose_table(cfg, sm, w.dt, 500)
+        np.testing.assert_allclose(J[:, :, k], (Pp - Pm) / (2 * h), atol=1e-7)
+    assert np.any(J[:, :, 3] != 0) and np.any(J[:, :, 4] != 0)
 
 
 # --------------------------------------------------------------------------

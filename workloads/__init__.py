@@ -71,10 +71,12 @@ class Material:
 
 @dataclass
 class Skill:
-    """Free skill parameters in physical units (Sec. III-B, phases 1-4)."""
+    """Skill parameters in physical units (Sec. III-B, phases 1-4)."""
     depth: float = 0.05       # insertion distance d2 [m]
     angle_deg: float = 30.0   # rotation phi1 [deg]
     push: float = 0.15        # push distance d3 [m]
+    displace: float = 0.0     # phase-1 displacement d1 along x [m] (theta_displace = 0)
+    push_angle_deg: float = 180.0   # push angle phi3 [deg] (theta_push_angle = 0)
 
 
 @dataclass
@@ -94,6 +96,8 @@ class Workload:
     bound: int = 3
     gravity: float = -9.8
     n_sub: int = 10                     # sub-steps per action
+    skill_unrounded: bool = False       # phases 1 and 4 divide by T^float (Sec. III-B)
+    particle_contact: bool = False      # collision of Algorithm 1 line 12
     checkpoint_every: int = 0
     target_seed: Optional[int] = None
     # Shovel and contact (the paper gives an SDF with Coulomb friction; sizes
@@ -148,10 +152,12 @@ class Workload:
         return HM_SIZE if self.dim == 3 else 1.0
 
     @property
-    def params7(self) -> np.ndarray:
-        """(E, nu, phi_deg, rho, depth, angle_deg, push): the differentiable inputs."""
+    def params(self) -> np.ndarray:
+        """(E, nu, phi_deg, rho, depth, angle_deg, push, displace, push_angle_deg):
+        the differentiable inputs."""
         m, s = self.material, self.skill or Skill()
-        return np.array([m.E, m.nu, m.phi_deg, m.rho, s.depth, s.angle_deg, s.push], dtype=np.float64)
+        return np.array([m.E, m.nu, m.phi_deg, m.rho, s.depth, s.angle_deg, s.push, s.displace,
+                         s.push_angle_deg], dtype=np.float64)
 
     @property
     def tip0(self) -> tuple:
