@@ -99,6 +99,13 @@ typedef struct ddm_config {
   int32_t sort_every;       /* R: particles are re-binned (sorted by cell) every R sub-steps, and
                                always after ddm_init_state / ddm_set_state and at every
                                checkpoint of a recorded rollout; 0 = only then */
+  int32_t skill_unrounded;  /* 1: the per-action steps of skill phases 1 and 4 divide by the
+                               real-valued T_1^float, T_4^float (Sec. III-B, the alternative
+                               mapping; the gradient flows through them); 0: by the rounded T_1, T_4 */
+  int32_t particle_contact; /* 1: the collision of Algorithm 1 line 12 after G2P: a particle whose
+                               position is within contact_skin of the blade gets the blade's Coulomb
+                               contact, one in the wall layers (closer than bound cells to a face)
+                               gets zero velocity; 0: grid collision only */
   int32_t pad0;
 } ddm_config;
 
@@ -115,7 +122,13 @@ typedef struct ddm_instance {
   double push;              /* skill: push distance d3 [m] */
   double dt;                /* sub-step [s] (> 0) */
   double tip0[3];           /* initial blade tip [m] */
+  double displace;          /* skill: phase-1 displacement d1 along x [m] (Eq. d1; 0 = theta_displace 0) */
+  double push_angle_deg;    /* skill: push angle phi3 [deg] (Eq. d3; 180 = theta_push_angle 0) */
 } ddm_instance;
+
+/* Differentiable inputs per instance, in the order of every gradient output:
+ * E, nu, phi_deg, rho, depth, angle_deg, push, displace, push_angle_deg. */
+#define DDM_N_PARAMS 9
 
 /* Sizes reported by ddm_workspace_query. */
 typedef struct ddm_sizes {
@@ -140,6 +153,17 @@ typedef struct ddm_device_error {
  * cohesion < 0, dt <= 0, n_particles <= 0, checkpoint_every < 1. */
 ddm_status ddm_validate_config(const ddm_config* cfg, int32_t n_inst, const ddm_instance* inst,
                                char* msg, size_t msg_len);
+
+/* The blade pose of every sub-step for one instance's skill (Sec. III-B,
+ * Eqs. d1 .. delta_d4, Algorithm 2, spread over n_sub sub-steps as Algorithm 1
+ * line 7): pose_out[n_steps][8] = tip xyz, psi, velocity xyz, omega (host
+ * memory, build frame, y up), and, if jac_out is not NULL, its Jacobian
+ * jac_out[n_steps][8][5] with respect to (depth, angle_deg, push, displace,
+ * push_angle_deg).  This is the table the library uploads at ddm_create; host
+ * only, for inspection and tests.  DDM_EINVAL for NULL pointers or
+ * n_steps < 1. */
+ddm_status ddm_skill_pose_table(const ddm_config* cfg, const ddm_instance* inst, int32_t n_steps,
+                                double* pose_out, double* jac_out);
 
 /* Device workspace needed for cfg and these instances (host only). */
 ddm_status ddm_workspace_query(const ddm_config* cfg, int32_t n_inst, const ddm_instance* inst,
@@ -185,9 +209,10 @@ ddm_status ddm_rollout(ddm_ctx* ctx, int32_t n_steps);
 ddm_status ddm_loss(ddm_ctx* ctx, const double* target_hm_dev, double* loss_dev);
 
 /* Reverse pass of the last ddm_rollout + ddm_loss: with dloss_dev[n_inst]
- * (double, device) the upstream gradient, writes grad_dev[n_inst][7] (double,
- * device) = d(sum_i dloss_i * loss_i) / d(E, nu, phi_deg, rho, depth,
- * angle_deg, push).  Recomputes each checkpoint segment forward, then runs the
+ * (double, device) the upstream gradient, writes grad_dev[n_inst][DDM_N_PARAMS]
+ * (double, device) = d(sum_i dloss_i * loss_i) / d(E, nu, phi_deg, rho, depth,
+ * angle_deg, push, displace, push_angle_deg); the skill entries are zero
+ * without a shovel.  Recomputes each checkpoint segment forward, then runs the
  * adjoint of every sub-step in reverse (Eq. po/pa).  DDM_ESTATE without a
  * preceding ddm_rollout and ddm_loss. */
 ddm_status ddm_backward(ddm_ctx* ctx, const double* dloss_dev, double* grad_dev);

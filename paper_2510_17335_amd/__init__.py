@@ -23,7 +23,9 @@ LIB_PATH = os.path.join(_HERE, "libddmpm.so")
 
 DDM_OK, DDM_EINVAL, DDM_ENOMEM, DDM_EDEVICE, DDM_ENAN, DDM_EDOMAIN, DDM_ESTATE = range(7)
 DDM_F32, DDM_F64 = 0, 1
-PARAM_NAMES = ("E", "nu", "phi_deg", "rho", "depth", "angle_deg", "push")
+# Differentiable inputs, in the order of every gradient (DDM_N_PARAMS).
+PARAM_NAMES = ("E", "nu", "phi_deg", "rho", "depth", "angle_deg", "push", "displace", "push_angle_deg")
+N_PARAMS = len(PARAM_NAMES)
 
 
 class DdmConfig(C.Structure):
@@ -35,7 +37,8 @@ class DdmConfig(C.Structure):
         ("v_ang", C.c_double), ("d_lift", C.c_double), ("hm_origin", C.c_double * 2), ("hm_size", C.c_double),
         ("hm_offset", C.c_double), ("region_depth", C.c_double), ("m_target", C.c_double), ("m_ref", C.c_double),
         ("w_mass", C.c_double), ("w_hm", C.c_double), ("checkpoint_every", C.c_int32), ("max_steps", C.c_int32),
-        ("sort_every", C.c_int32), ("pad0", C.c_int32),
+        ("sort_every", C.c_int32), ("skill_unrounded", C.c_int32), ("particle_contact", C.c_int32),
+        ("pad0", C.c_int32),
     ]
 
 
@@ -43,7 +46,8 @@ class DdmInstance(C.Structure):
     _fields_ = [
         ("n_particles", C.c_int64), ("E", C.c_double), ("nu", C.c_double), ("phi_deg", C.c_double),
         ("rho", C.c_double), ("cohesion", C.c_double), ("depth", C.c_double), ("angle_deg", C.c_double),
-        ("push", C.c_double), ("dt", C.c_double), ("tip0", C.c_double * 3),
+        ("push", C.c_double), ("dt", C.c_double), ("tip0", C.c_double * 3), ("displace", C.c_double),
+        ("push_angle_deg", C.c_double),
     ]
 
 
@@ -82,6 +86,7 @@ def lib():
         sig = {
             "ddm_validate_config": (C.c_int, [cfgp, i32, instp, C.c_char_p, C.c_size_t]),
             "ddm_workspace_query": (C.c_int, [cfgp, i32, instp, C.POINTER(DdmSizes)]),
+            "ddm_skill_pose_table": (C.c_int, [cfgp, instp, i32, vp, vp]),
             "ddm_create": (C.c_int, [cfgp, i32, instp, vp, C.c_size_t, vp, C.POINTER(vp)]),
             "ddm_init_state": (C.c_int, [vp, vp]),
             "ddm_set_instances": (C.c_int, [vp, i32, instp]),
@@ -131,7 +136,8 @@ def make_config(dim: int, n_grid: int, precision: str = "f32", *, bound: int = 3
                 hm_origin=(0.2, 0.2), hm_size: float = 0.6, hm_offset: Optional[float] = None,
                 region_depth: float = 0.03, m_target: float = 0.192, m_ref: float = 0.384, w_mass: float = 1.0,
                 w_hm: float = 1.0, region_sign: int = -1, checkpoint_every: int = 50,
-                max_steps: int = 1000, sort_every: int = 8) -> DdmConfig:
+                max_steps: int = 1000, sort_every: int = 8, skill_unrounded: bool = False,
+                particle_contact: bool = False) -> DdmConfig:
     c = DdmConfig()
     c.dim, c.n_grid, c.bound = dim, n_grid, bound
     c.precision = DDM_F64 if precision == "f64" else DDM_F32
@@ -146,15 +152,18 @@ def make_config(dim: int, n_grid: int, precision: str = "f32", *, bound: int = 3
     c.hm_offset = (1.0 / n_grid) / round(ppc ** (1.0 / dim)) if hm_offset is None else hm_offset
     c.region_depth, c.m_target, c.m_ref, c.w_mass, c.w_hm = region_depth, m_target, m_ref, w_mass, w_hm
     c.checkpoint_every, c.max_steps, c.sort_every = checkpoint_every, max_steps, sort_every
+    c.skill_unrounded, c.particle_contact = int(bool(skill_unrounded)), int(bool(particle_contact))
     return c
 
 
 def make_instance(n_particles: int, *, E=3.5e5, nu=0.3, phi_deg=30.0, rho=1600.0, cohesion=0.0, depth=0.05,
-                  angle_deg=30.0, push=0.15, dt=2e-4, tip0=(0.5, 0.34375, 0.5)) -> DdmInstance:
+                  angle_deg=30.0, push=0.15, dt=2e-4, tip0=(0.5, 0.34375, 0.5), displace=0.0,
+                  push_angle_deg=180.0) -> DdmInstance:
     s = DdmInstance()
     s.n_particles = int(n_particles)
     s.E, s.nu, s.phi_deg, s.rho, s.cohesion = E, nu, phi_deg, rho, cohesion
     s.depth, s.angle_deg, s.push, s.dt = depth, angle_deg, push, dt
+    s.displace, s.push_angle_deg = displace, push_angle_deg
     t = list(tip0) + [0.0] * (3 - len(tip0))
     for k in range(3):
         s.tip0[k] = t[k]
@@ -172,11 +181,23 @@ def from_workload(w, max_steps: Optional[int] = None, checkpoint_every: Optional
         hm_offset=w.hm_offset, region_depth=w.region_depth, m_target=w.m_target, m_ref=w.m_ref, w_mass=w.w_mass,
         w_hm=w.w_hm, region_sign=w.region_sign,
         checkpoint_every=checkpoint_every or w.checkpoint_every or 50,
-        max_steps=max_steps or w.steps, sort_every=sort_every)
+        max_steps=max_steps or w.steps, sort_every=sort_every, skill_unrounded=w.skill_unrounded,
+        particle_contact=w.particle_contact)
     p = w.params
     inst = make_instance(w.n_particles, E=p[0], nu=p[1], phi_deg=p[2], rho=p[3], cohesion=w.material.cohesion,
-                         depth=p[4], angle_deg=p[5], push=p[6], dt=w.dt, tip0=w.tip0)
+                         depth=p[4], angle_deg=p[5], push=p[6], dt=w.dt, tip0=w.tip0, displace=p[7],
+                         push_angle_deg=p[8])
     return cfg, inst
+
+
+def skill_pose_table(cfg: DdmConfig, inst: DdmInstance, n_steps: int):
+    """(pose [n_steps, 8], jacobian [n_steps, 8, 5]) of one instance's skill,
+    computed on the host by the library (ddm_skill_pose_table)."""
+    pose = np.zeros((n_steps, 8))
+    jac = np.zeros((n_steps, 8, 5))
+    _check(lib().ddm_skill_pose_table(C.byref(cfg), C.byref(inst), int(n_steps), C.c_void_p(pose.ctypes.data),
+                                      C.c_void_p(jac.ctypes.data)))
+    return pose, jac
 
 
 def validate_config(cfg: DdmConfig, instances: Sequence[DdmInstance]) -> str:
@@ -358,12 +379,12 @@ class Simulator:
         return out
 
     def backward(self, dloss=None):
-        """Gradient [n_inst, 7] of sum(dloss * loss) w.r.t. PARAM_NAMES."""
+        """Gradient [n_inst, N_PARAMS] of sum(dloss * loss) w.r.t. PARAM_NAMES."""
         t = self.torch
         if dloss is None:
             dloss = t.ones(self.n_inst, dtype=t.float64, device=self.device)
         dl = t.as_tensor(dloss, dtype=t.float64).to(self.device).contiguous()
-        grad = t.empty((self.n_inst, 7), dtype=t.float64, device=self.device)
+        grad = t.empty((self.n_inst, N_PARAMS), dtype=t.float64, device=self.device)
         self._inputs_ready()
         _check(lib().ddm_backward(self.ctx, C.c_void_p(dl.data_ptr()), C.c_void_p(grad.data_ptr())))
         self._keep = dl
@@ -376,7 +397,7 @@ class Simulator:
         on the first call and replays it on later calls; the inputs are copied
         into buffers this Simulator keeps, so the graph sees fixed pointers.
         Needs a Simulator created on a non-default stream for graph=True.
-        Returns (loss [n_inst], grad [n_inst, 7]), device tensors that the next
+        Returns (loss [n_inst], grad [n_inst, N_PARAMS]), device tensors that the next
         pass overwrites."""
         t = self.torch
         if not hasattr(self, "_pass_bufs"):
@@ -385,7 +406,7 @@ class Simulator:
                 "tg": t.empty((self.n_inst, self.npix), dtype=t.float64, device=self.device),
                 "dl": t.empty(self.n_inst, dtype=t.float64, device=self.device),
                 "loss": t.empty(self.n_inst, dtype=t.float64, device=self.device),
-                "grad": t.empty((self.n_inst, 7), dtype=t.float64, device=self.device),
+                "grad": t.empty((self.n_inst, N_PARAMS), dtype=t.float64, device=self.device),
             }
         B = self._pass_bufs
         self._inputs_ready()
@@ -476,8 +497,8 @@ def _autograd_function():
 
     class DigLoss(torch.autograd.Function):
         """loss[n_inst] = rollout + loss of the digging simulation; gradients with
-        respect to params[n_inst, 7] = (E, nu, phi_deg, rho, depth, angle_deg,
-        push) come from the library's reverse pass (checkpointed recompute)."""
+        respect to params[n_inst, N_PARAMS] (PARAM_NAMES order) come from the
+        library's reverse pass (checkpointed recompute)."""
 
         @staticmethod
         def forward(ctx, params, x0, target, cfg, instances, steps):
@@ -486,7 +507,8 @@ def _autograd_function():
             for i, base in enumerate(instances):
                 s = DdmInstance()
                 C.pointer(s)[0] = base
-                s.E, s.nu, s.phi_deg, s.rho, s.depth, s.angle_deg, s.push = (float(v) for v in p[i])
+                (s.E, s.nu, s.phi_deg, s.rho, s.depth, s.angle_deg, s.push, s.displace,
+                 s.push_angle_deg) = (float(v) for v in p[i])
                 insts.append(s)
             sim = Simulator(cfg, insts, device=x0.device if isinstance(x0, torch.Tensor) else "cuda")
             sim.init_state(x0)

@@ -737,11 +737,53 @@ void launch_grid_update(int prec, const KCfg& c, const Bufs& b, int step, const 
 }
 
 // ---------------------------------------------------------------------------
-// G2P (Algorithm 1 lines 10-13): v_p = sum w v_i, C_p = (4/dx^2) sum w v_i r^T,
-// x_p += dt v_p.
+// Particle-level collision (Algorithm 1 line 12): the grid's collision rule
+// applied to a particle's velocity at its position before advection.  A
+// particle in the wall layers (closer than bound cells to a face; the test is
+// exact on the fixed-point position) stops; otherwise, within the contact skin
+// of the blade, the blade's Coulomb contact acts on it.
 // ---------------------------------------------------------------------------
 template <typename T, int D>
-__global__ void __launch_bounds__(kBlock) k_g2p(KCfg c, Bufs b, const void* st_in, void* st_out, const T* __restrict__ post) {
+__device__ __forceinline__ bool in_wall_layers(const KCfg& c, const P<T, D>& st, int64_t p, double xr[3]) {
+  bool wall = false;
+  xr[0] = xr[1] = xr[2] = 0.0;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    xr[a] = Pos<T>::real(st.xr(a, p));
+    wall |= xr[a] < c.bound * c.dx || xr[a] >= (c.n - c.bound) * c.dx;
+  }
+  return wall;
+}
+
+template <typename T, int D>
+__device__ __forceinline__ void particle_collision(const KCfg& c, const Bufs& b, int inst, int step,
+                                                   const P<T, D>& st, int64_t p, T v[3]) {
+  double xr[3];
+  if (in_wall_layers<T, D>(c, st, p, xr)) {
+    v[0] = v[1] = v[2] = T(0);
+    return;
+  }
+  if (D == 3 && c.shovel) {
+    const Blade<T> bl = load_blade<T>(b.poses, inst, c.max_steps, step);
+    const T xp[3] = {T(xr[0]), T(xr[1]), T(xr[2])};
+    const T half[3] = {T(c.half[0]), T(c.half[1]), T(c.half[2])};
+    SDF<T> f;
+    sdf_eval<T>(bl, half, xp, f);
+    if (f.phi < T(c.skin)) {
+      T vs[3];
+      blade_velocity<T>(bl, xp, vs);
+      coulomb_forward<T>(vs, f.n, T(c.mu_b), v);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// G2P (Algorithm 1 lines 10-13): v_p = sum w v_i, C_p = (4/dx^2) sum w v_i r^T,
+// the particle-level collision when enabled, x_p += dt v_p.
+// ---------------------------------------------------------------------------
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock) k_g2p(KCfg c, Bufs b, int step, const void* st_in, void* st_out,
+                                                const T* __restrict__ post) {
   const int inst = b.blk_inst[blockIdx.x];
   const InstDev& I = b.inst[inst];
   const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -786,6 +828,7 @@ __global__ void __launch_bounds__(kBlock) k_g2p(KCfg c, Bufs b, const void* st_i
         Cn[a][D - 1] += wl2 * ul[a];
       }
     }
+  if (c.pcontact) particle_collision<T, D>(c, b, inst, step, si, p, vn);
   const T dt = T(b.inst[inst].dt);
   T chk = T(0);
   bool ok = true;
@@ -802,14 +845,14 @@ __global__ void __launch_bounds__(kBlock) k_g2p(KCfg c, Bufs b, const void* st_i
   if (!isfinite(chk) || !ok) flag_error(b.err, 1u, inst);
 }
 
-void launch_g2p(int prec, const KCfg& c, const Bufs& b, int nblk, const void* st_in, void* st_out,
+void launch_g2p(int prec, const KCfg& c, const Bufs& b, int nblk, int step, const void* st_in, void* st_out,
                 const void* post, hipStream_t s) {
   if (prec == 0) {
-    if (c.dim == 3) hipLaunchKernelGGL((k_g2p<float, 3>), dim3(nblk), dim3(kBlock), 0, s, c, b, st_in, st_out, (const float*)post);
-    else hipLaunchKernelGGL((k_g2p<float, 2>), dim3(nblk), dim3(kBlock), 0, s, c, b, st_in, st_out, (const float*)post);
+    if (c.dim == 3) hipLaunchKernelGGL((k_g2p<float, 3>), dim3(nblk), dim3(kBlock), 0, s, c, b, step, st_in, st_out, (const float*)post);
+    else hipLaunchKernelGGL((k_g2p<float, 2>), dim3(nblk), dim3(kBlock), 0, s, c, b, step, st_in, st_out, (const float*)post);
   } else {
-    if (c.dim == 3) hipLaunchKernelGGL((k_g2p<double, 3>), dim3(nblk), dim3(kBlock), 0, s, c, b, st_in, st_out, (const double*)post);
-    else hipLaunchKernelGGL((k_g2p<double, 2>), dim3(nblk), dim3(kBlock), 0, s, c, b, st_in, st_out, (const double*)post);
+    if (c.dim == 3) hipLaunchKernelGGL((k_g2p<double, 3>), dim3(nblk), dim3(kBlock), 0, s, c, b, step, st_in, st_out, (const double*)post);
+    else hipLaunchKernelGGL((k_g2p<double, 2>), dim3(nblk), dim3(kBlock), 0, s, c, b, step, st_in, st_out, (const double*)post);
   }
 }
 
@@ -1297,6 +1340,99 @@ void launch_g2p_adj(int prec, const KCfg& c, const Bufs& b, const TileList& tl, 
 }
 
 // ---------------------------------------------------------------------------
+// Adjoint of the particle-level collision.  With vb = v'bar + dt x'bar the
+// adjoint of the collided velocity: a particle in the wall layers passes no
+// adjoint to the G2P velocity; one in contact with the blade gets ub from the
+// Coulomb adjoint at the G2P velocity u (re-gathered from the grid), and,
+// since the contact sees x_p only through x_p - tip, the position adjoint
+// minus the tip adjoint of the normal and of the blade velocity.  The x and v
+// rows of adj_next are rewritten so that the G2P adjoint reads
+// v bar + dt x bar = ub and x bar with the contact term included.
+// ---------------------------------------------------------------------------
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock) k_pcontact_adj(KCfg c, Bufs b, int step, const void* stv,
+                                                         const T* __restrict__ post, void* adj_next,
+                                                         double* pose_bar) {
+  const int inst = b.blk_inst[blockIdx.x];
+  const InstDev& I = b.inst[inst];
+  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  double pb[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  bool any = false;
+  if (p - I.off < I.n) {
+    const P<T, D> st = pv<T, D>(stv, c.ntot);
+    const Adj<T, D> an = av<T, D>(adj_next, c.ntot);
+    const T dt = T(I.dt);
+    double xr[3];
+    if (in_wall_layers<T, D>(c, st, p, xr)) {
+#pragma unroll
+      for (int a = 0; a < D; ++a) an.v(a, p) = -dt * an.x(a, p);
+    } else if (D == 3 && c.shovel) {
+      const Blade<T> bl = load_blade<T>(b.poses, inst, c.max_steps, step);
+      const T xp[3] = {T(xr[0]), T(xr[1]), T(xr[2])};
+      const T half[3] = {T(c.half[0]), T(c.half[1]), T(c.half[2])};
+      SDF<T> f;
+      sdf_eval<T>(bl, half, xp, f);
+      Stencil<T, D> S;
+      if (f.phi < T(c.skin) && make_stencil<T, D>(st, p, c, S)) {
+        const T* g = post + I.goff * kNodeVals;
+        T u[3] = {T(0), T(0), T(0)};
+#pragma unroll 1
+        for (int o0 = 0; o0 < 3; ++o0)
+#pragma unroll 1
+          for (int o1 = 0; o1 < 3; ++o1)
+#pragma unroll
+            for (int o2 = 0; o2 < 3; ++o2) {
+              const T w = S.w[0][o0] * S.w[1][o1] * S.w[2][o2];
+              const Node4<T> nd = ld_node(g + node_of<D>(S.base, o0, o1, o2, c.n) * kNodeVals);
+#pragma unroll
+              for (int a = 0; a < 3; ++a) u[a] += w * nd.v[a];
+            }
+        T vb[3], vs[3], ub[3], vsb[3], nb[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) vb[a] = an.v(a, p) + dt * an.x(a, p);
+        blade_velocity<T>(bl, xp, vs);
+        coulomb_backward<T>(vs, f.n, T(c.mu_b), u, vb, ub, vsb, nb);
+        // v_s = v_lin + (omega (y - tip_y), -omega (x - tip_x), 0)
+        T tipb[3] = {T(0), T(0), T(0)}, psib = T(0);
+        const T omb = vsb[0] * (xp[1] - bl.tip[1]) - vsb[1] * (xp[0] - bl.tip[0]);
+        tipb[1] -= bl.omega * vsb[0];
+        tipb[0] += bl.omega * vsb[1];
+        sdf_normal_backward<T>(bl, half, xp, f, nb, tipb, psib);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const T xb = an.x(a, p) - tipb[a];
+          an.x(a, p) = xb;
+          an.v(a, p) = ub[a] - dt * xb;
+        }
+        pb[0] = tipb[0]; pb[1] = tipb[1]; pb[2] = tipb[2]; pb[3] = psib;
+        pb[4] = vsb[0]; pb[5] = vsb[1]; pb[6] = vsb[2]; pb[7] = omb;
+        any = true;
+      }
+    }
+  }
+  // a 256-slot block belongs to one instance
+  if (D == 3 && c.shovel && __any(any)) {
+    double* dst = pose_bar + ((int64_t)inst * c.max_steps + step) * 8;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const double sum = wave_sum(pb[k]);
+      if ((threadIdx.x & 63) == 0 && sum != 0.0) atomicAdd(dst + k, sum);
+    }
+  }
+}
+
+void launch_pcontact_adj(int prec, const KCfg& c, const Bufs& b, int nblk, int step, const void* st,
+                         const void* post, void* adj_next, double* pose_bar, hipStream_t s) {
+  if (prec == 0) {
+    if (c.dim == 3) hipLaunchKernelGGL((k_pcontact_adj<float, 3>), dim3(nblk), dim3(kBlock), 0, s, c, b, step, st, (const float*)post, adj_next, pose_bar);
+    else hipLaunchKernelGGL((k_pcontact_adj<float, 2>), dim3(nblk), dim3(kBlock), 0, s, c, b, step, st, (const float*)post, adj_next, pose_bar);
+  } else {
+    if (c.dim == 3) hipLaunchKernelGGL((k_pcontact_adj<double, 3>), dim3(nblk), dim3(kBlock), 0, s, c, b, step, st, (const double*)post, adj_next, pose_bar);
+    else hipLaunchKernelGGL((k_pcontact_adj<double, 2>), dim3(nblk), dim3(kBlock), 0, s, c, b, step, st, (const double*)post, adj_next, pose_bar);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Adjoint of the grid update: walls cut the gradient, contact is replayed with
 // the same branch, u = mv/m + dt g gives mv bar = u bar / m and
 // m bar = -u bar . (mv/m) / m.  Pose adjoints (tip, psi, v_lin, omega) of the
@@ -1620,20 +1756,22 @@ void launch_p2g_adj(int prec, const KCfg& c, const Bufs& b, int nblk, const void
 // ---------------------------------------------------------------------------
 // Final gradient per instance: chain (mu, lambda, alpha, k_c, rho) adjoints to
 // (E, nu, phi_deg, rho) and the per-sub-step pose adjoints through the pose
-// Jacobian d pose / d (depth, angle_deg, push); scale by dloss.
+// Jacobian d pose / d (depth, angle_deg, push, displace, push_angle_deg);
+// scale by dloss.
 // ---------------------------------------------------------------------------
 __global__ void k_grad_final(KCfg c, const InstDev* inst, const double* pacc, const double* pose_bar,
                              const double* pose_jac, int n_steps, const double* dloss, double* grad) {
+  constexpr int NS = kSkillParams;
   const int i = blockIdx.x;
-  double s[3] = {0.0, 0.0, 0.0};
+  double s[NS] = {0.0, 0.0, 0.0, 0.0, 0.0};
   for (int st = threadIdx.x; st < n_steps; st += blockDim.x) {
     const double* pb = pose_bar + ((int64_t)i * c.max_steps + st) * 8;
-    const double* J = pose_jac + ((int64_t)i * c.max_steps + st) * 24;
+    const double* J = pose_jac + ((int64_t)i * c.max_steps + st) * 8 * NS;
     for (int k = 0; k < 8; ++k)
-      for (int j = 0; j < 3; ++j) s[j] += pb[k] * J[k * 3 + j];
+      for (int j = 0; j < NS; ++j) s[j] += pb[k] * J[k * NS + j];
   }
-  __shared__ double red[kBlock / 64][3];
-  for (int j = 0; j < 3; ++j) {
+  __shared__ double red[kBlock / 64][NS];
+  for (int j = 0; j < NS; ++j) {
     const double v = wave_sum(s[j]);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][j] = v;
   }
@@ -1642,16 +1780,15 @@ __global__ void k_grad_final(KCfg c, const InstDev* inst, const double* pacc, co
     const InstDev& I = inst[i];
     const double* a = pacc + (int64_t)i * 8;
     const double sc = dloss[i];
-    double sk[3] = {0.0, 0.0, 0.0};
+    double sk[NS] = {0.0, 0.0, 0.0, 0.0, 0.0};
     for (int w = 0; w < (int)blockDim.x / 64; ++w)
-      for (int j = 0; j < 3; ++j) sk[j] += red[w][j];
-    grad[i * 7 + 0] = sc * (a[0] * I.dmu_dE + a[1] * I.dlam_dE);
-    grad[i * 7 + 1] = sc * (a[0] * I.dmu_dnu + a[1] * I.dlam_dnu);
-    grad[i * 7 + 2] = sc * (a[2] * I.dal_dphi + a[3] * I.dkc_dphi);
-    grad[i * 7 + 3] = sc * a[4];
-    grad[i * 7 + 4] = sc * sk[0];
-    grad[i * 7 + 5] = sc * sk[1];
-    grad[i * 7 + 6] = sc * sk[2];
+      for (int j = 0; j < NS; ++j) sk[j] += red[w][j];
+    double* gi = grad + (int64_t)i * kParams;
+    gi[0] = sc * (a[0] * I.dmu_dE + a[1] * I.dlam_dE);
+    gi[1] = sc * (a[0] * I.dmu_dnu + a[1] * I.dlam_dnu);
+    gi[2] = sc * (a[2] * I.dal_dphi + a[3] * I.dkc_dphi);
+    gi[3] = sc * a[4];
+    for (int j = 0; j < NS; ++j) gi[4 + j] = sc * sk[j];
   }
 }
 

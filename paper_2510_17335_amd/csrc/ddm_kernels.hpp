@@ -10,6 +10,8 @@ constexpr int kBlock = 256;          // particle kernels: threads per block, and
                                      // padding unit of every instance's particle range
 constexpr int kNodeVals = 4;         // node record: mv[0..2] (or v), m
 constexpr int kPoseVals = 10;        // device pose row of a sub-step
+constexpr int kSkillParams = 5;      // skill parameters of the pose Jacobian (depth, angle, push, displace, push angle)
+constexpr int kParams = 4 + kSkillParams;   // gradient entries per instance
 constexpr int kTile = 4;             // binning tile edge in cells
 constexpr int kWin = kTile + 4;      // LDS window edge in nodes: tile + stencil + 1-cell drift each side
 
@@ -50,6 +52,7 @@ struct DevErr {
 // Configuration passed by value to every kernel.
 struct KCfg {
   int dim, n, nlog2, bound, shovel, hm_res, region_sign, n_inst, max_steps;
+  int pcontact;                      // particle-level collision after G2P (Algorithm 1 line 12)
   int64_t nodes;                     // nodes per instance
   int64_t ntot;                      // padded particle slots (SoA stride)
   double dx, inv_dx, gravity, skin, mu_b, half[3];
@@ -103,7 +106,8 @@ void launch_grid_update(int prec, const KCfg& c, const Bufs& b, int step, const 
 // Active set of a fresh binning: the blocks of the occupied tiles and of their
 // neighbours (a tile's window reaches one block beyond it on each side).
 void launch_active_set(const KCfg& c, const TileList& tl, const ActiveSet& act, hipStream_t s);
-void launch_g2p(int prec, const KCfg& c, const Bufs& b, int nblk, const void* st_in, void* st_out,
+// G2P of sub-step `step`, with the particle-level collision when c.pcontact.
+void launch_g2p(int prec, const KCfg& c, const Bufs& b, int nblk, int step, const void* st_in, void* st_out,
                 const void* grid_post, hipStream_t s);
 void launch_export_state(const KCfg& c, const Bufs& b, int nblk, int rows, int elem_bytes, const void* in, void* out,
                          const uint32_t* pid, hipStream_t s);
@@ -130,6 +134,12 @@ void launch_loss_seed(int prec, const KCfg& c, const Bufs& b, int nblk, const vo
 // Adjoint sub-step pieces (reverse order: g2p_adj, grid_adj, p2g_adj).
 void launch_g2p_adj(int prec, const KCfg& c, const Bufs& b, const TileList& tl, int nwg, const void* st,
                     const void* grid_post, const void* adj_next, void* adj_cur, void* gvb, hipStream_t s);
+// Adjoint of the particle-level collision of sub-step `step` (run before the
+// G2P adjoint when c.pcontact): rewrites the x and v rows of adj_next so that
+// the G2P adjoint sees the adjoint of the velocity before the collision, adds
+// the collision's position adjoint to x, and adds its pose adjoints to pose_bar.
+void launch_pcontact_adj(int prec, const KCfg& c, const Bufs& b, int nblk, int step, const void* st,
+                         const void* grid_post, void* adj_next, double* pose_bar, hipStream_t s);
 // Over the active blocks (list, count) of the sub-step; zeroes gvb where it read it.
 void launch_grid_adj(int prec, const KCfg& c, const Bufs& b, int step, const uint32_t* list, const uint32_t* count,
                      const void* grid_pre, void* gvb, void* gb, double* pose_bar, hipStream_t s);

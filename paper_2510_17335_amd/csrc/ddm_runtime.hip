@@ -100,7 +100,7 @@ Layout make_layout(const ddm_config& c, int n_inst, const ddm_instance* in) {
   L.inst = cv.take(sizeof(ddm::InstDev) * n_inst);
   L.blk_inst = cv.take(sizeof(int) * L.nblk);
   L.poses = cv.take((size_t)n_inst * c.max_steps * ddm::kPoseVals * b);
-  L.pose_jac = cv.take((size_t)n_inst * c.max_steps * 24 * sizeof(double));
+  L.pose_jac = cv.take((size_t)n_inst * c.max_steps * 8 * ddm::kSkillParams * sizeof(double));
   L.err = cv.take(sizeof(ddm::DevErr));
   L.pid = cv.take(sizeof(uint32_t) * ntot);
   L.pid_tmp = cv.take(sizeof(uint32_t) * ntot);
@@ -155,57 +155,86 @@ Layout make_layout(const ddm_config& c, int n_inst, const ddm_instance* in) {
 
 // ---------------------------------------------------------------------------
 // Digging skill (Sec. III-B): phase lengths T_i = round(T^float_i) (half away
-// from zero, no derivative), per-action displacements of the four phases with
-// d1 = 0 and push angle phi3 = pi fixed, and the per-sub-step blade pose: the
-// action is spread evenly over the n_sub sub-steps and applied before the grid
-// collision (Algorithm 1 line 7).  Build frame: paper (x, y, z) -> (x, z, y),
-// rotation about the paper's x axis -> psi.  Jacobian columns: d/d(depth,
-// angle_deg, push).
+// from zero, no derivative), per-action displacements of the four phases, and
+// the per-sub-step blade pose: the action is spread evenly over the n_sub
+// sub-steps and applied before the grid collision (Algorithm 1 line 7).  With
+// skill_unrounded the steps of phases 1 and 4 divide by T^float_1, T^float_4
+// instead (the alternative mapping; its derivative is carried), where max()
+// keeps its first argument on ties.  Build frame: paper (x, y, z) -> (x, z,
+// y), rotation about the paper's x axis -> psi.  Jacobian columns:
+// d/d(depth, angle_deg, push, displace, push_angle_deg).
 // ---------------------------------------------------------------------------
-struct Action { double d[6]; double J[6][3]; };   // paper frame [dx, dy, dz, drx, dry, drz]
+constexpr int kSkill = ddm::kSkillParams;
+struct Action { double d[6]; double J[6][kSkill]; };   // paper frame [dx, dy, dz, drx, dry, drz]
 
 std::vector<Action> skill_actions(const ddm_config& c, const ddm_instance& in) {
   const double dta = c.n_sub * in.dt;
   const double rad = kPi / 180.0;
-  const double phi1 = in.angle_deg * rad, d2 = in.depth, d3 = in.push, d4 = c.d_lift;
-  const double phi3 = kPi;                           // push angle parameter 0 -> (0 + 3) pi / 3
-  const double Tf_phi1 = std::fabs(phi1 / (c.v_ang * dta));
-  const long T1 = std::lround(Tf_phi1);              // d1 = 0, so the rotation sets the length
+  const double phi1 = in.angle_deg * rad, d1 = in.displace, d2 = in.depth, d3 = in.push, d4 = c.d_lift;
+  const double phi3 = in.push_angle_deg * rad;
+  const bool unr = c.skill_unrounded != 0;
+  // T^float with their derivatives in (d1, phi1_deg): |d1| / (v_l dta), |phi1| / (v_w dta)
+  const double Tf_d1 = std::fabs(d1) / (c.v_lin * dta), Tf_phi1 = std::fabs(phi1) / (c.v_ang * dta);
+  const double dTd1 = (d1 >= 0 ? 1.0 : -1.0) / (c.v_lin * dta);            // d Tf_d1 / d d1
+  const double dTphi = (phi1 >= 0 ? 1.0 : -1.0) * rad / (c.v_ang * dta);   // d Tf_phi1 / d angle_deg
+  const bool t1_by_d1 = Tf_d1 >= Tf_phi1;
+  const double Tf1 = t1_by_d1 ? Tf_d1 : Tf_phi1;
+  const double Tf_lift = d4 / (c.v_lin * dta);
+  const bool t4_by_phi = Tf_phi1 >= Tf_lift;
+  const double Tf4 = t4_by_phi ? Tf_phi1 : Tf_lift;
+  const long T1 = std::lround(Tf1);
   const long T2 = std::lround(d2 / (c.v_lin * dta));
   const long T3 = std::lround(std::fabs(d3 / (c.v_lin * dta)));
-  const long T4 = std::lround(std::max(Tf_phi1, d4 / (c.v_lin * dta)));
+  const long T4 = std::lround(Tf4);
   const double phi2 = phi1 + kPi / 2.0;
   std::vector<Action> out;
   auto blank = [] { Action a; std::memset(&a, 0, sizeof(a)); return a; };
+  enum { DEPTH = 0, ANGLE = 1, PUSH = 2, DISP = 3, PANG = 4 };
+  // phase 1: (d1, phi1) / div1, div1 = T1 or Tf1
+  const double div1 = unr ? Tf1 : (double)T1;
+  double ddiv1[kSkill] = {0, 0, 0, 0, 0};
+  if (unr) { if (t1_by_d1) ddiv1[DISP] = dTd1; else ddiv1[ANGLE] = dTphi; }
   for (long t = 0; t < T1; ++t) {
     Action a = blank();
-    a.d[3] = phi1 / T1;
-    a.J[3][1] = rad / T1;
+    a.d[0] = d1 / div1;
+    a.d[3] = phi1 / div1;
+    for (int j = 0; j < kSkill; ++j) {
+      a.J[0][j] = -d1 * ddiv1[j] / (div1 * div1);
+      a.J[3][j] = -phi1 * ddiv1[j] / (div1 * div1);
+    }
+    a.J[0][DISP] += 1.0 / div1;
+    a.J[3][ANGLE] += rad / div1;
     out.push_back(a);
   }
   for (long t = 0; t < T2; ++t) {
     Action a = blank();
     a.d[0] = d2 * std::cos(phi2) / T2;
     a.d[2] = -(d2 * std::sin(phi2)) / T2;
-    a.J[0][0] = std::cos(phi2) / T2;
-    a.J[0][1] = -d2 * std::sin(phi2) * rad / T2;
-    a.J[2][0] = -std::sin(phi2) / T2;
-    a.J[2][1] = -d2 * std::cos(phi2) * rad / T2;
+    a.J[0][DEPTH] = std::cos(phi2) / T2;
+    a.J[0][ANGLE] = -d2 * std::sin(phi2) * rad / T2;
+    a.J[2][DEPTH] = -std::sin(phi2) / T2;
+    a.J[2][ANGLE] = -d2 * std::cos(phi2) * rad / T2;
     out.push_back(a);
   }
   for (long t = 0; t < T3; ++t) {
     Action a = blank();
     a.d[0] = d3 * std::cos(phi3) / T3;
     a.d[2] = d3 * std::sin(phi3) / T3;
-    a.J[0][2] = std::cos(phi3) / T3;
-    a.J[2][2] = std::sin(phi3) / T3;
+    a.J[0][PUSH] = std::cos(phi3) / T3;
+    a.J[2][PUSH] = std::sin(phi3) / T3;
+    a.J[0][PANG] = -d3 * std::sin(phi3) * rad / T3;
+    a.J[2][PANG] = d3 * std::cos(phi3) * rad / T3;
     out.push_back(a);
   }
+  // phase 4: (-phi1, d4) / div4, div4 = T4 or Tf4
+  const double div4 = unr ? Tf4 : (double)T4;
+  const double ddiv4_angle = (unr && t4_by_phi) ? dTphi : 0.0;
   for (long t = 0; t < T4; ++t) {
     Action a = blank();
-    a.d[3] = -phi1 / T4;
-    a.d[2] = d4 / T4;
-    a.J[3][1] = -rad / T4;
+    a.d[3] = -phi1 / div4;
+    a.d[2] = d4 / div4;
+    a.J[3][ANGLE] = -rad / div4 + phi1 * ddiv4_angle / (div4 * div4);
+    a.J[2][ANGLE] = -d4 * ddiv4_angle / (div4 * div4);
     out.push_back(a);
   }
   return out;
@@ -215,15 +244,15 @@ std::vector<Action> skill_actions(const ddm_config& c, const ddm_instance& in) {
 void pose_table(const ddm_config& c, const ddm_instance& in, std::vector<double>& pose, std::vector<double>& jac) {
   const std::vector<Action> acts = skill_actions(c, in);
   pose.assign((size_t)c.max_steps * 8, 0.0);
-  jac.assign((size_t)c.max_steps * 24, 0.0);
+  jac.assign((size_t)c.max_steps * 8 * kSkill, 0.0);
   double tip[3] = {in.tip0[0], in.tip0[1], in.tip0[2]}, psi = 0.0;
-  double Jtip[3][3] = {{0}}, Jpsi[3] = {0, 0, 0};
+  double Jtip[3][kSkill] = {{0}}, Jpsi[kSkill] = {0};
   const double inv_n = 1.0 / c.n_sub;
   for (int n = 0; n < c.max_steps; ++n) {
     const size_t t = (size_t)(n / c.n_sub);
     double* row = &pose[(size_t)n * 8];
-    double* J = &jac[(size_t)n * 24];
-    double vel[3] = {0, 0, 0}, om = 0.0, Jvel[3][3] = {{0}}, Jom[3] = {0, 0, 0};
+    double* J = &jac[(size_t)n * 8 * kSkill];
+    double vel[3] = {0, 0, 0}, om = 0.0, Jvel[3][kSkill] = {{0}}, Jom[kSkill] = {0};
     if (t < acts.size()) {
       const Action& a = acts[t];
       const int map[3] = {0, 2, 1};                // build axis k takes paper entry map[k]
@@ -231,7 +260,7 @@ void pose_table(const ddm_config& c, const ddm_instance& in, std::vector<double>
         const double dk = a.d[map[k]] * inv_n;
         tip[k] += dk;
         vel[k] = dk / in.dt;
-        for (int j = 0; j < 3; ++j) {
+        for (int j = 0; j < kSkill; ++j) {
           Jtip[k][j] += a.J[map[k]][j] * inv_n;
           Jvel[k][j] = a.J[map[k]][j] * inv_n / in.dt;
         }
@@ -239,15 +268,15 @@ void pose_table(const ddm_config& c, const ddm_instance& in, std::vector<double>
       const double dpsi = a.d[3] * inv_n;
       psi += dpsi;
       om = dpsi / in.dt;
-      for (int j = 0; j < 3; ++j) { Jpsi[j] += a.J[3][j] * inv_n; Jom[j] = a.J[3][j] * inv_n / in.dt; }
+      for (int j = 0; j < kSkill; ++j) { Jpsi[j] += a.J[3][j] * inv_n; Jom[j] = a.J[3][j] * inv_n / in.dt; }
     }
     for (int k = 0; k < 3; ++k) { row[k] = tip[k]; row[4 + k] = vel[k]; }
     row[3] = psi;
     row[7] = om;
-    for (int j = 0; j < 3; ++j) {
-      for (int k = 0; k < 3; ++k) { J[k * 3 + j] = Jtip[k][j]; J[(4 + k) * 3 + j] = Jvel[k][j]; }
-      J[3 * 3 + j] = Jpsi[j];
-      J[7 * 3 + j] = Jom[j];
+    for (int j = 0; j < kSkill; ++j) {
+      for (int k = 0; k < 3; ++k) { J[k * kSkill + j] = Jtip[k][j]; J[(4 + k) * kSkill + j] = Jvel[k][j]; }
+      J[3 * kSkill + j] = Jpsi[j];
+      J[7 * kSkill + j] = Jom[j];
     }
   }
 }
@@ -470,7 +499,7 @@ ddm_status forward_step(ddm_ctx* x, int64_t step, const ddm::TileList& tl, const
   { Timed t(x, 0); ddm::launch_p2g(x->prec, x->kc, b, tl, x->L.nwg, st_in, st_out, stg, gout, act, tau_out, x->stream); }
   { Timed t(x, 1); ddm::launch_grid_update(x->prec, x->kc, b, (int)step, stg, gout, act, gpre, gpost, list_out,
                                            count_out, x->stream); }
-  { Timed t(x, 2); ddm::launch_g2p(x->prec, x->kc, b, (int)x->L.nblk, st_in, st_out, gpost, x->stream); }
+  { Timed t(x, 2); ddm::launch_g2p(x->prec, x->kc, b, (int)x->L.nblk, (int)step, st_in, st_out, gpost, x->stream); }
   return launch_status();
 }
 
@@ -521,13 +550,14 @@ ddm_status upload_instances(ddm_ctx* x, const ddm_instance* inst) {
     for (int64_t bI = off / ddm::kBlock; bI < (off + np) / ddm::kBlock; ++bI) blk[(size_t)bI] = i;
     off += np;
   }
-  std::vector<double> poses((size_t)n_inst * cfg->max_steps * 8, 0.0), jac((size_t)n_inst * cfg->max_steps * 24, 0.0);
+  const size_t js = (size_t)8 * kSkill;      // pose Jacobian values per sub-step
+  std::vector<double> poses((size_t)n_inst * cfg->max_steps * 8, 0.0), jac((size_t)n_inst * cfg->max_steps * js, 0.0);
   if (cfg->shovel) {
     for (int i = 0; i < n_inst; ++i) {
       std::vector<double> p, j;
       pose_table(*cfg, inst[i], p, j);
       std::copy(p.begin(), p.end(), poses.begin() + (size_t)i * cfg->max_steps * 8);
-      std::copy(j.begin(), j.end(), jac.begin() + (size_t)i * cfg->max_steps * 24);
+      std::copy(j.begin(), j.end(), jac.begin() + (size_t)i * cfg->max_steps * js);
     }
   }
   // device rows: the 8 pose values and sin / cos of the blade angle
@@ -576,6 +606,19 @@ ddm_status ddm_validate_config(const ddm_config* cfg, int32_t n_inst, const ddm_
   return s;
 }
 
+ddm_status ddm_skill_pose_table(const ddm_config* cfg, const ddm_instance* inst, int32_t n_steps,
+                                double* pose_out, double* jac_out) {
+  if (!cfg || !inst || !pose_out) return fail(DDM_EINVAL, "NULL argument");
+  if (n_steps < 1) return fail(DDM_EINVAL, "n_steps must be >= 1");
+  ddm_config c = *cfg;
+  c.max_steps = n_steps;
+  std::vector<double> p, j;
+  pose_table(c, *inst, p, j);
+  std::copy(p.begin(), p.end(), pose_out);
+  if (jac_out) std::copy(j.begin(), j.end(), jac_out);
+  return DDM_OK;
+}
+
 ddm_status ddm_workspace_query(const ddm_config* cfg, int32_t n_inst, const ddm_instance* inst, ddm_sizes* out) {
   const ddm_status s = validate(cfg, n_inst, inst);
   if (s != DDM_OK) return s;
@@ -613,6 +656,7 @@ ddm_status ddm_create(const ddm_config* cfg, int32_t n_inst, const ddm_instance*
   x->prec = cfg->precision == DDM_F64 ? 1 : 0;
   ddm::KCfg& k = x->kc;
   k.dim = cfg->dim; k.n = cfg->n_grid; k.bound = cfg->bound; k.shovel = cfg->shovel;
+  k.pcontact = cfg->particle_contact != 0 ? 1 : 0;
   k.nlog2 = 0;
   while ((1 << k.nlog2) < cfg->n_grid) ++k.nlog2;
   k.hm_res = cfg->hm_res; k.region_sign = cfg->region_sign >= 0 ? 1 : -1; k.n_inst = n_inst;
@@ -826,7 +870,13 @@ ddm_status ddm_backward(ddm_ctx* x, const double* dloss_dev, double* grad_dev) {
       const bool treat = rec || x->treat.mode != ddm::kTreatNone;
       const bool reduce = rec || x->treat.mode == ddm::kTreatScale || x->treat.mode == ddm::kTreatNorm;
       if (reduce) { Timed t(x, 9); ddm::launch_fill_zero(acc, (int64_t)ddm::treat_acc_words(x->n_inst), 8, st); }
-      { Timed t(x, 4); ddm::launch_g2p_adj(x->prec, x->kc, b, tl, L.nwg, slot(j), gpost(j), adj[cur], adj[1 - cur], x->at(L.gvb), st); }
+      {
+        Timed t(x, 4);
+        if (x->kc.pcontact)
+          ddm::launch_pcontact_adj(x->prec, x->kc, b, (int)L.nblk, (int)k, slot(j), gpost(j), adj[cur],
+                                   x->at<double>(L.pose_bar), st);
+        ddm::launch_g2p_adj(x->prec, x->kc, b, tl, L.nwg, slot(j), gpost(j), adj[cur], adj[1 - cur], x->at(L.gvb), st);
+      }
       if (treat) {
         Timed t(x, 9);
         treat_vectors(x, rec, TreatTarget{true, x->at(L.gvb), x->seg_alist(j), x->seg_acount(j), 3, false});

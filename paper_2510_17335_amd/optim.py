@@ -15,8 +15,8 @@ simulator (Sec. III-D, III-E, III-F; experiment design in Sec. IV-B).
   taken.
 - Loss-landscape sweeps as batched forwards over a list of parameter sets.
 
-Parameters are the 7-vectors [E, nu, phi_deg, rho, depth, angle_deg, push]
-of the library's gradient.  The driver itself only needs two evaluators:
+Parameters are the 9-vectors [E, nu, phi_deg, rho, depth, angle_deg, push,
+displace, push_angle_deg] of the library's gradient.  The driver itself only needs two evaluators:
 loss and gradient at one parameter set, and the losses of a batch of
 parameter sets; `GpuEvaluator` provides both on the GPU.
 """
@@ -29,7 +29,7 @@ from typing import Callable, Dict, List, Optional, Sequence, Tuple
 
 import numpy as np
 
-PARAM_NAMES = ("E", "nu", "phi_deg", "rho", "depth", "angle_deg", "push")
+PARAM_NAMES = ("E", "nu", "phi_deg", "rho", "depth", "angle_deg", "push", "displace", "push_angle_deg")
 LINE_SEARCH = (0.1, 0.5, 1.0, 1.5, 2.0)
 
 # Table I: step sizes and ranges of the physics parameters.  The table gives
@@ -42,9 +42,11 @@ SYSID_HI = {"E": 2e5, "nu": 0.4, "rho": 2200.0, "phi_deg": 40.0}
 
 def skill_steps(theta_step: float = 0.03) -> Dict[str, float]:
     """The step on the normalised skill parameters (Sec. IV-C: 0.03) in
-    physical units: d2 = 0.03 (theta + 1) m, phi1 = theta pi/3 rad = 60 theta
-    deg, d3 = 0.1 (theta + 1) + 0.04 m (Eqs. d1-d3)."""
-    return {"depth": 0.03 * theta_step, "angle_deg": 60.0 * theta_step, "push": 0.1 * theta_step}
+    physical units: d1 = 0.12 theta m, phi1 = theta pi/3 rad = 60 theta deg,
+    d2 = 0.03 (theta + 1) m, d3 = 0.1 (theta + 1) + 0.04 m, phi3 = (theta + 3)
+    pi/3 rad = 60 (theta + 3) deg (Eqs. d1-d3)."""
+    return {"depth": 0.03 * theta_step, "angle_deg": 60.0 * theta_step, "push": 0.1 * theta_step,
+            "displace": 0.12 * theta_step, "push_angle_deg": 60.0 * theta_step}
 
 
 @dataclass
@@ -64,7 +66,7 @@ class OptimSpec:
 
 @dataclass
 class OptimState:
-    theta: np.ndarray                 # full 7-vector
+    theta: np.ndarray                 # full parameter vector (PARAM_NAMES)
     v: np.ndarray                     # RMSprop second moment of the free parameters
     history: List[dict] = field(default_factory=list)
 
@@ -91,7 +93,7 @@ def rmsprop_direction(g: np.ndarray, v: np.ndarray, spec: OptimSpec) -> Tuple[np
 def optimise(theta0: Sequence[float], spec: OptimSpec, grad_fn: Callable[[np.ndarray], Tuple[float, np.ndarray]],
              batch_loss_fn: Callable[[List[np.ndarray]], np.ndarray], iterations: int,
              callback: Optional[Callable[[dict], None]] = None) -> OptimState:
-    """RMSprop with line search.  grad_fn(theta) -> (loss, grad[7]);
+    """RMSprop with line search.  grad_fn(theta) -> (loss, grad[len(PARAM_NAMES)]);
     batch_loss_fn([theta, ...]) -> losses (one batched forward)."""
     idx = spec.index()
     st = OptimState(theta=clamp(np.asarray(theta0, dtype=np.float64), spec), v=np.zeros(len(idx)))
@@ -121,10 +123,12 @@ def optimise(theta0: Sequence[float], spec: OptimSpec, grad_fn: Callable[[np.nda
 # ---------------------------------------------------------------------------
 
 def instance_with(ddm, base, theta: Sequence[float]):
-    """A copy of a ddm_instance with the 7 parameters replaced."""
+    """A copy of a ddm_instance with the parameters (PARAM_NAMES order) replaced."""
     inst = copy.copy(base)
     inst.E, inst.nu, inst.phi_deg, inst.rho = float(theta[0]), float(theta[1]), float(theta[2]), float(theta[3])
     inst.depth, inst.angle_deg, inst.push = float(theta[4]), float(theta[5]), float(theta[6])
+    if len(theta) > 7:
+        inst.displace, inst.push_angle_deg = float(theta[7]), float(theta[8])
     return inst
 
 

@@ -152,6 +152,54 @@ def test_gradient_dig3d_f64(ddm, orc):
     assert np.all(rel < 1e-6), rel
 
 
+def _full_skill(w):
+    """The workload with the rank-3 features on: the unrounded skill mapping,
+    particle-level collision, a displacement and a push angle away from pi."""
+    w.skill_unrounded = True
+    w.particle_contact = True
+    w.skill.displace = 0.02
+    w.skill.push_angle_deg = 170.0
+    return w
+
+
+@pytest.mark.parametrize("steps", [60, 170])
+def test_gradient_full_skill_f64(ddm, orc, steps):
+    """Nine gradients with the unrounded mapping, particle-level collision and
+    the five-parameter skill (tiny 3D bed, FP64, checkpoints every 16) vs the
+    oracle's forward-mode gradient; 170 sub-steps reach the insertion."""
+    w = _full_skill(W.tiny(3, shovel=True, steps=steps))
+    tgt = W.target_heightmap(w)
+    _log(f"case gradient full skill tiny3d {steps} steps")
+    g = run_gpu(ddm, w, steps, record=True, target=tgt, K=16)
+    r = run_oracle(orc, w, steps, target=tgt, grad=True)
+    _log("gpu grad", g["grad"], "\noracle grad", r["grad"])
+    e = field_errors(g["state"], r["state"], 3)
+    assert all(v < 1e-9 for v in e.values()), e
+    assert abs(g["loss"] - r["loss"]) <= 1e-10 * abs(r["loss"])
+    assert np.all(r["grad"][7:] != 0)
+    rel = np.abs(g["grad"] - r["grad"]) / np.maximum(np.abs(r["grad"]), 1e-9 * np.abs(r["grad"]).max())
+    assert np.all(rel < 1e-6), rel
+
+
+def test_forward_particle_contact_f32(ddm, orc):
+    """64^3 dig at 1 ppc (27 436 particles) with particle-level collision and
+    the five-parameter skill, FP32, 200 sub-steps vs the FP64 oracle: <= 1e-4."""
+    w = _full_skill(W.dig_3d(steps=200, ppc=1))
+    _log("case dig3d f32 particle contact 200 steps")
+    g = run_gpu(ddm, w, 200)
+    r = run_oracle(orc, w, 200)
+    e = field_errors(g["state"], r["state"], 3)
+    _log("dig3d f32 particle contact errors", e)
+    assert g["err"].flags & 3 == 0
+    for k, v in e.items():
+        assert v < 1e-4, (k, v)
+    # the collision acted: the rollout differs from the one without it
+    w2 = _full_skill(W.dig_3d(steps=200, ppc=1))
+    w2.particle_contact = False
+    g2 = run_gpu(ddm, w2, 200)
+    assert field_errors(g2["state"], g["state"], 3)["v"] > 1e-3
+
+
 def test_batched_equals_plain_f64(ddm):
     """Three instances of different sizes and materials in one context give the
     same states, losses and gradients as three separate contexts."""
@@ -262,7 +310,7 @@ def test_backward_needs_rollout_and_loss(ddm):
 
 def test_cohesion_forward_and_gradient_f64(ddm, orc):
     """Cohesive variant of the return map (shifted cone apex k_c): tiny 3D dig with
-    c = 500 Pa, forward state and the 7 gradients against the oracle."""
+    c = 500 Pa, forward state and the gradients against the oracle."""
     w = W.tiny(3, shovel=True, steps=60)
     w.material = W.Material(cohesion=500.0)
     tgt = W.target_heightmap(w)

@@ -57,12 +57,12 @@ def test_line_search_takes_the_best_candidate_and_respects_bounds():
 
 
 def test_converges_on_a_separable_quadratic():
-    center = np.array([2e5, 0.25, 35.0, 1800.0, 0.06, 20.0, 0.12])
-    scale = np.array([1e5, 0.1, 10.0, 500.0, 0.03, 30.0, 0.1])
+    center = np.array([2e5, 0.25, 35.0, 1800.0, 0.06, 20.0, 0.12, 0.03, 175.0])
+    scale = np.array([1e5, 0.1, 10.0, 500.0, 0.03, 30.0, 0.1, 0.05, 20.0])
     grad_fn, batch_fn = quad_problem(center, scale)
     spec = O.OptimSpec(free=list(O.PARAM_NAMES),
                        step={"E": 1e4, "nu": 0.01, "phi_deg": 1.0, "rho": 50.0, **O.skill_steps()}, clip=1e30)
-    theta0 = center + np.array([-8e4, 0.1, -8.0, -300.0, 0.02, 15.0, -0.05])
+    theta0 = center + np.array([-8e4, 0.1, -8.0, -300.0, 0.02, 15.0, -0.05, -0.04, 12.0])
     st = O.optimise(theta0, spec, grad_fn, batch_fn, 60)
     losses = [h["loss"] for h in st.history]
     assert losses[-1] < 1e-2 * losses[0]
@@ -77,3 +77,6 @@ def test_skill_steps_follow_the_normalised_skill_mapping():
     assert s["depth"] == pytest.approx(0.03 * 0.03)
     assert s["angle_deg"] == pytest.approx(np.degrees(np.pi / 3) * 0.03)
     assert s["push"] == pytest.approx(0.1 * 0.03)
+    # d1 = 0.12 theta, phi3 = (theta + 3) pi/3 (in degrees 60 (theta + 3))
+    assert s["displace"] == pytest.approx(0.12 * 0.03)
+    assert s["push_angle_deg"] == pytest.approx(np.degrees(np.pi / 3) * 0.03)
