@@ -50,6 +50,7 @@ class OrcConfig(C.Structure):
         ("w_mass", C.c_double), ("w_hm", C.c_double),
         ("cohesion", C.c_double),
         ("particle_contact", C.c_int32), ("pad1", C.c_int32),
+        ("w_emd", C.c_double),
     ]
 
 
@@ -65,7 +66,11 @@ def lib():
         dp = C.POINTER(C.c_double)
         L.orc_rollout.restype = C.c_int
         L.orc_rollout.argtypes = [C.POINTER(OrcConfig), dp, C.c_int, dp, C.c_int, C.c_int, dp, dp, dp, dp, dp,
-                                  C.POINTER(C.c_int64), dp]
+                                  C.POINTER(C.c_int64), dp, dp, C.c_int]
+        L.orc_assign.restype = C.c_int
+        L.orc_assign.argtypes = [C.c_int, C.c_int, dp, C.POINTER(C.c_int)]
+        L.orc_surface_particles.restype = C.c_int
+        L.orc_surface_particles.argtypes = [C.POINTER(OrcConfig), C.c_int, dp, C.POINTER(C.c_int)]
         L.orc_skill_actions.restype = C.c_int
         L.orc_skill_actions.argtypes = [dp, C.c_double, C.c_double, C.c_double, C.c_double, C.c_int, C.c_int,
                                         C.POINTER(C.c_int), dp, dp]
@@ -119,6 +124,7 @@ def config(w, shovel: Optional[bool] = None, **over) -> OrcConfig:
     c.cohesion = w.material.cohesion
     c.skill_unrounded = int(w.skill_unrounded)
     c.particle_contact = int(w.particle_contact)
+    c.w_emd = float(getattr(w, "w_emd", 0.0))
     for k, v in over.items():
         setattr(c, k, v)
     return c
@@ -151,7 +157,8 @@ class OracleError(RuntimeError):
 
 
 def rollout(cfg: OrcConfig, params: np.ndarray, state: np.ndarray, n_steps: int, step0: int = 0,
-            target: Optional[np.ndarray] = None, grad: bool = False, want_grid: bool = False):
+            target: Optional[np.ndarray] = None, grad: bool = False, want_grid: bool = False,
+            emd_target: Optional[np.ndarray] = None):
     """Run sub-steps [step0, step0+n_steps).  Returns a dict with the final state,
     and loss / grad / height map when a target is given, grid of the last step
     (m, mv[3], v[3] per node) when asked."""
@@ -168,8 +175,10 @@ def rollout(cfg: OrcConfig, params: np.ndarray, state: np.ndarray, n_steps: int,
     stats = np.zeros(8, dtype=np.int64)
     nodes = cfg.n_grid ** cfg.dim
     grid = np.zeros((nodes, 7)) if want_grid else None
+    et = np.ascontiguousarray(emd_target, dtype=np.float64).reshape(-1, 3) if emd_target is not None else None
     rc = L.orc_rollout(C.byref(cfg), _p(params), n, _p(state), step0, n_steps, _p(out), _p(tgt), _p(loss),
-                       _p(g), _p(hm), stats.ctypes.data_as(C.POINTER(C.c_int64)), _p(grid))
+                       _p(g), _p(hm), stats.ctypes.data_as(C.POINTER(C.c_int64)), _p(grid), _p(et),
+                       0 if et is None else et.shape[0])
     if rc != 0:
         raise OracleError(f"oracle rollout failed with code {rc} (stats {stats.tolist()})")
     res = {"state": out, "stats": stats}
@@ -271,3 +280,21 @@ def bin_keys(x: np.ndarray, n_grid: int, tile: int, inst: Optional[np.ndarray] =
     if rc != 0:
         raise OracleError(f"binning failed with code {rc}")
     return keys, perm
+
+
+def assign(cost: np.ndarray) -> np.ndarray:
+    """Column of every row of the cheapest one-to-one assignment (rows <= columns)."""
+    cost = np.ascontiguousarray(cost, dtype=np.float64)
+    n, m = cost.shape
+    out = np.zeros(n, dtype=np.int32)
+    if lib().orc_assign(n, m, _p(cost), out.ctypes.data_as(C.POINTER(C.c_int))) != 0:
+        raise OracleError("bad assignment shape")
+    return out
+
+
+def surface_particles(cfg: OrcConfig, state: np.ndarray) -> np.ndarray:
+    """Indices of the particles of the surface observation, in pixel order."""
+    state = np.ascontiguousarray(state, dtype=np.float64)
+    out = np.zeros(cfg.hm_res ** 2, dtype=np.int32)
+    n = lib().orc_surface_particles(C.byref(cfg), state.shape[0], _p(state), out.ctypes.data_as(C.POINTER(C.c_int)))
+    return out[:n].copy()

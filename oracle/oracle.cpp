@@ -16,7 +16,9 @@
 //      optionally with the unrounded T_1^float, T_4^float in the per-action
 //      displacements of phases 1 and 4 (the ablation variant of Sec. III-B);
 //    * the particle-level collision of Algorithm 1 line 12 (optional);
-//    * the height-map observation and loss (Eq. hm, Sec. III-A "Goal").
+//    * the height-map observation and loss (Eq. hm, Sec. III-A "Goal"), and
+//      the earth mover's distance between the surface observation and a
+//      target point cloud (Eq. emd) through an exact linear assignment.
 //  Gradients are exact forward-mode tangents (Dual<9>) of all of the above with
 //  respect to (E, nu, phi_f[deg], rho, insert depth, rotate angle[deg], push
 //  distance, displacement d1, push angle phi3[deg]); the rounded phase lengths
@@ -34,6 +36,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <limits>
 #include <numeric>
 #include <vector>
 
@@ -62,6 +65,7 @@ typedef struct orc_config {
   double region_depth, m_target, m_ref, w_mass, w_hm;
   double cohesion;
   int32_t particle_contact, pad1;  // Algorithm 1 line 12 on (1) or off (0)
+  double w_emd;                    // weight of the EMD term (Eq. emd); 0 = off
 } orc_config;
 }
 
@@ -520,6 +524,52 @@ static double gradient_of(double, int) { return 0.0; }
 template <int K> static double gradient_of(const Dual<K>& x, int k) { return x.d[k]; }
 
 // ---------------------------------------------------------------------------
+// Linear assignment for Eq. emd: the injective map from n rows to m >= n
+// columns with the least total cost (the Hungarian method).  Rows are added
+// one at a time; each addition runs a Dijkstra-like search over the columns on
+// costs reduced by row and column potentials, and augments the matching along
+// the cheapest path found, after which the potentials are updated so that the
+// reduced costs stay non-negative.  O(n^2 m).  cost is n x m, row-major;
+// returns the column of every row.
+// ---------------------------------------------------------------------------
+static void assign_min_cost(int n, int m, const std::vector<double>& cost, std::vector<int>* row_col) {
+  const double kInf = std::numeric_limits<double>::infinity();
+  std::vector<double> u(n + 1, 0.0), v(m + 1, 0.0), slack(m + 1);
+  std::vector<int> match(m + 1, 0), from(m + 1, 0);   // match[j]: row of column j (1-based, 0 = free)
+  std::vector<char> done(m + 1);
+  for (int i = 1; i <= n; ++i) {
+    match[0] = i;                                     // column 0 is the root of the search
+    int j0 = 0;
+    std::fill(slack.begin(), slack.end(), kInf);
+    std::fill(done.begin(), done.end(), 0);
+    do {
+      done[j0] = 1;
+      const int i0 = match[j0];
+      double delta = kInf;
+      int j1 = 0;
+      for (int j = 1; j <= m; ++j) {
+        if (done[j]) continue;
+        const double red = cost[(size_t)(i0 - 1) * m + (j - 1)] - u[i0] - v[j];
+        if (red < slack[j]) { slack[j] = red; from[j] = j0; }
+        if (slack[j] < delta) { delta = slack[j]; j1 = j; }
+      }
+      for (int j = 0; j <= m; ++j) {
+        if (done[j]) { u[match[j]] += delta; v[j] -= delta; }
+        else slack[j] -= delta;
+      }
+      j0 = j1;
+    } while (match[j0] != 0);
+    while (j0) {                                      // augment along the path back to the root
+      const int j1 = from[j0];
+      match[j0] = match[j1];
+      j0 = j1;
+    }
+  }
+  row_col->assign(n, -1);
+  for (int j = 1; j <= m; ++j) if (match[j]) (*row_col)[match[j] - 1] = j - 1;
+}
+
+// ---------------------------------------------------------------------------
 // The simulator state and one sub-step (Algorithm 1).
 // ---------------------------------------------------------------------------
 template <class S>
@@ -531,7 +581,9 @@ struct Sim {
   std::vector<S> x, v, C, F;          // N*3, N*3, N*9, N*9
   std::vector<S> gm, gmv, gv;         // nodes, nodes*3, nodes*3
   std::vector<Pose<S>> poses;
-  int64_t stats[8];                    // clamps, case1, case2, case3, domain errors
+  const double* emd_target = nullptr;  // [emd_m][3] target surface points (Eq. emd)
+  int emd_m = 0;
+  int64_t stats[8];                    // clamps, case1, case2, case3, domain errors, EMD overflow
 
   Sim(const orc_config& cf, int N_) : c(cf), d(cf.dim), n(cf.n_grid), N(N_) {
     nodes = 1;
@@ -779,7 +831,54 @@ struct Sim {
       const S e = (Min - c.m_target) / c.m_ref;
       L += c.w_mass * e * e;
     }
+    if (d == 3 && c.w_emd != 0.0) L += c.w_emd * emd();
     return L;
+  }
+
+  // Surface observation (Sec. III-A, "States and observations"): in each pixel
+  // of the height-map window, the highest particle whose own (x, z) lies in it
+  // (ties keep the lowest particle index); empty pixels give no point.
+  std::vector<int> surface_particles() const {
+    const int res = c.hm_res;
+    const double pix = c.hm_size / res;
+    std::vector<int> own(res * res, -1);
+    for (int p = 0; p < N; ++p) {
+      const int ix = (int)std::floor((val(x[p * 3 + 0]) - c.hm_origin[0]) / pix);
+      const int iz = (int)std::floor((val(x[p * 3 + 2]) - c.hm_origin[1]) / pix);
+      if (ix < 0 || ix >= res || iz < 0 || iz >= res) continue;
+      int& o = own[ix * res + iz];
+      if (o < 0 || val(x[p * 3 + 1]) > val(x[o * 3 + 1])) o = p;
+    }
+    std::vector<int> out;
+    for (int o : own) if (o >= 0) out.push_back(o);
+    return out;
+  }
+
+  // Eq. emd: the sum over the observed points of the distance to their
+  // targets under the cheapest one-to-one assignment (it exists when there
+  // are no more points than targets; otherwise stats[5] counts the failure
+  // and the term is 0).  The assignment is a choice and carries no tangent.
+  S emd() {
+    const std::vector<int> obs = surface_particles();
+    const int n = (int)obs.size(), m = emd_m;
+    if (n == 0) return S(0.0);
+    if (n > m || !emd_target) { stats[5]++; return S(0.0); }
+    std::vector<double> cost((size_t)n * m);
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < m; ++j) {
+        double s2 = 0.0;
+        for (int a = 0; a < 3; ++a) { const double dd = val(x[obs[i] * 3 + a]) - emd_target[j * 3 + a]; s2 += dd * dd; }
+        cost[(size_t)i * m + j] = std::sqrt(s2);
+      }
+    std::vector<int> phi;
+    assign_min_cost(n, m, cost, &phi);
+    S total = S(0.0);
+    for (int i = 0; i < n; ++i) {
+      S s2 = S(0.0);
+      for (int a = 0; a < 3; ++a) { const S dd = x[obs[i] * 3 + a] - emd_target[phi[i] * 3 + a]; s2 += dd * dd; }
+      if (val(s2) > 0.0) total += sqrt(s2);
+    }
+    return total;
   }
 };
 
@@ -799,9 +898,12 @@ static int validate(const orc_config* c, const double* p) {
 template <class S>
 static int rollout(const orc_config* c, const double* p, int N, const double* state_in, int step0,
                    int n_steps, double* state_out, const double* target, double* loss_out,
-                   double* grad_out, double* hm_out, int64_t* stats, double* grid_out) {
+                   double* grad_out, double* hm_out, int64_t* stats, double* grid_out, const double* emd_target,
+                   int emd_m) {
   const bool dual = grad_out != nullptr;
   Sim<S> sim(*c, N);
+  sim.emd_target = emd_target;
+  sim.emd_m = emd_m;
   sim.set_material(param<S>(p, 0, dual), param<S>(p, 1, dual), param<S>(p, 2, dual), param<S>(p, 3, dual));
   const int total = step0 + n_steps;
   if (c->shovel && c->dim == 3) {
@@ -865,10 +967,33 @@ extern "C" {
 
 int orc_rollout(const orc_config* c, const double* p, int N, const double* state_in, int step0, int n_steps,
                 double* state_out, const double* target, double* loss_out, double* grad_out,
-                double* hm_out, int64_t* stats, double* grid_out) {
-  if (validate(c, p) != ORC_OK || N < 0 || n_steps < 0 || step0 < 0) return ORC_EINVAL;
-  if (grad_out) return rollout<Dual<9>>(c, p, N, state_in, step0, n_steps, state_out, target, loss_out, grad_out, hm_out, stats, grid_out);
-  return rollout<double>(c, p, N, state_in, step0, n_steps, state_out, target, loss_out, nullptr, hm_out, stats, grid_out);
+                double* hm_out, int64_t* stats, double* grid_out, const double* emd_target, int emd_m) {
+  if (validate(c, p) != ORC_OK || N < 0 || n_steps < 0 || step0 < 0 || emd_m < 0) return ORC_EINVAL;
+  if (grad_out)
+    return rollout<Dual<9>>(c, p, N, state_in, step0, n_steps, state_out, target, loss_out, grad_out, hm_out, stats,
+                            grid_out, emd_target, emd_m);
+  return rollout<double>(c, p, N, state_in, step0, n_steps, state_out, target, loss_out, nullptr, hm_out, stats,
+                         grid_out, emd_target, emd_m);
+}
+
+// The assignment of Eq. emd on an n x m cost matrix (n <= m): row_col[n].
+int orc_assign(int n, int m, const double* cost, int* row_col) {
+  if (n < 0 || m < n) return ORC_EINVAL;
+  std::vector<double> cm(cost, cost + (size_t)n * m);
+  std::vector<int> rc;
+  assign_min_cost(n, m, cm, &rc);
+  for (int i = 0; i < n; ++i) row_col[i] = rc[i];
+  return ORC_OK;
+}
+
+// Particles of the surface observation of a packed state (pixel order).
+int orc_surface_particles(const orc_config* c, int N, const double* state, int* out) {
+  Sim<double> sim(*c, N);
+  const int d = c->dim, sd = 2 * d + 2 * d * d;
+  for (int q = 0; q < N; ++q) for (int a = 0; a < d; ++a) sim.x[q * 3 + a] = state[(size_t)q * sd + a];
+  const std::vector<int> o = sim.surface_particles();
+  for (size_t i = 0; i < o.size(); ++i) out[i] = o[i];
+  return (int)o.size();
 }
 
 // Skill actions for the paper's theta; jac (optional) = d action / d theta,

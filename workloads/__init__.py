@@ -98,6 +98,7 @@ class Workload:
     n_sub: int = 10                     # sub-steps per action
     skill_unrounded: bool = False       # phases 1 and 4 divide by T^float (Sec. III-B)
     particle_contact: bool = False      # collision of Algorithm 1 line 12
+    w_emd: float = 0.0                  # weight of the EMD term (Eq. emd) in the loss
     checkpoint_every: int = 0
     target_seed: Optional[int] = None
     # Shovel and contact (the paper gives an SDF with Coulomb friction; sizes
@@ -296,6 +297,18 @@ def target_heightmap(w: Workload, seed: Optional[int] = None) -> np.ndarray:
 class Instance:
     workload: Workload
     material: Material
+
+
+def target_points(w: Workload, seed: Optional[int] = None) -> np.ndarray:
+    """Target surface point cloud for the EMD loss (Eq. emd): one point per
+    pixel of the target height map, at the pixel centre and the target height
+    (build frame, y up).  float64 [hm_res^2, 3], pixel order [ix, iz]."""
+    H = target_heightmap(w, seed)
+    res = w.hm_res
+    pix = w.hm_size / res
+    c = (np.arange(res) + 0.5) * pix
+    X, Z = np.meshgrid(w.hm_origin[0] + c, w.hm_origin[1] + c, indexing="ij")
+    return np.ascontiguousarray(np.stack([X.ravel(), H.reshape(-1), Z.ravel()], axis=1))
 
 
 def sysid_batch(n_inst: int = 64, seed: int = 4, n_lo: int = 20000, n_hi: int = 200000,
