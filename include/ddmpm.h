@@ -107,6 +107,9 @@ typedef struct ddm_config {
                                contact, one in the wall layers (closer than bound cells to a face)
                                gets zero velocity; 0: grid collision only */
   int32_t pad0;
+  double w_emd;             /* weight of the earth mover's distance (Eq. emd) between the surface
+                               observation and the target set by ddm_set_emd_target; 0 = off;
+                               dim 3 only */
 } ddm_config;
 
 /* One simulation instance: material, skill and time step. */
@@ -141,7 +144,9 @@ typedef struct ddm_ctx ddm_ctx;
 
 /* Device-side error report (ddm_check). */
 typedef struct ddm_device_error {
-  uint32_t flags;           /* bit 0: NaN/Inf, bit 1: stencil left the grid, bit 2: sigma clamped */
+  uint32_t flags;           /* bit 0: NaN/Inf, bit 1: stencil left the grid, bit 2: sigma clamped,
+                               bit 3: EMD with more observed points than targets (term set to 0),
+                               bit 4: EMD assignment stopped at its round limit (term set to 0) */
   uint32_t first_instance;  /* instance of the first flagged particle */
   uint64_t clamp_count;     /* singular values clamped to 1e-6 since the last reset */
 } ddm_device_error;
@@ -204,9 +209,21 @@ ddm_status ddm_rollout(ddm_ctx* ctx, int32_t n_steps);
 
 /* Loss of every instance at the current state: height map of Eq. hm (40x40,
  * five-point stencil, max height) against target_hm_dev
- * ([n_inst][hm_res^(dim-1)] in double, device), plus the scoop-mass term.
- * Writes loss_dev[n_inst] (double, device). */
+ * ([n_inst][hm_res^(dim-1)] in double, device), plus the scoop-mass term,
+ * plus w_emd times the earth mover's distance of Eq. emd when w_emd != 0: the
+ * surface observation (in each pixel of the height-map window the highest
+ * particle whose own (x, z) lies in it, Sec. III-A) against the target point
+ * cloud of ddm_set_emd_target, under the cheapest one-to-one assignment
+ * (auction algorithm, within m * 1e-10 * the diagonal of the two point sets
+ * of the least sum, m the number of targets).  Writes loss_dev[n_inst] (double, device).  DDM_ESTATE when w_emd != 0
+ * and no target was set. */
 ddm_status ddm_loss(ddm_ctx* ctx, const double* target_hm_dev, double* loss_dev);
+
+/* Target surface point clouds of the EMD term (Eq. emd): points_dev
+ * [n_inst][m][3] (double, device, build frame, y up), copied into the
+ * workspace on the context's stream; m in [1, hm_res^2].  Kept until replaced.
+ * Errors: DDM_EINVAL for NULL, m out of range, or dim != 3. */
+ddm_status ddm_set_emd_target(ddm_ctx* ctx, const double* points_dev, int32_t m);
 
 /* Reverse pass of the last ddm_rollout + ddm_loss: with dloss_dev[n_inst]
  * (double, device) the upstream gradient, writes grad_dev[n_inst][DDM_N_PARAMS]

@@ -38,7 +38,7 @@ class DdmConfig(C.Structure):
         ("hm_offset", C.c_double), ("region_depth", C.c_double), ("m_target", C.c_double), ("m_ref", C.c_double),
         ("w_mass", C.c_double), ("w_hm", C.c_double), ("checkpoint_every", C.c_int32), ("max_steps", C.c_int32),
         ("sort_every", C.c_int32), ("skill_unrounded", C.c_int32), ("particle_contact", C.c_int32),
-        ("pad0", C.c_int32),
+        ("pad0", C.c_int32), ("w_emd", C.c_double),
     ]
 
 
@@ -93,6 +93,7 @@ def lib():
             "ddm_step": (C.c_int, [vp, i32]),
             "ddm_rollout": (C.c_int, [vp, i32]),
             "ddm_loss": (C.c_int, [vp, vp, vp]),
+            "ddm_set_emd_target": (C.c_int, [vp, vp, i32]),
             "ddm_backward": (C.c_int, [vp, vp, vp]),
             "ddm_pass": (C.c_int, [vp, vp, i32, vp, vp, vp, vp, i32]),
             "ddm_autotune": (C.c_int, [vp, C.c_char_p, C.POINTER(i32)]),
@@ -137,7 +138,7 @@ def make_config(dim: int, n_grid: int, precision: str = "f32", *, bound: int = 3
                 region_depth: float = 0.03, m_target: float = 0.192, m_ref: float = 0.384, w_mass: float = 1.0,
                 w_hm: float = 1.0, region_sign: int = -1, checkpoint_every: int = 50,
                 max_steps: int = 1000, sort_every: int = 8, skill_unrounded: bool = False,
-                particle_contact: bool = False) -> DdmConfig:
+                particle_contact: bool = False, w_emd: float = 0.0) -> DdmConfig:
     c = DdmConfig()
     c.dim, c.n_grid, c.bound = dim, n_grid, bound
     c.precision = DDM_F64 if precision == "f64" else DDM_F32
@@ -153,6 +154,7 @@ def make_config(dim: int, n_grid: int, precision: str = "f32", *, bound: int = 3
     c.region_depth, c.m_target, c.m_ref, c.w_mass, c.w_hm = region_depth, m_target, m_ref, w_mass, w_hm
     c.checkpoint_every, c.max_steps, c.sort_every = checkpoint_every, max_steps, sort_every
     c.skill_unrounded, c.particle_contact = int(bool(skill_unrounded)), int(bool(particle_contact))
+    c.w_emd = float(w_emd)
     return c
 
 
@@ -182,7 +184,7 @@ def from_workload(w, max_steps: Optional[int] = None, checkpoint_every: Optional
         w_hm=w.w_hm, region_sign=w.region_sign,
         checkpoint_every=checkpoint_every or w.checkpoint_every or 50,
         max_steps=max_steps or w.steps, sort_every=sort_every, skill_unrounded=w.skill_unrounded,
-        particle_contact=w.particle_contact)
+        particle_contact=w.particle_contact, w_emd=w.w_emd)
     p = w.params
     inst = make_instance(w.n_particles, E=p[0], nu=p[1], phi_deg=p[2], rho=p[3], cohesion=w.material.cohesion,
                          depth=p[4], angle_deg=p[5], push=p[6], dt=w.dt, tip0=w.tip0, displace=p[7],
@@ -370,6 +372,17 @@ class Simulator:
         _check(lib().ddm_loss(self.ctx, C.c_void_p(self._target.data_ptr()), C.c_void_p(out.data_ptr())))
         self._outputs_ready()
         return out
+
+    def set_emd_target(self, points):
+        """Target point clouds of the EMD term, [n_inst, m, 3] or [m, 3] for
+        every instance (ddm_set_emd_target)."""
+        t = self.torch
+        pts = t.as_tensor(np.asarray(points) if not isinstance(points, t.Tensor) else points, dtype=t.float64)
+        if pts.dim() == 2:
+            pts = pts.unsqueeze(0).expand(self.n_inst, -1, -1)
+        self._emd_target = pts.to(self.device).contiguous()
+        self._inputs_ready()
+        _check(lib().ddm_set_emd_target(self.ctx, C.c_void_p(self._emd_target.data_ptr()), int(pts.shape[1])))
 
     def heightmap(self):
         out = self.torch.empty((self.n_inst, self.npix), dtype=self.torch.float64, device=self.device)

@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libddmpm.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["ddm_kernels.hip", "ddm_sort.hip", "ddm_treat.hip", "ddm_runtime.hip"]
+SOURCES = ["ddm_kernels.hip", "ddm_sort.hip", "ddm_treat.hip", "ddm_emd.hip", "ddm_runtime.hip"]
 HEADERS = ["ddm_device.hpp", "ddm_kernels.hpp", os.path.join("..", "..", "include", "ddmpm.h")]
 
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-munsafe-fp-atomics",

@@ -44,7 +44,7 @@ struct InstDev {
 
 // Device error word.
 struct DevErr {
-  unsigned int flags;                // 1: NaN/Inf, 2: stencil left the grid, 4: sigma clamped
+  unsigned int flags;                // 1: NaN/Inf, 2: stencil left the grid, 4: sigma clamped, 8/16: EMD (ddm_emd.hip)
   unsigned int first_inst;
   unsigned long long clamps;
 };
@@ -58,6 +58,7 @@ struct KCfg {
   double dx, inv_dx, gravity, skin, mu_b, half[3];
   double hm_ox, hm_oz, hm_pix, hm_off, region_depth;
   double w_hm, w_mass, m_target, m_ref;
+  double w_emd;
 };
 
 // Node of an active-set item: item i is node i % 4^D of listed block i / 4^D.
@@ -163,6 +164,31 @@ void launch_unpermute(int elem_bytes, const void* in, void* out, const uint32_t*
 // One record per occupied tile, and tslot (record of each tile, or kNoSlot).
 void launch_tile_list(const KCfg& c, const uint32_t* sorted_keys, uint32_t* tstart, uint32_t* tend, TileRec* list,
                       uint32_t* count, uint32_t* tslot, hipStream_t s);
+
+// Earth mover's distance of the surface observation to a target point cloud
+// (ddm_emd.hip); arrays are [n_inst][hm_res^2] (points [..][3]).
+struct EmdBufs {
+  unsigned long long* top;        // highest position key per pixel
+  unsigned long long* own;        // (particle id << 32 | slot) of the pixel's owner, ~0 if none
+  double* target;                 // target points, m per instance
+  double* obs;                    // observed points, pixel order
+  int* obs_slot;                  // owner slot of each observed point (relative to the instance)
+  int* n_obs;                     // [n_inst]
+  double* price;                  // auction prices of the targets
+  int* obj_owner;                 // point holding each target
+  int* assign;                    // target of each point
+  unsigned long long* bid_max;
+  int* bid_win;
+  double* bid_val;
+  int* bid_obj;
+  double* emd;                    // [n_inst]
+};
+// loss[inst] += w_emd * EMD of the state (the targets hold m points per instance).
+void launch_emd(int prec, const KCfg& c, const Bufs& b, int nblk, const void* state, const uint32_t* pid,
+                const EmdBufs& E, int m, double w_emd, double* loss, hipStream_t s);
+// adjoint x rows += w_emd * d EMD / d x (after the loss seed).
+void launch_emd_seed(int prec, const KCfg& c, const Bufs& b, const EmdBufs& E, double w_emd, void* adj,
+                     hipStream_t s);
 
 // Gradient treatments of the reverse pass (ddm_treat.hip).  Variables (one
 // vector per instance each): 0 particle x, 1 particle v, 2 particle F, 3 grid

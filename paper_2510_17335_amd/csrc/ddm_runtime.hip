@@ -52,6 +52,8 @@ struct Layout {
   size_t keys0 = 0, keys1 = 0, vals0 = 0, vals1 = 0, hist = 0, sums = 0, tstart = 0, tend = 0, tiles = 0, tcount = 0;
   size_t tslot = 0, staging = 0, gout = 0, amask = 0, alist = 0, acount = 0, seg_alist = 0, seg_acount = 0;
   size_t treat_acc = 0;
+  size_t emd_top = 0, emd_own = 0, emd_target = 0, emd_obs = 0, emd_slot = 0, emd_nobs = 0, emd_price = 0,
+         emd_owner = 0, emd_assign = 0, emd_bmax = 0, emd_bwin = 0, emd_bval = 0, emd_bobj = 0, emd_val = 0;
   size_t total = 0;
   size_t state_bytes = 0, grid_bytes = 0;
   int64_t ntot = 0, nblk = 0, total_tiles = 0, max_chunks = 0;
@@ -149,6 +151,23 @@ Layout make_layout(const ddm_config& c, int n_inst, const ddm_instance* in) {
   L.acount = cv.take(sizeof(uint32_t));
   L.seg_alist = cv.take(sizeof(uint32_t) * L.total_tiles * L.K);
   L.seg_acount = cv.take(sizeof(uint32_t) * L.K);
+  if (D == 3 && c.w_emd != 0.0) {
+    const size_t np = (size_t)n_inst * c.hm_res * c.hm_res;
+    L.emd_top = cv.take(8 * np);
+    L.emd_own = cv.take(8 * np);
+    L.emd_target = cv.take(24 * np);
+    L.emd_obs = cv.take(24 * np);
+    L.emd_slot = cv.take(4 * np);
+    L.emd_nobs = cv.take(4 * (size_t)n_inst);
+    L.emd_price = cv.take(8 * np);
+    L.emd_owner = cv.take(4 * np);
+    L.emd_assign = cv.take(4 * np);
+    L.emd_bmax = cv.take(8 * np);
+    L.emd_bwin = cv.take(4 * np);
+    L.emd_bval = cv.take(8 * np);
+    L.emd_bobj = cv.take(4 * np);
+    L.emd_val = cv.take(8 * (size_t)n_inst);
+  }
   L.total = cv.take(0);
   return L;
 }
@@ -325,6 +344,7 @@ struct ddm_ctx {
   ddm::Treat treat{ddm::kTreatNone, 1e4, 4.0, 1e-6};
   double* stats_dev = nullptr;
   int32_t stats_steps = 0;
+  int32_t emd_m = 0;              // target points per instance set by ddm_set_emd_target (0: none)
 
   template <typename T = char> T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
   void* cur() const { return at(cur_off); }
@@ -347,6 +367,24 @@ struct ddm_ctx {
     b.poses = at<const void>(L.poses);
     b.err = at<ddm::DevErr>(L.err);
     return b;
+  }
+  ddm::EmdBufs emdbufs() const {
+    ddm::EmdBufs e;
+    e.top = at<unsigned long long>(L.emd_top);
+    e.own = at<unsigned long long>(L.emd_own);
+    e.target = at<double>(L.emd_target);
+    e.obs = at<double>(L.emd_obs);
+    e.obs_slot = at<int>(L.emd_slot);
+    e.n_obs = at<int>(L.emd_nobs);
+    e.price = at<double>(L.emd_price);
+    e.obj_owner = at<int>(L.emd_owner);
+    e.assign = at<int>(L.emd_assign);
+    e.bid_max = at<unsigned long long>(L.emd_bmax);
+    e.bid_win = at<int>(L.emd_bwin);
+    e.bid_val = at<double>(L.emd_bval);
+    e.bid_obj = at<int>(L.emd_bobj);
+    e.emd = at<double>(L.emd_val);
+    return e;
   }
   ddm::LossBufs lossbufs() const {
     ddm::LossBufs l;
@@ -379,6 +417,8 @@ ddm_status validate(const ddm_config* c, int32_t n_inst, const ddm_instance* in)
   if (c->checkpoint_every < 1) return fail(DDM_EINVAL, "checkpoint_every must be >= 1");
   if (c->max_steps < 1) return fail(DDM_EINVAL, "max_steps must be >= 1");
   if (c->sort_every < 0) return fail(DDM_EINVAL, "sort_every must be >= 0");
+  if (c->w_emd != 0.0 && c->dim != 3) return fail(DDM_EINVAL, "the EMD term needs dim 3");
+  if (!std::isfinite(c->w_emd)) return fail(DDM_EINVAL, "w_emd must be finite");
   if (c->shovel && !(c->v_lin > 0 && c->v_ang > 0 && c->d_lift > 0 && c->contact_skin >= 0 && c->shovel_mu >= 0))
     return fail(DDM_EINVAL, "shovel speeds, lift, skin and friction must be positive");
   if (n_inst < 1 || !in) return fail(DDM_EINVAL, "need at least one instance");
@@ -670,6 +710,7 @@ ddm_status ddm_create(const ddm_config* cfg, int32_t n_inst, const ddm_instance*
   k.hm_ox = cfg->hm_origin[0]; k.hm_oz = cfg->hm_origin[1]; k.hm_pix = cfg->hm_size / cfg->hm_res;
   k.hm_off = cfg->hm_offset; k.region_depth = cfg->region_depth;
   k.w_hm = cfg->w_hm; k.w_mass = cfg->w_mass; k.m_target = cfg->m_target; k.m_ref = cfg->m_ref;
+  k.w_emd = cfg->w_emd;
 
   s = upload_instances(x, inst);
   if (s == DDM_OK) s = hip_check(hipMemset(x->at(L.err), 0, sizeof(ddm::DevErr)), "clear error word");
@@ -776,14 +817,31 @@ ddm_status ddm_loss(ddm_ctx* x, const double* target_hm_dev, double* loss_dev) {
   const int npix = x->cfg.dim == 3 ? x->cfg.hm_res * x->cfg.hm_res : x->cfg.hm_res;
   DDM_HIP(hipMemcpyAsync(x->at(x->L.target), target_hm_dev, sizeof(double) * (size_t)x->n_inst * npix,
                          hipMemcpyDeviceToDevice, x->stream));
+  if (x->cfg.w_emd != 0.0 && x->emd_m == 0) return fail(DDM_ESTATE, "w_emd != 0 needs ddm_set_emd_target");
   {
     Timed t(x, 8);
     ddm::launch_loss(x->prec, x->kc, x->bufs(), (int)x->L.nblk, x->cur(), x->pid(),
                      (int)x->steps - 1, x->lossbufs(), x->stream);
+    if (x->cfg.w_emd != 0.0)
+      ddm::launch_emd(x->prec, x->kc, x->bufs(), (int)x->L.nblk, x->cur(), x->pid(), x->emdbufs(), x->emd_m,
+                      x->cfg.w_emd, x->at<double>(x->L.loss), x->stream);
   }
   DDM_HIP(hipMemcpyAsync(loss_dev, x->at(x->L.loss), sizeof(double) * x->n_inst, hipMemcpyDeviceToDevice, x->stream));
   x->loss_ready = x->recorded && x->steps == x->rec_k0 + x->rec_n;
   return launch_status();
+}
+
+ddm_status ddm_set_emd_target(ddm_ctx* x, const double* points_dev, int32_t m) {
+  if (!x || !points_dev) return fail(DDM_EINVAL, "NULL argument");
+  if (x->cfg.dim != 3) return fail(DDM_EINVAL, "the EMD term needs dim 3");
+  if (x->cfg.w_emd == 0.0) return fail(DDM_EINVAL, "w_emd is 0: the workspace holds no EMD buffers");
+  const int npix = x->cfg.hm_res * x->cfg.hm_res;
+  if (m < 1 || m > npix) return fail(DDM_EINVAL, "m outside [1, hm_res^2]");
+  // [n_inst][m][3] into the workspace's [n_inst][hm_res^2][3]
+  DDM_HIP(hipMemcpy2DAsync(x->at(x->L.emd_target), sizeof(double) * 3 * npix, points_dev, sizeof(double) * 3 * m,
+                           sizeof(double) * 3 * m, x->n_inst, hipMemcpyDeviceToDevice, x->stream));
+  x->emd_m = m;
+  return DDM_OK;
 }
 
 namespace {
@@ -829,6 +887,7 @@ ddm_status ddm_backward(ddm_ctx* x, const double* dloss_dev, double* grad_dev) {
   int cur = 0;
   ddm::launch_loss_seed(x->prec, x->kc, b, (int)L.nblk, x->cur(), x->pid(), (int)x->steps - 1,
                         x->lossbufs(), adj[cur], x->at<double>(L.pacc), st);
+  if (x->cfg.w_emd != 0.0) ddm::launch_emd_seed(x->prec, x->kc, b, x->emdbufs(), x->cfg.w_emd, adj[cur], st);
   const int K = L.K;
   const int64_t n = x->rec_n, k0 = x->rec_k0;
   const int nseg = (int)((n + K - 1) / K);
