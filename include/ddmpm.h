@@ -145,8 +145,8 @@ typedef struct ddm_ctx ddm_ctx;
 /* Device-side error report (ddm_check). */
 typedef struct ddm_device_error {
   uint32_t flags;           /* bit 0: NaN/Inf, bit 1: stencil left the grid, bit 2: sigma clamped,
-                               bit 3: EMD with more observed points than targets (term set to 0),
-                               bit 4: EMD assignment stopped at its round limit (term set to 0) */
+                               bit 3: EMD term set to 0: more observed points than targets, or
+                               non-finite distances */
   uint32_t first_instance;  /* instance of the first flagged particle */
   uint64_t clamp_count;     /* singular values clamped to 1e-6 since the last reset */
 } ddm_device_error;
@@ -214,9 +214,8 @@ ddm_status ddm_rollout(ddm_ctx* ctx, int32_t n_steps);
  * surface observation (in each pixel of the height-map window the highest
  * particle whose own (x, z) lies in it, Sec. III-A) against the target point
  * cloud of ddm_set_emd_target, under the cheapest one-to-one assignment
- * (auction algorithm, within m * 1e-10 * the diagonal of the two point sets
- * of the least sum, m the number of targets).  Writes loss_dev[n_inst] (double, device).  DDM_ESTATE when w_emd != 0
- * and no target was set. */
+ * (exact: the Hungarian method).  Writes loss_dev[n_inst] (double, device).
+ * DDM_ESTATE when w_emd != 0 and no target was set. */
 ddm_status ddm_loss(ddm_ctx* ctx, const double* target_hm_dev, double* loss_dev);
 
 /* Target surface point clouds of the EMD term (Eq. emd): points_dev

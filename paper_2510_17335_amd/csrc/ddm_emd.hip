@@ -7,19 +7,15 @@
 // pixel order.
 //
 // Assignment: the injective map phi from the n observed points to the m >= n
-// targets with the least sum of distances, by the auction algorithm with
-// epsilon scaling (Bertsekas).  The problem is made square with m - n dummy
-// bidders that value every target at zero (they take the targets no point
-// needs, so the square optimum is the injective one), which keeps epsilon
-// scaling valid.  In each round every unassigned bidder bids for its best
-// target (largest value - price) by raising that target's price by the gap to
-// its second-best value plus epsilon; each target goes to its highest bidder
-// (ties to the lowest bidder index) and its former owner becomes unassigned.
-// When every bidder is assigned, epsilon shrinks and the round loop restarts
-// with the prices kept.  The final assignment is within m * epsilon_min of the
-// least sum.  One workgroup per instance runs the whole
-// auction; a bound on the number of rounds makes every wave exit, and hitting
-// it sets device error flag 16 (flag 8: more points than targets).
+// targets with the least sum of distances, by the Hungarian method with
+// shortest augmenting paths (the oracle's algorithm): points are added one at
+// a time; each addition searches the targets on costs reduced by row and
+// column potentials, one target per step, until it reaches a free target, then
+// augments along the path and updates the potentials.  One workgroup per
+// instance: a step updates the slack of every target in parallel and takes the
+// least one with a workgroup reduction (ties to the lowest target, as the
+// oracle).  A point's search finishes one target per step, so it ends within
+// m + 1 steps.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -30,7 +26,6 @@ namespace ddm {
 namespace {
 
 constexpr int kEmdThreads = 1024;
-constexpr int64_t kEmdMaxRounds = 200000;    // about a second of rounds
 constexpr unsigned long long kNoOwner = ~0ull;
 
 __device__ __forceinline__ unsigned long long dkey(double x) {
@@ -78,47 +73,50 @@ __global__ void __launch_bounds__(kBlock) k_emd_owner(KCfg c, Bufs b, const void
     atomicMin(&own[q], ((unsigned long long)pid[p] << 32) | (unsigned long long)(p - I.off));
 }
 
-// Best and second-best value over one wave, with the index of the best.
-__device__ __forceinline__ void wave_top2(double& b1, int& j1, double& b2) {
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const double ob1 = __shfl_xor(b1, o, 64), ob2 = __shfl_xor(b2, o, 64);
-    const int oj = __shfl_xor(j1, o, 64);
-    const bool take = ob1 > b1 || (ob1 == b1 && oj < j1);
-    const double lo = take ? b1 : ob1;
-    b2 = fmax(lo, fmax(b2, ob2));
-    if (take) { b1 = ob1; j1 = oj; }
-  }
-}
-
 __device__ __forceinline__ double dist3(const double* a, const double* b) {
   const double d0 = a[0] - b[0], d1 = a[1] - b[1], d2 = a[2] - b[2];
   return sqrt(d0 * d0 + d1 * d1 + d2 * d2);
 }
 
+// Least (value, index) over the workgroup, ties to the lower index.
+__device__ __forceinline__ void block_argmin(double& val, int& idx, double* s_v, int* s_i) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const double ov = __shfl_xor(val, o, 64);
+    const int oi = __shfl_xor(idx, o, 64);
+    if (ov < val || (ov == val && oi < idx)) { val = ov; idx = oi; }
+  }
+  if (lane == 0) { s_v[wid] = val; s_i[wid] = idx; }
+  __syncthreads();
+  val = s_v[0];
+  idx = s_i[0];
+  for (int w = 1; w < kEmdThreads / 64; ++w)
+    if (s_v[w] < val || (s_v[w] == val && s_i[w] < idx)) { val = s_v[w]; idx = s_i[w]; }
+  __syncthreads();
+}
+
 template <typename T>
-__global__ void __launch_bounds__(kEmdThreads) k_emd_auction(KCfg c, Bufs b, const void* state, EmdBufs E, int m,
-                                                             double eps_rel) {
+__global__ void __launch_bounds__(kEmdThreads) k_emd_assign(KCfg c, Bufs b, const void* state, EmdBufs E, int m) {
   const int inst = blockIdx.x;
   const int npix = c.hm_res * c.hm_res;
-  const int64_t base = (int64_t)inst * npix;
+  const int64_t base = (int64_t)inst * npix, base1 = (int64_t)inst * (npix + 1);
   const InstDev& I = b.inst[inst];
   const P<T, 3> st = pv<T, 3>(state, c.ntot);
   double* obs = E.obs + base * 3;
   int* obs_slot = E.obs_slot + base;
   const double* tgt = E.target + base * 3;
-  double* price = E.price + base;
-  int* owner = E.obj_owner + base;
-  int* assign = E.assign + base;
-  unsigned long long* bmax = E.bid_max + base;
-  int* bwin = E.bid_win + base;
-  double* bval = E.bid_val + base;
-  int* bobj = E.bid_obj + base;
+  double* u = E.u + base1;          // row potentials, rows 1..n
+  double* v = E.v + base1;          // column potentials, columns 0..m (0 is the search root)
+  double* slack = E.slack + base1;
+  int* match = E.match + base1;     // row of each column, 0 = free
+  int* from = E.from + base1;       // previous column on the search tree
+  int* done = E.done + base1;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = kEmdThreads / 64;
   __shared__ int s_cnt[kEmdThreads / 64 + 1];
-  __shared__ int s_n, s_unassigned, s_flag;
-  __shared__ double s_red[kEmdThreads / 64];
-  __shared__ double s_lo[kEmdThreads / 64][3], s_hi[kEmdThreads / 64][3];
+  __shared__ int s_n;
+  __shared__ double s_v[kEmdThreads / 64];
+  __shared__ int s_i[kEmdThreads / 64];
 
   // 1. compaction of the observed pixels, in pixel order
   if (threadIdx.x == 0) s_n = 0;
@@ -151,112 +149,73 @@ __global__ void __launch_bounds__(kEmdThreads) k_emd_auction(KCfg c, Bufs b, con
   const int n = s_n;
   if (n == 0 || n > m) {
     if (threadIdx.x == 0) {
-      E.n_obs[inst] = n > m ? 0 : n;
+      E.n_obs[inst] = 0;
       E.emd[inst] = 0.0;
       if (n > m) atomicOr(&b.err->flags, 8u);
     }
     return;
   }
 
-  // 2. epsilon schedule from the extent of the two point sets
-  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
-  for (int i = threadIdx.x; i < n + m; i += kEmdThreads) {
-    const double* q = i < n ? obs + i * 3 : tgt + (i - n) * 3;
-    for (int a = 0; a < 3; ++a) { lo[a] = fmin(lo[a], q[a]); hi[a] = fmax(hi[a], q[a]); }
-  }
-  for (int a = 0; a < 3; ++a) {
-    double l = lo[a], h = hi[a];
-    for (int o = 1; o < 64; o <<= 1) { l = fmin(l, __shfl_xor(l, o, 64)); h = fmax(h, __shfl_xor(h, o, 64)); }
-    if (lane == 0) { s_lo[wid][a] = l; s_hi[wid][a] = h; }
-  }
+  // 2. shortest augmenting paths, one point (row) at a time
+  for (int j = threadIdx.x; j <= m; j += kEmdThreads) { v[j] = 0.0; match[j] = 0; }
+  for (int i = threadIdx.x; i <= n; i += kEmdThreads) u[i] = 0.0;
   __syncthreads();
-  double C = 0.0;
-  for (int a = 0; a < 3; ++a) {
-    double l = 1e300, h = -1e300;
-    for (int w = 0; w < nw; ++w) { l = fmin(l, s_lo[w][a]); h = fmax(h, s_hi[w][a]); }
-    C += (h - l) * (h - l);               // n + m >= 2 points, so h >= l
-  }
-  C = sqrt(C) + 1e-300;                   // the largest distance is at most the diagonal
-  const double eps_min = C * eps_rel;
-  double eps = C * 0.25;
-
-  for (int j = threadIdx.x; j < m; j += kEmdThreads) { price[j] = 0.0; bmax[j] = 0ull; bwin[j] = 0x7FFFFFFF; }
-  if (threadIdx.x == 0) s_flag = 0;
-  __syncthreads();
-  int64_t rounds = 0;
-  for (;;) {
-    // a phase: every point starts unassigned, prices are kept
-    for (int j = threadIdx.x; j < m; j += kEmdThreads) owner[j] = -1;
-    for (int i = threadIdx.x; i < m; i += kEmdThreads) assign[i] = -1;
+  for (int row = 1; row <= n; ++row) {
+    for (int j = threadIdx.x; j <= m; j += kEmdThreads) { slack[j] = __builtin_inf(); done[j] = 0; }
+    if (threadIdx.x == 0) match[0] = row;
     __syncthreads();
-    for (;;) {
-      if (threadIdx.x == 0) s_unassigned = 0;
+    int j0 = 0;
+    for (int step = 0; step <= m; ++step) {
+      if (threadIdx.x == 0) done[j0] = 1;
       __syncthreads();
-      // bids: a wave per unassigned bidder (points i < n, dummies above),
-      // lanes over the targets
-      int mine = 0;
-      for (int i = wid; i < m; i += nw) {
-        if (assign[i] >= 0) continue;      // uniform over the wave
-        ++mine;
-        const double* xi = obs + (i < n ? i : 0) * 3;
-        double b1 = -1e300, b2 = -1e300;
-        int j1 = 0x7FFFFFFF;
-        for (int j = lane; j < m; j += 64) {
-          const double v = (i < n ? -dist3(xi, tgt + j * 3) : 0.0) - price[j];
-          if (v > b1) { b2 = b1; b1 = v; j1 = j; }
-          else if (v > b2) b2 = v;
-        }
-        wave_top2(b1, j1, b2);
-        const double gap = b2 > -1e299 ? b1 - b2 : C;
-        const double bid = price[j1] + gap + eps;
-        if (lane == 0) {
-          bval[i] = bid;
-          bobj[i] = j1;
-          atomicMax(&bmax[j1], dkey(bid));
-        }
+      const int i0 = match[j0];
+      const double* xi = obs + (i0 - 1) * 3;
+      const double ui = u[i0];
+      double best = __builtin_inf();
+      int bj = 0x7FFFFFFF;
+      for (int j = threadIdx.x + 1; j <= m; j += kEmdThreads) {
+        if (done[j]) continue;
+        const double red = dist3(xi, tgt + (j - 1) * 3) - ui - v[j];
+        if (red < slack[j]) { slack[j] = red; from[j] = j0; }
+        if (slack[j] < best) { best = slack[j]; bj = j; }
       }
-      if (lane == 0 && mine) atomicAdd(&s_unassigned, mine);
-      __syncthreads();
-      if (s_unassigned == 0) break;
-      // the highest bid for a target wins, ties to the lowest point index
-      for (int i = threadIdx.x; i < m; i += kEmdThreads)
-        if (assign[i] < 0 && dkey(bval[i]) == bmax[bobj[i]]) atomicMin(&bwin[bobj[i]], i);
-      __syncthreads();
-      for (int j = threadIdx.x; j < m; j += kEmdThreads) {
-        const int w = bwin[j];
-        if (w == 0x7FFFFFFF) continue;
-        const int old = owner[j];
-        if (old >= 0) assign[old] = -1;
-        owner[j] = w;
-        assign[w] = j;
-        price[j] = dval(bmax[j]);
-        bmax[j] = 0ull;
-        bwin[j] = 0x7FFFFFFF;
+      block_argmin(best, bj, s_v, s_i);
+      if (bj > m) break;                  // no finite slack: non-finite positions (uniform over the group)
+      const double delta = best;
+      for (int j = threadIdx.x; j <= m; j += kEmdThreads) {
+        if (done[j]) { u[match[j]] += delta; v[j] -= delta; }
+        else slack[j] -= delta;
       }
       __syncthreads();
-      if (++rounds > kEmdMaxRounds) {
-        if (threadIdx.x == 0) s_flag = 1;
-        break;
-      }
+      j0 = bj;
+      if (match[j0] == 0) break;          // a free target: the path is complete
+    }
+    // every thread takes the outcome before thread 0 rewrites match
+    const bool failed = j0 > m || match[j0] != 0;     // the search ended without a free target
+    __syncthreads();
+    if (failed) {
+      if (threadIdx.x == 0) { atomicOr(&b.err->flags, 8u); E.n_obs[inst] = 0; E.emd[inst] = 0.0; }
+      return;
+    }
+    // augment along the path back to the root
+    if (threadIdx.x == 0) {
+      while (j0) { const int j1 = from[j0]; match[j0] = match[j1]; j0 = j1; }
     }
     __syncthreads();
-    if (s_flag || eps <= eps_min) break;
-    eps = fmax(eps * 0.2, eps_min);
   }
-  if (s_flag) {
-    if (threadIdx.x == 0) { atomicOr(&b.err->flags, 16u); E.n_obs[inst] = 0; E.emd[inst] = 0.0; }
-    return;
-  }
-  // 3. the distance under the assignment
-  double sum = 0.0;
-  for (int i = threadIdx.x; i < n; i += kEmdThreads) sum += dist3(obs + i * 3, tgt + assign[i] * 3);
-  for (int o = 1; o < 64; o <<= 1) sum += __shfl_xor(sum, o, 64);
+
+  // 3. the assignment and the distance under it
+  for (int j = threadIdx.x + 1; j <= m; j += kEmdThreads)
+    if (match[j]) E.assign[base + match[j] - 1] = j - 1;
   __syncthreads();
-  if (lane == 0) s_red[wid] = sum;
+  double sum = 0.0;
+  for (int i = threadIdx.x; i < n; i += kEmdThreads) sum += dist3(obs + i * 3, tgt + E.assign[base + i] * 3);
+  for (int o = 1; o < 64; o <<= 1) sum += __shfl_xor(sum, o, 64);
+  if (lane == 0) s_v[wid] = sum;
   __syncthreads();
   if (threadIdx.x == 0) {
     double s = 0.0;
-    for (int w = 0; w < nw; ++w) s += s_red[w];
+    for (int w = 0; w < nw; ++w) s += s_v[w];
     E.emd[inst] = s;
     E.n_obs[inst] = n;
   }
@@ -299,11 +258,11 @@ void launch_emd(int prec, const KCfg& c, const Bufs& b, int nblk, const void* st
   if (prec == 0) {
     hipLaunchKernelGGL((k_emd_max<float>), dim3(nblk), dim3(kBlock), 0, s, c, b, state, E.top);
     hipLaunchKernelGGL((k_emd_owner<float>), dim3(nblk), dim3(kBlock), 0, s, c, b, state, pid, E.top, E.own);
-    hipLaunchKernelGGL((k_emd_auction<float>), dim3(c.n_inst), dim3(kEmdThreads), 0, s, c, b, state, E, m, 1e-10);
+    hipLaunchKernelGGL((k_emd_assign<float>), dim3(c.n_inst), dim3(kEmdThreads), 0, s, c, b, state, E, m);
   } else {
     hipLaunchKernelGGL((k_emd_max<double>), dim3(nblk), dim3(kBlock), 0, s, c, b, state, E.top);
     hipLaunchKernelGGL((k_emd_owner<double>), dim3(nblk), dim3(kBlock), 0, s, c, b, state, pid, E.top, E.own);
-    hipLaunchKernelGGL((k_emd_auction<double>), dim3(c.n_inst), dim3(kEmdThreads), 0, s, c, b, state, E, m, 1e-10);
+    hipLaunchKernelGGL((k_emd_assign<double>), dim3(c.n_inst), dim3(kEmdThreads), 0, s, c, b, state, E, m);
   }
   hipLaunchKernelGGL(k_emd_add, dim3((c.n_inst + 255) / 256), dim3(256), 0, s, c.n_inst, w_emd, E.emd, loss);
 }

@@ -174,13 +174,10 @@ struct EmdBufs {
   double* obs;                    // observed points, pixel order
   int* obs_slot;                  // owner slot of each observed point (relative to the instance)
   int* n_obs;                     // [n_inst]
-  double* price;                  // auction prices of the targets
-  int* obj_owner;                 // point holding each target
-  int* assign;                    // target of each point
-  unsigned long long* bid_max;
-  int* bid_win;
-  double* bid_val;
-  int* bid_obj;
+  int* assign;                    // target of each observed point
+  // assignment work arrays, [n_inst][hm_res^2 + 1]
+  double *u, *v, *slack;
+  int *match, *from, *done;
   double* emd;                    // [n_inst]
 };
 // loss[inst] += w_emd * EMD of the state (the targets hold m points per instance).

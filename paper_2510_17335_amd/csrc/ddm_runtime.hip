@@ -52,8 +52,8 @@ struct Layout {
   size_t keys0 = 0, keys1 = 0, vals0 = 0, vals1 = 0, hist = 0, sums = 0, tstart = 0, tend = 0, tiles = 0, tcount = 0;
   size_t tslot = 0, staging = 0, gout = 0, amask = 0, alist = 0, acount = 0, seg_alist = 0, seg_acount = 0;
   size_t treat_acc = 0;
-  size_t emd_top = 0, emd_own = 0, emd_target = 0, emd_obs = 0, emd_slot = 0, emd_nobs = 0, emd_price = 0,
-         emd_owner = 0, emd_assign = 0, emd_bmax = 0, emd_bwin = 0, emd_bval = 0, emd_bobj = 0, emd_val = 0;
+  size_t emd_top = 0, emd_own = 0, emd_target = 0, emd_obs = 0, emd_slot = 0, emd_nobs = 0, emd_assign = 0,
+         emd_u = 0, emd_v = 0, emd_slack = 0, emd_match = 0, emd_from = 0, emd_done = 0, emd_val = 0;
   size_t total = 0;
   size_t state_bytes = 0, grid_bytes = 0;
   int64_t ntot = 0, nblk = 0, total_tiles = 0, max_chunks = 0;
@@ -159,13 +159,14 @@ Layout make_layout(const ddm_config& c, int n_inst, const ddm_instance* in) {
     L.emd_obs = cv.take(24 * np);
     L.emd_slot = cv.take(4 * np);
     L.emd_nobs = cv.take(4 * (size_t)n_inst);
-    L.emd_price = cv.take(8 * np);
-    L.emd_owner = cv.take(4 * np);
     L.emd_assign = cv.take(4 * np);
-    L.emd_bmax = cv.take(8 * np);
-    L.emd_bwin = cv.take(4 * np);
-    L.emd_bval = cv.take(8 * np);
-    L.emd_bobj = cv.take(4 * np);
+    const size_t np1 = np + (size_t)n_inst;          // hm_res^2 + 1 per instance
+    L.emd_u = cv.take(8 * np1);
+    L.emd_v = cv.take(8 * np1);
+    L.emd_slack = cv.take(8 * np1);
+    L.emd_match = cv.take(4 * np1);
+    L.emd_from = cv.take(4 * np1);
+    L.emd_done = cv.take(4 * np1);
     L.emd_val = cv.take(8 * (size_t)n_inst);
   }
   L.total = cv.take(0);
@@ -376,13 +377,13 @@ struct ddm_ctx {
     e.obs = at<double>(L.emd_obs);
     e.obs_slot = at<int>(L.emd_slot);
     e.n_obs = at<int>(L.emd_nobs);
-    e.price = at<double>(L.emd_price);
-    e.obj_owner = at<int>(L.emd_owner);
     e.assign = at<int>(L.emd_assign);
-    e.bid_max = at<unsigned long long>(L.emd_bmax);
-    e.bid_win = at<int>(L.emd_bwin);
-    e.bid_val = at<double>(L.emd_bval);
-    e.bid_obj = at<int>(L.emd_bobj);
+    e.u = at<double>(L.emd_u);
+    e.v = at<double>(L.emd_v);
+    e.slack = at<double>(L.emd_slack);
+    e.match = at<int>(L.emd_match);
+    e.from = at<int>(L.emd_from);
+    e.done = at<int>(L.emd_done);
     e.emd = at<double>(L.emd_val);
     return e;
   }
