@@ -176,7 +176,9 @@ def test_gradient_full_skill_f64(ddm, orc, steps):
     e = field_errors(g["state"], r["state"], 3)
     assert all(v < 1e-9 for v in e.values()), e
     assert abs(g["loss"] - r["loss"]) <= 1e-10 * abs(r["loss"])
-    assert np.all(r["grad"][7:] != 0)
+    assert r["grad"][7] != 0                # the displacement acts in phase 1
+    if steps >= 170:
+        assert r["grad"][8] != 0            # the push angle once phase 3 has begun (sub-step 160)
     rel = np.abs(g["grad"] - r["grad"]) / np.maximum(np.abs(r["grad"]), 1e-9 * np.abs(r["grad"]).max())
     assert np.all(rel < 1e-6), rel
 
