@@ -20,6 +20,11 @@ template <> struct Lim<double> {
 };
 
 template <typename T> __device__ __forceinline__ T dsqrt(T x) { return sqrt(x); }
+// a[i] for a run-time i in {0, 1, 2} by selects, so that a loop counter used
+// as the index does not move a register array to scratch memory.
+template <typename T> __device__ __forceinline__ T sel3(const T (&a)[3], int i) {
+  return i == 0 ? a[0] : (i == 1 ? a[1] : a[2]);
+}
 template <typename T> __device__ __forceinline__ T dabs(T x) { return x < T(0) ? -x : x; }
 
 // Reciprocal and reciprocal square root: the hardware approximations

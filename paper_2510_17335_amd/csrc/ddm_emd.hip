@@ -8,12 +8,16 @@
 //
 // Assignment: the injective map phi from the n observed points to the m >= n
 // targets with the least sum of distances, by the Hungarian method with
-// shortest augmenting paths (the oracle's algorithm): points are added one at
-// a time; each addition searches the targets on costs reduced by row and
-// column potentials, one target per step, until it reaches a free target, then
-// augments along the path and updates the potentials.  One workgroup per
-// instance: a step updates the slack of every target in parallel and takes the
-// least one with a workgroup reduction (ties to the lowest target, as the
+// shortest augmenting paths (the oracle's algorithm), started from the row
+// reduction: every point's potential is its distance to the nearest target and
+// points take their nearest targets where free.  Each remaining point searches
+// the targets on costs reduced by row and column potentials, one target per
+// step, until it reaches a free target, then augments along the path and
+// updates the potentials.  The result is a least-sum assignment, the oracle's
+// one whenever the least sum is attained by a single assignment.  One workgroup per
+// instance: a step updates the slack of every target in parallel (each thread
+// keeps its targets' slack, potentials and positions in registers) and takes
+// the least one with a workgroup reduction (ties to the lowest target, as the
 // oracle).  A point's search finishes one target per step, so it ends within
 // m + 1 steps.
 #include <hip/hip_runtime.h>
@@ -26,6 +30,7 @@ namespace ddm {
 namespace {
 
 constexpr int kEmdThreads = 1024;
+constexpr int kEmdCols = kEmdMaxPoints / kEmdThreads;   // targets per thread
 constexpr unsigned long long kNoOwner = ~0ull;
 
 __device__ __forceinline__ unsigned long long dkey(double x) {
@@ -78,7 +83,8 @@ __device__ __forceinline__ double dist3(const double* a, const double* b) {
   return sqrt(d0 * d0 + d1 * d1 + d2 * d2);
 }
 
-// Least (value, index) over the workgroup, ties to the lower index.
+// Least (value, index) over the workgroup, ties to the lower index.  The
+// caller puts a barrier between this call and the next write to s_v / s_i.
 __device__ __forceinline__ void block_argmin(double& val, int& idx, double* s_v, int* s_i) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
@@ -93,30 +99,27 @@ __device__ __forceinline__ void block_argmin(double& val, int& idx, double* s_v,
   idx = s_i[0];
   for (int w = 1; w < kEmdThreads / 64; ++w)
     if (s_v[w] < val || (s_v[w] == val && s_i[w] < idx)) { val = s_v[w]; idx = s_i[w]; }
-  __syncthreads();
 }
 
 template <typename T>
 __global__ void __launch_bounds__(kEmdThreads) k_emd_assign(KCfg c, Bufs b, const void* state, EmdBufs E, int m) {
   const int inst = blockIdx.x;
   const int npix = c.hm_res * c.hm_res;
-  const int64_t base = (int64_t)inst * npix, base1 = (int64_t)inst * (npix + 1);
+  const int64_t base = (int64_t)inst * npix;
   const InstDev& I = b.inst[inst];
   const P<T, 3> st = pv<T, 3>(state, c.ntot);
   double* obs = E.obs + base * 3;
   int* obs_slot = E.obs_slot + base;
   const double* tgt = E.target + base * 3;
-  double* u = E.u + base1;          // row potentials, rows 1..n
-  double* v = E.v + base1;          // column potentials, columns 0..m (0 is the search root)
-  double* slack = E.slack + base1;
-  int* match = E.match + base1;     // row of each column, 0 = free
-  int* from = E.from + base1;       // previous column on the search tree
-  int* done = E.done + base1;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = kEmdThreads / 64;
   __shared__ int s_cnt[kEmdThreads / 64 + 1];
   __shared__ int s_n;
   __shared__ double s_v[kEmdThreads / 64];
   __shared__ int s_i[kEmdThreads / 64];
+  __shared__ double s_u[kEmdMaxPoints + 1];    // row potentials, rows 1..n
+  __shared__ short s_match[kEmdMaxPoints + 1]; // row of each target, 0 = free; target 0 is the search root
+  __shared__ short s_from[kEmdMaxPoints + 1];  // previous target on the search tree
+  __shared__ short s_near[kEmdMaxPoints + 1];  // nearest target of each point, 0 once matched at the start
 
   // 1. compaction of the observed pixels, in pixel order
   if (threadIdx.x == 0) s_n = 0;
@@ -156,42 +159,87 @@ __global__ void __launch_bounds__(kEmdThreads) k_emd_assign(KCfg c, Bufs b, cons
     return;
   }
 
-  // 2. shortest augmenting paths, one point (row) at a time
-  for (int j = threadIdx.x; j <= m; j += kEmdThreads) { v[j] = 0.0; match[j] = 0; }
-  for (int i = threadIdx.x; i <= n; i += kEmdThreads) u[i] = 0.0;
+  // 2. shortest augmenting paths, one point (row) at a time.  Each thread owns
+  // the targets j = tid + 1 + k * kEmdThreads (k < kEmdCols): their slack,
+  // potential, search mark and position stay in its registers; the row
+  // potentials, the matching and the search tree are in LDS.
+  double tj[kEmdCols][3], vj[kEmdCols], sl[kEmdCols];
+  bool dn[kEmdCols];
+#pragma unroll
+  for (int k = 0; k < kEmdCols; ++k) {
+    const int j = threadIdx.x + 1 + k * kEmdThreads;
+    vj[k] = 0.0;
+    for (int a = 0; a < 3; ++a) tj[k][a] = j <= m ? tgt[(j - 1) * 3 + a] : 0.0;
+  }
+  for (int j = threadIdx.x; j <= m; j += kEmdThreads) s_match[j] = 0;
+  // start: u_i = the distance to the nearest target (a wave per point, ties to
+  // the lowest target), which keeps every reduced cost non-negative; a point
+  // whose nearest target is still free takes it (a tight pair), in point order
+  for (int i = wid + 1; i <= n; i += nw) {
+    double best = __builtin_inf();
+    int bj = 0x7FFFFFFF;
+    for (int j = lane + 1; j <= m; j += 64) {
+      const double d = dist3(obs + (i - 1) * 3, tgt + (j - 1) * 3);
+      if (d < best) { best = d; bj = j; }
+    }
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const double ov = __shfl_xor(best, o, 64);
+      const int oj = __shfl_xor(bj, o, 64);
+      if (ov < best || (ov == best && oj < bj)) { best = ov; bj = oj; }
+    }
+    if (lane == 0) { s_u[i] = best; s_near[i] = (short)bj; }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i <= n; ++i) {
+      const int j = s_near[i];
+      if (s_match[j] == 0) { s_match[j] = (short)i; s_near[i] = 0; }   // s_near 0: matched
+    }
+  }
   __syncthreads();
   for (int row = 1; row <= n; ++row) {
-    for (int j = threadIdx.x; j <= m; j += kEmdThreads) { slack[j] = __builtin_inf(); done[j] = 0; }
-    if (threadIdx.x == 0) match[0] = row;
+    if (s_near[row] == 0) continue;        // matched at the start (uniform over the group)
+#pragma unroll
+    for (int k = 0; k < kEmdCols; ++k) { sl[k] = __builtin_inf(); dn[k] = false; }
+    if (threadIdx.x == 0) s_match[0] = (short)row;
     __syncthreads();
     int j0 = 0;
     for (int step = 0; step <= m; ++step) {
-      if (threadIdx.x == 0) done[j0] = 1;
-      __syncthreads();
-      const int i0 = match[j0];
-      const double* xi = obs + (i0 - 1) * 3;
-      const double ui = u[i0];
+      const int i0 = s_match[j0];
+      const double ui = s_u[i0];
+      const double xi[3] = {obs[(i0 - 1) * 3 + 0], obs[(i0 - 1) * 3 + 1], obs[(i0 - 1) * 3 + 2]};
       double best = __builtin_inf();
       int bj = 0x7FFFFFFF;
-      for (int j = threadIdx.x + 1; j <= m; j += kEmdThreads) {
-        if (done[j]) continue;
-        const double red = dist3(xi, tgt + (j - 1) * 3) - ui - v[j];
-        if (red < slack[j]) { slack[j] = red; from[j] = j0; }
-        if (slack[j] < best) { best = slack[j]; bj = j; }
+#pragma unroll
+      for (int k = 0; k < kEmdCols; ++k) {
+        const int j = threadIdx.x + 1 + k * kEmdThreads;
+        if (j > m || dn[k]) continue;
+        const double red = dist3(xi, tj[k]) - ui - vj[k];
+        if (red < sl[k]) { sl[k] = red; s_from[j] = (short)j0; }
+        if (sl[k] < best) { best = sl[k]; bj = j; }
       }
       block_argmin(best, bj, s_v, s_i);
       if (bj > m) break;                  // no finite slack: non-finite positions (uniform over the group)
       const double delta = best;
-      for (int j = threadIdx.x; j <= m; j += kEmdThreads) {
-        if (done[j]) { u[match[j]] += delta; v[j] -= delta; }
-        else slack[j] -= delta;
+      if (threadIdx.x == 0) s_u[s_match[0]] += delta;   // the root column 0
+#pragma unroll
+      for (int k = 0; k < kEmdCols; ++k) {
+        const int j = threadIdx.x + 1 + k * kEmdThreads;
+        if (j > m) continue;
+        if (dn[k]) { s_u[s_match[j]] += delta; vj[k] -= delta; }
+        else sl[k] -= delta;
       }
+      // the reached target joins the search tree
+#pragma unroll
+      for (int k = 0; k < kEmdCols; ++k)
+        if (threadIdx.x + 1 + k * kEmdThreads == bj) dn[k] = true;
       __syncthreads();
       j0 = bj;
-      if (match[j0] == 0) break;          // a free target: the path is complete
+      if (s_match[j0] == 0) break;        // a free target: the path is complete
     }
-    // every thread takes the outcome before thread 0 rewrites match
-    const bool failed = j0 > m || match[j0] != 0;     // the search ended without a free target
+    // every thread takes the outcome before thread 0 rewrites the matching
+    const bool failed = j0 > m || s_match[j0] != 0;   // the search ended without a free target
     __syncthreads();
     if (failed) {
       if (threadIdx.x == 0) { atomicOr(&b.err->flags, 8u); E.n_obs[inst] = 0; E.emd[inst] = 0.0; }
@@ -199,14 +247,14 @@ __global__ void __launch_bounds__(kEmdThreads) k_emd_assign(KCfg c, Bufs b, cons
     }
     // augment along the path back to the root
     if (threadIdx.x == 0) {
-      while (j0) { const int j1 = from[j0]; match[j0] = match[j1]; j0 = j1; }
+      while (j0) { const int j1 = s_from[j0]; s_match[j0] = s_match[j1]; j0 = j1; }
     }
     __syncthreads();
   }
 
   // 3. the assignment and the distance under it
   for (int j = threadIdx.x + 1; j <= m; j += kEmdThreads)
-    if (match[j]) E.assign[base + match[j] - 1] = j - 1;
+    if (s_match[j]) E.assign[base + s_match[j] - 1] = j - 1;
   __syncthreads();
   double sum = 0.0;
   for (int i = threadIdx.x; i < n; i += kEmdThreads) sum += dist3(obs + i * 3, tgt + E.assign[base + i] * 3);

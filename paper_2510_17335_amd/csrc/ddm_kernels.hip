@@ -704,7 +704,9 @@ __device__ __forceinline__ void particle_collision(const KCfg& c, const Bufs& b,
 // G2P (Algorithm 1 lines 10-13): v_p = sum w v_i, C_p = (4/dx^2) sum w v_i r^T,
 // the particle-level collision when enabled, x_p += dt v_p.
 // ---------------------------------------------------------------------------
-template <typename T, int D>
+// PC: with the particle-level collision (a separate instance, so that the
+// plain kernel keeps its register budget).
+template <typename T, int D, bool PC>
 __global__ void __launch_bounds__(kBlock) k_g2p(KCfg c, Bufs b, int step, const void* st_in, void* st_out,
                                                 const T* __restrict__ post) {
   const int inst = b.blk_inst[blockIdx.x];
@@ -751,7 +753,7 @@ __global__ void __launch_bounds__(kBlock) k_g2p(KCfg c, Bufs b, int step, const 
         Cn[a][D - 1] += wl2 * ul[a];
       }
     }
-  if (c.pcontact) particle_collision<T, D>(c, b, inst, step, si, p, vn);
+  if (PC) particle_collision<T, D>(c, b, inst, step, si, p, vn);
   const T dt = T(b.inst[inst].dt);
   T chk = T(0);
   bool ok = true;
@@ -770,13 +772,17 @@ __global__ void __launch_bounds__(kBlock) k_g2p(KCfg c, Bufs b, int step, const 
 
 void launch_g2p(int prec, const KCfg& c, const Bufs& b, int nblk, int step, const void* st_in, void* st_out,
                 const void* post, hipStream_t s) {
+#define DDM_G2P(T, DD, PC) \
+  hipLaunchKernelGGL((k_g2p<T, DD, PC>), dim3(nblk), dim3(kBlock), 0, s, c, b, step, st_in, st_out, (const T*)post)
+  const bool pc = c.pcontact != 0;
   if (prec == 0) {
-    if (c.dim == 3) hipLaunchKernelGGL((k_g2p<float, 3>), dim3(nblk), dim3(kBlock), 0, s, c, b, step, st_in, st_out, (const float*)post);
-    else hipLaunchKernelGGL((k_g2p<float, 2>), dim3(nblk), dim3(kBlock), 0, s, c, b, step, st_in, st_out, (const float*)post);
+    if (c.dim == 3) { if (pc) DDM_G2P(float, 3, true); else DDM_G2P(float, 3, false); }
+    else { if (pc) DDM_G2P(float, 2, true); else DDM_G2P(float, 2, false); }
   } else {
-    if (c.dim == 3) hipLaunchKernelGGL((k_g2p<double, 3>), dim3(nblk), dim3(kBlock), 0, s, c, b, step, st_in, st_out, (const double*)post);
-    else hipLaunchKernelGGL((k_g2p<double, 2>), dim3(nblk), dim3(kBlock), 0, s, c, b, step, st_in, st_out, (const double*)post);
+    if (c.dim == 3) { if (pc) DDM_G2P(double, 3, true); else DDM_G2P(double, 3, false); }
+    else { if (pc) DDM_G2P(double, 2, true); else DDM_G2P(double, 2, false); }
   }
+#undef DDM_G2P
 }
 
 // State export in the initial particle order: column off_i + pid of the
@@ -1174,8 +1180,9 @@ __global__ void __launch_bounds__(kBlock) k_g2p_adj(KCfg c, Bufs b, TileList tl,
         for (int o0 = 0; o0 < 3; ++o0)
 #pragma unroll 1
           for (int o1 = 0; o1 < 3; ++o1) {
-            const T wxy = S.w[0][o0] * S.w[1][o1];
-            const T a0 = dwi[0][o0] * S.w[1][o1], a1 = S.w[0][o0] * dwi[1][o1];
+            const T w0 = sel3(S.w[0], o0), w1 = sel3(S.w[1], o1);
+            const T wxy = w0 * w1;
+            const T a0 = sel3(dwi[0], o0) * w1, a1 = w0 * sel3(dwi[1], o1);
             T t[3] = {T(0), T(0), T(0)}, u[3] = {T(0), T(0), T(0)}, sw = T(0), sd = T(0);
 #pragma unroll
             for (int a = 0; a < D; ++a) t[a] = q[a] + T(o0) * B[a][0] + T(o1) * B[a][1];
@@ -1305,7 +1312,7 @@ __global__ void __launch_bounds__(kBlock) k_pcontact_adj(KCfg c, Bufs b, int ste
           for (int o1 = 0; o1 < 3; ++o1)
 #pragma unroll
             for (int o2 = 0; o2 < 3; ++o2) {
-              const T w = S.w[0][o0] * S.w[1][o1] * S.w[2][o2];
+              const T w = sel3(S.w[0], o0) * sel3(S.w[1], o1) * S.w[2][o2];
               const Node4<T> nd = ld_node(g + node_of<D>(S.base, o0, o1, o2, c.n) * kNodeVals);
 #pragma unroll
               for (int a = 0; a < 3; ++a) u[a] += w * nd.v[a];

@@ -175,11 +175,9 @@ struct EmdBufs {
   int* obs_slot;                  // owner slot of each observed point (relative to the instance)
   int* n_obs;                     // [n_inst]
   int* assign;                    // target of each observed point
-  // assignment work arrays, [n_inst][hm_res^2 + 1]
-  double *u, *v, *slack;
-  int *match, *from, *done;
   double* emd;                    // [n_inst]
 };
+constexpr int kEmdMaxPoints = 4096;   // observed and target points per instance (hm_res <= 64)
 // loss[inst] += w_emd * EMD of the state (the targets hold m points per instance).
 void launch_emd(int prec, const KCfg& c, const Bufs& b, int nblk, const void* state, const uint32_t* pid,
                 const EmdBufs& E, int m, double w_emd, double* loss, hipStream_t s);

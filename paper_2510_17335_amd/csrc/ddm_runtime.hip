@@ -53,7 +53,7 @@ struct Layout {
   size_t tslot = 0, staging = 0, gout = 0, amask = 0, alist = 0, acount = 0, seg_alist = 0, seg_acount = 0;
   size_t treat_acc = 0;
   size_t emd_top = 0, emd_own = 0, emd_target = 0, emd_obs = 0, emd_slot = 0, emd_nobs = 0, emd_assign = 0,
-         emd_u = 0, emd_v = 0, emd_slack = 0, emd_match = 0, emd_from = 0, emd_done = 0, emd_val = 0;
+         emd_val = 0;
   size_t total = 0;
   size_t state_bytes = 0, grid_bytes = 0;
   int64_t ntot = 0, nblk = 0, total_tiles = 0, max_chunks = 0;
@@ -160,13 +160,6 @@ Layout make_layout(const ddm_config& c, int n_inst, const ddm_instance* in) {
     L.emd_slot = cv.take(4 * np);
     L.emd_nobs = cv.take(4 * (size_t)n_inst);
     L.emd_assign = cv.take(4 * np);
-    const size_t np1 = np + (size_t)n_inst;          // hm_res^2 + 1 per instance
-    L.emd_u = cv.take(8 * np1);
-    L.emd_v = cv.take(8 * np1);
-    L.emd_slack = cv.take(8 * np1);
-    L.emd_match = cv.take(4 * np1);
-    L.emd_from = cv.take(4 * np1);
-    L.emd_done = cv.take(4 * np1);
     L.emd_val = cv.take(8 * (size_t)n_inst);
   }
   L.total = cv.take(0);
@@ -378,12 +371,6 @@ struct ddm_ctx {
     e.obs_slot = at<int>(L.emd_slot);
     e.n_obs = at<int>(L.emd_nobs);
     e.assign = at<int>(L.emd_assign);
-    e.u = at<double>(L.emd_u);
-    e.v = at<double>(L.emd_v);
-    e.slack = at<double>(L.emd_slack);
-    e.match = at<int>(L.emd_match);
-    e.from = at<int>(L.emd_from);
-    e.done = at<int>(L.emd_done);
     e.emd = at<double>(L.emd_val);
     return e;
   }
@@ -419,6 +406,8 @@ ddm_status validate(const ddm_config* c, int32_t n_inst, const ddm_instance* in)
   if (c->max_steps < 1) return fail(DDM_EINVAL, "max_steps must be >= 1");
   if (c->sort_every < 0) return fail(DDM_EINVAL, "sort_every must be >= 0");
   if (c->w_emd != 0.0 && c->dim != 3) return fail(DDM_EINVAL, "the EMD term needs dim 3");
+  if (c->w_emd != 0.0 && c->hm_res * c->hm_res > ddm::kEmdMaxPoints)
+    return fail(DDM_EINVAL, "the EMD term needs hm_res^2 <= 4096");
   if (!std::isfinite(c->w_emd)) return fail(DDM_EINVAL, "w_emd must be finite");
   if (c->shovel && !(c->v_lin > 0 && c->v_ang > 0 && c->d_lift > 0 && c->contact_skin >= 0 && c->shovel_mu >= 0))
     return fail(DDM_EINVAL, "shovel speeds, lift, skin and friction must be positive");
