@@ -102,7 +102,7 @@ typedef struct ddm_config {
   int32_t skill_unrounded;  /* 1: the per-action steps of skill phases 1 and 4 divide by the
                                real-valued T_1^float, T_4^float (Sec. III-B, the alternative
                                mapping; the gradient flows through them); 0: by the rounded T_1, T_4 */
-  int32_t particle_contact; /* 1: the collision of Algorithm 1 line 12 after G2P: a particle whose
+  int32_t particle_contact; /* 1: the particle collision of Algorithm 1 after G2P: a particle whose
                                position is within contact_skin of the blade gets the blade's Coulomb
                                contact, one in the wall layers (closer than bound cells to a face)
                                gets zero velocity; 0: grid collision only */
@@ -160,8 +160,8 @@ ddm_status ddm_validate_config(const ddm_config* cfg, int32_t n_inst, const ddm_
                                char* msg, size_t msg_len);
 
 /* The blade pose of every sub-step for one instance's skill (Sec. III-B,
- * Eqs. d1 .. delta_d4, Algorithm 2, spread over n_sub sub-steps as Algorithm 1
- * line 7): pose_out[n_steps][8] = tip xyz, psi, velocity xyz, omega (host
+ * Eqs. d1 .. delta_d4, Algorithm 2, spread over n_sub sub-steps as in
+ * Algorithm 1): pose_out[n_steps][8] = tip xyz, psi, velocity xyz, omega (host
  * memory, build frame, y up), and, if jac_out is not NULL, its Jacobian
  * jac_out[n_steps][8][5] with respect to (depth, angle_deg, push, displace,
  * push_angle_deg).  This is the table the library uploads at ddm_create; host

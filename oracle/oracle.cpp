@@ -15,7 +15,7 @@
 //    * the digging skill: Eqs. d1 .. delta_d4 and Algorithm 2 (Sec. III-B),
 //      optionally with the unrounded T_1^float, T_4^float in the per-action
 //      displacements of phases 1 and 4 (the ablation variant of Sec. III-B);
-//    * the particle-level collision of Algorithm 1 line 12 (optional);
+//    * the particle-level collision of Algorithm 1 (optional);
 //    * the height-map observation and loss (Eq. hm, Sec. III-A "Goal"), and
 //      the earth mover's distance between the surface observation and a
 //      target point cloud (Eq. emd) through an exact linear assignment.
@@ -64,7 +64,7 @@ typedef struct orc_config {
   double hm_origin[2], hm_size, hm_offset;
   double region_depth, m_target, m_ref, w_mass, w_hm;
   double cohesion;
-  int32_t particle_contact, pad1;  // Algorithm 1 line 12 on (1) or off (0)
+  int32_t particle_contact, pad1;  // Algorithm 1's particle collision on (1) or off (0)
   double w_emd;                    // weight of the EMD term (Eq. emd); 0 = off
 } orc_config;
 }
@@ -152,7 +152,7 @@ static void theta_from_physical(const S sk[5], S th[5]) {
   th[4] = sk[4] * (kPi / 180.0) / (kPi / 3.0) - 3.0;
 }
 
-// Agent pose per sub-step (Sec. III-A "Actions"; Algorithm 1 line 7).  Build
+// Agent pose per sub-step (Sec. III-A "Actions"; the agent move of Algorithm 1).  Build
 // frame is y up: paper (x, y, z) maps to (x, z, y), and the paper's rotation
 // about its x axis is a rotation psi about -z through the tip.  Entry n holds
 // the pose used by the grid collision of sub-step n (after the agent moved)
@@ -310,7 +310,7 @@ static void return_map(int d, const S s[3], const S& mu, const S& lam, const S& 
 namespace orc {
 
 // ---------------------------------------------------------------------------
-// Constitutive update of one particle (Algorithm 1 lines 3-4) in double.
+// Constitutive update of one particle (Algorithm 1, SVD and return map) in double.
 // F' = U diag(S_hat) V^T and sigma = U diag(h) U^T.
 // ---------------------------------------------------------------------------
 static void constitutive(int d, const double Ft[3][3], double mu, double lam, double alpha, double kc,
@@ -488,7 +488,7 @@ static S box_sdf(const orc_config& cf, const Frame<S>& f, const S x[3], S nrm[3]
   return phi;
 }
 
-// Coulomb frictional contact against a moving rigid surface (Alg. 1 line 9):
+// Coulomb frictional contact against a moving rigid surface (Algorithm 1, grid collision):
 // relative velocity, separating -> unchanged, sticking inside the friction
 // cone -> zero relative velocity, else slip with the tangential part reduced.
 template <class S>
@@ -619,7 +619,7 @@ struct Sim {
     return true;
   }
 
-  // Lines 1-6: F update, SVD, constitutive model, P2G.
+  // F update, SVD, constitutive model, P2G.
   bool p2g() {
     std::fill(gm.begin(), gm.end(), S(0.0));
     std::fill(gmv.begin(), gmv.end(), S(0.0));
@@ -664,7 +664,7 @@ struct Sim {
     return true;
   }
 
-  // Lines 7-9: agent pose of this sub-step, gravity, collision (shovel, then
+  // Agent pose of this sub-step, gravity, collision (shovel, then
   // sticky container walls of `bound` node layers).
   void grid_update(int step) {
     const bool shovel = c.shovel && d == 3;
@@ -700,7 +700,7 @@ struct Sim {
     }
   }
 
-  // Line 12: the collision of line 9 applied to a particle's velocity at its
+  // Particle collision: the grid collision applied to a particle's velocity at its
   // position x_p (before advection): the shovel's Coulomb contact when x_p is
   // within the contact skin, then the sticky container (zero velocity) when
   // x_p lies in the wall layers (closer than bound cells to a face).
@@ -726,7 +726,7 @@ struct Sim {
     if (wall) for (int a = 0; a < 3; ++a) vn[a] = S(0.0);
   }
 
-  // Lines 10-13: G2P (APIC velocity and affine matrix), particle collision
+  // G2P (APIC velocity and affine matrix), particle collision
   // (when enabled), advection.
   bool g2p(int step) {
     const double Dinv = 4.0 * inv_dx * inv_dx;

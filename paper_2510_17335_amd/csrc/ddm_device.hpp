@@ -485,14 +485,14 @@ __device__ __forceinline__ void sdf_eval(const Blade<T>& b, const T half[3], con
     for (int a = 0; a < 3; ++a) nl[a] = f.o[a] / f.od;
   } else {
     int am = 0;
-    if (f.q[1] > f.q[am]) am = 1;
-    if (f.q[2] > f.q[am]) am = 2;
-    f.phi = f.q[am];
+    if (f.q[1] > f.q[0]) am = 1;
+    if (f.q[2] > sel3(f.q, am)) am = 2;
+    f.phi = sel3(f.q, am);
     f.od = T(0);
     f.inside_axis = am;
+    const T sg = sel3(f.loc, am) >= T(0) ? T(1) : T(-1);
 #pragma unroll
-    for (int a = 0; a < 3; ++a) nl[a] = T(0);
-    nl[am] = f.loc[am] >= T(0) ? T(1) : T(-1);
+    for (int a = 0; a < 3; ++a) nl[a] = a == am ? sg : T(0);
   }
 #pragma unroll
   for (int k = 0; k < 3; ++k) f.n[k] = nl[0] * e[0][k] + nl[1] * e[1][k] + nl[2] * e[2][k];
@@ -507,9 +507,11 @@ __device__ __forceinline__ void sdf_normal_backward(const Blade<T>& b, const T h
   T eb[3][3] = {{T(0), T(0), T(0)}, {T(0), T(0), T(0)}, {T(0), T(0), T(0)}};
   if (f.inside_axis >= 0) {
     const int am = f.inside_axis;
-    const T sg = f.loc[am] >= T(0) ? T(1) : T(-1);
+    const T sg = sel3(f.loc, am) >= T(0) ? T(1) : T(-1);
 #pragma unroll
-    for (int k = 0; k < 3; ++k) eb[am][k] += sg * nb[k];
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) eb[a][k] += a == am ? sg * nb[k] : T(0);
   } else {
     T nl[3], nlb[3], dotb = T(0);
 #pragma unroll

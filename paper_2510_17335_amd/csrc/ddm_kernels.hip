@@ -153,7 +153,7 @@ void launch_init_state(int prec, const KCfg& c, const Bufs& b, int nblk, const v
 }
 
 // ---------------------------------------------------------------------------
-// P2G (Algorithm 1 lines 1-6): F_tmp = (I + dt C) F, i.e. G_tmp = G + dt C (I + G),
+// P2G (Algorithm 1, deformation update to scatter): F_tmp = (I + dt C) F, i.e. G_tmp = G + dt C (I + G),
 // SVD, return map, stress,
 // then the quadratic B-spline scatter of mass and MLS-MPM momentum
 // mv_i += w (m v + A (x_i - x_p)), A = -dt V_p (4/dx^2) tau + m C.
@@ -514,7 +514,7 @@ void launch_p2g(int prec, const KCfg& c, const Bufs& b, const TileList& tl, int 
 }
 
 // ---------------------------------------------------------------------------
-// Grid update (Algorithm 1 lines 7-9): v = mv/m + dt g, shovel contact at the
+// Grid update (Algorithm 1, agent move to grid collision): v = mv/m + dt g, shovel contact at the
 // pose of this sub-step, then sticky walls.  Nodes without mass get v = 0.
 // ---------------------------------------------------------------------------
 template <typename T>
@@ -660,7 +660,7 @@ void launch_grid_update(int prec, const KCfg& c, const Bufs& b, int step, const 
 }
 
 // ---------------------------------------------------------------------------
-// Particle-level collision (Algorithm 1 line 12): the grid's collision rule
+// Particle-level collision (Algorithm 1, after the gather): the grid's collision rule
 // applied to a particle's velocity at its position before advection.  A
 // particle in the wall layers (closer than bound cells to a face; the test is
 // exact on the fixed-point position) stops; otherwise, within the contact skin
@@ -701,7 +701,7 @@ __device__ __forceinline__ void particle_collision(const KCfg& c, const Bufs& b,
 }
 
 // ---------------------------------------------------------------------------
-// G2P (Algorithm 1 lines 10-13): v_p = sum w v_i, C_p = (4/dx^2) sum w v_i r^T,
+// G2P (Algorithm 1, gather to advection): v_p = sum w v_i, C_p = (4/dx^2) sum w v_i r^T,
 // the particle-level collision when enabled, x_p += dt v_p.
 // ---------------------------------------------------------------------------
 // PC: with the particle-level collision (a separate instance, so that the

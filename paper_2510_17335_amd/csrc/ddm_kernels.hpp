@@ -52,7 +52,7 @@ struct DevErr {
 // Configuration passed by value to every kernel.
 struct KCfg {
   int dim, n, nlog2, bound, shovel, hm_res, region_sign, n_inst, max_steps;
-  int pcontact;                      // particle-level collision after G2P (Algorithm 1 line 12)
+  int pcontact;                      // particle-level collision after G2P (Algorithm 1)
   int64_t nodes;                     // nodes per instance
   int64_t ntot;                      // padded particle slots (SoA stride)
   double dx, inv_dx, gravity, skin, mu_b, half[3];

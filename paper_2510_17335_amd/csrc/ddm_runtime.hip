@@ -170,7 +170,7 @@ Layout make_layout(const ddm_config& c, int n_inst, const ddm_instance* in) {
 // Digging skill (Sec. III-B): phase lengths T_i = round(T^float_i) (half away
 // from zero, no derivative), per-action displacements of the four phases, and
 // the per-sub-step blade pose: the action is spread evenly over the n_sub
-// sub-steps and applied before the grid collision (Algorithm 1 line 7).  With
+// sub-steps and applied before the grid collision (the agent move of Algorithm 1).  With
 // skill_unrounded the steps of phases 1 and 4 divide by T^float_1, T^float_4
 // instead (the alternative mapping; its derivative is carried), where max()
 // keeps its first argument on ties.  Build frame: paper (x, y, z) -> (x, z,

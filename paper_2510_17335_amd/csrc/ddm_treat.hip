@@ -207,14 +207,14 @@ __global__ void __launch_bounds__(kBlock) k_treat_particles(KCfg c, Bufs b, int 
 
 // The same over the nodes of the listed active blocks of one grid buffer
 // (every other node holds a zero adjoint): values 0 .. D-1 of a node form
-// variable `var`, value 3 forms variable var + 1 when with_mass is set.  A
+// variable `var`, value 3 forms variable var + 1 when WM is set.  A
 // group of 4^D lanes takes the nodes of one listed block per iteration and a
 // contiguous share of the list; the list holds the blocks of an instance
 // mostly together, so groups flush rarely.
-template <typename T, int D>
+template <typename T, int D, bool WM>
 __global__ void __launch_bounds__(kBlock) k_treat_grid(KCfg c, Bufs b, const uint32_t* __restrict__ list,
                                                        const uint32_t* __restrict__ count, T* __restrict__ g, int var,
-                                                       int with_mass, Treat t, unsigned long long* acc, int what) {
+                                                       Treat t, unsigned long long* acc, int what) {
   constexpr int NPB = D == 3 ? kTile * kTile * kTile : kTile * kTile;
   const int64_t n = *count;
   const int64_t groups = (int64_t)gridDim.x * (kBlock / NPB);
@@ -225,8 +225,9 @@ __global__ void __launch_bounds__(kBlock) k_treat_grid(KCfg c, Bufs b, const uin
   Stat pre[2], post[2];
   T f[2] = {T(1), T(1)};
   int cur = -1;
-  const int nv = with_mass ? 2 : 1;
+  constexpr int nv = WM ? 2 : 1;
   auto flush = [&]() {
+#pragma unroll
     for (int q = 0; q < nv; ++q) {
       if (what & kPre) group_flush<NPB>(pre[q], true, acc + acc_index(cur, var + q, 0));
       if (what & kPost) group_flush<NPB>(post[q], true, acc + acc_index(cur, var + q, 1));
@@ -260,14 +261,16 @@ __global__ void __launch_bounds__(kBlock) k_treat_grid(KCfg c, Bufs b, const uin
       if (ins[u] != cur) {
         if (cur >= 0) flush();
         cur = ins[u];
-        if (what & kApply)
+        if (what & kApply) {
+#pragma unroll
           for (int q = 0; q < nv; ++q) f[q] = T(treat_factor(t, acc + acc_index(cur, var + q, 0)));
+        }
       }
 #pragma unroll
       for (int a = 0; a < 4; ++a) {
         if (a >= D && a < 3) continue;
         const int q = a == 3 ? 1 : 0;
-        if (q == 1 && !with_mass) continue;
+        if (q == 1 && !WM) continue;
         if (what & kPre) pre[q].add((double)val[u][a]);
         if (what & kApply) val[u][a] = treat_value<T>(t, val[u][a], f[q]);
         if (what & kPost) post[q].add((double)val[u][a]);
@@ -348,8 +351,12 @@ void launch_treat_particles(int prec, const KCfg& c, const Bufs& b, int nblk, vo
 void launch_treat_grid(int prec, const KCfg& c, const Bufs& b, const uint32_t* list, const uint32_t* count, void* g,
                        int var, bool with_mass, const Treat& t, bool record, unsigned long long* acc, hipStream_t s) {
   treat_passes(t, record, [&](int what) {
-    DDM_DISPATCH(prec, c.dim, hipLaunchKernelGGL((k_treat_grid<T, D>), dim3(grid_groups(c)), dim3(kBlock), 0, s, c, b,
-                                                 list, count, (T*)g, var, with_mass ? 1 : 0, t, acc, what));
+    if (with_mass)
+      DDM_DISPATCH(prec, c.dim, hipLaunchKernelGGL((k_treat_grid<T, D, true>), dim3(grid_groups(c)), dim3(kBlock), 0, s,
+                                                   c, b, list, count, (T*)g, var, t, acc, what));
+    else
+      DDM_DISPATCH(prec, c.dim, hipLaunchKernelGGL((k_treat_grid<T, D, false>), dim3(grid_groups(c)), dim3(kBlock), 0,
+                                                   s, c, b, list, count, (T*)g, var, t, acc, what));
   });
 }
 

@@ -12,7 +12,6 @@ import pytest
 
 import workloads as W
 
-RNG = np.random.default_rng(99)
 
 
 def _free_flight(orc, w, **over):
@@ -36,15 +35,19 @@ def test_mass_conservation(orc, dim):
         assert np.all(r["grid"][:, 0] >= 0)
 
 
-def _random_motion(w, s, scale=0.2):
+def _random_motion(w, s, scale=0.2, seed=99):
+    """A random affine motion plus per-particle noise, from its own seeded
+    generator so that a test's input does not depend on which tests ran
+    before it in the same process."""
+    rng = np.random.default_rng(seed)
     d = w.dim
     n = s.shape[0]
     x = s[:, :d]
-    v0 = RNG.standard_normal(d) * scale
-    A = RNG.standard_normal((d, d)) * scale
+    v0 = rng.standard_normal(d) * scale
+    A = rng.standard_normal((d, d)) * scale
     s = s.copy()
-    s[:, d:2 * d] = v0 + x @ A.T + 0.05 * RNG.standard_normal((n, d))
-    s[:, 2 * d:2 * d + d * d] = (A + 0.5 * RNG.standard_normal((n, d, d))).reshape(n, -1)
+    s[:, d:2 * d] = v0 + x @ A.T + 0.05 * rng.standard_normal((n, d))
+    s[:, 2 * d:2 * d + d * d] = (A + 0.5 * rng.standard_normal((n, d, d))).reshape(n, -1)
     return s
 
 
@@ -107,8 +110,9 @@ def test_affine_field_reproduction(orc, dim):
     cfg = _free_flight(orc, w)
     s = orc.initial_state(W.bed_positions(w))
     d = w.dim
-    v0 = RNG.standard_normal(d) * 0.1
-    A = RNG.standard_normal((d, d)) * 0.1
+    rng = np.random.default_rng(5 + dim)
+    v0 = rng.standard_normal(d) * 0.1
+    A = rng.standard_normal((d, d)) * 0.1
     x = s[:, :d]
     s[:, d:2 * d] = v0 + x @ A.T
     s[:, 2 * d:2 * d + d * d] = A.reshape(-1)
@@ -123,11 +127,12 @@ def test_affine_field_reproduction(orc, dim):
 def test_p2g_moments_single_particle(orc):
     """Quadratic B-spline identities through the P2G grid of one particle:
     sum w = 1, sum w (x_i - x_p) = 0, sum w (x_i - x_p)(x_i - x_p)^T = dx^2/4 I."""
+    rng = np.random.default_rng(17)
     for dim in (2, 3):
         w = W.tiny(dim)
         cfg = orc.config(w, shovel=False, gravity=0.0, bound=0)
         for trial in range(5):
-            x = RNG.uniform(0.3, 0.7, size=(1, dim))
+            x = rng.uniform(0.3, 0.7, size=(1, dim))
             s = orc.initial_state(x)
             r = orc.rollout(cfg, w.params, s, 1, want_grid=True)
             m = r["grid"][:, 0]
@@ -166,9 +171,11 @@ def test_gradient_matches_central_differences(orc, dim, shovel, step0, full):
     full: the unrounded skill mapping, particle-level collision, and a
     non-zero displacement and push angle away from pi).
 
-    Contact and return-map branches make the loss piecewise smooth, so the
-    difference quotient is taken at several step sizes and must agree at one of
-    them to 1e-6 relative, beyond its own round-off floor 100 eps |L| / h."""
+    Contact and return-map branches make the loss piecewise smooth (a particle
+    that changes return-map case a relative 2.5e-5 away from the point is
+    common), so the difference quotient is taken at step sizes down to 1e-6
+    relative and must agree at one of them to 1e-6 relative, beyond its own
+    round-off floor 100 eps |L| / h."""
     w = W.tiny(dim, shovel=shovel)
     if w.target_seed is None:
         w.target_seed = 11
@@ -186,7 +193,7 @@ def test_gradient_matches_central_differences(orc, dim, shovel, step0, full):
     ks = range(9) if shovel else range(4)
     for k in ks:
         errs = []
-        for rel in (1e-4, 3e-5, 1e-5):
+        for rel in (1e-4, 3e-5, 1e-5, 3e-6, 1e-6):
             fd, h = _fd_grad(orc, cfg, w.params, s, w.steps, target, k, rel, step0)
             floor = 100 * np.finfo(float).eps * abs(L) / h
             errs.append(abs(g[k] - fd) / (1e-6 * abs(fd) + floor))
@@ -207,7 +214,7 @@ def _blade_at(orc, cfg, w, step):
 
 
 def test_particle_collision_postcondition(orc):
-    """Algorithm 1 line 12: after G2P every particle within the contact skin
+    """Particle collision of Algorithm 1: after G2P every particle within the contact skin
     of the blade leaves it no faster than the blade along the normal
     ((v - v_s) . n >= 0), and particles in the wall layers are at rest.  The
     particle position of the test is the one before advection, x' - dt v'."""
@@ -235,7 +242,7 @@ def test_particle_collision_postcondition(orc):
 
 
 def test_particle_collision_changes_only_contacts(orc):
-    """Without a blade near the bed and away from the walls the line-12
+    """Without a blade near the bed and away from the walls the particle-level
     collision does nothing: the rollout is bit-identical with and without it;
     with the blade digging it changes the state."""
     w = W.tiny(3, shovel=False, steps=20)

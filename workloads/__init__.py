@@ -97,7 +97,7 @@ class Workload:
     gravity: float = -9.8
     n_sub: int = 10                     # sub-steps per action
     skill_unrounded: bool = False       # phases 1 and 4 divide by T^float (Sec. III-B)
-    particle_contact: bool = False      # collision of Algorithm 1 line 12
+    particle_contact: bool = False      # particle-level collision of Algorithm 1
     w_emd: float = 0.0                  # weight of the EMD term (Eq. emd) in the loss
     checkpoint_every: int = 0
     target_seed: Optional[int] = None
