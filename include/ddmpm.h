@@ -286,6 +286,17 @@ ddm_status ddm_get_grid(ddm_ctx* ctx, void* grid_dev);
  * double) into caller device memory. */
 ddm_status ddm_get_heightmap(ddm_ctx* ctx, double* hm_dev);
 
+/* The FP32 elementary functions that the FP32 constitutive update and its
+ * adjoint use for ln s = log1p(s^2 - 1)/2, exp(eps') - 1 and the divided
+ * differences of the isotropic adjoint (Sec. III-C, Eq. DP, Appendix B):
+ * y[i] = log1p(x[i]) (fn 0) or expm1(x[i]) (fn 1), computed on the device
+ * exactly as the kernels compute them, for accuracy tests against a
+ * reference.  x_dev, y_dev: device float arrays of n elements, caller-owned;
+ * asynchronous on `stream` (a hipStream_t, NULL: the default stream); needs
+ * no context.  Errors: DDM_EINVAL for fn outside {0, 1}, n < 0, n > 2^40 or a
+ * NULL pointer with n > 0; DDM_EDEVICE for a failed launch. */
+ddm_status ddm_eval_math(int32_t fn, const float* x_dev, float* y_dev, int64_t n, void* stream);
+
 /* Gradient treatments inside the reverse pass (Sec. III-E) and the record of
  * how the adjoints grow backwards in time (Appendix D).
  *   The adjoint of each key variable of a sub-step is treated as one vector

@@ -102,6 +102,7 @@ def lib():
             "ddm_get_grid": (C.c_int, [vp, vp]),
             "ddm_bin_keys": (C.c_int, [vp, vp, vp]),
             "ddm_get_heightmap": (C.c_int, [vp, vp]),
+            "ddm_eval_math": (C.c_int, [i32, vp, vp, i64, vp]),
             "ddm_check": (C.c_int, [vp, C.POINTER(DdmDeviceError)]),
             "ddm_steps_taken": (i64, [vp]),
             "ddm_instance_offset": (i64, [vp, i32]),
@@ -190,6 +191,23 @@ def from_workload(w, max_steps: Optional[int] = None, checkpoint_every: Optional
                          depth=p[4], angle_deg=p[5], push=p[6], dt=w.dt, tip0=w.tip0, displace=p[7],
                          push_angle_deg=p[8])
     return cfg, inst
+
+
+MATH_FUNCTIONS = ("log1p", "expm1")
+
+
+def eval_math(fn: str, x):
+    """The FP32 log1p or expm1 of the device kernels applied to a float32
+    CUDA tensor (ddm_eval_math), on the current stream; returns a new tensor."""
+    import torch
+    if x.dtype != torch.float32 or not x.is_cuda:
+        raise ValueError("x must be a float32 CUDA tensor")
+    x = x.contiguous()
+    y = torch.empty_like(x)
+    stream = torch.cuda.current_stream(x.device)
+    _check(lib().ddm_eval_math(MATH_FUNCTIONS.index(fn), C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()),
+                               x.numel(), C.c_void_p(stream.cuda_stream)))
+    return y
 
 
 def skill_pose_table(cfg: DdmConfig, inst: DdmInstance, n_steps: int):

@@ -36,6 +36,40 @@ template <typename T> __device__ __forceinline__ T frsq(T x);
 template <> __device__ __forceinline__ float frsq(float x) { return __builtin_amdgcn_rsqf(x); }
 template <> __device__ __forceinline__ double frsq(double x) { return 1.0 / sqrt(x); }
 
+// log(1 + x) and exp(x) - 1 for small x.  In float: the hardware base-2
+// logarithm and exponential (v_log_f32, v_exp_f32) with the classical
+// corrections that cancel the rounding of 1 + x and of exp(x):
+//   log1p(x) = log(u) x / (u - 1), u = 1 + x (u == 1: x)   (Goldberg 1991, Thm. 4)
+//   expm1(x) = (u - 1) x / log(u), u = exp(x) (u == 1: x)  (Kahan; Higham 2002, 1.14.1)
+// A few ulp (the GPU accuracy test bounds them), about a quarter of the
+// instructions of the library routines.
+// In double: the library routines.
+template <typename T> __device__ __forceinline__ T flog1p(T x) { return log1p(x); }
+template <> __device__ __forceinline__ float flog1p(float x) {
+  const float u = 1.0f + x;
+  if (u == 1.0f) return x;
+  if (!(u < __builtin_inff())) return u;     // +inf and NaN as they come
+  return __builtin_amdgcn_logf(u) * 0.693147180559945f * (x * __builtin_amdgcn_rcpf(u - 1.0f));
+}
+template <typename T> __device__ __forceinline__ T fexpm1(T x) { return expm1(x); }
+template <> __device__ __forceinline__ float fexpm1(float x) {
+  // x log2(e) as t + e exactly enough (two-part constant, FMA for the
+  // product's rounding), so that exp(x) = 2^t (1 + e ln 2) keeps about an ulp
+  // for large |x| as well; the correction below then handles small x.
+  // Beyond the range of the float result: +inf and -1 (NaN passes through).
+  if (x > 88.8f) return __builtin_inff();
+  if (x < -104.0f) return -1.0f;
+  const float t = x * 1.44269502162933350f;
+  const float e = __builtin_fmaf(x, 1.44269502162933350f, -t) + x * 1.92596303350001e-8f;
+  float u = __builtin_amdgcn_exp2f(t);
+  u = __builtin_fmaf(u, e * 0.693147180559945f, u);
+  if (u == 1.0f) return x;
+  if (!(u < __builtin_inff())) return u;     // overflow (and NaN) as they come
+  const float um1 = u - 1.0f;
+  if (um1 == -1.0f) return -1.0f;
+  return um1 * x * __builtin_amdgcn_rcpf(__builtin_amdgcn_logf(u) * 0.693147180559945f);
+}
+
 // Sigma below this is clamped before the logarithm (ln S must exist).
 template <typename T> __device__ __forceinline__ T sigma_min() { return T(1e-6); }
 
@@ -230,10 +264,10 @@ template <typename T>
 __device__ __forceinline__ void divided(const DP<T>& o, T mu, T ds, T sj, T gj, T& ddg, T& ddh, T& y) {
   const T k = o.cs == 2 ? T(1) : (o.cs == 1 ? T(0) : -o.beta * frcp(o.nrm));
   const T isj = frcp(sj);
-  const T de = log1p(ds * isj);
+  const T de = flog1p(ds * isj);
   const T dl = ds != T(0) ? de * frcp(ds) : isj;        // (eps_i - eps_j) / (s_i - s_j)
   y = k * de;                                            // eps'_i - eps'_j
-  const T em1 = y != T(0) ? expm1(y) * frcp(y) : T(1);
+  const T em1 = y != T(0) ? fexpm1(y) * frcp(y) : T(1);
   ddg = gj * em1 * k * dl;
   ddh = T(2) * mu * k * dl;
 }
@@ -290,7 +324,7 @@ __device__ __forceinline__ void constit_forward(const T G[3][3], T mu, T lam, T 
     } else {
       c.s[i] = dsqrt(T(1) + l);
       c.sm1[i] = l * frcp(T(1) + c.s[i]);
-      c.eps[i] = T(0.5) * log1p(l);
+      c.eps[i] = T(0.5) * flog1p(l);
     }
   }
   // R - I = (G - (S - I)) S^-1
@@ -332,7 +366,7 @@ template <typename T, int D>
 __device__ __forceinline__ void constit_outputs(const Constit<T, D>& c, T Gn[3][3], T tau[3][3]) {
   T em[3], SpmI[3][3];
 #pragma unroll
-  for (int k = 0; k < D; ++k) em[k] = expm1(c.dp.ep[k]);
+  for (int k = 0; k < D; ++k) em[k] = fexpm1(c.dp.ep[k]);
   // both are symmetric: the upper triangle is computed and mirrored
 #pragma unroll
   for (int i = 0; i < D; ++i)

@@ -785,6 +785,19 @@ void launch_g2p(int prec, const KCfg& c, const Bufs& b, int nblk, int step, cons
 #undef DDM_G2P
 }
 
+// The FP32 elementary functions of the constitutive update, one value per
+// thread, for accuracy tests: fn 0 log1p, 1 expm1.
+__global__ void k_eval_math(int fn, const float* __restrict__ x, float* __restrict__ y, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  y[i] = fn == 0 ? flog1p(x[i]) : fexpm1(x[i]);
+}
+
+void launch_eval_math(int fn, const float* x, float* y, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_eval_math, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, fn, x, y, n);
+}
+
 // State export in the initial particle order: column off_i + pid of the
 // output takes the slot holding particle pid of instance i; padding columns
 // are zero.

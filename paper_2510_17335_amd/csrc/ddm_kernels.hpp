@@ -88,6 +88,7 @@ struct Bufs {
 
 // Forward sub-step pieces.  state_* are SoA particle states (stride ntot).
 void launch_fill_zero(void* p, int64_t count, int elem_bytes, hipStream_t s);
+void launch_eval_math(int fn, const float* x, float* y, int64_t n, hipStream_t s);
 void launch_fill_u32(void* p, int64_t words, uint32_t value, hipStream_t s);
 void launch_init_state(int prec, const KCfg& c, const Bufs& b, int nblk, const void* x0, void* state,
                        uint32_t* pid, hipStream_t s);

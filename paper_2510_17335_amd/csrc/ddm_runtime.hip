@@ -1168,6 +1168,15 @@ ddm_status ddm_get_grid(ddm_ctx* x, void* grid_dev) {
   return launch_status();
 }
 
+ddm_status ddm_eval_math(int32_t fn, const float* x_dev, float* y_dev, int64_t n, void* stream) {
+  if (fn != 0 && fn != 1) return fail(DDM_EINVAL, "fn must be 0 (log1p) or 1 (expm1)");
+  if (n < 0) return fail(DDM_EINVAL, "n < 0");
+  if (n > 0 && (!x_dev || !y_dev)) return fail(DDM_EINVAL, "NULL argument");
+  if (n > ((int64_t)1 << 40)) return fail(DDM_EINVAL, "n too large");
+  ddm::launch_eval_math(fn, x_dev, y_dev, n, static_cast<hipStream_t>(stream));
+  return launch_status();
+}
+
 ddm_status ddm_get_heightmap(ddm_ctx* x, double* hm_dev) {
   if (!x || !hm_dev) return fail(DDM_EINVAL, "NULL argument");
   const int npix = x->cfg.dim == 3 ? x->cfg.hm_res * x->cfg.hm_res : x->cfg.hm_res;
