@@ -20,6 +20,11 @@ template <> struct Lim<double> {
 };
 
 template <typename T> __device__ __forceinline__ T dsqrt(T x) { return sqrt(x); }
+// Square root of an argument that is never subnormal (at least 1e-12): the
+// hardware v_sqrt_f32 (about 1 ulp, no rescaling or rounding fix-up) in
+// float, the library routine in double.
+template <typename T> __device__ __forceinline__ T fsqrt(T x) { return sqrt(x); }
+template <> __device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 // a[i] for a run-time i in {0, 1, 2} by selects, so that a loop counter used
 // as the index does not move a register array to scratch memory.
 template <typename T> __device__ __forceinline__ T sel3(const T (&a)[3], int i) {
@@ -101,7 +106,7 @@ __device__ __forceinline__ void jacobi_sym(T a[3][3], T V[3][3], T ev[3]) {
       const T apq = a[p][q];
       if (apq == T(0)) continue;
       const T theta = (a[q][q] - a[p][p]) * frcp(T(2) * apq);
-      const T t = (theta >= T(0) ? T(1) : T(-1)) * frcp(dabs(theta) + dsqrt(theta * theta + T(1)));
+      const T t = (theta >= T(0) ? T(1) : T(-1)) * frcp(dabs(theta) + fsqrt(theta * theta + T(1)));
       const T c = frsq(t * t + T(1));
       const T sn = t * c;
       a[p][p] -= t * apq;
@@ -322,7 +327,7 @@ __device__ __forceinline__ void constit_forward(const T G[3][3], T mu, T lam, T 
       c.s[i] = smin; c.sm1[i] = smin - T(1); c.eps[i] = log(smin);
       c.clamped[i] = true; ++c.nclamp;
     } else {
-      c.s[i] = dsqrt(T(1) + l);
+      c.s[i] = fsqrt(T(1) + l);
       c.sm1[i] = l * frcp(T(1) + c.s[i]);
       c.eps[i] = T(0.5) * flog1p(l);
     }
