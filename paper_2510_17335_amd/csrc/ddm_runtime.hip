@@ -327,6 +327,12 @@ struct ddm_ctx {
   int32_t g_steps = 0;
   size_t g_cur_off = 0, g_spare_off = 0, g_pid_off = 0, g_pid_spare_off = 0;   // buffer roles at the end of the captured pass
   std::vector<char> rec_sorted;   // per recorded step: binned at its start
+  // The rollout runs its last checkpoint segment straight into the segment
+  // buffers that the reverse pass fills by replay: seg_rec is that segment
+  // while the buffers still hold it (-1: they do not), rec_tl_of its
+  // per-step tile lists.
+  int seg_rec = -1;
+  std::vector<int> rec_tl_of;
   // kernel timing
   bool timing = false;
   struct Ev { int group; hipEvent_t a, b; };
@@ -536,6 +542,46 @@ ddm_status forward_step(ddm_ctx* x, int64_t step, const ddm::TileList& tl, const
 bool sort_due(const ddm_ctx* x, int64_t step) {
   const int R = x->cfg.sort_every;
   return x->need_sort || (R > 0 && step % R == 0);
+}
+
+// Runs `len` sub-steps from step k_first into the segment buffers as the
+// reverse pass needs them: the state before step j in slot j (the state after
+// the last in slot len), its grids, stress, binning permutation, tile list and
+// active blocks.  bins[j] says whether step j bins first (from `src` for
+// j = 0, else from the spare state buffer that step j - 1 wrote).  With
+// move_pid the particle ids follow each binning (the forward pass); the
+// replay of the reverse pass leaves them alone.  tl_of[j]: the slot whose
+// tile list step j uses.
+ddm_status run_segment(ddm_ctx* x, int64_t k_first, int len, const void* src, const char* bins, bool move_pid,
+                       std::vector<int>& tl_of) {
+  const Layout& L = x->L;
+  auto slot = [&](int j) { return x->at(L.seg_state + (size_t)j * L.state_bytes); };
+  auto gpre = [&](int j) { return x->at(L.seg_grid + (size_t)(2 * j) * L.grid_bytes); };
+  auto gpost = [&](int j) { return x->at(L.seg_grid + (size_t)(2 * j + 1) * L.grid_bytes); };
+  auto perm = [&](int j) { return x->at<uint32_t>(L.seg_perm + sizeof(uint32_t) * (size_t)L.ntot * j); };
+  auto tau = [&](int j) { return x->at(L.seg_tau + L.tau_bytes * (size_t)j); };
+  void* spare = x->at(x->spare_off);
+  tl_of.assign((size_t)len, 0);
+  int last = 0;
+  for (int j = 0; j < len; ++j) {
+    if (bins[j]) {
+      const ddm_status s = bin_state(x, j == 0 ? src : spare, slot(j), move_pid ? x->pid() : nullptr,
+                                     move_pid ? x->at<uint32_t>(x->pid_spare_off) : nullptr, perm(j),
+                                     x->at<ddm::TileRec>(L.seg_tiles + sizeof(ddm::TileRec) * L.max_chunks * j),
+                                     x->at<uint32_t>(L.seg_tcount + sizeof(uint32_t) * j));
+      if (s != DDM_OK) return s;
+      if (move_pid) std::swap(x->pid_off, x->pid_spare_off);
+      last = j;
+    } else if (j == 0) {
+      DDM_HIP(hipMemcpyAsync(slot(0), src, L.state_bytes, hipMemcpyDeviceToDevice, x->stream));
+    }
+    tl_of[j] = last;
+    const bool next_bins = j + 1 < len && bins[j + 1];
+    const ddm_status s = forward_step(x, k_first + j, x->seg_tiles(last), slot(j), next_bins ? spare : slot(j + 1),
+                                      gpre(j), gpost(j), tau(j), x->seg_alist(j), x->seg_acount(j));
+    if (s != DDM_OK) return s;
+  }
+  return DDM_OK;
 }
 
 // Per-instance constants (Lame constants from (E, nu), alpha_f and the
@@ -773,8 +819,14 @@ ddm_status ddm_rollout(ddm_ctx* x, int32_t n_steps) {
   if (x->steps + n_steps > x->cfg.max_steps) return fail(DDM_EINVAL, "rollout longer than max_steps");
   const int K = x->L.K;
   const int64_t k0 = x->steps;
+  const Layout& L = x->L;
   x->rec_sorted.assign((size_t)n_steps, 0);
-  for (int i = 0; i < n_steps; ++i) {
+  x->seg_rec = -1;
+  // sub-steps before the last checkpoint segment; that one goes straight into
+  // the segment buffers, so the reverse pass does not replay it
+  const int last_seg = (n_steps - 1) / K;
+  const int64_t s_last = (int64_t)last_seg * K;
+  for (int i = 0; i < s_last; ++i) {
     // Checkpoints hold the state before the binning of their step; every
     // checkpointed step re-bins, so a replayed segment needs nothing older.
     if (i % K == 0) {
@@ -793,6 +845,28 @@ ddm_status ddm_rollout(ddm_ctx* x, int32_t n_steps) {
     if (s != DDM_OK) return s;
     ++x->steps;
     x->grid_valid = true;
+  }
+  {
+    const int len = (int)(n_steps - s_last);
+    DDM_HIP(hipMemcpyAsync(x->at(L.ckpt + (size_t)last_seg * L.state_bytes), x->cur(), L.state_bytes,
+                           hipMemcpyDeviceToDevice, x->stream));
+    // the forward's binning decisions: the first step of a segment, then every
+    // sort_every steps
+    const int R = x->cfg.sort_every;
+    for (int j = 0; j < len; ++j) x->rec_sorted[(size_t)(s_last + j)] = j == 0 || (R > 0 && (k0 + s_last + j) % R == 0);
+    const ddm_status s = run_segment(x, k0 + s_last, len, x->cur(), &x->rec_sorted[(size_t)s_last], true, x->rec_tl_of);
+    if (s != DDM_OK) return s;
+    // the final state, its grids and its binning become the current ones
+    DDM_HIP(hipMemcpyAsync(x->cur(), x->at(L.seg_state + (size_t)len * L.state_bytes), L.state_bytes,
+                           hipMemcpyDeviceToDevice, x->stream));
+    DDM_HIP(hipMemcpyAsync(x->at(L.grid_pre), x->at(L.seg_grid + (size_t)(2 * (len - 1)) * L.grid_bytes), L.grid_bytes,
+                           hipMemcpyDeviceToDevice, x->stream));
+    DDM_HIP(hipMemcpyAsync(x->at(L.grid_post), x->at(L.seg_grid + (size_t)(2 * len - 1) * L.grid_bytes), L.grid_bytes,
+                           hipMemcpyDeviceToDevice, x->stream));
+    x->steps += len;
+    x->need_sort = false;
+    x->grid_valid = true;
+    x->seg_rec = last_seg;
   }
   x->recorded = true;
   x->rec_k0 = k0;
@@ -886,30 +960,20 @@ ddm_status ddm_backward(ddm_ctx* x, const double* dloss_dev, double* grad_dev) {
   auto gpost = [&](int j) { return x->at(L.seg_grid + (size_t)(2 * j + 1) * L.grid_bytes); };
   auto perm = [&](int j) { return x->at<uint32_t>(L.seg_perm + sizeof(uint32_t) * (size_t)L.ntot * j); };
   auto tau = [&](int j) { return x->at(L.seg_tau + L.tau_bytes * (size_t)j); };
+  const int have = x->seg_rec;     // the segment the rollout left in the buffers
+  x->seg_rec = -1;                 // the replays below overwrite them
   for (int seg = nseg - 1; seg >= 0; --seg) {
     const int64_t s0 = (int64_t)seg * K;
     const int len = (int)std::min<int64_t>(K, n - s0);
-    // Replay the segment: same binning steps as the recorded forward pass.  A
-    // binning gathers into its slot from the checkpoint (the first step of a
-    // segment always re-bins) or from the spare buffer the previous step wrote.
-    const void* ck = x->at(L.ckpt + (size_t)seg * L.state_bytes);
-    void* spare = x->at(x->spare_off);
-    std::vector<int> tl_of(len, 0);
-    int last = 0;
-    for (int j = 0; j < len; ++j) {
-      if (x->rec_sorted[(size_t)(s0 + j)]) {
-        const ddm_status s = bin_state(x, j == 0 ? ck : spare, slot(j), nullptr, nullptr, perm(j),
-                                       x->at<ddm::TileRec>(L.seg_tiles + sizeof(ddm::TileRec) * L.max_chunks * j),
-                                       x->at<uint32_t>(L.seg_tcount + sizeof(uint32_t) * j));
-        if (s != DDM_OK) return s;
-        last = j;
-      } else if (j == 0) {
-        DDM_HIP(hipMemcpyAsync(slot(0), ck, L.state_bytes, hipMemcpyDeviceToDevice, st));
-      }
-      tl_of[j] = last;
-      const bool next_bins = j + 1 < len && x->rec_sorted[(size_t)(s0 + j + 1)];
-      const ddm_status s = forward_step(x, k0 + s0 + j, x->seg_tiles(last), slot(j), next_bins ? spare : slot(j + 1),
-                                          gpre(j), gpost(j), tau(j), x->seg_alist(j), x->seg_acount(j));
+    // Replay the segment: same binning steps as the recorded forward pass,
+    // the first from the checkpoint.  The last segment is in the buffers
+    // already when the rollout ran it there.
+    std::vector<int> tl_of;
+    if (seg == have) {
+      tl_of = x->rec_tl_of;
+    } else {
+      const ddm_status s = run_segment(x, k0 + s0, len, x->at(L.ckpt + (size_t)seg * L.state_bytes),
+                                       &x->rec_sorted[(size_t)s0], false, tl_of);
       if (s != DDM_OK) return s;
     }
     for (int j = len - 1; j >= 0; --j) {
