@@ -3,7 +3,10 @@
 One step = one full pass of the hot path over the batch: init state, a
 500-sub-step recorded rollout (P2G with the SVD / Drucker-Prager update, grid
 update with shovel contact, G2P, periodic binning, checkpoints), the loss,
-and the reverse pass (segment recompute + adjoint of every sub-step).
+and the reverse pass (segment recompute + adjoint of every sub-step).  The
+rollout records its last checkpoint segments whole, as many as device memory
+holds next to the rest of the workspace, so the reverse pass recomputes only
+the segments before them (--record-segments).
 
 Workload (default): batched system identification, 64 instances on 64^3
 grids with particle counts uniform in [20k, 200k] (seeded), log-uniform E in
@@ -53,6 +56,9 @@ def parse():
     ap.add_argument("--treat", default="none", choices=["none", "clip", "scale", "norm", "record"],
                     help="gradient treatment inside the reverse pass (Sec. III-E) at the paper's thresholds; "
                          "'record' keeps the per-sub-step adjoint statistics without treating")
+    ap.add_argument("--record-segments", type=int, default=0,
+                    help="checkpoint segments the rollout records whole for the reverse pass (fewer replays); "
+                         "0 = as many as fit in device memory with 16 GiB to spare")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB device copy (calibrates the HBM byte counters)")
     return ap.parse_args()
@@ -78,13 +84,11 @@ class Pass:
     """One context over a list of instances and the inputs of a full pass
     (init, recorded rollout, loss, backward: one ddm_pass call)."""
 
-    def __init__(self, ddm, ws, sort_every, precision=None, stream=None):
+    def __init__(self, ddm, ws, sort_every, precision=None, stream=None, record_segments=1):
         self.ws = ws
         self.steps = ws[0].steps
-        K = ws[0].checkpoint_every or 50
-        cfgs = [ddm.from_workload(w, max_steps=self.steps, checkpoint_every=K, precision=precision,
-                                  sort_every=sort_every) for w in ws]
-        self.sim = ddm.Simulator(cfgs[0][0], [c[1] for c in cfgs], stream=stream)
+        cfg, insts = configs(ddm, ws, sort_every, precision, record_segments)
+        self.sim = ddm.Simulator(cfg, insts, stream=stream)
         self.x0 = np.concatenate([W.bed_positions(w) for w in ws])
         self.tg = np.stack([W.target_heightmap(w) for w in ws])
 
@@ -94,6 +98,28 @@ class Pass:
     @property
     def particle_steps(self):
         return sum(w.n_particles for w in self.ws) * self.steps
+
+
+def configs(ddm, ws, sort_every, precision=None, record_segments=1):
+    K = ws[0].checkpoint_every or 50
+    cfgs = [ddm.from_workload(w, max_steps=ws[0].steps, checkpoint_every=K, precision=precision,
+                              sort_every=sort_every) for w in ws]
+    cfg = cfgs[0][0]
+    cfg.record_segments = record_segments
+    return cfg, [c[1] for c in cfgs]
+
+
+def pick_record_segments(ddm, torch, ws, sort_every, spare=16 << 30):
+    """The most checkpoint segments whose whole record fits in free device
+    memory next to the rest of the workspace, with `spare` bytes left over."""
+    free = torch.cuda.mem_get_info()[0]
+    K = ws[0].checkpoint_every or 50
+    best = 1
+    for m in range(1, (ws[0].steps + K - 1) // K + 1):
+        cfg, insts = configs(ddm, ws, sort_every, record_segments=m)
+        if ddm.workspace_query(cfg, insts).workspace_bytes + spare <= free:
+            best = m
+    return best
 
 
 def algorithmic_bytes_p2g(ws, b=4, d=3):
@@ -220,7 +246,9 @@ def main():
 
     # batched: one context on its own stream, binning interval autotuned on the
     # initial state (unless --sort-every is given)
-    bp = Pass(ddm, ws, args.sort_every or 8, stream=torch.cuda.Stream())
+    rseg = args.record_segments or pick_record_segments(ddm, torch, ws, args.sort_every or 8)
+    print(f"# checkpoint segments recorded by the rollout: {rseg}", flush=True)
+    bp = Pass(ddm, ws, args.sort_every or 8, stream=torch.cuda.Stream(), record_segments=rseg)
     treat = treatment_kwargs(args, ws[0].steps)
     if treat:
         bp.sim.set_grad_treatment(**treat)
@@ -278,7 +306,7 @@ def main():
         torch.cuda.empty_cache()
         t_plain = 0.0
         for w in ws:
-            pp = Pass(ddm, [w], 8)
+            pp = Pass(ddm, [w], 8, record_segments=rseg)
             pp.run()
             torch.cuda.synchronize()
             t1 = time.perf_counter()
@@ -323,6 +351,7 @@ def main():
         "config": {"workload": wname, "instances": len(ws), "particles": sum(w.n_particles for w in ws),
                    "sub_steps": ws[0].steps, "checkpoint_every": ws[0].checkpoint_every,
                    "sort_every": tuned or args.sort_every, "sort_every_autotuned": tuned is not None,
+                   "record_segments": rseg,
                    "grad_treatment": args.treat,
                    "peak_mem_gb": round(peak_gb, 2)},
         "graph_value": graph_value,

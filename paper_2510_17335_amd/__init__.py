@@ -38,7 +38,7 @@ class DdmConfig(C.Structure):
         ("hm_offset", C.c_double), ("region_depth", C.c_double), ("m_target", C.c_double), ("m_ref", C.c_double),
         ("w_mass", C.c_double), ("w_hm", C.c_double), ("checkpoint_every", C.c_int32), ("max_steps", C.c_int32),
         ("sort_every", C.c_int32), ("skill_unrounded", C.c_int32), ("particle_contact", C.c_int32),
-        ("pad0", C.c_int32), ("w_emd", C.c_double),
+        ("record_segments", C.c_int32), ("w_emd", C.c_double),
     ]
 
 
@@ -139,7 +139,7 @@ def make_config(dim: int, n_grid: int, precision: str = "f32", *, bound: int = 3
                 region_depth: float = 0.03, m_target: float = 0.192, m_ref: float = 0.384, w_mass: float = 1.0,
                 w_hm: float = 1.0, region_sign: int = -1, checkpoint_every: int = 50,
                 max_steps: int = 1000, sort_every: int = 8, skill_unrounded: bool = False,
-                particle_contact: bool = False, w_emd: float = 0.0) -> DdmConfig:
+                particle_contact: bool = False, w_emd: float = 0.0, record_segments: int = 1) -> DdmConfig:
     c = DdmConfig()
     c.dim, c.n_grid, c.bound = dim, n_grid, bound
     c.precision = DDM_F64 if precision == "f64" else DDM_F32
@@ -156,6 +156,7 @@ def make_config(dim: int, n_grid: int, precision: str = "f32", *, bound: int = 3
     c.checkpoint_every, c.max_steps, c.sort_every = checkpoint_every, max_steps, sort_every
     c.skill_unrounded, c.particle_contact = int(bool(skill_unrounded)), int(bool(particle_contact))
     c.w_emd = float(w_emd)
+    c.record_segments = int(record_segments)
     return c
 
 

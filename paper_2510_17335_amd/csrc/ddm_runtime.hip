@@ -59,6 +59,8 @@ struct Layout {
   int64_t ntot = 0, nblk = 0, total_tiles = 0, max_chunks = 0;
   size_t win_bytes = 0;               // one staged window
   int n_ckpt = 0, K = 1, rows = 0, esz = 4, nwg = 1;
+  int M = 1;                          // sets of segment buffers
+  size_t seg_set = 0;                 // bytes of one set (sets follow each other)
   uint32_t max_key = 0;
 };
 
@@ -111,13 +113,22 @@ Layout make_layout(const ddm_config& c, int n_inst, const ddm_instance* in) {
   L.grid_pre = cv.take(L.grid_bytes);
   L.grid_post = cv.take(L.grid_bytes);
   L.ckpt = cv.take(L.state_bytes * L.n_ckpt);
+  // Segment buffers: the reverse pass's record of one checkpoint segment
+  // (per sub-step the state, both grids, the stress, the binning permutation,
+  // the tile list and the active blocks), M sets back to back.
+  L.tau_bytes = (size_t)(D * (D + 1) / 2) * ntot * b;
+  L.M = std::max(1, std::min<int>(c.record_segments, (c.max_steps + L.K - 1) / L.K));
+  const size_t seg0 = cv.take(0);
   L.seg_state = cv.take(L.state_bytes * (L.K + 1));
   L.seg_grid = cv.take(L.grid_bytes * 2 * L.K);
-  L.tau_bytes = (size_t)(D * (D + 1) / 2) * ntot * b;
   L.seg_tau = cv.take(L.tau_bytes * L.K);
   L.seg_perm = cv.take(sizeof(uint32_t) * ntot * L.K);
   L.seg_tiles = cv.take(sizeof(ddm::TileRec) * L.max_chunks * L.K);
   L.seg_tcount = cv.take(sizeof(uint32_t) * L.K);
+  L.seg_alist = cv.take(sizeof(uint32_t) * L.total_tiles * L.K);
+  L.seg_acount = cv.take(sizeof(uint32_t) * L.K);
+  L.seg_set = cv.take(0) - seg0;
+  cv.take(L.seg_set * (L.M - 1));
   L.adj0 = cv.take(L.state_bytes);
   L.adj1 = cv.take(L.state_bytes);
   L.gvb = cv.take(L.grid_bytes);
@@ -149,8 +160,6 @@ Layout make_layout(const ddm_config& c, int n_inst, const ddm_instance* in) {
   L.amask = cv.take(sizeof(uint32_t) * L.total_tiles);
   L.alist = cv.take(sizeof(uint32_t) * L.total_tiles);
   L.acount = cv.take(sizeof(uint32_t));
-  L.seg_alist = cv.take(sizeof(uint32_t) * L.total_tiles * L.K);
-  L.seg_acount = cv.take(sizeof(uint32_t) * L.K);
   if (D == 3 && c.w_emd != 0.0) {
     const size_t np = (size_t)n_inst * c.hm_res * c.hm_res;
     L.emd_top = cv.take(8 * np);
@@ -327,12 +336,13 @@ struct ddm_ctx {
   int32_t g_steps = 0;
   size_t g_cur_off = 0, g_spare_off = 0, g_pid_off = 0, g_pid_spare_off = 0;   // buffer roles at the end of the captured pass
   std::vector<char> rec_sorted;   // per recorded step: binned at its start
-  // The rollout runs its last checkpoint segment straight into the segment
-  // buffers that the reverse pass fills by replay: seg_rec is that segment
-  // while the buffers still hold it (-1: they do not), rec_tl_of its
-  // per-step tile lists.
-  int seg_rec = -1;
-  std::vector<int> rec_tl_of;
+  // The rollout runs its last checkpoint segments (as many as there are sets
+  // of segment buffers) straight into those buffers, the last segment into
+  // set 0, the one before into set 1, ...; the reverse pass replays only the
+  // others.  rec_first: the first segment so recorded while the buffers still
+  // hold them (INT32_MAX: none); rec_tl_of[set]: per-step tile lists.
+  int rec_first = INT32_MAX;
+  std::vector<std::vector<int>> rec_tl_of;
   // kernel timing
   bool timing = false;
   struct Ev { int group; hipEvent_t a, b; };
@@ -350,16 +360,26 @@ struct ddm_ctx {
   void* cur() const { return at(cur_off); }
   uint32_t* pid() const { return at<uint32_t>(pid_off); }
   ddm::TileList tiles() const { return ddm::TileList{at<const ddm::TileRec>(L.tiles), at<const uint32_t>(L.tcount)}; }
-  ddm::TileList seg_tiles(int j) const {
-    return ddm::TileList{at<const ddm::TileRec>(L.seg_tiles + sizeof(ddm::TileRec) * L.max_chunks * j),
-                         at<const uint32_t>(L.seg_tcount + sizeof(uint32_t) * j)};
+  // buffers of sub-step j of segment-buffer set m
+  size_t sb(int m) const { return (size_t)m * L.seg_set; }
+  void* slot(int m, int j) const { return at(sb(m) + L.seg_state + (size_t)j * L.state_bytes); }
+  void* gpre(int m, int j) const { return at(sb(m) + L.seg_grid + (size_t)(2 * j) * L.grid_bytes); }
+  void* gpost(int m, int j) const { return at(sb(m) + L.seg_grid + (size_t)(2 * j + 1) * L.grid_bytes); }
+  void* tau(int m, int j) const { return at(sb(m) + L.seg_tau + L.tau_bytes * (size_t)j); }
+  uint32_t* perm(int m, int j) const { return at<uint32_t>(sb(m) + L.seg_perm + sizeof(uint32_t) * (size_t)L.ntot * j); }
+  ddm::TileRec* seg_tile_recs(int m, int j) const {
+    return at<ddm::TileRec>(sb(m) + L.seg_tiles + sizeof(ddm::TileRec) * L.max_chunks * j);
   }
+  uint32_t* seg_tcount(int m, int j) const { return at<uint32_t>(sb(m) + L.seg_tcount + sizeof(uint32_t) * j); }
+  ddm::TileList seg_tiles(int m, int j) const { return ddm::TileList{seg_tile_recs(m, j), seg_tcount(m, j)}; }
   ddm::Staging staging() const { return ddm::Staging{at<void>(L.staging), at<const uint32_t>(L.tslot)}; }
   ddm::ActiveSet active() const {
     return ddm::ActiveSet{at<uint32_t>(L.amask), at<uint32_t>(L.alist), at<uint32_t>(L.acount)};
   }
-  uint32_t* seg_alist(int j) const { return at<uint32_t>(L.seg_alist + sizeof(uint32_t) * L.total_tiles * j); }
-  uint32_t* seg_acount(int j) const { return at<uint32_t>(L.seg_acount + sizeof(uint32_t) * j); }
+  uint32_t* seg_alist(int m, int j) const {
+    return at<uint32_t>(sb(m) + L.seg_alist + sizeof(uint32_t) * L.total_tiles * j);
+  }
+  uint32_t* seg_acount(int m, int j) const { return at<uint32_t>(sb(m) + L.seg_acount + sizeof(uint32_t) * j); }
   ddm::Bufs bufs() const {
     ddm::Bufs b;
     b.inst = at<const ddm::InstDev>(L.inst);
@@ -409,6 +429,7 @@ ddm_status validate(const ddm_config* c, int32_t n_inst, const ddm_instance* in)
   if (c->hm_res < 1 || c->hm_res > 4096) return fail(DDM_EINVAL, "hm_res out of [1, 4096]");
   if (!(c->hm_size > 0)) return fail(DDM_EINVAL, "hm_size must be > 0");
   if (c->checkpoint_every < 1) return fail(DDM_EINVAL, "checkpoint_every must be >= 1");
+  if (c->record_segments < 0) return fail(DDM_EINVAL, "record_segments must be >= 0");
   if (c->max_steps < 1) return fail(DDM_EINVAL, "max_steps must be >= 1");
   if (c->sort_every < 0) return fail(DDM_EINVAL, "sort_every must be >= 0");
   if (c->w_emd != 0.0 && c->dim != 3) return fail(DDM_EINVAL, "the EMD term needs dim 3");
@@ -552,33 +573,27 @@ bool sort_due(const ddm_ctx* x, int64_t step) {
 // move_pid the particle ids follow each binning (the forward pass); the
 // replay of the reverse pass leaves them alone.  tl_of[j]: the slot whose
 // tile list step j uses.
-ddm_status run_segment(ddm_ctx* x, int64_t k_first, int len, const void* src, const char* bins, bool move_pid,
-                       std::vector<int>& tl_of) {
-  const Layout& L = x->L;
-  auto slot = [&](int j) { return x->at(L.seg_state + (size_t)j * L.state_bytes); };
-  auto gpre = [&](int j) { return x->at(L.seg_grid + (size_t)(2 * j) * L.grid_bytes); };
-  auto gpost = [&](int j) { return x->at(L.seg_grid + (size_t)(2 * j + 1) * L.grid_bytes); };
-  auto perm = [&](int j) { return x->at<uint32_t>(L.seg_perm + sizeof(uint32_t) * (size_t)L.ntot * j); };
-  auto tau = [&](int j) { return x->at(L.seg_tau + L.tau_bytes * (size_t)j); };
+ddm_status run_segment(ddm_ctx* x, int m, int64_t k_first, int len, const void* src, const char* bins,
+                       bool move_pid, std::vector<int>& tl_of) {
   void* spare = x->at(x->spare_off);
   tl_of.assign((size_t)len, 0);
   int last = 0;
   for (int j = 0; j < len; ++j) {
     if (bins[j]) {
-      const ddm_status s = bin_state(x, j == 0 ? src : spare, slot(j), move_pid ? x->pid() : nullptr,
-                                     move_pid ? x->at<uint32_t>(x->pid_spare_off) : nullptr, perm(j),
-                                     x->at<ddm::TileRec>(L.seg_tiles + sizeof(ddm::TileRec) * L.max_chunks * j),
-                                     x->at<uint32_t>(L.seg_tcount + sizeof(uint32_t) * j));
+      const ddm_status s = bin_state(x, j == 0 ? src : spare, x->slot(m, j), move_pid ? x->pid() : nullptr,
+                                     move_pid ? x->at<uint32_t>(x->pid_spare_off) : nullptr, x->perm(m, j),
+                                     x->seg_tile_recs(m, j), x->seg_tcount(m, j));
       if (s != DDM_OK) return s;
       if (move_pid) std::swap(x->pid_off, x->pid_spare_off);
       last = j;
     } else if (j == 0) {
-      DDM_HIP(hipMemcpyAsync(slot(0), src, L.state_bytes, hipMemcpyDeviceToDevice, x->stream));
+      DDM_HIP(hipMemcpyAsync(x->slot(m, 0), src, x->L.state_bytes, hipMemcpyDeviceToDevice, x->stream));
     }
     tl_of[j] = last;
     const bool next_bins = j + 1 < len && bins[j + 1];
-    const ddm_status s = forward_step(x, k_first + j, x->seg_tiles(last), slot(j), next_bins ? spare : slot(j + 1),
-                                      gpre(j), gpost(j), tau(j), x->seg_alist(j), x->seg_acount(j));
+    const ddm_status s = forward_step(x, k_first + j, x->seg_tiles(m, last), x->slot(m, j),
+                                      next_bins ? spare : x->slot(m, j + 1), x->gpre(m, j), x->gpost(m, j),
+                                      x->tau(m, j), x->seg_alist(m, j), x->seg_acount(m, j));
     if (s != DDM_OK) return s;
   }
   return DDM_OK;
@@ -821,12 +836,13 @@ ddm_status ddm_rollout(ddm_ctx* x, int32_t n_steps) {
   const int64_t k0 = x->steps;
   const Layout& L = x->L;
   x->rec_sorted.assign((size_t)n_steps, 0);
-  x->seg_rec = -1;
-  // sub-steps before the last checkpoint segment; that one goes straight into
-  // the segment buffers, so the reverse pass does not replay it
-  const int last_seg = (n_steps - 1) / K;
-  const int64_t s_last = (int64_t)last_seg * K;
-  for (int i = 0; i < s_last; ++i) {
+  x->rec_first = INT32_MAX;
+  // sub-steps before the recorded checkpoint segments; those go straight into
+  // the segment buffers, so the reverse pass does not replay them
+  const int nseg = (n_steps + K - 1) / K;
+  const int first_rec = nseg - std::min(L.M, nseg);
+  const int64_t s_rec = (int64_t)first_rec * K;
+  for (int i = 0; i < s_rec; ++i) {
     // Checkpoints hold the state before the binning of their step; every
     // checkpointed step re-bins, so a replayed segment needs nothing older.
     if (i % K == 0) {
@@ -846,28 +862,32 @@ ddm_status ddm_rollout(ddm_ctx* x, int32_t n_steps) {
     ++x->steps;
     x->grid_valid = true;
   }
-  {
-    const int len = (int)(n_steps - s_last);
-    DDM_HIP(hipMemcpyAsync(x->at(L.ckpt + (size_t)last_seg * L.state_bytes), x->cur(), L.state_bytes,
-                           hipMemcpyDeviceToDevice, x->stream));
+  x->rec_tl_of.assign((size_t)L.M, std::vector<int>());
+  const void* src = x->cur();
+  int m = 0, len = 0;
+  for (int seg = first_rec; seg < nseg; ++seg) {
+    const int64_t s0 = (int64_t)seg * K;
+    m = nseg - 1 - seg;
+    len = (int)std::min<int64_t>(K, n_steps - s0);
+    // the checkpoint, for a reverse pass that has to replay the segment after all
+    DDM_HIP(hipMemcpyAsync(x->at(L.ckpt + (size_t)seg * L.state_bytes), src, L.state_bytes, hipMemcpyDeviceToDevice,
+                           x->stream));
     // the forward's binning decisions: the first step of a segment, then every
     // sort_every steps
     const int R = x->cfg.sort_every;
-    for (int j = 0; j < len; ++j) x->rec_sorted[(size_t)(s_last + j)] = j == 0 || (R > 0 && (k0 + s_last + j) % R == 0);
-    const ddm_status s = run_segment(x, k0 + s_last, len, x->cur(), &x->rec_sorted[(size_t)s_last], true, x->rec_tl_of);
+    for (int j = 0; j < len; ++j) x->rec_sorted[(size_t)(s0 + j)] = j == 0 || (R > 0 && (k0 + s0 + j) % R == 0);
+    const ddm_status s = run_segment(x, m, k0 + s0, len, src, &x->rec_sorted[(size_t)s0], true, x->rec_tl_of[(size_t)m]);
     if (s != DDM_OK) return s;
-    // the final state, its grids and its binning become the current ones
-    DDM_HIP(hipMemcpyAsync(x->cur(), x->at(L.seg_state + (size_t)len * L.state_bytes), L.state_bytes,
-                           hipMemcpyDeviceToDevice, x->stream));
-    DDM_HIP(hipMemcpyAsync(x->at(L.grid_pre), x->at(L.seg_grid + (size_t)(2 * (len - 1)) * L.grid_bytes), L.grid_bytes,
-                           hipMemcpyDeviceToDevice, x->stream));
-    DDM_HIP(hipMemcpyAsync(x->at(L.grid_post), x->at(L.seg_grid + (size_t)(2 * len - 1) * L.grid_bytes), L.grid_bytes,
-                           hipMemcpyDeviceToDevice, x->stream));
+    src = x->slot(m, len);
     x->steps += len;
-    x->need_sort = false;
-    x->grid_valid = true;
-    x->seg_rec = last_seg;
   }
+  // the final state, its grids and its binning become the current ones
+  DDM_HIP(hipMemcpyAsync(x->cur(), src, L.state_bytes, hipMemcpyDeviceToDevice, x->stream));
+  DDM_HIP(hipMemcpyAsync(x->at(L.grid_pre), x->gpre(m, len - 1), L.grid_bytes, hipMemcpyDeviceToDevice, x->stream));
+  DDM_HIP(hipMemcpyAsync(x->at(L.grid_post), x->gpost(m, len - 1), L.grid_bytes, hipMemcpyDeviceToDevice, x->stream));
+  x->need_sort = false;
+  x->grid_valid = true;
+  x->rec_first = first_rec;
   x->recorded = true;
   x->rec_k0 = k0;
   x->rec_n = n_steps;
@@ -955,29 +975,31 @@ ddm_status ddm_backward(ddm_ctx* x, const double* dloss_dev, double* grad_dev) {
   const int K = L.K;
   const int64_t n = x->rec_n, k0 = x->rec_k0;
   const int nseg = (int)((n + K - 1) / K);
-  auto slot = [&](int j) { return x->at(L.seg_state + (size_t)j * L.state_bytes); };
-  auto gpre = [&](int j) { return x->at(L.seg_grid + (size_t)(2 * j) * L.grid_bytes); };
-  auto gpost = [&](int j) { return x->at(L.seg_grid + (size_t)(2 * j + 1) * L.grid_bytes); };
-  auto perm = [&](int j) { return x->at<uint32_t>(L.seg_perm + sizeof(uint32_t) * (size_t)L.ntot * j); };
-  auto tau = [&](int j) { return x->at(L.seg_tau + L.tau_bytes * (size_t)j); };
-  const int have = x->seg_rec;     // the segment the rollout left in the buffers
-  x->seg_rec = -1;                 // the replays below overwrite them
+  const int have = x->rec_first;   // segments the rollout left in the buffers
+  x->rec_first = INT32_MAX;        // the replays below overwrite them
   for (int seg = nseg - 1; seg >= 0; --seg) {
     const int64_t s0 = (int64_t)seg * K;
     const int len = (int)std::min<int64_t>(K, n - s0);
-    // Replay the segment: same binning steps as the recorded forward pass,
-    // the first from the checkpoint.  The last segment is in the buffers
-    // already when the rollout ran it there.
+    // A segment the rollout recorded is in buffer set nseg - 1 - seg.  The
+    // others are replayed into set 0 (whose segment, the last, is done by
+    // then): same binning steps as the recorded forward pass, the first from
+    // the checkpoint.
+    const int m = seg >= have ? nseg - 1 - seg : 0;
     std::vector<int> tl_of;
-    if (seg == have) {
-      tl_of = x->rec_tl_of;
+    if (seg >= have) {
+      tl_of = x->rec_tl_of[(size_t)m];
     } else {
-      const ddm_status s = run_segment(x, k0 + s0, len, x->at(L.ckpt + (size_t)seg * L.state_bytes),
+      const ddm_status s = run_segment(x, 0, k0 + s0, len, x->at(L.ckpt + (size_t)seg * L.state_bytes),
                                        &x->rec_sorted[(size_t)s0], false, tl_of);
       if (s != DDM_OK) return s;
     }
+    auto slot = [&](int j) { return x->slot(m, j); };
+    auto gpre = [&](int j) { return x->gpre(m, j); };
+    auto gpost = [&](int j) { return x->gpost(m, j); };
+    auto perm = [&](int j) { return x->perm(m, j); };
+    auto tau = [&](int j) { return x->tau(m, j); };
     for (int j = len - 1; j >= 0; --j) {
-      const ddm::TileList tl = x->seg_tiles(tl_of[j]);
+      const ddm::TileList tl = x->seg_tiles(m, tl_of[j]);
       const int64_t k = k0 + s0 + j;
       const bool rec = x->stats_dev && k < x->stats_steps;
       const bool treat = rec || x->treat.mode != ddm::kTreatNone;
@@ -992,13 +1014,13 @@ ddm_status ddm_backward(ddm_ctx* x, const double* dloss_dev, double* grad_dev) {
       }
       if (treat) {
         Timed t(x, 9);
-        treat_vectors(x, rec, TreatTarget{true, x->at(L.gvb), x->seg_alist(j), x->seg_acount(j), 3, false});
+        treat_vectors(x, rec, TreatTarget{true, x->at(L.gvb), x->seg_alist(m, j), x->seg_acount(m, j), 3, false});
       }
-      { Timed t(x, 5); ddm::launch_grid_adj(x->prec, x->kc, b, (int)k, x->seg_alist(j), x->seg_acount(j),
+      { Timed t(x, 5); ddm::launch_grid_adj(x->prec, x->kc, b, (int)k, x->seg_alist(m, j), x->seg_acount(m, j),
                                             gpre(j), x->at(L.gvb), x->at(L.gb), x->at<double>(L.pose_bar), st); }
       if (treat) {
         Timed t(x, 9);
-        treat_vectors(x, rec, TreatTarget{true, x->at(L.gb), x->seg_alist(j), x->seg_acount(j), 4, true});
+        treat_vectors(x, rec, TreatTarget{true, x->at(L.gb), x->seg_alist(m, j), x->seg_acount(m, j), 4, true});
       }
       { Timed t(x, 6); ddm::launch_p2g_adj(x->prec, x->kc, b, (int)L.nblk, slot(j), tau(j), x->at(L.gb), adj[cur], adj[1 - cur],
                                            x->at<double>(L.pacc), st); }
@@ -1138,6 +1160,7 @@ ddm_status ddm_autotune(ddm_ctx* x, const char* cache_path, int32_t* sort_every_
     const int cand[] = {2, 4, 8, 16, 32};
     void* snap = x->at(L.seg_state);
     void* pid_snap = x->at(L.seg_perm);
+    x->rec_first = INT32_MAX;      // the snapshot overwrites recorded segments
     DDM_HIP(hipMemcpyAsync(snap, x->cur(), L.state_bytes, hipMemcpyDeviceToDevice, x->stream));
     DDM_HIP(hipMemcpyAsync(pid_snap, x->pid(), sizeof(uint32_t) * L.ntot, hipMemcpyDeviceToDevice, x->stream));
     const int saved_R = x->cfg.sort_every;

@@ -1,0 +1,91 @@
+"""Recording the last checkpoint segments during the rollout
+(ddm_config.record_segments) changes where the reverse pass finds the data of
+each sub-step, not what it computes: final states, losses and gradients agree
+with 1, 2 and all segments recorded as closely as two runs of one setting do
+(the order of atomic sums varies), also for a second reverse pass after the
+first, which replays every segment from its checkpoint; the
+workspace grows by one segment set per recorded segment, up to the segments
+of a max_steps rollout."""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+STEPS, K = 60, 16          # four segments, the last one of 12 sub-steps
+
+
+def _log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ddm():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2510_17335_amd as m
+    return m
+
+
+def _run(ddm, record, precision="f32", passes=1):
+    w = W.dig_3d(steps=STEPS)
+    cfg, inst = ddm.from_workload(w, max_steps=STEPS, checkpoint_every=K, precision=precision)
+    cfg.record_segments = record
+    sim = ddm.Simulator(cfg, [inst])
+    x0, tg = W.bed_positions(w), W.target_heightmap(w).reshape(1, -1)
+    sim.init_state(x0)
+    sim.rollout(STEPS)
+    state = sim.packed_state(0)            # decoded: x, v, C, F per particle
+    loss = sim.loss(tg).cpu().numpy()
+    grads = [sim.backward().cpu().numpy() for _ in range(passes)]
+    assert sim.check().flags & 1 == 0
+    return int(sim.sizes.workspace_bytes), state, loss, grads
+
+
+def _close(a, b, what, rtol=1e-6):
+    rel = float(np.max(np.abs(a - b) / np.maximum(np.abs(b), 1e-30)))
+    _log(f"{what}: max relative difference {rel:.3e}")
+    assert rel <= rtol, (what, a, b)
+
+
+def _same_state(a, b, what, rtol):
+    """Per state component (x, v, C, F entries) the largest difference
+    relative to the component's largest magnitude."""
+    rel = np.max(np.abs(a - b), axis=0) / np.maximum(np.max(np.abs(b), axis=0), 1e-30)
+    _log(f"{what}: largest relative state difference {float(rel.max()):.3e} (component {int(rel.argmax())})")
+    assert float(rel.max()) <= rtol, what
+
+
+def test_recorded_segments_give_the_same_pass(ddm):
+    _log(f"case record_segments 1/2/4/9 dig3d {STEPS} steps K={K} f32")
+    ws1, s1, l1, g1 = _run(ddm, 1, passes=2)
+    _close(g1[1], g1[0], "second reverse pass, every segment replayed")
+    ws0, s0, l0, g0 = _run(ddm, 0)
+    assert ws0 == ws1
+    # run to run: particles that drift out of their tile's window add to the
+    # grid with FP32 atomics, whose order varies
+    _same_state(s0, s1, "same setting, second run", 1e-5)
+    prev = ws1
+    for r in (2, 4):
+        ws, s, l, g = _run(ddm, r)
+        _log(f"record_segments {r}: workspace {ws / 2**30:.2f} GiB (1: {ws1 / 2**30:.2f} GiB)")
+        assert ws > prev
+        prev = ws
+        _same_state(s, s1, f"final state with {r} segments recorded", 1e-5)
+        _close(l, l1, "loss", rtol=1e-6)
+        _close(g[0], g1[0], f"gradient with {r} segments recorded", rtol=1e-5)
+    # more sets than segments: capped
+    assert _run(ddm, 9)[0] == prev
+
+
+def test_recorded_segments_f64(ddm):
+    _log(f"case record_segments 1/4 dig3d {STEPS} steps K={K} f64")
+    _, s1, l1, g1 = _run(ddm, 1, precision="f64")
+    _, s4, l4, g4 = _run(ddm, 4, precision="f64")
+    # FP64 sums add in a different order from run to run (about 1e-15 of the state)
+    _close(l4, l1, "loss", rtol=1e-10)
+    _close(g4[0], g1[0], "gradient", rtol=1e-8)
