@@ -174,7 +174,7 @@ def copy_calibration(torch):
 
 
 def cpu_baseline(ws):
-    """The FP64 oracle (single thread) with 7 forward-mode tangents on the
+    """The FP64 oracle (single thread) with 9 forward-mode tangents on the
     smallest instance of the batch, for about 15 s of work: the fwd+bwd-equivalent
     rate."""
     import oracle
@@ -186,7 +186,7 @@ def cpu_baseline(ws):
     oracle.rollout(oracle.config(w), w.params, s0, steps, target=W.target_heightmap(w), grad=True)
     dt = time.perf_counter() - t0
     return {"value": w.n_particles * steps / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"smallest instance ({w.n_particles} particles), {steps} sub-steps, FP64 with 7 "
+            "sample": f"smallest instance ({w.n_particles} particles), {steps} sub-steps, FP64 with 9 "
                       f"forward-mode tangents, {dt:.1f} s"}
 
 
