@@ -513,10 +513,7 @@ void launch_p2g(int prec, const KCfg& c, const Bufs& b, const TileList& tl, int 
 #undef DDM_P2G
 }
 
-// ---------------------------------------------------------------------------
-// Grid update (Algorithm 1, agent move to grid collision): v = mv/m + dt g, shovel contact at the
-// pose of this sub-step, then sticky walls.  Nodes without mass get v = 0.
-// ---------------------------------------------------------------------------
+// Blade pose of one sub-step (tip, angle, velocities) from the pose table.
 template <typename T>
 __device__ __forceinline__ Blade<T> load_blade(const void* poses, int inst, int max_steps, int step) {
   const T* q = static_cast<const T*>(poses) + ((int64_t)inst * max_steps + step) * kPoseVals;
@@ -536,6 +533,10 @@ __device__ __forceinline__ void blade_velocity(const Blade<T>& bl, const T xi[3]
   vs[2] = bl.vel[2];
 }
 
+// ---------------------------------------------------------------------------
+// Grid update (Algorithm 1, agent move to grid collision): v = mv/m + dt g, shovel contact at the
+// pose of this sub-step, then sticky walls.  Nodes without mass get v = 0.
+// ---------------------------------------------------------------------------
 template <int D>
 __device__ __forceinline__ void node_coords(int64_t node, int n, int idx[3]) {
   if (D == 2) { idx[0] = (int)(node / n); idx[1] = (int)(node % n); idx[2] = 0; }
@@ -700,32 +701,25 @@ __device__ __forceinline__ void particle_collision(const KCfg& c, const Bufs& b,
   }
 }
 
-// ---------------------------------------------------------------------------
-// G2P (Algorithm 1, gather to advection): v_p = sum w v_i, C_p = (4/dx^2) sum w v_i r^T,
-// the particle-level collision when enabled, x_p += dt v_p.
-// ---------------------------------------------------------------------------
-// PC: with the particle-level collision (a separate instance, so that the
-// plain kernel keeps its register budget).
+// G2P of one particle (Algorithm 1, gather to advection) without writing it:
+// v_p = sum w v_i and C_p = (4/dx^2) sum w v_i r^T from the grid velocities g
+// of its instance, the particle-level collision when PC, and the advanced
+// position.  Returns false when the advance leaves the fixed-point range or
+// the result is not finite (the caller flags it).  Computing everything
+// before the stores lets the compiler keep the kernel at 89 registers.
 template <typename T, int D, bool PC>
-__global__ void __launch_bounds__(kBlock) k_g2p(KCfg c, Bufs b, int step, const void* st_in, void* st_out,
-                                                const T* __restrict__ post) {
-  const int inst = b.blk_inst[blockIdx.x];
-  const InstDev& I = b.inst[inst];
-  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const P<T, D> si = pv<T, D>(st_in, c.ntot), so = pv<T, D>(st_out, c.ntot);
-  if (p - I.off >= I.n) {
-    // padding slots keep a harmless position so they never trip a check
-#pragma unroll
-    for (int a = 0; a < D; ++a) so.xr(a, p) = Pos<T>::from_real(0.5);
-    return;
-  }
-  Stencil<T, D> S;
-  if (!make_stencil<T, D>(si, p, c, S)) { flag_error(b.err, 2u, inst); return; }
+__device__ __forceinline__ bool g2p_compute(const KCfg& c, const Bufs& b, int inst, int step, const P<T, D>& si,
+                                            int64_t p, const Stencil<T, D>& S, const T* __restrict__ g, T (&vn)[3],
+                                            T (&Cn)[3][3], typename Pos<T>::X (&xn)[3]) {
   const T dx = T(c.dx), Dk = T(4.0 * c.inv_dx * c.inv_dx);
-  const T* g = post + I.goff * kNodeVals;
   // v_p = sum w_o v_o, C_p = (4/dx^2) sum w_o v_o r_o^T with r_o = (o - f) dx:
   // sums along the last axis first, then per row
-  T vn[3] = {T(0), T(0), T(0)}, Cn[3][3] = {{T(0), T(0), T(0)}, {T(0), T(0), T(0)}, {T(0), T(0), T(0)}};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    vn[a] = T(0);
+#pragma unroll
+    for (int bb = 0; bb < 3; ++bb) Cn[a][bb] = T(0);
+  }
   T rr[3][3];
 #pragma unroll
   for (int a = 0; a < 3; ++a)
@@ -760,14 +754,47 @@ __global__ void __launch_bounds__(kBlock) k_g2p(KCfg c, Bufs b, int step, const 
 #pragma unroll
   for (int a = 0; a < D; ++a) {
     bool oka;
-    so.xr(a, p) = Pos<T>::advance(si.xr(a, p), dt * vn[a], oka);
+    xn[a] = Pos<T>::advance(si.xr(a, p), dt * vn[a], oka);
     ok &= oka;
-    so.v(a, p) = vn[a];
     chk += vn[a];
 #pragma unroll
-    for (int bb = 0; bb < D; ++bb) { so.C(a, bb, p) = Cn[a][bb]; chk += Cn[a][bb]; }
+    for (int bb = 0; bb < D; ++bb) chk += Cn[a][bb];
   }
-  if (!isfinite(chk) || !ok) flag_error(b.err, 1u, inst);
+  return isfinite(chk) && ok;
+}
+
+// ---------------------------------------------------------------------------
+// G2P (Algorithm 1, gather to advection): v_p = sum w v_i, C_p = (4/dx^2) sum w v_i r^T,
+// the particle-level collision when enabled, x_p += dt v_p.
+// ---------------------------------------------------------------------------
+// PC: with the particle-level collision (a separate instance, so that the
+// plain kernel keeps its register budget).
+template <typename T, int D, bool PC>
+__global__ void __launch_bounds__(kBlock) k_g2p(KCfg c, Bufs b, int step, const void* st_in, void* st_out,
+                                                const T* __restrict__ post) {
+  const int inst = b.blk_inst[blockIdx.x];
+  const InstDev& I = b.inst[inst];
+  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const P<T, D> si = pv<T, D>(st_in, c.ntot), so = pv<T, D>(st_out, c.ntot);
+  if (p - I.off >= I.n) {
+    // padding slots keep a harmless position so they never trip a check
+#pragma unroll
+    for (int a = 0; a < D; ++a) so.xr(a, p) = Pos<T>::from_real(0.5);
+    return;
+  }
+  Stencil<T, D> S;
+  if (!make_stencil<T, D>(si, p, c, S)) { flag_error(b.err, 2u, inst); return; }
+  T vn[3], Cn[3][3];
+  typename Pos<T>::X xn[3];
+  const bool ok = g2p_compute<T, D, PC>(c, b, inst, step, si, p, S, post + I.goff * kNodeVals, vn, Cn, xn);
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    so.xr(a, p) = xn[a];
+    so.v(a, p) = vn[a];
+#pragma unroll
+    for (int bb = 0; bb < D; ++bb) so.C(a, bb, p) = Cn[a][bb];
+  }
+  if (!ok) flag_error(b.err, 1u, inst);
 }
 
 void launch_g2p(int prec, const KCfg& c, const Bufs& b, int nblk, int step, const void* st_in, void* st_out,
