@@ -12,7 +12,7 @@ namespace ddm {
 template <typename T> struct Lim;
 template <> struct Lim<float> {
   static constexpr int sweeps = 6;
-  static __device__ __forceinline__ float tol() { return 1e-7f; }
+  static __device__ __forceinline__ float tol() { return 1e-6f; }
 };
 template <> struct Lim<double> {
   static constexpr int sweeps = 12;
