@@ -104,9 +104,11 @@ __device__ __forceinline__ void jacobi_sym(T a[3][3], T V[3][3], T ev[3]) {
       const int p = pq == 2 ? 1 : 0;
       const int q = pq == 0 ? 1 : 2;
       const T apq = a[p][q];
-      if (apq == T(0)) continue;
+      // a zero a_pq gives t = 0, the identity rotation (selected rather than
+      // branched over: no merge of register copies in the unrolled sweeps)
       const T theta = (a[q][q] - a[p][p]) * frcp(T(2) * apq);
-      const T t = (theta >= T(0) ? T(1) : T(-1)) * frcp(dabs(theta) + fsqrt(theta * theta + T(1)));
+      const T tr = (theta >= T(0) ? T(1) : T(-1)) * frcp(dabs(theta) + fsqrt(theta * theta + T(1)));
+      const T t = apq == T(0) ? T(0) : tr;
       const T c = frsq(t * t + T(1));
       const T sn = t * c;
       a[p][p] -= t * apq;
@@ -332,19 +334,25 @@ __device__ __forceinline__ void constit_forward(const T G[3][3], T mu, T lam, T 
       c.eps[i] = T(0.5) * flog1p(l);
     }
   }
-  // R - I = (G - (S - I)) S^-1
+  // R - I = (G - (S - I)) S^-1; S - I = V diag(s - 1) V^T and S^-1 are
+  // symmetric, so each entry pair is formed once
   T GmS[3][3], Sinv[3][3], is[3];
 #pragma unroll
   for (int k = 0; k < D; ++k) is[k] = frcp(c.s[k]);
 #pragma unroll
   for (int i = 0; i < D; ++i)
 #pragma unroll
-    for (int j = 0; j < D; ++j) {
+    for (int j = i; j < D; ++j) {
       T smi = T(0), si = T(0);
 #pragma unroll
-      for (int k = 0; k < D; ++k) { smi += c.V[i][k] * c.sm1[k] * c.V[j][k]; si += c.V[i][k] * c.V[j][k] * is[k]; }
+      for (int k = 0; k < D; ++k) {
+        const T vv = c.V[i][k] * c.V[j][k];
+        smi += vv * c.sm1[k];
+        si += vv * is[k];
+      }
       GmS[i][j] = G[i][j] - smi;
-      Sinv[i][j] = si;
+      GmS[j][i] = G[j][i] - smi;
+      Sinv[i][j] = Sinv[j][i] = si;
     }
 #pragma unroll
   for (int i = 0; i < D; ++i)
