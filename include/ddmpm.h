@@ -209,9 +209,12 @@ ddm_status ddm_init_state(ddm_ctx* ctx, const void* x0_dev);
 /* Advances every instance by n_steps sub-steps (Algorithm 1), no recording. */
 ddm_status ddm_step(ddm_ctx* ctx, int32_t n_steps);
 
-/* Runs n_steps sub-steps from the initial state and records a snapshot every
- * checkpoint_every steps, so that ddm_backward can replay the rollout.
- * n_steps <= max_steps. */
+/* Runs n_steps sub-steps from the current state and records a snapshot every
+ * checkpoint_every steps, so that ddm_backward can replay the rollout; the
+ * last record_segments checkpoint segments are recorded whole (every
+ * sub-step's state, grids, stress and binning) and need no replay.  The
+ * steps and results are those of ddm_step.  DDM_EINVAL when the rollout would
+ * pass max_steps. */
 ddm_status ddm_rollout(ddm_ctx* ctx, int32_t n_steps);
 
 /* Loss of every instance at the current state: height map of Eq. hm (40x40,
@@ -235,9 +238,10 @@ ddm_status ddm_set_emd_target(ddm_ctx* ctx, const double* points_dev, int32_t m)
  * (double, device) the upstream gradient, writes grad_dev[n_inst][DDM_N_PARAMS]
  * (double, device) = d(sum_i dloss_i * loss_i) / d(E, nu, phi_deg, rho, depth,
  * angle_deg, push, displace, push_angle_deg); the skill entries are zero
- * without a shovel.  Recomputes each checkpoint segment forward, then runs the
- * adjoint of every sub-step in reverse (Eq. po/pa).  DDM_ESTATE without a
- * preceding ddm_rollout and ddm_loss. */
+ * without a shovel.  Recomputes each checkpoint segment forward (except those
+ * the rollout recorded whole), then runs the adjoint of every sub-step in
+ * reverse (Eq. po/pa).  A second call replays every segment.  DDM_ESTATE
+ * without a preceding ddm_rollout and ddm_loss. */
 ddm_status ddm_backward(ddm_ctx* ctx, const double* dloss_dev, double* grad_dev);
 
 /* One full pass of a gradient-based optimiser or line search (Sec. III-D,
