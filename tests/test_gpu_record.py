@@ -89,3 +89,49 @@ def test_recorded_segments_f64(ddm):
     # FP64 sums add in a different order from run to run (about 1e-15 of the state)
     _close(l4, l1, "loss", rtol=1e-10)
     _close(g4[0], g1[0], "gradient", rtol=1e-8)
+
+
+def test_graph_replays_with_recorded_segments(ddm):
+    """A pass captured into a HIP graph with two segments recorded gives the
+    eager gradient on every replay, with eager work between the replays."""
+    import torch
+    _log(f"case record_segments 2 graph replays dig3d {STEPS} steps K={K} f32")
+    w = W.dig_3d(steps=STEPS)
+    cfg, inst = ddm.from_workload(w, max_steps=STEPS, checkpoint_every=K, precision="f32")
+    cfg.record_segments = 2
+    sim = ddm.Simulator(cfg, [inst], stream=torch.cuda.Stream())
+    x0, tg = W.bed_positions(w), W.target_heightmap(w).reshape(1, -1)
+    sim.init_state(x0)
+    sim.rollout(STEPS)
+    l_e = sim.loss(tg).cpu().numpy()
+    g_e = sim.backward().cpu().numpy()
+    for rep in range(3):
+        loss, grad = sim.full_pass(x0, STEPS, tg, graph=True)
+        torch.cuda.synchronize()
+        _close(loss.cpu().numpy(), l_e, f"loss of replay {rep}", rtol=1e-6)
+        _close(grad.cpu().numpy(), g_e, f"gradient of replay {rep}", rtol=1e-5)
+        # eager work of the program between replays
+        sim.init_state(x0)
+        sim.step(3)
+        torch.cuda.synchronize()
+    assert sim.check().flags & 1 == 0
+
+
+def test_autotune_between_rollout_and_backward(ddm):
+    """ddm_autotune probes from the current state in the segment buffers: a
+    reverse pass after it replays every segment from its snapshot and gives
+    the gradient of an undisturbed pass."""
+    _log(f"case autotune after a rollout with all segments recorded, dig3d {STEPS} steps K={K} f32")
+    _, _, _, g1 = _run(ddm, 1)
+    w = W.dig_3d(steps=STEPS)
+    cfg, inst = ddm.from_workload(w, max_steps=STEPS, checkpoint_every=K, precision="f32")
+    cfg.record_segments = 4
+    sim = ddm.Simulator(cfg, [inst])
+    x0, tg = W.bed_positions(w), W.target_heightmap(w).reshape(1, -1)
+    sim.init_state(x0)
+    sim.rollout(STEPS)
+    sim.loss(tg)
+    sim.autotune()
+    g = sim.backward().cpu().numpy()
+    assert sim.check().flags & 1 == 0
+    _close(g, g1[0], "gradient after autotune", rtol=1e-5)
