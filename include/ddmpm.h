@@ -107,12 +107,12 @@ typedef struct ddm_config {
                                contact, one in the wall layers (closer than bound cells to a face)
                                gets zero velocity; 0: grid collision only */
   int32_t record_segments;  /* how many checkpoint segments the workspace can hold whole for the
-                               reverse pass (the state, grids, stress and binning of every sub-step
-                               of a segment); 0 counts as 1.  ddm_rollout runs its last
+                               reverse pass (the state, pre-update grid, stress and binning of every
+                               sub-step of a segment); 0 counts as 1.  ddm_rollout runs its last
                                record_segments segments straight into these buffers and
                                ddm_backward replays only the segments before them from their
                                checkpoints: fewer replays for more memory.  Each
-                               adds about K (S_p n_total + 2 grid + stress) bytes to the
+                               adds about K (S_p n_total + grid + stress) bytes to the
                                workspace; capped at the segments of a max_steps rollout */
   double w_emd;             /* weight of the earth mover's distance (Eq. emd) between the surface
                                observation and the target set by ddm_set_emd_target; 0 = off;

@@ -576,6 +576,38 @@ __device__ __forceinline__ void gather_windows(const KCfg& c, int inst, const in
       }
 }
 
+// Velocity of one node from its momentum and mass (acc = mv, m): v = mv/m + dt g,
+// the shovel contact at the pose of sub-step `step`, the sticky walls; zero
+// without mass.
+template <typename T, int D>
+__device__ __forceinline__ void node_velocity(const KCfg& c, const Bufs& b, int inst, int step, const int idx[3],
+                                              const T (&acc)[4], T (&v)[3]) {
+  const T m = acc[3];
+  v[0] = v[1] = v[2] = T(0);
+  if (m > T(0)) {
+    const T dt = T(b.inst[inst].dt);
+#pragma unroll
+    for (int a = 0; a < D; ++a) v[a] = acc[a] / m;
+    v[1] += dt * T(c.gravity);
+    if (D == 3 && c.shovel) {
+      const Blade<T> bl = load_blade<T>(b.poses, inst, c.max_steps, step);
+      const T xi[3] = {T(idx[0]) * T(c.dx), T(idx[1]) * T(c.dx), T(idx[2]) * T(c.dx)};
+      const T half[3] = {T(c.half[0]), T(c.half[1]), T(c.half[2])};
+      SDF<T> f;
+      sdf_eval<T>(bl, half, xi, f);
+      if (f.phi < T(c.skin)) {
+        T vs[3];
+        blade_velocity<T>(bl, xi, vs);
+        coulomb_forward<T>(vs, f.n, T(c.mu_b), v);
+      }
+    }
+    bool wall = false;
+#pragma unroll
+    for (int a = 0; a < D; ++a) wall |= (idx[a] < c.bound) || (idx[a] >= c.n - c.bound);
+    if (wall) v[0] = v[1] = v[2] = T(0);
+  }
+}
+
 template <typename T, int D>
 __global__ void __launch_bounds__(kBlock) k_grid_update(KCfg c, Bufs b, int step, const T* __restrict__ stg,
                                                         const uint32_t* __restrict__ tslot, T* __restrict__ gout,
@@ -604,36 +636,38 @@ __global__ void __launch_bounds__(kBlock) k_grid_update(KCfg c, Bufs b, int step
         for (int a = 0; a < kNodeVals; ++a) { acc[a] += o.v[a]; go[a] = T(0); }
       }
     }
-    const T m = acc[3];
-    T v[3] = {T(0), T(0), T(0)};
-    if (m > T(0)) {
-      const T dt = T(b.inst[inst].dt);
-#pragma unroll
-      for (int a = 0; a < D; ++a) v[a] = acc[a] / m;
-      v[1] += dt * T(c.gravity);
-      if (D == 3 && c.shovel) {
-        const Blade<T> bl = load_blade<T>(b.poses, inst, c.max_steps, step);
-        const T xi[3] = {T(idx[0]) * T(c.dx), T(idx[1]) * T(c.dx), T(idx[2]) * T(c.dx)};
-        const T half[3] = {T(c.half[0]), T(c.half[1]), T(c.half[2])};
-        SDF<T> f;
-        sdf_eval<T>(bl, half, xi, f);
-        if (f.phi < T(c.skin)) {
-          T vs[3];
-          blade_velocity<T>(bl, xi, vs);
-          coulomb_forward<T>(vs, f.n, T(c.mu_b), v);
-        }
-      }
-      bool wall = false;
-#pragma unroll
-      for (int a = 0; a < D; ++a) wall |= (idx[a] < c.bound) || (idx[a] >= c.n - c.bound);
-      if (wall) v[0] = v[1] = v[2] = T(0);
-    }
+    T v[3];
+    node_velocity<T, D>(c, b, inst, step, idx, acc, v);
 #pragma unroll
     for (int a = 0; a < kNodeVals; ++a) pre[gid * kNodeVals + a] = acc[a];
     post[gid * kNodeVals + 0] = v[0];
     post[gid * kNodeVals + 1] = v[1];
     post[gid * kNodeVals + 2] = v[2];
-    post[gid * kNodeVals + 3] = m;
+    post[gid * kNodeVals + 3] = acc[3];
+  }
+}
+
+// The post-update grid of a sub-step again from its pre-update grid, over the
+// sub-step's listed active blocks: the same arithmetic on the same values as
+// k_grid_update, so the velocities are the ones G2P used.  The reverse pass
+// keeps only the pre-update grids and rebuilds these.
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock) k_grid_post_from_pre(KCfg c, Bufs b, int step,
+                                                               const uint32_t* __restrict__ list,
+                                                               const uint32_t* __restrict__ count,
+                                                               const T* __restrict__ pre, T* __restrict__ post) {
+  constexpr int NPB = D == 3 ? kTile * kTile * kTile : kTile * kTile;
+  const int64_t items = (int64_t)(*count) * NPB;
+  for (int64_t it = (int64_t)blockIdx.x * kBlock + threadIdx.x; it < items; it += (int64_t)gridDim.x * kBlock) {
+    int inst, idx[3];
+    int64_t node;
+    active_node<D>(c, list[it / NPB], (int)(it % NPB), inst, idx, node);
+    const int64_t gid = b.inst[inst].goff + node;
+    const Node4<T> q = ld_node(pre + gid * kNodeVals);
+    const T acc[4] = {q.v[0], q.v[1], q.v[2], q.v[3]};
+    T v[3];
+    node_velocity<T, D>(c, b, inst, step, idx, acc, v);
+    st_node(post + gid * kNodeVals, v[0], v[1], v[2], acc[3]);
   }
 }
 
@@ -643,6 +677,20 @@ static unsigned active_grid(const KCfg& c) {
   const int64_t items = total_tiles << tshift;
   const int64_t nb = (items + kBlock - 1) / kBlock;
   return (unsigned)(nb < 4096 ? nb : 4096);
+}
+
+void launch_grid_post_from_pre(int prec, const KCfg& c, const Bufs& b, int step, const uint32_t* list,
+                               const uint32_t* count, const void* pre, void* post, hipStream_t s) {
+  const unsigned nb = active_grid(c);
+#define DDM_GP(T, DD)                                                                                       \
+  hipLaunchKernelGGL((k_grid_post_from_pre<T, DD>), dim3(nb), dim3(kBlock), 0, s, c, b, step, list, count, \
+                     (const T*)pre, (T*)post)
+  if (prec == 0) {
+    if (c.dim == 3) DDM_GP(float, 3); else DDM_GP(float, 2);
+  } else {
+    if (c.dim == 3) DDM_GP(double, 3); else DDM_GP(double, 2);
+  }
+#undef DDM_GP
 }
 
 void launch_grid_update(int prec, const KCfg& c, const Bufs& b, int step, const Staging& stg, void* gout,

@@ -102,6 +102,10 @@ void launch_p2g(int prec, const KCfg& c, const Bufs& b, const TileList& tl, int 
 // Grid update over the active blocks: sums the staged windows and the outlier
 // grid (zeroing what it read) into grid_pre (m, mv), writes grid_post (v, m).
 // list_out / count_out (may be NULL) receive a copy of the active list.
+// The post-update grid of sub-step `step` rebuilt from its pre-update grid
+// over the listed active blocks (list, count: as the grid update wrote them).
+void launch_grid_post_from_pre(int prec, const KCfg& c, const Bufs& b, int step, const uint32_t* list,
+                               const uint32_t* count, const void* pre, void* post, hipStream_t s);
 void launch_grid_update(int prec, const KCfg& c, const Bufs& b, int step, const Staging& stg, void* gout,
                         const ActiveSet& act, void* grid_pre, void* grid_post, uint32_t* list_out,
                         uint32_t* count_out, hipStream_t s);

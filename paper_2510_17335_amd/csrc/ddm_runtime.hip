@@ -114,13 +114,14 @@ Layout make_layout(const ddm_config& c, int n_inst, const ddm_instance* in) {
   L.grid_post = cv.take(L.grid_bytes);
   L.ckpt = cv.take(L.state_bytes * L.n_ckpt);
   // Segment buffers: the reverse pass's record of one checkpoint segment
-  // (per sub-step the state, both grids, the stress, the binning permutation,
-  // the tile list and the active blocks), M sets back to back.
+  // (per sub-step the state, the pre-update grid, the stress, the binning
+  // permutation, the tile list and the active blocks; the post-update grid is
+  // rebuilt from the pre-update one when needed), M sets back to back.
   L.tau_bytes = (size_t)(D * (D + 1) / 2) * ntot * b;
   L.M = std::max(1, std::min<int>(c.record_segments, (c.max_steps + L.K - 1) / L.K));
   const size_t seg0 = cv.take(0);
   L.seg_state = cv.take(L.state_bytes * (L.K + 1));
-  L.seg_grid = cv.take(L.grid_bytes * 2 * L.K);
+  L.seg_grid = cv.take(L.grid_bytes * L.K);
   L.seg_tau = cv.take(L.tau_bytes * L.K);
   L.seg_perm = cv.take(sizeof(uint32_t) * ntot * L.K);
   L.seg_tiles = cv.take(sizeof(ddm::TileRec) * L.max_chunks * L.K);
@@ -363,8 +364,7 @@ struct ddm_ctx {
   // buffers of sub-step j of segment-buffer set m
   size_t sb(int m) const { return (size_t)m * L.seg_set; }
   void* slot(int m, int j) const { return at(sb(m) + L.seg_state + (size_t)j * L.state_bytes); }
-  void* gpre(int m, int j) const { return at(sb(m) + L.seg_grid + (size_t)(2 * j) * L.grid_bytes); }
-  void* gpost(int m, int j) const { return at(sb(m) + L.seg_grid + (size_t)(2 * j + 1) * L.grid_bytes); }
+  void* gpre(int m, int j) const { return at(sb(m) + L.seg_grid + (size_t)j * L.grid_bytes); }
   void* tau(int m, int j) const { return at(sb(m) + L.seg_tau + L.tau_bytes * (size_t)j); }
   uint32_t* perm(int m, int j) const { return at<uint32_t>(sb(m) + L.seg_perm + sizeof(uint32_t) * (size_t)L.ntot * j); }
   ddm::TileRec* seg_tile_recs(int m, int j) const {
@@ -592,7 +592,7 @@ ddm_status run_segment(ddm_ctx* x, int m, int64_t k_first, int len, const void* 
     tl_of[j] = last;
     const bool next_bins = j + 1 < len && bins[j + 1];
     const ddm_status s = forward_step(x, k_first + j, x->seg_tiles(m, last), x->slot(m, j),
-                                      next_bins ? spare : x->slot(m, j + 1), x->gpre(m, j), x->gpost(m, j),
+                                      next_bins ? spare : x->slot(m, j + 1), x->gpre(m, j), x->at(x->L.grid_post),
                                       x->tau(m, j), x->seg_alist(m, j), x->seg_acount(m, j));
     if (s != DDM_OK) return s;
   }
@@ -883,8 +883,8 @@ ddm_status ddm_rollout(ddm_ctx* x, int32_t n_steps) {
   }
   // the final state, its grids and its binning become the current ones
   DDM_HIP(hipMemcpyAsync(x->cur(), src, L.state_bytes, hipMemcpyDeviceToDevice, x->stream));
+  // (the post-update grid of the last sub-step is in grid_post already)
   DDM_HIP(hipMemcpyAsync(x->at(L.grid_pre), x->gpre(m, len - 1), L.grid_bytes, hipMemcpyDeviceToDevice, x->stream));
-  DDM_HIP(hipMemcpyAsync(x->at(L.grid_post), x->gpost(m, len - 1), L.grid_bytes, hipMemcpyDeviceToDevice, x->stream));
   x->need_sort = false;
   x->grid_valid = true;
   x->rec_first = first_rec;
@@ -995,7 +995,8 @@ ddm_status ddm_backward(ddm_ctx* x, const double* dloss_dev, double* grad_dev) {
     }
     auto slot = [&](int j) { return x->slot(m, j); };
     auto gpre = [&](int j) { return x->gpre(m, j); };
-    auto gpost = [&](int j) { return x->gpost(m, j); };
+    // post-update grid of the sub-step being reversed, rebuilt into grid_post
+    auto gpost = [&](int) { return x->at(L.grid_post); };
     auto perm = [&](int j) { return x->perm(m, j); };
     auto tau = [&](int j) { return x->tau(m, j); };
     for (int j = len - 1; j >= 0; --j) {
@@ -1005,6 +1006,8 @@ ddm_status ddm_backward(ddm_ctx* x, const double* dloss_dev, double* grad_dev) {
       const bool treat = rec || x->treat.mode != ddm::kTreatNone;
       const bool reduce = rec || x->treat.mode == ddm::kTreatScale || x->treat.mode == ddm::kTreatNorm;
       if (reduce) { Timed t(x, 9); ddm::launch_fill_zero(acc, (int64_t)ddm::treat_acc_words(x->n_inst), 8, st); }
+      { Timed t(x, 1); ddm::launch_grid_post_from_pre(x->prec, x->kc, b, (int)k, x->seg_alist(m, j), x->seg_acount(m, j),
+                                                      gpre(j), x->at(L.grid_post), st); }
       {
         Timed t(x, 4);
         if (x->kc.pcontact)
