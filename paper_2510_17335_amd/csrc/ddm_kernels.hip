@@ -250,9 +250,11 @@ __device__ __forceinline__ bool p2g_particle(const KCfg& c, const Bufs& b, const
 template <typename T> struct alignas(16) RunLDS {
   // group g of slot t (w_a^k: weight of offset k on axis a; w_a^1 = 1 - w_a^0 - w_a^2):
   //   0: q0 q1 q2 w_0^0   1: B00 B01 B02 w_0^2   2: B10 B11 B12 w_1^0
-  //   3: B20 B21 B22 w_1^2   4: w_2^0 w_2^2 - -
-  T rec[5][kBlock][4];
-  int wbase[kBlock];
+  //   3: B20 B21 B22 w_1^2   and w4: w_2^0 w_2^2
+  // (kept small: the G2P adjoint fits 4 workgroups per CU at 40 KB of LDS)
+  T rec[4][kBlock][4];
+  T w4[kBlock][2];
+  short wbase[kBlock];
   int wcount[kBlock / 64];
   unsigned short start[kBlock + 1];
   int nruns;
@@ -276,7 +278,8 @@ __device__ __forceinline__ void put_record(RunLDS<T>& L, int t, const T (&q)[3],
   st4<T>(L.rec[2][t], B[1][0], B[1][1], D == 3 ? B[1][2] : T(0), w[1][0]);
   if (D == 3) {
     st4<T>(L.rec[3][t], B[2][0], B[2][1], B[2][2], w[1][2]);
-    st4<T>(L.rec[4][t], w[2][0], w[2][2], T(0), T(0));
+    L.w4[t][0] = w[2][0];
+    L.w4[t][1] = w[2][2];
   } else {
     st4<T>(L.rec[3][t], T(0), T(0), T(0), w[1][2]);
   }
@@ -326,7 +329,7 @@ __device__ void run_scatter_round(RunLDS<T>& L, int rc, double* win, T m) {
       ld4<T>(L.rec[1][sl], g1);
       ld4<T>(L.rec[2][sl], g2);
       ld4<T>(L.rec[3][sl], g3);
-      if (D == 3) ld4<T>(L.rec[4][sl], g4);
+      if (D == 3) { g4[0] = L.w4[sl][0]; g4[1] = L.w4[sl][1]; }
       // per-axis weights
       const T wa[3] = {g0[3], T(1) - g0[3] - g1[3], g1[3]};
       const T wb[3] = {g2[3], T(1) - g2[3] - g3[3], g3[3]};
