@@ -257,7 +257,6 @@ template <typename T> struct alignas(16) RunLDS {
   short wbase[kBlock];
   int wcount[kBlock / 64];
   unsigned short start[kBlock + 1];
-  int nruns;
 };
 
 template <typename T> __device__ __forceinline__ void st4(T* p, T a, T b, T c, T d) { p[0] = a; p[1] = b; p[2] = c; p[3] = d; }
