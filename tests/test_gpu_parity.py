@@ -118,6 +118,40 @@ def test_forward_dig3d_f32_full(ddm, orc):
         assert v < 1e-4, (k, v)
 
 
+def test_forward_column2d_f32(ddm, orc):
+    """The 2D column collapse in FP32 (fixed-point positions, G = F - I, FP64
+    LDS windows, the FP32 elementary functions) against the FP64 oracle after
+    200 sub-steps: <= 1e-4 per field."""
+    w = W.column_2d()
+    _log("case column2d f32 200 steps")
+    g = run_gpu(ddm, w, 200, precision="f32")
+    r = run_oracle(orc, w, 200)
+    e = field_errors(g["state"], r["state"], 2)
+    _log("column2d f32 errors", e)
+    assert g["err"].flags & 3 == 0
+    for k, v in e.items():
+        assert v < 1e-4, (k, v)
+
+
+def test_gradient_tiny2d_f32(ddm, orc):
+    """The 2D reverse pass in FP32 against the oracle's FP64 forward-mode
+    gradient (tiny bed, 60 sub-steps, checkpoints every 16): <= 1e-3 relative
+    per parameter, the gradient bar."""
+    w = W.tiny(2, shovel=False, steps=60)
+    if w.target_seed is None:
+        w.target_seed = 11
+    tgt = W.target_heightmap(w)
+    _log("case gradient tiny2d f32")
+    g = run_gpu(ddm, w, 60, record=True, target=tgt, K=16, precision="f32")
+    r = run_oracle(orc, w, 60, target=tgt, grad=True)
+    _log("gpu grad", g["grad"], "\noracle grad", r["grad"])
+    assert abs(g["loss"] - r["loss"]) <= 1e-5 * abs(r["loss"])
+    nz = np.abs(r["grad"]) > 0
+    rel = np.abs(g["grad"][nz] - r["grad"][nz]) / np.maximum(np.abs(r["grad"][nz]), 1e-6 * np.abs(r["grad"]).max())
+    _log("rel", rel)
+    assert np.all(rel < 1e-3), rel
+
+
 @pytest.mark.parametrize("dim", [2, 3])
 def test_gradient_tiny_f64(ddm, orc, dim):
     """Reverse pass vs the oracle's forward-mode gradient: tiny bed, 60 sub-steps,
