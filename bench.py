@@ -132,6 +132,19 @@ def algorithmic_bytes_p2g(ws, b=4, d=3):
     return n * per_particle + nodes * (d + 1) * b
 
 
+def algorithmic_bytes_pass(ws, b=4, d=3):
+    """Bytes per particle-step that a fwd+bwd pass must move: per particle the
+    state written and read in the forward (2 S_p), again in the recompute
+    (2 S_p), read once more in the reverse step (S_p) and the adjoint read and
+    written (2 S_p), S_p = (2d + 2d^2) b; per occupied node, in the forward,
+    the recompute and the reverse step, m and mv written and read
+    (2 (1 + d) b) and v written and read (2 d b)."""
+    n = sum(w.n_particles for w in ws)
+    s_p = (2 * d + 2 * d * d) * b
+    nodes = sum(w.n_particles / w.ppc * 1.3 for w in ws)
+    return 7 * s_p + 3 * (2 * (1 + d) * b + 2 * d * b) * nodes / n
+
+
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "p2g_sysid64_traffic.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_2510_17335_amd", "csrc", "ddm_kernels.hip")
 
@@ -340,6 +353,9 @@ def main():
         print(f"# gradient gate (FP32 vs FP64): {gate}", flush=True)
 
     cpu = None if args.no_cpu else cpu_baseline(ws)
+    # the whole pass against the HBM roofline of its algorithmic bytes
+    pass_bytes = algorithmic_bytes_pass(ws)
+    pass_bound = HBM_PEAK_GBS * 1e9 / pass_bytes
     out = {
         "metric": METRIC,
         "value": value,
@@ -368,6 +384,8 @@ def main():
                      "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": measured_traffic(),
                      "algorithmic_bytes": per_launch_bytes,
                      "dominant_group": dom},
+        "pass_roofline": {"bytes_per_particle_step": pass_bytes, "bound_value": pass_bound, "unit": "particle-steps/s",
+                          "frac": value / pass_bound},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
