@@ -184,6 +184,16 @@ def test_gradient_tiny_f64(ddm, orc, dim):
     np.testing.assert_allclose(g["hm"], r["heightmap"], rtol=0, atol=1e-12)
     rel = np.abs(g["grad"] - r["grad"]) / np.maximum(np.abs(r["grad"]), 1e-9 * np.abs(r["grad"]).max())
     assert np.all(rel < 1e-6), rel
+    if dim == 2:
+        # No shovel: the stress term of the grid momentum is linear in E, the
+        # grid mass in rho, and the height-map loss has no mass term, so the
+        # loss depends on E / rho only and E dL/dE + rho dL/drho = 0.  The
+        # reverse pass reaches the two by different routes (stress adjoint;
+        # particle mass sensitivities).
+        p = np.asarray(w.params[:4], dtype=np.float64)
+        resid = p[0] * g["grad"][0] + p[3] * g["grad"][3]
+        _log("E dL/dE + rho dL/drho", resid, "of", p[0] * g["grad"][0])
+        assert abs(resid) <= 1e-10 * abs(p[0] * g["grad"][0]), resid
 
 
 @pytest.mark.timeout(400)
