@@ -30,7 +30,7 @@ def build(force: bool = True) -> str:
         return LIB_PATH
     tmp = LIB_PATH + ".tmp"
     cmd = ["g++", "-std=c++17", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
-           "-Wall", "-o", tmp, _SRC[0]]
+           "-Wall", "-o", tmp, _SRC[0], "-lquadmath"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB_PATH)
     return LIB_PATH
@@ -69,6 +69,8 @@ def lib():
                                   C.POINTER(C.c_int64), dp, dp, C.c_int]
         L.orc_assign.restype = C.c_int
         L.orc_assign.argtypes = [C.c_int, C.c_int, dp, C.POINTER(C.c_int)]
+        L.orc_heightmap.restype = C.c_int
+        L.orc_heightmap.argtypes = [C.POINTER(OrcConfig), C.c_int, dp, dp, C.POINTER(C.c_int)]
         L.orc_surface_particles.restype = C.c_int
         L.orc_surface_particles.argtypes = [C.POINTER(OrcConfig), C.c_int, dp, C.POINTER(C.c_int)]
         L.orc_skill_actions.restype = C.c_int
@@ -298,3 +300,14 @@ def surface_particles(cfg: OrcConfig, state: np.ndarray) -> np.ndarray:
     out = np.zeros(cfg.hm_res ** 2, dtype=np.int32)
     n = lib().orc_surface_particles(C.byref(cfg), state.shape[0], _p(state), out.ctypes.data_as(C.POINTER(C.c_int)))
     return out[:n].copy()
+
+
+def heightmap(cfg: OrcConfig, state: np.ndarray):
+    """Height map of Eq. hm for the positions of a packed state, and the owner
+    (particle index, -1 when empty) of every pixel."""
+    state = np.ascontiguousarray(state, dtype=np.float64)
+    npix = cfg.hm_res ** (cfg.dim - 1)
+    hm = np.zeros(npix)
+    own = np.zeros(npix, dtype=np.int32)
+    lib().orc_heightmap(C.byref(cfg), state.shape[0], _p(state), _p(hm), own.ctypes.data_as(C.POINTER(C.c_int)))
+    return hm, own

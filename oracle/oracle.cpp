@@ -24,6 +24,13 @@
 //  distance, displacement d1, push angle phi3[deg]); the rounded phase lengths
 //  T_i carry no tangent (Sec. III-B).
 //
+//  Arithmetic is FP64 throughout, except in the tangents of the SVD-based
+//  update: the return map and its tangents run in x87 extended precision and
+//  the divided differences of its outputs across pairs of singular values in
+//  IEEE binary128 (libquadmath), so that near-equal singular values and small
+//  deviators cost no digits (the quotient is evaluated as written, with no
+//  threshold or rewrite).
+//
 //  Nothing in the product may include, link or call this file.  It shares no
 //  source with the GPU path.  Readings of points the paper leaves open (grid,
 //  walls, shovel shape, contact law, loss terms, cohesion) are listed at each
@@ -40,6 +47,8 @@
 #include <numeric>
 #include <vector>
 
+#include <quadmath.h>
+
 #include "dual.hpp"
 
 namespace orc {
@@ -48,6 +57,15 @@ static const double kPi = 3.14159265358979323846;
 static const double kSigmaMin = 1e-6;   // singular values are clamped before ln
 
 enum { ORC_OK = 0, ORC_EINVAL = 1, ORC_EDOMAIN = 6 };
+
+// IEEE binary128 scalar (113-bit significand, libquadmath), used only to
+// evaluate divided differences of the return map where its FP64 evaluation
+// would cancel.
+using quad = __float128;
+inline quad log(quad x) { return logq(x); }
+inline quad exp(quad x) { return expq(x); }
+inline quad sqrt(quad x) { return sqrtq(x); }
+inline double val(quad x) { return (double)x; }
 
 }  // namespace orc
 
@@ -273,9 +291,11 @@ static void svd(int d, const double F[3][3], double U[3][3], double S[3], double
 // Cohesion c (not in the paper): the yield surface is shifted by
 // k_c = sqrt(2/3) 6 c cos(phi) / (3 - sin(phi)); it reduces to Eq. DP at c = 0.
 // ---------------------------------------------------------------------------
+// forced_case (1, 2 or 3) takes that case without testing the conditions; 0
+// decides as Eq. DP states.
 template <class S>
 static void return_map(int d, const S s[3], const S& mu, const S& lam, const S& alpha, const S& kc,
-                       S g[3], S h[3], int* dp_case) {
+                       S g[3], S h[3], int* dp_case, int forced_case = 0) {
   S eps[3], tr = S(0.0);
   for (int i = 0; i < d; ++i) { eps[i] = log(s[i]); tr += eps[i]; }
   S eh[3], nrm2 = S(0.0);
@@ -283,7 +303,8 @@ static void return_map(int d, const S s[3], const S& mu, const S& lam, const S& 
   const S stiff = double(d) * lam + 2.0 * mu;
   S ep[3];
   // Case 1 (tension: tr eps > 0 when c = 0): project to the cone apex.
-  const bool tension = val(kc) == 0.0 ? val(tr) > 0.0 : val(alpha * stiff * tr) > val(kc);
+  const bool tension = forced_case ? forced_case == 1
+                                   : (val(kc) == 0.0 ? val(tr) > 0.0 : val(alpha * stiff * tr) > val(kc));
   if (tension) {
     const S apex = kc / (double(d) * alpha * stiff);
     for (int i = 0; i < d; ++i) ep[i] = apex;
@@ -291,7 +312,7 @@ static void return_map(int d, const S s[3], const S& mu, const S& lam, const S& 
   } else {
     const S nrm = val(nrm2) > 0.0 ? sqrt(nrm2) : S(0.0);
     const S dgam = nrm + stiff / (2.0 * mu) * tr * alpha - kc / (2.0 * mu);
-    if (val(dgam) <= 0.0) {           // Case 2: inside the cone, unchanged
+    if (forced_case ? forced_case == 2 : val(dgam) <= 0.0) {   // Case 2: inside the cone, unchanged
       for (int i = 0; i < d; ++i) ep[i] = eps[i];
       *dp_case = 2;
     } else {                          // Case 3: project onto the cone surface
@@ -343,12 +364,13 @@ static void constitutive(int d, const double Ft[3][3], double mu, double lam, do
 //                  dG~_ji = sym (g_i-g_j)/(s_i-s_j) - skw (g_i+g_j)/(s_i+s_j),
 //                  dT~_ij = dT~_ji = sym (h_i-h_j)/(s_i-s_j) + skw (h_j-h_i)/(s_i+s_j)
 //                  (sigma's frame is U on both sides).
-// Where |s_i - s_j| is below 1e-8 max(s), the divided difference is computed as
-// the mean of dg_i/ds_i - dg_i/ds_j along the segment from s to s with s_i and
-// s_j swapped (for a symmetric g this mean equals (g_i - g_j)/(s_i - s_j)),
-// by two-point Gauss-Legendre quadrature of Dual<3> derivatives in s.  The
-// derivative at s itself is not accurate when g varies on a scale as small
-// as |s_i - s_j| (near-isotropic states on the cone).
+// The divided differences (g_i - g_j)/(s_i - s_j) and (h_i - h_j)/(s_i - s_j)
+// are those quotients as written, with g and h evaluated in binary128 at the
+// same (double) singular values, parameters and return-map case: for s_i and
+// s_j one ulp apart the subtraction still leaves about 18 significant digits,
+// so no threshold, quadrature or closed-form rewrite is involved.  Only at an
+// exact tie s_i == s_j is the quotient replaced by its limit
+// dg_i/ds_i - dg_i/ds_j (Dual<3> derivative at s; g is symmetric).
 // This follows from F = U S V^T and never differentiates the SVD iteration.
 // ---------------------------------------------------------------------------
 template <int K>
@@ -378,50 +400,60 @@ static void constitutive(int d, const Dual<K> Ft[3][3], const Dual<K>& mu, const
   for (int i = 0; i < 3; ++i) s[i] = Dual<K>(sc[i]);
   for (int i = 0; i < d; ++i)
     for (int k = 0; k < K; ++k) s[i].d[k] = cl[i] ? 0.0 : Fk[k][i][i];
+  // The return map and its tangents in extended precision: near the cone's
+  // apex the deviator eps - tr/d is a small difference of logarithms.
+  using XD = Dual<K, long double>;
+  auto widen = [](const Dual<K>& a) { XD r((long double)a.v); for (int k = 0; k < K; ++k) r.d[k] = a.d[k]; return r; };
+  auto narrow = [](const XD& a) { Dual<K> r((double)a.v); for (int k = 0; k < K; ++k) r.d[k] = (double)a.d[k]; return r; };
+  XD sx[3], gx[3], hx[3];
+  for (int q = 0; q < 3; ++q) sx[q] = widen(s[q]);
+  return_map(d, sx, widen(mu), widen(lam), widen(alpha), widen(kc), gx, hx, dp_case);
   Dual<K> g[3], h[3];
-  return_map(d, s, mu, lam, alpha, kc, g, h, dp_case);
-  // Divided differences of pair (i, j) by quadrature along the swap segment.
-  auto pair_limit = [&](int i, int j, double* ddg, double* ddh) {
-    *ddg = 0.0;
-    *ddh = 0.0;
-    const double tq[2] = {0.5 - 0.5 / std::sqrt(3.0), 0.5 + 0.5 / std::sqrt(3.0)};
-    for (int k = 0; k < 2; ++k) {
-      Dual<3> s3[3], g3[3], h3[3];
-      double sm[3] = {sc[0], sc[1], sc[2]};
-      sm[i] = sc[j] + tq[k] * (sc[i] - sc[j]);
-      sm[j] = sc[i] + tq[k] * (sc[j] - sc[i]);
-      for (int q = 0; q < 3; ++q) s3[q] = (q < d && !cl[q]) ? Dual<3>::var(sm[q], q) : Dual<3>(sm[q]);
-      int c3;
-      return_map(d, s3, Dual<3>(mu.v), Dual<3>(lam.v), Dual<3>(alpha.v), Dual<3>(kc.v), g3, h3, &c3);
-      *ddg += 0.5 * (g3[i].d[i] - g3[i].d[j]);
-      *ddh += 0.5 * (h3[i].d[i] - h3[i].d[j]);
+  for (int q = 0; q < 3; ++q) { g[q] = narrow(gx[q]); h[q] = narrow(hx[q]); }
+  // Divided differences of pair (i, j): the quotient of the binary128 return
+  // map (evaluated once, at the first untied pair), or its limit at a tie.
+  quad gq[3], hq[3];
+  bool have_q = false;
+  auto pair_dd = [&](int i, int j, double* ddg, double* ddh) {
+    if (sc[i] != sc[j]) {
+      if (!have_q) {
+        const quad sq[3] = {(quad)sc[0], (quad)sc[1], (quad)sc[2]};
+        int cq;
+        return_map(d, sq, (quad)mu.v, (quad)lam.v, (quad)alpha.v, (quad)kc.v, gq, hq, &cq, *dp_case);
+        have_q = true;
+      }
+      const quad ds = (quad)sc[i] - (quad)sc[j];
+      *ddg = (double)((gq[i] - gq[j]) / ds);
+      *ddh = (double)((hq[i] - hq[j]) / ds);
+      return;
     }
+    using X3 = Dual<3, long double>;
+    X3 s3[3], g3[3], h3[3];
+    for (int q = 0; q < 3; ++q) s3[q] = (q < d && !cl[q]) ? X3::var(sc[q], q) : X3(sc[q]);
+    int c3;
+    return_map(d, s3, X3(mu.v), X3(lam.v), X3(alpha.v), X3(kc.v), g3, h3, &c3, *dp_case);
+    *ddg = (double)(g3[i].d[i] - g3[i].d[j]);
+    *ddh = (double)(h3[i].d[i] - h3[i].d[j]);
   };
-  const double smax = std::max(sc[0], std::max(sc[1], d == 3 ? sc[2] : 0.0));
   for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) { Fn[i][j] = Dual<K>(0.0); tau[i][j] = Dual<K>(0.0); }
   for (int i = 0; i < d; ++i) for (int j = 0; j < d; ++j) {
     double a = 0, b = 0;
     for (int p = 0; p < d; ++p) { a += U[i][p] * g[p].v * V[j][p]; b += U[i][p] * h[p].v * U[j][p]; }
     Fn[i][j].v = a; tau[i][j].v = b;
   }
+  double ddg[3][3] = {}, ddh[3][3] = {};
+  for (int i = 0; i < d; ++i) for (int j = i + 1; j < d; ++j) pair_dd(i, j, &ddg[i][j], &ddh[i][j]);
   for (int k = 0; k < K; ++k) {
     double Gt[3][3] = {}, Tt[3][3] = {};
     for (int i = 0; i < d; ++i) { Gt[i][i] = g[i].d[k]; Tt[i][i] = h[i].d[k]; }
     for (int i = 0; i < d; ++i) for (int j = i + 1; j < d; ++j) {
       const double sym = 0.5 * (Fk[k][i][j] + Fk[k][j][i]);
       const double skw = 0.5 * (Fk[k][i][j] - Fk[k][j][i]);
-      double ddg, ddh;
-      if (std::fabs(sc[i] - sc[j]) > 1e-8 * smax) {
-        ddg = (g[i].v - g[j].v) / (sc[i] - sc[j]);
-        ddh = (h[i].v - h[j].v) / (sc[i] - sc[j]);
-      } else {
-        pair_limit(i, j, &ddg, &ddh);
-      }
       const double sgg = (g[i].v + g[j].v) / (sc[i] + sc[j]);
       const double shh = (h[j].v - h[i].v) / (sc[i] + sc[j]);
-      Gt[i][j] = sym * ddg + skw * sgg;
-      Gt[j][i] = sym * ddg - skw * sgg;
-      Tt[i][j] = Tt[j][i] = sym * ddh + skw * shh;
+      Gt[i][j] = sym * ddg[i][j] + skw * sgg;
+      Gt[j][i] = sym * ddg[i][j] - skw * sgg;
+      Tt[i][j] = Tt[j][i] = sym * ddh[i][j] + skw * shh;
     }
     for (int i = 0; i < d; ++i) for (int j = 0; j < d; ++j) {
       double a = 0, b = 0;
@@ -776,14 +808,17 @@ struct Sim {
   // (a P2G of particle masses at the final positions) of the nodes inside the
   // scoop slab on the push side of the final blade pose.
   // ------------------------------------------------------------------------
-  S loss(const double* target, int final_step, std::vector<S>* H_out) {
+  // Owner of every height-map pixel: the particle with the largest height y
+  // among those whose stencil points fall in the pixel, lowest index on ties;
+  // -1 when no particle above y = 0 reaches it (the map starts at 0).
+  std::vector<int> heightmap_owners() const {
     const int res = c.hm_res;
     const int npix = d == 3 ? res * res : res;
-    std::vector<S> H(npix, S(0.0));
+    std::vector<int> own(npix, -1);
     const double pix = c.hm_size / res;
     const double r = c.hm_offset;
     for (int p = 0; p < N; ++p) {
-      const S y = x[p * 3 + 1];
+      const double y = val(x[p * 3 + 1]);
       const int npts = d == 3 ? 5 : 3;
       const double ox[5] = {0, r, -r, 0, 0}, oz[5] = {0, 0, 0, r, -r};
       for (int k = 0; k < npts; ++k) {
@@ -796,10 +831,19 @@ struct Sim {
           if (iz < 0 || iz >= res) continue;
         }
         if (ix < 0 || ix >= res) continue;
-        const int pi = d == 3 ? ix * res + iz : ix;
-        if (val(y) > val(H[pi])) H[pi] = y;
+        int& o = own[d == 3 ? ix * res + iz : ix];
+        if (y > (o < 0 ? 0.0 : val(x[o * 3 + 1]))) o = p;
       }
     }
+    return own;
+  }
+
+  S loss(const double* target, int final_step, std::vector<S>* H_out) {
+    const int res = c.hm_res;
+    const int npix = d == 3 ? res * res : res;
+    const std::vector<int> own = heightmap_owners();
+    std::vector<S> H(npix, S(0.0));
+    for (int i = 0; i < npix; ++i) if (own[i] >= 0) H[i] = x[own[i] * 3 + 1];
     S L = S(0.0);
     for (int i = 0; i < npix; ++i) {
       const S e = (H[i] - target[i]) * inv_dx;
@@ -993,6 +1037,17 @@ int orc_surface_particles(const orc_config* c, int N, const double* state, int* 
   for (int q = 0; q < N; ++q) for (int a = 0; a < d; ++a) sim.x[q * 3 + a] = state[(size_t)q * sd + a];
   const std::vector<int> o = sim.surface_particles();
   for (size_t i = 0; i < o.size(); ++i) out[i] = o[i];
+  return (int)o.size();
+}
+
+// Height map of Eq. hm and its pixel owners (particle index, -1 for an empty
+// pixel) for the positions of a packed state.
+int orc_heightmap(const orc_config* c, int N, const double* state, double* hm, int* owner) {
+  Sim<double> sim(*c, N);
+  const int d = c->dim, sd = 2 * d + 2 * d * d;
+  for (int q = 0; q < N; ++q) for (int a = 0; a < d; ++a) sim.x[q * 3 + a] = state[(size_t)q * sd + a];
+  const std::vector<int> o = sim.heightmap_owners();
+  for (size_t i = 0; i < o.size(); ++i) { owner[i] = o[i]; hm[i] = o[i] >= 0 ? sim.x[o[i] * 3 + 1] : 0.0; }
   return (int)o.size();
 }
 

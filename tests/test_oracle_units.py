@@ -4,8 +4,10 @@ Each test checks the oracle against something other than itself: closed forms
 printed in the paper, textbook identities, a library routine on a special case,
 or brute force.  CPU only.
 """
+import itertools
 import math
 
+import mpmath as mp
 import numpy as np
 import pytest
 
@@ -424,6 +426,105 @@ def test_constitutive_tangent_near_apex(orc, d, gap):
         rt = 1e-5 if d == 3 else 1e-4
         np.testing.assert_allclose(dFn, fdF, rtol=rt, atol=rt * np.abs(fdF).max())
         np.testing.assert_allclose(dtau, fdT, rtol=rt, atol=rt * np.abs(fdT).max())
+
+
+def _mp_update(F, d, mu, lam, alpha, kc):
+    """F' = U diag(g) V^T and tau = U diag(h) U^T of one F_tmp in mpmath: the
+    singular values from mpmath's own SVD, then the return map of Eq. DP on
+    eps = ln s (with the cohesion shift) and the stress with det F' := 1."""
+    U, S, Vt = mp.svd_r(F)
+    s = [S[i] for i in range(d)]
+    eps = [mp.log(x) for x in s]
+    tr = mp.fsum(eps)
+    dev = [e - tr / d for e in eps]
+    nrm = mp.sqrt(mp.fsum([e * e for e in dev]))
+    stiff = d * lam + 2 * mu
+    tension = tr > 0 if kc == 0 else alpha * stiff * tr > kc
+    if tension:
+        ep, case = [kc / (d * alpha * stiff)] * d, 1
+    else:
+        dgam = nrm + stiff / (2 * mu) * tr * alpha - kc / (2 * mu)
+        if dgam <= 0:
+            ep, case = eps, 2
+        else:
+            ep, case = [e - dgam * x / nrm for e, x in zip(eps, dev)], 3
+    tre = mp.fsum(ep)
+    g = mp.diag([mp.exp(e) for e in ep])
+    h = mp.diag([2 * mu * e + lam * tre for e in ep])
+    return U * g * Vt, U * h * U.T, case
+
+
+@pytest.mark.parametrize("d", [2, 3])
+@pytest.mark.parametrize("state", ["cone_apex", "cone", "elastic", "tension"])
+@pytest.mark.parametrize("coh", [0.0, 500.0])
+@pytest.mark.parametrize("gap", [1e-6, 3e-9, 1e-10, 1e-12, 1e-14, 0.0])
+def test_constitutive_tangent_exact_near_ties(orc, d, state, coh, gap):
+    """The SVD-frame tangent of F_tmp -> (F', tau) at close or tied singular
+    values against the derivative of the same map evaluated at 80 digits
+    (mpmath SVD, Eq. DP on ln s, central difference with step 1e-35).
+    F_tmp is diagonal with decreasing entries, so the oracle's SVD frame is the
+    identity exactly and the comparison sees only its divided differences.
+    The strains are eps = (tr/d) 1 + dev with dev_0 - dev_1 = gap:
+    "cone_apex": projection onto the cone (Eq. DP, third case) with a deviator
+    as small as the gap, as for particles just off F = I (gap 3e-9 is a state
+    where a two-point quadrature of the divided difference misses by several
+    percent); "cone": the same case with a deviator of about 3e-3; "elastic":
+    inside the cone; "tension": the apex case.  coh = 500 Pa shifts the cone
+    (the cohesive variant), which puts the trace of the cone cases near the
+    shifted apex."""
+    E, nu, phi = 3.5e5, 0.3, 30.0
+    mu, lam, alpha, kc = orc.material(E, nu, phi, coh)
+    if d == 2 and gap == 0.0:
+        pytest.skip("an exact tie in 2D leaves no deviator")
+    g = gap if gap > 0 else 1e-9
+    if state == "cone":
+        raw = np.array([1e-3 + gap, 1e-3, -2e-3]) if d == 3 else np.array([gap, -2e-3])
+    else:
+        raw = np.array([g, 0.0 if gap > 0 else g, -1.5 * g]) if d == 3 else np.array([g, 0.0])
+    dev = raw - raw.mean()
+    nd = np.linalg.norm(dev)
+    stiff = d * lam + 2 * mu
+    tr = {"cone_apex": (kc - 0.3 * 2 * mu * nd) / (stiff * alpha),
+          "cone": (kc - 0.3 * 2 * mu * nd) / (stiff * alpha),
+          "elastic": (kc - 3.0 * 2 * mu * nd) / (stiff * alpha),
+          "tension": kc / (stiff * alpha) + 1e-3}[state]
+    s = np.exp(tr / d + dev)
+    if gap == 0.0:
+        s[1] = s[0]
+    assert np.all(np.diff(s) <= 0)
+    F = np.diag(s)
+    rng = np.random.default_rng(abs(hash((d, state, coh, gap))) % 2**32)
+    dF = rng.standard_normal((d, d))
+    cs, Fn, tau, dFn, dtau = orc.constitutive(F, E, nu, phi, coh, dFt=dF)
+    assert cs == {"cone_apex": 3, "cone": 3, "elastic": 2, "tension": 1}[state]
+    def reference(Fd):
+        with mp.workdps(80):
+            mF = mp.matrix([[mp.mpf(float(v)) for v in row] for row in Fd])
+            mdF = mp.matrix([[mp.mpf(float(v)) for v in row] for row in dF])
+            mu_, lam_, al_, kc_ = (mp.mpf(float(v)) for v in (mu, lam, alpha, kc))
+            h = mp.mpf("1e-35")
+            Fp, Tp, cp = _mp_update(mF + h * mdF, d, mu_, lam_, al_, kc_)
+            Fm, Tm, cm = _mp_update(mF - h * mdF, d, mu_, lam_, al_, kc_)
+            _, _, c0 = _mp_update(mF, d, mu_, lam_, al_, kc_)
+            assert cp == cm == c0 == cs, (cs, c0, cp, cm)
+            rF = np.array([[float((Fp[i, j] - Fm[i, j]) / (2 * h)) for j in range(d)] for i in range(d)])
+            rT = np.array([[float((Tp[i, j] - Tm[i, j]) / (2 * h)) for j in range(d)] for i in range(d)])
+        return rF, rT
+
+    rF, rT = reference(F)
+    # Near the cohesive model's shifted apex (trace about 3e-3, deviator down
+    # to 1e-14) the map itself is ill-conditioned in its FP64 inputs: the
+    # trace's distance from the apex and the deviator are differences of
+    # O(1e-3) logarithms.  There the bar is 1e-10 plus twice the change of the
+    # exact derivative when each singular value moves by one ulp, which no
+    # FP64 evaluation can go below.  Elsewhere the spread is far below 1e-10.
+    sF, sT = np.zeros_like(rF), np.zeros_like(rT)
+    if coh > 0 and state == "cone_apex":
+        for signs in itertools.product((-1.0, 1.0), repeat=d):
+            pF, pT = reference(np.diag(s * (1.0 + np.array(signs) * 2.0 ** -52)))
+            sF, sT = np.maximum(sF, np.abs(pF - rF)), np.maximum(sT, np.abs(pT - rT))
+    np.testing.assert_array_less(np.abs(dFn - rF), 1e-10 * np.abs(rF) + 2 * sF + 1e-12)
+    np.testing.assert_array_less(np.abs(dtau - rT), 1e-10 * np.abs(rT) + 2 * sT + 1e-12 * max(1.0, np.abs(rT).max()))
 
 
 @pytest.mark.parametrize("d", [2, 3])
