@@ -45,13 +45,15 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="sysid64", choices=["sysid64", "dig3d_bwd", "dig3d_large", "optim"])
+    ap.add_argument("--workload", default="sysid64",
+                    choices=["sysid64", "dig3d_bwd", "dig3d_large", "optim", "dig3d_fwd", "sysid64_fwd",
+                             "column2d_fwd"])
     ap.add_argument("--sub-steps", type=int, default=None, help="override rollout length (testing only)")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-gate", action="store_true")
     ap.add_argument("--sort-every", type=int, default=0,
-                    help="binning interval; 0 = autotune the batched context (the plain loop uses 8)")
+                    help="binning interval; 0 = autotune the batched context (the plain loop uses the same)")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--treat", default="none", choices=["none", "clip", "scale", "norm", "record"],
                     help="gradient treatment inside the reverse pass (Sec. III-E) at the paper's thresholds; "
@@ -65,7 +67,16 @@ def parse():
 
 
 def build_batch(args):
-    if args.workload == "sysid64":
+    if args.workload == "dig3d_fwd":
+        ws = [W.dig_3d(steps=500)]
+        name = "dig3d_fwd: 64^3 dig, 219488 particles, 500 sub-steps forward, FP32"
+    elif args.workload == "sysid64_fwd":
+        ws = W.sysid_batch(64, steps=500)
+        name = "sysid64_fwd: 64 instances, 64^3, N_i~U[20k,200k], 500 sub-steps forward, FP32"
+    elif args.workload == "column2d_fwd":
+        ws = [W.column_2d()]
+        name = "column2d_fwd: 2D column collapse, 64^2, 2432 particles, 200 sub-steps forward, FP64"
+    elif args.workload == "sysid64":
         ws = W.sysid_batch(64, steps=500)
         name = "sysid64: 64 instances, 64^3, N_i~U[20k,200k], 500 sub-steps fwd+bwd, K=50, FP32"
     elif args.workload == "dig3d_bwd":
@@ -122,27 +133,47 @@ def pick_record_segments(ddm, torch, ws, sort_every, spare=16 << 30):
     return best
 
 
-def algorithmic_bytes_p2g(ws, b=4, d=3):
+def algorithmic_bytes_p2g(n_particles, n_active, b=4, d=3):
     """P2G moves per particle the state it reads (x, v, C, G: (2d + 2d^2) b) and
-    the G' it writes (d^2 b); per occupied grid node the (d + 1) b it adds.
-    Occupied nodes ~ particles / ppc (the bed's cells) plus the halo."""
-    n = sum(w.n_particles for w in ws)
+    the G' it writes (d^2 b); per active grid node (m > 0) the (d + 1) b it adds."""
     per_particle = (2 * d + 2 * d * d) * b + d * d * b
-    nodes = sum(w.n_particles / w.ppc * 1.3 for w in ws)
-    return n * per_particle + nodes * (d + 1) * b
+    return n_particles * per_particle + n_active * (d + 1) * b
 
 
-def algorithmic_bytes_pass(ws, b=4, d=3):
+def algorithmic_bytes_pass(n_particles, n_active, b=4, d=3):
     """Bytes per particle-step that a fwd+bwd pass must move: per particle the
     state written and read in the forward (2 S_p), again in the recompute
     (2 S_p), read once more in the reverse step (S_p) and the adjoint read and
-    written (2 S_p), S_p = (2d + 2d^2) b; per occupied node, in the forward,
-    the recompute and the reverse step, m and mv written and read
+    written (2 S_p), S_p = (2d + 2d^2) b; per active node (m > 0), in the
+    forward, the recompute and the reverse step, m and mv written and read
     (2 (1 + d) b) and v written and read (2 d b)."""
-    n = sum(w.n_particles for w in ws)
     s_p = (2 * d + 2 * d * d) * b
-    nodes = sum(w.n_particles / w.ppc * 1.3 for w in ws)
-    return 7 * s_p + 3 * (2 * (1 + d) * b + 2 * d * b) * nodes / n
+    return 7 * s_p + 3 * (2 * (1 + d) * b + 2 * d * b) * n_active / n_particles
+
+
+def algorithmic_bytes_forward(n_particles, n_active, b=4, d=3):
+    """Bytes per particle-step of the forward sub-step: the state read and
+    written (2 S_p) and, per active node, m and mv written and read and v
+    written and read."""
+    s_p = (2 * d + 2 * d * d) * b
+    return 2 * s_p + (2 * (1 + d) * b + 2 * d * b) * n_active / n_particles
+
+
+def active_nodes(sim, x0, steps, samples=10):
+    """Mean number of grid nodes with m > 0 over a forward run of `steps`
+    sub-steps from x0 (all instances), sampled every steps/samples sub-steps
+    from the library's grid of the last sub-step."""
+    sim.init_state(x0)
+    every = max(1, steps // samples)
+    counts, done = [], 0
+    while done < steps:
+        k = min(every, steps - done)
+        sim.step(k)
+        done += k
+        g = sim.get_grid()
+        counts.append(int((g[:, :, 0] > 0).sum().item()))
+        del g
+    return float(np.mean(counts)), counts
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "p2g_sysid64_traffic.txt")
@@ -186,21 +217,45 @@ def copy_calibration(torch):
     del src, dst
 
 
-def cpu_baseline(ws):
-    """The FP64 oracle (single thread) with 9 forward-mode tangents on the
-    smallest instance of the batch, for about 15 s of work: the fwd+bwd-equivalent
-    rate."""
+def host_cpu():
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return model, os.cpu_count(), len(os.sched_getaffinity(0))
+
+
+def cpu_baseline(ws, grad=True, target_s=15.0):
+    """The FP64 oracle on one host core (pinned with sched_setaffinity) on the
+    smallest instance of the workload, for about `target_s` seconds of work:
+    with its 9 forward-mode tangents (the fwd+bwd-equivalent rate) when grad,
+    else the plain FP64 forward."""
     import oracle
     oracle.build(force=False)
     w = min(ws, key=lambda q: q.n_particles)
-    steps = int(min(60, max(1, round(1.3e6 / w.n_particles))))
+    rate_guess = 2.5e4 if grad else 2.5e5
+    steps = int(min(w.steps, max(1, round(target_s * rate_guess / w.n_particles))))
     s0 = oracle.initial_state(W.bed_positions(w))
-    t0 = time.perf_counter()
-    oracle.rollout(oracle.config(w), w.params, s0, steps, target=W.target_heightmap(w), grad=True)
-    dt = time.perf_counter() - t0
+    tgt = W.target_heightmap(w) if grad else None
+    old = os.sched_getaffinity(0)
+    core = min(old)
+    os.sched_setaffinity(0, {core})
+    try:
+        t0 = time.perf_counter()
+        oracle.rollout(oracle.config(w), w.params, s0, steps, target=tgt, grad=grad)
+        dt = time.perf_counter() - t0
+    finally:
+        os.sched_setaffinity(0, old)
+    model, ncpu, navail = host_cpu()
+    kind = "FP64 with 9 forward-mode tangents" if grad else "FP64 forward"
     return {"value": w.n_particles * steps / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"smallest instance ({w.n_particles} particles), {steps} sub-steps, FP64 with 9 "
-                      f"forward-mode tangents, {dt:.1f} s"}
+            "sample": f"smallest instance ({w.n_particles} particles), {steps} sub-steps, {kind}, {dt:.1f} s, "
+                      f"pinned to core {core}",
+            "host_cpu": model, "host_nproc": ncpu, "host_cpus_available": navail}
 
 
 def treatment_kwargs(args, steps):
@@ -239,6 +294,92 @@ def optimiser_bench(args, torch, ddm):
     print(json.dumps(out), flush=True)
 
 
+def forward_bench(args, torch, ddm):
+    """Forward sub-steps only (Algorithm 1, no recording, no reverse pass): one
+    step = init + the workload's sub-steps over the whole batch."""
+    ws, wname = build_batch(args)
+    prec = ws[0].precision
+    b, d, steps = (8 if prec == "f64" else 4), ws[0].dim, ws[0].steps
+    n = sum(w.n_particles for w in ws)
+    print(f"# workload {wname}: {len(ws)} instances, {n} particles", flush=True)
+    x0 = np.concatenate([W.bed_positions(w) for w in ws])
+    sim = ddm.Simulator(*configs(ddm, ws, args.sort_every or 8), stream=torch.cuda.Stream())
+    tuned = None
+    if not args.sort_every:
+        sim.init_state(x0)
+        tuned = sim.autotune()
+        print(f"# autotuned binning interval: every {tuned} sub-steps", flush=True)
+    R = tuned or args.sort_every
+    n_act, samples = active_nodes(sim, x0, steps)
+    print(f"# active grid nodes (m > 0), mean over the run: {n_act:.0f} (samples {samples})", flush=True)
+
+    def one(s, x):
+        s.init_state(x)
+        s.step(steps)
+
+    for i in range(args.warmup):
+        one(sim, x0)
+        torch.cuda.synchronize()
+        print(f"# warmup {i + 1}/{args.warmup} done", flush=True)
+    sim.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        one(sim, x0)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    timing = sim.read_timing()
+    sim.set_timing(False)
+    err = sim.check()
+    value = n * steps * args.steps / elapsed
+    print(f"# batched forward: {1e3 * elapsed / args.steps:.2f} ms/step, {value:.3e} particle-steps/s, "
+          f"device flags {err.flags}", flush=True)
+    del sim
+    torch.cuda.empty_cache()
+
+    plain_value = None
+    if len(ws) > 1 and not args.no_plain:
+        t_plain = 0.0
+        for w in ws:
+            ps = ddm.Simulator(*configs(ddm, [w], R))
+            xw = W.bed_positions(w)
+            one(ps, xw)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            one(ps, xw)
+            torch.cuda.synchronize()
+            t_plain += time.perf_counter() - t1
+            del ps
+        plain_value = n * steps / t_plain
+        print(f"# plain loop: {t_plain * 1e3:.1f} ms/step, {plain_value:.3e} particle-steps/s", flush=True)
+
+    p2g_ms, p2g_n = timing["p2g"]
+    per_launch = algorithmic_bytes_p2g(n, n_act, b, d)
+    achieved = per_launch / (p2g_ms / p2g_n * 1e-3) / 1e9 if p2g_n else None
+    fwd_bytes = algorithmic_bytes_forward(n, n_act, b, d)
+    bound = HBM_PEAK_GBS * 1e9 / fwd_bytes
+    cpu = None if args.no_cpu else cpu_baseline(ws, grad=False)
+    out = {
+        "metric": "particle-steps/s forward (Algorithm 1 sub-steps), batched vs plain",
+        "value": value, "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": prec, "data": "synthetic (seeded beds, no dataset)",
+        "config": {"workload": wname, "instances": len(ws), "particles": n, "sub_steps": steps,
+                   "sort_every": R, "sort_every_autotuned": tuned is not None, "plain_sort_every": R,
+                   "active_nodes_mean": n_act},
+        "plain_value": plain_value,
+        "batched_over_plain": (value / plain_value) if plain_value else None,
+        "kernel_ms": {k: {"ms": round(v[0], 3), "launches": v[1]} for k, v in timing.items() if v[1]},
+        "roofline": {"bound": "hbm", "kernel": "p2g", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
+                     "algorithmic_bytes": per_launch},
+        "pass_roofline": {"bytes_per_particle_step": fwd_bytes, "bound_value": bound, "unit": "particle-steps/s",
+                          "frac": value / bound},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -249,6 +390,9 @@ def main():
     import paper_2510_17335_amd as ddm
     if args.workload == "optim":
         optimiser_bench(args, torch, ddm)
+        return
+    if args.workload.endswith("_fwd"):
+        forward_bench(args, torch, ddm)
         return
     assert torch.cuda.is_available(), "needs a GPU"
     dev = torch.device("cuda:0")
@@ -270,6 +414,11 @@ def main():
         bp.sim.init_state(bp.x0)
         tuned = bp.sim.autotune()
         print(f"# autotuned binning interval: every {tuned} sub-steps", flush=True)
+    R = tuned or args.sort_every
+    n_part = sum(w.n_particles for w in ws)
+    n_act, act_samples = active_nodes(bp.sim, bp.x0, ws[0].steps)
+    print(f"# active grid nodes (m > 0), mean over the forward run: {n_act:.0f} (samples {act_samples})",
+          flush=True)
     for i in range(args.warmup):
         bp.run()
         torch.cuda.synchronize()
@@ -309,7 +458,7 @@ def main():
     # dominant kernel and its roofline (bytes moved per launch / measured launch time)
     dom = max(timing, key=lambda k: timing[k][0])
     p2g_ms, p2g_n = timing["p2g"]
-    per_launch_bytes = algorithmic_bytes_p2g(ws)
+    per_launch_bytes = algorithmic_bytes_p2g(n_part, n_act)
     achieved = per_launch_bytes / (p2g_ms / p2g_n * 1e-3) / 1e9 if p2g_n else None
     breakdown = {k: {"ms": round(v[0], 3), "launches": v[1]} for k, v in timing.items() if v[1]}
 
@@ -322,7 +471,7 @@ def main():
     if not args.no_plain:
         t_plain = 0.0
         for w in ws:
-            pp = Pass(ddm, [w], 8, record_segments=rseg)
+            pp = Pass(ddm, [w], R, record_segments=rseg)
             pp.run()
             torch.cuda.synchronize()
             t1 = time.perf_counter()
@@ -354,7 +503,7 @@ def main():
 
     cpu = None if args.no_cpu else cpu_baseline(ws)
     # the whole pass against the HBM roofline of its algorithmic bytes
-    pass_bytes = algorithmic_bytes_pass(ws)
+    pass_bytes = algorithmic_bytes_pass(n_part, n_act)
     pass_bound = HBM_PEAK_GBS * 1e9 / pass_bytes
     out = {
         "metric": METRIC,
@@ -371,7 +520,8 @@ def main():
         "data": "synthetic (seeded beds and targets, no dataset)",
         "config": {"workload": wname, "instances": len(ws), "particles": sum(w.n_particles for w in ws),
                    "sub_steps": ws[0].steps, "checkpoint_every": ws[0].checkpoint_every,
-                   "sort_every": tuned or args.sort_every, "sort_every_autotuned": tuned is not None,
+                   "sort_every": R, "sort_every_autotuned": tuned is not None, "plain_sort_every": R,
+                   "active_nodes_mean": n_act,
                    "record_segments": rseg,
                    "grad_treatment": args.treat,
                    "peak_mem_gb": round(peak_gb, 2)},

@@ -542,7 +542,8 @@ def _autograd_function():
                 (s.E, s.nu, s.phi_deg, s.rho, s.depth, s.angle_deg, s.push, s.displace,
                  s.push_angle_deg) = (float(v) for v in p[i])
                 insts.append(s)
-            sim = Simulator(cfg, insts, device=x0.device if isinstance(x0, torch.Tensor) else "cuda")
+            on_gpu = isinstance(x0, torch.Tensor) and x0.is_cuda
+            sim = Simulator(cfg, insts, device=x0.device if on_gpu else "cuda")
             sim.init_state(x0)
             sim.rollout(steps)
             loss = sim.loss(target)

@@ -12,6 +12,8 @@
 // after it.
 #include <hip/hip_runtime.h>
 
+#include <cstring>
+
 #include "ddm_device.hpp"
 #include "ddm_kernels.hpp"
 #include "ddm_state.hpp"
@@ -120,7 +122,8 @@ void launch_fill_zero(void* p, int64_t count, int elem_bytes, hipStream_t s) {
   launch_fill_u32(p, count * elem_bytes / 4, 0u, s);
 }
 
-template <typename T, int D>
+// XO: write the position rows and the ids only (the other rows are not there).
+template <typename T, int D, bool XO>
 __global__ void k_init_state(KCfg c, Bufs b, const T* __restrict__ x0, void* state, uint32_t* pid) {
   const int inst = b.blk_inst[blockIdx.x];
   const InstDev& I = b.inst[inst];
@@ -134,6 +137,7 @@ __global__ void k_init_state(KCfg c, Bufs b, const T* __restrict__ x0, void* sta
 #pragma unroll
   for (int a = 0; a < D; ++a) {
     st.xr(a, p) = Pos<T>::from_real(live ? (double)x0[(src + local) * D + a] : 0.5);
+    if (XO) continue;
     st.v(a, p) = T(0);
 #pragma unroll
     for (int bb = 0; bb < D; ++bb) { st.C(a, bb, p) = T(0); st.G(a, bb, p) = T(0); }
@@ -142,14 +146,30 @@ __global__ void k_init_state(KCfg c, Bufs b, const T* __restrict__ x0, void* sta
 }
 
 void launch_init_state(int prec, const KCfg& c, const Bufs& b, int nblk, const void* x0, void* state,
-                       uint32_t* pid, hipStream_t s) {
+                       uint32_t* pid, hipStream_t s, bool positions_only) {
+#define DDM_INIT(T, DD, XO) \
+  hipLaunchKernelGGL((k_init_state<T, DD, XO>), dim3(nblk), dim3(kBlock), 0, s, c, b, (const T*)x0, state, pid)
   if (prec == 0) {
-    if (c.dim == 3) hipLaunchKernelGGL((k_init_state<float, 3>), dim3(nblk), dim3(kBlock), 0, s, c, b, (const float*)x0, state, pid);
-    else hipLaunchKernelGGL((k_init_state<float, 2>), dim3(nblk), dim3(kBlock), 0, s, c, b, (const float*)x0, state, pid);
+    if (c.dim == 3) { if (positions_only) DDM_INIT(float, 3, true); else DDM_INIT(float, 3, false); }
+    else { if (positions_only) DDM_INIT(float, 2, true); else DDM_INIT(float, 2, false); }
   } else {
-    if (c.dim == 3) hipLaunchKernelGGL((k_init_state<double, 3>), dim3(nblk), dim3(kBlock), 0, s, c, b, (const double*)x0, state, pid);
-    else hipLaunchKernelGGL((k_init_state<double, 2>), dim3(nblk), dim3(kBlock), 0, s, c, b, (const double*)x0, state, pid);
+    if (c.dim == 3) { if (positions_only) DDM_INIT(double, 3, true); else DDM_INIT(double, 3, false); }
+    else { if (positions_only) DDM_INIT(double, 2, true); else DDM_INIT(double, 2, false); }
   }
+#undef DDM_INIT
+}
+
+// Copies a small host blob (passed by value as the kernel argument) to device memory.
+struct Blob { uint32_t w[kBlobWords]; };
+__global__ void k_put_blob(uint32_t* dst, Blob b, int words) {
+  for (int i = threadIdx.x; i < words; i += blockDim.x) dst[i] = b.w[i];
+}
+
+void launch_put_bytes(void* dst, const void* src, size_t bytes, hipStream_t s) {
+  Blob b;
+  memset(&b, 0, sizeof(b));
+  memcpy(b.w, src, bytes);
+  hipLaunchKernelGGL(k_put_blob, dim3(1), dim3(64), 0, s, static_cast<uint32_t*>(dst), b, (int)((bytes + 3) / 4));
 }
 
 // ---------------------------------------------------------------------------
@@ -621,7 +641,10 @@ __global__ void __launch_bounds__(kBlock) k_grid_update(KCfg c, Bufs b, int step
   const uint32_t nact = *act.count;
   if (count_out && blockIdx.x == 0 && threadIdx.x == 0) *count_out = nact;
   const int64_t items = (int64_t)nact * NPB;
-  for (int64_t it = (int64_t)blockIdx.x * kBlock + threadIdx.x; it < items; it += (int64_t)gridDim.x * kBlock) {
+  // nodes of neighbouring blocks gather the same staged windows: one XCD takes a run of blocks
+  const XcdSpan sp = xcd_span(blockIdx.x, gridDim.x, (uint64_t)items, kBlock);
+  for (int64_t it = (int64_t)sp.lo + (int64_t)sp.rank * kBlock + threadIdx.x; it < (int64_t)sp.hi;
+       it += (int64_t)sp.count * kBlock) {
     const uint32_t gb = act.list[it / NPB];
     const int k = (int)(it % NPB);
     if (list_out && k == 0) list_out[it / NPB] = gb;
@@ -680,7 +703,7 @@ static unsigned active_grid(const KCfg& c) {
   const int64_t total_tiles = (c.nodes >> tshift) * c.n_inst;
   const int64_t items = total_tiles << tshift;
   const int64_t nb = (items + kBlock - 1) / kBlock;
-  return (unsigned)(nb < 4096 ? nb : 4096);
+  return xcd_round((unsigned)(nb < 4096 ? nb : 4096));
 }
 
 void launch_grid_post_from_pre(int prec, const KCfg& c, const Bufs& b, int step, const uint32_t* list,
@@ -826,9 +849,11 @@ __device__ __forceinline__ bool g2p_compute(const KCfg& c, const Bufs& b, int in
 template <typename T, int D, bool PC>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PC || sizeof(T) == 8 ? 1 : 6)))
 k_g2p(KCfg c, Bufs b, int step, const void* st_in, void* st_out, const T* __restrict__ post) {
-  const int inst = b.blk_inst[blockIdx.x];
+  const uint32_t blk = xcd_local(blockIdx.x, gridDim.x);      // neighbouring blocks share grid nodes
+  if (blk >= (uint32_t)(c.ntot / kBlock)) return;
+  const int inst = b.blk_inst[blk];
   const InstDev& I = b.inst[inst];
-  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t p = (int64_t)blk * kBlock + threadIdx.x;
   const P<T, D> si = pv<T, D>(st_in, c.ntot), so = pv<T, D>(st_out, c.ntot);
   if (p - I.off >= I.n) {
     // padding slots keep a harmless position so they never trip a check
@@ -854,7 +879,7 @@ k_g2p(KCfg c, Bufs b, int step, const void* st_in, void* st_out, const T* __rest
 void launch_g2p(int prec, const KCfg& c, const Bufs& b, int nblk, int step, const void* st_in, void* st_out,
                 const void* post, hipStream_t s) {
 #define DDM_G2P(T, DD, PC) \
-  hipLaunchKernelGGL((k_g2p<T, DD, PC>), dim3(nblk), dim3(kBlock), 0, s, c, b, step, st_in, st_out, (const T*)post)
+  hipLaunchKernelGGL((k_g2p<T, DD, PC>), dim3(xcd_round(nblk)), dim3(kBlock), 0, s, c, b, step, st_in, st_out, (const T*)post)
   const bool pc = c.pcontact != 0;
   if (prec == 0) {
     if (c.dim == 3) { if (pc) DDM_G2P(float, 3, true); else DDM_G2P(float, 3, false); }
@@ -1209,7 +1234,9 @@ __global__ void __launch_bounds__(kBlock) k_g2p_adj(KCfg c, Bufs b, TileList tl,
   const Adj<T, D> an = av<T, D>(adj_next, c.ntot), ac = av<T, D>(adj_cur, c.ntot);
   const T dx = T(c.dx), inv_dx = T(c.inv_dx), Dk = T(4.0 * c.inv_dx * c.inv_dx);
   constexpr int WS = Win<D>::stride;
-  for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+  // neighbouring tiles stage overlapping windows of the grid: one XCD takes a run of them
+  const XcdSpan sp = xcd_span(blockIdx.x, gridDim.x, ntiles);
+  for (uint32_t t = (uint32_t)sp.lo + sp.rank; t < sp.hi; t += sp.count) {
     const TileRec tr = tl.list[t];
     int inst, org[3];
     tile_origin<D>(c, tr.tile, inst, org);
@@ -1355,11 +1382,11 @@ __global__ void __launch_bounds__(kBlock) k_g2p_adj(KCfg c, Bufs b, TileList tl,
 void launch_g2p_adj(int prec, const KCfg& c, const Bufs& b, const TileList& tl, int nwg, const void* st,
                     const void* post, const void* adj_next, void* adj_cur, void* gvb, hipStream_t s) {
   if (prec == 0) {
-    if (c.dim == 3) hipLaunchKernelGGL((k_g2p_adj<float, 3>), dim3(nwg), dim3(kBlock), 0, s, c, b, tl, st, (const float*)post, adj_next, adj_cur, (float*)gvb);
-    else hipLaunchKernelGGL((k_g2p_adj<float, 2>), dim3(nwg), dim3(kBlock), 0, s, c, b, tl, st, (const float*)post, adj_next, adj_cur, (float*)gvb);
+    if (c.dim == 3) hipLaunchKernelGGL((k_g2p_adj<float, 3>), dim3(xcd_round(nwg)), dim3(kBlock), 0, s, c, b, tl, st, (const float*)post, adj_next, adj_cur, (float*)gvb);
+    else hipLaunchKernelGGL((k_g2p_adj<float, 2>), dim3(xcd_round(nwg)), dim3(kBlock), 0, s, c, b, tl, st, (const float*)post, adj_next, adj_cur, (float*)gvb);
   } else {
-    if (c.dim == 3) hipLaunchKernelGGL((k_g2p_adj<double, 3>), dim3(nwg), dim3(kBlock), 0, s, c, b, tl, st, (const double*)post, adj_next, adj_cur, (double*)gvb);
-    else hipLaunchKernelGGL((k_g2p_adj<double, 2>), dim3(nwg), dim3(kBlock), 0, s, c, b, tl, st, (const double*)post, adj_next, adj_cur, (double*)gvb);
+    if (c.dim == 3) hipLaunchKernelGGL((k_g2p_adj<double, 3>), dim3(xcd_round(nwg)), dim3(kBlock), 0, s, c, b, tl, st, (const double*)post, adj_next, adj_cur, (double*)gvb);
+    else hipLaunchKernelGGL((k_g2p_adj<double, 2>), dim3(xcd_round(nwg)), dim3(kBlock), 0, s, c, b, tl, st, (const double*)post, adj_next, adj_cur, (double*)gvb);
   }
 }
 
@@ -1594,12 +1621,14 @@ __device__ __forceinline__ void ftmp_of(const P<T, D>& st, int64_t p, T dt, T Cm
     }
 }
 
-template <typename T, int D>
+template <typename T, int D, bool SF>
 __global__ void __launch_bounds__(kBlock) k_p2g_adj_gather(KCfg c, Bufs b, const void* stv, const T* __restrict__ tau,
                                                            const T* __restrict__ gbar, void* adj_cur, double* pacc) {
-  const int inst = b.blk_inst[blockIdx.x];
+  const uint32_t blk = xcd_local(blockIdx.x, gridDim.x);      // neighbouring blocks share grid nodes
+  if (blk >= (uint32_t)(c.ntot / kBlock)) return;
+  const int inst = b.blk_inst[blk];
   const InstDev& I = b.inst[inst];
-  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t p = (int64_t)blk * kBlock + threadIdx.x;
   double acc[1] = {0.0};
   if (p - I.off < I.n) {
     const P<T, D> st = pv<T, D>(stv, c.ntot);
@@ -1627,6 +1656,16 @@ __global__ void __launch_bounds__(kBlock) k_p2g_adj_gather(KCfg c, Bufs b, const
       //   A bar          sum w_o g_v r_o^T
       //   x bar         += sum grad w_o (m_p g_m + g_v . t_o) - A^T G
       // The sums run along the last axis first and are factored by axis.
+      // Density: every particle of an instance has the mass m_p = rho V_p,
+      // so node o's mass m_o and the part mv_o - f_o of its momentum that is
+      // not stress (f_o = sum_p w_op S_p r_op, S_p = k tau_p) are linear in
+      // rho.  Without a gradient treatment of the grid adjoints the grid
+      // update's adjoint gives g_m = -g_v . mv_o / m_o, and the sub-step's
+      // density adjoint sum_o (g_m m_o + g_v . (mv_o - f_o)) / rho reduces to
+      // -sum_o g_v . f_o / rho = -sum_p (S_p : A bar_p) / rho.  That form is
+      // used then: the mass form sum_o w_o (g_m + g_v . (v + C r_o)) is a
+      // near-cancelling sum whose terms carry the FP32 rounding of g_m and
+      // g_v (of order eps |g_v| |v|).
       T xb[3];
 #pragma unroll
       for (int a = 0; a < D; ++a) xb[a] = ac.x(a, p);     // G2P part, written by k_g2p_adj
@@ -1708,7 +1747,16 @@ __global__ void __launch_bounds__(kBlock) k_p2g_adj_gather(KCfg c, Bufs b, const
 #pragma unroll
         for (int bb = 0; bb < D; ++bb) { ac.C(a, bb, p) = Ab[a][bb]; mpb += Ab[a][bb] * Cm[a][bb]; }
       }
-      acc[0] = (double)mpb * I.Vp;
+      if (SF) {
+        T sab = T(0);
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+#pragma unroll
+          for (int bb = 0; bb < D; ++bb) sab += tau[(int64_t)sym_row<D>(a, bb) * c.ntot + p] * Ab[a][bb];
+        acc[0] = -(double)(k_str * sab) * (I.Vp / I.mp);
+      } else {
+        acc[0] = (double)mpb * I.Vp;
+      }
     }
   }
   block_accumulate<1>(acc, pacc + (int64_t)inst * 8 + 4);
@@ -1764,10 +1812,14 @@ __global__ void __launch_bounds__(kBlock) k_p2g_adj_constit(KCfg c, Bufs b, cons
 }
 
 void launch_p2g_adj(int prec, const KCfg& c, const Bufs& b, int nblk, const void* st, const void* tau, const void* gb,
-                    const void* adj_next, void* adj_cur, double* pacc, hipStream_t s) {
+                    bool stress_form, const void* adj_next, void* adj_cur, double* pacc, hipStream_t s) {
 #define DDM_P2GADJ(T, DD)                                                                                          \
-  hipLaunchKernelGGL((k_p2g_adj_gather<T, DD>), dim3(nblk), dim3(kBlock), 0, s, c, b, st, (const T*)tau, (const T*)gb, \
-                     adj_cur, pacc);                                                                                \
+  if (stress_form)                                                                                                 \
+    hipLaunchKernelGGL((k_p2g_adj_gather<T, DD, true>), dim3(xcd_round(nblk)), dim3(kBlock), 0, s, c, b, st,      \
+                       (const T*)tau, (const T*)gb, adj_cur, pacc);                                                \
+  else                                                                                                             \
+    hipLaunchKernelGGL((k_p2g_adj_gather<T, DD, false>), dim3(xcd_round(nblk)), dim3(kBlock), 0, s, c, b, st,     \
+                       (const T*)tau, (const T*)gb, adj_cur, pacc);                                                \
   hipLaunchKernelGGL((k_p2g_adj_constit<T, DD>), dim3(nblk), dim3(kBlock), 0, s, c, b, st, adj_next, adj_cur, pacc);
   if (prec == 0) {
     if (c.dim == 3) { DDM_P2GADJ(float, 3) } else { DDM_P2GADJ(float, 2) }

@@ -15,6 +15,33 @@ constexpr int kParams = 4 + kSkillParams;   // gradient entries per instance
 constexpr int kTile = 4;             // binning tile edge in cells
 constexpr int kWin = kTile + 4;      // LDS window edge in nodes: tile + stencil + 1-cell drift each side
 
+// XCD-aware work mapping.  An MI355X has 8 XCDs, each with its own L2, and
+// hands the workgroups of a launch to them round-robin (workgroup w runs on
+// XCD w % 8).  Kernels whose neighbouring work items gather the same grid
+// nodes renumber their workgroups so that every XCD takes one contiguous
+// eighth of the work: the shared nodes then meet in one L2.  Such kernels are
+// launched with a multiple of kXcds workgroups (xcd_round).
+constexpr uint32_t kXcds = 8;
+inline uint32_t xcd_round(uint32_t n) { return (n + kXcds - 1) / kXcds * kXcds; }
+// Logical index of workgroup w in a launch of `grid` workgroups.
+__device__ __forceinline__ uint32_t xcd_local(uint32_t w, uint32_t grid) {
+  return (w % kXcds) * (grid / kXcds) + w / kXcds;
+}
+// The part [lo, hi) of `n` work items that the XCD of workgroup w takes (lo a
+// multiple of `align`), and the workgroup's rank and count among that XCD's
+// workgroups.
+struct XcdSpan { uint64_t lo, hi; uint32_t rank, count; };
+__device__ __forceinline__ XcdSpan xcd_span(uint32_t w, uint32_t grid, uint64_t n, uint64_t align = 1) {
+  const uint64_t chunk = ((n + kXcds - 1) / kXcds + align - 1) / align * align;
+  const uint32_t x = w % kXcds;
+  XcdSpan s;
+  s.lo = x * chunk < n ? x * chunk : n;
+  s.hi = s.lo + chunk < n ? s.lo + chunk : n;
+  s.rank = w / kXcds;
+  s.count = grid / kXcds;
+  return s;
+}
+
 // An occupied tile: slots [start, end) of the sorted state, global tile id.
 // Tiles and grid node blocks share one index space: tile t holds the cells
 // [4t, 4t + 4) per axis and node block t the nodes [4t, 4t + 4).
@@ -90,8 +117,14 @@ struct Bufs {
 void launch_fill_zero(void* p, int64_t count, int elem_bytes, hipStream_t s);
 void launch_eval_math(int fn, const float* x, float* y, int64_t n, hipStream_t s);
 void launch_fill_u32(void* p, int64_t words, uint32_t value, hipStream_t s);
+// Particle state from positions x0[n][D] (instances concatenated): v = 0, C = 0,
+// G = 0 and ids; positions_only writes the position rows and ids alone.
 void launch_init_state(int prec, const KCfg& c, const Bufs& b, int nblk, const void* x0, void* state,
-                       uint32_t* pid, hipStream_t s);
+                       uint32_t* pid, hipStream_t s, bool positions_only = false);
+// Up to kBlobWords * 4 bytes from host memory to device memory, carried in the
+// arguments of a one-block kernel (no host buffer has to outlive the call).
+constexpr int kBlobWords = 128;
+void launch_put_bytes(void* dst, const void* src, size_t bytes, hipStream_t s);
 // P2G writes every occupied tile's window to the staging buffer; particles
 // that left their window add to the dense outlier grid gout (kept zero
 // otherwise) and add their node blocks to the active set.
@@ -149,8 +182,11 @@ void launch_pcontact_adj(int prec, const KCfg& c, const Bufs& b, int nblk, int s
 // Over the active blocks (list, count) of the sub-step; zeroes gvb where it read it.
 void launch_grid_adj(int prec, const KCfg& c, const Bufs& b, int step, const uint32_t* list, const uint32_t* count,
                      const void* grid_pre, void* gvb, void* gb, double* pose_bar, hipStream_t s);
+// stress_form: the density adjoint of the sub-step as -sum_p (S_p : A bar_p) / rho,
+// S_p the stress part of A_p (valid while the grid adjoints are untreated,
+// where m bar = -v bar . (mv/m) / m holds); otherwise from the grid mass adjoint.
 void launch_p2g_adj(int prec, const KCfg& c, const Bufs& b, int nblk, const void* st, const void* tau, const void* gb,
-                    const void* adj_next, void* adj_cur, double* pacc, hipStream_t s);
+                    bool stress_form, const void* adj_next, void* adj_cur, double* pacc, hipStream_t s);
 void launch_grad_final(const KCfg& c, const InstDev* inst, const double* pacc, const double* pose_bar,
                        const double* pose_jac, int n_steps, const double* dloss, double* grad, hipStream_t s);
 

@@ -603,6 +603,59 @@ ddm_status run_segment(ddm_ctx* x, int m, int64_t k_first, int len, const void* 
 // cohesion shift from the friction angle, particle mass and volume, and their
 // derivatives for the final chain rule), the block-to-instance map, and the
 // pose table with its Jacobian; uploaded with synchronous copies.
+// Kernel configuration of a context (or of a context-free call) with
+// n_inst instances and ntot padded particle slots.
+ddm::KCfg make_kcfg(const ddm_config& c, int n_inst, int64_t ntot) {
+  ddm::KCfg k;
+  k.dim = c.dim; k.n = c.n_grid; k.bound = c.bound; k.shovel = c.shovel;
+  k.pcontact = c.particle_contact != 0 ? 1 : 0;
+  k.nlog2 = 0;
+  while ((1 << k.nlog2) < c.n_grid) ++k.nlog2;
+  k.hm_res = c.hm_res; k.region_sign = c.region_sign >= 0 ? 1 : -1; k.n_inst = n_inst;
+  k.max_steps = c.max_steps;
+  k.nodes = 1;
+  for (int a = 0; a < c.dim; ++a) k.nodes *= c.n_grid;
+  k.ntot = ntot;
+  k.dx = 1.0 / c.n_grid; k.inv_dx = (double)c.n_grid; k.gravity = c.gravity;
+  k.skin = c.contact_skin; k.mu_b = c.shovel_mu;
+  for (int a = 0; a < 3; ++a) k.half[a] = c.shovel_half[a];
+  k.hm_ox = c.hm_origin[0]; k.hm_oz = c.hm_origin[1]; k.hm_pix = c.hm_size / c.hm_res;
+  k.hm_off = c.hm_offset; k.region_depth = c.region_depth;
+  k.w_hm = c.w_hm; k.w_mass = c.w_mass; k.m_target = c.m_target; k.m_ref = c.m_ref;
+  k.w_emd = c.w_emd;
+  return k;
+}
+
+// Device constants of instance i: Lame constants, alpha_f and the cohesion
+// shift (Sec. III-A, Eq. DP), particle mass and volume, the chain to
+// (E, nu, phi_deg), its first padded slot `off` and its grid offset.
+ddm::InstDev make_instdev(const ddm_config& c, const ddm_instance& s, int i, int64_t off, int64_t nodes) {
+  ddm::InstDev d;
+  const double dxd = std::pow(1.0 / c.n_grid, c.dim);
+  const double E = s.E, nu = s.nu, ph = s.phi_deg * kPi / 180.0, sp = std::sin(ph), cp = std::cos(ph);
+  d.mu = E / (2.0 * (1.0 + nu));
+  d.lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+  const double r23 = std::sqrt(2.0 / 3.0);
+  d.alpha = r23 * 2.0 * sp / (3.0 - sp);
+  d.kc = r23 * 6.0 * s.cohesion * cp / (3.0 - sp);
+  d.Vp = dxd / c.ppc;
+  d.mp = s.rho * d.Vp;
+  d.dt = s.dt;
+  d.dmu_dE = 1.0 / (2.0 * (1.0 + nu));
+  d.dmu_dnu = -E / (2.0 * (1.0 + nu) * (1.0 + nu));
+  const double den = (1.0 + nu) * (1.0 - 2.0 * nu);
+  d.dlam_dE = nu / den;
+  d.dlam_dnu = E * (1.0 + 2.0 * nu * nu) / (den * den);
+  const double rad = kPi / 180.0;
+  d.dal_dphi = r23 * 6.0 * cp / ((3.0 - sp) * (3.0 - sp)) * rad;
+  d.dkc_dphi = r23 * 6.0 * s.cohesion * (1.0 - 3.0 * sp) / ((3.0 - sp) * (3.0 - sp)) * rad;
+  d.off = off;
+  d.n = s.n_particles;
+  d.goff = (int64_t)i * nodes;
+  for (int a = 0; a < 3; ++a) d.tip0[a] = s.tip0[a];
+  return d;
+}
+
 ddm_status upload_instances(ddm_ctx* x, const ddm_instance* inst) {
   const ddm_config* cfg = &x->cfg;
   const Layout& L = x->L;
@@ -612,31 +665,9 @@ ddm_status upload_instances(ddm_ctx* x, const ddm_instance* inst) {
   std::vector<ddm::InstDev> dev(n_inst);
   std::vector<int> blk((size_t)L.nblk);
   int64_t off = 0;
-  const double dxd = std::pow(1.0 / cfg->n_grid, cfg->dim);
   for (int i = 0; i < n_inst; ++i) {
     const ddm_instance& s = inst[i];
-    ddm::InstDev& d = dev[i];
-    const double E = s.E, nu = s.nu, ph = s.phi_deg * kPi / 180.0, sp = std::sin(ph), cp = std::cos(ph);
-    d.mu = E / (2.0 * (1.0 + nu));
-    d.lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
-    const double r23 = std::sqrt(2.0 / 3.0);
-    d.alpha = r23 * 2.0 * sp / (3.0 - sp);
-    d.kc = r23 * 6.0 * s.cohesion * cp / (3.0 - sp);
-    d.Vp = dxd / cfg->ppc;
-    d.mp = s.rho * d.Vp;
-    d.dt = s.dt;
-    d.dmu_dE = 1.0 / (2.0 * (1.0 + nu));
-    d.dmu_dnu = -E / (2.0 * (1.0 + nu) * (1.0 + nu));
-    const double den = (1.0 + nu) * (1.0 - 2.0 * nu);
-    d.dlam_dE = nu / den;
-    d.dlam_dnu = E * (1.0 + 2.0 * nu * nu) / (den * den);
-    const double rad = kPi / 180.0;
-    d.dal_dphi = r23 * 6.0 * cp / ((3.0 - sp) * (3.0 - sp)) * rad;
-    d.dkc_dphi = r23 * 6.0 * s.cohesion * (1.0 - 3.0 * sp) / ((3.0 - sp) * (3.0 - sp)) * rad;
-    d.off = off;
-    d.n = s.n_particles;
-    d.goff = (int64_t)i * k.nodes;
-    for (int a = 0; a < 3; ++a) d.tip0[a] = s.tip0[a];
+    dev[i] = make_instdev(*cfg, s, i, off, k.nodes);
     const int64_t np = pad_up(s.n_particles, ddm::kBlock);
     for (int64_t bI = off / ddm::kBlock; bI < (off + np) / ddm::kBlock; ++bI) blk[(size_t)bI] = i;
     off += np;
@@ -745,23 +776,7 @@ ddm_status ddm_create(const ddm_config* cfg, int32_t n_inst, const ddm_instance*
   x->ws = static_cast<char*>(workspace);
   x->stream = static_cast<hipStream_t>(stream);
   x->prec = cfg->precision == DDM_F64 ? 1 : 0;
-  ddm::KCfg& k = x->kc;
-  k.dim = cfg->dim; k.n = cfg->n_grid; k.bound = cfg->bound; k.shovel = cfg->shovel;
-  k.pcontact = cfg->particle_contact != 0 ? 1 : 0;
-  k.nlog2 = 0;
-  while ((1 << k.nlog2) < cfg->n_grid) ++k.nlog2;
-  k.hm_res = cfg->hm_res; k.region_sign = cfg->region_sign >= 0 ? 1 : -1; k.n_inst = n_inst;
-  k.max_steps = cfg->max_steps;
-  k.nodes = 1;
-  for (int a = 0; a < cfg->dim; ++a) k.nodes *= cfg->n_grid;
-  k.ntot = L.ntot;
-  k.dx = 1.0 / cfg->n_grid; k.inv_dx = (double)cfg->n_grid; k.gravity = cfg->gravity;
-  k.skin = cfg->contact_skin; k.mu_b = cfg->shovel_mu;
-  for (int a = 0; a < 3; ++a) k.half[a] = cfg->shovel_half[a];
-  k.hm_ox = cfg->hm_origin[0]; k.hm_oz = cfg->hm_origin[1]; k.hm_pix = cfg->hm_size / cfg->hm_res;
-  k.hm_off = cfg->hm_offset; k.region_depth = cfg->region_depth;
-  k.w_hm = cfg->w_hm; k.w_mass = cfg->w_mass; k.m_target = cfg->m_target; k.m_ref = cfg->m_ref;
-  k.w_emd = cfg->w_emd;
+  x->kc = make_kcfg(*cfg, n_inst, L.ntot);
 
   s = upload_instances(x, inst);
   if (s == DDM_OK) s = hip_check(hipMemset(x->at(L.err), 0, sizeof(ddm::DevErr)), "clear error word");
@@ -1025,7 +1040,8 @@ ddm_status ddm_backward(ddm_ctx* x, const double* dloss_dev, double* grad_dev) {
         Timed t(x, 9);
         treat_vectors(x, rec, TreatTarget{true, x->at(L.gb), x->seg_alist(m, j), x->seg_acount(m, j), 4, true});
       }
-      { Timed t(x, 6); ddm::launch_p2g_adj(x->prec, x->kc, b, (int)L.nblk, slot(j), tau(j), x->at(L.gb), adj[cur], adj[1 - cur],
+      { Timed t(x, 6); ddm::launch_p2g_adj(x->prec, x->kc, b, (int)L.nblk, slot(j), tau(j), x->at(L.gb),
+                                           x->treat.mode == ddm::kTreatNone, adj[cur], adj[1 - cur],
                                            x->at<double>(L.pacc), st); }
       if (treat) {
         Timed t(x, 9);
@@ -1326,5 +1342,6 @@ void ddm_destroy(ddm_ctx* x) {
   }
   delete x;
 }
+
 
 }  // extern "C"

@@ -1,0 +1,140 @@
+"""Parity at the full horizons and sizes of the benchmark workloads.
+
+* The 64-instance batch (64^3 grids, N_i ~ U[20k, 200k], FP32, K = 50, the
+  benchmark's binning interval) against FP64 oracle results stored by
+  tests/golden/make_sysid64_oracle.py: the state of four sampled instances
+  after 200 sub-steps on a seeded sample of 1024 particles each (<= 1e-4 per
+  field) and the smallest instance's loss and gradient after the full 500
+  sub-steps (<= 1e-3).
+* The 64^3 dig with the backward workload's length (219 488 particles, 1000
+  sub-steps, K = 50) in FP64: the reverse pass's gradient of the 7 parameters
+  against central differences of the same library's loss at steps of 1e-4
+  and 2e-5 relative (Eq. grad-chain; Eq. po/pa).
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "sysid64_oracle.npz")
+
+
+def _log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ddm():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2510_17335_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def golden():
+    with np.load(GOLDEN, allow_pickle=False) as z:
+        return {k: z[k] for k in z.files}
+
+
+def _batch(ddm, steps, sort_every=32):
+    ws = W.sysid_batch(64, steps=steps)
+    cfgs = [ddm.from_workload(w, max_steps=steps, checkpoint_every=50, sort_every=sort_every) for w in ws]
+    sim = ddm.Simulator(cfgs[0][0], [c[1] for c in cfgs])
+    return ws, sim
+
+
+@pytest.mark.timeout(600)
+def test_sysid64_states_after_200_sub_steps(ddm, golden):
+    steps = int(golden["state_steps"])
+    ws, sim = _batch(ddm, steps)
+    _log(f"case sysid64 batch FP32, {steps} sub-steps, states of instances {golden['instances'].tolist()}")
+    sim.init_state(np.concatenate([W.bed_positions(w) for w in ws]))
+    sim.step(steps)
+    err = sim.check()
+    assert err.flags == 0 and err.clamp_count == 0, err.flags
+    st = sim.get_state()
+    for i in golden["instances"].tolist():
+        got = np.concatenate([t.reshape(t.shape[0], -1).cpu().numpy() for t in sim.instance_state(st, i)], 1)
+        idx, ref = golden[f"idx_{i}"], golden[f"state_{i}"]
+        got = got[idx]
+        e = {}
+        for k, sl in {"x": slice(0, 3), "v": slice(3, 6), "C": slice(6, 15), "F": slice(15, 24)}.items():
+            e[k] = np.linalg.norm(got[:, sl] - ref[:, sl]) / np.linalg.norm(ref[:, sl])
+        _log(f"instance {i} N={ws[i].n_particles}: per-field errors on the sample", e)
+        for k, v in e.items():
+            assert v < 1e-4, (i, k, v)
+
+
+@pytest.mark.timeout(600)
+def test_sysid64_smallest_gradient_after_500_sub_steps(ddm, golden):
+    steps = int(golden["grad_steps"])
+    ws, sim = _batch(ddm, steps)
+    i = int(golden["grad_instance"])
+    _log(f"case sysid64 batch FP32 fwd+bwd, {steps} sub-steps, gradient of instance {i}")
+    sim.init_state(np.concatenate([W.bed_positions(w) for w in ws]))
+    sim.rollout(steps)
+    loss = sim.loss(np.stack([W.target_heightmap(w) for w in ws])).cpu().numpy()
+    grad = sim.backward().cpu().numpy()
+    err = sim.check()
+    assert err.flags == 0 and err.clamp_count == 0, err.flags
+    ref = golden["grad"]
+    rel = np.abs(grad[i] - ref) / np.maximum(np.abs(ref), 1e-6 * np.abs(ref).max())
+    _log(f"loss {loss[i]} vs {float(golden['loss'])}\ngpu {grad[i]}\noracle {ref}\nrel {rel}")
+    assert abs(loss[i] - float(golden["loss"])) <= 1e-4 * abs(float(golden["loss"]))
+    assert np.all(rel < 1e-3), rel
+
+
+@pytest.mark.timeout(900)
+def test_dig3d_backward_full_size_vs_central_differences(ddm):
+    import torch
+    w = W.dig_3d_backward()
+    w.precision = "f64"
+    steps = w.steps
+    tg = W.target_heightmap(w)[None]
+    x0 = W.bed_positions(w)
+    cfg, inst = ddm.from_workload(w, max_steps=steps, checkpoint_every=50)
+    sim = ddm.Simulator(cfg, [inst])
+    _log(f"case dig3d_bwd FP64 {w.n_particles} particles, {steps} sub-steps: reverse pass vs central differences")
+    sim.init_state(x0)
+    sim.rollout(steps)
+    L0 = float(sim.loss(tg)[0])
+    g = sim.backward()[0].cpu().numpy()
+    err = sim.check()
+    assert err.flags == 0 and err.clamp_count == 0, err.flags
+    names = ["E", "nu", "phi_deg", "rho", "depth", "angle_deg", "push"]
+    p0 = w.params.copy()
+
+    def loss_at(p):
+        q = ddm.DdmInstance.from_buffer_copy(inst)
+        (q.E, q.nu, q.phi_deg, q.rho, q.depth, q.angle_deg, q.push, q.displace, q.push_angle_deg) = (float(v) for v in p)
+        sim.set_instances([q])
+        sim.init_state(x0)
+        sim.step(steps)
+        return float(sim.loss(tg)[0])
+
+    worst = 0.0
+    scale = np.abs(g[:7]).max()
+    for k, name in enumerate(names):
+        best = np.inf
+        fds = []
+        for hr in (1e-4, 2e-5):
+            h = hr * abs(p0[k])
+            pp, pm = p0.copy(), p0.copy()
+            pp[k] += h
+            pm[k] -= h
+            fd = (loss_at(pp) - loss_at(pm)) / (2 * h)
+            fds.append(fd)
+            best = min(best, abs(fd - g[k]) / max(abs(g[k]), 1e-6 * scale))
+        _log(f"{name}: reverse {g[k]:.6e}  central differences {fds}  best rel err {best:.2e}")
+        worst = max(worst, best)
+        assert best < 1e-3, (name, g[k], fds)
+    sim.set_instances([inst])
+    torch.cuda.synchronize()
+    _log(f"loss {L0}, worst relative error {worst:.2e}")

@@ -113,7 +113,7 @@ def test_forward_dig3d_f32_full(ddm, orc):
     r = run_oracle(orc, w, 200)
     e = field_errors(g["state"], r["state"], 3)
     _log("dig3d f32 errors", e)
-    assert g["err"].flags & 3 == 0
+    assert g["err"].flags == 0 and g["err"].clamp_count == 0 and r["stats"][0] == 0, (g["err"].flags, r["stats"])
     for k, v in e.items():
         assert v < 1e-4, (k, v)
 
@@ -128,44 +128,49 @@ def test_forward_column2d_f32(ddm, orc):
     r = run_oracle(orc, w, 200)
     e = field_errors(g["state"], r["state"], 2)
     _log("column2d f32 errors", e)
-    assert g["err"].flags & 3 == 0
+    assert g["err"].flags == 0 and g["err"].clamp_count == 0 and r["stats"][0] == 0, (g["err"].flags, r["stats"])
     for k, v in e.items():
         assert v < 1e-4, (k, v)
 
 
-def test_gradient_tiny2d_f32(ddm, orc):
+@pytest.mark.parametrize("sort_every", [1, 4, 0])
+def test_gradient_tiny2d_f32(ddm, orc, sort_every):
     """The 2D reverse pass in FP32 against the oracle's FP64 forward-mode
     gradient (tiny bed, 60 sub-steps, checkpoints every 16): <= 1e-3 relative
-    for E, nu and phi; density to 1e-2.
+    for E, nu, phi and density, at three binning intervals (which change the
+    order of the FP32 atomic sums).
 
-    Without a shovel the loss sees E and rho only through E / rho (the stress
-    term of the grid momentum is linear in E, the grid mass in rho, and the
-    height map has no mass term), so rho dL/drho = -E dL/dE; the oracle gives
-    the two to 8 digits.  The reverse pass does not use that identity: it sums
-    every particle's mass sensitivity over every sub-step, and here that sum
-    nearly cancels, so the FP32 rounding of its terms is a large part of the
-    result.  Three runs that differ only in the order of the FP32 atomic sums
-    gave density errors of 5e-4, 1.1e-3 and 2.3e-3 (E on the same runs: 6e-6
-    to 3e-5).  The density gradient of the batched dig, where the scoop mass
-    gives it a direct part, stays at 6e-5 (the gradient gate of bench.py)."""
+    Without a shovel the loss sees E and rho only through E / rho, so
+    rho dL/drho = -E dL/dE; the oracle gives the two to 8 digits.  Summed
+    particle by particle as mass sensitivities, the density gradient is a
+    near-cancelling sum whose terms carry FP32 rounding of order
+    eps |v bar| |v| (5e-4 to 2.3e-3 here); the reverse pass takes it instead
+    as -(1/rho) times the stress part of the P2G momentum adjoint, the same
+    quantity without the cancellation."""
     w = W.tiny(2, shovel=False, steps=60)
     if w.target_seed is None:
         w.target_seed = 11
     tgt = W.target_heightmap(w)
-    _log("case gradient tiny2d f32")
-    g = run_gpu(ddm, w, 60, record=True, target=tgt, K=16, precision="f32")
+    _log(f"case gradient tiny2d f32 sort_every={sort_every}")
+    cfg, inst = ddm.from_workload(w, max_steps=60, checkpoint_every=16, precision="f32", sort_every=sort_every)
+    sim = ddm.Simulator(cfg, [inst])
+    sim.init_state(W.bed_positions(w))
+    sim.rollout(60)
+    loss = float(sim.loss(tgt[None])[0])
+    gg = sim.backward()[0].cpu().numpy()
+    err = sim.check()
     r = run_oracle(orc, w, 60, target=tgt, grad=True)
-    gg, rg = g["grad"][:4], r["grad"][:4]
-    _log("gpu grad", gg, "\noracle grad", rg)
-    assert abs(g["loss"] - r["loss"]) <= 1e-5 * abs(r["loss"])
-    assert np.all(g["grad"][4:] == 0) and np.all(rg != 0)
+    rg = r["grad"][:4]
+    _log("gpu grad", gg[:4], "\noracle grad", rg)
+    assert err.flags == 0 and err.clamp_count == 0 and r["stats"][0] == 0
+    assert abs(loss - r["loss"]) <= 1e-5 * abs(r["loss"])
+    assert np.all(gg[4:] == 0) and np.all(rg != 0)
     # the scale identity that leaves density as a residual, on the oracle's side
     p = np.asarray(w.params[:4], dtype=np.float64)
     assert abs(p[0] * rg[0] + p[3] * rg[3]) <= 1e-6 * abs(p[0] * rg[0])
-    rel = np.abs(gg - rg) / np.abs(rg)
+    rel = np.abs(gg[:4] - rg) / np.abs(rg)
     _log("rel", rel)
-    assert np.all(rel[:3] < 1e-3), rel
-    assert rel[3] < 1e-2, rel
+    assert np.all(rel < 1e-3), rel
 
 
 @pytest.mark.parametrize("dim", [2, 3])
@@ -252,7 +257,7 @@ def test_forward_particle_contact_f32(ddm, orc):
     r = run_oracle(orc, w, 200)
     e = field_errors(g["state"], r["state"], 3)
     _log("dig3d f32 particle contact errors", e)
-    assert g["err"].flags & 3 == 0
+    assert g["err"].flags == 0 and g["err"].clamp_count == 0 and r["stats"][0] == 0, (g["err"].flags, r["stats"])
     for k, v in e.items():
         assert v < 1e-4, (k, v)
     # the collision acted: the rollout differs from the one without it
@@ -444,7 +449,7 @@ def test_large_cohesive_bed_vs_oracle(ddm, orc):
     r = run_oracle(orc, w, 5)
     e = field_errors(g["state"], r["state"], 3)
     _log("dig3d_large errors", e)
-    assert g["err"].flags & 3 == 0
+    assert g["err"].flags == 0 and g["err"].clamp_count == 0 and r["stats"][0] == 0, (g["err"].flags, r["stats"])
     for k, v in e.items():
         assert v < 1e-4, (k, v)
 
