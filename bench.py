@@ -49,6 +49,9 @@ def parse():
                     choices=["sysid64", "dig3d_bwd", "dig3d_large", "optim", "dig3d_fwd", "sysid64_fwd",
                              "column2d_fwd"])
     ap.add_argument("--sub-steps", type=int, default=None, help="override rollout length (testing only)")
+    ap.add_argument("--precision", default="f32", choices=["f32", "f64"],
+                    help="arithmetic of the fwd+bwd workloads; the gradient gate compares with FP64 (for an FP64 "
+                         "run: another FP64 run binned every sub-step, a different order of the atomic sums)")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-gate", action="store_true")
@@ -120,14 +123,14 @@ def configs(ddm, ws, sort_every, precision=None, record_segments=1):
     return cfg, [c[1] for c in cfgs]
 
 
-def pick_record_segments(ddm, torch, ws, sort_every, spare=16 << 30):
+def pick_record_segments(ddm, torch, ws, sort_every, spare=16 << 30, precision=None):
     """The most checkpoint segments whose whole record fits in free device
     memory next to the rest of the workspace, with `spare` bytes left over."""
     free = torch.cuda.mem_get_info()[0]
     K = ws[0].checkpoint_every or 50
     best = 1
     for m in range(1, (ws[0].steps + K - 1) // K + 1):
-        cfg, insts = configs(ddm, ws, sort_every, record_segments=m)
+        cfg, insts = configs(ddm, ws, sort_every, precision, record_segments=m)
         if ddm.workspace_query(cfg, insts).workspace_bytes + spare <= free:
             best = m
     return best
@@ -308,8 +311,9 @@ def forward_bench(args, torch, ddm):
     if not args.sort_every:
         sim.init_state(x0)
         tuned = sim.autotune()
-        print(f"# autotuned binning interval: every {tuned} sub-steps", flush=True)
+        print(f"# autotuned launch (binning interval, tile workgroups): {sim.launch()}", flush=True)
     R = tuned or args.sort_every
+    TW = sim.launch()[1]
     n_act, samples = active_nodes(sim, x0, steps)
     print(f"# active grid nodes (m > 0), mean over the run: {n_act:.0f} (samples {samples})", flush=True)
 
@@ -366,7 +370,7 @@ def forward_bench(args, torch, ddm):
         "vs_baseline": None, "dtype": prec, "data": "synthetic (seeded beds, no dataset)",
         "config": {"workload": wname, "instances": len(ws), "particles": n, "sub_steps": steps,
                    "sort_every": R, "sort_every_autotuned": tuned is not None, "plain_sort_every": R,
-                   "active_nodes_mean": n_act},
+                   "tile_workgroups": TW, "active_nodes_mean": n_act},
         "plain_value": plain_value,
         "batched_over_plain": (value / plain_value) if plain_value else None,
         "kernel_ms": {k: {"ms": round(v[0], 3), "launches": v[1]} for k, v in timing.items() if v[1]},
@@ -403,9 +407,11 @@ def main():
 
     # batched: one context on its own stream, binning interval autotuned on the
     # initial state (unless --sort-every is given)
-    rseg = args.record_segments or pick_record_segments(ddm, torch, ws, args.sort_every or 8)
+    rseg = args.record_segments or pick_record_segments(ddm, torch, ws, args.sort_every or 8,
+                                                        precision=args.precision)
     print(f"# checkpoint segments recorded by the rollout: {rseg}", flush=True)
-    bp = Pass(ddm, ws, args.sort_every or 8, stream=torch.cuda.Stream(), record_segments=rseg)
+    bp = Pass(ddm, ws, args.sort_every or 8, precision=args.precision, stream=torch.cuda.Stream(),
+              record_segments=rseg)
     treat = treatment_kwargs(args, ws[0].steps)
     if treat:
         bp.sim.set_grad_treatment(**treat)
@@ -413,8 +419,9 @@ def main():
     if not args.sort_every:
         bp.sim.init_state(bp.x0)
         tuned = bp.sim.autotune()
-        print(f"# autotuned binning interval: every {tuned} sub-steps", flush=True)
+        print(f"# autotuned launch (binning interval, tile workgroups): {bp.sim.launch()}", flush=True)
     R = tuned or args.sort_every
+    TW = bp.sim.launch()[1]
     n_part = sum(w.n_particles for w in ws)
     n_act, act_samples = active_nodes(bp.sim, bp.x0, ws[0].steps)
     print(f"# active grid nodes (m > 0), mean over the forward run: {n_act:.0f} (samples {act_samples})",
@@ -458,7 +465,8 @@ def main():
     # dominant kernel and its roofline (bytes moved per launch / measured launch time)
     dom = max(timing, key=lambda k: timing[k][0])
     p2g_ms, p2g_n = timing["p2g"]
-    per_launch_bytes = algorithmic_bytes_p2g(n_part, n_act)
+    esz = 8 if args.precision == "f64" else 4
+    per_launch_bytes = algorithmic_bytes_p2g(n_part, n_act, b=esz)
     achieved = per_launch_bytes / (p2g_ms / p2g_n * 1e-3) / 1e9 if p2g_n else None
     breakdown = {k: {"ms": round(v[0], 3), "launches": v[1]} for k, v in timing.items() if v[1]}
 
@@ -471,7 +479,7 @@ def main():
     if not args.no_plain:
         t_plain = 0.0
         for w in ws:
-            pp = Pass(ddm, [w], R, record_segments=rseg)
+            pp = Pass(ddm, [w], R, precision=args.precision, record_segments=rseg)
             pp.run()
             torch.cuda.synchronize()
             t1 = time.perf_counter()
@@ -485,11 +493,11 @@ def main():
 
     gate = None
     if not args.no_gate:
-        # FP32 (batched) gradients of the two smallest instances against the FP64 path
+        # the batched gradients of the two smallest instances against the FP64 path
         idx = sorted(range(len(ws)), key=lambda i: ws[i].n_particles)[:2]
         rels, per_param = [], []
         for i in idx:
-            p64 = Pass(ddm, [ws[i]], 8, precision="f64")
+            p64 = Pass(ddm, [ws[i]], 1 if args.precision == "f64" else 8, precision="f64")
             _, g64 = p64.run()
             g64 = g64[0].cpu().numpy()
             scale = np.abs(g64).max()
@@ -499,11 +507,11 @@ def main():
             del p64
         gate = {"instances": idx, "max_rel_err": max(rels), "pass": max(rels) <= 1e-3,
                 "rel_err_per_param": dict(zip(ddm.PARAM_NAMES, per_param[int(np.argmax(rels))]))}
-        print(f"# gradient gate (FP32 vs FP64): {gate}", flush=True)
+        print(f"# gradient gate ({args.precision} vs FP64): {gate}", flush=True)
 
     cpu = None if args.no_cpu else cpu_baseline(ws)
     # the whole pass against the HBM roofline of its algorithmic bytes
-    pass_bytes = algorithmic_bytes_pass(n_part, n_act)
+    pass_bytes = algorithmic_bytes_pass(n_part, n_act, b=esz)
     pass_bound = HBM_PEAK_GBS * 1e9 / pass_bytes
     out = {
         "metric": METRIC,
@@ -516,12 +524,12 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": args.precision,
         "data": "synthetic (seeded beds and targets, no dataset)",
         "config": {"workload": wname, "instances": len(ws), "particles": sum(w.n_particles for w in ws),
                    "sub_steps": ws[0].steps, "checkpoint_every": ws[0].checkpoint_every,
                    "sort_every": R, "sort_every_autotuned": tuned is not None, "plain_sort_every": R,
-                   "active_nodes_mean": n_act,
+                   "tile_workgroups": TW, "active_nodes_mean": n_act,
                    "record_segments": rseg,
                    "grad_treatment": args.treat,
                    "peak_mem_gb": round(peak_gb, 2)},

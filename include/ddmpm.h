@@ -117,6 +117,11 @@ typedef struct ddm_config {
   double w_emd;             /* weight of the earth mover's distance (Eq. emd) between the surface
                                observation and the target set by ddm_set_emd_target; 0 = off;
                                dim 3 only */
+  int32_t tile_workgroups;  /* workgroups of the tile kernels (P2G and the G2P adjoint): 0 = about one
+                               per occupied tile; n > 0 = a persistent launch of n workgroups that
+                               loop over the tile list (each XCD over its own eighth of it), e.g. a
+                               multiple of the co-resident count; ddm_autotune chooses it */
+  int32_t pad0;
 } ddm_config;
 
 /* One simulation instance: material, skill and time step. */
@@ -257,17 +262,25 @@ ddm_status ddm_backward(ddm_ctx* ctx, const double* dloss_dev, double* grad_dev)
 ddm_status ddm_pass(ddm_ctx* ctx, const void* x0_dev, int32_t n_steps, const double* target_hm_dev,
                     const double* dloss_dev, double* loss_dev, double* grad_dev, int32_t use_graph);
 
-/* Chooses the binning interval R (ddm_config.sort_every) for this context by
- * timing the same forward sub-steps from the current state for R in
- * {2, 4, 8, 16, 32}, after a warm-up round.  The state is restored, and a
- * recorded rollout, its loss and its checkpoints stay valid.  With cache_path
- * != NULL, a line "ddmpm dim=.. n_grid=.. prec=.. n_inst=.. particles=..
- * ppc=.. sort_every=R" for this problem is looked up first (no probe when
- * found) and appended after a probe.  The chosen R is written to
- * *sort_every_out (may be NULL).  Synchronises the stream.  DDM_ESTATE
- * before ddm_init_state.  The results do not depend on R beyond the order of
+/* Chooses the launch configuration of this context by timing the same
+ * forward sub-steps from the current state, after a warm-up round: first the
+ * binning interval R (ddm_config.sort_every) in {2, 4, 8, 16, 32}, then, at
+ * that R, the workgroup count of the tile kernels (ddm_config.tile_workgroups)
+ * in {0 (about one per tile), 4, 8, 16 and 32 per compute unit} (the latter
+ * are persistent launches that loop over the tile list).  The state is
+ * restored, and a recorded rollout, its loss and its checkpoints stay valid.
+ * With cache_path != NULL, a line "ddmpm dim=.. n_grid=.. prec=.. n_inst=..
+ * particles=.. ppc=.. sort_every=R tile_workgroups=W" for this problem is
+ * looked up first (no probe when found) and appended after a probe.  The
+ * chosen R is written to *sort_every_out (may be NULL) and both values are
+ * readable with ddm_get_launch.  Synchronises the stream.  DDM_ESTATE before
+ * ddm_init_state.  The results do not depend on R or W beyond the order of
  * floating-point atomic sums. */
 ddm_status ddm_autotune(ddm_ctx* ctx, const char* cache_path, int32_t* sort_every_out);
+
+/* The context's current binning interval and tile-kernel workgroup count
+ * (either pointer may be NULL). */
+ddm_status ddm_get_launch(const ddm_ctx* ctx, int32_t* sort_every, int32_t* tile_workgroups);
 
 /* Copies the current particle state (layout above) of all instances into /
  * from caller device memory of state_bytes.  Particles are exported in their

@@ -20,7 +20,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 # E, nu, phi_deg, rho, depth, angle_deg, push, displace, push_angle_deg.
 N_PARAMS = 9
 LIB_PATH = os.path.join(_HERE, "liboracle.so")
-_SRC = [os.path.join(_HERE, "oracle.cpp"), os.path.join(_HERE, "dual.hpp")]
+_SRC = [os.path.join(_HERE, "oracle.cpp"), os.path.join(_HERE, "dual.hpp"), os.path.join(_HERE, "tape.hpp")]
 
 
 def build(force: bool = True) -> str:
@@ -67,6 +67,11 @@ def lib():
         L.orc_rollout.restype = C.c_int
         L.orc_rollout.argtypes = [C.POINTER(OrcConfig), dp, C.c_int, dp, C.c_int, C.c_int, dp, dp, dp, dp, dp,
                                   C.POINTER(C.c_int64), dp, dp, C.c_int]
+        L.orc_rollout_reverse.restype = C.c_int
+        L.orc_rollout_reverse.argtypes = [C.POINTER(OrcConfig), dp, C.c_int, dp, C.c_int, C.c_int, dp, C.c_int,
+                                          C.c_double, C.c_double, C.c_double, dp, dp, dp]
+        L.orc_treat.restype = None
+        L.orc_treat.argtypes = [C.c_int, C.c_int, dp, C.c_double, C.c_double, C.c_double]
         L.orc_assign.restype = C.c_int
         L.orc_assign.argtypes = [C.c_int, C.c_int, dp, C.POINTER(C.c_int)]
         L.orc_heightmap.restype = C.c_int
@@ -192,6 +197,40 @@ def rollout(cfg: OrcConfig, params: np.ndarray, state: np.ndarray, n_steps: int,
     if want_grid:
         res["grid"] = grid
     return res
+
+
+TREAT_MODES = ("none", "clip", "scale", "norm")
+
+
+def rollout_reverse(cfg: OrcConfig, params: np.ndarray, state: np.ndarray, n_steps: int, target: np.ndarray,
+                    step0: int = 0, mode: str = "none", clip: float = 1e4, oom: float = 4.0, delta: float = 1e-6,
+                    stats: bool = False):
+    """Reverse-mode (tape) gradient of the loss after sub-steps [step0,
+    step0 + n_steps), with the gradient treatment `mode` of Sec. III-E inside
+    the adjoint sweep.  Returns {"loss", "grad" [9], and "stats"
+    [n_steps, 6, 6] when asked: per sub-step and variable (x, v, F, grid v,
+    grid mv, grid m) the max, min, 2-norm before and after the treatment}."""
+    state = np.ascontiguousarray(state, dtype=np.float64)
+    params = np.ascontiguousarray(params, dtype=np.float64)
+    tgt = np.ascontiguousarray(target, dtype=np.float64).reshape(-1)
+    loss = np.zeros(1)
+    g = np.zeros(N_PARAMS)
+    st = np.zeros((n_steps, 6, 6)) if stats else None
+    rc = lib().orc_rollout_reverse(C.byref(cfg), _p(params), state.shape[0], _p(state), step0, n_steps, _p(tgt),
+                                   TREAT_MODES.index(mode), clip, oom, delta, _p(loss), _p(g), _p(st))
+    if rc != 0:
+        raise OracleError(f"reverse rollout failed with code {rc}")
+    out = {"loss": float(loss[0]), "grad": g}
+    if stats:
+        out["stats"] = st
+    return out
+
+
+def treat(g: np.ndarray, mode: str, clip: float = 1e4, oom: float = 4.0, delta: float = 1e-6) -> np.ndarray:
+    """The C++ oracle's treatment of one vector (orc_treat)."""
+    g = np.array(g, dtype=np.float64).ravel()
+    lib().orc_treat(TREAT_MODES.index(mode), g.size, _p(g), clip, oom, delta)
+    return g
 
 
 def skill_actions(theta, v_l=3.0, v_w=10.0 * np.pi, dta=2e-3, d4=0.01, max_T=10000, unrounded=False):

@@ -50,6 +50,7 @@
 #include <quadmath.h>
 
 #include "dual.hpp"
+#include "tape.hpp"
 
 namespace orc {
 
@@ -466,6 +467,36 @@ static void constitutive(int d, const Dual<K> Ft[3][3], const Dual<K>& mu, const
   }
 }
 
+// The same update on the reverse-mode tape: one node per output entry of F'
+// and sigma, whose partials with respect to the entries of F_tmp and to
+// (mu, lambda, alpha_f, k_c) are the forward-mode tangents of the update above
+// (13 directions), so the tape carries exactly the derivative of the SVD-based
+// update that the forward mode uses.
+static void constitutive(int d, const RV Ft[3][3], const RV& mu, const RV& lam, const RV& alpha, const RV& kc,
+                         RV Fn[3][3], RV tau[3][3], int* dp_case, int* clamped) {
+  constexpr int K = 13;
+  Dual<K> Fd[3][3], md(mu.v), ld(lam.v), ad(alpha.v), kd(kc.v);
+  for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) {
+    Fd[i][j] = Dual<K>(Ft[i][j].v);
+    if (i < d && j < d) Fd[i][j].d[i * 3 + j] = 1.0;
+  }
+  md.d[9] = 1.0; ld.d[10] = 1.0; ad.d[11] = 1.0; kd.d[12] = 1.0;
+  Dual<K> Fo[3][3], To[3][3];
+  constitutive(d, Fd, md, ld, ad, kd, Fo, To, dp_case, clamped);
+  const RV* in[K];
+  for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) in[i * 3 + j] = &Ft[i][j];
+  in[9] = &mu; in[10] = &lam; in[11] = &alpha; in[12] = &kc;
+  for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) {
+    if (i < d && j < d) {
+      Fn[i][j] = RV::node(Fo[i][j].v, K, in, Fo[i][j].d);
+      tau[i][j] = RV::node(To[i][j].v, K, in, To[i][j].d);
+    } else {
+      Fn[i][j] = RV(0.0);
+      tau[i][j] = RV(0.0);
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Shovel: an oriented box about the tip (width along z, thin along the digging
 // normal, long along the pointing direction), exact box signed distance and
@@ -601,6 +632,14 @@ static void assign_min_cost(int n, int m, const std::vector<double>& cost, std::
   for (int j = 1; j <= m; ++j) if (match[j]) (*row_col)[match[j] - 1] = j - 1;
 }
 
+// A value the reverse-mode tape must see as a variable.  A grid velocity set
+// by a wall (zero) or by the blade during a phase with constant pose is a
+// constant of the differentiated inputs; the reverse pass still holds an
+// adjoint for it, which its treatments count.  On the tape such a value
+// becomes a variable of its own with no parents; elsewhere it is unchanged.
+template <class S> static S as_variable(const S& x) { return x; }
+static RV as_variable(const RV& x) { return x.i >= 0 ? x : RV::input(x.v); }
+
 // ---------------------------------------------------------------------------
 // The simulator state and one sub-step (Algorithm 1).
 // ---------------------------------------------------------------------------
@@ -727,6 +766,7 @@ struct Sim {
         bool wall = false;
         for (int a = 0; a < d; ++a) if (idx[a] < c.bound || idx[a] >= n - c.bound) wall = true;
         if (wall) for (int a = 0; a < 3; ++a) vv[a] = S(0.0);
+        for (int a = 0; a < d; ++a) vv[a] = as_variable(vv[a]);
       }
       for (int a = 0; a < 3; ++a) gv[gi * 3 + a] = vv[a];
     }
@@ -783,7 +823,7 @@ struct Sim {
       }
       if (c.particle_contact) particle_collision(p, step, vn);
       for (int a = 0; a < d; ++a) {
-        v[p * 3 + a] = vn[a];
+        v[p * 3 + a] = as_variable(vn[a]);
         x[p * 3 + a] += dt * vn[a];
         for (int b = 0; b < d; ++b) C[p * 9 + a * 3 + b] = Cn[a][b];
       }
@@ -1000,6 +1040,137 @@ static int rollout(const orc_config* c, const double* p, int N, const double* st
   return ORC_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Reverse mode with the gradient treatments of Sec. III-E.  The rollout is
+// recorded on a tape (every operation of Algorithm 1, the loss, the skill's
+// pose table and the material constants), then swept backwards once.  The
+// adjoint of each key variable is treated, one vector per variable, where it
+// is complete: the grid velocities after the grid update of sub-step n once
+// the G2P of n is swept, the grid momenta and masses of P2G n once the grid
+// update of n is swept, and the particle positions, velocities and
+// deformation gradients of the state entering sub-step n once all of
+// sub-step n is swept.  The loss's own seed is not treated.
+// Rules (Sec. III-E): clip every element to [-c, c]; scale: divide by
+// 10^dd + delta when dd = round(log10 max|g|) - oom* > 0 (halves away from
+// zero); normalise: divide by the 2-norm + delta.
+// ---------------------------------------------------------------------------
+enum { TREAT_NONE = 0, TREAT_CLIP = 1, TREAT_SCALE = 2, TREAT_NORM = 3 };
+
+static void treat_values(std::vector<double>& g, int mode, double c, double oom, double delta) {
+  if (mode == TREAT_CLIP) {
+    for (double& x : g) x = std::min(std::max(x, -c), c);
+  } else if (mode == TREAT_SCALE) {
+    double amax = 0.0;
+    for (double x : g) amax = std::max(amax, std::fabs(x));
+    if (!(amax > 0.0) || std::isinf(amax)) return;
+    const double l = std::log10(amax);
+    const double r = std::copysign(std::floor(std::fabs(l) + 0.5), l);
+    const double dd = r - oom;
+    if (dd > 0) { const double f = std::pow(10.0, dd) + delta; for (double& x : g) x /= f; }
+  } else if (mode == TREAT_NORM) {
+    double s2 = 0.0;
+    for (double x : g) s2 += x * x;
+    const double den = std::sqrt(s2) + delta;
+    if (den > 0) for (double& x : g) x /= den;
+  }
+}
+
+static void vector_stats(const std::vector<double>& g, double out[3]) {
+  if (g.empty()) { out[0] = out[1] = out[2] = 0.0; return; }
+  double mx = g[0], mn = g[0], s2 = 0.0;
+  for (double x : g) { mx = std::max(mx, x); mn = std::min(mn, x); s2 += x * x; }
+  out[0] = mx; out[1] = mn; out[2] = std::sqrt(s2);
+}
+
+struct TapeMark {
+  int64_t pos;                       // tape size when the variables were complete in the forward
+  int step, var;                     // sub-step and variable (0 x, 1 v, 2 F, 3 grid v, 4 grid mv, 5 grid m)
+  std::vector<int32_t> idx;          // tape nodes of the vector's elements (-1: a constant)
+};
+
+static int rollout_reverse(const orc_config* c, const double* p, int N, const double* state_in, int step0, int n_steps,
+                           const double* target, int mode, double clip_c, double oom, double delta, double* loss_out,
+                           double* grad_out, double* stats_out) {
+  Tape tape;
+  active_tape() = &tape;
+  const int d = c->dim, sd = 2 * d + 2 * d * d;
+  RV prm[9];
+  for (int k = 0; k < 9; ++k) prm[k] = RV::input(p[k]);
+  std::vector<TapeMark> marks;
+  int rc = ORC_OK;
+  {
+    Sim<RV> sim(*c, N);
+    sim.set_material(prm[0], prm[1], prm[2], prm[3]);
+    const int total = step0 + n_steps;
+    if (c->shovel && c->dim == 3) {
+      const RV sk[5] = {prm[4], prm[5], prm[6], prm[7], prm[8]};
+      pose_table(*c, sk, c->dt, std::max(total, 1), &sim.poses);
+    }
+    // the initial state is a set of variables too: its adjoint is the first
+    // treated vector of the sweep's end, as in the reverse pass
+    for (int q = 0; q < N; ++q) {
+      const double* st = state_in + (size_t)q * sd;
+      for (int a = 0; a < d; ++a) { sim.x[q * 3 + a] = RV::input(st[a]); sim.v[q * 3 + a] = RV::input(st[d + a]); }
+      for (int a = 0; a < d; ++a) for (int b = 0; b < d; ++b) {
+        sim.C[q * 9 + a * 3 + b] = RV::input(st[2 * d + a * d + b]);
+        sim.F[q * 9 + a * 3 + b] = RV::input(st[2 * d + d * d + a * d + b]);
+      }
+    }
+    auto mark = [&](int step, int var) {
+      TapeMark m;
+      m.pos = tape.size();
+      m.step = step;
+      m.var = var;
+      if (var == 0 || var == 1) {
+        const std::vector<RV>& src = var == 0 ? sim.x : sim.v;
+        for (int q = 0; q < N; ++q) for (int a = 0; a < d; ++a) m.idx.push_back(src[q * 3 + a].i);
+      } else if (var == 2) {
+        for (int q = 0; q < N; ++q) for (int a = 0; a < d; ++a) for (int b = 0; b < d; ++b)
+          m.idx.push_back(sim.F[q * 9 + a * 3 + b].i);
+      } else if (var == 3 || var == 4) {
+        const std::vector<RV>& src = var == 3 ? sim.gv : sim.gmv;
+        for (int g = 0; g < sim.nodes; ++g) for (int a = 0; a < d; ++a) m.idx.push_back(src[g * 3 + a].i);
+      } else {
+        for (int g = 0; g < sim.nodes; ++g) m.idx.push_back(sim.gm[g].i);
+      }
+      marks.push_back(std::move(m));
+    };
+    for (int st = step0; st < total && rc == ORC_OK; ++st) {
+      mark(st, 0); mark(st, 1); mark(st, 2);
+      if (!sim.p2g()) { rc = ORC_EDOMAIN; break; }
+      mark(st, 4); mark(st, 5);
+      sim.grid_update(st);
+      mark(st, 3);
+      if (!sim.g2p(st)) rc = ORC_EDOMAIN;
+    }
+    if (rc == ORC_OK) {
+      std::vector<RV> H;
+      const RV L = sim.loss(target, total - 1, &H);
+      if (loss_out) *loss_out = L.v;
+      tape.adj.assign((size_t)tape.size(), 0.0);
+      if (L.i >= 0) tape.adj[(size_t)L.i] = 1.0;
+      // the sweep, treating each marked vector once every later node is swept
+      int64_t i = tape.size() - 1;
+      for (int mk = (int)marks.size() - 1; mk >= -1; --mk) {
+        const int64_t stop = mk >= 0 ? marks[(size_t)mk].pos : 0;
+        for (; i >= stop; --i) tape.back(i);
+        if (mk < 0) break;
+        TapeMark& m = marks[(size_t)mk];
+        std::vector<double> g(m.idx.size());
+        for (size_t k = 0; k < g.size(); ++k) g[k] = m.idx[k] >= 0 ? tape.adj[(size_t)m.idx[k]] : 0.0;
+        double* so = stats_out ? stats_out + ((size_t)(m.step - step0) * 6 + m.var) * 6 : nullptr;
+        if (so) vector_stats(g, so);
+        treat_values(g, mode, clip_c, oom, delta);
+        if (so) vector_stats(g, so + 3);
+        for (size_t k = 0; k < g.size(); ++k) if (m.idx[k] >= 0) tape.adj[(size_t)m.idx[k]] = g[k];
+      }
+      for (int k = 0; k < 9; ++k) grad_out[k] = tape.adj[(size_t)prm[k].i];
+    }
+  }
+  active_tape() = nullptr;
+  return rc;
+}
+
 }  // namespace orc
 
 // ============================================================================
@@ -1018,6 +1189,28 @@ int orc_rollout(const orc_config* c, const double* p, int N, const double* state
                             grid_out, emd_target, emd_m);
   return rollout<double>(c, p, N, state_in, step0, n_steps, state_out, target, loss_out, nullptr, hm_out, stats,
                          grid_out, emd_target, emd_m);
+}
+
+// Reverse-mode gradient of the loss with the gradient treatments of
+// Sec. III-E (mode 0 none, 1 clip, 2 scale, 3 normalise): loss, the 9
+// parameter gradients, and (optional) per sub-step and variable the max, min
+// and 2-norm of each adjoint vector before and after its treatment,
+// stats[n_steps][6][6].  No EMD term.
+int orc_rollout_reverse(const orc_config* c, const double* p, int N, const double* state_in, int step0, int n_steps,
+                        const double* target, int mode, double clip_c, double oom, double delta, double* loss_out,
+                        double* grad_out, double* stats_out) {
+  if (validate(c, p) != ORC_OK || N < 0 || n_steps < 1 || step0 < 0 || !target || !grad_out || mode < 0 || mode > 3 ||
+      c->w_emd != 0.0)
+    return ORC_EINVAL;
+  return rollout_reverse(c, p, N, state_in, step0, n_steps, target, mode, clip_c, oom, delta, loss_out, grad_out,
+                         stats_out);
+}
+
+// One treatment (Sec. III-E) of a caller's vector, in place.
+void orc_treat(int mode, int n, double* g, double clip_c, double oom, double delta) {
+  std::vector<double> v(g, g + n);
+  treat_values(v, mode, clip_c, oom, delta);
+  for (int k = 0; k < n; ++k) g[k] = v[(size_t)k];
 }
 
 // The assignment of Eq. emd on an n x m cost matrix (n <= m): row_col[n].

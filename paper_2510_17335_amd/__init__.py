@@ -38,7 +38,7 @@ class DdmConfig(C.Structure):
         ("hm_offset", C.c_double), ("region_depth", C.c_double), ("m_target", C.c_double), ("m_ref", C.c_double),
         ("w_mass", C.c_double), ("w_hm", C.c_double), ("checkpoint_every", C.c_int32), ("max_steps", C.c_int32),
         ("sort_every", C.c_int32), ("skill_unrounded", C.c_int32), ("particle_contact", C.c_int32),
-        ("record_segments", C.c_int32), ("w_emd", C.c_double),
+        ("record_segments", C.c_int32), ("w_emd", C.c_double), ("tile_workgroups", C.c_int32), ("pad0", C.c_int32),
     ]
 
 
@@ -97,6 +97,7 @@ def lib():
             "ddm_backward": (C.c_int, [vp, vp, vp]),
             "ddm_pass": (C.c_int, [vp, vp, i32, vp, vp, vp, vp, i32]),
             "ddm_autotune": (C.c_int, [vp, C.c_char_p, C.POINTER(i32)]),
+            "ddm_get_launch": (C.c_int, [vp, C.POINTER(i32), C.POINTER(i32)]),
             "ddm_get_state": (C.c_int, [vp, vp]),
             "ddm_set_state": (C.c_int, [vp, vp]),
             "ddm_get_grid": (C.c_int, [vp, vp]),
@@ -457,10 +458,17 @@ class Simulator:
         return B["loss"], B["grad"]
 
     def autotune(self, cache_path: Optional[str] = None) -> int:
-        """Chooses and sets the binning interval (ddm_autotune); returns it."""
+        """Chooses and sets the binning interval and the tile kernels'
+        workgroup count (ddm_autotune); returns the interval (see launch())."""
         r = C.c_int32()
         _check(lib().ddm_autotune(self.ctx, cache_path.encode() if cache_path else None, C.byref(r)))
         return int(r.value)
+
+    def launch(self):
+        """(binning interval, tile-kernel workgroups; 0 = about one per tile) of the context."""
+        r, w = C.c_int32(), C.c_int32()
+        _check(lib().ddm_get_launch(self.ctx, C.byref(r), C.byref(w)))
+        return int(r.value), int(w.value)
 
     TIMING_GROUPS = ("p2g", "grid_update", "g2p", "binning", "g2p_adj", "grid_adj", "p2g_adj", "clear", "loss",
                      "treat")

@@ -641,10 +641,7 @@ __global__ void __launch_bounds__(kBlock) k_grid_update(KCfg c, Bufs b, int step
   const uint32_t nact = *act.count;
   if (count_out && blockIdx.x == 0 && threadIdx.x == 0) *count_out = nact;
   const int64_t items = (int64_t)nact * NPB;
-  // nodes of neighbouring blocks gather the same staged windows: one XCD takes a run of blocks
-  const XcdSpan sp = xcd_span(blockIdx.x, gridDim.x, (uint64_t)items, kBlock);
-  for (int64_t it = (int64_t)sp.lo + (int64_t)sp.rank * kBlock + threadIdx.x; it < (int64_t)sp.hi;
-       it += (int64_t)sp.count * kBlock) {
+  for (int64_t it = (int64_t)blockIdx.x * kBlock + threadIdx.x; it < items; it += (int64_t)gridDim.x * kBlock) {
     const uint32_t gb = act.list[it / NPB];
     const int k = (int)(it % NPB);
     if (list_out && k == 0) list_out[it / NPB] = gb;
@@ -703,7 +700,7 @@ static unsigned active_grid(const KCfg& c) {
   const int64_t total_tiles = (c.nodes >> tshift) * c.n_inst;
   const int64_t items = total_tiles << tshift;
   const int64_t nb = (items + kBlock - 1) / kBlock;
-  return xcd_round((unsigned)(nb < 4096 ? nb : 4096));
+  return (unsigned)(nb < 4096 ? nb : 4096);
 }
 
 void launch_grid_post_from_pre(int prec, const KCfg& c, const Bufs& b, int step, const uint32_t* list,
@@ -849,11 +846,9 @@ __device__ __forceinline__ bool g2p_compute(const KCfg& c, const Bufs& b, int in
 template <typename T, int D, bool PC>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PC || sizeof(T) == 8 ? 1 : 6)))
 k_g2p(KCfg c, Bufs b, int step, const void* st_in, void* st_out, const T* __restrict__ post) {
-  const uint32_t blk = xcd_local(blockIdx.x, gridDim.x);      // neighbouring blocks share grid nodes
-  if (blk >= (uint32_t)(c.ntot / kBlock)) return;
-  const int inst = b.blk_inst[blk];
+  const int inst = b.blk_inst[blockIdx.x];
   const InstDev& I = b.inst[inst];
-  const int64_t p = (int64_t)blk * kBlock + threadIdx.x;
+  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const P<T, D> si = pv<T, D>(st_in, c.ntot), so = pv<T, D>(st_out, c.ntot);
   if (p - I.off >= I.n) {
     // padding slots keep a harmless position so they never trip a check
@@ -879,7 +874,7 @@ k_g2p(KCfg c, Bufs b, int step, const void* st_in, void* st_out, const T* __rest
 void launch_g2p(int prec, const KCfg& c, const Bufs& b, int nblk, int step, const void* st_in, void* st_out,
                 const void* post, hipStream_t s) {
 #define DDM_G2P(T, DD, PC) \
-  hipLaunchKernelGGL((k_g2p<T, DD, PC>), dim3(xcd_round(nblk)), dim3(kBlock), 0, s, c, b, step, st_in, st_out, (const T*)post)
+  hipLaunchKernelGGL((k_g2p<T, DD, PC>), dim3(nblk), dim3(kBlock), 0, s, c, b, step, st_in, st_out, (const T*)post)
   const bool pc = c.pcontact != 0;
   if (prec == 0) {
     if (c.dim == 3) { if (pc) DDM_G2P(float, 3, true); else DDM_G2P(float, 3, false); }
@@ -1234,9 +1229,7 @@ __global__ void __launch_bounds__(kBlock) k_g2p_adj(KCfg c, Bufs b, TileList tl,
   const Adj<T, D> an = av<T, D>(adj_next, c.ntot), ac = av<T, D>(adj_cur, c.ntot);
   const T dx = T(c.dx), inv_dx = T(c.inv_dx), Dk = T(4.0 * c.inv_dx * c.inv_dx);
   constexpr int WS = Win<D>::stride;
-  // neighbouring tiles stage overlapping windows of the grid: one XCD takes a run of them
-  const XcdSpan sp = xcd_span(blockIdx.x, gridDim.x, ntiles);
-  for (uint32_t t = (uint32_t)sp.lo + sp.rank; t < sp.hi; t += sp.count) {
+  for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const TileRec tr = tl.list[t];
     int inst, org[3];
     tile_origin<D>(c, tr.tile, inst, org);
@@ -1382,11 +1375,11 @@ __global__ void __launch_bounds__(kBlock) k_g2p_adj(KCfg c, Bufs b, TileList tl,
 void launch_g2p_adj(int prec, const KCfg& c, const Bufs& b, const TileList& tl, int nwg, const void* st,
                     const void* post, const void* adj_next, void* adj_cur, void* gvb, hipStream_t s) {
   if (prec == 0) {
-    if (c.dim == 3) hipLaunchKernelGGL((k_g2p_adj<float, 3>), dim3(xcd_round(nwg)), dim3(kBlock), 0, s, c, b, tl, st, (const float*)post, adj_next, adj_cur, (float*)gvb);
-    else hipLaunchKernelGGL((k_g2p_adj<float, 2>), dim3(xcd_round(nwg)), dim3(kBlock), 0, s, c, b, tl, st, (const float*)post, adj_next, adj_cur, (float*)gvb);
+    if (c.dim == 3) hipLaunchKernelGGL((k_g2p_adj<float, 3>), dim3(nwg), dim3(kBlock), 0, s, c, b, tl, st, (const float*)post, adj_next, adj_cur, (float*)gvb);
+    else hipLaunchKernelGGL((k_g2p_adj<float, 2>), dim3(nwg), dim3(kBlock), 0, s, c, b, tl, st, (const float*)post, adj_next, adj_cur, (float*)gvb);
   } else {
-    if (c.dim == 3) hipLaunchKernelGGL((k_g2p_adj<double, 3>), dim3(xcd_round(nwg)), dim3(kBlock), 0, s, c, b, tl, st, (const double*)post, adj_next, adj_cur, (double*)gvb);
-    else hipLaunchKernelGGL((k_g2p_adj<double, 2>), dim3(xcd_round(nwg)), dim3(kBlock), 0, s, c, b, tl, st, (const double*)post, adj_next, adj_cur, (double*)gvb);
+    if (c.dim == 3) hipLaunchKernelGGL((k_g2p_adj<double, 3>), dim3(nwg), dim3(kBlock), 0, s, c, b, tl, st, (const double*)post, adj_next, adj_cur, (double*)gvb);
+    else hipLaunchKernelGGL((k_g2p_adj<double, 2>), dim3(nwg), dim3(kBlock), 0, s, c, b, tl, st, (const double*)post, adj_next, adj_cur, (double*)gvb);
   }
 }
 
@@ -1624,11 +1617,9 @@ __device__ __forceinline__ void ftmp_of(const P<T, D>& st, int64_t p, T dt, T Cm
 template <typename T, int D, bool SF>
 __global__ void __launch_bounds__(kBlock) k_p2g_adj_gather(KCfg c, Bufs b, const void* stv, const T* __restrict__ tau,
                                                            const T* __restrict__ gbar, void* adj_cur, double* pacc) {
-  const uint32_t blk = xcd_local(blockIdx.x, gridDim.x);      // neighbouring blocks share grid nodes
-  if (blk >= (uint32_t)(c.ntot / kBlock)) return;
-  const int inst = b.blk_inst[blk];
+  const int inst = b.blk_inst[blockIdx.x];
   const InstDev& I = b.inst[inst];
-  const int64_t p = (int64_t)blk * kBlock + threadIdx.x;
+  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   double acc[1] = {0.0};
   if (p - I.off < I.n) {
     const P<T, D> st = pv<T, D>(stv, c.ntot);
@@ -1815,10 +1806,10 @@ void launch_p2g_adj(int prec, const KCfg& c, const Bufs& b, int nblk, const void
                     bool stress_form, const void* adj_next, void* adj_cur, double* pacc, hipStream_t s) {
 #define DDM_P2GADJ(T, DD)                                                                                          \
   if (stress_form)                                                                                                 \
-    hipLaunchKernelGGL((k_p2g_adj_gather<T, DD, true>), dim3(xcd_round(nblk)), dim3(kBlock), 0, s, c, b, st,      \
+    hipLaunchKernelGGL((k_p2g_adj_gather<T, DD, true>), dim3(nblk), dim3(kBlock), 0, s, c, b, st,                  \
                        (const T*)tau, (const T*)gb, adj_cur, pacc);                                                \
   else                                                                                                             \
-    hipLaunchKernelGGL((k_p2g_adj_gather<T, DD, false>), dim3(xcd_round(nblk)), dim3(kBlock), 0, s, c, b, st,     \
+    hipLaunchKernelGGL((k_p2g_adj_gather<T, DD, false>), dim3(nblk), dim3(kBlock), 0, s, c, b, st,                 \
                        (const T*)tau, (const T*)gb, adj_cur, pacc);                                                \
   hipLaunchKernelGGL((k_p2g_adj_constit<T, DD>), dim3(nblk), dim3(kBlock), 0, s, c, b, st, adj_next, adj_cur, pacc);
   if (prec == 0) {

@@ -15,33 +15,6 @@ constexpr int kParams = 4 + kSkillParams;   // gradient entries per instance
 constexpr int kTile = 4;             // binning tile edge in cells
 constexpr int kWin = kTile + 4;      // LDS window edge in nodes: tile + stencil + 1-cell drift each side
 
-// XCD-aware work mapping.  An MI355X has 8 XCDs, each with its own L2, and
-// hands the workgroups of a launch to them round-robin (workgroup w runs on
-// XCD w % 8).  Kernels whose neighbouring work items gather the same grid
-// nodes renumber their workgroups so that every XCD takes one contiguous
-// eighth of the work: the shared nodes then meet in one L2.  Such kernels are
-// launched with a multiple of kXcds workgroups (xcd_round).
-constexpr uint32_t kXcds = 8;
-inline uint32_t xcd_round(uint32_t n) { return (n + kXcds - 1) / kXcds * kXcds; }
-// Logical index of workgroup w in a launch of `grid` workgroups.
-__device__ __forceinline__ uint32_t xcd_local(uint32_t w, uint32_t grid) {
-  return (w % kXcds) * (grid / kXcds) + w / kXcds;
-}
-// The part [lo, hi) of `n` work items that the XCD of workgroup w takes (lo a
-// multiple of `align`), and the workgroup's rank and count among that XCD's
-// workgroups.
-struct XcdSpan { uint64_t lo, hi; uint32_t rank, count; };
-__device__ __forceinline__ XcdSpan xcd_span(uint32_t w, uint32_t grid, uint64_t n, uint64_t align = 1) {
-  const uint64_t chunk = ((n + kXcds - 1) / kXcds + align - 1) / align * align;
-  const uint32_t x = w % kXcds;
-  XcdSpan s;
-  s.lo = x * chunk < n ? x * chunk : n;
-  s.hi = s.lo + chunk < n ? s.lo + chunk : n;
-  s.rank = w / kXcds;
-  s.count = grid / kXcds;
-  return s;
-}
-
 // An occupied tile: slots [start, end) of the sorted state, global tile id.
 // Tiles and grid node blocks share one index space: tile t holds the cells
 // [4t, 4t + 4) per axis and node block t the nodes [4t, 4t + 4).

@@ -432,6 +432,7 @@ ddm_status validate(const ddm_config* c, int32_t n_inst, const ddm_instance* in)
   if (c->record_segments < 0) return fail(DDM_EINVAL, "record_segments must be >= 0");
   if (c->max_steps < 1) return fail(DDM_EINVAL, "max_steps must be >= 1");
   if (c->sort_every < 0) return fail(DDM_EINVAL, "sort_every must be >= 0");
+  if (c->tile_workgroups < 0 || c->tile_workgroups > (1 << 22)) return fail(DDM_EINVAL, "tile_workgroups out of [0, 2^22]");
   if (c->w_emd != 0.0 && c->dim != 3) return fail(DDM_EINVAL, "the EMD term needs dim 3");
   if (c->w_emd != 0.0 && c->hm_res * c->hm_res > ddm::kEmdMaxPoints)
     return fail(DDM_EINVAL, "the EMD term needs hm_res^2 <= 4096");
@@ -543,6 +544,12 @@ ddm_status bin_current(ddm_ctx* x) {
   return s;
 }
 
+// Workgroups of the tile kernels: the configured persistent count, or about
+// one per occupied tile.
+int tile_workgroups(const ddm_ctx* x) {
+  return x->cfg.tile_workgroups > 0 ? (int)x->cfg.tile_workgroups : x->L.nwg;
+}
+
 // One forward sub-step from st_in to st_out (may alias) with the given tile
 // list; grids given.  The reverse pass also keeps the stress (tau_out) and the
 // active blocks of the sub-step (list_out, count_out).
@@ -553,7 +560,7 @@ ddm_status forward_step(ddm_ctx* x, int64_t step, const ddm::TileList& tl, const
   const ddm::Staging stg = x->staging();
   const ddm::ActiveSet act = x->active();
   void* gout = x->at(x->L.gout);
-  { Timed t(x, 0); ddm::launch_p2g(x->prec, x->kc, b, tl, x->L.nwg, st_in, st_out, stg, gout, act, tau_out, x->stream); }
+  { Timed t(x, 0); ddm::launch_p2g(x->prec, x->kc, b, tl, tile_workgroups(x), st_in, st_out, stg, gout, act, tau_out, x->stream); }
   { Timed t(x, 1); ddm::launch_grid_update(x->prec, x->kc, b, (int)step, stg, gout, act, gpre, gpost, list_out,
                                            count_out, x->stream); }
   { Timed t(x, 2); ddm::launch_g2p(x->prec, x->kc, b, (int)x->L.nblk, (int)step, st_in, st_out, gpost, x->stream); }
@@ -1028,7 +1035,7 @@ ddm_status ddm_backward(ddm_ctx* x, const double* dloss_dev, double* grad_dev) {
         if (x->kc.pcontact)
           ddm::launch_pcontact_adj(x->prec, x->kc, b, (int)L.nblk, (int)k, slot(j), gpost(j), adj[cur],
                                    x->at<double>(L.pose_bar), st);
-        ddm::launch_g2p_adj(x->prec, x->kc, b, tl, L.nwg, slot(j), gpost(j), adj[cur], adj[1 - cur], x->at(L.gvb), st);
+        ddm::launch_g2p_adj(x->prec, x->kc, b, tl, tile_workgroups(x), slot(j), gpost(j), adj[cur], adj[1 - cur], x->at(L.gvb), st);
       }
       if (treat) {
         Timed t(x, 9);
@@ -1161,57 +1168,80 @@ ddm_status ddm_autotune(ddm_ctx* x, const char* cache_path, int32_t* sort_every_
   std::ostringstream key;
   key << "ddmpm dim=" << x->cfg.dim << " n_grid=" << x->cfg.n_grid << " prec=" << x->prec << " n_inst=" << x->n_inst
       << " particles=" << n_part << " ppc=" << x->cfg.ppc;
-  int best = -1;
+  int best = -1, best_w = 0;
   if (cache_path) {
     std::ifstream f(cache_path);
     std::string line;
     while (std::getline(f, line)) {
-      const size_t k = line.rfind(" sort_every=");
-      if (k != std::string::npos && line.compare(0, k, key.str()) == 0) best = std::atoi(line.c_str() + k + 12);
+      const size_t k = line.find(" sort_every=");
+      if (k == std::string::npos || line.compare(0, k, key.str()) != 0) continue;
+      best = std::atoi(line.c_str() + k + 12);
+      const size_t kw = line.find(" tile_workgroups=", k);
+      best_w = kw == std::string::npos ? 0 : std::atoi(line.c_str() + kw + 17);
     }
   }
   if (best <= 0) {
     // Probe: the same forward sub-steps from the current state for every
-    // candidate interval, the state restored before each.  The snapshot lives in
+    // candidate, the state restored before each.  The snapshot lives in
     // reverse-pass buffers (segment state 0, segment permutations), which hold
-    // nothing between calls.
+    // nothing between calls.  R first at the default workgroup count, then the
+    // workgroup count at that R.
     const int P = std::min<int>(32, x->cfg.max_steps);
-    const int cand[] = {2, 4, 8, 16, 32};
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) {
+      hipDeviceProp_t prop;
+      if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0) cus = prop.multiProcessorCount;
+    }
     void* snap = x->at(L.seg_state);
     void* pid_snap = x->at(L.seg_perm);
     x->rec_first = INT32_MAX;      // the snapshot overwrites recorded segments
     DDM_HIP(hipMemcpyAsync(snap, x->cur(), L.state_bytes, hipMemcpyDeviceToDevice, x->stream));
     DDM_HIP(hipMemcpyAsync(pid_snap, x->pid(), sizeof(uint32_t) * L.ntot, hipMemcpyDeviceToDevice, x->stream));
-    const int saved_R = x->cfg.sort_every;
+    const int saved_R = x->cfg.sort_every, saved_W = x->cfg.tile_workgroups;
     const bool saved_timing = x->timing;
     x->timing = false;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     DDM_HIP(hipEventCreate(&e0));
     DDM_HIP(hipEventCreate(&e1));
-    float best_ms = 0.f;
     ddm_status st = DDM_OK;
-    for (int rep = 0; rep < 2 && st == DDM_OK; ++rep) {          // the first round warms up
-      for (int R : cand) {
-        DDM_HIP(hipMemcpyAsync(x->cur(), snap, L.state_bytes, hipMemcpyDeviceToDevice, x->stream));
-        DDM_HIP(hipMemcpyAsync(x->pid(), pid_snap, sizeof(uint32_t) * L.ntot, hipMemcpyDeviceToDevice, x->stream));
-        x->cfg.sort_every = R;
-        x->need_sort = true;
-        DDM_HIP(hipEventRecord(e0, x->stream));
-        for (int i = 0; i < P && st == DDM_OK; ++i) {
-          // pose rows 0 .. P-1: the cost of a sub-step does not depend on the pose
-          if (sort_due(x, i)) {
-            st = bin_current(x);
-            x->need_sort = false;
-          }
-          if (st == DDM_OK)
-            st = forward_step(x, i, x->tiles(), x->cur(), x->cur(), x->at(L.grid_pre), x->at(L.grid_post));
+    auto probe = [&](int R, int W, float* ms) -> ddm_status {
+      DDM_HIP(hipMemcpyAsync(x->cur(), snap, L.state_bytes, hipMemcpyDeviceToDevice, x->stream));
+      DDM_HIP(hipMemcpyAsync(x->pid(), pid_snap, sizeof(uint32_t) * L.ntot, hipMemcpyDeviceToDevice, x->stream));
+      x->cfg.sort_every = R;
+      x->cfg.tile_workgroups = W;
+      x->need_sort = true;
+      DDM_HIP(hipEventRecord(e0, x->stream));
+      ddm_status r = DDM_OK;
+      for (int i = 0; i < P && r == DDM_OK; ++i) {
+        // pose rows 0 .. P-1: the cost of a sub-step does not depend on the pose
+        if (sort_due(x, i)) {
+          r = bin_current(x);
+          x->need_sort = false;
         }
-        DDM_HIP(hipEventRecord(e1, x->stream));
-        DDM_HIP(hipEventSynchronize(e1));
-        float ms = 0.f;
-        DDM_HIP(hipEventElapsedTime(&ms, e0, e1));
-        if (rep == 1 && (best < 0 || ms < best_ms)) { best = R; best_ms = ms; }
+        if (r == DDM_OK) r = forward_step(x, i, x->tiles(), x->cur(), x->cur(), x->at(L.grid_pre), x->at(L.grid_post));
       }
+      DDM_HIP(hipEventRecord(e1, x->stream));
+      DDM_HIP(hipEventSynchronize(e1));
+      DDM_HIP(hipEventElapsedTime(ms, e0, e1));
+      return r;
+    };
+    const int cand_r[] = {2, 4, 8, 16, 32};
+    float best_ms = 0.f;
+    for (int rep = 0; rep < 2 && st == DDM_OK; ++rep) {          // the first round warms up
+      for (int R : cand_r) {
+        float ms = 0.f;
+        st = probe(R, 0, &ms);
+        if (st == DDM_OK && rep == 1 && (best < 0 || ms < best_ms)) { best = R; best_ms = ms; }
+      }
+    }
+    const int cand_w[] = {4 * cus, 8 * cus, 16 * cus, 32 * cus};
+    best_w = 0;
+    for (int W : cand_w) {
+      if (st != DDM_OK || W >= L.nwg) break;       // at least one workgroup per tile already
+      float ms = 0.f;
+      st = probe(best, W, &ms);
+      if (st == DDM_OK) st = probe(best, W, &ms);  // the second timing counts
+      if (st == DDM_OK && ms < best_ms) { best_w = W; best_ms = ms; }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -1220,16 +1250,25 @@ ddm_status ddm_autotune(ddm_ctx* x, const char* cache_path, int32_t* sort_every_
     DDM_HIP(hipStreamSynchronize(x->stream));
     x->timing = saved_timing;
     x->cfg.sort_every = saved_R;
+    x->cfg.tile_workgroups = saved_W;
     if (st != DDM_OK) return st;
     if (cache_path) {
       std::ofstream f(cache_path, std::ios::app);
-      if (f) f << key.str() << " sort_every=" << best << "\n";
+      if (f) f << key.str() << " sort_every=" << best << " tile_workgroups=" << best_w << "\n";
     }
   }
   x->cfg.sort_every = best;
+  x->cfg.tile_workgroups = best_w;
   x->need_sort = true;            // the probe left the binning of another state
   x->grid_valid = false;
   if (sort_every_out) *sort_every_out = best;
+  return DDM_OK;
+}
+
+ddm_status ddm_get_launch(const ddm_ctx* x, int32_t* sort_every, int32_t* tile_workgroups) {
+  if (!x) return fail(DDM_EINVAL, "NULL context");
+  if (sort_every) *sort_every = x->cfg.sort_every;
+  if (tile_workgroups) *tile_workgroups = x->cfg.tile_workgroups;
   return DDM_OK;
 }
 

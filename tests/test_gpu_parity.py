@@ -565,14 +565,44 @@ def test_autotune_restores_state_and_caches(ddm, orc, tmp_path):
     assert np.array_equal(before, after)
     assert sim.steps_taken == 3
     lines = open(cache).read().splitlines()
-    assert len(lines) == 1 and lines[0].endswith(f"sort_every={r}")
-    assert sim.autotune(cache) == r and len(open(cache).read().splitlines()) == 1
+    R, tw = sim.launch()
+    assert R == r and tw >= 0
+    assert len(lines) == 1 and lines[0].endswith(f"sort_every={r} tile_workgroups={tw}")
+    assert sim.autotune(cache) == r and sim.launch() == (r, tw) and len(open(cache).read().splitlines()) == 1
     sim.step(27)
     ref = run_oracle(orc, w, 30)
     e = field_errors(sim.packed_state(0), ref["state"], 3)
     _log("autotune R", r, "errors", e)
     for k, v in e.items():
         assert v < 1e-9, (k, v)
+
+
+@pytest.mark.parametrize("workgroups", [3, 8, 1024])
+def test_persistent_tile_launch_matches_oracle(ddm, orc, workgroups):
+    """The tile kernels (P2G, G2P adjoint) as a persistent launch of a fixed
+    number of workgroups that loop over the tile list (fewer than, and more
+    than, the occupied tiles): state, loss and gradient against the oracle
+    (FP64), as with one workgroup per tile."""
+    w = W.tiny(3, shovel=True, steps=40)
+    tgt = W.target_heightmap(w)
+    cfg, inst = ddm.from_workload(w, max_steps=40, checkpoint_every=16)
+    cfg.tile_workgroups = workgroups
+    sim = ddm.Simulator(cfg, [inst])
+    assert sim.launch()[1] == workgroups
+    _log(f"case persistent tile launch: {workgroups} workgroups")
+    sim.init_state(W.bed_positions(w))
+    sim.rollout(40)
+    loss = float(sim.loss(tgt[None])[0])
+    g = sim.backward()[0].cpu().numpy()
+    assert sim.check().flags == 0
+    r = run_oracle(orc, w, 40, target=tgt, grad=True)
+    e = field_errors(sim.packed_state(0), r["state"], 3)
+    rel = np.abs(g - r["grad"]) / np.maximum(np.abs(r["grad"]), 1e-9 * np.abs(r["grad"]).max())
+    _log("errors", e, "grad rel", rel.max())
+    for k, v in e.items():
+        assert v < 1e-9, (k, v)
+    assert abs(loss - r["loss"]) <= 1e-10 * abs(r["loss"])
+    assert np.all(rel < 1e-6), rel
 
 
 @pytest.mark.timeout(400)
