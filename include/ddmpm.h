@@ -321,6 +321,31 @@ ddm_status ddm_get_heightmap(ddm_ctx* ctx, double* hm_dev);
  * NULL pointer with n > 0; DDM_EDEVICE for a failed launch. */
 ddm_status ddm_eval_math(int32_t fn, const float* x_dev, float* y_dev, int64_t n, void* stream);
 
+/* The loss of ddm_loss without a context and without allocating, for callers
+ * that cannot allocate device memory (code under stream capture, tight
+ * serving loops, harnesses that forbid hipMalloc).  It evaluates the height
+ * map of Eq. hm and the scoop-mass term (not the EMD term) for one instance's
+ * particle positions x_dev ([inst->n_particles][dim], device, float for
+ * DDM_F32 and double for DDM_F64, as ddm_init_state takes them), with the
+ * blade at its pose after sub-step final_step of the instance's skill (-1: the
+ * initial pose tip0), against target_hm_dev ([hm_res^(dim-1)] double,
+ * device), with the same kernels as ddm_loss.  Writes loss_dev[1] and, when
+ * hm_dev is not NULL, the height map hm_dev[hm_res^(dim-1)] (double, device).
+ * Asynchronous on `stream` (a hipStream_t, NULL: the default stream).
+ * Memory: no allocation of any kind.  Every intermediate lives in one static
+ * device array of the library, 8 MiB on each device it runs on, held until
+ * the process ends; its address is taken on the first call on a device.
+ * Calls on one device share that array: calls that overlap on one device
+ * (other streams, other threads) race and must be ordered by the caller.
+ * Errors: DDM_EINVAL as ddm_validate_config for cfg and inst, for NULL
+ * pointers, n_particles above DDM_NOALLOC_MAX_PARTICLES, hm_res^(dim-1) above
+ * DDM_NOALLOC_MAX_PIXELS, w_emd != 0, or final_step outside [-1, max_steps);
+ * DDM_EDEVICE when the array's address cannot be taken or a launch fails. */
+#define DDM_NOALLOC_MAX_PARTICLES 262144
+#define DDM_NOALLOC_MAX_PIXELS 4096
+ddm_status ddm_loss_noalloc(const ddm_config* cfg, const ddm_instance* inst, int32_t final_step, const void* x_dev,
+                            const double* target_hm_dev, double* loss_dev, double* hm_dev, void* stream);
+
 /* Gradient treatments inside the reverse pass (Sec. III-E) and the record of
  * how the adjoints grow backwards in time (Appendix D).
  *   The adjoint of each key variable of a sub-step is treated as one vector

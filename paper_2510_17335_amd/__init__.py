@@ -104,6 +104,7 @@ def lib():
             "ddm_bin_keys": (C.c_int, [vp, vp, vp]),
             "ddm_get_heightmap": (C.c_int, [vp, vp]),
             "ddm_eval_math": (C.c_int, [i32, vp, vp, i64, vp]),
+            "ddm_loss_noalloc": (C.c_int, [cfgp, instp, i32, vp, vp, vp, vp, vp]),
             "ddm_check": (C.c_int, [vp, C.POINTER(DdmDeviceError)]),
             "ddm_steps_taken": (i64, [vp]),
             "ddm_instance_offset": (i64, [vp, i32]),
@@ -210,6 +211,26 @@ def eval_math(fn: str, x):
     _check(lib().ddm_eval_math(MATH_FUNCTIONS.index(fn), C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()),
                                x.numel(), C.c_void_p(stream.cuda_stream)))
     return y
+
+
+def loss_noalloc(cfg: DdmConfig, inst: DdmInstance, final_step: int, x, target, hm=True):
+    """ddm_loss_noalloc on the current stream: the loss (and height map) of one
+    instance's positions x [n, dim] (CUDA tensor of the context precision)
+    with the blade after sub-step final_step (-1: the initial pose), without a
+    context or any allocation inside the library.  Returns (loss [1], hm or None)."""
+    import torch
+    dt = torch.float64 if cfg.precision == DDM_F64 else torch.float32
+    if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == dt):
+        raise ValueError("x must be a CUDA tensor of the configuration's precision")
+    x = x.contiguous()
+    tg = torch.as_tensor(target, dtype=torch.float64).to(x.device).contiguous()
+    loss = torch.empty(1, dtype=torch.float64, device=x.device)
+    out = torch.empty(tg.numel(), dtype=torch.float64, device=x.device) if hm else None
+    stream = torch.cuda.current_stream(x.device)
+    _check(lib().ddm_loss_noalloc(C.byref(cfg), C.byref(inst), int(final_step), C.c_void_p(x.data_ptr()),
+                                  C.c_void_p(tg.data_ptr()), C.c_void_p(loss.data_ptr()),
+                                  C.c_void_p(out.data_ptr()) if hm else None, C.c_void_p(stream.cuda_stream)))
+    return loss, out
 
 
 def skill_pose_table(cfg: DdmConfig, inst: DdmInstance, n_steps: int):

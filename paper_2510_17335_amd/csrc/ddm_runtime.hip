@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <fstream>
+#include <mutex>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -1382,5 +1383,128 @@ void ddm_destroy(ddm_ctx* x) {
   delete x;
 }
 
+
+// ---------------------------------------------------------------------------
+// ddm_loss_noalloc: the loss of ddm_loss for one instance's positions, with
+// every intermediate in one static device array (`scratch`) instead of a
+// workspace.  Host code never names the array: its address on each device is
+// taken once with hipGetSymbolAddress (that device current) and kept.
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+namespace {
+
+constexpr size_t kNoAllocBytes = (size_t)8 << 20;
+__device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_ptr;     // per device: the address of `scratch` there
+
+ddm_status scratch_address(void** out) {
+  int dev = 0;
+  DDM_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize((size_t)dev + 1, nullptr);
+  if (!g_scratch_ptr[(size_t)dev]) {
+    void* p = nullptr;
+    DDM_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    g_scratch_ptr[(size_t)dev] = p;
+  }
+  *out = g_scratch_ptr[(size_t)dev];
+  return DDM_OK;
+}
+
+// Offsets of the pieces inside the static array for ntot particle slots and
+// npix pixels (the largest case fits: checked at compile time below).
+struct NoAllocLayout {
+  size_t err, inst, poses, blk, pid, x, hm_bits, owner, dldh, hm_val, region, dldm, total;
+};
+constexpr NoAllocLayout noalloc_layout(int64_t ntot, int64_t npix, int dim, int esz) {
+  NoAllocLayout L{};
+  size_t off = 0;
+  auto take = [&off](size_t bytes) { off = (off + 255) / 256 * 256; const size_t o = off; off += bytes; return o; };
+  L.err = take(sizeof(ddm::DevErr));
+  L.inst = take(sizeof(ddm::InstDev));
+  L.poses = take((size_t)ddm::kPoseVals * esz);
+  L.blk = take(sizeof(int) * (size_t)(ntot / ddm::kBlock));
+  L.pid = take(sizeof(uint32_t) * (size_t)ntot);
+  L.x = take((size_t)dim * ntot * esz);
+  L.hm_bits = take(sizeof(unsigned long long) * (size_t)npix);
+  L.owner = take(sizeof(unsigned int) * (size_t)npix);
+  L.dldh = take(sizeof(double) * (size_t)npix);
+  L.hm_val = take(sizeof(double) * (size_t)npix);
+  L.region = take(sizeof(double));
+  L.dldm = take(sizeof(double));
+  L.total = take(0);
+  return L;
+}
+static_assert(noalloc_layout(DDM_NOALLOC_MAX_PARTICLES, DDM_NOALLOC_MAX_PIXELS, 3, 8).total <= kNoAllocBytes,
+              "the static scratch must hold the largest case");
+
+}  // namespace
+
+extern "C" {
+
+ddm_status ddm_loss_noalloc(const ddm_config* cfg, const ddm_instance* inst, int32_t final_step, const void* x_dev,
+                            const double* target_hm_dev, double* loss_dev, double* hm_dev, void* stream) {
+  if (!cfg || !inst || !x_dev || !target_hm_dev || !loss_dev) return fail(DDM_EINVAL, "NULL argument");
+  ddm_status s = validate(cfg, 1, inst);
+  if (s != DDM_OK) return s;
+  if (inst->n_particles > DDM_NOALLOC_MAX_PARTICLES)
+    return fail(DDM_EINVAL, "n_particles above DDM_NOALLOC_MAX_PARTICLES (" +
+                                std::to_string(DDM_NOALLOC_MAX_PARTICLES) + ")");
+  const int64_t npix = cfg->dim == 3 ? (int64_t)cfg->hm_res * cfg->hm_res : cfg->hm_res;
+  if (npix > DDM_NOALLOC_MAX_PIXELS)
+    return fail(DDM_EINVAL, "hm_res^(dim-1) above DDM_NOALLOC_MAX_PIXELS (" + std::to_string(DDM_NOALLOC_MAX_PIXELS) + ")");
+  if (cfg->w_emd != 0.0) return fail(DDM_EINVAL, "ddm_loss_noalloc has no EMD term: w_emd must be 0");
+  if (final_step < -1 || final_step >= cfg->max_steps) return fail(DDM_EINVAL, "final_step outside [-1, max_steps)");
+  void* base = nullptr;
+  s = scratch_address(&base);
+  if (s != DDM_OK) return s;
+  char* sc = static_cast<char*>(base);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int prec = cfg->precision == DDM_F64 ? 1 : 0, esz = prec ? 8 : 4;
+  const int64_t ntot = pad_up(inst->n_particles, ddm::kBlock), nblk = ntot / ddm::kBlock;
+  const NoAllocLayout A = noalloc_layout(ntot, npix, cfg->dim, esz);
+  // one instance, one pose row (that of final_step; the kernels read row 0)
+  ddm_config c1 = *cfg;
+  c1.max_steps = 1;
+  ddm::KCfg kc = make_kcfg(c1, 1, ntot);
+  const ddm::InstDev dev = make_instdev(*cfg, *inst, 0, 0, kc.nodes);
+  double row[ddm::kPoseVals] = {0};
+  if (final_step >= 0 && cfg->shovel) {
+    ddm_config cp = *cfg;
+    cp.max_steps = final_step + 1;
+    std::vector<double> pose, jac;
+    pose_table(cp, *inst, pose, jac);
+    std::copy(pose.begin() + (size_t)final_step * 8, pose.begin() + (size_t)final_step * 8 + 8, row);
+    row[8] = std::sin(row[3]);
+    row[9] = std::cos(row[3]);
+  }
+  float rowf[ddm::kPoseVals];
+  for (int k = 0; k < ddm::kPoseVals; ++k) rowf[k] = (float)row[k];
+  ddm::launch_put_bytes(sc + A.inst, &dev, sizeof(dev), st);
+  ddm::launch_put_bytes(sc + A.poses, prec ? (const void*)row : (const void*)rowf, (size_t)ddm::kPoseVals * esz, st);
+  ddm::launch_fill_zero(sc + A.err, sizeof(ddm::DevErr) / 4, 4, st);
+  ddm::launch_fill_zero(sc + A.blk, nblk, 4, st);            // every block belongs to instance 0
+  ddm::Bufs b;
+  b.inst = reinterpret_cast<const ddm::InstDev*>(sc + A.inst);
+  b.blk_inst = reinterpret_cast<const int*>(sc + A.blk);
+  b.poses = sc + A.poses;
+  b.err = reinterpret_cast<ddm::DevErr*>(sc + A.err);
+  uint32_t* pid = reinterpret_cast<uint32_t*>(sc + A.pid);
+  ddm::launch_init_state(prec, kc, b, (int)nblk, x_dev, sc + A.x, pid, st, true);
+  ddm::LossBufs lb;
+  lb.hm_bits = reinterpret_cast<unsigned long long*>(sc + A.hm_bits);
+  lb.owner = reinterpret_cast<unsigned int*>(sc + A.owner);
+  lb.target = target_hm_dev;
+  lb.hm_val = hm_dev ? hm_dev : reinterpret_cast<double*>(sc + A.hm_val);
+  lb.dldh = reinterpret_cast<double*>(sc + A.dldh);
+  lb.region = reinterpret_cast<double*>(sc + A.region);
+  lb.dldm = reinterpret_cast<double*>(sc + A.dldm);
+  lb.loss = loss_dev;
+  ddm::launch_loss(prec, kc, b, (int)nblk, sc + A.x, pid, final_step >= 0 ? 0 : -1, lb, st);
+  return launch_status();
+}
 
 }  // extern "C"
