@@ -240,24 +240,38 @@ def cpu_baseline(ws, grad=True, target_s=15.0):
     import oracle
     oracle.build(force=False)
     w = min(ws, key=lambda q: q.n_particles)
-    rate_guess = 2.5e4 if grad else 2.5e5
-    steps = int(min(w.steps, max(1, round(target_s * rate_guess / w.n_particles))))
+    cfg = oracle.config(w)
     s0 = oracle.initial_state(W.bed_positions(w))
     tgt = W.target_heightmap(w) if grad else None
     old = os.sched_getaffinity(0)
     core = min(old)
     os.sched_setaffinity(0, {core})
     try:
+        # a short run (doubled until it takes 0.5 s) sizes the sample: the
+        # rollout's first sub-steps, up to the workload's length, repeated to
+        # fill about target_s
+        n = 1
+        while True:
+            t0 = time.perf_counter()
+            oracle.rollout(cfg, w.params, s0, n, target=tgt, grad=grad)
+            dt = time.perf_counter() - t0
+            if dt >= 0.5 or n >= w.steps:
+                break
+            n = min(2 * n, w.steps)
+        rate = w.n_particles * n / dt
+        steps = int(min(w.steps, max(1, round(target_s * rate / w.n_particles))))
+        reps = max(1, int(round(target_s * rate / (w.n_particles * steps))))
         t0 = time.perf_counter()
-        oracle.rollout(oracle.config(w), w.params, s0, steps, target=tgt, grad=grad)
+        for _ in range(reps):
+            oracle.rollout(cfg, w.params, s0, steps, target=tgt, grad=grad)
         dt = time.perf_counter() - t0
     finally:
         os.sched_setaffinity(0, old)
     model, ncpu, navail = host_cpu()
     kind = "FP64 with 9 forward-mode tangents" if grad else "FP64 forward"
-    return {"value": w.n_particles * steps / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"smallest instance ({w.n_particles} particles), {steps} sub-steps, {kind}, {dt:.1f} s, "
-                      f"pinned to core {core}",
+    return {"value": w.n_particles * steps * reps / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"smallest instance ({w.n_particles} particles), {reps} x {steps} sub-steps from its initial "
+                      f"state, {kind}, {dt:.1f} s, pinned to core {core}",
             "host_cpu": model, "host_nproc": ncpu, "host_cpus_available": navail}
 
 

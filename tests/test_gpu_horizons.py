@@ -186,6 +186,9 @@ def test_dig3d_large_2000_steps_fp32_gate(ddm):
     _log("case dig3d_large FP32 vs FP64, 2000 sub-steps")
     _, g64 = _large_grad(ddm, "f64", 8)
     _, g32 = _large_grad(ddm, "f32", 8)
+    # FP32 against itself with another summation order (binning every 32)
+    _, g32b = _large_grad(ddm, "f32", 32)
     rel = _rel(g32, g64)
-    _log(f"grad FP64 {g64}\ngrad FP32 {g32}\nrel {rel}")
+    _log(f"grad FP64 {g64}\ngrad FP32 R=8 {g32}\ngrad FP32 R=32 {g32b}\nrel FP32 vs FP64 {rel}\n"
+         f"rel FP32 R=32 vs R=8 {_rel(g32b, g32)}")
     assert np.all(rel < 1e-3), rel
