@@ -381,14 +381,19 @@ typedef enum ddm_grad_treatment {
 ddm_status ddm_set_grad_treatment(ddm_ctx* ctx, int32_t mode, double clip, double oom, double delta,
                                   double* stats_dev, int32_t stats_steps);
 
-/* Kernel timing for measurement: when enabled, every launch group of the
- * sub-step is bracketed by HIP events on the context's stream.  Groups:
- * 0 P2G, 1 grid update, 2 G2P, 3 binning (keys, sort, gather, tile list),
- * 4 G2P adjoint, 5 grid adjoint, 6 P2G adjoint, 7 grid clears, 8 loss,
- * 9 gradient treatments and their statistics.
+/* Kernel timing for measurement: each launch of a selected group is
+ * bracketed by HIP events on the context's stream (an event pair costs a few
+ * microseconds of stream time, so a timed run selects only the groups it
+ * needs).  Groups: 0 P2G, 1 grid update, 2 G2P, 3 binning (keys, sort,
+ * gather, tile list), 4 G2P adjoint, 5 grid adjoint, 6 P2G adjoint, 7 grid
+ * clears, 8 loss, 9 gradient treatments and their statistics.
+ * groups: bit g selects group g; 0 turns timing off; DDM_TIMING_ALL selects
+ * every group.  Synchronises the stream and resets the sums.
  * ddm_read_timing synchronises and returns the summed milliseconds and the
- * number of launches of a group since timing was enabled. */
-ddm_status ddm_set_timing(ddm_ctx* ctx, int32_t enable);
+ * number of launches of a group since timing was set.
+ * Errors: DDM_EINVAL for a NULL context or bits above DDM_TIMING_ALL. */
+#define DDM_TIMING_ALL 0x3FF
+ddm_status ddm_set_timing(ddm_ctx* ctx, int32_t groups);
 ddm_status ddm_read_timing(ddm_ctx* ctx, int32_t group, double* total_ms, int64_t* launches);
 
 /* Synchronises the stream and reads the device error word. */

@@ -23,6 +23,7 @@ LIB_PATH = os.path.join(_HERE, "libddmpm.so")
 
 DDM_OK, DDM_EINVAL, DDM_ENOMEM, DDM_EDEVICE, DDM_ENAN, DDM_EDOMAIN, DDM_ESTATE = range(7)
 DDM_F32, DDM_F64 = 0, 1
+TIMING_ALL = 0x3FF          # DDM_TIMING_ALL: every launch group
 # Differentiable inputs, in the order of every gradient (DDM_N_PARAMS).
 PARAM_NAMES = ("E", "nu", "phi_deg", "rho", "depth", "angle_deg", "push", "displace", "push_angle_deg")
 N_PARAMS = len(PARAM_NAMES)
@@ -531,8 +532,17 @@ class Simulator:
             out.append(np.stack([amax[k:k + seg].max(axis=0), S[k:k + seg, ..., 2].max(axis=0)], axis=-1))
         return np.stack(out)
 
-    def set_timing(self, enable: bool):
-        _check(lib().ddm_set_timing(self.ctx, int(bool(enable))))
+    def set_timing(self, enable=True, groups=None):
+        """Time launch groups with HIP events: every group (enable=True), none
+        (False), or the named groups of TIMING_GROUPS (groups=[...]).  Each
+        event pair costs a few microseconds of stream time."""
+        if groups is not None:
+            mask = 0
+            for g in groups:
+                mask |= 1 << self.TIMING_GROUPS.index(g)
+        else:
+            mask = TIMING_ALL if enable else 0
+        _check(lib().ddm_set_timing(self.ctx, mask))
 
     def read_timing(self) -> dict:
         """{group: (total_ms, launches)} since timing was enabled."""

@@ -346,7 +346,7 @@ struct ddm_ctx {
   int rec_first = INT32_MAX;
   std::vector<std::vector<int>> rec_tl_of;
   // kernel timing
-  bool timing = false;
+  int32_t timing = 0;             // groups bracketed by timing events (bit g: group g)
   struct Ev { int group; hipEvent_t a, b; };
   std::vector<Ev> events;
   std::vector<hipEvent_t> pool;
@@ -483,13 +483,13 @@ hipEvent_t take_event(ddm_ctx* x) {
   return e;
 }
 
-// Brackets a launch group with events when timing is on.
+// Brackets a launch group with events when timing selects its group.
 struct Timed {
   ddm_ctx* x;
   int group;
   hipEvent_t a = nullptr;
   Timed(ddm_ctx* x_, int g) : x(x_), group(g) {
-    if (x->timing && (a = take_event(x))) (void)hipEventRecord(a, x->stream);
+    if (((x->timing >> group) & 1) && (a = take_event(x))) (void)hipEventRecord(a, x->stream);
   }
   ~Timed() {
     if (!a) return;
@@ -1127,8 +1127,8 @@ ddm_status ddm_pass(ddm_ctx* x, const void* x0_dev, int32_t n_steps, const doubl
     drop_graph(x);
     // Capture: the sequence of kernels and copies is fixed by (n_steps, config),
     // and nothing in it waits for the host.  Timing events stay out of the graph.
-    const bool timing = x->timing;
-    x->timing = false;
+    const int32_t timing = x->timing;
+    x->timing = 0;
     DDM_HIP(hipStreamBeginCapture(x->stream, hipStreamCaptureModeThreadLocal));
     const ddm_status s = run_pass(x, x0_dev, n_steps, target_hm_dev, dloss_dev, loss_dev, grad_dev);
     hipGraph_t g = nullptr;
@@ -1199,8 +1199,8 @@ ddm_status ddm_autotune(ddm_ctx* x, const char* cache_path, int32_t* sort_every_
     DDM_HIP(hipMemcpyAsync(snap, x->cur(), L.state_bytes, hipMemcpyDeviceToDevice, x->stream));
     DDM_HIP(hipMemcpyAsync(pid_snap, x->pid(), sizeof(uint32_t) * L.ntot, hipMemcpyDeviceToDevice, x->stream));
     const int saved_R = x->cfg.sort_every, saved_W = x->cfg.tile_workgroups;
-    const bool saved_timing = x->timing;
-    x->timing = false;
+    const int32_t saved_timing = x->timing;
+    x->timing = 0;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     DDM_HIP(hipEventCreate(&e0));
     DDM_HIP(hipEventCreate(&e1));
@@ -1355,12 +1355,13 @@ int64_t ddm_instance_offset(const ddm_ctx* x, int32_t i) {
   return off;
 }
 
-ddm_status ddm_set_timing(ddm_ctx* x, int32_t enable) {
+ddm_status ddm_set_timing(ddm_ctx* x, int32_t groups) {
   if (!x) return fail(DDM_EINVAL, "NULL context");
+  if (groups & ~DDM_TIMING_ALL) return fail(DDM_EINVAL, "timing groups outside DDM_TIMING_ALL");
   DDM_HIP(hipStreamSynchronize(x->stream));
   resolve_events(x);
   for (int g = 0; g < kTimingGroups; ++g) { x->t_ms[g] = 0.0; x->t_n[g] = 0; }
-  x->timing = enable != 0;
+  x->timing = groups;
   return DDM_OK;
 }
 
