@@ -98,10 +98,10 @@ class Pass:
     """One context over a list of instances and the inputs of a full pass
     (init, recorded rollout, loss, backward: one ddm_pass call)."""
 
-    def __init__(self, ddm, ws, sort_every, precision=None, stream=None, record_segments=1):
+    def __init__(self, ddm, ws, sort_every, precision=None, stream=None, record_segments=1, grid_record_blocks=0):
         self.ws = ws
         self.steps = ws[0].steps
-        cfg, insts = configs(ddm, ws, sort_every, precision, record_segments)
+        cfg, insts = configs(ddm, ws, sort_every, precision, record_segments, grid_record_blocks)
         self.sim = ddm.Simulator(cfg, insts, stream=stream)
         self.x0 = np.concatenate([W.bed_positions(w) for w in ws])
         self.tg = np.stack([W.target_heightmap(w) for w in ws])
@@ -114,23 +114,24 @@ class Pass:
         return sum(w.n_particles for w in self.ws) * self.steps
 
 
-def configs(ddm, ws, sort_every, precision=None, record_segments=1):
+def configs(ddm, ws, sort_every, precision=None, record_segments=1, grid_record_blocks=0):
     K = ws[0].checkpoint_every or 50
     cfgs = [ddm.from_workload(w, max_steps=ws[0].steps, checkpoint_every=K, precision=precision,
                               sort_every=sort_every) for w in ws]
     cfg = cfgs[0][0]
     cfg.record_segments = record_segments
+    cfg.grid_record_blocks = grid_record_blocks
     return cfg, [c[1] for c in cfgs]
 
 
-def pick_record_segments(ddm, torch, ws, sort_every, spare=16 << 30, precision=None):
+def pick_record_segments(ddm, torch, ws, sort_every, spare=16 << 30, precision=None, grid_record_blocks=0):
     """The most checkpoint segments whose whole record fits in free device
     memory next to the rest of the workspace, with `spare` bytes left over."""
     free = torch.cuda.mem_get_info()[0]
     K = ws[0].checkpoint_every or 50
     best = 1
     for m in range(1, (ws[0].steps + K - 1) // K + 1):
-        cfg, insts = configs(ddm, ws, sort_every, precision, record_segments=m)
+        cfg, insts = configs(ddm, ws, sort_every, precision, record_segments=m, grid_record_blocks=grid_record_blocks)
         if ddm.workspace_query(cfg, insts).workspace_bytes + spare <= free:
             best = m
     return best
@@ -162,21 +163,40 @@ def algorithmic_bytes_forward(n_particles, n_active, b=4, d=3):
     return 2 * s_p + (2 * (1 + d) * b + 2 * d * b) * n_active / n_particles
 
 
-def active_nodes(sim, x0, steps, samples=10):
+def active_nodes(sim, x0, steps, samples=10, blocks=False):
     """Mean number of grid nodes with m > 0 over a forward run of `steps`
     sub-steps from x0 (all instances), sampled every steps/samples sub-steps
-    from the library's grid of the last sub-step."""
+    from the library's grid of the last sub-step.  blocks: also the largest
+    sampled number of active blocks (4^dim nodes the grid update processed)."""
     sim.init_state(x0)
     every = max(1, steps // samples)
-    counts, done = [], 0
+    counts, nblk, done = [], [], 0
+    npb = 4 ** sim.dim
     while done < steps:
         k = min(every, steps - done)
         sim.step(k)
         done += k
         g = sim.get_grid()
         counts.append(int((g[:, :, 0] > 0).sum().item()))
+        nblk.append(int(round((g[:, :, 7] > 0).sum().item() / npb)))
         del g
+    if blocks:
+        return float(np.mean(counts)), counts, max(nblk)
     return float(np.mean(counts)), counts
+
+
+def grid_record_capacity(ddm, torch, ws, sort_every, precision=None):
+    """Capacity of the pre-update grid record (blocks per sub-step): 1.5x the
+    most active blocks sampled over a forward run of the workload (a smaller
+    record leaves room for more recorded segments), with the mean active-node
+    count of that run."""
+    cfg, insts = configs(ddm, ws, sort_every, precision, record_segments=1)
+    sim = ddm.Simulator(cfg, insts)
+    x0 = np.concatenate([W.bed_positions(w) for w in ws])
+    n_act, samples, most = active_nodes(sim, x0, ws[0].steps, blocks=True)
+    del sim
+    torch.cuda.empty_cache()
+    return int(np.ceil(1.5 * most)), most, n_act, samples
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "p2g_sysid64_traffic.txt")
@@ -430,37 +450,53 @@ def main():
     print(f"# workload {wname}: {len(ws)} instances, {sum(w.n_particles for w in ws)} particles", flush=True)
 
     # batched: one context on its own stream, binning interval autotuned on the
-    # initial state (unless --sort-every is given)
-    rseg = args.record_segments or pick_record_segments(ddm, torch, ws, args.sort_every or 8,
-                                                        precision=args.precision)
-    print(f"# checkpoint segments recorded by the rollout: {rseg}", flush=True)
-    bp = Pass(ddm, ws, args.sort_every or 8, precision=args.precision, stream=torch.cuda.Stream(),
-              record_segments=rseg)
-    treat = treatment_kwargs(args, ws[0].steps)
-    if treat:
-        bp.sim.set_grad_treatment(**treat)
-    tuned = None
-    if not args.sort_every:
-        bp.sim.init_state(bp.x0)
-        tuned = bp.sim.autotune()
-        print(f"# autotuned launch (binning interval, tile workgroups): {bp.sim.launch()}", flush=True)
-    R = tuned or args.sort_every
-    TW = bp.sim.launch()[1]
-    n_part = sum(w.n_particles for w in ws)
-    n_act, act_samples = active_nodes(bp.sim, bp.x0, ws[0].steps)
-    print(f"# active grid nodes (m > 0), mean over the forward run: {n_act:.0f} (samples {act_samples})",
-          flush=True)
-    breakdown = None
-    for i in range(args.warmup):
-        last = i == args.warmup - 1
-        if last:
-            bp.sim.set_timing(True)
-        bp.run()
-        torch.cuda.synchronize()
-        if last:
-            breakdown = bp.sim.read_timing()
-            bp.sim.set_timing(False)
-        print(f"# warmup {i + 1}/{args.warmup} done", flush=True)
+    # initial state (unless --sort-every is given).  A forward run first counts
+    # the active grid nodes and blocks: the record of each sub-step's
+    # pre-update grid holds 1.5x the most active blocks seen (fewer bytes per
+    # recorded segment, so more segments fit).
+    cap, most, n_act, act_samples = grid_record_capacity(ddm, torch, ws, args.sort_every or 32, args.precision)
+    for attempt in range(2):
+        rseg = args.record_segments or pick_record_segments(ddm, torch, ws, args.sort_every or 8,
+                                                            precision=args.precision, grid_record_blocks=cap)
+        print(f"# checkpoint segments recorded by the rollout: {rseg} (pre-update grid record: "
+              f"{cap or 'every'} blocks per sub-step; most active blocks sampled: {most})", flush=True)
+        bp = Pass(ddm, ws, args.sort_every or 8, precision=args.precision, stream=torch.cuda.Stream(),
+                  record_segments=rseg, grid_record_blocks=cap)
+        treat = treatment_kwargs(args, ws[0].steps)
+        if treat:
+            bp.sim.set_grad_treatment(**treat)
+        tuned = None
+        if not args.sort_every:
+            bp.sim.init_state(bp.x0)
+            tuned = bp.sim.autotune()
+            print(f"# autotuned launch (binning interval, tile workgroups): {bp.sim.launch()}", flush=True)
+        R = tuned or args.sort_every
+        TW = bp.sim.launch()[1]
+        n_part = sum(w.n_particles for w in ws)
+        print(f"# active grid nodes (m > 0), mean over the forward run: {n_act:.0f} (samples {act_samples})",
+              flush=True)
+        breakdown = None
+        for i in range(args.warmup):
+            last = i == args.warmup - 1
+            if last:
+                bp.sim.set_timing(True)
+            bp.run()
+            torch.cuda.synchronize()
+            if last:
+                breakdown = bp.sim.read_timing()
+                bp.sim.set_timing(False)
+            print(f"# warmup {i + 1}/{args.warmup} done", flush=True)
+        try:
+            bp.sim.check()
+            break
+        except ddm.DdmError as e:
+            if e.code != ddm.DDM_ENOMEM or cap == 0:
+                raise
+            # a sub-step had more active blocks than the record holds: every block then
+            print(f"# {e}; again with a record of every block", flush=True)
+            del bp
+            torch.cuda.empty_cache()
+            cap = 0
     bp.sim.check()
     torch.cuda.reset_peak_memory_stats()
     # the timed region brackets only P2G (the roofline kernel) with events: an
@@ -566,7 +602,7 @@ def main():
                    "sub_steps": ws[0].steps, "checkpoint_every": ws[0].checkpoint_every,
                    "sort_every": R, "sort_every_autotuned": tuned is not None, "plain_sort_every": R,
                    "tile_workgroups": TW, "active_nodes_mean": n_act,
-                   "record_segments": rseg,
+                   "record_segments": rseg, "grid_record_blocks": cap, "active_blocks_max_sampled": most,
                    "grad_treatment": args.treat,
                    "peak_mem_gb": round(peak_gb, 2)},
         "graph_value": graph_value,

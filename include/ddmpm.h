@@ -119,9 +119,16 @@ typedef struct ddm_config {
                                dim 3 only */
   int32_t tile_workgroups;  /* workgroups of the tile kernels (P2G and the G2P adjoint): 0 = about one
                                per occupied tile; n > 0 = a persistent launch of n workgroups that
-                               loop over the tile list (each XCD over its own eighth of it), e.g. a
-                               multiple of the co-resident count; ddm_autotune chooses it */
-  int32_t pad0;
+                               loop over the tile list, e.g. a multiple of the co-resident count;
+                               ddm_autotune chooses it */
+  int32_t grid_record_blocks; /* capacity of the record of one sub-step's pre-update grid in the
+                               segment buffers, in blocks of 4^dim nodes over all instances: the
+                               record keeps the active blocks only (those within one tile of an
+                               occupied tile).  0 = every block of every instance (no limit).  A
+                               smaller capacity shrinks each segment set by K (blocks - capacity)
+                               4^dim 4 element-size bytes; a recorded sub-step with more active
+                               blocks than that sets device error bit 4 and ddm_check then reports
+                               DDM_ENOMEM (the gradient of that pass is not valid) */
 } ddm_config;
 
 /* One simulation instance: material, skill and time step. */
@@ -158,7 +165,8 @@ typedef struct ddm_ctx ddm_ctx;
 typedef struct ddm_device_error {
   uint32_t flags;           /* bit 0: NaN/Inf, bit 1: stencil left the grid, bit 2: sigma clamped,
                                bit 3: EMD term set to 0: more observed points than targets, or
-                               non-finite distances */
+                               non-finite distances, bit 4: a recorded sub-step had more active
+                               grid blocks than grid_record_blocks */
   uint32_t first_instance;  /* instance of the first flagged particle */
   uint64_t clamp_count;     /* singular values clamped to 1e-6 since the last reset */
 } ddm_device_error;
@@ -299,8 +307,10 @@ ddm_status ddm_set_state(ddm_ctx* ctx, const void* state_dev);
 ddm_status ddm_bin_keys(ddm_ctx* ctx, uint32_t* keys_dev, uint32_t* perm_dev);
 
 /* Copies the grid of the last sub-step (per instance, n_grid^dim nodes,
- * 8 values each: m, mv[3], v[3], 0) into caller device memory, in the
- * context's precision; nodes that cannot hold mass are zero.  For
+ * 8 values each: m, mv[3], v[3], a) into caller device memory, in the
+ * context's precision; a is 1 for a node of an active block (one the grid
+ * update processed) and 0 elsewhere, and nodes outside active blocks are
+ * zero.  For
  * kernel-level tests.  DDM_ESTATE when no forward sub-step ran since
  * ddm_init_state, ddm_set_state or ddm_backward (the reverse pass reuses the
  * grid buffers). */

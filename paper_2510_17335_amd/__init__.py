@@ -39,7 +39,7 @@ class DdmConfig(C.Structure):
         ("hm_offset", C.c_double), ("region_depth", C.c_double), ("m_target", C.c_double), ("m_ref", C.c_double),
         ("w_mass", C.c_double), ("w_hm", C.c_double), ("checkpoint_every", C.c_int32), ("max_steps", C.c_int32),
         ("sort_every", C.c_int32), ("skill_unrounded", C.c_int32), ("particle_contact", C.c_int32),
-        ("record_segments", C.c_int32), ("w_emd", C.c_double), ("tile_workgroups", C.c_int32), ("pad0", C.c_int32),
+        ("record_segments", C.c_int32), ("w_emd", C.c_double), ("tile_workgroups", C.c_int32), ("grid_record_blocks", C.c_int32),
     ]
 
 

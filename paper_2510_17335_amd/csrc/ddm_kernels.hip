@@ -632,15 +632,20 @@ __device__ __forceinline__ void node_velocity(const KCfg& c, const Bufs& b, int 
   }
 }
 
+// pre_cap < 0: grid_pre is the dense grid (node gid at gid); pre_cap >= 0:
+// grid_pre is a record of pre_cap node entries in the order of the active list
+// (item it at it), and more items than that set error bit 4.
 template <typename T, int D>
 __global__ void __launch_bounds__(kBlock) k_grid_update(KCfg c, Bufs b, int step, const T* __restrict__ stg,
                                                         const uint32_t* __restrict__ tslot, T* __restrict__ gout,
-                                                        ActiveSet act, T* __restrict__ pre, T* __restrict__ post,
-                                                        uint32_t* __restrict__ list_out, uint32_t* __restrict__ count_out) {
+                                                        ActiveSet act, T* __restrict__ pre, int64_t pre_cap,
+                                                        T* __restrict__ post, uint32_t* __restrict__ list_out,
+                                                        uint32_t* __restrict__ count_out) {
   constexpr int NPB = D == 3 ? kTile * kTile * kTile : kTile * kTile;
   const uint32_t nact = *act.count;
   if (count_out && blockIdx.x == 0 && threadIdx.x == 0) *count_out = nact;
   const int64_t items = (int64_t)nact * NPB;
+  if (pre_cap >= 0 && items > pre_cap && blockIdx.x == 0 && threadIdx.x == 0) flag_error(b.err, 16u, 0);
   for (int64_t it = (int64_t)blockIdx.x * kBlock + threadIdx.x; it < items; it += (int64_t)gridDim.x * kBlock) {
     const uint32_t gb = act.list[it / NPB];
     const int k = (int)(it % NPB);
@@ -662,8 +667,8 @@ __global__ void __launch_bounds__(kBlock) k_grid_update(KCfg c, Bufs b, int step
     }
     T v[3];
     node_velocity<T, D>(c, b, inst, step, idx, acc, v);
-#pragma unroll
-    for (int a = 0; a < kNodeVals; ++a) pre[gid * kNodeVals + a] = acc[a];
+    if (pre_cap < 0) st_node(pre + gid * kNodeVals, acc[0], acc[1], acc[2], acc[3]);
+    else if (it < pre_cap) st_node(pre + it * kNodeVals, acc[0], acc[1], acc[2], acc[3]);
     post[gid * kNodeVals + 0] = v[0];
     post[gid * kNodeVals + 1] = v[1];
     post[gid * kNodeVals + 2] = v[2];
@@ -671,15 +676,19 @@ __global__ void __launch_bounds__(kBlock) k_grid_update(KCfg c, Bufs b, int step
   }
 }
 
-// The post-update grid of a sub-step again from its pre-update grid, over the
-// sub-step's listed active blocks: the same arithmetic on the same values as
+// The post-update grid of a sub-step again from the record of its pre-update
+// grid (pre_cap entries in the order of the active list), over the sub-step's
+// listed active blocks: the same arithmetic on the same values as
 // k_grid_update, so the velocities are the ones G2P used.  The reverse pass
-// keeps only the pre-update grids and rebuilds these.
+// keeps only the pre-update grids and rebuilds these.  pre_dense (may be
+// NULL) also receives the pre-update values at their grid positions.
+// Entries beyond the record's capacity (flagged when recorded) read as empty.
 template <typename T, int D>
 __global__ void __launch_bounds__(kBlock) k_grid_post_from_pre(KCfg c, Bufs b, int step,
                                                                const uint32_t* __restrict__ list,
                                                                const uint32_t* __restrict__ count,
-                                                               const T* __restrict__ pre, T* __restrict__ post) {
+                                                               const T* __restrict__ pre, int64_t pre_cap,
+                                                               T* __restrict__ post, T* __restrict__ pre_dense) {
   constexpr int NPB = D == 3 ? kTile * kTile * kTile : kTile * kTile;
   const int64_t items = (int64_t)(*count) * NPB;
   for (int64_t it = (int64_t)blockIdx.x * kBlock + threadIdx.x; it < items; it += (int64_t)gridDim.x * kBlock) {
@@ -687,11 +696,13 @@ __global__ void __launch_bounds__(kBlock) k_grid_post_from_pre(KCfg c, Bufs b, i
     int64_t node;
     active_node<D>(c, list[it / NPB], (int)(it % NPB), inst, idx, node);
     const int64_t gid = b.inst[inst].goff + node;
-    const Node4<T> q = ld_node(pre + gid * kNodeVals);
+    Node4<T> q = {{T(0), T(0), T(0), T(0)}};
+    if (it < pre_cap) q = ld_node(pre + it * kNodeVals);
     const T acc[4] = {q.v[0], q.v[1], q.v[2], q.v[3]};
     T v[3];
     node_velocity<T, D>(c, b, inst, step, idx, acc, v);
     st_node(post + gid * kNodeVals, v[0], v[1], v[2], acc[3]);
+    if (pre_dense) st_node(pre_dense + gid * kNodeVals, acc[0], acc[1], acc[2], acc[3]);
   }
 }
 
@@ -704,11 +715,12 @@ static unsigned active_grid(const KCfg& c) {
 }
 
 void launch_grid_post_from_pre(int prec, const KCfg& c, const Bufs& b, int step, const uint32_t* list,
-                               const uint32_t* count, const void* pre, void* post, hipStream_t s) {
+                               const uint32_t* count, const void* pre, int64_t pre_cap, void* post, void* pre_dense,
+                               hipStream_t s) {
   const unsigned nb = active_grid(c);
 #define DDM_GP(T, DD)                                                                                       \
   hipLaunchKernelGGL((k_grid_post_from_pre<T, DD>), dim3(nb), dim3(kBlock), 0, s, c, b, step, list, count, \
-                     (const T*)pre, (T*)post)
+                     (const T*)pre, pre_cap, (T*)post, (T*)pre_dense)
   if (prec == 0) {
     if (c.dim == 3) DDM_GP(float, 3); else DDM_GP(float, 2);
   } else {
@@ -718,12 +730,12 @@ void launch_grid_post_from_pre(int prec, const KCfg& c, const Bufs& b, int step,
 }
 
 void launch_grid_update(int prec, const KCfg& c, const Bufs& b, int step, const Staging& stg, void* gout,
-                        const ActiveSet& act, void* pre, void* post, uint32_t* list_out, uint32_t* count_out,
-                        hipStream_t s) {
+                        const ActiveSet& act, void* pre, int64_t pre_cap, void* post, uint32_t* list_out,
+                        uint32_t* count_out, hipStream_t s) {
   const unsigned nb = active_grid(c);
 #define DDM_GU(T, DD)                                                                                              \
   hipLaunchKernelGGL((k_grid_update<T, DD>), dim3(nb), dim3(kBlock), 0, s, c, b, step, (const T*)stg.win, stg.tslot, \
-                     (T*)gout, act, (T*)pre, (T*)post, list_out, count_out)
+                     (T*)gout, act, (T*)pre, pre_cap, (T*)post, list_out, count_out)
   if (prec == 0) {
     if (c.dim == 3) DDM_GU(float, 3); else DDM_GU(float, 2);
   } else {
@@ -951,7 +963,7 @@ __global__ void k_grid_export(KCfg c, const T* pre, const T* post, const uint32_
     out[g * 8 + 1 + a] = act ? pre[g * 4 + a] : T(0);
     out[g * 8 + 4 + a] = act ? post[g * 4 + a] : T(0);
   }
-  out[g * 8 + 7] = T(0);
+  out[g * 8 + 7] = act ? T(1) : T(0);
 }
 
 void launch_grid_export(int prec, const KCfg& c, const void* pre, const void* post, const uint32_t* mask, void* out,
@@ -1485,7 +1497,8 @@ void launch_pcontact_adj(int prec, const KCfg& c, const Bufs& b, int nblk, int s
 template <typename T, int D>
 __global__ void __launch_bounds__(kBlock) k_grid_adj(KCfg c, Bufs b, int step, const uint32_t* __restrict__ list,
                                                      const uint32_t* __restrict__ count, const T* __restrict__ pre,
-                                                     T* __restrict__ gvb, T* __restrict__ gb, double* pose_bar) {
+                                                     int64_t pre_cap, T* __restrict__ gvb, T* __restrict__ gb,
+                                                     double* pose_bar) {
   constexpr int NPB = D == 3 ? kTile * kTile * kTile : kTile * kTile;
   const int64_t items = (int64_t)(*count) * NPB;
   // 3D: the 64 lanes of a wave take the 64 nodes of one block, hence one instance
@@ -1496,7 +1509,8 @@ __global__ void __launch_bounds__(kBlock) k_grid_adj(KCfg c, Bufs b, int step, c
     const int64_t gid = b.inst[inst].goff + node;
     double pb[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     bool any = false;
-    const Node4<T> pr = ld_node(pre + gid * kNodeVals);
+    Node4<T> pr = {{T(0), T(0), T(0), T(0)}};
+    if (it < pre_cap) pr = ld_node(pre + it * kNodeVals);
     T vb[3] = {T(0), T(0), T(0)};
     {
       T* gv = gvb + gid * kNodeVals;
@@ -1571,11 +1585,11 @@ __global__ void __launch_bounds__(kBlock) k_grid_adj(KCfg c, Bufs b, int step, c
 }
 
 void launch_grid_adj(int prec, const KCfg& c, const Bufs& b, int step, const uint32_t* list, const uint32_t* count,
-                     const void* pre, void* gvb, void* gb, double* pose_bar, hipStream_t s) {
+                     const void* pre, int64_t pre_cap, void* gvb, void* gb, double* pose_bar, hipStream_t s) {
   const unsigned nb = active_grid(c);
 #define DDM_GA(T, DD)                                                                                             \
   hipLaunchKernelGGL((k_grid_adj<T, DD>), dim3(nb), dim3(kBlock), 0, s, c, b, step, list, count, (const T*)pre,  \
-                     (T*)gvb, (T*)gb, pose_bar)
+                     pre_cap, (T*)gvb, (T*)gb, pose_bar)
   if (prec == 0) {
     if (c.dim == 3) DDM_GA(float, 3); else DDM_GA(float, 2);
   } else {

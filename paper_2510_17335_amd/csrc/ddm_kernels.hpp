@@ -107,13 +107,18 @@ void launch_p2g(int prec, const KCfg& c, const Bufs& b, const TileList& tl, int 
                 const Staging& stg, void* gout, const ActiveSet& act, void* tau_out, hipStream_t s);
 // Grid update over the active blocks: sums the staged windows and the outlier
 // grid (zeroing what it read) into grid_pre (m, mv), writes grid_post (v, m).
+// pre_cap < 0: grid_pre is the dense grid; pre_cap >= 0: grid_pre is a record
+// of pre_cap node entries in the order of the active list (more flag bit 4).
 // list_out / count_out (may be NULL) receive a copy of the active list.
-// The post-update grid of sub-step `step` rebuilt from its pre-update grid
-// over the listed active blocks (list, count: as the grid update wrote them).
+// The post-update grid of sub-step `step` rebuilt from the record of its
+// pre-update grid (pre_cap entries) over the listed active blocks (list,
+// count: as the grid update wrote them); pre_dense (may be NULL) also
+// receives the pre-update values at their grid positions.
 void launch_grid_post_from_pre(int prec, const KCfg& c, const Bufs& b, int step, const uint32_t* list,
-                               const uint32_t* count, const void* pre, void* post, hipStream_t s);
+                               const uint32_t* count, const void* pre, int64_t pre_cap, void* post, void* pre_dense,
+                               hipStream_t s);
 void launch_grid_update(int prec, const KCfg& c, const Bufs& b, int step, const Staging& stg, void* gout,
-                        const ActiveSet& act, void* grid_pre, void* grid_post, uint32_t* list_out,
+                        const ActiveSet& act, void* grid_pre, int64_t pre_cap, void* grid_post, uint32_t* list_out,
                         uint32_t* count_out, hipStream_t s);
 // Active set of a fresh binning: the blocks of the occupied tiles and of their
 // neighbours (a tile's window reaches one block beyond it on each side).
@@ -152,9 +157,11 @@ void launch_g2p_adj(int prec, const KCfg& c, const Bufs& b, const TileList& tl, 
 // the collision's position adjoint to x, and adds its pose adjoints to pose_bar.
 void launch_pcontact_adj(int prec, const KCfg& c, const Bufs& b, int nblk, int step, const void* st,
                          const void* grid_post, void* adj_next, double* pose_bar, hipStream_t s);
-// Over the active blocks (list, count) of the sub-step; zeroes gvb where it read it.
+// Over the active blocks (list, count) of the sub-step, with the record of
+// its pre-update grid (pre_cap entries in list order); zeroes gvb where it
+// read it.
 void launch_grid_adj(int prec, const KCfg& c, const Bufs& b, int step, const uint32_t* list, const uint32_t* count,
-                     const void* grid_pre, void* gvb, void* gb, double* pose_bar, hipStream_t s);
+                     const void* grid_pre, int64_t pre_cap, void* gvb, void* gb, double* pose_bar, hipStream_t s);
 // stress_form: the density adjoint of the sub-step as -sum_p (S_p : A bar_p) / rho,
 // S_p the stress part of A_p (valid while the grid adjoints are untreated,
 // where m bar = -v bar . (mv/m) / m holds); otherwise from the grid mass adjoint.

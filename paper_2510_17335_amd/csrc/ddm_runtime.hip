@@ -57,6 +57,8 @@ struct Layout {
          emd_val = 0;
   size_t total = 0;
   size_t state_bytes = 0, grid_bytes = 0;
+  int64_t rec_items = 0;              // node entries of one sub-step's pre-update grid record
+  size_t rec_bytes = 0;               // bytes of that record
   int64_t ntot = 0, nblk = 0, total_tiles = 0, max_chunks = 0;
   size_t win_bytes = 0;               // one staged window
   int n_ckpt = 0, K = 1, rows = 0, esz = 4, nwg = 1;
@@ -122,7 +124,14 @@ Layout make_layout(const ddm_config& c, int n_inst, const ddm_instance* in) {
   L.M = std::max(1, std::min<int>(c.record_segments, (c.max_steps + L.K - 1) / L.K));
   const size_t seg0 = cv.take(0);
   L.seg_state = cv.take(L.state_bytes * (L.K + 1));
-  L.seg_grid = cv.take(L.grid_bytes * L.K);
+  {
+    const int64_t npb = D == 3 ? ddm::kTile * ddm::kTile * ddm::kTile : ddm::kTile * ddm::kTile;
+    const int64_t blocks = c.grid_record_blocks > 0 ? std::min<int64_t>(c.grid_record_blocks, L.total_tiles)
+                                                     : L.total_tiles;
+    L.rec_items = blocks * npb;
+    L.rec_bytes = (size_t)L.rec_items * ddm::kNodeVals * b;
+  }
+  L.seg_grid = cv.take(L.rec_bytes * L.K);
   L.seg_tau = cv.take(L.tau_bytes * L.K);
   L.seg_perm = cv.take(sizeof(uint32_t) * ntot * L.K);
   L.seg_tiles = cv.take(sizeof(ddm::TileRec) * L.max_chunks * L.K);
@@ -365,7 +374,7 @@ struct ddm_ctx {
   // buffers of sub-step j of segment-buffer set m
   size_t sb(int m) const { return (size_t)m * L.seg_set; }
   void* slot(int m, int j) const { return at(sb(m) + L.seg_state + (size_t)j * L.state_bytes); }
-  void* gpre(int m, int j) const { return at(sb(m) + L.seg_grid + (size_t)j * L.grid_bytes); }
+  void* gpre(int m, int j) const { return at(sb(m) + L.seg_grid + (size_t)j * L.rec_bytes); }
   void* tau(int m, int j) const { return at(sb(m) + L.seg_tau + L.tau_bytes * (size_t)j); }
   uint32_t* perm(int m, int j) const { return at<uint32_t>(sb(m) + L.seg_perm + sizeof(uint32_t) * (size_t)L.ntot * j); }
   ddm::TileRec* seg_tile_recs(int m, int j) const {
@@ -434,6 +443,7 @@ ddm_status validate(const ddm_config* c, int32_t n_inst, const ddm_instance* in)
   if (c->max_steps < 1) return fail(DDM_EINVAL, "max_steps must be >= 1");
   if (c->sort_every < 0) return fail(DDM_EINVAL, "sort_every must be >= 0");
   if (c->tile_workgroups < 0 || c->tile_workgroups > (1 << 22)) return fail(DDM_EINVAL, "tile_workgroups out of [0, 2^22]");
+  if (c->grid_record_blocks < 0) return fail(DDM_EINVAL, "grid_record_blocks < 0");
   if (c->w_emd != 0.0 && c->dim != 3) return fail(DDM_EINVAL, "the EMD term needs dim 3");
   if (c->w_emd != 0.0 && c->hm_res * c->hm_res > ddm::kEmdMaxPoints)
     return fail(DDM_EINVAL, "the EMD term needs hm_res^2 <= 4096");
@@ -562,8 +572,9 @@ ddm_status forward_step(ddm_ctx* x, int64_t step, const ddm::TileList& tl, const
   const ddm::ActiveSet act = x->active();
   void* gout = x->at(x->L.gout);
   { Timed t(x, 0); ddm::launch_p2g(x->prec, x->kc, b, tl, tile_workgroups(x), st_in, st_out, stg, gout, act, tau_out, x->stream); }
-  { Timed t(x, 1); ddm::launch_grid_update(x->prec, x->kc, b, (int)step, stg, gout, act, gpre, gpost, list_out,
-                                           count_out, x->stream); }
+  // a recorded sub-step (list_out given) writes its pre-update grid as a record in active-list order
+  { Timed t(x, 1); ddm::launch_grid_update(x->prec, x->kc, b, (int)step, stg, gout, act, gpre,
+                                           list_out ? x->L.rec_items : -1, gpost, list_out, count_out, x->stream); }
   { Timed t(x, 2); ddm::launch_g2p(x->prec, x->kc, b, (int)x->L.nblk, (int)step, st_in, st_out, gpost, x->stream); }
   return launch_status();
 }
@@ -906,8 +917,11 @@ ddm_status ddm_rollout(ddm_ctx* x, int32_t n_steps) {
   }
   // the final state, its grids and its binning become the current ones
   DDM_HIP(hipMemcpyAsync(x->cur(), src, L.state_bytes, hipMemcpyDeviceToDevice, x->stream));
-  // (the post-update grid of the last sub-step is in grid_post already)
-  DDM_HIP(hipMemcpyAsync(x->at(L.grid_pre), x->gpre(m, len - 1), L.grid_bytes, hipMemcpyDeviceToDevice, x->stream));
+  // (the post-update grid of the last sub-step is in grid_post already and is
+  // rebuilt with the same values; the dense pre-update grid comes from its record)
+  ddm::launch_grid_post_from_pre(x->prec, x->kc, x->bufs(), (int)(x->steps - 1), x->seg_alist(m, len - 1),
+                                 x->seg_acount(m, len - 1), x->gpre(m, len - 1), L.rec_items, x->at(L.grid_post),
+                                 x->at(L.grid_pre), x->stream);
   x->need_sort = false;
   x->grid_valid = true;
   x->rec_first = first_rec;
@@ -1030,7 +1044,7 @@ ddm_status ddm_backward(ddm_ctx* x, const double* dloss_dev, double* grad_dev) {
       const bool reduce = rec || x->treat.mode == ddm::kTreatScale || x->treat.mode == ddm::kTreatNorm;
       if (reduce) { Timed t(x, 9); ddm::launch_fill_zero(acc, (int64_t)ddm::treat_acc_words(x->n_inst), 8, st); }
       { Timed t(x, 1); ddm::launch_grid_post_from_pre(x->prec, x->kc, b, (int)k, x->seg_alist(m, j), x->seg_acount(m, j),
-                                                      gpre(j), x->at(L.grid_post), st); }
+                                                      gpre(j), L.rec_items, x->at(L.grid_post), nullptr, st); }
       {
         Timed t(x, 4);
         if (x->kc.pcontact)
@@ -1043,7 +1057,7 @@ ddm_status ddm_backward(ddm_ctx* x, const double* dloss_dev, double* grad_dev) {
         treat_vectors(x, rec, TreatTarget{true, x->at(L.gvb), x->seg_alist(m, j), x->seg_acount(m, j), 3, false});
       }
       { Timed t(x, 5); ddm::launch_grid_adj(x->prec, x->kc, b, (int)k, x->seg_alist(m, j), x->seg_acount(m, j),
-                                            gpre(j), x->at(L.gvb), x->at(L.gb), x->at<double>(L.pose_bar), st); }
+                                            gpre(j), L.rec_items, x->at(L.gvb), x->at(L.gb), x->at<double>(L.pose_bar), st); }
       if (treat) {
         Timed t(x, 9);
         treat_vectors(x, rec, TreatTarget{true, x->at(L.gb), x->seg_alist(m, j), x->seg_acount(m, j), 4, true});
@@ -1343,6 +1357,9 @@ ddm_status ddm_check(ddm_ctx* x, ddm_device_error* out) {
   }
   if (e.flags & 1u) return fail(DDM_ENAN, "NaN or Inf in instance " + std::to_string(e.first_inst));
   if (e.flags & 2u) return fail(DDM_EDOMAIN, "a particle stencil left the grid in instance " + std::to_string(e.first_inst));
+  if (e.flags & 16u)
+    return fail(DDM_ENOMEM, "a recorded sub-step had more active grid blocks than grid_record_blocks (" +
+                                std::to_string(x->cfg.grid_record_blocks) + "): the reverse pass is not valid");
   return DDM_OK;
 }
 

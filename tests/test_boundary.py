@@ -102,6 +102,25 @@ def test_workspace_sizes(lib):
     assert s4.padded_particles == s3.padded_particles + 1024
 
 
+def test_grid_record_capacity_shrinks_the_workspace(lib):
+    """A record of the pre-update grid with a capacity of `blocks` active
+    blocks per sub-step takes K * (all blocks - blocks) * 4^3 nodes * 4 values
+    * 4 bytes less per segment set; 0 and more than all blocks are the full
+    record; a negative capacity is rejected."""
+    cfg, inst = _good()
+    cfg.record_segments = 3
+    all_blocks = (cfg.n_grid // 4) ** 3
+    full = ddm.workspace_query(cfg, [inst]).workspace_bytes
+    cfg.grid_record_blocks = all_blocks + 10
+    assert ddm.workspace_query(cfg, [inst]).workspace_bytes == full
+    cfg.grid_record_blocks = 100
+    small = ddm.workspace_query(cfg, [inst]).workspace_bytes
+    saved = cfg.record_segments * cfg.checkpoint_every * (all_blocks - 100) * 64 * 4 * 4
+    assert abs((full - small) - saved) <= 256 * 8 * cfg.record_segments, (full - small, saved)
+    cfg.grid_record_blocks = -1
+    assert "grid_record_blocks" in ddm.validate_config(cfg, [inst])
+
+
 def test_workspace_query_rejects_bad(lib):
     cfg, inst = _good()
     inst.nu = 0.7

@@ -5,7 +5,9 @@ with 1, 2 and all segments recorded as closely as two runs of one setting do
 (the order of atomic sums varies), also for a second reverse pass after the
 first, which replays every segment from its checkpoint; the
 workspace grows by one segment set per recorded segment, up to the segments
-of a max_steps rollout."""
+of a max_steps rollout.  A record of the pre-update grids that holds only
+the active blocks (ddm_config.grid_record_blocks) gives the same pass while
+it is large enough, and flags DDM_ENOMEM when it is not."""
 import sys
 
 import numpy as np
@@ -31,10 +33,11 @@ def ddm():
     return m
 
 
-def _run(ddm, record, precision="f32", passes=1):
+def _run(ddm, record, precision="f32", passes=1, grid_blocks=0, check=True):
     w = W.dig_3d(steps=STEPS)
     cfg, inst = ddm.from_workload(w, max_steps=STEPS, checkpoint_every=K, precision=precision)
     cfg.record_segments = record
+    cfg.grid_record_blocks = grid_blocks
     sim = ddm.Simulator(cfg, [inst])
     x0, tg = W.bed_positions(w), W.target_heightmap(w).reshape(1, -1)
     sim.init_state(x0)
@@ -42,8 +45,10 @@ def _run(ddm, record, precision="f32", passes=1):
     state = sim.packed_state(0)            # decoded: x, v, C, F per particle
     loss = sim.loss(tg).cpu().numpy()
     grads = [sim.backward().cpu().numpy() for _ in range(passes)]
-    assert sim.check().flags & 1 == 0
-    return int(sim.sizes.workspace_bytes), state, loss, grads
+    if check:
+        assert sim.check().flags & 1 == 0
+        return int(sim.sizes.workspace_bytes), state, loss, grads
+    return sim
 
 
 def _close(a, b, what, rtol=1e-6):
@@ -135,3 +140,52 @@ def test_autotune_between_rollout_and_backward(ddm):
     g = sim.backward().cpu().numpy()
     assert sim.check().flags & 1 == 0
     _close(g, g1[0], "gradient after autotune", rtol=1e-5)
+
+
+def _active_blocks(ddm, precision):
+    """The most active blocks over the sub-steps of a forward run of the dig."""
+    w = W.dig_3d(steps=STEPS)
+    cfg, inst = ddm.from_workload(w, max_steps=STEPS, checkpoint_every=K, precision=precision)
+    sim = ddm.Simulator(cfg, [inst])
+    sim.init_state(W.bed_positions(w))
+    most = 0
+    for _ in range(STEPS):
+        sim.step(1)
+        g = sim.get_grid()
+        most = max(most, int(round(float((g[0, :, 7] > 0).sum().item()) / 64)))
+    return most
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_grid_record_of_active_blocks(ddm, precision):
+    """The pre-update grids recorded as their active blocks only, with the
+    capacity set to the most active blocks of the run (every sub-step fits,
+    the largest exactly): the same final state, loss and gradient as the full
+    record, for all segments recorded (4) and for one (the others replayed
+    into the same smaller buffers); the workspace shrinks."""
+    most = _active_blocks(ddm, precision)
+    _log(f"case grid record of {most} active blocks (of 4096), dig3d {STEPS} steps K={K} {precision}")
+    assert 0 < most < 4096
+    tol = (1e-10, 1e-8) if precision == "f64" else (1e-6, 1e-5)
+    for record in (4, 1):
+        wsf, sf, lf, gf = _run(ddm, record, precision=precision)
+        wsc, sc, lc, gc = _run(ddm, record, precision=precision, grid_blocks=most)
+        _log(f"record_segments {record}: workspace {wsc / 2**30:.3f} GiB against {wsf / 2**30:.3f} GiB")
+        assert wsc < wsf
+        _same_state(sc, sf, f"final state, {record} recorded", 1e-5 if precision == "f32" else 1e-12)
+        _close(lc, lf, "loss", rtol=tol[0])
+        _close(gc[0], gf[0], f"gradient, {record} recorded", rtol=tol[1])
+
+
+def test_grid_record_too_small_is_flagged(ddm):
+    """A capacity below what a recorded sub-step needs: the grid update writes
+    only what fits, the reverse pass reads the rest as empty nodes, and
+    ddm_check reports DDM_ENOMEM with device error bit 4."""
+    _log(f"case grid record of 8 blocks, dig3d {STEPS} steps K={K} f32")
+    sim = _run(ddm, 2, grid_blocks=8, check=False)
+    with pytest.raises(ddm.DdmError) as e:
+        sim.check()
+    assert e.value.code == ddm.DDM_ENOMEM
+    err = ddm.DdmDeviceError()
+    ddm.lib().ddm_check(sim.ctx, ddm.C.byref(err))
+    assert err.flags & 16
