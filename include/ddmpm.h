@@ -409,6 +409,25 @@ ddm_status ddm_read_timing(ddm_ctx* ctx, int32_t group, double* total_ms, int64_
 /* Synchronises the stream and reads the device error word. */
 ddm_status ddm_check(ddm_ctx* ctx, ddm_device_error* out);
 
+/* Per-step diagnostics of the current state, per instance, into out_dev
+ * ([n_inst][DDM_N_DIAG] double, device, caller-owned), in this order:
+ *   0 particle mass N m_p (m_p = rho dx^dim / ppc),
+ *   1-3 momentum sum m_p v_p, 4 kinetic energy sum m_p |v_p|^2 / 2,
+ *   5-7 particles whose next constitutive update (on F_tmp = (I + dt C) F of
+ *       the current state) takes the return-map case tension/apex, inside the
+ *       cone, projection onto the cone (Eq. DP), 8 singular values that update
+ *       would clamp,
+ *   9 CFL number max_p max_a |v_a| dt / dx,
+ *   10 grid mass of the last sub-step's P2G (sum of the nodal masses the grid
+ *       update saw; equal to item 0 up to rounding, since each particle's
+ *       B-spline weights sum to one), NaN when no sub-step ran since
+ *       ddm_init_state, ddm_set_state or ddm_backward.
+ * Sums and counts are accumulated in FP64.  Asynchronous on the context's
+ * stream.  Errors: DDM_EINVAL for NULL pointers, DDM_ESTATE before
+ * ddm_init_state. */
+#define DDM_N_DIAG 11
+ddm_status ddm_diagnostics(ddm_ctx* ctx, double* out_dev);
+
 /* Sub-steps taken since ddm_init_state. */
 int64_t ddm_steps_taken(const ddm_ctx* ctx);
 

@@ -74,6 +74,8 @@ def lib():
         L.orc_treat.argtypes = [C.c_int, C.c_int, dp, C.c_double, C.c_double, C.c_double]
         L.orc_assign.restype = C.c_int
         L.orc_assign.argtypes = [C.c_int, C.c_int, dp, C.POINTER(C.c_int)]
+        L.orc_diagnostics.restype = C.c_int
+        L.orc_diagnostics.argtypes = [C.POINTER(OrcConfig), dp, C.c_int, dp, dp]
         L.orc_heightmap.restype = C.c_int
         L.orc_heightmap.argtypes = [C.POINTER(OrcConfig), C.c_int, dp, dp, C.POINTER(C.c_int)]
         L.orc_surface_particles.restype = C.c_int
@@ -350,3 +352,21 @@ def heightmap(cfg: OrcConfig, state: np.ndarray):
     own = np.zeros(npix, dtype=np.int32)
     lib().orc_heightmap(C.byref(cfg), state.shape[0], _p(state), _p(hm), own.ctypes.data_as(C.POINTER(C.c_int)))
     return hm, own
+
+
+DIAG_NAMES = ("mass", "momentum_x", "momentum_y", "momentum_z", "kinetic_energy", "case_tension", "case_elastic",
+              "case_projected", "clamps", "cfl", "grid_mass")
+
+
+def diagnostics(cfg: OrcConfig, params: np.ndarray, state: np.ndarray) -> np.ndarray:
+    """Diagnostics of a packed state (DIAG_NAMES): mass, momentum, kinetic
+    energy, the return-map cases and clamps of the next constitutive update,
+    the CFL number; the grid mass entry is NaN (it needs the last sub-step's
+    grid: sum the masses of rollout(..., grid=True))."""
+    state = np.ascontiguousarray(state, dtype=np.float64)
+    out = np.zeros(len(DIAG_NAMES))
+    rc = lib().orc_diagnostics(C.byref(cfg), _p(np.asarray(params, dtype=np.float64)), state.shape[0], _p(state),
+                               _p(out))
+    if rc != 0:
+        raise ValueError(f"orc_diagnostics failed ({rc})")
+    return out

@@ -1171,6 +1171,50 @@ static int rollout_reverse(const orc_config* c, const double* p, int N, const do
   return rc;
 }
 
+// ---------------------------------------------------------------------------
+// Per-step diagnostics of a state (x, v, C, F per particle): the particle
+// mass N m_p, the momentum sum m_p v_p, the kinetic energy sum m_p |v_p|^2 / 2,
+// the return-map case (Eq. DP) and the clamped singular values of the next
+// constitutive update on F_tmp = (I + dt C) F, and the CFL number
+// max_p max_a |v_a| dt / dx.  Plain loops over the particles; the cases come
+// from the same constitutive update the rollout runs.
+// ---------------------------------------------------------------------------
+static int diagnostics(const orc_config* c, const double* p, int N, const double* state_in, double* out) {
+  Sim<double> sim(*c, N);
+  sim.set_material(p[0], p[1], p[2], p[3]);
+  const int d = c->dim, sd = 2 * d + 2 * d * d;
+  for (int k = 0; k < 10; ++k) out[k] = 0.0;
+  for (int q = 0; q < N; ++q) {
+    const double* s = state_in + (size_t)q * sd;
+    double Cm[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, F[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+    for (int a = 0; a < d; ++a) for (int b = 0; b < d; ++b) {
+      Cm[a][b] = s[2 * d + a * d + b];
+      F[a][b] = s[2 * d + d * d + a * d + b];
+    }
+    out[0] += sim.mp;
+    double vmax = 0.0;
+    for (int a = 0; a < d; ++a) {
+      const double va = s[d + a];
+      out[1 + a] += sim.mp * va;
+      out[4] += 0.5 * sim.mp * va * va;
+      vmax = std::max(vmax, std::fabs(va));
+    }
+    out[9] = std::max(out[9], vmax * sim.dt * sim.inv_dx);
+    double Ft[3][3], Fn[3][3], tau[3][3];
+    for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) {
+      double acc = 0.0;
+      for (int k = 0; k < d; ++k) acc += ((i == k ? 1.0 : 0.0) + sim.dt * Cm[i][k]) * F[k][j];
+      Ft[i][j] = (i < d && j < d) ? acc : 0.0;
+    }
+    int cs = 0, ncl = 0;
+    constitutive(d, Ft, sim.mu, sim.lam, sim.alpha, sim.kc, Fn, tau, &cs, &ncl);
+    out[4 + cs] += 1.0;
+    out[8] += ncl;
+  }
+  out[10] = std::nan("");
+  return ORC_OK;
+}
+
 }  // namespace orc
 
 // ============================================================================
@@ -1189,6 +1233,14 @@ int orc_rollout(const orc_config* c, const double* p, int N, const double* state
                             grid_out, emd_target, emd_m);
   return rollout<double>(c, p, N, state_in, step0, n_steps, state_out, target, loss_out, nullptr, hm_out, stats,
                          grid_out, emd_target, emd_m);
+}
+
+// Diagnostics of a state (11 doubles: mass, momentum[3], kinetic energy,
+// return-map cases 1..3 and clamps of the next constitutive update, CFL
+// number, and NaN for the grid mass, which needs the last sub-step's grid).
+int orc_diagnostics(const orc_config* c, const double* p, int N, const double* state_in, double* out) {
+  if (validate(c, p) != ORC_OK || N < 0 || !state_in || !out) return ORC_EINVAL;
+  return diagnostics(c, p, N, state_in, out);
 }
 
 // Reverse-mode gradient of the loss with the gradient treatments of

@@ -107,6 +107,7 @@ def lib():
             "ddm_eval_math": (C.c_int, [i32, vp, vp, i64, vp]),
             "ddm_loss_noalloc": (C.c_int, [cfgp, instp, i32, vp, vp, vp, vp, vp]),
             "ddm_check": (C.c_int, [vp, C.POINTER(DdmDeviceError)]),
+            "ddm_diagnostics": (C.c_int, [vp, vp]),
             "ddm_steps_taken": (i64, [vp]),
             "ddm_instance_offset": (i64, [vp, i32]),
             "ddm_set_grad_treatment": (C.c_int, [vp, i32, C.c_double, C.c_double, C.c_double, vp, i32]),
@@ -552,6 +553,22 @@ class Simulator:
             _check(lib().ddm_read_timing(self.ctx, g, C.byref(ms), C.byref(n)))
             out[name] = (ms.value, n.value)
         return out
+
+    # -- diagnostics --------------------------------------------------------------
+    DIAG_NAMES = ("mass", "momentum_x", "momentum_y", "momentum_z", "kinetic_energy", "case_tension",
+                  "case_elastic", "case_projected", "clamps", "cfl", "grid_mass")
+
+    def diagnostics(self) -> np.ndarray:
+        """ddm_diagnostics: [n_inst, len(DIAG_NAMES)] float64 (host) for the
+        current state: particle mass, momentum, kinetic energy, the return-map
+        cases and clamps of the next constitutive update, the CFL number, and
+        the grid mass of the last sub-step (NaN when there is none)."""
+        t = self.torch
+        out = t.empty((self.n_inst, len(self.DIAG_NAMES)), dtype=t.float64, device=self.device)
+        self._inputs_ready()
+        _check(lib().ddm_diagnostics(self.ctx, C.c_void_p(out.data_ptr())))
+        self._outputs_ready()
+        return out.cpu().numpy()
 
     def check(self) -> DdmDeviceError:
         e = DdmDeviceError()

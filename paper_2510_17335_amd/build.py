@@ -15,8 +15,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libddmpm.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["ddm_kernels.hip", "ddm_sort.hip", "ddm_treat.hip", "ddm_emd.hip", "ddm_runtime.hip"]
-HEADERS = ["ddm_device.hpp", "ddm_kernels.hpp", os.path.join("..", "..", "include", "ddmpm.h")]
+SOURCES = ["ddm_kernels.hip", "ddm_sort.hip", "ddm_treat.hip", "ddm_emd.hip", "ddm_diag.hip", "ddm_runtime.hip"]
+HEADERS = ["ddm_device.hpp", "ddm_kernels.hpp", "ddm_state.hpp", os.path.join("..", "..", "include", "ddmpm.h")]
 
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-munsafe-fp-atomics",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wall"]

@@ -44,7 +44,8 @@ struct InstDev {
 
 // Device error word.
 struct DevErr {
-  unsigned int flags;                // 1: NaN/Inf, 2: stencil left the grid, 4: sigma clamped, 8/16: EMD (ddm_emd.hip)
+  unsigned int flags;                // 1: NaN/Inf, 2: stencil left the grid, 4: sigma clamped, 8: EMD (ddm_emd.hip),
+                                     // 16: a recorded sub-step had more active blocks than the grid record holds
   unsigned int first_inst;
   unsigned long long clamps;
 };
@@ -88,6 +89,10 @@ struct Bufs {
 
 // Forward sub-step pieces.  state_* are SoA particle states (stride ntot).
 void launch_fill_zero(void* p, int64_t count, int elem_bytes, hipStream_t s);
+// Per-instance diagnostics of the state and of the last grid (grid_pre may be
+// NULL: no grid), DDM_N_DIAG doubles per instance (ddm_diag.hip).
+void launch_diagnostics(int prec, const KCfg& c, const Bufs& b, int nblk, const void* state, const void* grid_pre,
+                        const ActiveSet& act, double* out, hipStream_t s);
 void launch_eval_math(int fn, const float* x, float* y, int64_t n, hipStream_t s);
 void launch_fill_u32(void* p, int64_t words, uint32_t value, hipStream_t s);
 // Particle state from positions x0[n][D] (instances concatenated): v = 0, C = 0,

@@ -1363,6 +1363,15 @@ ddm_status ddm_check(ddm_ctx* x, ddm_device_error* out) {
   return DDM_OK;
 }
 
+ddm_status ddm_diagnostics(ddm_ctx* x, double* out_dev) {
+  if (!x || !out_dev) return fail(DDM_EINVAL, "NULL argument");
+  if (!x->initialised) return fail(DDM_ESTATE, "ddm_init_state first");
+  static_assert(DDM_N_DIAG == 11, "diagnostics row");
+  ddm::launch_diagnostics(x->prec, x->kc, x->bufs(), (int)x->L.nblk, x->cur(),
+                          x->grid_valid ? x->at(x->L.grid_pre) : nullptr, x->active(), out_dev, x->stream);
+  return launch_status();
+}
+
 int64_t ddm_steps_taken(const ddm_ctx* x) { return x ? x->steps : -1; }
 
 int64_t ddm_instance_offset(const ddm_ctx* x, int32_t i) {
