@@ -40,7 +40,8 @@ def build(verbose: bool = False) -> str:
         if lines and verbose:
             print("\n".join(lines), file=sys.stderr)
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs, "-L/opt/rocm/lib",
+           "-lrocprofiler-sdk-roctx"]
     subprocess.run(cmd, check=True, stderr=subprocess.PIPE)
     os.replace(tmp, LIB)
     for o in objs:

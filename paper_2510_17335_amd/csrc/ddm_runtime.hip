@@ -2,6 +2,7 @@
 // skill's pose tables, the rollout with checkpoints and the reverse pass, and
 // the C interface declared in include/ddmpm.h.
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
 #include <cmath>
@@ -15,6 +16,17 @@
 
 #include "../../include/ddmpm.h"
 #include "ddm_kernels.hpp"
+
+// A roctx range over one phase of the library (host-side marker: a
+// `rocprofv3 --marker-trace` run shows rollouts, replays and reverse passes
+// as named spans; without a profiler the calls return at once).
+struct Phase {
+  bool on;
+  explicit Phase(const char* name, bool active = true) : on(active) { if (on) roctxRangePushA(name); }
+  ~Phase() { if (on) roctxRangePop(); }
+  Phase(const Phase&) = delete;
+  Phase& operator=(const Phase&) = delete;
+};
 
 namespace {
 
@@ -839,6 +851,7 @@ ddm_status ddm_init_state(ddm_ctx* x, const void* x0_dev) {
 }
 
 ddm_status ddm_step(ddm_ctx* x, int32_t n_steps) {
+  Phase phase("ddm_step");
   if (!x) return fail(DDM_EINVAL, "NULL context");
   if (!x->initialised) return fail(DDM_ESTATE, "ddm_init_state first");
   if (n_steps < 0) return fail(DDM_EINVAL, "n_steps < 0");
@@ -862,6 +875,7 @@ ddm_status ddm_step(ddm_ctx* x, int32_t n_steps) {
 }
 
 ddm_status ddm_rollout(ddm_ctx* x, int32_t n_steps) {
+  Phase phase("ddm_rollout");
   if (!x) return fail(DDM_EINVAL, "NULL context");
   if (!x->initialised) return fail(DDM_ESTATE, "ddm_init_state first");
   if (n_steps < 1) return fail(DDM_EINVAL, "n_steps must be >= 1");
@@ -876,6 +890,8 @@ ddm_status ddm_rollout(ddm_ctx* x, int32_t n_steps) {
   const int nseg = (n_steps + K - 1) / K;
   const int first_rec = nseg - std::min(L.M, nseg);
   const int64_t s_rec = (int64_t)first_rec * K;
+  {
+  Phase plain("unrecorded sub-steps", s_rec > 0);
   for (int i = 0; i < s_rec; ++i) {
     // Checkpoints hold the state before the binning of their step; every
     // checkpointed step re-bins, so a replayed segment needs nothing older.
@@ -896,6 +912,7 @@ ddm_status ddm_rollout(ddm_ctx* x, int32_t n_steps) {
     ++x->steps;
     x->grid_valid = true;
   }
+  }
   x->rec_tl_of.assign((size_t)L.M, std::vector<int>());
   const void* src = x->cur();
   int m = 0, len = 0;
@@ -910,6 +927,7 @@ ddm_status ddm_rollout(ddm_ctx* x, int32_t n_steps) {
     // sort_every steps
     const int R = x->cfg.sort_every;
     for (int j = 0; j < len; ++j) x->rec_sorted[(size_t)(s0 + j)] = j == 0 || (R > 0 && (k0 + s0 + j) % R == 0);
+    Phase record("recorded segment");
     const ddm_status s = run_segment(x, m, k0 + s0, len, src, &x->rec_sorted[(size_t)s0], true, x->rec_tl_of[(size_t)m]);
     if (s != DDM_OK) return s;
     src = x->slot(m, len);
@@ -933,6 +951,7 @@ ddm_status ddm_rollout(ddm_ctx* x, int32_t n_steps) {
 }
 
 ddm_status ddm_loss(ddm_ctx* x, const double* target_hm_dev, double* loss_dev) {
+  Phase phase("ddm_loss");
   if (!x || !target_hm_dev || !loss_dev) return fail(DDM_EINVAL, "NULL argument");
   if (!x->initialised) return fail(DDM_ESTATE, "ddm_init_state first");
   const int npix = x->cfg.dim == 3 ? x->cfg.hm_res * x->cfg.hm_res : x->cfg.hm_res;
@@ -991,6 +1010,7 @@ void treat_vectors(ddm_ctx* x, bool record, const TreatTarget& t) {
 }  // namespace
 
 ddm_status ddm_backward(ddm_ctx* x, const double* dloss_dev, double* grad_dev) {
+  Phase phase("ddm_backward");
   if (!x || !dloss_dev || !grad_dev) return fail(DDM_EINVAL, "NULL argument");
   if (!x->recorded || !x->loss_ready) return fail(DDM_ESTATE, "ddm_backward needs ddm_rollout then ddm_loss");
   const Layout& L = x->L;
@@ -1026,6 +1046,7 @@ ddm_status ddm_backward(ddm_ctx* x, const double* dloss_dev, double* grad_dev) {
     if (seg >= have) {
       tl_of = x->rec_tl_of[(size_t)m];
     } else {
+      Phase replay("replay segment");
       const ddm_status s = run_segment(x, 0, k0 + s0, len, x->at(L.ckpt + (size_t)seg * L.state_bytes),
                                        &x->rec_sorted[(size_t)s0], false, tl_of);
       if (s != DDM_OK) return s;
@@ -1036,6 +1057,7 @@ ddm_status ddm_backward(ddm_ctx* x, const double* dloss_dev, double* grad_dev) {
     auto gpost = [&](int) { return x->at(L.grid_post); };
     auto perm = [&](int j) { return x->perm(m, j); };
     auto tau = [&](int j) { return x->tau(m, j); };
+    Phase reverse("reverse segment");
     for (int j = len - 1; j >= 0; --j) {
       const ddm::TileList tl = x->seg_tiles(m, tl_of[j]);
       const int64_t k = k0 + s0 + j;
@@ -1175,6 +1197,7 @@ ddm_status ddm_pass(ddm_ctx* x, const void* x0_dev, int32_t n_steps, const doubl
 }
 
 ddm_status ddm_autotune(ddm_ctx* x, const char* cache_path, int32_t* sort_every_out) {
+  Phase phase("ddm_autotune");
   if (!x) return fail(DDM_EINVAL, "NULL context");
   if (!x->initialised) return fail(DDM_ESTATE, "ddm_init_state first (the probe runs on the current state)");
   const Layout& L = x->L;
