@@ -119,8 +119,8 @@ typedef struct ddm_config {
                                dim 3 only */
   int32_t tile_workgroups;  /* workgroups of the tile kernels (P2G and the G2P adjoint): 0 = about one
                                per occupied tile; n > 0 = a persistent launch of n workgroups that
-                               loop over the tile list, e.g. a multiple of the co-resident count;
-                               ddm_autotune chooses it */
+                               take the next tile from a counter in the workspace as they finish
+                               one (best near the co-resident count); ddm_autotune chooses it */
   int32_t grid_record_blocks; /* capacity of the record of one sub-step's pre-update grid in the
                                segment buffers, in blocks of 4^dim nodes over all instances: the
                                record keeps the active blocks only (those within one tile of an
@@ -275,7 +275,7 @@ ddm_status ddm_pass(ddm_ctx* ctx, const void* x0_dev, int32_t n_steps, const dou
  * binning interval R (ddm_config.sort_every) in {2, 4, 8, 16, 32}, then, at
  * that R, the workgroup count of the tile kernels (ddm_config.tile_workgroups)
  * in {0 (about one per tile), 4, 8, 16 and 32 per compute unit} (the latter
- * are persistent launches that loop over the tile list).  The state is
+ * are persistent launches that draw tiles from a work queue).  The state is
  * restored, and a recorded rollout, its loss and its checkpoints stay valid.
  * With cache_path != NULL, a line "ddmpm dim=.. n_grid=.. prec=.. n_inst=..
  * particles=.. ppc=.. sort_every=R tile_workgroups=W" for this problem is

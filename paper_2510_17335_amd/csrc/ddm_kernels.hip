@@ -25,6 +25,36 @@ __device__ __forceinline__ void flag_error(DevErr* e, unsigned int bit, int inst
   if (old == 0) atomicExch(&e->first_inst, (unsigned int)inst);
 }
 
+// Tiles of a tile kernel.  Without a queue, workgroup b takes tiles b, b +
+// gridDim.x, ... (one each when the grid has a workgroup per tile).  With one
+// (a persistent launch of fewer workgroups), thread 0 claims the next tile
+// from the queue's counter, so a workgroup that finishes early takes the next
+// tile without a new dispatch and the load balances itself; the workgroup
+// that finishes last resets the counters for the next launch.  Every call
+// is reached by the whole workgroup; the loop body ends with a barrier, so the
+// shared slot is read by all threads before thread 0 overwrites it.
+__device__ __forceinline__ uint32_t next_tile(const TileList& tl, uint32_t t, uint32_t* slot) {
+  if (!tl.queue) return t + gridDim.x;
+  if (threadIdx.x == 0) *slot = atomicAdd(tl.queue, 1u);
+  __syncthreads();
+  return *slot;
+}
+__device__ __forceinline__ uint32_t first_tile(const TileList& tl, uint32_t* slot) {
+  if (!tl.queue) return blockIdx.x;
+  if (threadIdx.x == 0) *slot = atomicAdd(tl.queue, 1u);
+  __syncthreads();
+  return *slot;
+}
+__device__ __forceinline__ void finish_tiles(const TileList& tl) {
+  if (!tl.queue || threadIdx.x != 0) return;
+  __threadfence();
+  if (atomicAdd(tl.queue + 1, 1u) == gridDim.x - 1) {
+    tl.queue[0] = 0u;
+    tl.queue[1] = 0u;
+    __threadfence();
+  }
+}
+
 // Stencil of one particle: base node, fractional offset, weights and their
 // derivatives per axis.  Returns false (and flags) when a node would fall
 // outside [0, n).
@@ -460,7 +490,8 @@ __global__ void __launch_bounds__(kBlock) k_p2g(KCfg c, Bufs b, TileList tl, con
   __shared__ RunLDS<T> rl;
   const uint32_t ntiles = *tl.count;
   const P<T, D> si = pv<T, D>(st_in, c.ntot), so = pv<T, D>(st_out, c.ntot);
-  for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+  __shared__ uint32_t tile_slot;
+  for (uint32_t t = first_tile(tl, &tile_slot); t < ntiles; t = next_tile(tl, t, &tile_slot)) {
     const TileRec tr = tl.list[t];
     int inst, org[3];
     tile_origin<D>(c, tr.tile, inst, org);
@@ -522,6 +553,7 @@ __global__ void __launch_bounds__(kBlock) k_p2g(KCfg c, Bufs b, TileList tl, con
     }
     __syncthreads();
   }
+  finish_tiles(tl);
 }
 
 void launch_p2g(int prec, const KCfg& c, const Bufs& b, const TileList& tl, int nwg, const void* st_in, void* st_out,
@@ -1241,7 +1273,8 @@ __global__ void __launch_bounds__(kBlock) k_g2p_adj(KCfg c, Bufs b, TileList tl,
   const Adj<T, D> an = av<T, D>(adj_next, c.ntot), ac = av<T, D>(adj_cur, c.ntot);
   const T dx = T(c.dx), inv_dx = T(c.inv_dx), Dk = T(4.0 * c.inv_dx * c.inv_dx);
   constexpr int WS = Win<D>::stride;
-  for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+  __shared__ uint32_t tile_slot;
+  for (uint32_t t = first_tile(tl, &tile_slot); t < ntiles; t = next_tile(tl, t, &tile_slot)) {
     const TileRec tr = tl.list[t];
     int inst, org[3];
     tile_origin<D>(c, tr.tile, inst, org);
@@ -1382,6 +1415,7 @@ __global__ void __launch_bounds__(kBlock) k_g2p_adj(KCfg c, Bufs b, TileList tl,
     }
     __syncthreads();
   }
+  finish_tiles(tl);
 }
 
 void launch_g2p_adj(int prec, const KCfg& c, const Bufs& b, const TileList& tl, int nwg, const void* st,

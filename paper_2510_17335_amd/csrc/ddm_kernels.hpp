@@ -19,7 +19,9 @@ constexpr int kWin = kTile + 4;      // LDS window edge in nodes: tile + stencil
 // Tiles and grid node blocks share one index space: tile t holds the cells
 // [4t, 4t + 4) per axis and node block t the nodes [4t, 4t + 4).
 struct TileRec { uint32_t start, end, tile; };
-struct TileList { const TileRec* list; const uint32_t* count; };
+// queue (may be NULL): two words {next, done} of a persistent launch, zero
+// before the launch and again after it (the last workgroup resets them).
+struct TileList { const TileRec* list; const uint32_t* count; uint32_t* queue; };
 
 // Window of a tile in the staging buffer: record r holds kWin^D nodes of
 // kNodeVals values (node (l0, l1[, l2]) of the window at ((l0 kWin + l1) kWin + l2)),

@@ -64,7 +64,7 @@ struct Layout {
   size_t hm_bits = 0, owner = 0, target = 0, hm_val = 0, dldh = 0, region = 0, dldm = 0, loss = 0;
   size_t keys0 = 0, keys1 = 0, vals0 = 0, vals1 = 0, hist = 0, sums = 0, tstart = 0, tend = 0, tiles = 0, tcount = 0;
   size_t tslot = 0, staging = 0, gout = 0, amask = 0, alist = 0, acount = 0, seg_alist = 0, seg_acount = 0;
-  size_t treat_acc = 0;
+  size_t treat_acc = 0, tqueue = 0;
   size_t emd_top = 0, emd_own = 0, emd_target = 0, emd_obs = 0, emd_slot = 0, emd_nobs = 0, emd_assign = 0,
          emd_val = 0;
   size_t total = 0;
@@ -121,6 +121,7 @@ Layout make_layout(const ddm_config& c, int n_inst, const ddm_instance* in) {
   L.poses = cv.take((size_t)n_inst * c.max_steps * ddm::kPoseVals * b);
   L.pose_jac = cv.take((size_t)n_inst * c.max_steps * 8 * ddm::kSkillParams * sizeof(double));
   L.err = cv.take(sizeof(ddm::DevErr));
+  L.tqueue = cv.take(2 * sizeof(uint32_t));
   L.pid = cv.take(sizeof(uint32_t) * ntot);
   L.pid_tmp = cv.take(sizeof(uint32_t) * ntot);
   L.cur = cv.take(L.state_bytes);
@@ -382,7 +383,11 @@ struct ddm_ctx {
   template <typename T = char> T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
   void* cur() const { return at(cur_off); }
   uint32_t* pid() const { return at<uint32_t>(pid_off); }
-  ddm::TileList tiles() const { return ddm::TileList{at<const ddm::TileRec>(L.tiles), at<const uint32_t>(L.tcount)}; }
+  // a persistent launch (tile_workgroups > 0) takes its tiles from the queue words
+  uint32_t* tile_queue() const { return cfg.tile_workgroups > 0 ? at<uint32_t>(L.tqueue) : nullptr; }
+  ddm::TileList tiles() const {
+    return ddm::TileList{at<const ddm::TileRec>(L.tiles), at<const uint32_t>(L.tcount), tile_queue()};
+  }
   // buffers of sub-step j of segment-buffer set m
   size_t sb(int m) const { return (size_t)m * L.seg_set; }
   void* slot(int m, int j) const { return at(sb(m) + L.seg_state + (size_t)j * L.state_bytes); }
@@ -393,7 +398,7 @@ struct ddm_ctx {
     return at<ddm::TileRec>(sb(m) + L.seg_tiles + sizeof(ddm::TileRec) * L.max_chunks * j);
   }
   uint32_t* seg_tcount(int m, int j) const { return at<uint32_t>(sb(m) + L.seg_tcount + sizeof(uint32_t) * j); }
-  ddm::TileList seg_tiles(int m, int j) const { return ddm::TileList{seg_tile_recs(m, j), seg_tcount(m, j)}; }
+  ddm::TileList seg_tiles(int m, int j) const { return ddm::TileList{seg_tile_recs(m, j), seg_tcount(m, j), tile_queue()}; }
   ddm::Staging staging() const { return ddm::Staging{at<void>(L.staging), at<const uint32_t>(L.tslot)}; }
   ddm::ActiveSet active() const {
     return ddm::ActiveSet{at<uint32_t>(L.amask), at<uint32_t>(L.alist), at<uint32_t>(L.acount)};
@@ -811,6 +816,7 @@ ddm_status ddm_create(const ddm_config* cfg, int32_t n_inst, const ddm_instance*
 
   s = upload_instances(x, inst);
   if (s == DDM_OK) s = hip_check(hipMemset(x->at(L.err), 0, sizeof(ddm::DevErr)), "clear error word");
+  if (s == DDM_OK) s = hip_check(hipMemset(x->at(L.tqueue), 0, 2 * sizeof(uint32_t)), "clear tile queue");
   if (s != DDM_OK) { delete x; return s; }
   *out = x;
   return DDM_OK;

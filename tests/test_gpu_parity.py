@@ -508,15 +508,19 @@ def test_drift_beyond_windows_f64(ddm, orc):
     assert np.all(rel < 1e-6), rel
 
 
-def test_pass_graph_replays_match_eager(ddm):
+@pytest.mark.parametrize("workgroups", [0, 8])
+def test_pass_graph_replays_match_eager(ddm, workgroups):
     """A captured full pass (init, recorded rollout, loss, backward) replayed
     several times, with eager work and synchronisations in between and new
-    input values in between, gives what the eager calls give each time."""
+    input values in between, gives what the eager calls give each time; with
+    one workgroup per tile and with a persistent launch of 8 workgroups, whose
+    tile queue every launch leaves cleared for the next replay."""
     import torch
     w = W.tiny(3, shovel=True, steps=40)
     tgt = W.target_heightmap(w)
     x0 = W.bed_positions(w)
     cfg, inst = ddm.from_workload(w, max_steps=40, checkpoint_every=16)
+    cfg.tile_workgroups = workgroups
 
     def eager(xa, tg):
         sim = ddm.Simulator(cfg, [inst])
@@ -526,7 +530,7 @@ def test_pass_graph_replays_match_eager(ddm):
         grad = sim.backward().cpu().numpy()
         return loss, grad, sim.packed_state(0)
 
-    _log("case graph replay")
+    _log(f"case graph replay, tile workgroups {workgroups}")
     ref = eager(x0, tgt)
     x1 = x0 + 0.25 / w.n_grid * np.sin(np.arange(x0.size)).reshape(x0.shape)
     tgt1 = tgt + 0.01
@@ -580,9 +584,9 @@ def test_autotune_restores_state_and_caches(ddm, orc, tmp_path):
 @pytest.mark.parametrize("workgroups", [3, 8, 1024])
 def test_persistent_tile_launch_matches_oracle(ddm, orc, workgroups):
     """The tile kernels (P2G, G2P adjoint) as a persistent launch of a fixed
-    number of workgroups that loop over the tile list (fewer than, and more
-    than, the occupied tiles): state, loss and gradient against the oracle
-    (FP64), as with one workgroup per tile."""
+    number of workgroups that draw tiles from a work queue (fewer than, and
+    more than, the occupied tiles): state, loss and gradient against the
+    oracle (FP64), as with one workgroup per tile."""
     w = W.tiny(3, shovel=True, steps=40)
     tgt = W.target_heightmap(w)
     cfg, inst = ddm.from_workload(w, max_steps=40, checkpoint_every=16)
