@@ -117,10 +117,11 @@ typedef struct ddm_config {
   double w_emd;             /* weight of the earth mover's distance (Eq. emd) between the surface
                                observation and the target set by ddm_set_emd_target; 0 = off;
                                dim 3 only */
-  int32_t tile_workgroups;  /* workgroups of the tile kernels (P2G and the G2P adjoint): 0 = about one
-                               per occupied tile; n > 0 = a persistent launch of n workgroups that
-                               take the next tile from a counter in the workspace as they finish
-                               one (best near the co-resident count); ddm_autotune chooses it */
+  int32_t tile_workgroups;  /* workgroups of the P2G tile kernel: 0 = about one per occupied tile;
+                               n > 0 = a persistent launch of n workgroups that take the next tile
+                               from a counter in the workspace as they finish one (best near the
+                               co-resident count); ddm_autotune chooses it.  The G2P adjoint, the
+                               other tile kernel, runs one workgroup per tile */
   int32_t grid_record_blocks; /* capacity of the record of one sub-step's pre-update grid in the
                                segment buffers, in blocks of 4^dim nodes over all instances: the
                                record keeps the active blocks only (those within one tile of an
@@ -129,6 +130,20 @@ typedef struct ddm_config {
                                4^dim 4 element-size bytes; a recorded sub-step with more active
                                blocks than that sets device error bit 4 and ddm_check then reports
                                DDM_ENOMEM (the gradient of that pass is not valid) */
+  int32_t deterministic;    /* 1: every result (states, grids, loss, gradients, pose and material
+                               adjoints) is bitwise the same from run to run and for any
+                               tile_workgroups: the particles are binned before every sub-step
+                               (sort_every is then ignored), a cell's particles in the order of their
+                               ids (so that a state set with ddm_set_state continues bitwise as the
+                               uninterrupted run), the LDS windows of the tile kernels add
+                               their cells' contributions in a fixed order (cells in 3^dim residue
+                               classes, one class at a time), the G2P adjoint stages its windows and
+                               the grid adjoint's input sums them in a fixed order, and every
+                               reduction over particles or grid blocks sums per-workgroup partials
+                               in index order (no floating-point atomics).  Slower (about 4x the
+                               pass time), for debugging and reproducibility; ddm_diagnostics sums
+                               stay unordered, and the normalisation treatment (whose 2-norm is
+                               reduced with atomics) is rejected.  0: the fast unordered sums */
 } ddm_config;
 
 /* One simulation instance: material, skill and time step. */
@@ -273,9 +288,11 @@ ddm_status ddm_pass(ddm_ctx* ctx, const void* x0_dev, int32_t n_steps, const dou
 /* Chooses the launch configuration of this context by timing the same
  * forward sub-steps from the current state, after a warm-up round: first the
  * binning interval R (ddm_config.sort_every) in {2, 4, 8, 16, 32}, then, at
- * that R, the workgroup count of the tile kernels (ddm_config.tile_workgroups)
- * in {0 (about one per tile), 4, 8, 16 and 32 per compute unit} (the latter
- * are persistent launches that draw tiles from a work queue).  The state is
+ * that R, the workgroup count of P2G (ddm_config.tile_workgroups) in {0
+ * (about one per tile), 4, 8, 16 and 32 per compute unit} (the latter are
+ * persistent launches that draw tiles from a work queue).  In the
+ * deterministic mode R has no effect and only the workgroup count is
+ * probed.  The state is
  * restored, and a recorded rollout, its loss and its checkpoints stay valid.
  * With cache_path != NULL, a line "ddmpm dim=.. n_grid=.. prec=.. n_inst=..
  * particles=.. ppc=.. sort_every=R tile_workgroups=W" for this problem is
@@ -283,7 +300,7 @@ ddm_status ddm_pass(ddm_ctx* ctx, const void* x0_dev, int32_t n_steps, const dou
  * chosen R is written to *sort_every_out (may be NULL) and both values are
  * readable with ddm_get_launch.  Synchronises the stream.  DDM_ESTATE before
  * ddm_init_state.  The results do not depend on R or W beyond the order of
- * floating-point atomic sums. */
+ * floating-point atomic sums (not at all in the deterministic mode). */
 ddm_status ddm_autotune(ddm_ctx* ctx, const char* cache_path, int32_t* sort_every_out);
 
 /* The context's current binning interval and tile-kernel workgroup count
@@ -380,7 +397,8 @@ ddm_status ddm_loss_noalloc(const ddm_config* cfg, const ddm_instance* inst, int
  *   drops a captured ddm_pass graph.
  *   Errors: DDM_EINVAL for a NULL context, an unknown mode, clip <= 0 with
  *   DDM_TREAT_CLIP, a non-finite oom, delta < 0 or non-finite, stats_steps < 0,
- *   or stats_dev and stats_steps > 0 not given together. */
+ *   stats_dev and stats_steps > 0 not given together, or DDM_TREAT_NORM in a
+ *   deterministic context. */
 typedef enum ddm_grad_treatment {
   DDM_TREAT_NONE = 0,
   DDM_TREAT_CLIP = 1,

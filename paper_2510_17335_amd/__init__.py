@@ -40,6 +40,7 @@ class DdmConfig(C.Structure):
         ("w_mass", C.c_double), ("w_hm", C.c_double), ("checkpoint_every", C.c_int32), ("max_steps", C.c_int32),
         ("sort_every", C.c_int32), ("skill_unrounded", C.c_int32), ("particle_contact", C.c_int32),
         ("record_segments", C.c_int32), ("w_emd", C.c_double), ("tile_workgroups", C.c_int32), ("grid_record_blocks", C.c_int32),
+        ("deterministic", C.c_int32),
     ]
 
 
@@ -143,7 +144,8 @@ def make_config(dim: int, n_grid: int, precision: str = "f32", *, bound: int = 3
                 region_depth: float = 0.03, m_target: float = 0.192, m_ref: float = 0.384, w_mass: float = 1.0,
                 w_hm: float = 1.0, region_sign: int = -1, checkpoint_every: int = 50,
                 max_steps: int = 1000, sort_every: int = 8, skill_unrounded: bool = False,
-                particle_contact: bool = False, w_emd: float = 0.0, record_segments: int = 1) -> DdmConfig:
+                particle_contact: bool = False, w_emd: float = 0.0, record_segments: int = 1,
+                deterministic: bool = False) -> DdmConfig:
     c = DdmConfig()
     c.dim, c.n_grid, c.bound = dim, n_grid, bound
     c.precision = DDM_F64 if precision == "f64" else DDM_F32
@@ -161,6 +163,7 @@ def make_config(dim: int, n_grid: int, precision: str = "f32", *, bound: int = 3
     c.skill_unrounded, c.particle_contact = int(bool(skill_unrounded)), int(bool(particle_contact))
     c.w_emd = float(w_emd)
     c.record_segments = int(record_segments)
+    c.deterministic = int(bool(deterministic))
     return c
 
 
@@ -179,7 +182,7 @@ def make_instance(n_particles: int, *, E=3.5e5, nu=0.3, phi_deg=30.0, rho=1600.0
 
 
 def from_workload(w, max_steps: Optional[int] = None, checkpoint_every: Optional[int] = None,
-                  precision: Optional[str] = None, sort_every: int = 8):
+                  precision: Optional[str] = None, sort_every: int = 8, deterministic: bool = False):
     """(config, instance) for an object with the attributes of a workload
     description (dim, n_grid, dt, ppc, material, skill, ...)."""
     cfg = make_config(
@@ -190,7 +193,7 @@ def from_workload(w, max_steps: Optional[int] = None, checkpoint_every: Optional
         w_hm=w.w_hm, region_sign=w.region_sign,
         checkpoint_every=checkpoint_every or w.checkpoint_every or 50,
         max_steps=max_steps or w.steps, sort_every=sort_every, skill_unrounded=w.skill_unrounded,
-        particle_contact=w.particle_contact, w_emd=w.w_emd)
+        particle_contact=w.particle_contact, w_emd=w.w_emd, deterministic=deterministic)
     p = w.params
     inst = make_instance(w.n_particles, E=p[0], nu=p[1], phi_deg=p[2], rho=p[3], cohesion=w.material.cohesion,
                          depth=p[4], angle_deg=p[5], push=p[6], dt=w.dt, tip0=w.tip0, displace=p[7],

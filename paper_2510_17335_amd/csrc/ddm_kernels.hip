@@ -33,17 +33,19 @@ __device__ __forceinline__ void flag_error(DevErr* e, unsigned int bit, int inst
 // that finishes last resets the counters for the next launch.  Every call
 // is reached by the whole workgroup; the loop body ends with a barrier, so the
 // shared slot is read by all threads before thread 0 overwrites it.
+// The claimed index is read back as a wave-uniform value, so that the tile's
+// record and origin stay in scalar registers.
 __device__ __forceinline__ uint32_t next_tile(const TileList& tl, uint32_t t, uint32_t* slot) {
   if (!tl.queue) return t + gridDim.x;
   if (threadIdx.x == 0) *slot = atomicAdd(tl.queue, 1u);
   __syncthreads();
-  return *slot;
+  return __builtin_amdgcn_readfirstlane(*slot);
 }
 __device__ __forceinline__ uint32_t first_tile(const TileList& tl, uint32_t* slot) {
   if (!tl.queue) return blockIdx.x;
   if (threadIdx.x == 0) *slot = atomicAdd(tl.queue, 1u);
   __syncthreads();
-  return *slot;
+  return __builtin_amdgcn_readfirstlane(*slot);
 }
 __device__ __forceinline__ void finish_tiles(const TileList& tl) {
   if (!tl.queue || threadIdx.x != 0) return;
@@ -113,8 +115,10 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// With part (the deterministic mode's partials) the workgroup's sums go to
+// part[blockIdx.x][k] instead, zeros included, for launch_det_finish.
 template <int N>
-__device__ __forceinline__ void block_accumulate(double (&v)[N], double* dst) {
+__device__ __forceinline__ void block_accumulate(double (&v)[N], double* dst, double* part = nullptr) {
   __shared__ double red[kBlock / 64][N];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
@@ -127,7 +131,52 @@ __device__ __forceinline__ void block_accumulate(double (&v)[N], double* dst) {
     double s = 0.0;
 #pragma unroll
     for (int w = 0; w < kBlock / 64; ++w) s += red[w][threadIdx.x];
-    if (s != 0.0) atomicAdd(&dst[threadIdx.x], s);
+    if (part) part[(int64_t)blockIdx.x * kDetVals + threadIdx.x] = s;
+    else if (s != 0.0) atomicAdd(&dst[threadIdx.x], s);
+  }
+}
+
+// Fixed-order sum of one instance's partials (one workgroup per instance):
+// thread t sums a contiguous run of blocks, the runs are combined by the wave
+// butterfly and then wave by wave; the partials read are zeroed.
+__global__ void __launch_bounds__(kBlock) k_det_finish(KCfg c, Bufs b, int grid_blocks, int nvals, double* dst,
+                                                       int64_t stride) {
+  __shared__ double red[kBlock / 64][kDetVals];
+  const int inst = blockIdx.x;
+  int64_t b0, b1;
+  if (grid_blocks) {
+    const int64_t per = (int64_t)1 << (c.dim * (c.nlog2 - 2));
+    b0 = inst * per;
+    b1 = b0 + per;
+  } else {
+    const InstDev& I = b.inst[inst];
+    b0 = I.off / kBlock;
+    b1 = b0 + (I.n + kBlock - 1) / kBlock;
+  }
+  const int64_t chunk = (b1 - b0 + kBlock - 1) / kBlock;
+  const int64_t lo = b0 + threadIdx.x * chunk, hi = min(b1, lo + chunk);
+  double acc[kDetVals];
+#pragma unroll
+  for (int k = 0; k < kDetVals; ++k) acc[k] = 0.0;
+  for (int64_t q = lo; q < hi; ++q) {
+    double* row = b.dpart + q * kDetVals;
+#pragma unroll
+    for (int k = 0; k < kDetVals; ++k) {
+      if (k < nvals) { acc[k] += row[k]; row[k] = 0.0; }
+    }
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < kDetVals; ++k) {
+    const double v = wave_sum(acc[k]);
+    if (lane == 0) red[wid][k] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < nvals) {
+    double v = 0.0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) v += red[w][threadIdx.x];
+    dst[(int64_t)inst * stride + threadIdx.x] += v;
   }
 }
 
@@ -342,7 +391,20 @@ __device__ __forceinline__ void put_record(RunLDS<T>& L, int t, const T (&q)[3],
 // registers, more items, but each item reads the run's records again).  Both
 // scatter kernels use planes: P2G ran 568 us per launch with rows and 516 with
 // planes on the 64-instance workload.  Ends synchronised.
-template <typename T, int D, int NV, int NN>
+// NCOL = 1: every item adds to the window at once (LDS atomics in arbitrary
+// order).  NCOL = 3^D (the deterministic mode, with particles binned before
+// the sub-step so that a cell's particles form one run): pass k takes the runs
+// whose base cell lies in residue class k (window coordinates modulo 3 per
+// axis), whose 3^D stencils are disjoint, so that every node receives at most
+// one addition per pass and the passes fix the order.
+template <int D>
+__device__ __forceinline__ int base_class(int wbase) {
+  const int i = wbase / Win<D>::xs, r = wbase - i * Win<D>::xs;
+  if (D == 2) return (i % 3) * 3 + r % 3;
+  return ((i % 3) * 3 + (r / kWin) % 3) * 3 + (r % kWin) % 3;
+}
+
+template <typename T, int D, int NV, int NN, int NCOL>
 __device__ void run_scatter_round(RunLDS<T>& L, int rc, double* win, T m) {
   constexpr int WS = Win<D>::stride;
   constexpr int NJ = NN / 3;                                  // rows per item
@@ -358,6 +420,7 @@ __device__ void run_scatter_round(RunLDS<T>& L, int rc, double* win, T m) {
   if (flag) L.start[off + __popcll(bal & ((1ull << lane) - 1ull))] = (unsigned short)t;
   if (t == 0) L.start[tot] = (unsigned short)rc;
   __syncthreads();
+  for (int col = 0; col < NCOL; ++col) {
   for (int it = t; it < tot * ITEMS; it += kBlock) {
     const int r = it / ITEMS, sub = it - r * ITEMS;
     // the item's first row: 3D (o0, j0), 2D j0; rows j0 .. j0 + NJ - 1 along the middle axis
@@ -365,6 +428,7 @@ __device__ void run_scatter_round(RunLDS<T>& L, int rc, double* win, T m) {
     const int j0 = NJ == 3 ? 0 : (D == 3 ? sub % 3 : sub);
     const int s0 = L.start[r], s1 = L.start[r + 1];
     const int base = L.wbase[s0];
+    if (NCOL > 1 && base_class<D>(base) != col) continue;
     // acc[row j][node k][value]: 3D node (o0, j0 + j, k), 2D node (j0 + j, k)
     T acc[NJ][3][4];
 #pragma unroll
@@ -427,6 +491,8 @@ __device__ void run_scatter_round(RunLDS<T>& L, int rc, double* win, T m) {
         if (NV == D + 1) atomicAdd(win + 3 * WS + wi, (double)(acc[j][k][3] * m));
       }
   }
+  if (NCOL > 1) __syncthreads();
+  }
   __syncthreads();
 }
 
@@ -482,7 +548,7 @@ __device__ __forceinline__ void scatter_stencil(const T (&wt)[3][3], const T (&q
 // grid update sums the windows covering each node.  Particles outside the
 // window (drifted more than one cell since binning) add to the outlier grid
 // with global atomics and put their node blocks in the active set.
-template <typename T, int D>
+template <typename T, int D, bool DET>
 __global__ void __launch_bounds__(kBlock) k_p2g(KCfg c, Bufs b, TileList tl, const void* st_in, void* st_out,
                                                 T* __restrict__ stg, T* __restrict__ gout, ActiveSet act,
                                                 T* __restrict__ tau_out) {
@@ -539,7 +605,7 @@ __global__ void __launch_bounds__(kBlock) k_p2g(KCfg c, Bufs b, TileList tl, con
       }
       rl.wbase[threadIdx.x] = wb;
       __syncthreads();
-      run_scatter_round<T, D, D + 1, 9>(rl, rc, win, mpt);
+      run_scatter_round<T, D, D + 1, 9, DET ? (D == 3 ? 27 : 9) : 1>(rl, rc, win, mpt);
     }
     __syncthreads();
     // the whole window, zeros included, to the tile's staging record
@@ -556,15 +622,24 @@ __global__ void __launch_bounds__(kBlock) k_p2g(KCfg c, Bufs b, TileList tl, con
   finish_tiles(tl);
 }
 
+void launch_det_finish(const KCfg& c, const Bufs& b, bool grid_blocks, int nvals, double* dst, int64_t stride,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_det_finish, dim3(c.n_inst), dim3(kBlock), 0, s, c, b, grid_blocks ? 1 : 0, nvals, dst, stride);
+}
+
 void launch_p2g(int prec, const KCfg& c, const Bufs& b, const TileList& tl, int nwg, const void* st_in, void* st_out,
                 const Staging& stg, void* gout, const ActiveSet& act, void* tau_out, hipStream_t s) {
 #define DDM_P2G(T, DD)                                                                                             \
-  hipLaunchKernelGGL((k_p2g<T, DD>), dim3(nwg), dim3(kBlock), 0, s, c, b, tl, st_in, st_out, (T*)stg.win, (T*)gout, \
-                     act, (T*)tau_out)
+  if (c.det)                                                                                                       \
+    hipLaunchKernelGGL((k_p2g<T, DD, true>), dim3(nwg), dim3(kBlock), 0, s, c, b, tl, st_in, st_out, (T*)stg.win,  \
+                       (T*)gout, act, (T*)tau_out);                                                                \
+  else                                                                                                             \
+    hipLaunchKernelGGL((k_p2g<T, DD, false>), dim3(nwg), dim3(kBlock), 0, s, c, b, tl, st_in, st_out, (T*)stg.win, \
+                       (T*)gout, act, (T*)tau_out)
   if (prec == 0) {
-    if (c.dim == 3) DDM_P2G(float, 3); else DDM_P2G(float, 2);
+    if (c.dim == 3) { DDM_P2G(float, 3); } else { DDM_P2G(float, 2); }
   } else {
-    if (c.dim == 3) DDM_P2G(double, 3); else DDM_P2G(double, 2);
+    if (c.dim == 3) { DDM_P2G(double, 3); } else { DDM_P2G(double, 2); }
   }
 #undef DDM_P2G
 }
@@ -1140,7 +1215,7 @@ __global__ void __launch_bounds__(kBlock) k_region_mass(KCfg c, Bufs b, const vo
       v[0] = (double)(region_weights<T, D>(c, bl, S, gw) * T(I.mp));
     }
   }
-  block_accumulate<1>(v, region + inst);
+  block_accumulate<1>(v, region + inst, b.dpart);
 }
 
 template <typename T, int D>
@@ -1185,8 +1260,10 @@ void launch_loss(int prec, const KCfg& c, const Bufs& b, int nblk, const void* s
 #define DDM_LOSS(T, DD)                                                                                      \
   hipLaunchKernelGGL((k_hm_max<T, DD>), dim3(nblk), dim3(kBlock), 0, s, c, b, state, L.hm_bits);            \
   hipLaunchKernelGGL((k_hm_owner<T, DD>), dim3(nblk), dim3(kBlock), 0, s, c, b, state, pid, L.hm_bits, L.owner); \
-  if (DD == 3 && c.shovel && c.w_mass != 0.0)                                                                \
+  if (DD == 3 && c.shovel && c.w_mass != 0.0) {                                                              \
     hipLaunchKernelGGL((k_region_mass<T, 3>), dim3(nblk), dim3(kBlock), 0, s, c, b, state, final_step, L.region); \
+    if (b.dpart) launch_det_finish(c, b, false, 1, L.region, 1, s);                                           \
+  }                                                                                                          \
   hipLaunchKernelGGL((k_loss_final<T, DD>), dim3(c.n_inst), dim3(kBlock), 0, s, c, L.hm_bits, L.owner, L);
   if (prec == 0) {
     if (c.dim == 3) { DDM_LOSS(float, 3) } else { DDM_LOSS(float, 2) }
@@ -1242,7 +1319,7 @@ __global__ void __launch_bounds__(kBlock) k_loss_seed(KCfg c, Bufs b, const void
     ad.v(a, p) = T(0);
     for (int bb = 0; bb < D; ++bb) { ad.C(a, bb, p) = T(0); ad.G(a, bb, p) = T(0); }
   }
-  block_accumulate<1>(racc, pacc + (int64_t)inst * 8 + 4);
+  block_accumulate<1>(racc, pacc + (int64_t)inst * 8 + 4, b.dpart);
 }
 
 void launch_loss_seed(int prec, const KCfg& c, const Bufs& b, int nblk, const void* state, const uint32_t* pid,
@@ -1254,6 +1331,7 @@ void launch_loss_seed(int prec, const KCfg& c, const Bufs& b, int nblk, const vo
     if (c.dim == 3) hipLaunchKernelGGL((k_loss_seed<double, 3>), dim3(nblk), dim3(kBlock), 0, s, c, b, state, pid, final_step, L, adj, pacc);
     else hipLaunchKernelGGL((k_loss_seed<double, 2>), dim3(nblk), dim3(kBlock), 0, s, c, b, state, pid, final_step, L, adj, pacc);
   }
+  if (b.dpart) launch_det_finish(c, b, false, 1, pacc + 4, 8, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -1261,10 +1339,10 @@ void launch_loss_seed(int prec, const KCfg& c, const Bufs& b, int nblk, const vo
 //   xbar = x'bar + sum_i [grad w (v_i . vb + (4/dx^2) v_i^T C'bar r) - (4/dx^2) w C'bar^T v_i]
 //   v_i bar += w (vb + (4/dx^2) C'bar r)            (scattered to the grid)
 // ---------------------------------------------------------------------------
-template <typename T, int D>
+template <typename T, int D, bool DET>
 __global__ void __launch_bounds__(kBlock) k_g2p_adj(KCfg c, Bufs b, TileList tl, const void* stv,
                                                     const T* __restrict__ post, const void* adj_next, void* adj_cur,
-                                                    T* __restrict__ gvb) {
+                                                    T* __restrict__ gvb, T* __restrict__ stg) {
   __shared__ double win[Win<D>::stride * D];
   __shared__ RunLDS<T> rl;
   __shared__ alignas(16) T gwin[Win<D>::nodes][kNodeVals];     // grid velocities of the tile's window
@@ -1273,8 +1351,9 @@ __global__ void __launch_bounds__(kBlock) k_g2p_adj(KCfg c, Bufs b, TileList tl,
   const Adj<T, D> an = av<T, D>(adj_next, c.ntot), ac = av<T, D>(adj_cur, c.ntot);
   const T dx = T(c.dx), inv_dx = T(c.inv_dx), Dk = T(4.0 * c.inv_dx * c.inv_dx);
   constexpr int WS = Win<D>::stride;
-  __shared__ uint32_t tile_slot;
-  for (uint32_t t = first_tile(tl, &tile_slot); t < ntiles; t = next_tile(tl, t, &tile_slot)) {
+  // a plain grid-stride loop: the work queue's loop form costs this kernel ten
+  // registers and a wave per SIMD
+  for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const TileRec tr = tl.list[t];
     int inst, org[3];
     tile_origin<D>(c, tr.tile, inst, org);
@@ -1397,13 +1476,19 @@ __global__ void __launch_bounds__(kBlock) k_g2p_adj(KCfg c, Bufs b, TileList tl,
     } while (false);
     rl.wbase[threadIdx.x] = wb;
     __syncthreads();
-    run_scatter_round<T, D, D, 9>(rl, rc, win, T(0));
+    run_scatter_round<T, D, D, 9, DET ? (D == 3 ? 27 : 9) : 1>(rl, rc, win, T(0));
     }
     __syncthreads();
     for (int i = threadIdx.x; i < Win<D>::nodes; i += kBlock) {
       int l[3];
       Win<D>::coords(i, l);
       const int wi = Win<D>::idx(l[0], l[1], l[2]);
+      if (DET) {
+        // the whole window, zeros included, to the tile's record (the layout of P2G's staging)
+        st_node(stg + ((int64_t)t * Win<D>::nodes + i) * kNodeVals, (T)win[wi], (T)win[WS + wi],
+                D == 3 ? (T)win[2 * WS + wi] : T(0), T(0));
+        continue;
+      }
       bool any = false;
 #pragma unroll
       for (int a = 0; a < D; ++a) any |= win[a * WS + wi] != 0.0;
@@ -1415,18 +1500,57 @@ __global__ void __launch_bounds__(kBlock) k_g2p_adj(KCfg c, Bufs b, TileList tl,
     }
     __syncthreads();
   }
-  finish_tiles(tl);
+}
+
+// The staged windows of the G2P adjoint (deterministic mode) added to the
+// v-bar grid node by node, each node's covering windows in a fixed order.
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock) k_adj_windows(KCfg c, Bufs b, const uint32_t* __restrict__ list,
+                                                        const uint32_t* __restrict__ count, const T* __restrict__ stg,
+                                                        const uint32_t* __restrict__ tslot, T* __restrict__ gvb) {
+  constexpr int NPB = D == 3 ? kTile * kTile * kTile : kTile * kTile;
+  const int64_t items = (int64_t)(*count) * NPB;
+  for (int64_t it = (int64_t)blockIdx.x * kBlock + threadIdx.x; it < items; it += (int64_t)gridDim.x * kBlock) {
+    int inst, idx[3];
+    int64_t node;
+    active_node<D>(c, list[it / NPB], (int)(it % NPB), inst, idx, node);
+    T acc[4] = {T(0), T(0), T(0), T(0)};
+    gather_windows<T, D>(c, inst, idx, stg, tslot, acc);
+    T* dst = gvb + (b.inst[inst].goff + node) * kNodeVals;
+#pragma unroll
+    for (int a = 0; a < D; ++a) dst[a] += acc[a];
+  }
 }
 
 void launch_g2p_adj(int prec, const KCfg& c, const Bufs& b, const TileList& tl, int nwg, const void* st,
-                    const void* post, const void* adj_next, void* adj_cur, void* gvb, hipStream_t s) {
+                    const void* post, const void* adj_next, void* adj_cur, void* gvb, void* stg, hipStream_t s) {
+#define DDM_G2PADJ(T, DD)                                                                                         \
+  if (stg)                                                                                                          \
+    hipLaunchKernelGGL((k_g2p_adj<T, DD, true>), dim3(nwg), dim3(kBlock), 0, s, c, b, tl, st, (const T*)post,      \
+                       adj_next, adj_cur, (T*)gvb, (T*)stg);                                                        \
+  else                                                                                                              \
+    hipLaunchKernelGGL((k_g2p_adj<T, DD, false>), dim3(nwg), dim3(kBlock), 0, s, c, b, tl, st, (const T*)post,     \
+                       adj_next, adj_cur, (T*)gvb, (T*)nullptr)
   if (prec == 0) {
-    if (c.dim == 3) hipLaunchKernelGGL((k_g2p_adj<float, 3>), dim3(nwg), dim3(kBlock), 0, s, c, b, tl, st, (const float*)post, adj_next, adj_cur, (float*)gvb);
-    else hipLaunchKernelGGL((k_g2p_adj<float, 2>), dim3(nwg), dim3(kBlock), 0, s, c, b, tl, st, (const float*)post, adj_next, adj_cur, (float*)gvb);
+    if (c.dim == 3) { DDM_G2PADJ(float, 3); } else { DDM_G2PADJ(float, 2); }
   } else {
-    if (c.dim == 3) hipLaunchKernelGGL((k_g2p_adj<double, 3>), dim3(nwg), dim3(kBlock), 0, s, c, b, tl, st, (const double*)post, adj_next, adj_cur, (double*)gvb);
-    else hipLaunchKernelGGL((k_g2p_adj<double, 2>), dim3(nwg), dim3(kBlock), 0, s, c, b, tl, st, (const double*)post, adj_next, adj_cur, (double*)gvb);
+    if (c.dim == 3) { DDM_G2PADJ(double, 3); } else { DDM_G2PADJ(double, 2); }
   }
+#undef DDM_G2PADJ
+}
+
+void launch_adj_windows(int prec, const KCfg& c, const Bufs& b, const uint32_t* list, const uint32_t* count,
+                        const void* stg, const uint32_t* tslot, void* gvb, hipStream_t s) {
+  const unsigned nb = active_grid(c);
+#define DDM_AW(T, DD)                                                                                            \
+  hipLaunchKernelGGL((k_adj_windows<T, DD>), dim3(nb), dim3(kBlock), 0, s, c, b, list, count, (const T*)stg, tslot, \
+                     (T*)gvb)
+  if (prec == 0) {
+    if (c.dim == 3) DDM_AW(float, 3); else DDM_AW(float, 2);
+  } else {
+    if (c.dim == 3) DDM_AW(double, 3); else DDM_AW(double, 2);
+  }
+#undef DDM_AW
 }
 
 // ---------------------------------------------------------------------------
@@ -1501,7 +1625,9 @@ __global__ void __launch_bounds__(kBlock) k_pcontact_adj(KCfg c, Bufs b, int ste
     }
   }
   // a 256-slot block belongs to one instance
-  if (D == 3 && c.shovel && __any(any)) {
+  if (D == 3 && c.shovel && b.dpart) {
+    block_accumulate<8>(pb, nullptr, b.dpart);
+  } else if (D == 3 && c.shovel && __any(any)) {
     double* dst = pose_bar + ((int64_t)inst * c.max_steps + step) * 8;
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
@@ -1520,6 +1646,8 @@ void launch_pcontact_adj(int prec, const KCfg& c, const Bufs& b, int nblk, int s
     if (c.dim == 3) hipLaunchKernelGGL((k_pcontact_adj<double, 3>), dim3(nblk), dim3(kBlock), 0, s, c, b, step, st, (const double*)post, adj_next, pose_bar);
     else hipLaunchKernelGGL((k_pcontact_adj<double, 2>), dim3(nblk), dim3(kBlock), 0, s, c, b, step, st, (const double*)post, adj_next, pose_bar);
   }
+  if (b.dpart && c.dim == 3 && c.shovel)
+    launch_det_finish(c, b, false, 8, pose_bar + (int64_t)step * 8, (int64_t)c.max_steps * 8, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -1608,11 +1736,17 @@ __global__ void __launch_bounds__(kBlock) k_grid_adj(KCfg c, Bufs b, int step, c
     gb[gid * kNodeVals + 2] = ub[2];
     gb[gid * kNodeVals + 3] = mb;
     if (D == 3 && c.shovel && __any(any)) {
-      double* dst = pose_bar + ((int64_t)inst * c.max_steps + step) * 8;
+      // the 64 lanes hold the nodes of one block: its sums go to the block's
+      // partials in the deterministic mode
+      double* dst = b.dpart ? b.dpart + (int64_t)list[it / NPB] * kDetVals
+                            : pose_bar + ((int64_t)inst * c.max_steps + step) * 8;
 #pragma unroll
       for (int k = 0; k < 8; ++k) {
         const double sum = wave_sum(pb[k]);
-        if ((threadIdx.x & 63) == 0 && sum != 0.0) atomicAdd(dst + k, sum);
+        if ((threadIdx.x & 63) == 0) {
+          if (b.dpart) dst[k] = sum;
+          else if (sum != 0.0) atomicAdd(dst + k, sum);
+        }
       }
     }
   }
@@ -1630,6 +1764,8 @@ void launch_grid_adj(int prec, const KCfg& c, const Bufs& b, int step, const uin
     if (c.dim == 3) DDM_GA(double, 3); else DDM_GA(double, 2);
   }
 #undef DDM_GA
+  if (b.dpart && c.dim == 3 && c.shovel)
+    launch_det_finish(c, b, true, 8, pose_bar + (int64_t)step * 8, (int64_t)c.max_steps * 8, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -1798,7 +1934,7 @@ __global__ void __launch_bounds__(kBlock) k_p2g_adj_gather(KCfg c, Bufs b, const
       }
     }
   }
-  block_accumulate<1>(acc, pacc + (int64_t)inst * 8 + 4);
+  block_accumulate<1>(acc, pacc + (int64_t)inst * 8 + 4, b.dpart);
 }
 
 template <typename T, int D>
@@ -1847,7 +1983,7 @@ __global__ void __launch_bounds__(kBlock) k_p2g_adj_constit(KCfg c, Bufs b, cons
     acc[2] = (double)alb;
     acc[3] = (double)kcb;
   }
-  block_accumulate<4>(acc, pacc + (int64_t)inst * 8);
+  block_accumulate<4>(acc, pacc + (int64_t)inst * 8, b.dpart);
 }
 
 void launch_p2g_adj(int prec, const KCfg& c, const Bufs& b, int nblk, const void* st, const void* tau, const void* gb,
@@ -1859,7 +1995,9 @@ void launch_p2g_adj(int prec, const KCfg& c, const Bufs& b, int nblk, const void
   else                                                                                                             \
     hipLaunchKernelGGL((k_p2g_adj_gather<T, DD, false>), dim3(nblk), dim3(kBlock), 0, s, c, b, st,                 \
                        (const T*)tau, (const T*)gb, adj_cur, pacc);                                                \
-  hipLaunchKernelGGL((k_p2g_adj_constit<T, DD>), dim3(nblk), dim3(kBlock), 0, s, c, b, st, adj_next, adj_cur, pacc);
+  if (b.dpart) launch_det_finish(c, b, false, 1, pacc + 4, 8, s);                                                  \
+  hipLaunchKernelGGL((k_p2g_adj_constit<T, DD>), dim3(nblk), dim3(kBlock), 0, s, c, b, st, adj_next, adj_cur, pacc); \
+  if (b.dpart) launch_det_finish(c, b, false, 4, pacc, 8, s);
   if (prec == 0) {
     if (c.dim == 3) { DDM_P2GADJ(float, 3) } else { DDM_P2GADJ(float, 2) }
   } else {

@@ -8,6 +8,7 @@ namespace ddm {
 
 constexpr int kBlock = 256;          // particle kernels: threads per block, and the
                                      // padding unit of every instance's particle range
+constexpr int kDetVals = 8;          // partial sums per block in the deterministic mode
 constexpr int kNodeVals = 4;         // node record: mv[0..2] (or v), m
 constexpr int kPoseVals = 10;        // device pose row of a sub-step
 constexpr int kSkillParams = 5;      // skill parameters of the pose Jacobian (depth, angle, push, displace, push angle)
@@ -62,6 +63,7 @@ struct KCfg {
   double hm_ox, hm_oz, hm_pix, hm_off, region_depth;
   double w_hm, w_mass, m_target, m_ref;
   double w_emd;
+  int det;                           // deterministic mode: fixed-order window and reduction sums
 };
 
 // Node of an active-set item: item i is node i % 4^D of listed block i / 4^D.
@@ -87,7 +89,18 @@ struct Bufs {
   const int* blk_inst;               // instance of every particle block
   const void* poses;                 // [n_inst][max_steps][kPoseVals]: tip xyz, psi, vel xyz, omega, sin psi, cos psi
   DevErr* err;
+  // deterministic mode: 8 partial sums per particle block or per grid block,
+  // all zero between uses (each reduction's finish clears what it read); NULL
+  // otherwise (reductions add with atomics)
+  double* dpart = nullptr;
 };
+
+// Deterministic reductions: adds to dst[i * stride + k] (k < nvals) the
+// partials of instance i in dpart, summed in a fixed order, and zeroes them.
+// grid_blocks: the partials are indexed by global node block (instance i owns
+// blocks [i per, (i + 1) per)); otherwise by particle block.
+void launch_det_finish(const KCfg& c, const Bufs& b, bool grid_blocks, int nvals, double* dst, int64_t stride,
+                       hipStream_t s);
 
 // Forward sub-step pieces.  state_* are SoA particle states (stride ntot).
 void launch_fill_zero(void* p, int64_t count, int elem_bytes, hipStream_t s);
@@ -156,8 +169,14 @@ void launch_loss_seed(int prec, const KCfg& c, const Bufs& b, int nblk, const vo
                       int final_step, const LossBufs& L, void* adj, double* pacc, hipStream_t s);
 
 // Adjoint sub-step pieces (reverse order: g2p_adj, grid_adj, p2g_adj).
+// stg (may be NULL): the deterministic mode's staging records, one per listed
+// tile, which receive each tile's window instead of atomics into gvb; then
+// launch_adj_windows adds them to gvb (tslot: the record of each tile of the
+// sub-step's list, as launch_tile_slots builds it).
 void launch_g2p_adj(int prec, const KCfg& c, const Bufs& b, const TileList& tl, int nwg, const void* st,
-                    const void* grid_post, const void* adj_next, void* adj_cur, void* gvb, hipStream_t s);
+                    const void* grid_post, const void* adj_next, void* adj_cur, void* gvb, void* stg, hipStream_t s);
+void launch_adj_windows(int prec, const KCfg& c, const Bufs& b, const uint32_t* list, const uint32_t* count,
+                        const void* stg, const uint32_t* tslot, void* gvb, hipStream_t s);
 // Adjoint of the particle-level collision of sub-step `step` (run before the
 // G2P adjoint when c.pcontact): rewrites the x and v rows of adj_next so that
 // the G2P adjoint sees the adjoint of the velocity before the collision, adds
@@ -178,8 +197,11 @@ void launch_grad_final(const KCfg& c, const InstDev* inst, const double* pacc, c
                        const double* pose_jac, int n_steps, const double* dloss, double* grad, hipStream_t s);
 
 // Binning (ddm_sort.hip).
+// Cell keys of the particles in slot order, or of the particles order[j]
+// (order may be NULL); vals receive the particle slots.
 void launch_keys(int prec, const KCfg& c, const Bufs& b, int nblk, const void* state, uint32_t* keys, uint32_t* vals,
-                 hipStream_t s);
+                 hipStream_t s, const uint32_t* order = nullptr);
+void launch_pid_keys(const uint32_t* pid, uint32_t* keys, uint32_t* vals, int64_t ntot, hipStream_t s);
 int sort_passes(uint32_t max_key);
 int64_t sort_hist_words(int64_t n);
 int64_t sort_sum_words(int64_t n);
@@ -189,6 +211,8 @@ void launch_gather(int elem_bytes, const void* in, void* out, const uint32_t* pe
                    const uint32_t* pid_in, uint32_t* pid_out, hipStream_t s);
 void launch_unpermute(int elem_bytes, const void* in, void* out, const uint32_t* perm, int rows, int64_t ntot,
                       hipStream_t s);
+// tslot of a recorded tile list: tslot[list[r].tile] = r, kNoSlot elsewhere.
+void launch_tile_slots(const KCfg& c, const TileList& tl, int64_t max_records, uint32_t* tslot, hipStream_t s);
 // One record per occupied tile, and tslot (record of each tile, or kNoSlot).
 void launch_tile_list(const KCfg& c, const uint32_t* sorted_keys, uint32_t* tstart, uint32_t* tend, TileRec* list,
                       uint32_t* count, uint32_t* tslot, hipStream_t s);

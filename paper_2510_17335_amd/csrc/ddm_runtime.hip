@@ -64,7 +64,7 @@ struct Layout {
   size_t hm_bits = 0, owner = 0, target = 0, hm_val = 0, dldh = 0, region = 0, dldm = 0, loss = 0;
   size_t keys0 = 0, keys1 = 0, vals0 = 0, vals1 = 0, hist = 0, sums = 0, tstart = 0, tend = 0, tiles = 0, tcount = 0;
   size_t tslot = 0, staging = 0, gout = 0, amask = 0, alist = 0, acount = 0, seg_alist = 0, seg_acount = 0;
-  size_t treat_acc = 0, tqueue = 0;
+  size_t treat_acc = 0, tqueue = 0, dpart = 0, ckpt_pid = 0, rpid0 = 0, rpid1 = 0;
   size_t emd_top = 0, emd_own = 0, emd_target = 0, emd_obs = 0, emd_slot = 0, emd_nobs = 0, emd_assign = 0,
          emd_val = 0;
   size_t total = 0;
@@ -184,6 +184,15 @@ Layout make_layout(const ddm_config& c, int n_inst, const ddm_instance* in) {
   L.amask = cv.take(sizeof(uint32_t) * L.total_tiles);
   L.alist = cv.take(sizeof(uint32_t) * L.total_tiles);
   L.acount = cv.take(sizeof(uint32_t));
+  // deterministic mode: partial sums per particle block or grid block
+  if (c.deterministic) {
+    L.dpart = cv.take(sizeof(double) * ddm::kDetVals * (size_t)std::max(L.nblk, L.total_tiles));
+    // the particle ids at every checkpoint and a pair for the replays: a cell's
+    // particles are ordered by id at every binning
+    L.ckpt_pid = cv.take(sizeof(uint32_t) * (size_t)ntot * L.n_ckpt);
+    L.rpid0 = cv.take(sizeof(uint32_t) * (size_t)ntot);
+    L.rpid1 = cv.take(sizeof(uint32_t) * (size_t)ntot);
+  }
   if (D == 3 && c.w_emd != 0.0) {
     const size_t np = (size_t)n_inst * c.hm_res * c.hm_res;
     L.emd_top = cv.take(8 * np);
@@ -407,12 +416,14 @@ struct ddm_ctx {
     return at<uint32_t>(sb(m) + L.seg_alist + sizeof(uint32_t) * L.total_tiles * j);
   }
   uint32_t* seg_acount(int m, int j) const { return at<uint32_t>(sb(m) + L.seg_acount + sizeof(uint32_t) * j); }
+  uint32_t* ckpt_pid(int64_t k) const { return at<uint32_t>(L.ckpt_pid + sizeof(uint32_t) * (size_t)L.ntot * k); }
   ddm::Bufs bufs() const {
     ddm::Bufs b;
     b.inst = at<const ddm::InstDev>(L.inst);
     b.blk_inst = at<const int>(L.blk_inst);
     b.poses = at<const void>(L.poses);
     b.err = at<ddm::DevErr>(L.err);
+    b.dpart = cfg.deterministic ? at<double>(L.dpart) : nullptr;
     return b;
   }
   ddm::EmdBufs emdbufs() const {
@@ -461,6 +472,7 @@ ddm_status validate(const ddm_config* c, int32_t n_inst, const ddm_instance* in)
   if (c->sort_every < 0) return fail(DDM_EINVAL, "sort_every must be >= 0");
   if (c->tile_workgroups < 0 || c->tile_workgroups > (1 << 22)) return fail(DDM_EINVAL, "tile_workgroups out of [0, 2^22]");
   if (c->grid_record_blocks < 0) return fail(DDM_EINVAL, "grid_record_blocks < 0");
+  if (c->deterministic != 0 && c->deterministic != 1) return fail(DDM_EINVAL, "deterministic must be 0 or 1");
   if (c->w_emd != 0.0 && c->dim != 3) return fail(DDM_EINVAL, "the EMD term needs dim 3");
   if (c->w_emd != 0.0 && c->hm_res * c->hm_res > ddm::kEmdMaxPoints)
     return fail(DDM_EINVAL, "the EMD term needs hm_res^2 <= 4096");
@@ -549,8 +561,23 @@ ddm_status bin_state(ddm_ctx* x, const void* src, void* dst, const uint32_t* pid
   hipStream_t st = x->stream;
   uint32_t* keys[2] = {x->at<uint32_t>(L.keys0), x->at<uint32_t>(L.keys1)};
   uint32_t* vals[2] = {x->at<uint32_t>(L.vals0), x->at<uint32_t>(L.vals1)};
-  ddm::launch_keys(x->prec, x->kc, x->bufs(), (int)L.nblk, src, keys[0], vals[0], st);
-  const int r = ddm::radix_sort(keys, vals, L.ntot, L.max_key, x->at<uint32_t>(L.hist), x->at<uint32_t>(L.sums), st);
+  int r = 0;
+  if (x->kc.det) {
+    // deterministic mode: a cell's particles in id order, whatever their slot
+    // order before (a stable sort by id, then the stable sort by cell)
+    if (!pid_src) return fail(DDM_ESTATE, "binning without particle ids in the deterministic mode");
+    ddm::launch_pid_keys(pid_src, keys[0], vals[0], L.ntot, st);
+    const int r1 = ddm::radix_sort(keys, vals, L.ntot, (uint32_t)L.ntot, x->at<uint32_t>(L.hist),
+                                   x->at<uint32_t>(L.sums), st);
+    uint32_t* k2[2] = {keys[1 - r1], keys[r1]};
+    uint32_t* v2[2] = {vals[1 - r1], vals[r1]};
+    ddm::launch_keys(x->prec, x->kc, x->bufs(), (int)L.nblk, src, k2[0], v2[0], st, vals[r1]);
+    const int r2 = ddm::radix_sort(k2, v2, L.ntot, L.max_key, x->at<uint32_t>(L.hist), x->at<uint32_t>(L.sums), st);
+    r = k2[r2] == keys[0] ? 0 : 1;
+  } else {
+    ddm::launch_keys(x->prec, x->kc, x->bufs(), (int)L.nblk, src, keys[0], vals[0], st);
+    r = ddm::radix_sort(keys, vals, L.ntot, L.max_key, x->at<uint32_t>(L.hist), x->at<uint32_t>(L.sums), st);
+  }
   ddm::launch_gather(L.esz, src, dst, vals[r], L.rows, L.ntot, pid_src, pid_dst, st);
   ddm::launch_tile_list(x->kc, keys[r], x->at<uint32_t>(L.tstart), x->at<uint32_t>(L.tend), x->at<ddm::TileRec>(L.tiles),
                         x->at<uint32_t>(L.tcount), x->at<uint32_t>(L.tslot), st);
@@ -572,8 +599,8 @@ ddm_status bin_current(ddm_ctx* x) {
   return s;
 }
 
-// Workgroups of the tile kernels: the configured persistent count, or about
-// one per occupied tile.
+// Workgroups of P2G: the configured persistent count, or about one per
+// occupied tile.
 int tile_workgroups(const ddm_ctx* x) {
   return x->cfg.tile_workgroups > 0 ? (int)x->cfg.tile_workgroups : x->L.nwg;
 }
@@ -596,9 +623,11 @@ ddm_status forward_step(ddm_ctx* x, int64_t step, const ddm::TileList& tl, const
   return launch_status();
 }
 
+// The deterministic mode bins before every sub-step (a cell's particles then
+// form one run of the tile kernels' scatter).
 bool sort_due(const ddm_ctx* x, int64_t step) {
   const int R = x->cfg.sort_every;
-  return x->need_sort || (R > 0 && step % R == 0);
+  return x->need_sort || x->cfg.deterministic || (R > 0 && step % R == 0);
 }
 
 // Runs `len` sub-steps from step k_first into the segment buffers as the
@@ -610,17 +639,24 @@ bool sort_due(const ddm_ctx* x, int64_t step) {
 // replay of the reverse pass leaves them alone.  tl_of[j]: the slot whose
 // tile list step j uses.
 ddm_status run_segment(ddm_ctx* x, int m, int64_t k_first, int len, const void* src, const char* bins,
-                       bool move_pid, std::vector<int>& tl_of) {
+                       bool move_pid, std::vector<int>& tl_of, const uint32_t* replay_pid = nullptr) {
   void* spare = x->at(x->spare_off);
   tl_of.assign((size_t)len, 0);
   int last = 0;
+  // a replay in the deterministic mode carries the ids of its checkpoint
+  // through its binnings in a pair of its own
+  uint32_t* rp[2] = {x->at<uint32_t>(x->L.rpid0), x->at<uint32_t>(x->L.rpid1)};
+  const uint32_t* rpid_cur = replay_pid;
+  int rsel = 0;
   for (int j = 0; j < len; ++j) {
     if (bins[j]) {
-      const ddm_status s = bin_state(x, j == 0 ? src : spare, x->slot(m, j), move_pid ? x->pid() : nullptr,
-                                     move_pid ? x->at<uint32_t>(x->pid_spare_off) : nullptr, x->perm(m, j),
+      const uint32_t* pin = move_pid ? x->pid() : rpid_cur;
+      uint32_t* pout = move_pid ? x->at<uint32_t>(x->pid_spare_off) : (rpid_cur ? rp[rsel] : nullptr);
+      const ddm_status s = bin_state(x, j == 0 ? src : spare, x->slot(m, j), pin, pout, x->perm(m, j),
                                      x->seg_tile_recs(m, j), x->seg_tcount(m, j));
       if (s != DDM_OK) return s;
       if (move_pid) std::swap(x->pid_off, x->pid_spare_off);
+      else if (rpid_cur) { rpid_cur = rp[rsel]; rsel = 1 - rsel; }
       last = j;
     } else if (j == 0) {
       DDM_HIP(hipMemcpyAsync(x->slot(m, 0), src, x->L.state_bytes, hipMemcpyDeviceToDevice, x->stream));
@@ -659,6 +695,7 @@ ddm::KCfg make_kcfg(const ddm_config& c, int n_inst, int64_t ntot) {
   k.hm_off = c.hm_offset; k.region_depth = c.region_depth;
   k.w_hm = c.w_hm; k.w_mass = c.w_mass; k.m_target = c.m_target; k.m_ref = c.m_ref;
   k.w_emd = c.w_emd;
+  k.det = c.deterministic ? 1 : 0;
   return k;
 }
 
@@ -817,6 +854,9 @@ ddm_status ddm_create(const ddm_config* cfg, int32_t n_inst, const ddm_instance*
   s = upload_instances(x, inst);
   if (s == DDM_OK) s = hip_check(hipMemset(x->at(L.err), 0, sizeof(ddm::DevErr)), "clear error word");
   if (s == DDM_OK) s = hip_check(hipMemset(x->at(L.tqueue), 0, 2 * sizeof(uint32_t)), "clear tile queue");
+  if (s == DDM_OK && cfg->deterministic)
+    s = hip_check(hipMemset(x->at(L.dpart), 0, sizeof(double) * ddm::kDetVals * (size_t)std::max(L.nblk, L.total_tiles)),
+                  "clear deterministic partials");
   if (s != DDM_OK) { delete x; return s; }
   *out = x;
   return DDM_OK;
@@ -904,6 +944,9 @@ ddm_status ddm_rollout(ddm_ctx* x, int32_t n_steps) {
     if (i % K == 0) {
       DDM_HIP(hipMemcpyAsync(x->at(x->L.ckpt + (size_t)(i / K) * x->L.state_bytes), x->cur(), x->L.state_bytes,
                              hipMemcpyDeviceToDevice, x->stream));
+      if (x->kc.det)
+        DDM_HIP(hipMemcpyAsync(x->ckpt_pid(i / K), x->pid(), sizeof(uint32_t) * L.ntot, hipMemcpyDeviceToDevice,
+                               x->stream));
       x->need_sort = true;
     }
     if (sort_due(x, k0 + i)) {
@@ -929,10 +972,13 @@ ddm_status ddm_rollout(ddm_ctx* x, int32_t n_steps) {
     // the checkpoint, for a reverse pass that has to replay the segment after all
     DDM_HIP(hipMemcpyAsync(x->at(L.ckpt + (size_t)seg * L.state_bytes), src, L.state_bytes, hipMemcpyDeviceToDevice,
                            x->stream));
+    if (x->kc.det)
+      DDM_HIP(hipMemcpyAsync(x->ckpt_pid(seg), x->pid(), sizeof(uint32_t) * L.ntot, hipMemcpyDeviceToDevice, x->stream));
     // the forward's binning decisions: the first step of a segment, then every
-    // sort_every steps
+    // sort_every steps (every step in the deterministic mode)
     const int R = x->cfg.sort_every;
-    for (int j = 0; j < len; ++j) x->rec_sorted[(size_t)(s0 + j)] = j == 0 || (R > 0 && (k0 + s0 + j) % R == 0);
+    for (int j = 0; j < len; ++j)
+      x->rec_sorted[(size_t)(s0 + j)] = j == 0 || x->kc.det || (R > 0 && (k0 + s0 + j) % R == 0);
     Phase record("recorded segment");
     const ddm_status s = run_segment(x, m, k0 + s0, len, src, &x->rec_sorted[(size_t)s0], true, x->rec_tl_of[(size_t)m]);
     if (s != DDM_OK) return s;
@@ -1054,7 +1100,8 @@ ddm_status ddm_backward(ddm_ctx* x, const double* dloss_dev, double* grad_dev) {
     } else {
       Phase replay("replay segment");
       const ddm_status s = run_segment(x, 0, k0 + s0, len, x->at(L.ckpt + (size_t)seg * L.state_bytes),
-                                       &x->rec_sorted[(size_t)s0], false, tl_of);
+                                       &x->rec_sorted[(size_t)s0], false, tl_of,
+                                       x->kc.det ? x->ckpt_pid(seg) : nullptr);
       if (s != DDM_OK) return s;
     }
     auto slot = [&](int j) { return x->slot(m, j); };
@@ -1078,7 +1125,16 @@ ddm_status ddm_backward(ddm_ctx* x, const double* dloss_dev, double* grad_dev) {
         if (x->kc.pcontact)
           ddm::launch_pcontact_adj(x->prec, x->kc, b, (int)L.nblk, (int)k, slot(j), gpost(j), adj[cur],
                                    x->at<double>(L.pose_bar), st);
-        ddm::launch_g2p_adj(x->prec, x->kc, b, tl, tile_workgroups(x), slot(j), gpost(j), adj[cur], adj[1 - cur], x->at(L.gvb), st);
+        // one workgroup per tile: a persistent G2P adjoint ran slower (548 against 505 us per launch on the
+        // 64-instance batch)
+        ddm::launch_g2p_adj(x->prec, x->kc, b, tl, (int)L.nwg, slot(j), gpost(j), adj[cur], adj[1 - cur],
+                            x->at(L.gvb), x->kc.det ? x->at(L.staging) : nullptr, st);
+        if (x->kc.det) {
+          // the staged windows, summed node by node in a fixed order
+          ddm::launch_tile_slots(x->kc, tl, L.total_tiles, x->at<uint32_t>(L.tslot), st);
+          ddm::launch_adj_windows(x->prec, x->kc, b, x->seg_alist(m, j), x->seg_acount(m, j), x->at(L.staging),
+                                  x->at<const uint32_t>(L.tslot), x->at(L.gvb), st);
+        }
       }
       if (treat) {
         Timed t(x, 9);
@@ -1149,6 +1205,8 @@ ddm_status ddm_set_grad_treatment(ddm_ctx* x, int32_t mode, double clip, double 
   if (!(delta >= 0) || !std::isfinite(delta)) return fail(DDM_EINVAL, "delta must be finite and >= 0");
   if (stats_steps < 0 || (stats_steps > 0) != (stats_dev != nullptr))
     return fail(DDM_EINVAL, "stats_dev and stats_steps > 0 go together");
+  if (mode == DDM_TREAT_NORM && x->cfg.deterministic)
+    return fail(DDM_EINVAL, "normalisation reduces its 2-norm with atomics: not available in the deterministic mode");
   static_assert(DDM_TREAT_CLIP == ddm::kTreatClip && DDM_TREAT_SCALE == ddm::kTreatScale &&
                     DDM_TREAT_NORM == ddm::kTreatNorm, "treatment codes");
   x->treat = ddm::Treat{mode, clip, oom, delta};
@@ -1273,6 +1331,7 @@ ddm_status ddm_autotune(ddm_ctx* x, const char* cache_path, int32_t* sort_every_
     float best_ms = 0.f;
     for (int rep = 0; rep < 2 && st == DDM_OK; ++rep) {          // the first round warms up
       for (int R : cand_r) {
+        if (x->cfg.deterministic && R != cand_r[0]) continue;   // binned every sub-step: R has no effect
         float ms = 0.f;
         st = probe(R, 0, &ms);
         if (st == DDM_OK && rep == 1 && (best < 0 || ms < best_ms)) { best = R; best_ms = ms; }

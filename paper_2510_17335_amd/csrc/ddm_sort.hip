@@ -35,9 +35,10 @@ __device__ __forceinline__ bool cell_f64(double xr, const KCfg& c, int& base) {
 
 template <int PREC>
 __global__ void k_keys(KCfg c, const int* blk_inst, const InstDev* inst, const void* state, uint32_t* keys,
-                       uint32_t* vals, DevErr* err) {
-  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const int i = blk_inst[blockIdx.x];
+                       uint32_t* vals, DevErr* err, const uint32_t* order) {
+  const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t p = order ? (int64_t)order[j] : j;
+  const int i = blk_inst[p / kBlock];
   const InstDev& I = inst[i];
   const uint32_t cells = (uint32_t)c.nodes;
   uint32_t key = (uint32_t)i * (cells + 1u) + cells;
@@ -56,14 +57,29 @@ __global__ void k_keys(KCfg c, const int* blk_inst, const InstDev* inst, const v
     const uint32_t tcells = c.dim == 3 ? kTile * kTile * kTile : kTile * kTile;
     key = (uint32_t)i * (cells + 1u) + t * tcells + cl;
   }
-  keys[p] = key;
-  vals[p] = (uint32_t)p;
+  keys[j] = key;
+  vals[j] = (uint32_t)p;
 }
 
 void launch_keys(int prec, const KCfg& c, const Bufs& b, int nblk, const void* state, uint32_t* keys, uint32_t* vals,
-                 hipStream_t s) {
-  if (prec == 0) hipLaunchKernelGGL(k_keys<0>, dim3(nblk), dim3(kBlock), 0, s, c, b.blk_inst, b.inst, state, keys, vals, b.err);
-  else hipLaunchKernelGGL(k_keys<1>, dim3(nblk), dim3(kBlock), 0, s, c, b.blk_inst, b.inst, state, keys, vals, b.err);
+                 hipStream_t s, const uint32_t* order) {
+  if (prec == 0) hipLaunchKernelGGL(k_keys<0>, dim3(nblk), dim3(kBlock), 0, s, c, b.blk_inst, b.inst, state, keys, vals, b.err, order);
+  else hipLaunchKernelGGL(k_keys<1>, dim3(nblk), dim3(kBlock), 0, s, c, b.blk_inst, b.inst, state, keys, vals, b.err, order);
+}
+
+// Keys of the deterministic mode's first sort: the particle id (padding slots
+// last), so that a stable sort by cell afterwards orders a cell's particles by id.
+__global__ void k_pid_keys(const uint32_t* pid, uint32_t* keys, uint32_t* vals, int64_t ntot) {
+  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (p >= ntot) return;
+  const uint32_t id = pid[p];
+  keys[p] = id == 0xFFFFFFFFu ? (uint32_t)ntot : id;
+  vals[p] = (uint32_t)p;
+}
+
+void launch_pid_keys(const uint32_t* pid, uint32_t* keys, uint32_t* vals, int64_t ntot, hipStream_t s) {
+  hipLaunchKernelGGL(k_pid_keys, dim3((unsigned)((ntot + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, pid, keys, vals,
+                     ntot);
 }
 
 // ---------------------------------------------------------------------------
@@ -309,6 +325,20 @@ __global__ void k_tile_list(int64_t total_tiles, const uint32_t* tstart, const u
   const uint32_t idx = atomicAdd(count, 1u);
   list[idx] = TileRec{tstart[t], e, (uint32_t)t};
   tslot[t] = idx;
+}
+
+__global__ void k_tile_slots(TileList tl, int64_t max_records, uint32_t* tslot) {
+  const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (r >= max_records || r >= (int64_t)*tl.count) return;
+  tslot[tl.list[r].tile] = (uint32_t)r;
+}
+
+void launch_tile_slots(const KCfg& c, const TileList& tl, int64_t max_records, uint32_t* tslot, hipStream_t s) {
+  const int tshift = c.dim == 3 ? 6 : 4;
+  const int64_t total_tiles = (c.nodes >> tshift) * c.n_inst;
+  launch_fill_u32(tslot, total_tiles, kNoSlot, s);
+  hipLaunchKernelGGL(k_tile_slots, dim3((unsigned)((max_records + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, tl,
+                     max_records, tslot);
 }
 
 void launch_tile_list(const KCfg& c, const uint32_t* sorted_keys, uint32_t* tstart, uint32_t* tend, TileRec* list,

@@ -121,6 +121,25 @@ def test_grid_record_capacity_shrinks_the_workspace(lib):
     assert "grid_record_blocks" in ddm.validate_config(cfg, [inst])
 
 
+def test_deterministic_mode_workspace_and_validation(lib):
+    """The deterministic mode adds 8 FP64 partial sums per particle block or
+    grid block (whichever is more), the particle ids at every checkpoint and a
+    pair of id arrays for the replays; values other than 0 and 1 are
+    rejected."""
+    cfg, inst = _good()
+    base = ddm.workspace_query(cfg, [inst]).workspace_bytes
+    cfg.deterministic = 1
+    assert ddm.validate_config(cfg, [inst]) == ""
+    det = ddm.workspace_query(cfg, [inst]).workspace_bytes
+    ntot = -(-inst.n_particles // 256) * 256
+    blocks = max(ntot // 256, (cfg.n_grid // 4) ** cfg.dim)
+    n_ckpt = -(-cfg.max_steps // cfg.checkpoint_every) + 1
+    extra = 8 * 8 * blocks + 4 * ntot * (n_ckpt + 2)
+    assert abs((det - base) - extra) <= 4 * 256, (det - base, extra)
+    cfg.deterministic = 2
+    assert "deterministic" in ddm.validate_config(cfg, [inst])
+
+
 def test_workspace_query_rejects_bad(lib):
     cfg, inst = _good()
     inst.nu = 0.7

@@ -583,10 +583,10 @@ def test_autotune_restores_state_and_caches(ddm, orc, tmp_path):
 
 @pytest.mark.parametrize("workgroups", [3, 8, 1024])
 def test_persistent_tile_launch_matches_oracle(ddm, orc, workgroups):
-    """The tile kernels (P2G, G2P adjoint) as a persistent launch of a fixed
-    number of workgroups that draw tiles from a work queue (fewer than, and
-    more than, the occupied tiles): state, loss and gradient against the
-    oracle (FP64), as with one workgroup per tile."""
+    """P2G as a persistent launch of a fixed number of workgroups that draw
+    tiles from a work queue (fewer than, and more than, the occupied tiles):
+    state, loss and gradient against the oracle (FP64), as with one workgroup
+    per tile."""
     w = W.tiny(3, shovel=True, steps=40)
     tgt = W.target_heightmap(w)
     cfg, inst = ddm.from_workload(w, max_steps=40, checkpoint_every=16)
