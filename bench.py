@@ -581,7 +581,13 @@ def main():
                 "rel_err_per_param": dict(zip(ddm.PARAM_NAMES, per_param[int(np.argmax(rels))]))}
         print(f"# gradient gate ({args.precision} vs FP64): {gate}", flush=True)
 
-    cpu = None if args.no_cpu else cpu_baseline(ws)
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(ws)
+        # the oracle's plain FP64 forward as well (no tangents), a shorter sample
+        fwd = cpu_baseline(ws, grad=False, target_s=5.0)
+        cpu["forward_value"] = fwd["value"]
+        cpu["forward_sample"] = fwd["sample"]
     # the whole pass against the HBM roofline of its algorithmic bytes
     pass_bytes = algorithmic_bytes_pass(n_part, n_act, b=esz)
     pass_bound = HBM_PEAK_GBS * 1e9 / pass_bytes
