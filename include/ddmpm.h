@@ -141,9 +141,10 @@ typedef struct ddm_config {
                                the grid adjoint's input sums them in a fixed order, and every
                                reduction over particles or grid blocks sums per-workgroup partials
                                in index order (no floating-point atomics).  Slower (about 4x the
-                               pass time), for debugging and reproducibility; ddm_diagnostics sums
-                               stay unordered, and the normalisation treatment (whose 2-norm is
-                               reduced with atomics) is rejected.  0: the fast unordered sums */
+                               pass time), for debugging and reproducibility; the sums of
+                               ddm_diagnostics and the 2-norms of the adjoint-growth record stay
+                               unordered, and the normalisation treatment (whose 2-norm is reduced
+                               with atomics) is rejected.  0: the fast unordered sums */
 } ddm_config;
 
 /* One simulation instance: material, skill and time step. */
