@@ -351,6 +351,48 @@ def test_sort_interval_does_not_change_results(ddm, orc, sort_every):
     assert np.all(rel < 1e-6), rel
 
 
+def test_ragged_instances_f64(ddm, orc):
+    """One batch of instances holding 1, 257 and 480 particles of the same
+    3D bed with the shovel (the first alone in its 256-slot block, the second
+    one slot into a second block, the third filling two blocks short of 32):
+    each instance's final state, loss and gradient equal the oracle's run of
+    the same particles, so padding slots and ragged blocks add nothing."""
+    from dataclasses import replace
+    w = replace(W.tiny(3, shovel=True, steps=24), bed_lo=(5, 3, 5), bed_hi=(11, 5, 10))
+    x0 = W.bed_positions(w)
+    tg = W.target_heightmap(w)
+    counts = [1, 257, x0.shape[0]]
+    cfg, inst = ddm.from_workload(w, max_steps=24, checkpoint_every=8)
+    insts = []
+    for n in counts:
+        q = ddm.DdmInstance.from_buffer_copy(inst)
+        q.n_particles = n
+        insts.append(q)
+    _log(f"case ragged instances {counts}")
+    sim = ddm.Simulator(cfg, insts)
+    sim.init_state(np.concatenate([x0[:n] for n in counts]))
+    sim.rollout(24)
+    loss = sim.loss(np.stack([tg] * len(counts))).cpu().numpy()
+    grad = sim.backward().cpu().numpy()
+    err = sim.check()
+    assert err.flags == 0 and err.clamp_count == 0, err.flags
+    ocfg = orc.config(w)
+    for i, n in enumerate(counts):
+        r = orc.rollout(ocfg, w.params, orc.initial_state(x0[:n]), 24, target=tg, grad=True)
+        got = sim.packed_state(i)
+        e = field_errors(got, r["state"], 3)
+        # a field that is zero in the oracle (none is expected) is judged absolutely
+        e = {k: (v if np.isfinite(v) and v < 1e200 else float(np.abs(got - r["state"]).max())) for k, v in e.items()}
+        g = grad[i]
+        scale = np.abs(r["grad"]).max()
+        rel = np.abs(g - r["grad"]) / np.maximum(np.abs(r["grad"]), 1e-9 * scale)
+        _log(f"instance of {n} particles: state {e}, loss {loss[i]!r} vs {r['loss']!r}, grad rel {rel.max():.2e}")
+        for k, v in e.items():
+            assert v < 1e-9, (n, k, v)
+        assert abs(loss[i] - r["loss"]) <= 1e-10 * abs(r["loss"])
+        assert np.all(rel < 1e-6), (n, rel)
+
+
 def test_domain_error_is_reported(ddm):
     w = W.tiny(3)
     x0 = W.bed_positions(w)
