@@ -203,11 +203,13 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "p2g_sysid64_traffic.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_2510_17335_amd", "csrc", "ddm_kernels.hip")
 
 
-def measured_traffic():
+def measured_traffic(forward=False):
     """HBM bytes per P2G launch from the committed counter summary (FETCH_SIZE and
     WRITE_SIZE per dispatch, each scaled by what the same counter reads for a
-    plain copy of known size).  None when the summary is absent or the kernel
-    source has changed since the counters were taken."""
+    plain copy of known size): of a launch of the recorded pass (which also
+    keeps the stress for the reverse pass), or of a forward-only launch.  None
+    when the summary is absent or the kernel source has changed since the
+    counters were taken."""
     import hashlib
     if not os.path.exists(TRAFFIC_FILE):
         return None
@@ -223,9 +225,20 @@ def measured_traffic():
         copy_bytes = float(rec["copy_bytes"])
         f_fac = copy_bytes / (float(rec["copy_fetch_kib"]) * 1024)
         w_fac = copy_bytes / (float(rec["copy_write_kib"]) * 1024)
-        return (float(rec["p2g_fetch_kib"]) * f_fac + float(rec["p2g_write_kib"]) * w_fac) * 1024
+        pre = "p2g_forward_" if forward else "p2g_"
+        return (float(rec[pre + "fetch_kib"]) * f_fac + float(rec[pre + "write_kib"]) * w_fac) * 1024
     except (KeyError, ValueError):
         return None
+
+
+def fwd_traffic_applies(args):
+    """The forward-only counters were taken on the 64-instance FP32 batch."""
+    return args.workload == "sysid64_fwd" and args.precision == "f32"
+
+
+def pass_traffic_applies(args):
+    """The pass counters were taken on the 64-instance FP32 batch, untreated."""
+    return args.workload == "sysid64" and args.precision == "f32" and args.treat == "none"
 
 
 def copy_calibration(torch):
@@ -419,7 +432,8 @@ def forward_bench(args, torch, ddm):
         "kernel_ms": {k: {"ms": round(v[0], 3), "launches": v[1]} for k, v in breakdown.items() if v[1]},
         "kernel_ms_from": "last warm-up run, every launch group timed" if args.warmup else "timed region",
         "roofline": {"bound": "hbm", "kernel": "p2g", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
+                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
+                     "traffic": measured_traffic(forward=True) if fwd_traffic_applies(args) else None,
                      "algorithmic_bytes": per_launch},
         "pass_roofline": {"bytes_per_particle_step": fwd_bytes, "bound_value": bound, "unit": "particle-steps/s",
                           "frac": value / bound},
@@ -618,7 +632,8 @@ def main():
         "kernel_ms": breakdown,
         "kernel_ms_from": "last warm-up pass, every launch group timed" if args.warmup else "timed region",
         "roofline": {"bound": "hbm", "kernel": "p2g", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": measured_traffic(),
+                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
+                     "traffic": measured_traffic() if pass_traffic_applies(args) else None,
                      "algorithmic_bytes": per_launch_bytes,
                      "dominant_group": dom},
         "pass_roofline": {"bytes_per_particle_step": pass_bytes, "bound_value": pass_bound, "unit": "particle-steps/s",
