@@ -405,6 +405,114 @@ __device__ __forceinline__ void constit_outputs(const Constit<T, D>& c, T Gn[3][
     }
 }
 
+// The forward constitutive update alone (P2G), without the polar factors.
+// Since eps' and eps share the eigenvectors V of F^T F,
+//   F' = U diag(s') V^T = F V diag(exp(eps' - eps)) V^T,
+// so G' = G + M + G M with M = V diag(expm1(d)) V^T, d = eps' - eps taken per
+// case without cancellation (0 inside the cone, apex - eps in tension,
+// -(dgam/|dev|) dev on projection): an elastic step leaves G' = G exactly.
+// With U = F' V diag(1/s'), tau = U diag(h) U^T = F' N F'^T, N = V diag(h / s'^2) V^T,
+// s'^2 = (1 + lambda'_i)(1 + expm1(d_i))^2.  The result equals
+// constit_forward + constit_outputs up to rounding (clamped singular values
+// aside, which are flagged).  Returns the number of clamps.
+template <typename T, int D>
+__device__ __forceinline__ int constit_step(const T G[3][3], T mu, T lam, T alpha, T kc, T Gn[3][3], T tau[3][3]) {
+  T a[3][3], V[3][3], ev[3];
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      T acc = G[i][j] + G[j][i];
+#pragma unroll
+      for (int k = 0; k < D; ++k) acc += G[k][i] * G[k][j];
+      a[i][j] = acc;
+    }
+  jacobi_sym<T, D>(a, V, ev);
+  T detF;
+  if (D == 2) {
+    detF = (T(1) + G[0][0]) * (T(1) + G[1][1]) - G[0][1] * G[1][0];
+  } else {
+    const T f00 = T(1) + G[0][0], f11 = T(1) + G[1][1], f22 = T(1) + G[2][2];
+    detF = f00 * (f11 * f22 - G[1][2] * G[2][1]) - G[0][1] * (G[1][0] * f22 - G[1][2] * G[2][0]) +
+           G[0][2] * (G[1][0] * G[2][1] - f11 * G[2][0]);
+  }
+  int nclamp = detF > T(0) ? 0 : 1;
+  const T smin = sigma_min<T>();
+  T eps[3], s2[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    if (i >= D) { eps[i] = T(0); s2[i] = T(1); continue; }
+    const T l = ev[i];                       // s^2 - 1
+    if (!(T(1) + l > smin * smin)) {
+      eps[i] = log(smin); s2[i] = smin * smin; ++nclamp;
+    } else {
+      eps[i] = T(0.5) * flog1p(l); s2[i] = T(1) + l;
+    }
+  }
+  DP<T> dp;
+  dp_forward<T, D>(eps, mu, lam, alpha, kc, dp);
+  T e[3] = {T(0), T(0), T(0)}, cn[3] = {T(0), T(0), T(0)};
+  const T mean = dp.tr * T(1.0 / D);
+  const T f = dp.cs == 3 ? (dp.nrm + dp.beta) * frcp(dp.nrm) : T(0);
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    const T d = dp.cs == 2 ? T(0) : (dp.cs == 1 ? dp.apex - eps[i] : -f * (eps[i] - mean));
+    e[i] = fexpm1(d);
+    const T g = T(1) + e[i];
+    cn[i] = dp.h[i] * frcp(s2[i] * g * g);
+  }
+  // M and N share the products V_ik V_jk; both are symmetric
+  T M[3][3], N[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) { M[i][j] = T(0); N[i][j] = T(0); }
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = i; j < D; ++j) {
+      T m = T(0), n = T(0);
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        const T vv = V[i][k] * V[j][k];
+        m += vv * e[k];
+        n += vv * cn[k];
+      }
+      M[i][j] = M[j][i] = m;
+      N[i][j] = N[j][i] = n;
+    }
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      T acc = G[i][j] + M[i][j];
+#pragma unroll
+      for (int k = 0; k < D; ++k) acc += G[i][k] * M[k][j];
+      Gn[i][j] = acc;
+    }
+  // tau = F' N F'^T with F' = I + G': P = N + G' N, tau = P + P G'^T
+  T P[3][3];
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      T acc = N[i][j];
+#pragma unroll
+      for (int k = 0; k < D; ++k) acc += Gn[i][k] * N[k][j];
+      P[i][j] = acc;
+    }
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = i; j < D; ++j) {
+      T acc = P[i][j];
+#pragma unroll
+      for (int k = 0; k < D; ++k) acc += P[i][k] * Gn[j][k];
+      tau[i][j] = tau[j][i] = acc;
+    }
+  return nclamp;
+}
+
 // Adjoint of (F_tmp -> F', tau) for adjoints Fnb (of F', equally of G') and
 // taub (of tau); the result is the adjoint of F_tmp (equally of G_tmp).
 // In the SVD frame, with sym/skw the symmetric/skew parts of dF~ = U^T dF V,

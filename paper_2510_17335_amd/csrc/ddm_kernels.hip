@@ -307,11 +307,9 @@ __device__ __forceinline__ bool p2g_particle(const KCfg& c, const Bufs& b, const
       for (int k = 0; k < D; ++k) acc += Cm[a][k] * Gm[k][bb];
       Ft[a][bb] = Gm[a][bb] + dt * acc;
     }
-  Constit<T, D> cs;
-  constit_forward<T, D>(Ft, T(I.mu), T(I.lam), T(I.alpha), T(I.kc), cs);
-  if (cs.nclamp) { flag_error(b.err, 4u, inst); atomicAdd(&b.err->clamps, (unsigned long long)cs.nclamp); }
   T Fn[3][3], tau[3][3];
-  constit_outputs<T, D>(cs, Fn, tau);
+  const int nclamp = constit_step<T, D>(Ft, T(I.mu), T(I.lam), T(I.alpha), T(I.kc), Fn, tau);
+  if (nclamp) { flag_error(b.err, 4u, inst); atomicAdd(&b.err->clamps, (unsigned long long)nclamp); }
 #pragma unroll
   for (int a = 0; a < D; ++a)
 #pragma unroll
