@@ -213,9 +213,11 @@ void launch_unpermute(int elem_bytes, const void* in, void* out, const uint32_t*
                       hipStream_t s);
 // tslot of a recorded tile list: tslot[list[r].tile] = r, kNoSlot elsewhere.
 void launch_tile_slots(const KCfg& c, const TileList& tl, int64_t max_records, uint32_t* tslot, hipStream_t s);
-// One record per occupied tile, and tslot (record of each tile, or kNoSlot).
+// One record per occupied tile, largest particle count first (bucket: 2
+// kTileBuckets words of scratch), and tslot (record of each tile, or kNoSlot).
+constexpr int kTileBuckets = 16;
 void launch_tile_list(const KCfg& c, const uint32_t* sorted_keys, uint32_t* tstart, uint32_t* tend, TileRec* list,
-                      uint32_t* count, uint32_t* tslot, hipStream_t s);
+                      uint32_t* count, uint32_t* tslot, uint32_t* bucket, hipStream_t s);
 
 // Earth mover's distance of the surface observation to a target point cloud
 // (ddm_emd.hip); arrays are [n_inst][hm_res^2] (points [..][3]).

@@ -63,7 +63,7 @@ struct Layout {
   size_t adj0 = 0, adj1 = 0, gvb = 0, gb = 0, pacc = 0, pose_bar = 0;
   size_t hm_bits = 0, owner = 0, target = 0, hm_val = 0, dldh = 0, region = 0, dldm = 0, loss = 0;
   size_t keys0 = 0, keys1 = 0, vals0 = 0, vals1 = 0, hist = 0, sums = 0, tstart = 0, tend = 0, tiles = 0, tcount = 0;
-  size_t tslot = 0, staging = 0, gout = 0, amask = 0, alist = 0, acount = 0, seg_alist = 0, seg_acount = 0;
+  size_t tslot = 0, tbucket = 0, staging = 0, gout = 0, amask = 0, alist = 0, acount = 0, seg_alist = 0, seg_acount = 0;
   size_t treat_acc = 0, tqueue = 0, dpart = 0, ckpt_pid = 0, rpid0 = 0, rpid1 = 0;
   size_t emd_top = 0, emd_own = 0, emd_target = 0, emd_obs = 0, emd_slot = 0, emd_nobs = 0, emd_assign = 0,
          emd_val = 0;
@@ -179,6 +179,7 @@ Layout make_layout(const ddm_config& c, int n_inst, const ddm_instance* in) {
   L.tiles = cv.take(sizeof(ddm::TileRec) * L.max_chunks);
   L.tcount = cv.take(sizeof(uint32_t));
   L.tslot = cv.take(sizeof(uint32_t) * L.total_tiles);
+  L.tbucket = cv.take(sizeof(uint32_t) * 2 * ddm::kTileBuckets);
   L.staging = cv.take(L.win_bytes * L.total_tiles);
   L.gout = cv.take(L.grid_bytes);
   L.amask = cv.take(sizeof(uint32_t) * L.total_tiles);
@@ -580,7 +581,7 @@ ddm_status bin_state(ddm_ctx* x, const void* src, void* dst, const uint32_t* pid
   }
   ddm::launch_gather(L.esz, src, dst, vals[r], L.rows, L.ntot, pid_src, pid_dst, st);
   ddm::launch_tile_list(x->kc, keys[r], x->at<uint32_t>(L.tstart), x->at<uint32_t>(L.tend), x->at<ddm::TileRec>(L.tiles),
-                        x->at<uint32_t>(L.tcount), x->at<uint32_t>(L.tslot), st);
+                        x->at<uint32_t>(L.tcount), x->at<uint32_t>(L.tslot), x->at<uint32_t>(L.tbucket), st);
   ddm::launch_active_set(x->kc, x->tiles(), x->active(), st);
   if (perm_out) DDM_HIP(hipMemcpyAsync(perm_out, vals[r], sizeof(uint32_t) * L.ntot, hipMemcpyDeviceToDevice, st));
   if (tiles_out) {
