@@ -58,6 +58,9 @@ def parse():
     ap.add_argument("--sort-every", type=int, default=0,
                     help="binning interval; 0 = autotune the batched context (the plain loop uses the same)")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--streams", type=int, default=2,
+                    help="contexts run at once for the headline pass (StreamGroup: the instances in groups of "
+                         "balanced particle count, one stream each, graph-replayed); 1 = the single context")
     ap.add_argument("--treat", default="none", choices=["none", "clip", "scale", "norm", "record"],
                     help="gradient treatment inside the reverse pass (Sec. III-E) at the paper's thresholds; "
                          "'record' keeps the per-sub-step adjoint statistics without treating")
@@ -306,6 +309,76 @@ def cpu_baseline(ws, grad=True, target_s=15.0):
             "sample": f"smallest instance ({w.n_particles} particles), {reps} x {steps} sub-steps from its initial "
                       f"state, {kind}, {dt:.1f} s, pinned to core {core}",
             "host_cpu": model, "host_nproc": ncpu, "host_cpus_available": navail}
+
+
+def stream_group_bench(args, torch, ddm, ws, R, TW, spare=16 << 30):
+    """The batch as args.streams contexts at once (ddm.StreamGroup), each
+    group's passes graph-replayed on its own stream: per group, a grid record
+    of 1.5x its most active blocks (its own forward run) and the most segment
+    sets that fit for all groups together with `spare` bytes left.  Returns
+    (particle-steps/s, ms per pass, a config record, the gradients in the
+    original instance order)."""
+    S = args.streams
+    groups = ddm.balanced_groups([w.n_particles for w in ws], S)
+    caps = []
+    for g in groups:
+        cap_g, _, _, _ = grid_record_capacity(ddm, torch, [ws[i] for i in g], R, args.precision)
+        caps.append(cap_g)
+    free = torch.cuda.mem_get_info()[0]
+    K = ws[0].checkpoint_every or 50
+    M = 1
+    for m in range(1, (ws[0].steps + K - 1) // K + 1):
+        need = 0
+        for g, cap_g in zip(groups, caps):
+            cfg_g, insts_g = configs(ddm, [ws[i] for i in g], R, args.precision, record_segments=m,
+                                     grid_record_blocks=cap_g)
+            need += ddm.workspace_query(cfg_g, insts_g).workspace_bytes
+        if need + spare <= free:
+            M = m
+    cfg, insts = configs(ddm, ws, R, args.precision)
+    cfg.tile_workgroups = TW
+    sg = ddm.StreamGroup(cfg, insts, groups, record_segments=[M] * len(groups), grid_record_blocks=caps)
+    dev = torch.device("cuda:0")
+    x0 = torch.as_tensor(np.concatenate([W.bed_positions(w) for w in ws]), device=dev)
+    tg = torch.as_tensor(np.stack([W.target_heightmap(w) for w in ws]), device=dev)
+    steps = ws[0].steps
+    sg.set_inputs(x0, tg)
+    for _ in range(2):                        # capture, then one replay
+        sg.run(steps)
+    torch.cuda.synchronize()
+    err = sg.check()
+    if err.flags:
+        raise RuntimeError(f"stream group: device flags {err.flags}")
+    # every step joins the groups: its inputs wait for the previous step's
+    # results, as an optimiser step that reads every gradient would
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        loss, grad = sg.full_pass(x0, steps, tg)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    err = sg.check()
+    work = sum(w.n_particles for w in ws) * steps
+    value = work * args.steps / elapsed
+    ms = 1e3 * elapsed / args.steps
+    # the same passes with no join between steps: each group queues behind
+    # its own previous pass only (independent instances)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        sg.run(steps)
+    sg.results()
+    torch.cuda.synchronize()
+    pipelined = work * args.steps / (time.perf_counter() - t0)
+    err2 = sg.check()
+    rec = {"contexts": len(groups), "particles": [sum(ws[i].n_particles for i in g) for g in groups],
+           "record_segments": M, "grid_record_blocks": caps, "ms_per_step": ms,
+           "unjoined_value": pipelined, "device_flags": int(err.flags | err2.flags)}
+    print(f"# {len(groups)} contexts at once (graph-replayed): {ms:.1f} ms/step, {value:.3e} particle-steps/s, "
+          f"{M} segment sets each, grid records {caps}; without a join between steps {pipelined:.3e}", flush=True)
+    grads = grad.cpu().numpy()
+    del sg
+    return value, ms, rec, grads
 
 
 def treatment_kwargs(args, steps):
@@ -561,6 +634,14 @@ def main():
     del bp
     torch.cuda.empty_cache()
 
+    # the headline: the same batch as args.streams contexts at once
+    streams_value, streams_ms, streams_cfg = None, None, None
+    if args.streams > 1 and len(ws) >= args.streams and args.treat == "none":
+        streams_value, streams_ms, streams_cfg, grads_s = stream_group_bench(args, torch, ddm, ws, R, TW)
+        rel = np.abs(grads_s - grads32) / np.maximum(np.abs(grads32), 1e-6 * np.abs(grads32).max())
+        streams_cfg["grad_rel_diff_vs_single_context"] = float(rel.max())
+        torch.cuda.empty_cache()
+
     plain_value = None
     if not args.no_plain:
         t_plain = 0.0
@@ -605,6 +686,9 @@ def main():
     # the whole pass against the HBM roofline of its algorithmic bytes
     pass_bytes = algorithmic_bytes_pass(n_part, n_act, b=esz)
     pass_bound = HBM_PEAK_GBS * 1e9 / pass_bytes
+    single_value, single_ms = value, ms_per_step
+    if streams_value:
+        value, ms_per_step = streams_value, streams_ms
     out = {
         "metric": METRIC,
         "value": value,
@@ -625,7 +709,12 @@ def main():
                    "record_segments": rseg, "grid_record_blocks": cap, "active_blocks_max_sampled": most,
                    "grad_treatment": args.treat,
                    "peak_mem_gb": round(peak_gb, 2)},
+        "headline": (f"{args.streams} contexts at once, graph-replayed passes" if streams_value
+                     else "one context, eager launches"),
+        "single_context_value": single_value,
+        "single_context_ms_per_step": single_ms,
         "graph_value": graph_value,
+        "streams": streams_cfg,
         "plain_value": plain_value,
         "batched_over_plain": (value / plain_value) if plain_value else None,
         "grad_gate": gate,

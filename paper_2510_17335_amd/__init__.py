@@ -580,6 +580,122 @@ class Simulator:
 
 
 # ---------------------------------------------------------------------------
+# a batch on several streams
+# ---------------------------------------------------------------------------
+
+def balanced_groups(counts: Sequence[int], n_groups: int):
+    """Instance indices in n_groups groups of near-equal particle count: the
+    instances by decreasing count dealt out in snake order (0, 1, .., n-1,
+    n-1, .., 0, ...); each group keeps its instances in their original order."""
+    order = sorted(range(len(counts)), key=lambda i: -int(counts[i]))
+    groups = [[] for _ in range(n_groups)]
+    for k, i in enumerate(order):
+        r = k % (2 * n_groups)
+        groups[r if r < n_groups else 2 * n_groups - 1 - r].append(i)
+    return [sorted(g) for g in groups if g]
+
+
+class StreamGroup:
+    """A batch run as several contexts at once: the instances split into
+    groups (balanced_groups), one Simulator per group on a stream of its own.
+    A pass issues every group's ddm_pass (graph-replayed by default) without
+    waits between the streams, so one group's kernels fill the slots that
+    another's leave idle (launch tails, the short grid kernels, binning).  The
+    results are those of the groups' own contexts, returned in the original
+    instance order; every kernel is the library's, and this class only splits
+    the inputs and gathers the outputs."""
+
+    def __init__(self, cfg: DdmConfig, instances: Sequence[DdmInstance], groups, record_segments=None,
+                 grid_record_blocks=None, device="cuda"):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.instances = list(instances)
+        self.n_inst = len(self.instances)
+        self.groups = [list(g) for g in groups]
+        assert sorted(i for g in self.groups for i in g) == list(range(self.n_inst)), "groups must partition"
+        self.sims = []
+        for k, g in enumerate(self.groups):
+            c = DdmConfig.from_buffer_copy(cfg)
+            if record_segments is not None:
+                c.record_segments = int(record_segments[k])
+            if grid_record_blocks is not None:
+                c.grid_record_blocks = int(grid_record_blocks[k])
+            self.sims.append(Simulator(c, [self.instances[i] for i in g], device=device,
+                                       stream=torch.cuda.Stream(self.device)))
+        counts = [int(s.n_particles) for s in self.instances]
+        starts = np.concatenate([[0], np.cumsum(counts)])
+        # rows of the concatenated positions of each group, in the group's order
+        self._rows = [torch.as_tensor(np.concatenate([np.arange(starts[i], starts[i + 1]) for i in g]),
+                                      device=self.device) for g in self.groups]
+        self._inst = [torch.as_tensor(g, device=self.device) for g in self.groups]
+        self.npix = self.sims[0].npix
+        self.dim = self.sims[0].dim
+        self.dtype = self.sims[0].dtype
+
+    def set_inputs(self, x0, target, dloss=None):
+        """Splits the batch's inputs into the groups' buffers: x0 [sum N_i,
+        dim], target [n_inst, npix] and dloss [n_inst] (ones when None) in
+        the original instance order, host or device; each group's stream
+        waits for the current stream before it reads them."""
+        t = self.torch
+        cur = t.cuda.current_stream(self.device)
+        x0 = t.as_tensor(x0, device=self.device).reshape(-1, self.dim).to(self.dtype)
+        tg = t.as_tensor(target, device=self.device, dtype=t.float64).reshape(self.n_inst, self.npix)
+        dl = (t.ones(self.n_inst, dtype=t.float64, device=self.device) if dloss is None
+              else t.as_tensor(dloss, device=self.device, dtype=t.float64).reshape(-1))
+        self._in = []
+        for sim, rows, idx in zip(self.sims, self._rows, self._inst):
+            sim.stream.wait_stream(cur)
+            with t.cuda.stream(sim.stream):
+                self._in.append((x0.index_select(0, rows), tg.index_select(0, idx), dl.index_select(0, idx)))
+
+    def run(self, n: int, graph: bool = True):
+        """Issues one pass of every group (init, recorded rollout, loss,
+        backward) on its own stream, with the inputs of set_inputs, and
+        returns at once.  Successive calls queue each group behind its own
+        previous pass only, so a group that finishes early starts its next
+        pass while the others still run."""
+        t = self.torch
+        self._out = []
+        for sim, (x0, tg, dl) in zip(self.sims, self._in):
+            with t.cuda.stream(sim.stream):
+                self._out.append(sim.full_pass(x0, n, tg, dl, graph=graph))
+
+    def results(self):
+        """(loss [n_inst], grad [n_inst, N_PARAMS]) of the last run, in the
+        original instance order, on the current stream."""
+        t = self.torch
+        cur = t.cuda.current_stream(self.device)
+        loss = t.empty(self.n_inst, dtype=t.float64, device=self.device)
+        grad = t.empty((self.n_inst, N_PARAMS), dtype=t.float64, device=self.device)
+        for sim, idx, (l, g) in zip(self.sims, self._inst, self._out):
+            cur.wait_stream(sim.stream)
+            loss.index_copy_(0, idx, l)
+            grad.index_copy_(0, idx, g)
+        return loss, grad
+
+    def full_pass(self, x0, n: int, target, dloss=None, graph: bool = True):
+        """set_inputs, run and results in one call."""
+        self.set_inputs(x0, target, dloss)
+        self.run(n, graph=graph)
+        return self.results()
+
+    def check(self):
+        """ddm_check of every group: the first failing group's error, else the
+        (all-zero) error record of the first."""
+        errs = [s.check() for s in self.sims]
+        for e in errs:
+            if e.flags:
+                return e
+        return errs[0]
+
+    def synchronize(self):
+        for s in self.sims:
+            s.stream.synchronize()
+
+
+# ---------------------------------------------------------------------------
 # autograd
 # ---------------------------------------------------------------------------
 

@@ -191,3 +191,18 @@ def test_skill_pose_table_matches_oracle(lib, orc, skill, unrounded):
     P, J = orc.pose_table(orc.config(w), np.array(skill), w.dt, 600)
     np.testing.assert_allclose(pose, P, rtol=0, atol=1e-13)
     np.testing.assert_allclose(jac, J, rtol=1e-12, atol=1e-12 * np.abs(J).max())
+
+
+def test_balanced_groups_partition():
+    """balanced_groups (the instance split of StreamGroup) partitions the
+    instances, keeps each group in instance order, and leaves the groups'
+    particle counts within one instance of each other."""
+    rng = np.random.default_rng(5)
+    counts = rng.integers(20000, 200000, 64)
+    for n in (1, 2, 3, 4):
+        groups = ddm.balanced_groups(counts, n)
+        assert len(groups) == n
+        assert sorted(i for g in groups for i in g) == list(range(64))
+        sums = [int(counts[g].sum()) for g in groups]
+        assert max(sums) - min(sums) <= counts.max(), sums
+        assert all(g == sorted(g) for g in groups)
