@@ -343,7 +343,7 @@ def stream_group_bench(args, torch, ddm, ws, R, TW, spare=16 << 30):
     tg = torch.as_tensor(np.stack([W.target_heightmap(w) for w in ws]), device=dev)
     steps = ws[0].steps
     sg.set_inputs(x0, tg)
-    for _ in range(2):                        # capture, then one replay
+    for _ in range(max(1, args.warmup)):      # the first captures each group's pass
         sg.run(steps)
     torch.cuda.synchronize()
     err = sg.check()
@@ -363,13 +363,14 @@ def stream_group_bench(args, torch, ddm, ws, R, TW, spare=16 << 30):
     ms = 1e3 * elapsed / args.steps
     # the same passes with no join between steps: each group queues behind
     # its own previous pass only (independent instances)
+    k_unjoined = min(args.steps, 3)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(k_unjoined):
         sg.run(steps)
     sg.results()
     torch.cuda.synchronize()
-    pipelined = work * args.steps / (time.perf_counter() - t0)
+    pipelined = work * k_unjoined / (time.perf_counter() - t0)
     err2 = sg.check()
     rec = {"contexts": len(groups), "particles": [sum(ws[i].n_particles for i in g) for g in groups],
            "record_segments": M, "grid_record_blocks": caps, "ms_per_step": ms,
