@@ -653,12 +653,17 @@ class StreamGroup:
     def run(self, n: int, graph: bool = True):
         """Issues one pass of every group (init, recorded rollout, loss,
         backward) on its own stream, with the inputs of set_inputs, and
-        returns at once.  Successive calls queue each group behind its own
-        previous pass only, so a group that finishes early starts its next
-        pass while the others still run."""
+        returns at once.  Each group's stream first waits for the work
+        queued so far on the current stream (a results() copy of the last
+        outputs, which the new pass overwrites); successive calls with
+        nothing queued between them keep each group behind its own previous
+        pass only, so a group that finishes early starts its next pass while
+        the others still run."""
         t = self.torch
+        cur = t.cuda.current_stream(self.device)
         self._out = []
         for sim, (x0, tg, dl) in zip(self.sims, self._in):
+            sim.stream.wait_stream(cur)
             with t.cuda.stream(sim.stream):
                 self._out.append(sim.full_pass(x0, n, tg, dl, graph=graph))
 
