@@ -2,7 +2,7 @@
 passes, issued on their own streams without waits between them and replayed
 from captured graphs, give the losses and gradients of one context over the
 whole batch, in the original instance order (FP64, so the only difference is
-the order of atomic sums)."""
+the order of atomic sums); in the deterministic mode, bit for bit."""
 import sys
 from dataclasses import replace
 
@@ -83,3 +83,27 @@ def test_unjoined_runs_keep_the_last_results(ddm):
     rel = np.abs(gs - g1) / np.maximum(np.abs(g1), 1e-9 * np.abs(g1).max())
     np.testing.assert_allclose(ls, l1, rtol=1e-12)
     assert np.all(rel < 1e-9), rel
+
+
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+def test_deterministic_groups_are_bitwise_one_context(ddm, precision):
+    """In the deterministic mode an instance's sums do not depend on the
+    other instances of its batch (fixed-order window passes, per-instance
+    partials summed in a fixed order), so two concurrent groups give the
+    single context's losses and gradients bit for bit."""
+    import torch
+    ws = _batch()
+    for w in ws:
+        w.precision = precision
+    cfgs = [ddm.from_workload(w, max_steps=24, checkpoint_every=8, deterministic=True) for w in ws]
+    cfg, insts = cfgs[0][0], [c[1] for c in cfgs]
+    x0 = np.concatenate([W.bed_positions(w) for w in ws])
+    tg = np.stack([W.target_heightmap(w) for w in ws])
+    one = ddm.Simulator(cfg, insts, stream=torch.cuda.Stream())
+    l1, g1 = (a.cpu().numpy() for a in one.full_pass(x0, 24, tg))
+    sg = ddm.StreamGroup(cfg, insts, ddm.balanced_groups([w.n_particles for w in ws], 2))
+    _log(f"case deterministic stream group {sg.groups}, {precision}")
+    ls, gs = (a.cpu().numpy() for a in sg.full_pass(x0, 24, tg))
+    assert sg.check().flags == 0 and one.check().flags == 0
+    assert np.array_equal(ls, l1), np.abs(ls - l1).max()
+    assert np.array_equal(gs, g1), np.abs(gs - g1).max()
