@@ -638,9 +638,17 @@ def main():
     # the headline: the same batch as args.streams contexts at once
     streams_value, streams_ms, streams_cfg = None, None, None
     if args.streams > 1 and len(ws) >= args.streams and args.treat == "none":
-        streams_value, streams_ms, streams_cfg, grads_s = stream_group_bench(args, torch, ddm, ws, R, TW)
-        rel = np.abs(grads_s - grads32) / np.maximum(np.abs(grads32), 1e-6 * np.abs(grads32).max())
-        streams_cfg["grad_rel_diff_vs_single_context"] = float(rel.max())
+        try:
+            streams_value, streams_ms, streams_cfg, grads_s = stream_group_bench(args, torch, ddm, ws, R, TW)
+        except (ddm.DdmError, torch.cuda.OutOfMemoryError) as e:
+            if isinstance(e, ddm.DdmError) and e.code != ddm.DDM_ENOMEM:
+                raise
+            # out of device memory: the line then reports the single context (the same work)
+            print(f"# {args.streams} contexts at once: not run ({e})", flush=True)
+            streams_cfg = {"contexts": args.streams, "error": str(e)}
+        else:
+            rel = np.abs(grads_s - grads32) / np.maximum(np.abs(grads32), 1e-6 * np.abs(grads32).max())
+            streams_cfg["grad_rel_diff_vs_single_context"] = float(rel.max())
         torch.cuda.empty_cache()
 
     plain_value = None
