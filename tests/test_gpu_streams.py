@@ -64,8 +64,9 @@ def test_stream_group_equals_one_context(ddm, graph):
 
 def test_unjoined_runs_keep_the_last_results(ddm):
     """Passes issued back to back with run(), each group queued behind its
-    own previous pass only: results() gives the last pass's losses and
-    gradients, those of a joined full_pass."""
+    own previous pass only, and passes joined by join() after each run():
+    results() gives the last pass's losses and gradients, those of a joined
+    full_pass."""
     import torch
     ws = _batch()
     cfgs = [ddm.from_workload(w, max_steps=24, checkpoint_every=8) for w in ws]
@@ -80,6 +81,14 @@ def test_unjoined_runs_keep_the_last_results(ddm):
         sg.run(24)
     ls, gs = (a.cpu().numpy() for a in sg.results())
     assert sg.check().flags == 0
+    rel = np.abs(gs - g1) / np.maximum(np.abs(g1), 1e-9 * np.abs(g1).max())
+    np.testing.assert_allclose(ls, l1, rtol=1e-12)
+    assert np.all(rel < 1e-9), rel
+    # joined steps: run, then the current stream waits for every group
+    for _ in range(2):
+        sg.run(24)
+        sg.join()
+    ls, gs = (a.cpu().numpy() for a in sg.results())
     rel = np.abs(gs - g1) / np.maximum(np.abs(g1), 1e-9 * np.abs(g1).max())
     np.testing.assert_allclose(ls, l1, rtol=1e-12)
     assert np.all(rel < 1e-9), rel
