@@ -106,8 +106,11 @@ class Pass:
         self.steps = ws[0].steps
         cfg, insts = configs(ddm, ws, sort_every, precision, record_segments, grid_record_blocks)
         self.sim = ddm.Simulator(cfg, insts, stream=stream)
-        self.x0 = np.concatenate([W.bed_positions(w) for w in ws])
-        self.tg = np.stack([W.target_heightmap(w) for w in ws])
+        # inputs resident in device memory, in the context's precision, before any timed pass
+        torch = self.sim.torch
+        self.x0 = torch.as_tensor(np.concatenate([W.bed_positions(w) for w in ws]),
+                                  device=self.sim.device).to(self.sim.dtype)
+        self.tg = torch.as_tensor(np.stack([W.target_heightmap(w) for w in ws]), device=self.sim.device)
 
     def run(self, graph=False):
         return self.sim.full_pass(self.x0, self.steps, self.tg, graph=graph)
@@ -440,6 +443,8 @@ def forward_bench(args, torch, ddm):
     TW = sim.launch()[1]
     n_act, samples = active_nodes(sim, x0, steps)
     print(f"# active grid nodes (m > 0), mean over the run: {n_act:.0f} (samples {samples})", flush=True)
+    # positions resident in device memory, in the context's precision, before the timed region
+    x0 = torch.as_tensor(x0, device=sim.device).to(sim.dtype)
 
     def one(s, x):
         s.init_state(x)
@@ -479,7 +484,7 @@ def forward_bench(args, torch, ddm):
         t_plain = 0.0
         for w in ws:
             ps = ddm.Simulator(*configs(ddm, [w], R))
-            xw = W.bed_positions(w)
+            xw = torch.as_tensor(W.bed_positions(w), device=ps.device).to(ps.dtype)
             one(ps, xw)
             torch.cuda.synchronize()
             t1 = time.perf_counter()

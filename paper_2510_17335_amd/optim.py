@@ -153,10 +153,14 @@ class GpuEvaluator:
             self.grad_sim.set_grad_treatment(**treatment)
         self.batch = batch
         self.batch_sim = ddm.Simulator(cfg, [inst] * batch)
-        self.x0 = np.asarray(x0)
-        self.x0_batch = np.concatenate([self.x0] * batch)
-        self.target = np.asarray(target).reshape(1, -1)
-        self.target_batch = np.repeat(self.target, batch, axis=0)
+        # the inputs stay in device memory, in the contexts' precision
+        torch, dev, dt = self.grad_sim.torch, self.grad_sim.device, self.grad_sim.dtype
+        x0 = np.asarray(x0)
+        self.x0 = torch.as_tensor(x0, device=dev).to(dt)
+        self.x0_batch = torch.as_tensor(np.concatenate([x0] * batch), device=dev).to(dt)
+        target = np.asarray(target, dtype=np.float64).reshape(1, -1)
+        self.target = torch.as_tensor(target, device=dev)
+        self.target_batch = torch.as_tensor(np.repeat(target, batch, axis=0), device=dev)
         self.passes = 0
 
     def grad(self, theta: np.ndarray) -> Tuple[float, np.ndarray]:
