@@ -271,13 +271,17 @@ __device__ __forceinline__ void tile_origin(const KCfg& c, uint32_t gt, int& ins
 }
 
 // LDS window: component-major (one plane of `stride` entries per scattered
-// value), x stride padded from kWin^2 to kWin^2 + 4 nodes.  Entries are
+// value), x stride padded from kWin^2 to kWin^2 + 2 nodes.  Entries are
 // double in every precision: on gfx950 an LDS float atomic add takes about
 // 195 cycles per wave instruction per CU against about 10 for a double one
-// (measured), and the sums gain precision.
+// (measured), and the sums gain precision.  The padding sets which lanes of
+// a scatter instruction (same stencil node, different runs and planes) land
+// on the same banks: with 2, P2G took 520 us per launch on the 64-instance
+// batch against 525 with 4, and the G2P adjoint 499 against 500.5 (6 grows
+// the G2P adjoint past 40 KB of LDS, three workgroups per CU, 588 us).
 template <int D> struct Win {
   static constexpr int nodes = D == 3 ? kWin * kWin * kWin : kWin * kWin;
-  static constexpr int xs = D == 3 ? kWin * kWin + 4 : kWin;
+  static constexpr int xs = D == 3 ? kWin * kWin + 2 : kWin;
   static constexpr int stride = kWin * xs;
   static __device__ __forceinline__ int idx(int i, int j, int k) { return D == 3 ? i * xs + j * kWin + k : i * xs + j; }
   static __device__ __forceinline__ void coords(int n, int l[3]) {
